@@ -53,12 +53,18 @@ def test_closed_form_helpers_vs_quadrature():
 # ----------------------------------------------------------------------------- potential collocation (eq. galten)
 
 @pytest.mark.parametrize("x,h,t,A", [(0.1, 0.2, 1.0, 0.0), (3.0, 0.1, 2.0, 0.0), (-4.0, 0.3, 1.5, 0.5),
-                                     (0.05, 0.1, 30.0, 0.0), (12.0, 0.5, 0.2, -1.0)])
-def test_cell_integral_vs_quadrature(x, h, t, A):
+                                     (0.05, 0.1, 30.0, 0.0), (12.0, 0.5, 0.2, -1.0),
+                                     # cells much narrower than the Gaussian (small sinc nodes)
+                                     (5.0, 0.066, 3.7e-6, 0.0), (1.0, 0.066, 3.7e-6, 0.0),
+                                     (40.0, 0.625, 2e-3, 0.3), (-7.0, 0.3, 0.05, 0.1), (0.0, 0.02, 1.0, 0.0)])
+def test_cell_integral_vs_high_precision(x, h, t, A):
+    """Against the erf difference evaluated with 100 significant digits."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 100
+    X, Hh, T, AA = (mpmath.mpf(v) for v in (x, h, t, A))
+    ref = float(mpmath.sqrt(mpmath.pi) / (2 * T) * (mpmath.erf(T * (X + Hh / 2 - AA)) - mpmath.erf(T * (X - Hh / 2 - AA))))
     got = model.cell_integral_gauss(np.array([x]), h, t, A)[0]
-    ref = scipy.integrate.quad(lambda y: math.exp(-t * t * (y - A) ** 2), x - h / 2, x + h / 2,
-                               epsabs=0, epsrel=2e-14)[0]
-    assert abs(got - ref) <= 1e-13 * abs(ref) + 1e-300
+    assert abs(got - ref) <= 2e-14 * abs(ref), (got, ref)
 
 
 def test_sinc_rule_converges_to_inverse_distance():
