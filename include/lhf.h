@@ -1,0 +1,222 @@
+/*
+ * lhf.h -- C ABI of the MI355X (gfx950) lattice core-Hamiltonian library.
+ *
+ * The library implements the periodic-lattice hot path of Khoromskaia and
+ * Khoromskij, "Block circulant and Toeplitz structures in the linearized
+ * Hartree-Fock equation on finite lattices: tensor approach"
+ * (arXiv:1702.00339):
+ *   1. assemble the m0 x m0 generator blocks of the three-level
+ *      block-circulant Galerkin matrices H (core Hamiltonian) and S (overlap)
+ *      from 1D Gram contractions on the grid                  (lhf_assemble_blocks)
+ *   2. block-diagonalise them by a Fourier transform over the lattice
+ *      index                                                  (lhf_block_fft)
+ *   3. solve the L1 L2 L3 small generalized Hermitian eigenproblems
+ *                                                             (lhf_heev_batched)
+ * plus the Dirichlet-box block-Toeplitz matvec by circulant embedding
+ * (lhf_toeplitz_*).
+ *
+ * Conventions
+ *   * Units: bohr and hartree.
+ *   * Every pointer named d_* or documented "device" is HIP device memory the
+ *     caller owns; every other pointer is host memory read before the call
+ *     returns.  The library never keeps a caller pointer.
+ *   * Hot calls (assemble, fft, heev, toeplitz_matvec) enqueue work on the
+ *     given stream (a hipStream_t; NULL is the null stream), return at once,
+ *     allocate nothing and use only the caller's workspace.  Buffers must stay
+ *     alive until the stream has completed the work.
+ *   * Argument errors are reported synchronously by the return code before
+ *     anything is launched; numerical failures are reported per block in the
+ *     device array `info` (LAPACK style).  lhf_last_error() gives a message
+ *     for the last failing call of the calling thread.
+ *   * Plans are immutable after creation and may be used from several streams
+ *     at once, each with its own workspace.
+ */
+#ifndef LHF_H
+#define LHF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* lhf_stream_t;          /* a hipStream_t */
+typedef struct lhf_plan_s* lhf_plan_t;
+typedef struct lhf_toeplitz_s* lhf_toeplitz_t;
+
+/* Status codes returned by every call. */
+enum {
+  LHF_OK = 0,
+  LHF_ERR_INVALID = -1,      /* an argument or descriptor is invalid          */
+  LHF_ERR_UNSUPPORTED = -2,  /* valid input outside what this build supports  */
+  LHF_ERR_WORKSPACE = -3,    /* workspace missing or smaller than required    */
+  LHF_ERR_HIP = -4,          /* a HIP runtime call failed                     */
+  LHF_ERR_ALLOC = -5         /* plan creation could not allocate              */
+};
+
+/* Pipeline precision. */
+enum {
+  LHF_PREC_FP64 = 0,   /* FP64 Grams, FP64 stacks, complex128 blocks, FP64 Jacobi */
+  LHF_PREC_MIXED = 1   /* split-precision MFMA Grams, FP32 stacks, complex64 blocks,
+                          FP32 Jacobi, FP64 eigenpair refinement                 */
+};
+
+/* Arithmetic of the Gram contractions that feed the mixed-precision stack. */
+enum {
+  LHF_GRAM_FP64 = 0,   /* FP64 MFMA (also what the FP64 pipeline always uses)  */
+  LHF_GRAM_FP32 = 1,   /* FP32 MFMA on FP32-rounded operands                   */
+  LHF_GRAM_BF16X3 = 2  /* bf16 hi+lo split, hi*hi + hi*lo + lo*hi, FP32 accum.  */
+};
+
+/* Boundary conditions. */
+enum { LHF_BC_PERIODIC = 0, LHF_BC_DIRICHLET = 1 };
+
+/* Angular type of a basis function: power 1 of one coordinate. */
+enum { LHF_ANG_S = 0, LHF_ANG_PX = 1, LHF_ANG_PY = 2, LHF_ANG_PZ = 3 };
+
+/* heev flags. */
+enum {
+  LHF_HEEV_VECTORS = 1u,      /* write eigenvectors to V                          */
+  LHF_HEEV_REFINE_FP64 = 2u   /* mixed precision: refine every eigenpair in FP64 */
+};
+
+/*
+ * Unit cell (paper Sec. 2.1, eqs. ElectrostPot and expand; Sec. 2.3):
+ * m0 Gaussian basis functions g(x) = prod_l N (x_l - c_l)^{p_l}
+ * exp(-alpha |x - c|^2) with p = 0 except p_l = 1 for a p function along l,
+ * each 1D factor normalised to one; M0 nuclei of charge Z.  Positions are
+ * relative to the cell centre.
+ */
+typedef struct {
+  int32_t m0;            /* 1..32                                    */
+  const double* alpha;   /* [m0] exponents, > 0                      */
+  const double* centre;  /* [m0][3]                                  */
+  const int32_t* ang;    /* [m0] LHF_ANG_*, NULL = all s             */
+  int32_t M0;            /* 1..4                                     */
+  const double* Z;       /* [M0] charges, > 0                        */
+  const double* nuc;     /* [M0][3]                                  */
+} lhf_cell;
+
+/*
+ * Lattice system (paper Sec. 2.3 and 3.3): L1 x L2 x L3 cells of step a,
+ * n nodes per dimension, periodic or Dirichlet.  A dimension is periodic when
+ * bc is periodic and L >= 2: nodes x_i = i h, h = L a / n (n a multiple of L),
+ * cell k centred at (k + 1/2) a.  Otherwise it is a box dimension of width
+ * L a + 2 pad with nodes -W/2 + i h, i = 1..n, h = W / (n + 1) and zero
+ * Dirichlet values outside.  1/r is the R-term Gaussian sum with nodes
+ * t_q = exp(sinc_u0 + q sinc_step) and weights 2/sqrt(pi) sinc_step t_q
+ * (eq. sinc_general).  L0[l] is the generator band half-width: blocks with a
+ * lattice offset beyond L0 in dimension l are taken as zero; a negative value
+ * lets the library choose it from the smallest exponent (Gaussian overlap
+ * decay below 1e-22), a value >= (L-1)/2 keeps every offset.
+ */
+typedef struct {
+  int32_t L[3];
+  int32_t n[3];
+  double a;
+  double pad[3];
+  int32_t bc;            /* LHF_BC_*                                  */
+  int32_t R;             /* 1..64, M0 R <= 96                         */
+  double sinc_u0;
+  double sinc_step;
+  int32_t L0[3];
+  lhf_cell cell;
+} lhf_lattice;
+
+/* Element counts of the caller's buffers for a plan (all lattices concatenated). */
+typedef struct {
+  int64_t nlat;
+  int64_t nblocks;       /* sum L1 L2 L3: Fourier blocks (k points)               */
+  int64_t gen_elems;     /* sum L1 L2 L3 m0^2: one generator / Fourier-block stack */
+  int64_t w_elems;       /* sum L1 L2 L3 m0: eigenvalues                           */
+  int64_t grams_elems;   /* FP64 elements of the 1D Gram buffer                    */
+  size_t ws_bytes;       /* workspace bytes every hot call of this plan needs      */
+} lhf_sizes;
+
+/* ---------------------------------------------------------------- plans
+ * Validate nlat lattice descriptors, derive grids, bands, split factors and
+ * buffer offsets, and upload the per-lattice tables to device memory of the
+ * current HIP device (synchronously; this is the only call that allocates).
+ * prec: LHF_PREC_*; gram: LHF_GRAM_* (the stack Gram of the mixed pipeline;
+ * ignored for FP64).  Periodic and one-cell dimensions only; a Dirichlet
+ * dimension with L >= 2 is accepted only by lhf_toeplitz_create.
+ * Errors: LHF_ERR_INVALID (bad descriptor), LHF_ERR_UNSUPPORTED (m0 > 32,
+ * M0 R > 96, ...), LHF_ERR_ALLOC, LHF_ERR_HIP.  *out is NULL on error. */
+int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int32_t gram,
+                        lhf_plan_t* out);
+int32_t lhf_plan_sizes(lhf_plan_t plan, lhf_sizes* out);
+/* Workspace bytes for every hot call of the plan (same as lhf_sizes.ws_bytes). */
+size_t lhf_workspace_size(lhf_plan_t plan);
+/* Free the plan's device tables.  No work using it may be pending. */
+int32_t lhf_plan_destroy(lhf_plan_t plan);
+
+/* ---------------------------------------------------------------- assembly
+ * Generator blocks A_k = block(k, 0) of the block-circulant matrices, i.e.
+ * A_k(mu, nu) = <g_(k,mu), Op g_(0,nu)> for Op = H and S (Lemma 3.4, eqs.
+ * BC-Core, BC-mass, BC-Laplace), from 1D Gram matrices of nodal factors
+ * (Prop. 2.2, eqs. Mass_Gal_fact, Lapl_Gal_fact; eq. nuc_pot with the
+ * lattice-summed rank-R potential of eqs. EwaldTensorGl / EwaldSumP):
+ *   S_k = S1[k1] o S2[k2] o S3[k3]
+ *   H_k = 1/2 (K1 o S2 o S3 + S1 o K2 o S3 + S1 o S2 o K3) - sum_r M1_r o M2_r o M3_r
+ * d_H_gen, d_S_gen: device, gen_elems elements each, layout per lattice
+ *   [k1][k2][k3][mu][nu]; FP64 for LHF_PREC_FP64, FP32 for LHF_PREC_MIXED.
+ * d_grams64: device, optional (NULL skips it), grams_elems FP64: the FP64 1D
+ *   Grams per lattice and dimension, [term][slot][mu][nu] with term 0 = S
+ *   (mass), 1 = K (stiffness, int g' g'), 2 + nu R + q = potential term with
+ *   Z_nu w_q folded into dimension 1.  Needed by FP64 refinement and by the
+ *   FP64 generator stack of a mixed pipeline (see d_H_gen64).
+ * d_H_gen64, d_S_gen64: device, optional FP64 stacks written in mixed mode
+ *   (the FP64 generator band used by refinement); must be NULL in FP64 mode.
+ * Errors: LHF_ERR_INVALID (NULL outputs, bad plan), LHF_ERR_WORKSPACE. */
+int32_t lhf_assemble_blocks(lhf_plan_t plan, void* d_H_gen, void* d_S_gen, double* d_grams64,
+                            double* d_H_gen64, double* d_S_gen64,
+                            void* d_ws, size_t ws_bytes, lhf_stream_t stream);
+
+/* ---------------------------------------------------------------- block DFT
+ * Fourier blocks Hbar_j = sum_k w1^(j1 k1) w2^(j2 k2) w3^(j3 k3) A_k,
+ * w_l = exp(-2 pi i / L_l) (Lemma 3.1, Prop. 5.1), for every lattice of the
+ * plan; only generator offsets inside the band are read (the others are
+ * zero by construction).  prec selects the arithmetic: LHF_PREC_FP64 reads
+ * FP64 stacks and writes complex128, LHF_PREC_MIXED reads FP32 stacks and
+ * writes complex64 (interleaved re, im), layout per lattice
+ * [j1][j2][j3][mu][nu].  All four buffers are required.
+ * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE. */
+int32_t lhf_block_fft(lhf_plan_t plan, int32_t prec, const void* d_H_gen, const void* d_S_gen,
+                      void* d_H_bar, void* d_S_bar, void* d_ws, size_t ws_bytes,
+                      lhf_stream_t stream);
+
+/* ---------------------------------------------------------------- eigensolve
+ * For every block j: Hbar_j u = lambda Sbar_j u (eq. HF-FSpace-Block), by
+ * Cholesky reduction and cyclic parallel-order complex Jacobi sweeps; the
+ * union over j is the spectrum of the full matrix pair (eq. lambdAbc).
+ * Conjugate blocks j and -j share their spectrum; each pair is solved once.
+ * d_H_bar, d_S_bar: device, complex128 (FP64 plan) or complex64 (mixed plan).
+ * flags: LHF_HEEV_VECTORS, LHF_HEEV_REFINE_FP64 (mixed plans: after the FP32
+ *   solve, form U^H Hbar U and U^H Sbar U in FP64 with FP64-accurate blocks
+ *   and re-solve them in FP64).
+ * d_H_bar64, d_S_bar64: device complex128 Fourier blocks used by refinement;
+ *   may be NULL, then refinement regenerates each block from the FP64
+ *   generator stacks d_H_gen64 / d_S_gen64 (band offsets only), which then
+ *   must be given.  All four are ignored without LHF_HEEV_REFINE_FP64.
+ * d_w: device FP64 [w_elems], ascending per block.
+ * d_V: device, optional, complex (plan precision; complex128 after
+ *   refinement) [nblocks][m0][m0], column c = eigenvector c, S-orthonormal.
+ * d_info: device int32 [nblocks]: 0 ok; k > 0 Sbar not positive definite at
+ *   column k; -1 Jacobi did not converge; -2 non-finite input.
+ * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE. */
+int32_t lhf_heev_batched(lhf_plan_t plan, uint32_t flags, const void* d_H_bar, const void* d_S_bar,
+                         const void* d_H_bar64, const void* d_S_bar64,
+                         const double* d_H_gen64, const double* d_S_gen64,
+                         double* d_w, void* d_V, int32_t* d_info,
+                         void* d_ws, size_t ws_bytes, lhf_stream_t stream);
+
+/* ---------------------------------------------------------------- status */
+const char* lhf_status_string(int32_t status);
+const char* lhf_last_error(void);
+int32_t lhf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LHF_H */

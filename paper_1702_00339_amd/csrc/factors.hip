@@ -1,0 +1,101 @@
+// One-dimensional factors of one lattice, in FP64:
+//  * nodal values of every basis function of cell 0 (Sec. 2.4 interpolant),
+//    periodised over supercell translates on periodic dimensions;
+//  * the collocated, lattice-summed potential factor of every (nucleus, sinc
+//    term) pair (eqs. galten, sinc_general, EwaldTensorGl, EwaldSumP): on a
+//    replicated dimension the sum over the L-image window centred on a cell is
+//    stored for one cell's nodes; on a one-cell dimension the cell's own
+//    nucleus is evaluated on every node.  Z_nu w_q is folded into dimension 1.
+#include <algorithm>
+
+#include "plan.h"
+
+namespace lhf {
+namespace {
+
+// Integral of exp(-t^2 (y - A)^2) over [x - h/2, x + h/2].  With u = t h and
+// v = t (x - A): when the cell is much narrower than the Gaussian
+// (u <= 0.1 and u |v| <= 0.1) the erf difference would cancel, so the
+// midpoint expansion h exp(-v^2) sum_k u^2k H_2k(v) / (4^k (2k+1)!), k <= 4,
+// is used (H_n: physicists' Hermite polynomials); otherwise the difference
+// of erf, or of erfc on the far side of A.
+__device__ double cell_gauss(double x, double h, double t, double A) {
+  const double u = t * h, v = t * (x - A);
+  if (u <= 0.1 && u * fabs(v) <= 0.1) {
+    const double v2 = v * v, u2 = u * u;
+    const double H2 = 4.0 * v2 - 2.0;
+    const double H4 = (16.0 * v2 - 48.0) * v2 + 12.0;
+    const double H6 = ((64.0 * v2 - 480.0) * v2 + 720.0) * v2 - 120.0;
+    const double H8 = (((256.0 * v2 - 3584.0) * v2 + 13440.0) * v2 - 13440.0) * v2 + 1680.0;
+    const double s = 1.0 + u2 * (H2 / 24.0 + u2 * (H4 / 1920.0 + u2 * (H6 / 322560.0 + u2 * H8 / 92897280.0)));
+    return h * exp(-v2) * s;
+  }
+  const double lo = t * (x - 0.5 * h - A);
+  const double hi = t * (x + 0.5 * h - A);
+  double d;
+  if (lo > 0.0) d = erfc(lo) - erfc(hi);
+  else if (hi < 0.0) d = erfc(-hi) - erfc(-lo);
+  else d = erf(hi) - erf(lo);
+  return d * (0.886226925452758014 / t);  // sqrt(pi) / 2
+}
+
+// grid: x = node chunks of 256, y = row (m0 basis rows, then M0 R potential rows), z = dimension
+__global__ void __launch_bounds__(256) factors_kernel(const LatDev* __restrict__ lats, int li,
+                                                      double* __restrict__ fac) {
+  const LatDev& L = lats[li];
+  const int d = blockIdx.z;
+  const DimDev& D = L.dim[d];
+  const int row = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (row < L.m0) {
+    if (i >= D.n) return;
+    const int mu = row;
+    const double al = L.alpha[mu];
+    const double c = D.X0 + L.cen[mu][d];
+    const double x = D.x0 + i * D.h;
+    const int pw = L.lpow[mu][d];
+    double acc = 0.0;
+    for (int s = -D.nimg; s <= D.nimg; ++s) {
+      double u = x - c - s * D.period;
+      double g = exp(-al * u * u);
+      acc += pw ? g * u : g;
+    }
+    fac[D.g_off + (int64_t)i * L.m0 + mu] = L.norm[mu][d] * acc;
+    return;
+  }
+  const int r = row - L.m0;           // potential term nu R + q
+  if (r >= L.M0 * L.R || i >= D.npot) return;
+  const int nu = r / L.R, q = r % L.R;
+  const double t = L.tq[q];
+  const double A = L.nuc[nu][d];
+  double v;
+  if (D.replicate) {
+    const double y = D.y0 + i * D.h;    // offset from the centre of the node's cell
+    v = 0.0;
+    int klo, khi;
+    if (D.L & 1) { klo = -(D.L - 1) / 2; khi = (D.L - 1) / 2; }
+    else { klo = -D.L / 2; khi = D.L / 2; }
+    for (int k = klo; k <= khi; ++k) {
+      double wk = ((D.L & 1) == 0 && (k == klo || k == khi)) ? 0.5 : 1.0;
+      v += wk * cell_gauss(y, D.h, t, A + k * D.a);
+    }
+  } else {
+    const double x = D.x0 + i * D.h;
+    v = cell_gauss(x, D.h, t, D.X0 + A);
+  }
+  if (d == 0) v *= L.Z[nu] * L.wq[q];
+  fac[D.p_off + (int64_t)r * D.npot + i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_factors(const lhf_plan_s* p, int li, double* fac, hipStream_t s) {
+  const LatDev& L = p->lat[li];
+  int nmax = 0;
+  for (int d = 0; d < 3; ++d) nmax = std::max(nmax, std::max(L.dim[d].n, L.dim[d].npot));
+  dim3 grid((nmax + 255) / 256, L.m0 + L.M0 * L.R, 3);
+  hipLaunchKernelGGL(factors_kernel, grid, dim3(256), 0, s, p->d_lat, li, fac);
+  return hipGetLastError();
+}
+
+}  // namespace lhf

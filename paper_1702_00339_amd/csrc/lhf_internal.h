@@ -1,0 +1,61 @@
+// Internal device-visible descriptors shared by the host planner and the HIP
+// kernels of the lattice core-Hamiltonian library.  Plain-old-data only: the
+// planner fills them on the host and copies them to device memory once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lhf {
+
+constexpr int kMaxM0 = 32;     // basis functions per cell
+constexpr int kMaxNuc = 4;     // nuclei per cell
+constexpr int kMaxR = 64;      // sinc terms
+constexpr int kMaxTerms = 2 + 96;  // S, K and at most 96 potential terms (M0 * R)
+
+// One dimension of one lattice.
+struct DimDev {
+  int32_t L;          // cells along this dimension
+  int32_t n;          // grid nodes
+  int32_t nc;         // nodes per cell (replicated potential dims), else 0
+  int32_t periodic;   // cyclic FEM operators and periodised basis
+  int32_t replicate;  // potential stored for one cell and replicated (L >= 2)
+  int32_t npot;       // stored potential nodes per term (nc or n)
+  int32_t nimg;       // periodic images each side for the basis factors
+  int32_t nshift;     // generator shifts computed for the Grams (slots)
+  int32_t full;       // 1: slots are shifts 0..L-1; 0: slots are -L0..L0
+  int32_t L0;         // band half-width (banded dims)
+  int32_t ksplit;     // split-K factor of the Gram contraction
+  int32_t kchunk;     // nodes per split (multiple of 32)
+  double h;           // node spacing
+  double x0;          // coordinate of node 0
+  double y0;          // replicated dims: offset of a cell's first node from its centre
+  double a;           // lattice step
+  double X0;          // centre of cell 0
+  double period;      // supercell length on periodic dims
+  int64_t g_off;      // doubles: nodal factors [n][m0] (node-major)
+  int64_t p_off;      // doubles: potential factors [terms][npot]
+  int64_t gram_off;   // elements: Grams [T][nshift][m0][m0]
+  int64_t part_off;   // elements: split-K partials [ksplit][T m0][nshift m0]
+  int64_t tw_off;     // complex elements: twiddles exp(-2 pi i m / L), m < L
+};
+
+struct LatDev {
+  int32_t m0, M0, R, T;       // T = 2 + M0 R Gram terms
+  int32_t L[3];
+  int32_t nblk;               // L1 L2 L3
+  int64_t gen_off;            // elements of this lattice's generator / Fourier stack
+  int64_t w_off;              // eigenvalue offset (nblk m0)
+  int64_t blk_off;            // first global block index
+  DimDev dim[3];
+  int32_t lpow[kMaxM0][3];    // angular power per function and dimension
+  double alpha[kMaxM0];
+  double cen[kMaxM0][3];      // centre relative to the cell centre
+  double norm[kMaxM0][3];     // 1D normalisation per dimension
+  double Z[kMaxNuc];
+  double nuc[kMaxNuc][3];
+  double tq[kMaxR];
+  double wq[kMaxR];
+};
+
+}  // namespace lhf

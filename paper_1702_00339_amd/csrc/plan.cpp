@@ -1,0 +1,276 @@
+// Plan creation: validation of the lattice descriptors, derivation of grids,
+// bands, split factors and buffer offsets, upload of the device tables.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+namespace lhf {
+
+namespace {
+thread_local std::string g_last_error;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool finite(double x) { return std::isfinite(x); }
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+Ws ws_view(const lhf_plan_s* p, void* base) {
+  char* b = static_cast<char*>(base);
+  Ws w;
+  w.fac = reinterpret_cast<double*>(b + p->ws_fac);
+  w.grams64 = reinterpret_cast<double*>(b + p->ws_grams64);
+  w.grams32 = reinterpret_cast<float*>(b + p->ws_grams32);
+  w.part64 = reinterpret_cast<double*>(b + p->ws_part64);
+  w.part32 = reinterpret_cast<float*>(b + p->ws_part32);
+  w.dft_a = b + p->ws_dft_a;
+  w.dft_b = b + p->ws_dft_b;
+  w.U = reinterpret_cast<float2*>(b + p->ws_U);
+  w.info32 = reinterpret_cast<int32_t*>(b + p->ws_info);
+  return w;
+}
+
+// Fill one lattice's device descriptor; returns LHF_OK or an error code.
+static int32_t derive_lattice(const lhf_lattice& in, int idx, LatDev& L, std::string& err) {
+  std::memset(&L, 0, sizeof(L));
+  const lhf_cell& c = in.cell;
+  auto bad = [&](const std::string& m) {
+    err = "lattice " + std::to_string(idx) + ": " + m;
+    return LHF_ERR_INVALID;
+  };
+  if (c.m0 < 1) return bad("m0 must be >= 1");
+  if (c.m0 > kMaxM0) { err = "lattice " + std::to_string(idx) + ": m0 > 32 unsupported"; return LHF_ERR_UNSUPPORTED; }
+  if (!c.alpha || !c.centre) return bad("alpha and centre are required");
+  if (c.M0 < 1 || !c.Z || !c.nuc) return bad("at least one nucleus with Z and position is required");
+  if (c.M0 > kMaxNuc) { err = "lattice " + std::to_string(idx) + ": more than 4 nuclei per cell unsupported"; return LHF_ERR_UNSUPPORTED; }
+  if (in.R < 1) return bad("R must be >= 1");
+  if (in.R > kMaxR || c.M0 * in.R > kMaxTerms - 2) {
+    err = "lattice " + std::to_string(idx) + ": R > 64 or M0 R > 96 unsupported";
+    return LHF_ERR_UNSUPPORTED;
+  }
+  if (!(in.a > 0) || !finite(in.a)) return bad("lattice step a must be positive");
+  if (!(in.sinc_step > 0) || !finite(in.sinc_step) || !finite(in.sinc_u0)) return bad("bad sinc parameters");
+  if (in.bc != LHF_BC_PERIODIC && in.bc != LHF_BC_DIRICHLET) return bad("bc must be periodic or Dirichlet");
+
+  L.m0 = c.m0; L.M0 = c.M0; L.R = in.R; L.T = 2 + c.M0 * in.R;
+  double amin = 1e300, jmax = 0.0;
+  for (int mu = 0; mu < c.m0; ++mu) {
+    double al = c.alpha[mu];
+    if (!(al > 0) || !finite(al)) return bad("exponents must be positive and finite");
+    int ang = c.ang ? c.ang[mu] : LHF_ANG_S;
+    if (ang < 0 || ang > 3) return bad("angular type must be 0..3");
+    L.alpha[mu] = al;
+    amin = std::min(amin, al);
+    for (int d = 0; d < 3; ++d) {
+      double x = c.centre[3 * mu + d];
+      if (!finite(x)) return bad("centres must be finite");
+      L.cen[mu][d] = x;
+      jmax = std::max(jmax, std::fabs(x));
+      int pw = (ang == d + 1) ? 1 : 0;
+      L.lpow[mu][d] = pw;
+      double base = std::pow(2.0 * al / M_PI, 0.25);
+      L.norm[mu][d] = pw ? base * 2.0 * std::sqrt(al) : base;
+    }
+  }
+  for (int nu = 0; nu < c.M0; ++nu) {
+    if (!(c.Z[nu] > 0) || !finite(c.Z[nu])) return bad("charges must be positive");
+    L.Z[nu] = c.Z[nu];
+    for (int d = 0; d < 3; ++d) {
+      if (!finite(c.nuc[3 * nu + d])) return bad("nuclear positions must be finite");
+      L.nuc[nu][d] = c.nuc[3 * nu + d];
+    }
+  }
+  for (int q = 0; q < in.R; ++q) {
+    double t = std::exp(in.sinc_u0 + q * in.sinc_step);
+    L.tq[q] = t;
+    L.wq[q] = (2.0 / std::sqrt(M_PI)) * in.sinc_step * t;
+  }
+  int64_t nblk = 1;
+  for (int d = 0; d < 3; ++d) {
+    DimDev& D = L.dim[d];
+    int Ld = in.L[d], nd = in.n[d];
+    if (Ld < 1) return bad("L must be >= 1");
+    if (nd < 4) return bad("n must be >= 4");
+    L.L[d] = Ld;
+    nblk *= Ld;
+    D.L = Ld; D.n = nd; D.a = in.a;
+    bool periodic = in.bc == LHF_BC_PERIODIC && Ld >= 2;
+    if (periodic) {
+      if (nd % Ld != 0) return bad("on a periodic dimension n must be a multiple of L");
+      D.periodic = 1; D.replicate = 1;
+      D.nc = nd / Ld; D.npot = D.nc;
+      if (D.nc < 2) return bad("need at least two nodes per cell");
+      D.h = Ld * in.a / nd;
+      D.x0 = 0.0;
+      D.X0 = 0.5 * in.a;
+      D.y0 = -0.5 * in.a;
+      D.period = Ld * in.a;
+      D.nimg = (int)std::ceil(std::sqrt(800.0 / amin) / D.period) + 1;
+    } else {
+      if (Ld >= 2) {
+        err = "lattice " + std::to_string(idx) + ": Dirichlet dimensions with L >= 2 are handled by lhf_toeplitz_create";
+        return LHF_ERR_UNSUPPORTED;
+      }
+      if (!(in.pad[d] >= 0) || !finite(in.pad[d])) return bad("pad must be >= 0");
+      double W = Ld * in.a + 2.0 * in.pad[d];
+      D.h = W / (nd + 1);
+      D.x0 = -0.5 * W + D.h;
+      D.X0 = -0.5 * Ld * in.a + 0.5 * in.a;
+      D.y0 = 0.0;
+      D.replicate = 0; D.npot = nd; D.nc = 0; D.nimg = 0;
+    }
+    // band half-width
+    int L0 = in.L0[d];
+    if (L0 < 0) {
+      double reach = 2.0 * jmax + std::sqrt(101.4 / amin);
+      L0 = (int)std::ceil(reach / in.a);
+    }
+    if (Ld == 1) {
+      D.full = 1; D.nshift = 1; D.L0 = 0;
+    } else if (2 * L0 + 1 >= Ld) {
+      D.full = 1; D.nshift = Ld; D.L0 = (Ld - 1) / 2;
+    } else {
+      D.full = 0; D.nshift = 2 * L0 + 1; D.L0 = L0;
+    }
+    // split-K of the Gram contraction: aim at ~2048 waves of 32 x 32 tiles
+    int M = L.T * L.m0, N = D.nshift * L.m0;
+    int64_t tiles = (int64_t)((M + 31) / 32) * ((N + 31) / 32);
+    int ks = (int)std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
+    ks = std::min(ks, std::max(1, nd / 32));
+    int kchunk = ((nd + ks - 1) / ks + 31) / 32 * 32;
+    D.kchunk = kchunk;
+    D.ksplit = (nd + kchunk - 1) / kchunk;
+  }
+  if (nblk > (int64_t)1 << 30) return bad("too many cells");
+  L.nblk = (int32_t)nblk;
+  return LHF_OK;
+}
+
+}  // namespace lhf
+
+using namespace lhf;
+
+extern "C" {
+
+const char* lhf_last_error(void) { return g_last_error.c_str(); }
+
+const char* lhf_status_string(int32_t s) {
+  switch (s) {
+    case LHF_OK: return "ok";
+    case LHF_ERR_INVALID: return "invalid argument";
+    case LHF_ERR_UNSUPPORTED: return "unsupported";
+    case LHF_ERR_WORKSPACE: return "workspace too small";
+    case LHF_ERR_HIP: return "HIP runtime error";
+    case LHF_ERR_ALLOC: return "allocation failed";
+    default: return "unknown status";
+  }
+}
+
+int32_t lhf_version(void) { return 1; }
+
+int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int32_t gram,
+                        lhf_plan_t* out) {
+  if (!out) { set_error("out is NULL"); return LHF_ERR_INVALID; }
+  *out = nullptr;
+  if (!lats || nlat < 1) { set_error("need at least one lattice"); return LHF_ERR_INVALID; }
+  if (prec != LHF_PREC_FP64 && prec != LHF_PREC_MIXED) { set_error("bad precision"); return LHF_ERR_INVALID; }
+  if (gram < LHF_GRAM_FP64 || gram > LHF_GRAM_BF16X3) { set_error("bad gram mode"); return LHF_ERR_INVALID; }
+  auto* p = new (std::nothrow) lhf_plan_s();
+  if (!p) { set_error("out of host memory"); return LHF_ERR_ALLOC; }
+  p->prec = prec; p->gram = gram; p->nlat = nlat;
+  p->lat.resize(nlat);
+  std::string err;
+  int64_t fac = 0, grams = 0, part = 0, tw = 0, gen = 0, w = 0, blk = 0, dtmp = 0;
+  for (int i = 0; i < nlat; ++i) {
+    int32_t st = derive_lattice(lats[i], i, p->lat[i], err);
+    if (st != LHF_OK) { set_error(err); delete p; return st; }
+    LatDev& L = p->lat[i];
+    for (int d = 0; d < 3; ++d) {
+      DimDev& D = L.dim[d];
+      D.g_off = fac; fac += (int64_t)D.n * L.m0;
+      D.p_off = fac; fac += (int64_t)(L.M0 * L.R) * D.npot;
+      D.gram_off = grams; grams += (int64_t)L.T * D.nshift * L.m0 * L.m0;
+      D.part_off = part; part += (int64_t)D.ksplit * (L.T * L.m0) * (D.nshift * L.m0);
+      D.tw_off = tw; tw += D.L;
+    }
+    L.gen_off = gen; gen += (int64_t)L.nblk * L.m0 * L.m0;
+    L.w_off = w; w += (int64_t)L.nblk * L.m0;
+    L.blk_off = blk; blk += L.nblk;
+    dtmp = std::max(dtmp, block_dft_tmp_elems(L));
+  }
+  p->sizes.nlat = nlat;
+  p->sizes.nblocks = blk;
+  p->sizes.gen_elems = gen;
+  p->sizes.w_elems = w;
+  p->sizes.grams_elems = grams;
+  p->fac_doubles = fac;
+  p->part_elems = part;
+  p->dft_tmp_elems = dtmp;
+  size_t off = 0;
+  p->ws_fac = off; off = align256(off + (size_t)fac * 8);
+  p->ws_grams64 = off; off = align256(off + (size_t)grams * 8);
+  p->ws_part64 = off; off = align256(off + (size_t)part * 8);
+  if (prec == LHF_PREC_MIXED) {
+    p->ws_grams32 = off; off = align256(off + (size_t)grams * 4);
+    p->ws_part32 = off; off = align256(off + (size_t)part * 4);
+    p->ws_U = off; off = align256(off + (size_t)gen * 8);
+    p->ws_info = off; off = align256(off + (size_t)blk * 4);
+  }
+  p->ws_dft_a = off; off = align256(off + (size_t)dtmp * 16);
+  p->ws_dft_b = off; off = align256(off + (size_t)dtmp * 16);
+  p->sizes.ws_bytes = off;
+
+  // twiddle tables exp(-2 pi i m / L)
+  std::vector<double2> tw64(tw);
+  std::vector<float2> tw32(tw);
+  for (int i = 0; i < nlat; ++i) {
+    for (int d = 0; d < 3; ++d) {
+      const DimDev& D = p->lat[i].dim[d];
+      for (int m = 0; m < D.L; ++m) {
+        double ang = -2.0 * M_PI * (double)m / (double)D.L;
+        tw64[D.tw_off + m] = make_double2(std::cos(ang), std::sin(ang));
+        tw32[D.tw_off + m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+      }
+    }
+  }
+  if (hipGetDevice(&p->device) != hipSuccess ||
+      hipMalloc(&p->d_lat, sizeof(LatDev) * nlat) != hipSuccess ||
+      hipMalloc(&p->d_tw64, sizeof(double2) * tw) != hipSuccess ||
+      hipMalloc(&p->d_tw32, sizeof(float2) * tw) != hipSuccess) {
+    set_error("device allocation of the plan tables failed");
+    lhf_plan_destroy(p);
+    return LHF_ERR_ALLOC;
+  }
+  if (hipMemcpy(p->d_lat, p->lat.data(), sizeof(LatDev) * nlat, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_tw64, tw64.data(), sizeof(double2) * tw, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_tw32, tw32.data(), sizeof(float2) * tw, hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("upload of the plan tables failed");
+    lhf_plan_destroy(p);
+    return LHF_ERR_HIP;
+  }
+  *out = p;
+  return LHF_OK;
+}
+
+int32_t lhf_plan_sizes(lhf_plan_t plan, lhf_sizes* out) {
+  if (!plan || !out) { set_error("NULL plan or output"); return LHF_ERR_INVALID; }
+  *out = plan->sizes;
+  return LHF_OK;
+}
+
+size_t lhf_workspace_size(lhf_plan_t plan) { return plan ? plan->sizes.ws_bytes : 0; }
+
+int32_t lhf_plan_destroy(lhf_plan_t plan) {
+  if (!plan) return LHF_OK;
+  if (plan->d_lat) (void)hipFree(plan->d_lat);
+  if (plan->d_tw64) (void)hipFree(plan->d_tw64);
+  if (plan->d_tw32) (void)hipFree(plan->d_tw32);
+  delete plan;
+  return LHF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+"""ctypes binding of liblhf.so (argument marshalling only).
+
+The functions keep the C names and signatures of include/lhf.h; ``Plan``
+wraps a plan handle and passes torch tensors' device pointers and the current
+torch stream.  Every computation runs in the HIP library: there is no CPU
+fallback, and loading fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "liblhf.so")
+
+LHF_OK, LHF_ERR_INVALID, LHF_ERR_UNSUPPORTED, LHF_ERR_WORKSPACE, LHF_ERR_HIP, LHF_ERR_ALLOC = 0, -1, -2, -3, -4, -5
+LHF_PREC_FP64, LHF_PREC_MIXED = 0, 1
+LHF_GRAM_FP64, LHF_GRAM_FP32, LHF_GRAM_BF16X3 = 0, 1, 2
+LHF_BC_PERIODIC, LHF_BC_DIRICHLET = 0, 1
+LHF_HEEV_VECTORS, LHF_HEEV_REFINE_FP64 = 1, 2
+
+
+class lhf_cell(C.Structure):
+    _fields_ = [("m0", C.c_int32), ("alpha", C.POINTER(C.c_double)), ("centre", C.POINTER(C.c_double)),
+                ("ang", C.POINTER(C.c_int32)), ("M0", C.c_int32), ("Z", C.POINTER(C.c_double)),
+                ("nuc", C.POINTER(C.c_double))]
+
+
+class lhf_lattice(C.Structure):
+    _fields_ = [("L", C.c_int32 * 3), ("n", C.c_int32 * 3), ("a", C.c_double), ("pad", C.c_double * 3),
+                ("bc", C.c_int32), ("R", C.c_int32), ("sinc_u0", C.c_double), ("sinc_step", C.c_double),
+                ("L0", C.c_int32 * 3), ("cell", lhf_cell)]
+
+
+class lhf_sizes(C.Structure):
+    _fields_ = [("nlat", C.c_int64), ("nblocks", C.c_int64), ("gen_elems", C.c_int64),
+                ("w_elems", C.c_int64), ("grams_elems", C.c_int64), ("ws_bytes", C.c_size_t)]
+
+
+class LhfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"lhf status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblhf.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch first: its bundled HIP runtime has the same soname as the system
+    # one, so the library then binds to the runtime that owns torch's streams
+    import torch  # noqa: F401
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it first (python -m paper_1702_00339_amd.build_lib)")
+    lib = C.CDLL(path)
+    vp, i32, u32, sz = C.c_void_p, C.c_int32, C.c_uint32, C.c_size_t
+    sig = {
+        "lhf_plan_create": (i32, [C.POINTER(lhf_lattice), i32, i32, i32, C.POINTER(vp)]),
+        "lhf_plan_sizes": (i32, [vp, C.POINTER(lhf_sizes)]),
+        "lhf_workspace_size": (sz, [vp]),
+        "lhf_plan_destroy": (i32, [vp]),
+        "lhf_assemble_blocks": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "lhf_block_fft": (i32, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),
+        "lhf_heev_batched": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "lhf_status_string": (C.c_char_p, [i32]),
+        "lhf_last_error": (C.c_char_p, []),
+        "lhf_version": (i32, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the binding expects the library to export."""
+    return ["lhf_plan_create", "lhf_plan_sizes", "lhf_workspace_size", "lhf_plan_destroy",
+            "lhf_assemble_blocks", "lhf_block_fft", "lhf_heev_batched", "lhf_status_string",
+            "lhf_last_error", "lhf_version"]
+
+
+def _check(st):
+    if st != LHF_OK:
+        lib = load()
+        raise LhfError(st, lib.lhf_last_error().decode())
+
+
+def lattice_from_instance(inst, L0=(-1, -1, -1)):
+    """Fill an lhf_lattice from a synth Instance; returns (struct, keepalive)."""
+    keep = []
+
+    def arr(x, dt, ct):
+        a = np.ascontiguousarray(np.asarray(x, dtype=dt).ravel())
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(ct))
+
+    lat = lhf_lattice()
+    lat.L[:] = [int(v) for v in inst.L]
+    lat.n[:] = [int(v) for v in inst.n]
+    lat.a = float(inst.a)
+    lat.pad[:] = [float(v) for v in inst.pad]
+    lat.bc = LHF_BC_PERIODIC if inst.bc == "periodic" else LHF_BC_DIRICHLET
+    lat.R = int(inst.R)
+    lat.sinc_u0 = float(inst.sinc_u0)
+    lat.sinc_step = float(inst.sinc_step)
+    lat.L0[:] = [int(v) for v in L0]
+    cell = lhf_cell()
+    cell.m0 = inst.m0
+    cell.alpha = arr(inst.alpha, np.float64, C.c_double)
+    cell.centre = arr(inst.centre, np.float64, C.c_double)
+    cell.ang = arr(inst.ang, np.int32, C.c_int32)
+    cell.M0 = inst.M0
+    cell.Z = arr(inst.Z, np.float64, C.c_double)
+    cell.nuc = arr(inst.nuc, np.float64, C.c_double)
+    lat.cell = cell
+    return lat, keep
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A plan over one or more lattices (lhf_plan_create / lhf_plan_destroy)."""
+
+    def __init__(self, instances, prec=LHF_PREC_FP64, gram=LHF_GRAM_FP64, L0=None):
+        lib = load()
+        if not isinstance(instances, (list, tuple)):
+            instances = [instances]
+        arr = (lhf_lattice * len(instances))()
+        self._keep = []
+        for i, inst in enumerate(instances):
+            lat, keep = lattice_from_instance(inst, L0 if L0 is not None else (-1, -1, -1))
+            arr[i] = lat
+            self._keep.append(keep)
+        h = C.c_void_p()
+        _check(lib.lhf_plan_create(arr, len(instances), prec, gram, C.byref(h)))
+        self.handle = h
+        self.prec = prec
+        self.gram = gram
+        self.instances = list(instances)
+        s = lhf_sizes()
+        _check(lib.lhf_plan_sizes(h, C.byref(s)))
+        self.sizes = s
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().lhf_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------- buffers
+    def workspace(self, device="cuda"):
+        import torch
+        return torch.empty(max(1, int(self.sizes.ws_bytes)), dtype=torch.uint8, device=device)
+
+    # ----------------------------------------------------------------- calls
+    def lhf_assemble_blocks(self, H_gen, S_gen, grams64, ws, H_gen64=None, S_gen64=None):
+        _check(load().lhf_assemble_blocks(self.handle, _ptr(H_gen), _ptr(S_gen), _ptr(grams64),
+                                          _ptr(H_gen64), _ptr(S_gen64), _ptr(ws), ws.numel(), _stream()))
+
+    def lhf_block_fft(self, prec, H_gen, S_gen, H_bar, S_bar, ws):
+        _check(load().lhf_block_fft(self.handle, prec, _ptr(H_gen), _ptr(S_gen), _ptr(H_bar), _ptr(S_bar),
+                                    _ptr(ws), ws.numel(), _stream()))
+
+    def lhf_heev_batched(self, flags, H_bar, S_bar, w, info, ws, V=None, H_bar64=None, S_bar64=None,
+                         H_gen64=None, S_gen64=None):
+        _check(load().lhf_heev_batched(self.handle, flags, _ptr(H_bar), _ptr(S_bar), _ptr(H_bar64),
+                                       _ptr(S_bar64), _ptr(H_gen64), _ptr(S_gen64), _ptr(w), _ptr(V),
+                                       _ptr(info), _ptr(ws), ws.numel(), _stream()))

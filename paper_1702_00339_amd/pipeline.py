@@ -1,0 +1,94 @@
+"""The periodic hot path on device buffers: assemble -> block DFT -> eigensolve.
+
+``Pipeline`` owns the plan and every device buffer of one configuration and
+runs one step with three (FP64) or four-plus (mixed) C-ABI calls on the
+current torch stream.  All arithmetic happens in the HIP library.
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import lhf
+
+
+class Pipeline:
+    """prec: lhf.LHF_PREC_FP64 or lhf.LHF_PREC_MIXED.  For the mixed path the
+    refinement source is either the complex128 Fourier blocks (``refine_src``
+    = "bar64", general) or regeneration from the FP64 generator band
+    (``refine_src`` = "band", cheap for chains)."""
+
+    def __init__(self, instances, prec=lhf.LHF_PREC_FP64, gram=lhf.LHF_GRAM_BF16X3, refine_src="auto",
+                 want_vectors=False, device="cuda", L0=None):
+        if not isinstance(instances, (list, tuple)):
+            instances = [instances]
+        self.plan = lhf.Plan(instances, prec=prec, gram=gram if prec == lhf.LHF_PREC_MIXED else lhf.LHF_GRAM_FP64,
+                             L0=L0)
+        sz = self.plan.sizes
+        self.prec = prec
+        self.sizes = sz
+        dev = torch.device(device)
+        G, B = int(sz.gen_elems), int(sz.nblocks)
+        rdt = torch.float64 if prec == lhf.LHF_PREC_FP64 else torch.float32
+        cdt = torch.complex128 if prec == lhf.LHF_PREC_FP64 else torch.complex64
+        self.ws = self.plan.workspace(dev)
+        self.H_gen = torch.empty(G, dtype=rdt, device=dev)
+        self.S_gen = torch.empty(G, dtype=rdt, device=dev)
+        self.H_bar = torch.empty(G, dtype=cdt, device=dev)
+        self.S_bar = torch.empty(G, dtype=cdt, device=dev)
+        self.grams64 = torch.empty(max(1, int(sz.grams_elems)), dtype=torch.float64, device=dev)
+        self.w = torch.empty(int(sz.w_elems), dtype=torch.float64, device=dev)
+        self.info = torch.empty(B, dtype=torch.int32, device=dev)
+        self.want_vectors = want_vectors
+        self.V = None
+        if want_vectors:
+            # FP64 solves and refined mixed solves both return complex128 vectors
+            self.V = torch.empty(G, dtype=torch.complex128, device=dev)
+        self.H_gen64 = self.S_gen64 = self.H_bar64 = self.S_bar64 = None
+        if prec == lhf.LHF_PREC_MIXED:
+            if refine_src == "auto":
+                refine_src = "band" if all(inst.L[1] == 1 and inst.L[2] == 1 for inst in instances) else "bar64"
+            self.refine_src = refine_src
+            self.H_gen64 = torch.empty(G, dtype=torch.float64, device=dev)
+            self.S_gen64 = torch.empty(G, dtype=torch.float64, device=dev)
+            if refine_src == "bar64":
+                self.H_bar64 = torch.empty(G, dtype=torch.complex128, device=dev)
+                self.S_bar64 = torch.empty(G, dtype=torch.complex128, device=dev)
+        else:
+            self.refine_src = None
+
+    def step(self):
+        p = self.plan
+        if self.prec == lhf.LHF_PREC_FP64:
+            p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws)
+            p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen, self.S_gen, self.H_bar, self.S_bar, self.ws)
+            flags = lhf.LHF_HEEV_VECTORS if self.want_vectors else 0
+            p.lhf_heev_batched(flags, self.H_bar, self.S_bar, self.w, self.info, self.ws, V=self.V)
+            return
+        p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws, H_gen64=self.H_gen64,
+                              S_gen64=self.S_gen64)
+        p.lhf_block_fft(lhf.LHF_PREC_MIXED, self.H_gen, self.S_gen, self.H_bar, self.S_bar, self.ws)
+        if self.refine_src == "bar64":
+            p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.ws)
+        flags = lhf.LHF_HEEV_REFINE_FP64 | (lhf.LHF_HEEV_VECTORS if self.want_vectors else 0)
+        p.lhf_heev_batched(flags, self.H_bar, self.S_bar, self.w, self.info, self.ws, V=self.V,
+                           H_bar64=self.H_bar64, S_bar64=self.S_bar64, H_gen64=self.H_gen64, S_gen64=self.S_gen64)
+
+    def eigenvalues(self):
+        """Per-lattice eigenvalue arrays [L1, L2, L3, m0] on the host."""
+        w = self.w.cpu().numpy()
+        out, off = [], 0
+        for inst in self.plan.instances:
+            cnt = inst.ncells * inst.m0
+            out.append(w[off:off + cnt].reshape(*inst.L, inst.m0))
+            off += cnt
+        return out
+
+    def stacks(self, which="H_gen"):
+        t = getattr(self, which).cpu().numpy()
+        out, off = [], 0
+        for inst in self.plan.instances:
+            cnt = inst.ncells * inst.m0 * inst.m0
+            out.append(t[off:off + cnt].reshape(*inst.L, inst.m0, inst.m0))
+            off += cnt
+        return out
