@@ -148,6 +148,11 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
 int32_t lhf_plan_sizes(lhf_plan_t plan, lhf_sizes* out);
 /* Workspace bytes for every hot call of the plan (same as lhf_sizes.ws_bytes). */
 size_t lhf_workspace_size(lhf_plan_t plan);
+/* Generator slots per dimension of lattice `index` (nshift[l]: offsets
+ * 0..L-1 when full[l] = 1, else -L0..L0 with L0[l] given) -- the band the
+ * plan uses for the Grams, the generator stacks and the block DFT.
+ * Errors: LHF_ERR_INVALID (NULL pointer, index out of range). */
+int32_t lhf_plan_band(lhf_plan_t plan, int32_t index, int32_t* nshift, int32_t* L0, int32_t* full);
 /* Free the plan's device tables.  No work using it may be pending. */
 int32_t lhf_plan_destroy(lhf_plan_t plan);
 

@@ -31,85 +31,145 @@ __device__ __forceinline__ int slot_cell(const DimDev& D, int s) {
 
 __device__ __forceinline__ int nslot(const DimDev& D) { return D.L == 1 ? 1 : D.nshift; }
 
-// First pass: real generator stack -> complex, transforming dimension df.
-template <typename R>
-__global__ void __launch_bounds__(256) dft_first_kernel(const LatDev* __restrict__ lats, int li, int df,
-                                                        const typename Cx<R>::T* __restrict__ tw,
-                                                        const R* __restrict__ genH, const R* __restrict__ genS,
-                                                        typename Cx<R>::T* __restrict__ outH,
-                                                        typename Cx<R>::T* __restrict__ outS) {
-  typedef typename Cx<R>::T C;
-  const LatDev& L = lats[li];
-  const int E = L.m0 * L.m0;
-  const DimDev& D = L.dim[df];
-  int O = 1;
-  for (int d = 0; d < df; ++d) O *= nslot(L.dim[d]);
-  const int64_t tot = (int64_t)O * D.L * E;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= tot) return;
-  const R* X = (blockIdx.y == 0 ? genH : genS) + L.gen_off;
-  C* Y = blockIdx.y == 0 ? outH : outS;
-  const int e = (int)(idx % E);
-  const int j = (int)((idx / E) % D.L);
-  int o = (int)(idx / ((int64_t)E * D.L));
-  // cells of the outer (not yet transformed) dimensions from their band slots
-  int kk[3] = {0, 0, 0};
-  for (int d = df - 1; d >= 0; --d) {
-    const int ns = nslot(L.dim[d]);
-    kk[d] = slot_cell(L.dim[d], o % ns);
-    o /= ns;
-  }
-  const C* T = tw + D.tw_off;
-  R re = 0, im = 0;
-  const int B = nslot(D);
-  for (int b = 0; b < B; ++b) {
-    kk[df] = slot_cell(D, b);
-    const int64_t cell = ((int64_t)kk[0] * L.L[1] + kk[1]) * L.L[2] + kk[2];
-    const R x = X[cell * E + e];
-    const C w = T[(int)(((int64_t)j * kk[df]) % D.L)];
-    re += w.x * x;
-    im += w.y * x;
-  }
-  C r;
-  r.x = re;
-  r.y = im;
-  Y[idx] = r;
-}
-
-// Later passes: [O][B][I] (slots of dimension d) -> [O][L_d][I].
-template <typename R>
-__global__ void __launch_bounds__(256) dft_next_kernel(const LatDev* __restrict__ lats, int li, int d, int O,
-                                                       int64_t I, const typename Cx<R>::T* __restrict__ tw,
-                                                       const typename Cx<R>::T* __restrict__ inH,
-                                                       const typename Cx<R>::T* __restrict__ inS,
+// One pass of the pruned DFT along dimension d.  Thread t owns one input
+// column (o, i) and a chunk of JC outputs j along the transformed axis: it
+// loads the column's B band inputs once into registers and writes
+//   Y[o][j][i] = sum_b w^(j k_b) X[o][b][i],  k_b the lattice offset of slot b
+// for its JC values of j (twiddle indices advance by k_b per j, 32-bit).
+// FIRST: X is the real generator stack, band-gathered over the outer dims
+// (o enumerates their slots) with inner index i = block entry.
+template <typename R, int BMAX, bool FIRST>
+__global__ void __launch_bounds__(256) dft_pass_kernel(const LatDev* __restrict__ lats, int li, int d, int O,
+                                                       int I, int JC, const typename Cx<R>::T* __restrict__ tw,
+                                                       const void* __restrict__ inH, const void* __restrict__ inS,
                                                        typename Cx<R>::T* __restrict__ outH,
                                                        typename Cx<R>::T* __restrict__ outS) {
   typedef typename Cx<R>::T C;
   const LatDev& L = lats[li];
   const DimDev& D = L.dim[d];
+  const int Ld = D.L;
   const int B = nslot(D);
-  const int64_t tot = (int64_t)O * D.L * I;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= tot) return;
-  const C* X = blockIdx.y == 0 ? inH : inS;
-  C* Y = blockIdx.y == 0 ? outH : outS;
-  const int64_t i = idx % I;
-  const int j = (int)((idx / I) % D.L);
-  const int64_t o = idx / (I * D.L);
+  const int njc = (Ld + JC - 1) / JC;
+  const int tid = blockIdx.x * 256 + threadIdx.x;
+  if (tid >= O * njc * I) return;
+  const int i = tid % I;
+  const int jc = (tid / I) % njc;
+  const int o = tid / (I * njc);
+  const bool isH = blockIdx.y == 0;
+  C* Y = isH ? outH : outS;
+  R xr[BMAX], xi[BMAX];
+  int kb[BMAX];
+  if constexpr (FIRST) {
+    const R* X = (const R*)(isH ? inH : inS) + L.gen_off;
+    const int E = L.m0 * L.m0;
+    int kk[3] = {0, 0, 0};
+    int oo = o;
+    for (int q = d - 1; q >= 0; --q) {
+      const int ns = nslot(L.dim[q]);
+      kk[q] = slot_cell(L.dim[q], oo % ns);
+      oo /= ns;
+    }
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) {
+      if (b < B) {
+        kk[d] = slot_cell(D, b);
+        kb[b] = kk[d];
+        const int cell = (kk[0] * L.L[1] + kk[1]) * L.L[2] + kk[2];
+        xr[b] = X[cell * E + i];
+        xi[b] = R(0);
+      }
+    }
+  } else {
+    const C* X = (const C*)(isH ? inH : inS) + (int64_t)o * B * I + i;
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) {
+      if (b < B) {
+        kb[b] = slot_cell(D, b);
+        const C x = X[(int64_t)b * I];
+        xr[b] = x.x;
+        xi[b] = x.y;
+      }
+    }
+  }
+  const int j0 = jc * JC;
+  const int j1 = min(Ld, j0 + JC);
+  int idx[BMAX];
+#pragma unroll
+  for (int b = 0; b < BMAX; ++b)
+    if (b < B) idx[b] = (j0 * kb[b]) % Ld;
   const C* T = tw + D.tw_off;
-  const C* src = X + o * B * I + i;
+  C* dst = Y + (int64_t)o * Ld * I + i;
+  for (int j = j0; j < j1; ++j) {
+    R re = 0, im = 0;
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) {
+      if (b < B) {
+        const C w = T[idx[b]];
+        re += w.x * xr[b] - w.y * xi[b];
+        im += w.x * xi[b] + w.y * xr[b];
+        idx[b] += kb[b];
+        if (idx[b] >= Ld) idx[b] -= Ld;
+      }
+    }
+    C r;
+    r.x = re;
+    r.y = im;
+    dst[(int64_t)j * I] = r;
+  }
+}
+
+// Fallback for bands wider than 32 slots: one thread per output.
+template <typename R, bool FIRST>
+__global__ void __launch_bounds__(256) dft_wide_kernel(const LatDev* __restrict__ lats, int li, int d, int O,
+                                                       int I, const typename Cx<R>::T* __restrict__ tw,
+                                                       const void* __restrict__ inH, const void* __restrict__ inS,
+                                                       typename Cx<R>::T* __restrict__ outH,
+                                                       typename Cx<R>::T* __restrict__ outS) {
+  typedef typename Cx<R>::T C;
+  const LatDev& L = lats[li];
+  const DimDev& D = L.dim[d];
+  const int Ld = D.L;
+  const int B = nslot(D);
+  const int64_t tot = (int64_t)O * Ld * I;
+  const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (tid >= tot) return;
+  const int i = (int)(tid % I);
+  const int j = (int)((tid / I) % Ld);
+  const int o = (int)(tid / ((int64_t)I * Ld));
+  const bool isH = blockIdx.y == 0;
+  C* Y = isH ? outH : outS;
+  const C* T = tw + D.tw_off;
   R re = 0, im = 0;
+  int kk[3] = {0, 0, 0};
+  if (FIRST) {
+    int oo = o;
+    for (int q = d - 1; q >= 0; --q) {
+      const int ns = nslot(L.dim[q]);
+      kk[q] = slot_cell(L.dim[q], oo % ns);
+      oo /= ns;
+    }
+  }
   for (int b = 0; b < B; ++b) {
     const int k = slot_cell(D, b);
-    const C w = T[(int)(((int64_t)j * k) % D.L)];
-    const C x = src[(int64_t)b * I];
-    re += w.x * x.x - w.y * x.y;
-    im += w.x * x.y + w.y * x.x;
+    const C w = T[(int)(((int64_t)j * k) % Ld)];
+    R xr, xi;
+    if (FIRST) {
+      kk[d] = k;
+      const int cell = (kk[0] * L.L[1] + kk[1]) * L.L[2] + kk[2];
+      xr = ((const R*)(isH ? inH : inS))[L.gen_off + (int64_t)cell * L.m0 * L.m0 + i];
+      xi = R(0);
+    } else {
+      const C x = ((const C*)(isH ? inH : inS))[((int64_t)o * B + b) * I + i];
+      xr = x.x;
+      xi = x.y;
+    }
+    re += w.x * xr - w.y * xi;
+    im += w.x * xi + w.y * xr;
   }
   C r;
   r.x = re;
   r.y = im;
-  Y[idx] = r;
+  Y[tid] = r;
 }
 
 // A one-cell lattice: the single block is its own transform.
@@ -175,8 +235,8 @@ static hipError_t dft_lattice(const lhf_plan_s* p, int li, const R* gH, const R*
     for (int q = 0; q < 3; ++q) sz *= (q < d) ? nsl(q) : L.L[q];
     return sz;
   };
-  C* cur_h = nullptr;
-  C* cur_s = nullptr;
+  const void* cur_h = gH;
+  const void* cur_s = gS;
   for (int pi = 0; pi < nd; ++pi) {
     const int d = dims[pi];
     const bool last = pi + 1 == nd;
@@ -186,15 +246,35 @@ static hipError_t dft_lattice(const lhf_plan_s* p, int li, const R* gH, const R*
     C* os = last ? outS : dst + sz;
     int64_t O = 1;
     for (int q = 0; q < d; ++q) O *= nsl(q);
-    const int64_t tot = O * L.L[d] * (pi == 0 ? E : sz / (O * L.L[d]));
-    const dim3 grid((unsigned)((tot + 255) / 256), ny);
-    if (pi == 0) {
-      hipLaunchKernelGGL(dft_first_kernel<R>, grid, dim3(256), 0, s, p->d_lat, li, d, tw, gH, gS,
-                         oh ? oh : dst, os ? os : dst + sz);
+    const int Ld = L.L[d];
+    const int64_t I = pi == 0 ? E : sz / (O * Ld);
+    const int B = (int)nsl(d);
+    if (B <= 32) {
+      // chunk the transformed axis so that at least ~128k threads run
+      int64_t cols = O * I;
+      int JC = (int)std::max<int64_t>(1, std::min<int64_t>(Ld, cols * Ld / 131072));
+      const int njc = (Ld + JC - 1) / JC;
+      const dim3 grid((unsigned)((cols * njc + 255) / 256), ny);
+#define LHF_PASS(BM)                                                                                   \
+  if (pi == 0)                                                                                         \
+    hipLaunchKernelGGL((dft_pass_kernel<R, BM, true>), grid, dim3(256), 0, s, p->d_lat, li, d, (int)O, \
+                       (int)I, JC, tw, cur_h, cur_s, oh, os);                                          \
+  else                                                                                                 \
+    hipLaunchKernelGGL((dft_pass_kernel<R, BM, false>), grid, dim3(256), 0, s, p->d_lat, li, d, (int)O,\
+                       (int)I, JC, tw, cur_h, cur_s, oh, os);
+      if (B <= 4) { LHF_PASS(4) }
+      else if (B <= 8) { LHF_PASS(8) }
+      else if (B <= 16) { LHF_PASS(16) }
+      else { LHF_PASS(32) }
+#undef LHF_PASS
     } else {
-      const int64_t I = sz / (O * L.L[d]);
-      hipLaunchKernelGGL(dft_next_kernel<R>, grid, dim3(256), 0, s, p->d_lat, li, d, (int)O, I, tw,
-                         cur_h, cur_s, oh ? oh : dst, os ? os : dst + sz);
+      const dim3 grid((unsigned)((O * Ld * I + 255) / 256), ny);
+      if (pi == 0)
+        hipLaunchKernelGGL((dft_wide_kernel<R, true>), grid, dim3(256), 0, s, p->d_lat, li, d, (int)O, (int)I, tw,
+                           cur_h, cur_s, oh, os);
+      else
+        hipLaunchKernelGGL((dft_wide_kernel<R, false>), grid, dim3(256), 0, s, p->d_lat, li, d, (int)O, (int)I, tw,
+                           cur_h, cur_s, oh, os);
     }
     cur_h = dst;
     cur_s = dst + sz;

@@ -32,6 +32,7 @@ __device__ double cell_gauss(double x, double h, double t, double A) {
   }
   const double lo = t * (x - 0.5 * h - A);
   const double hi = t * (x + 0.5 * h - A);
+  if (lo > 27.5 || hi < -27.5) return 0.0;   // erfc below the smallest double
   double d;
   if (lo > 0.0) d = erfc(lo) - erfc(hi);
   else if (hi < 0.0) d = erfc(-hi) - erfc(-lo);
@@ -39,7 +40,9 @@ __device__ double cell_gauss(double x, double h, double t, double A) {
   return d * (0.886226925452758014 / t);  // sqrt(pi) / 2
 }
 
-// grid: x = node chunks of 256, y = row (m0 basis rows, then M0 R potential rows), z = dimension
+// Basis factors and one-cell potential factors: one thread per node.
+// grid: x = node chunks of 256, y = row (m0 basis rows, then M0 R potential
+// rows of one-cell dims), z = dimension
 __global__ void __launch_bounds__(256) factors_kernel(const LatDev* __restrict__ lats, int li,
                                                       double* __restrict__ fac) {
   const LatDev& L = lats[li];
@@ -64,27 +67,50 @@ __global__ void __launch_bounds__(256) factors_kernel(const LatDev* __restrict__
     return;
   }
   const int r = row - L.m0;           // potential term nu R + q
-  if (r >= L.M0 * L.R || i >= D.npot) return;
+  if (D.replicate || r >= L.M0 * L.R || i >= D.npot) return;
   const int nu = r / L.R, q = r % L.R;
-  const double t = L.tq[q];
-  const double A = L.nuc[nu][d];
-  double v;
-  if (D.replicate) {
-    const double y = D.y0 + i * D.h;    // offset from the centre of the node's cell
-    v = 0.0;
-    int klo, khi;
-    if (D.L & 1) { klo = -(D.L - 1) / 2; khi = (D.L - 1) / 2; }
-    else { klo = -D.L / 2; khi = D.L / 2; }
-    for (int k = klo; k <= khi; ++k) {
-      double wk = ((D.L & 1) == 0 && (k == klo || k == khi)) ? 0.5 : 1.0;
-      v += wk * cell_gauss(y, D.h, t, A + k * D.a);
-    }
-  } else {
-    const double x = D.x0 + i * D.h;
-    v = cell_gauss(x, D.h, t, D.X0 + A);
-  }
+  double v = cell_gauss(D.x0 + i * D.h, D.h, L.tq[q], D.X0 + L.nuc[nu][d]);
   if (d == 0) v *= L.Z[nu] * L.wq[q];
   fac[D.p_off + (int64_t)r * D.npot + i] = v;
+}
+
+// Lattice-window potential factors of replicated dims (eq. EwaldSumP): one
+// workgroup per (term, dimension); thread t sums the images k = klo + c,
+// c = t / nc (mod 256 / nc), for node t % nc of the central cell; the chunk
+// sums are added in a fixed order, so the result is deterministic.
+__global__ void __launch_bounds__(256) window_kernel(const LatDev* __restrict__ lats, int li,
+                                                     double* __restrict__ fac) {
+  __shared__ double part[256];
+  const LatDev& L = lats[li];
+  const int d = blockIdx.y;
+  const DimDev& D = L.dim[d];
+  const int r = blockIdx.x;
+  if (!D.replicate || r >= L.M0 * L.R) return;   // uniform over the workgroup
+  const int nu = r / L.R, q = r % L.R;
+  const double t = L.tq[q], A = L.nuc[nu][d];
+  const int nc = D.nc;
+  const int chunks = 256 / nc;
+  const int tid = threadIdx.x;
+  const int j = tid % nc, c = tid / nc;
+  int klo, khi;
+  if (D.L & 1) { klo = -(D.L - 1) / 2; khi = (D.L - 1) / 2; }
+  else { klo = -D.L / 2; khi = D.L / 2; }
+  double acc = 0.0;
+  if (c < chunks) {
+    const double y = D.y0 + j * D.h;
+    for (int k = klo + c; k <= khi; k += chunks) {
+      const double wk = ((D.L & 1) == 0 && (k == klo || k == khi)) ? 0.5 : 1.0;
+      acc += wk * cell_gauss(y, D.h, t, A + k * D.a);
+    }
+  }
+  part[tid] = acc;
+  __syncthreads();
+  if (tid < nc) {
+    double v = 0.0;
+    for (int cc = 0; cc < chunks; ++cc) v += part[cc * nc + tid];
+    if (d == 0) v *= L.Z[nu] * L.wq[q];
+    fac[D.p_off + (int64_t)r * D.npot + tid] = v;
+  }
 }
 
 }  // namespace
@@ -95,6 +121,7 @@ hipError_t launch_factors(const lhf_plan_s* p, int li, double* fac, hipStream_t 
   for (int d = 0; d < 3; ++d) nmax = std::max(nmax, std::max(L.dim[d].n, L.dim[d].npot));
   dim3 grid((nmax + 255) / 256, L.m0 + L.M0 * L.R, 3);
   hipLaunchKernelGGL(factors_kernel, grid, dim3(256), 0, s, p->d_lat, li, fac);
+  hipLaunchKernelGGL(window_kernel, dim3(L.M0 * L.R, 3), dim3(256), 0, s, p->d_lat, li, fac);
   return hipGetLastError();
 }
 

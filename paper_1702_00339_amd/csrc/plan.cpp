@@ -94,6 +94,10 @@ static int32_t derive_lattice(const lhf_lattice& in, int idx, LatDev& L, std::st
     DimDev& D = L.dim[d];
     int Ld = in.L[d], nd = in.n[d];
     if (Ld < 1) return bad("L must be >= 1");
+    if (Ld > 32768) {
+      err = "lattice " + std::to_string(idx) + ": more than 32768 cells along one dimension unsupported";
+      return LHF_ERR_UNSUPPORTED;
+    }
     if (nd < 4) return bad("n must be >= 4");
     L.L[d] = Ld;
     nblk *= Ld;
@@ -104,6 +108,10 @@ static int32_t derive_lattice(const lhf_lattice& in, int idx, LatDev& L, std::st
       D.periodic = 1; D.replicate = 1;
       D.nc = nd / Ld; D.npot = D.nc;
       if (D.nc < 2) return bad("need at least two nodes per cell");
+      if (D.nc > 256) {
+        err = "lattice " + std::to_string(idx) + ": more than 256 nodes per cell unsupported";
+        return LHF_ERR_UNSUPPORTED;
+      }
       D.h = Ld * in.a / nd;
       D.x0 = 0.0;
       D.X0 = 0.5 * in.a;
@@ -224,6 +232,22 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->ws_dft_b = off; off = align256(off + (size_t)dtmp * 16);
   p->sizes.ws_bytes = off;
 
+  // canonical blocks: j with (-j mod L) >= j in linear order
+  std::vector<int32_t> canon;
+  p->canon_off.resize(nlat);
+  p->ncanon.resize(nlat);
+  for (int i = 0; i < nlat; ++i) {
+    const LatDev& L = p->lat[i];
+    p->canon_off[i] = (int64_t)canon.size();
+    for (int b = 0; b < L.nblk; ++b) {
+      const int k3 = b % L.L[2], k2 = (b / L.L[2]) % L.L[1], k1 = b / (L.L[2] * L.L[1]);
+      const int c1 = k1 ? L.L[0] - k1 : 0, c2 = k2 ? L.L[1] - k2 : 0, c3 = k3 ? L.L[2] - k3 : 0;
+      const int cb = (c1 * L.L[1] + c2) * L.L[2] + c3;
+      if (cb >= b) canon.push_back(b);
+    }
+    p->ncanon[i] = (int32_t)((int64_t)canon.size() - p->canon_off[i]);
+  }
+
   // twiddle tables exp(-2 pi i m / L)
   std::vector<double2> tw64(tw);
   std::vector<float2> tw32(tw);
@@ -240,14 +264,16 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   if (hipGetDevice(&p->device) != hipSuccess ||
       hipMalloc(&p->d_lat, sizeof(LatDev) * nlat) != hipSuccess ||
       hipMalloc(&p->d_tw64, sizeof(double2) * tw) != hipSuccess ||
-      hipMalloc(&p->d_tw32, sizeof(float2) * tw) != hipSuccess) {
+      hipMalloc(&p->d_tw32, sizeof(float2) * tw) != hipSuccess ||
+      hipMalloc(&p->d_canon, sizeof(int32_t) * canon.size()) != hipSuccess) {
     set_error("device allocation of the plan tables failed");
     lhf_plan_destroy(p);
     return LHF_ERR_ALLOC;
   }
   if (hipMemcpy(p->d_lat, p->lat.data(), sizeof(LatDev) * nlat, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->d_tw64, tw64.data(), sizeof(double2) * tw, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->d_tw32, tw32.data(), sizeof(float2) * tw, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(p->d_tw32, tw32.data(), sizeof(float2) * tw, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_canon, canon.data(), sizeof(int32_t) * canon.size(), hipMemcpyHostToDevice) != hipSuccess) {
     set_error("upload of the plan tables failed");
     lhf_plan_destroy(p);
     return LHF_ERR_HIP;
@@ -262,6 +288,20 @@ int32_t lhf_plan_sizes(lhf_plan_t plan, lhf_sizes* out) {
   return LHF_OK;
 }
 
+int32_t lhf_plan_band(lhf_plan_t plan, int32_t index, int32_t* nshift, int32_t* L0, int32_t* full) {
+  if (!plan || !nshift || !L0 || !full || index < 0 || index >= plan->nlat) {
+    set_error("lhf_plan_band: bad argument");
+    return LHF_ERR_INVALID;
+  }
+  for (int d = 0; d < 3; ++d) {
+    const DimDev& D = plan->lat[index].dim[d];
+    nshift[d] = D.nshift;
+    L0[d] = D.L0;
+    full[d] = D.full;
+  }
+  return LHF_OK;
+}
+
 size_t lhf_workspace_size(lhf_plan_t plan) { return plan ? plan->sizes.ws_bytes : 0; }
 
 int32_t lhf_plan_destroy(lhf_plan_t plan) {
@@ -269,6 +309,7 @@ int32_t lhf_plan_destroy(lhf_plan_t plan) {
   if (plan->d_lat) (void)hipFree(plan->d_lat);
   if (plan->d_tw64) (void)hipFree(plan->d_tw64);
   if (plan->d_tw32) (void)hipFree(plan->d_tw32);
+  if (plan->d_canon) (void)hipFree(plan->d_canon);
   delete plan;
   return LHF_OK;
 }

@@ -19,6 +19,9 @@ struct lhf_plan_s {
   lhf::LatDev* d_lat = nullptr;         // device table [nlat]
   double2* d_tw64 = nullptr;            // twiddles, complex128
   float2* d_tw32 = nullptr;             // twiddles, complex64
+  int32_t* d_canon = nullptr;           // canonical block of each conjugate pair, per lattice
+  std::vector<int64_t> canon_off;       // offset of each lattice's list in d_canon
+  std::vector<int32_t> ncanon;          // list length per lattice
   lhf_sizes sizes{};
   // element counts of the workspace sections
   int64_t fac_doubles = 0;

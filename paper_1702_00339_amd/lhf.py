@@ -64,6 +64,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "lhf_plan_create": (i32, [C.POINTER(lhf_lattice), i32, i32, i32, C.POINTER(vp)]),
         "lhf_plan_sizes": (i32, [vp, C.POINTER(lhf_sizes)]),
+        "lhf_plan_band": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "lhf_workspace_size": (sz, [vp]),
         "lhf_plan_destroy": (i32, [vp]),
         "lhf_assemble_blocks": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
@@ -83,7 +84,7 @@ def load(path: str = LIB_PATH):
 
 def exported_symbols():
     """Names the binding expects the library to export."""
-    return ["lhf_plan_create", "lhf_plan_sizes", "lhf_workspace_size", "lhf_plan_destroy",
+    return ["lhf_plan_create", "lhf_plan_sizes", "lhf_plan_band", "lhf_workspace_size", "lhf_plan_destroy",
             "lhf_assemble_blocks", "lhf_block_fft", "lhf_heev_batched", "lhf_status_string",
             "lhf_last_error", "lhf_version"]
 
@@ -167,6 +168,12 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def lhf_plan_band(self, index=0):
+        """(nshift, L0, full) per dimension of lattice ``index``."""
+        ns, l0, fu = (C.c_int32 * 3)(), (C.c_int32 * 3)(), (C.c_int32 * 3)()
+        _check(load().lhf_plan_band(self.handle, index, ns, l0, fu))
+        return list(ns), list(l0), list(fu)
 
     # ----------------------------------------------------------------- buffers
     def workspace(self, device="cuda"):
