@@ -41,19 +41,20 @@ int32_t lhf_assemble_blocks(lhf_plan_t p, void* H_gen, void* S_gen, double* gram
   const bool mixed = p->prec == LHF_PREC_MIXED;
   const bool split = mixed && p->gram != LHF_GRAM_FP64;
   const bool need64 = !mixed || !split || grams64 || H_gen64;
+  hipError_t e;
   for (int li = 0; li < p->nlat; ++li) {
-    hipError_t e = launch_factors(p, li, w.fac, s);
+    e = launch_factors(p, li, w.fac, s);
     if ((st = hip_status(e, "factors")) != LHF_OK) return st;
-    for (int d = 0; d < 3; ++d) {
-      if (need64) {
-        e = launch_gram_f64(p, li, d, w.fac, w.part64, g64, s);
-        if ((st = hip_status(e, "gram fp64")) != LHF_OK) return st;
-      }
-      if (split) {
-        e = launch_gram_split(p, li, d, p->gram, w.fac, w.part32, w.grams32, s);
-        if ((st = hip_status(e, "gram split")) != LHF_OK) return st;
-      }
-    }
+  }
+  if (need64) {
+    e = launch_grams(p, LHF_GRAM_FP64, w.fac, w.part64, g64, s);
+    if ((st = hip_status(e, "gram fp64")) != LHF_OK) return st;
+  }
+  if (split) {
+    e = launch_grams(p, p->gram, w.fac, w.part32, w.grams32, s);
+    if ((st = hip_status(e, "gram split")) != LHF_OK) return st;
+  }
+  for (int li = 0; li < p->nlat; ++li) {
     if (!mixed) {
       e = launch_combine(p, li, g64, nullptr, (double*)H_gen, (double*)S_gen, nullptr, nullptr, s);
     } else {

@@ -23,6 +23,8 @@ template <typename R> struct Cx;
 template <> struct Cx<double> { typedef double2 T; };
 template <> struct Cx<float> { typedef float2 T; };
 
+constexpr int kLdsTwiddles = 2048;   // longest axis whose twiddles are staged in LDS
+
 __device__ __forceinline__ int slot_cell(const DimDev& D, int s) {
   if (D.full) return s;
   int k = s - D.L0;
@@ -51,6 +53,14 @@ __global__ void __launch_bounds__(256) dft_pass_kernel(const LatDev* __restrict_
   const int B = nslot(D);
   const int njc = (Ld + JC - 1) / JC;
   const int tid = blockIdx.x * 256 + threadIdx.x;
+  // twiddle table staged in LDS when the launch gives room for it
+  extern __shared__ char lds_raw[];
+  C* sT = reinterpret_cast<C*>(lds_raw);
+  const bool lds_tw = Ld <= kLdsTwiddles;
+  if (lds_tw) {
+    for (int q = threadIdx.x; q < Ld; q += 256) sT[q] = tw[D.tw_off + q];
+    __syncthreads();
+  }
   if (tid >= O * njc * I) return;
   const int i = tid % I;
   const int jc = (tid / I) % njc;
@@ -97,7 +107,7 @@ __global__ void __launch_bounds__(256) dft_pass_kernel(const LatDev* __restrict_
 #pragma unroll
   for (int b = 0; b < BMAX; ++b)
     if (b < B) idx[b] = (j0 * kb[b]) % Ld;
-  const C* T = tw + D.tw_off;
+  const C* T = lds_tw ? sT : tw + D.tw_off;
   C* dst = Y + (int64_t)o * Ld * I + i;
   for (int j = j0; j < j1; ++j) {
     R re = 0, im = 0;
@@ -255,12 +265,13 @@ static hipError_t dft_lattice(const lhf_plan_s* p, int li, const R* gH, const R*
       int JC = (int)std::max<int64_t>(1, std::min<int64_t>(Ld, cols * Ld / 131072));
       const int njc = (Ld + JC - 1) / JC;
       const dim3 grid((unsigned)((cols * njc + 255) / 256), ny);
-#define LHF_PASS(BM)                                                                                   \
-  if (pi == 0)                                                                                         \
-    hipLaunchKernelGGL((dft_pass_kernel<R, BM, true>), grid, dim3(256), 0, s, p->d_lat, li, d, (int)O, \
-                       (int)I, JC, tw, cur_h, cur_s, oh, os);                                          \
-  else                                                                                                 \
-    hipLaunchKernelGGL((dft_pass_kernel<R, BM, false>), grid, dim3(256), 0, s, p->d_lat, li, d, (int)O,\
+      const size_t shb = Ld <= kLdsTwiddles ? sizeof(C) * Ld : 0;
+#define LHF_PASS(BM)                                                                                     \
+  if (pi == 0)                                                                                           \
+    hipLaunchKernelGGL((dft_pass_kernel<R, BM, true>), grid, dim3(256), shb, s, p->d_lat, li, d, (int)O, \
+                       (int)I, JC, tw, cur_h, cur_s, oh, os);                                            \
+  else                                                                                                   \
+    hipLaunchKernelGGL((dft_pass_kernel<R, BM, false>), grid, dim3(256), shb, s, p->d_lat, li, d, (int)O,\
                        (int)I, JC, tw, cur_h, cur_s, oh, os);
       if (B <= 4) { LHF_PASS(4) }
       else if (B <= 8) { LHF_PASS(8) }

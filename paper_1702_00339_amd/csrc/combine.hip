@@ -26,10 +26,10 @@ __global__ void __launch_bounds__(256) combine_kernel(const LatDev* __restrict__
                                                       O* __restrict__ H, O* __restrict__ S) {
   const LatDev& L = lats[li];
   const int m2 = L.m0 * L.m0;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)L.nblk * m2) return;
-  const int e = (int)(idx % m2);
-  const int cell = (int)(idx / m2);
+  const int idx = blockIdx.x * 256 + threadIdx.x;   // the planner keeps nblk m0^2 < 2^31
+  if (idx >= L.nblk * m2) return;
+  const int cell = idx / m2;
+  const int e = idx - cell * m2;
   const int k3 = cell % L.L[2];
   const int k2 = (cell / L.L[2]) % L.L[1];
   const int k1 = cell / (L.L[2] * L.L[1]);

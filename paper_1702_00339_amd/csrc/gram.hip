@@ -6,16 +6,23 @@
 // Op_0 = S = (h/6) tridiag(1, 4, 1), Op_1 = A = (1/h) tridiag(-1, 2, -1)
 // (cyclic on periodic dims, truncated on box dims), Op_(2+r) = diag(P_r).
 // This is one GEMM C = A B with rows (t, nu), columns (s, mu) and the grid as
-// the contraction index; the operands are formed in registers from the
-// L2-resident factors (the shifted right operand is a cyclic window of G, so
-// it is never materialised).  Each wave owns a 32 x 32 output tile (2 x 2
-// MFMA tiles); the contraction is split over waves and the partial tiles are
-// summed by a second kernel that also scatters to the Gram layout
-// [t][s][mu][nu].
+// the contraction index, restricted to the window of nodes where the cell-0
+// factor in every summand is not negligible (all nodes on one-cell dims).
 //
-// Variants: FP64 (v_mfma_f64_16x16x4f64), FP32 operands
-// (v_mfma_f32_16x16x4f32), and bf16 hi+lo split products
-// hi*hi + hi*lo + lo*hi (v_mfma_f32_16x16x32_bf16), both with FP32 accumulation.
+// Grouped launch: one work list covers every lattice, dimension, 64 x 64
+// output tile and split of the window.  A workgroup (4 waves) stages 32-node
+// chunks of both operands in LDS -- the left operand formed from the factors
+// (stencil or potential product), the right one a cyclic window of G, so the
+// shifted copies are never materialised -- and each wave accumulates a
+// 32 x 32 sub-tile with MFMA.  Partial tiles of the splits are summed by a
+// grouped reduction that also scatters to the Gram layout [t][s][mu][nu].
+//
+// Arithmetic: FP64 (v_mfma_f64_16x16x4f64), FP32 operands
+// (v_mfma_f32_16x16x4f32), or bf16 hi+lo split products hi*hi + hi*lo + lo*hi
+// (v_mfma_f32_16x16x32_bf16), the last two with FP32 accumulation.
+#include <algorithm>
+#include <type_traits>
+
 #include "plan.h"
 
 namespace lhf {
@@ -25,10 +32,8 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int TM = 2, TN = 2;   // 16 x 16 MFMA tiles per wave along rows / columns
-
-struct RowInfo { int t, nu; bool ok; };
-struct ColInfo { int mu, sn; bool ok; };
+constexpr int KC = 32;   // window nodes per LDS chunk
+constexpr int TILE = 64; // workgroup output tile (rows and columns)
 
 __device__ __forceinline__ double gval(const double* G, const DimDev& D, int m0, int j, int f) {
   if (D.periodic) {
@@ -39,235 +44,173 @@ __device__ __forceinline__ double gval(const double* G, const DimDev& D, int m0,
   return G[(int64_t)j * m0 + f];
 }
 
-// Left operand (Op_t G)[i][nu].
-__device__ __forceinline__ double aval(const double* G, const double* P, const DimDev& D, int m0,
-                                       const RowInfo& r, int i) {
-  if (!r.ok || i >= D.n) return 0.0;
-  double g0 = gval(G, D, m0, i, r.nu);
-  if (r.t >= 2) {
-    int pi = D.replicate ? i % D.nc : i;
-    return P[(int64_t)(r.t - 2) * D.npot + pi] * g0;
-  }
-  double gm = gval(G, D, m0, i - 1, r.nu), gp = gval(G, D, m0, i + 1, r.nu);
-  if (r.t == 0) return (D.h / 6.0) * (gm + 4.0 * g0 + gp);
-  return (2.0 * g0 - gm - gp) / D.h;
-}
-
-// Right operand G[(i - k_s nc) mod n][mu].
-__device__ __forceinline__ double bval(const double* G, const DimDev& D, int m0, const ColInfo& c,
-                                       int i) {
-  if (!c.ok || i >= D.n) return 0.0;
-  int j = i - c.sn;
-  if (j < 0) j += D.n;
-  return G[(int64_t)j * m0 + c.mu];
-}
-
-__device__ __forceinline__ void lane_info(const LatDev& L, const DimDev& D, int tm, int tn, int lr,
-                                          RowInfo* ri, ColInfo* ci) {
-  const int M = L.T * L.m0, N = D.nshift * L.m0;
+template <int MODE>
+__global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ lats,
+                                                   const GramItem* __restrict__ items, int nitems,
+                                                   const double* __restrict__ fac, void* __restrict__ part_) {
+  __shared__ double As[KC][TILE + 1];
+  __shared__ double Bs[KC][TILE + 1];
+  typedef typename std::conditional<MODE == 0, d4, f4>::type Acc;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const GramItem item = items[it];
+    const LatDev& L = lats[item.li];
+    const DimDev& D = L.dim[item.d];
+    const int m0 = L.m0, M = L.T * m0, N = D.nshift * m0;
+    const double* G = fac + D.g_off;
+    const double* P = fac + D.p_off;
+    const int row0 = item.tm * TILE, col0 = item.tn * TILE;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // wave sub-tile within the tile
+    Acc acc[2][2];
 #pragma unroll
-  for (int a = 0; a < TM; ++a) {
-    int r = (tm * TM + a) * 16 + lr;
-    ri[a].ok = r < M;
-    ri[a].t = r / L.m0;
-    ri[a].nu = r % L.m0;
-  }
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-  for (int b = 0; b < TN; ++b) {
-    int c = (tn * TN + b) * 16 + lr;
-    ci[b].ok = c < N;
-    int slot = c / L.m0;
-    ci[b].mu = c % L.m0;
-    int k = D.full ? slot : slot - D.L0;
+      for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+    const int k_beg = item.ks * D.kchunk;
+    const int k_end = min(D.kwin, k_beg + D.kchunk);
+    // this thread stages column `col` of both operand tiles, nodes kq + 4 v
+    const int col = tid & (TILE - 1), kq = tid >> 6;
+    const int r = row0 + col, c = col0 + col;
+    const bool rok = r < M, cok = c < N;
+    const int t = r / m0, nu = r - t * m0;
+    const int slot = c / m0, mu = c - slot * m0;
     int sn = 0;
     if (D.periodic) {
-      sn = (int)(((int64_t)k * D.nc) % D.n);
+      const int k = D.full ? slot : slot - D.L0;
+      sn = (k * D.nc) % D.n;
       if (sn < 0) sn += D.n;
     }
-    ci[b].sn = sn;
+    const double* Pt = P + (int64_t)(t >= 2 ? t - 2 : 0) * D.npot;
+    const double h6 = D.h / 6.0, hinv = 1.0 / D.h;
+    for (int kc0 = k_beg; kc0 < k_end; kc0 += KC) {
+#pragma unroll
+      for (int v = 0; v < KC / 4; ++v) {
+        const int kk = kq + 4 * v;
+        const int k = kc0 + kk;
+        double av = 0.0, bv = 0.0;
+        if (k < k_end) {
+          int i = D.kstart + k;
+          if (i >= D.n) i -= D.n;
+          if (rok) {
+            const double g0 = G[(int64_t)i * m0 + nu];
+            if (t >= 2) {
+              av = Pt[D.replicate ? i % D.nc : i] * g0;
+            } else {
+              const double gm = gval(G, D, m0, i - 1, nu), gp = gval(G, D, m0, i + 1, nu);
+              av = t == 0 ? h6 * (gm + 4.0 * g0 + gp) : hinv * (2.0 * g0 - gm - gp);
+            }
+          }
+          if (cok) {
+            int j = i - sn;
+            if (j < 0) j += D.n;
+            bv = G[(int64_t)j * m0 + mu];
+          }
+        }
+        As[kk][col] = av;
+        Bs[kk][col] = bv;
+      }
+      __syncthreads();
+      if constexpr (MODE == 2) {
+        bf8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const float x = (float)As[8 * lk + e][wr + a * 16 + lr];
+            const __bf16 hi = (__bf16)x;
+            ah[a][e] = hi;
+            al[a][e] = (__bf16)(x - (float)hi);
+          }
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const float x = (float)Bs[8 * lk + e][wc + b * 16 + lr];
+            const __bf16 hi = (__bf16)x;
+            bh[b][e] = hi;
+            bl[b][e] = (__bf16)(x - (float)hi);
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              const double x = As[kk + lk][wr + a * 16 + lr];
+              const double y = Bs[kk + lk][wc + b * 16 + lr];
+              if constexpr (MODE == 0)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[a][b], 0, 0, 0);
+              else
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)x, (float)y, acc[a][b], 0, 0, 0);
+            }
+        }
+      }
+      __syncthreads();
+    }
+    // result layout: f64 MFMA row lk + 4 v; f32 / bf16 MFMA row 4 lk + v; column lr
+    typedef typename std::conditional<MODE == 0, double, float>::type T;
+    T* out = reinterpret_cast<T*>(part_) + D.part_off + (int64_t)item.ks * M * N;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int c = col0 + wc + b * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = row0 + wr + a * 16 + (MODE == 0 ? lk + 4 * v : 4 * lk + v);
+          if (r < M && c < N) out[(int64_t)r * N + c] = (T)acc[a][b][v];
+        }
+      }
   }
 }
 
-__global__ void __launch_bounds__(64) gram_f64_kernel(const LatDev* __restrict__ lats, int li, int d,
-                                                      const double* __restrict__ fac,
-                                                      double* __restrict__ part) {
-  const LatDev& L = lats[li];
-  const DimDev& D = L.dim[d];
-  const int M = L.T * L.m0, N = D.nshift * L.m0;
-  const int tiles_n = (N + 16 * TN - 1) / (16 * TN);
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
-  const int ks = blockIdx.y;
-  const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
-  const double* G = fac + D.g_off;
-  const double* P = fac + D.p_off;
-  RowInfo ri[TM];
-  ColInfo ci[TN];
-  lane_info(L, D, tm, tn, lr, ri, ci);
-  d4 acc[TM][TN];
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < TN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  const int k_beg = ks * D.kchunk;
-  const int k_end = min(D.n, k_beg + D.kchunk);
-  for (int k0 = k_beg; k0 < k_end; k0 += 4) {
-    const int i = k0 + lk;
-    double av[TM], bv[TN];
-#pragma unroll
-    for (int a = 0; a < TM; ++a) av[a] = aval(G, P, D, L.m0, ri[a], i);
-#pragma unroll
-    for (int b = 0; b < TN; ++b) bv[b] = bval(G, D, L.m0, ci[b], i);
-#pragma unroll
-    for (int a = 0; a < TM; ++a)
-#pragma unroll
-      for (int b = 0; b < TN; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-  }
-  // v_mfma_f64_16x16x4f64 result layout: row lk + 4 v, column lr
-  double* out = part + D.part_off + (int64_t)ks * M * N;
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < TN; ++b) {
-      const int c = (tn * TN + b) * 16 + lr;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = (tm * TM + a) * 16 + lk + 4 * v;
-        if (r < M && c < N) out[(int64_t)r * N + c] = acc[a][b][v];
-      }
-    }
-}
-
-// Split-precision variants; MODE 1 = FP32 operands, MODE 2 = bf16 hi + lo.
-template <int MODE>
-__global__ void __launch_bounds__(64) gram_split_kernel(const LatDev* __restrict__ lats, int li,
-                                                        int d, const double* __restrict__ fac,
-                                                        float* __restrict__ part) {
-  const LatDev& L = lats[li];
-  const DimDev& D = L.dim[d];
-  const int M = L.T * L.m0, N = D.nshift * L.m0;
-  const int tiles_n = (N + 16 * TN - 1) / (16 * TN);
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
-  const int ks = blockIdx.y;
-  const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
-  const double* G = fac + D.g_off;
-  const double* P = fac + D.p_off;
-  RowInfo ri[TM];
-  ColInfo ci[TN];
-  lane_info(L, D, tm, tn, lr, ri, ci);
-  f4 acc[TM][TN];
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
-  const int k_beg = ks * D.kchunk;
-  const int k_end = min(D.n, k_beg + D.kchunk);
-  if constexpr (MODE == 1) {
-    for (int k0 = k_beg; k0 < k_end; k0 += 4) {
-      const int i = k0 + lk;
-      float av[TM], bv[TN];
-#pragma unroll
-      for (int a = 0; a < TM; ++a) av[a] = (float)aval(G, P, D, L.m0, ri[a], i);
-#pragma unroll
-      for (int b = 0; b < TN; ++b) bv[b] = (float)bval(G, D, L.m0, ci[b], i);
-#pragma unroll
-      for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int b = 0; b < TN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
-    }
-  } else {
-    for (int k0 = k_beg; k0 < k_end; k0 += 32) {
-      bf8 ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int i = k0 + 8 * lk + e;
-#pragma unroll
-        for (int a = 0; a < TM; ++a) {
-          float x = (float)aval(G, P, D, L.m0, ri[a], i);
-          __bf16 hi = (__bf16)x;
-          ah[a][e] = hi;
-          al[a][e] = (__bf16)(x - (float)hi);
-        }
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-          float x = (float)bval(G, D, L.m0, ci[b], i);
-          __bf16 hi = (__bf16)x;
-          bh[b][e] = hi;
-          bl[b][e] = (__bf16)(x - (float)hi);
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < TM; ++a)
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
-        }
-    }
-  }
-  // f32 / bf16 MFMA result layout: row 4 lk + v, column lr
-  float* out = part + D.part_off + (int64_t)ks * M * N;
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < TN; ++b) {
-      const int c = (tn * TN + b) * 16 + lr;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = (tm * TM + a) * 16 + 4 * lk + v;
-        if (r < M && c < N) out[(int64_t)r * N + c] = acc[a][b][v];
-      }
-    }
-}
-
-// Sum the split-K partials and scatter C[(t, nu)][(s, mu)] to Gram[t][s][mu][nu].
+// Sum the split partials and scatter C[(t, nu)][(s, mu)] to Gram[t][s][mu][nu];
+// blockIdx.y enumerates (lattice, dimension).
 template <typename T>
-__global__ void __launch_bounds__(256) gram_reduce_kernel(const LatDev* __restrict__ lats, int li, int d,
-                                                          const T* __restrict__ part,
-                                                          T* __restrict__ grams) {
+__global__ void __launch_bounds__(256) gram_reduce_kernel(const LatDev* __restrict__ lats,
+                                                          const T* __restrict__ part, T* __restrict__ grams) {
+  const int li = blockIdx.y / 3, d = blockIdx.y % 3;
   const LatDev& L = lats[li];
   const DimDev& D = L.dim[d];
   const int M = L.T * L.m0, N = D.nshift * L.m0;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)M * N) return;
-  const int r = (int)(idx / N), c = (int)(idx % N);
-  const T* src = part + D.part_off + idx;
-  T acc = 0;
-  for (int ks = 0; ks < D.ksplit; ++ks) acc += src[(int64_t)ks * M * N];
-  const int t = r / L.m0, nu = r % L.m0, slot = c / L.m0, mu = c % L.m0;
-  grams[D.gram_off + (((int64_t)t * D.nshift + slot) * L.m0 + mu) * L.m0 + nu] = acc;
+  const int MN = M * N;
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < MN; idx += gridDim.x * 256) {
+    const int r = idx / N, c = idx - r * N;
+    const T* src = part + D.part_off + idx;
+    T acc = 0;
+    for (int ks = 0; ks < D.ksplit; ++ks) acc += src[(int64_t)ks * MN];
+    const int t = r / L.m0, nu = r - t * L.m0, slot = c / L.m0, mu = c - slot * L.m0;
+    grams[D.gram_off + (((int64_t)t * D.nshift + slot) * L.m0 + mu) * L.m0 + nu] = acc;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_gram_f64(const lhf_plan_s* p, int li, int d, const double* fac, double* part,
-                           double* grams, hipStream_t s) {
-  const LatDev& L = p->lat[li];
-  const DimDev& D = L.dim[d];
-  const int M = L.T * L.m0, N = D.nshift * L.m0;
-  const int tiles = ((M + 16 * TM - 1) / (16 * TM)) * ((N + 16 * TN - 1) / (16 * TN));
-  hipLaunchKernelGGL(gram_f64_kernel, dim3(tiles, D.ksplit), dim3(64), 0, s, p->d_lat, li, d, fac, part);
-  const int64_t tot = (int64_t)M * N;
-  hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     p->d_lat, li, d, part, grams);
-  return hipGetLastError();
-}
-
-hipError_t launch_gram_split(const lhf_plan_s* p, int li, int d, int mode, const double* fac,
-                             float* part, float* grams, hipStream_t s) {
-  const LatDev& L = p->lat[li];
-  const DimDev& D = L.dim[d];
-  const int M = L.T * L.m0, N = D.nshift * L.m0;
-  const int tiles = ((M + 16 * TM - 1) / (16 * TM)) * ((N + 16 * TN - 1) / (16 * TN));
-  if (mode == LHF_GRAM_FP32)
-    hipLaunchKernelGGL(gram_split_kernel<1>, dim3(tiles, D.ksplit), dim3(64), 0, s, p->d_lat, li, d, fac, part);
+hipError_t launch_grams(const lhf_plan_s* p, int mode, const double* fac, void* part, void* grams,
+                        hipStream_t s) {
+  const int grid = std::min(p->n_gram_items, 4096);
+  if (mode == LHF_GRAM_FP64)
+    hipLaunchKernelGGL(gram_kernel<0>, dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+  else if (mode == LHF_GRAM_FP32)
+    hipLaunchKernelGGL(gram_kernel<1>, dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
   else
-    hipLaunchKernelGGL(gram_split_kernel<2>, dim3(tiles, D.ksplit), dim3(64), 0, s, p->d_lat, li, d, fac, part);
-  const int64_t tot = (int64_t)M * N;
-  hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     p->d_lat, li, d, part, grams);
+    hipLaunchKernelGGL(gram_kernel<2>, dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+  int64_t maxmn = 0;
+  for (const LatDev& L : p->lat)
+    for (int d = 0; d < 3; ++d) maxmn = std::max<int64_t>(maxmn, (int64_t)L.T * L.m0 * L.dim[d].nshift * L.m0);
+  const dim3 rgrid((unsigned)std::min<int64_t>((maxmn + 255) / 256, 1024), (unsigned)(3 * p->nlat));
+  if (mode == LHF_GRAM_FP64)
+    hipLaunchKernelGGL(gram_reduce_kernel<double>, rgrid, dim3(256), 0, s, p->d_lat, (const double*)part, (double*)grams);
+  else
+    hipLaunchKernelGGL(gram_reduce_kernel<float>, rgrid, dim3(256), 0, s, p->d_lat, (const float*)part, (float*)grams);
   return hipGetLastError();
 }
 

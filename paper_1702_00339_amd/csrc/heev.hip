@@ -73,13 +73,14 @@ struct Smem {
   C F[G][M][M + 1];              // Cholesky factor
   C V[HASV ? G : 1][HASV ? M : 1][M + 1];
   C U[HASU ? G : 1][HASU ? M : 1][M + 1];
+  R red[G][4];                   // cross-wave partial sums
+  R lam[G][M];
   R jc[G][M / 2];                // rotation cosine per pair
   C js[G][M / 2];                // s b / |b| per pair
   R dn[G][M];                    // rotated diagonal
-  R red[G][4];                   // cross-wave partial sums
-  R lam[G][M];
   int rank[G][M];
   int flag[G][4];                // 0: Cholesky failure column, 1: non-finite, 2: converged
+  C tw[HASU ? G : 1][HASU ? 32 : 1];   // refinement: twiddles of up to 32 band cells
 };
 
 // Sum over the TPM threads of one matrix; all threads of the workgroup call it.
@@ -103,13 +104,17 @@ __device__ __forceinline__ R group_sum(Smem<R, M, G, HASU, HASV>& sh, int g, int
   }
 }
 
-// Cholesky of B into F, reduction of A, Jacobi on A (with V if WANTV),
-// eigenvalues into lam/rank and, with WANTV, eigenvectors C^-H V into A.
-template <typename R, int M, int G, bool HASU, bool WANTV>
-__device__ void solve_pair(Smem<R, M, G, HASU, HASU || WANTV>& sh, int g, int t, int m, int maxsw, R tol) {
+// Entries owned by thread t of a matrix in the O(M^3) phases: t + k TPM, k < 4.
+#define LHF_FOR_ENTRIES                                   \
+  _Pragma("unroll") for (int k = 0; k < 4; ++k)           \
+    if (const int e = t + k * TPM, r = e / M, c = e % M; true)
+
+// 1-2. Cholesky of B into F (B is overwritten), A <- F^-1 A F^-H (Hermitian);
+// V <- I when HASV.
+template <typename R, int M, int G, bool HASU, bool HASV>
+__device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
   typedef typename Cx<R>::T C;
-  constexpr int H = M / 2, TPM = H * H;
-  // ---- 1. Cholesky: F[:, j] = B[:, j] / sqrt(B_jj); trailing update of B
+  constexpr int TPM = (M / 2) * (M / 2);
 #pragma unroll 1
   for (int j = 0; j < M; ++j) {
     const R d = sh.B[g][j][j].x;
@@ -117,32 +122,25 @@ __device__ void solve_pair(Smem<R, M, G, HASU, HASU || WANTV>& sh, int g, int t,
     const R piv = ok ? sqrt(d) : R(1);
     const R dinv = ok ? R(1) / d : R(1);
     if (t == 0 && !ok && sh.flag[g][0] == 0) sh.flag[g][0] = j + 1;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = t + k * TPM, r = e / M, c = e % M;
+    LHF_FOR_ENTRIES {
       if (c == j && r >= j) sh.F[g][r][j] = r == j ? cmk<C>(piv, R(0)) : cscale(sh.B[g][r][j], R(1) / piv);
       else if (c > j && r >= c)
         sh.B[g][r][c] = csub(sh.B[g][r][c], cscale(cmulc(sh.B[g][c][j], sh.B[g][r][j]), dinv));
     }
     __syncthreads();
   }
-  // ---- 2. A <- F^-1 A into B, then A <- conj(B)^T, again, and symmetrise
 #pragma unroll 1
   for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll 1
     for (int j = 0; j < M; ++j) {
       const R fj = R(1) / sh.F[g][j][j].x;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = t + k * TPM, r = e / M, c = e % M;
+      LHF_FOR_ENTRIES {
         if (r == j) sh.B[g][j][c] = cscale(sh.A[g][j][c], fj);
         else if (r > j) sh.A[g][r][c] = csub(sh.A[g][r][c], cmul(cscale(sh.F[g][r][j], fj), sh.A[g][j][c]));
       }
       __syncthreads();
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = t + k * TPM, r = e / M, c = e % M;
+    LHF_FOR_ENTRIES {
       if (pass == 0) {
         sh.A[g][r][c] = cconj(sh.B[g][c][r]);
       } else {
@@ -150,17 +148,45 @@ __device__ void solve_pair(Smem<R, M, G, HASU, HASU || WANTV>& sh, int g, int t,
         C s = cmk<C>(R(0.5) * (x.x + y.x), R(0.5) * (x.y - y.y));
         if (r == c) s.y = R(0);
         sh.A[g][r][c] = s;
-        if (WANTV) sh.V[g][r][c] = cmk<C>(r == c ? R(1) : R(0), R(0));
+        if constexpr (HASV) sh.V[g][r][c] = cmk<C>(r == c ? R(1) : R(0), R(0));
       }
     }
     __syncthreads();
   }
-  // ---- 3. Jacobi sweeps
+}
+
+// Jacobi rotation of the Hermitian 2 x 2 block [[app, b], [conj b, aqq]]:
+// cosine c, s = sin * b / |b| and the rotated diagonal (dp, dq).
+template <typename R, typename C>
+__device__ __forceinline__ void rotation(R app, R aqq, C b, R& c, C& s, R& dp, R& dq) {
+  const R ab = sqrt(b.x * b.x + b.y * b.y);
+  if (ab > R(0)) {
+    const R tau = (aqq - app) / (R(2) * ab);
+    const R t = (tau >= R(0) ? R(1) : R(-1)) / (fabs(tau) + sqrt(R(1) + tau * tau));
+    c = R(1) / sqrt(R(1) + t * t);
+    s = cscale(b, t * c / ab);
+    dp = app - t * ab;
+    dq = aqq + t * ab;
+  } else {
+    c = R(1);
+    s = cmk<C>(R(0), R(0));
+    dp = app;
+    dq = aqq;
+  }
+}
+
+// 3. Jacobi sweeps on A (and V <- V J when WANTV).  In each round the thread
+// owning a diagonal pair block computes that pair's rotation and publishes it
+// in LDS; after a barrier every thread rotates its own 2 x 2 block in
+// registers and writes it back in place (each entry belongs to exactly one
+// block per round).  Returns the buffer holding the result (always A here).
+template <typename R, int M, int G, bool HASU, bool HASV, bool WANTV>
+__device__ int jacobi(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int maxsw, R tol) {
+  typedef typename Cx<R>::T C;
+  constexpr int H = M / 2, TPM = H * H;
   R nloc = R(0);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int e = t + k * TPM;
-    const C a = sh.A[g][e / M][e % M];
+  LHF_FOR_ENTRIES {
+    const C a = sh.A[g][r][c];
     nloc += a.x * a.x + a.y * a.y;
   }
   const R nrm2 = group_sum(sh, g, t, nloc);
@@ -168,9 +194,7 @@ __device__ void solve_pair(Smem<R, M, G, HASU, HASU || WANTV>& sh, int g, int t,
 #pragma unroll 1
   for (int sw = 0;; ++sw) {
     R oloc = R(0);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = t + k * TPM, r = e / M, c = e % M;
+    LHF_FOR_ENTRIES {
       const C a = sh.A[g][r][c];
       if (r != c) oloc += a.x * a.x + a.y * a.y;
     }
@@ -188,46 +212,36 @@ __device__ void solve_pair(Smem<R, M, G, HASU, HASU || WANTV>& sh, int g, int t,
       pair_of<M>(bj, s, pj, qj);
       C a00 = sh.A[g][pi][pj], a01 = sh.A[g][pi][qj], a10 = sh.A[g][qi][pj], a11 = sh.A[g][qi][qj];
       if (bi == bj) {
-        const R app = a00.x, aqq = a11.x;
-        const R ab = sqrt(a01.x * a01.x + a01.y * a01.y);
-        if (ab > R(0)) {
-          const R tau = (aqq - app) / (R(2) * ab);
-          const R tt = (tau >= R(0) ? R(1) : R(-1)) / (fabs(tau) + sqrt(R(1) + tau * tau));
-          const R cs = R(1) / sqrt(R(1) + tt * tt);
-          sh.jc[g][bi] = cs;
-          sh.js[g][bi] = cscale(a01, tt * cs / ab);
-          sh.dn[g][pi] = app - tt * ab;
-          sh.dn[g][qi] = aqq + tt * ab;
-        } else {
-          sh.jc[g][bi] = R(1);
-          sh.js[g][bi] = cmk<C>(R(0), R(0));
-          sh.dn[g][pi] = app;
-          sh.dn[g][qi] = aqq;
-        }
+        R cs, dp, dq;
+        C sv;
+        rotation<R, C>(a00.x, a11.x, a01, cs, sv, dp, dq);
+        sh.jc[g][bi] = cs;
+        sh.js[g][bi] = sv;
+        sh.dn[g][pi] = dp;
+        sh.dn[g][qi] = dq;
       }
       __syncthreads();
       const R ci = sh.jc[g][bi], cj = sh.jc[g][bj];
       const C si = sh.js[g][bi], sj = sh.js[g][bj];
       const C msj = cmk<C>(-sj.x, sj.y);   // J_qp of pair j = -conj(s_j)
-      // T = A J_j
-      const C t00 = cadd(cscale(a00, cj), cmul(a01, msj));
-      const C t01 = cadd(cmul(a00, sj), cscale(a01, cj));
-      const C t10 = cadd(cscale(a10, cj), cmul(a11, msj));
-      const C t11 = cadd(cmul(a10, sj), cscale(a11, cj));
-      // A' = J_i^H T
       if (bi == bj) {
         a00 = cmk<C>(sh.dn[g][pi], R(0));
         a11 = cmk<C>(sh.dn[g][qi], R(0));
         a01 = cmk<C>(R(0), R(0));
         a10 = cmk<C>(R(0), R(0));
       } else {
+        // T = A J_j, then A' = J_i^H T
+        const C t00 = cadd(cscale(a00, cj), cmul(a01, msj));
+        const C t01 = cadd(cmul(a00, sj), cscale(a01, cj));
+        const C t10 = cadd(cscale(a10, cj), cmul(a11, msj));
+        const C t11 = cadd(cmul(a10, sj), cscale(a11, cj));
         a00 = csub(cscale(t00, ci), cmul(si, t10));
         a01 = csub(cscale(t01, ci), cmul(si, t11));
         a10 = cadd(cmulc(si, t00), cscale(t10, ci));
         a11 = cadd(cmulc(si, t01), cscale(t11, ci));
       }
       sh.A[g][pi][pj] = a00; sh.A[g][pi][qj] = a01; sh.A[g][qi][pj] = a10; sh.A[g][qi][qj] = a11;
-      if (WANTV) {
+      if constexpr (WANTV) {
         // columns {pj, qj} of rows {pi, qi}: V <- V J_j
         C vp = sh.V[g][pi][pj], vq = sh.V[g][pi][qj];
         sh.V[g][pi][pj] = cadd(cscale(vp, cj), cmul(vq, msj));
@@ -239,8 +253,13 @@ __device__ void solve_pair(Smem<R, M, G, HASU, HASU || WANTV>& sh, int g, int t,
       __syncthreads();
     }
   }
-  // ---- 4. eigenvalues, ranks, eigenvectors F^-H V (into A)
-  if (t < M) sh.lam[g][t] = sh.A[g][t][t].x;
+  return 0;
+}
+
+// 4. Eigenvalues (diagonal of A) and their ascending ranks among the first m.
+template <typename R, int M, int G, bool HASU, bool HASV>
+__device__ void eig_rank(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int m, int cur) {
+  if (t < M) sh.lam[g][t] = (cur ? sh.B[g] : sh.A[g])[t][t].x;
   __syncthreads();
   if (t < m) {
     const R lr = sh.lam[g][t];
@@ -251,20 +270,22 @@ __device__ void solve_pair(Smem<R, M, G, HASU, HASU || WANTV>& sh, int g, int t,
     }
     sh.rank[g][t] = k;
   }
-  if (WANTV) {
-#pragma unroll 1
-    for (int j = M - 1; j >= 0; --j) {
-      const R fj = R(1) / sh.F[g][j][j].x;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = t + k * TPM, r = e / M, c = e % M;
-        if (r == j) sh.A[g][j][c] = cscale(sh.V[g][j][c], fj);
-        else if (r < j) sh.V[g][r][c] = csub(sh.V[g][r][c], cmulc(cscale(sh.F[g][j][r], fj), sh.V[g][j][c]));
-      }
-      __syncthreads();
-    }
-  }
   __syncthreads();
+}
+
+// Eigenvectors F^-H V into A (back substitution, one barrier per row).
+template <typename R, int M, int G, bool HASU, bool HASV>
+__device__ void backsub_vectors(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
+  constexpr int TPM = (M / 2) * (M / 2);
+#pragma unroll 1
+  for (int j = M - 1; j >= 0; --j) {
+    const R fj = R(1) / sh.F[g][j][j].x;
+    LHF_FOR_ENTRIES {
+      if (r == j) sh.A[g][j][c] = cscale(sh.V[g][j][c], fj);
+      else if (r < j) sh.V[g][r][c] = csub(sh.V[g][r][c], cmulc(cscale(sh.F[g][j][r], fj), sh.V[g][j][c]));
+    }
+    __syncthreads();
+  }
 }
 
 template <int M>
@@ -317,7 +338,10 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
   }
   if (bad) sh.flag[g][1] = 1;
   __syncthreads();
-  solve_pair<R, M, G, false, WANTV>(sh, g, t, m, maxsw, tol);
+  chol_reduce(sh, g, t);
+  const int cur = jacobi<R, M, G, false, WANTV, WANTV>(sh, g, t, maxsw, tol);
+  eig_rank(sh, g, t, m, cur);
+  if constexpr (WANTV) backsub_vectors(sh, g, t);
   if (!valid) return;   // no barrier follows
   const int64_t wb = L.w_off + (int64_t)blk * m, wc = L.w_off + (int64_t)cblk * m;
   if (t < m) {
@@ -381,6 +405,18 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
   const int ns1 = L.dim[0].L == 1 ? 1 : L.dim[0].nshift;
   const int ns2 = L.dim[1].L == 1 ? 1 : L.dim[1].nshift;
   const int ns3 = L.dim[2].L == 1 ? 1 : L.dim[2].nshift;
+  // band-cell twiddles w^(j.k) of this block (regeneration path)
+  const int ncell = ns1 * ns2 * ns3;
+  const bool twl = ncell <= 32;
+  if (!H64 && twl) {
+    for (int q = t; q < ncell; q += TPM) {
+      const int t3 = q % ns3, t2 = (q / ns3) % ns2, t1 = q / (ns3 * ns2);
+      const int k1 = cell_of(L.dim[0], t1), k2 = cell_of(L.dim[1], t2), k3 = cell_of(L.dim[2], t3);
+      C ww = cmul(tw[L.dim[0].tw_off + (j1 * k1) % L.L[0]], tw[L.dim[1].tw_off + (j2 * k2) % L.L[1]]);
+      sh.tw[g][q] = cmul(ww, tw[L.dim[2].tw_off + (j3 * k3) % L.L[2]]);
+    }
+  }
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = t + k * TPM, r = e / M, c = e % M;
@@ -393,20 +429,20 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
         // regenerate: sum over band cells k of w^(j.k) A_k
         h = cmk<C>(0.0, 0.0);
         s = cmk<C>(0.0, 0.0);
-        for (int t1 = 0; t1 < ns1; ++t1) {
-          const int k1 = cell_of(L.dim[0], t1);
-          const C w1 = tw[L.dim[0].tw_off + (j1 * k1) % L.L[0]];
-          for (int t2 = 0; t2 < ns2; ++t2) {
-            const int k2 = cell_of(L.dim[1], t2);
-            const C w12 = cmul(w1, tw[L.dim[1].tw_off + (j2 * k2) % L.L[1]]);
-            for (int t3 = 0; t3 < ns3; ++t3) {
-              const int k3 = cell_of(L.dim[2], t3);
-              const C ww = cmul(w12, tw[L.dim[2].tw_off + (j3 * k3) % L.L[2]]);
-              const int64_t o = L.gen_off + ((int64_t)(k1 * L.L[1] + k2) * L.L[2] + k3) * m * m + r * m + c;
-              h = cadd(h, cscale(ww, Hg[o]));
-              s = cadd(s, cscale(ww, Sg[o]));
-            }
+#pragma unroll 4
+        for (int q = 0; q < ncell; ++q) {
+          const int t3 = q % ns3, t2 = (q / ns3) % ns2, t1 = q / (ns3 * ns2);
+          const int k1 = cell_of(L.dim[0], t1), k2 = cell_of(L.dim[1], t2), k3 = cell_of(L.dim[2], t3);
+          C ww;
+          if (twl) {
+            ww = sh.tw[g][q];
+          } else {
+            ww = cmul(cmul(tw[L.dim[0].tw_off + (j1 * k1) % L.L[0]], tw[L.dim[1].tw_off + (j2 * k2) % L.L[1]]),
+                      tw[L.dim[2].tw_off + (j3 * k3) % L.L[2]]);
           }
+          const int64_t o = L.gen_off + ((int64_t)(k1 * L.L[1] + k2) * L.L[2] + k3) * m * m + r * m + c;
+          h = cadd(h, cscale(ww, Hg[o]));
+          s = cadd(s, cscale(ww, Sg[o]));
         }
       }
       if (!fresh) {
@@ -450,12 +486,99 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     }
     __syncthreads();
   }
-  solve_pair<R, M, G, true, WANTV>(sh, g, t, m, maxsw, tol);
+  // B = I + E with E small when U is S-orthonormal to FP32 accuracy (E is
+  // about kappa(Sbar) times the FP32 rounding): then
+  // X = (I + E)^-1/2 = I - E/2 + 3/8 E^2 - 5/16 E^3 + 35/128 E^4 - 63/256 E^5
+  // + O(E^6), summed by Horner's rule, and A <- X A X (all products parallel).
+  // Otherwise Cholesky reduction.
+  R eloc = R(0);
+  LHF_FOR_ENTRIES {
+    const C b = sh.B[g][r][c];
+    const R br = b.x - (r == c ? R(1) : R(0));
+    eloc += br * br + b.y * b.y;
+  }
+  const R e2 = group_sum(sh, g, t, eloc);
+  if (t == 0) sh.flag[g][3] = (e2 <= R(4e-6)) ? 1 : 0;   // ||E||_F <= 2e-3
+  __syncthreads();
+  bool series = true;
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg) series = series && sh.flag[gg][3] != 0;
+  __syncthreads();
+  if (series) {
+    C acc[4];
+    // E in B; F <- c5 E + c4 I, then F <- E F + c I for c = c3, c2, c1, c0
+    LHF_FOR_ENTRIES {
+      C ev = sh.B[g][r][c];
+      if (r == c) ev.x -= R(1);
+      sh.B[g][r][c] = ev;
+      C f = cscale(ev, R(-63.0 / 256.0));
+      if (r == c) f.x += R(35.0 / 128.0);
+      sh.F[g][r][c] = f;
+    }
+    __syncthreads();
+    const R coef[4] = {R(-5.0 / 16.0), R(3.0 / 8.0), R(-0.5), R(1.0)};
+#pragma unroll 1
+    for (int h = 0; h < 4; ++h) {
+      LHF_FOR_ENTRIES {
+        C a = cmk<C>(0.0, 0.0);
+        for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.B[g][r][q], sh.F[g][q][c]));
+        if (r == c) a.x += coef[h];
+        acc[k] = a;
+      }
+      __syncthreads();
+      LHF_FOR_ENTRIES { sh.F[g][r][c] = acc[k]; }
+      __syncthreads();
+    }
+    // V <- A X, then A <- X V (Hermitian), V <- I
+    LHF_FOR_ENTRIES {
+      C a = cmk<C>(0.0, 0.0);
+      for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.A[g][r][q], sh.F[g][q][c]));
+      sh.V[g][r][c] = a;
+    }
+    __syncthreads();
+    LHF_FOR_ENTRIES {
+      C a = cmk<C>(0.0, 0.0);
+      for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.F[g][r][q], sh.V[g][q][c]));
+      acc[k] = a;
+    }
+    __syncthreads();
+    LHF_FOR_ENTRIES {
+      sh.A[g][r][c] = acc[k];
+      sh.V[g][r][c] = cmk<C>(r == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    LHF_FOR_ENTRIES {
+      const C x = sh.A[g][r][c], y = sh.A[g][c][r];
+      C s2 = cmk<C>(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+      if (r == c) s2.y = 0.0;
+      acc[k] = s2;
+    }
+    __syncthreads();
+    LHF_FOR_ENTRIES { sh.A[g][r][c] = acc[k]; }
+    __syncthreads();
+  } else {
+    chol_reduce(sh, g, t);
+  }
+  const int cur = jacobi<R, M, G, true, true, WANTV>(sh, g, t, maxsw, tol);
+  eig_rank(sh, g, t, m, cur);
+  if (WANTV) {
+    if (series) {
+      // A <- X V
+      C acc[4];
+      LHF_FOR_ENTRIES {
+        C a = cmk<C>(0.0, 0.0);
+        for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.F[g][r][q], sh.V[g][q][c]));
+        acc[k] = a;
+      }
+      LHF_FOR_ENTRIES { sh.A[g][r][c] = acc[k]; }
+      __syncthreads();
+    } else {
+      backsub_vectors(sh, g, t);
+    }
+  }
   C vfin[4];
   if (WANTV) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = t + k * TPM, r = e / M, c = e % M;
+    LHF_FOR_ENTRIES {
       C a = cmk<C>(0.0, 0.0);
       for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.U[g][r][q], sh.A[g][q][c]));
       vfin[k] = a;

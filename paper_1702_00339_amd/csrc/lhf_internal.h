@@ -25,8 +25,11 @@ struct DimDev {
   int32_t nshift;     // generator shifts computed for the Grams (slots)
   int32_t full;       // 1: slots are shifts 0..L-1; 0: slots are -L0..L0
   int32_t L0;         // band half-width (banded dims)
+  int32_t kstart;     // first node of the Gram contraction window
+  int32_t kwin;       // nodes in the window (cyclic from kstart); n when the
+                      // basis factors are non-negligible everywhere
   int32_t ksplit;     // split-K factor of the Gram contraction
-  int32_t kchunk;     // nodes per split (multiple of 32)
+  int32_t kchunk;     // window nodes per split (multiple of 32)
   double h;           // node spacing
   double x0;          // coordinate of node 0
   double y0;          // replicated dims: offset of a cell's first node from its centre
@@ -56,6 +59,13 @@ struct LatDev {
   double nuc[kMaxNuc][3];
   double tq[kMaxR];
   double wq[kMaxR];
+};
+
+// One workgroup's share of the grouped Gram contraction: a 64 x 64 output
+// tile (rows (t, nu), columns (slot, mu)) of one lattice and dimension, over
+// split ks of the contraction window.
+struct GramItem {
+  int32_t li, d, tm, tn, ks, pad;
 };
 
 }  // namespace lhf

@@ -144,16 +144,32 @@ static int32_t derive_lattice(const lhf_lattice& in, int idx, LatDev& L, std::st
     } else {
       D.full = 0; D.nshift = 2 * L0 + 1; D.L0 = L0;
     }
-    // split-K of the Gram contraction: aim at ~2048 waves of 32 x 32 tiles
+    // Gram contraction window: every summand contains a cell-0 factor
+    // (G_0[nu] in Op_t G_0), which is below 1e-25 of its peak farther than
+    // W cells from cell 0, with W a >= sqrt(57.6 / alpha_min) + 2 max|centre|.
+    D.kstart = 0;
+    D.kwin = nd;
+    if (periodic) {
+      const int W = (int)std::ceil((std::sqrt(57.6 / amin) + 2.0 * jmax) / in.a);
+      if ((int64_t)(2 * W + 1) * D.nc < nd) {
+        D.kwin = (2 * W + 1) * D.nc;
+        D.kstart = nd - W * D.nc;
+      }
+    }
+    // split-K of the Gram contraction over 64 x 64 workgroup tiles: at least
+    // 64 window nodes per split, ~256 workgroups per (lattice, dimension)
     int M = L.T * L.m0, N = D.nshift * L.m0;
-    int64_t tiles = (int64_t)((M + 31) / 32) * ((N + 31) / 32);
-    int ks = (int)std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
-    ks = std::min(ks, std::max(1, nd / 32));
-    int kchunk = ((nd + ks - 1) / ks + 31) / 32 * 32;
+    int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+    int ks = (int)std::max<int64_t>(1, (256 + tiles - 1) / tiles);
+    ks = std::min(ks, std::max(1, D.kwin / 64));
+    int kchunk = ((D.kwin + ks - 1) / ks + 31) / 32 * 32;
     D.kchunk = kchunk;
-    D.ksplit = (nd + kchunk - 1) / kchunk;
+    D.ksplit = (D.kwin + kchunk - 1) / kchunk;
   }
-  if (nblk > (int64_t)1 << 30) return bad("too many cells");
+  if (nblk * c.m0 * c.m0 >= ((int64_t)1 << 31)) {
+    err = "lattice " + std::to_string(idx) + ": L1 L2 L3 m0^2 >= 2^31 unsupported";
+    return LHF_ERR_UNSUPPORTED;
+  }
   L.nblk = (int32_t)nblk;
   return LHF_OK;
 }
@@ -232,6 +248,21 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->ws_dft_b = off; off = align256(off + (size_t)dtmp * 16);
   p->sizes.ws_bytes = off;
 
+  // grouped Gram work: one item per (lattice, dimension, 64x64 tile, split)
+  std::vector<GramItem> items;
+  std::vector<int32_t> red_items;   // (lattice, dimension) pairs, 2 ints each
+  for (int i = 0; i < nlat; ++i) {
+    const LatDev& L = p->lat[i];
+    for (int d = 0; d < 3; ++d) {
+      const DimDev& D = L.dim[d];
+      const int M = L.T * L.m0, N = D.nshift * L.m0;
+      for (int tm = 0; tm < (M + 63) / 64; ++tm)
+        for (int tn = 0; tn < (N + 63) / 64; ++tn)
+          for (int ks = 0; ks < D.ksplit; ++ks) items.push_back(GramItem{i, d, tm, tn, ks, 0});
+    }
+  }
+  p->n_gram_items = (int32_t)items.size();
+
   // canonical blocks: j with (-j mod L) >= j in linear order
   std::vector<int32_t> canon;
   p->canon_off.resize(nlat);
@@ -265,7 +296,8 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
       hipMalloc(&p->d_lat, sizeof(LatDev) * nlat) != hipSuccess ||
       hipMalloc(&p->d_tw64, sizeof(double2) * tw) != hipSuccess ||
       hipMalloc(&p->d_tw32, sizeof(float2) * tw) != hipSuccess ||
-      hipMalloc(&p->d_canon, sizeof(int32_t) * canon.size()) != hipSuccess) {
+      hipMalloc(&p->d_canon, sizeof(int32_t) * canon.size()) != hipSuccess ||
+      hipMalloc(&p->d_gram_items, sizeof(GramItem) * items.size()) != hipSuccess) {
     set_error("device allocation of the plan tables failed");
     lhf_plan_destroy(p);
     return LHF_ERR_ALLOC;
@@ -273,7 +305,8 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   if (hipMemcpy(p->d_lat, p->lat.data(), sizeof(LatDev) * nlat, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->d_tw64, tw64.data(), sizeof(double2) * tw, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->d_tw32, tw32.data(), sizeof(float2) * tw, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->d_canon, canon.data(), sizeof(int32_t) * canon.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(p->d_canon, canon.data(), sizeof(int32_t) * canon.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_gram_items, items.data(), sizeof(GramItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
     set_error("upload of the plan tables failed");
     lhf_plan_destroy(p);
     return LHF_ERR_HIP;
@@ -310,6 +343,7 @@ int32_t lhf_plan_destroy(lhf_plan_t plan) {
   if (plan->d_tw64) (void)hipFree(plan->d_tw64);
   if (plan->d_tw32) (void)hipFree(plan->d_tw32);
   if (plan->d_canon) (void)hipFree(plan->d_canon);
+  if (plan->d_gram_items) (void)hipFree(plan->d_gram_items);
   delete plan;
   return LHF_OK;
 }

@@ -20,6 +20,8 @@ struct lhf_plan_s {
   double2* d_tw64 = nullptr;            // twiddles, complex128
   float2* d_tw32 = nullptr;             // twiddles, complex64
   int32_t* d_canon = nullptr;           // canonical block of each conjugate pair, per lattice
+  lhf::GramItem* d_gram_items = nullptr;  // grouped Gram work list
+  int32_t n_gram_items = 0;
   std::vector<int64_t> canon_off;       // offset of each lattice's list in d_canon
   std::vector<int32_t> ncanon;          // list length per lattice
   lhf_sizes sizes{};
@@ -52,11 +54,10 @@ Ws ws_view(const lhf_plan_s* p, void* base);
 
 // factors.hip
 hipError_t launch_factors(const lhf_plan_s* p, int li, double* fac, hipStream_t s);
-// gram.hip
-hipError_t launch_gram_f64(const lhf_plan_s* p, int li, int ell, const double* fac, double* part,
-                           double* grams, hipStream_t s);
-hipError_t launch_gram_split(const lhf_plan_s* p, int li, int ell, int mode, const double* fac,
-                             float* part, float* grams, hipStream_t s);
+// gram.hip: every lattice and dimension of the plan in one grouped launch
+// (mode LHF_GRAM_*), then one grouped split-K reduction into the Gram layout
+hipError_t launch_grams(const lhf_plan_s* p, int mode, const double* fac, void* part, void* grams,
+                        hipStream_t s);
 // combine.hip
 hipError_t launch_combine(const lhf_plan_s* p, int li, const double* g64, const float* g32,
                           double* H64, double* S64, float* H32, float* S32, hipStream_t s);
