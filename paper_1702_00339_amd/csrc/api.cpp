@@ -42,10 +42,8 @@ int32_t lhf_assemble_blocks(lhf_plan_t p, void* H_gen, void* S_gen, double* gram
   const bool split = mixed && p->gram != LHF_GRAM_FP64;
   const bool need64 = !mixed || !split || grams64 || H_gen64;
   hipError_t e;
-  for (int li = 0; li < p->nlat; ++li) {
-    e = launch_factors(p, li, w.fac, s);
-    if ((st = hip_status(e, "factors")) != LHF_OK) return st;
-  }
+  e = launch_factors(p, w.fac, s);
+  if ((st = hip_status(e, "factors")) != LHF_OK) return st;
   if (need64) {
     e = launch_grams(p, LHF_GRAM_FP64, w.fac, w.part64, g64, s);
     if ((st = hip_status(e, "gram fp64")) != LHF_OK) return st;
@@ -54,16 +52,11 @@ int32_t lhf_assemble_blocks(lhf_plan_t p, void* H_gen, void* S_gen, double* gram
     e = launch_grams(p, p->gram, w.fac, w.part32, w.grams32, s);
     if ((st = hip_status(e, "gram split")) != LHF_OK) return st;
   }
-  for (int li = 0; li < p->nlat; ++li) {
-    if (!mixed) {
-      e = launch_combine(p, li, g64, nullptr, (double*)H_gen, (double*)S_gen, nullptr, nullptr, s);
-    } else {
-      e = launch_combine(p, li, g64, split ? w.grams32 : nullptr, H_gen64, S_gen64, (float*)H_gen,
-                         (float*)S_gen, s);
-    }
-    if ((st = hip_status(e, "combine")) != LHF_OK) return st;
-  }
-  return LHF_OK;
+  if (!mixed)
+    e = launch_combine(p, g64, nullptr, (double*)H_gen, (double*)S_gen, nullptr, nullptr, s);
+  else
+    e = launch_combine(p, g64, split ? w.grams32 : nullptr, H_gen64, S_gen64, (float*)H_gen, (float*)S_gen, s);
+  return hip_status(e, "combine");
 }
 
 int32_t lhf_block_fft(lhf_plan_t p, int32_t prec, const void* H_gen, const void* S_gen, void* H_bar,
@@ -75,11 +68,7 @@ int32_t lhf_block_fft(lhf_plan_t p, int32_t prec, const void* H_gen, const void*
   if (st != LHF_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = ws_view(p, ws);
-  for (int li = 0; li < p->nlat; ++li) {
-    hipError_t e = launch_block_dft(p, li, prec, H_gen, S_gen, H_bar, S_bar, w.dft_a, w.dft_b, s);
-    if ((st = hip_status(e, "block dft")) != LHF_OK) return st;
-  }
-  return LHF_OK;
+  return hip_status(launch_block_dft(p, prec, H_gen, S_gen, H_bar, S_bar, w.dft, s), "block dft");
 }
 
 int32_t lhf_heev_batched(lhf_plan_t p, uint32_t flags, const void* H_bar, const void* S_bar,
@@ -103,12 +92,9 @@ int32_t lhf_heev_batched(lhf_plan_t p, uint32_t flags, const void* H_bar, const 
   if (st != LHF_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = ws_view(p, ws);
-  for (int li = 0; li < p->nlat; ++li) {
-    hipError_t e = launch_heev(p, li, flags, H_bar, S_bar, H_bar64, S_bar64, H_gen64, S_gen64, w_out, V,
-                               info, w.U, w.info32, s);
-    if ((st = hip_status(e, "heev")) != LHF_OK) return st;
-  }
-  return LHF_OK;
+  return hip_status(launch_heev(p, flags, H_bar, S_bar, H_bar64, S_bar64, H_gen64, S_gen64, w_out, V, info,
+                                w.U, w.info32, s),
+                    "heev");
 }
 
 }  // extern "C"

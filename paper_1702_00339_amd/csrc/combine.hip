@@ -8,6 +8,10 @@
 // dimension are written as zero.  One thread per (cell, mu, nu); the Grams
 // are small and stay in L2.  Arithmetic in FP64 (FP64 Grams) or FP32 (the
 // split-precision Grams of the mixed pipeline).
+//
+// Grouped launch: every lattice's thread range starts at a multiple of 256
+// (table elem_start), so a workgroup serves one lattice, found by binary
+// search over the table.
 #include "plan.h"
 
 namespace lhf {
@@ -21,12 +25,19 @@ __device__ __forceinline__ int slot_of(const DimDev& D, int k) {
 }
 
 template <typename G, typename O>
-__global__ void __launch_bounds__(256) combine_kernel(const LatDev* __restrict__ lats, int li,
+__global__ void __launch_bounds__(256) combine_kernel(const LatDev* __restrict__ lats,
+                                                      const int64_t* __restrict__ elem_start, int nlat,
                                                       const G* __restrict__ grams,
                                                       O* __restrict__ H, O* __restrict__ S) {
-  const LatDev& L = lats[li];
+  const int64_t wg0 = (int64_t)blockIdx.x * 256;
+  int lo = 0, hi = nlat - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (elem_start[mid] <= wg0) lo = mid; else hi = mid - 1;
+  }
+  const LatDev& L = lats[lo];
   const int m2 = L.m0 * L.m0;
-  const int idx = blockIdx.x * 256 + threadIdx.x;   // the planner keeps nblk m0^2 < 2^31
+  const int idx = (int)(wg0 - elem_start[lo]) + threadIdx.x;   // the planner keeps nblk m0^2 < 2^31
   if (idx >= L.nblk * m2) return;
   const int cell = idx / m2;
   const int e = idx - cell * m2;
@@ -59,17 +70,16 @@ __global__ void __launch_bounds__(256) combine_kernel(const LatDev* __restrict__
 
 }  // namespace
 
-hipError_t launch_combine(const lhf_plan_s* p, int li, const double* g64, const float* g32,
-                          double* H64, double* S64, float* H32, float* S32, hipStream_t s) {
-  const LatDev& L = p->lat[li];
-  const int64_t tot = (int64_t)L.nblk * L.m0 * L.m0;
-  const dim3 grid((unsigned)((tot + 255) / 256));
-  if (H64) hipLaunchKernelGGL((combine_kernel<double, double>), grid, dim3(256), 0, s, p->d_lat, li, g64, H64, S64);
+hipError_t launch_combine(const lhf_plan_s* p, const double* g64, const float* g32, double* H64,
+                          double* S64, float* H32, float* S32, hipStream_t s) {
+  const dim3 grid((unsigned)(p->combine_threads / 256));
+  const int64_t* es = p->d_elem_start;
+  if (H64) hipLaunchKernelGGL((combine_kernel<double, double>), grid, dim3(256), 0, s, p->d_lat, es, p->nlat, g64, H64, S64);
   if (H32) {
     if (g32)
-      hipLaunchKernelGGL((combine_kernel<float, float>), grid, dim3(256), 0, s, p->d_lat, li, g32, H32, S32);
+      hipLaunchKernelGGL((combine_kernel<float, float>), grid, dim3(256), 0, s, p->d_lat, es, p->nlat, g32, H32, S32);
     else
-      hipLaunchKernelGGL((combine_kernel<double, float>), grid, dim3(256), 0, s, p->d_lat, li, g64, H32, S32);
+      hipLaunchKernelGGL((combine_kernel<double, float>), grid, dim3(256), 0, s, p->d_lat, es, p->nlat, g64, H32, S32);
   }
   return hipGetLastError();
 }

@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(const LatDev* __restri
 
 hipError_t launch_grams(const lhf_plan_s* p, int mode, const double* fac, void* part, void* grams,
                         hipStream_t s) {
-  const int grid = std::min(p->n_gram_items, 4096);
+  const int grid = std::min(p->n_gram_items, p->gram_grid);
   if (mode == LHF_GRAM_FP64)
     hipLaunchKernelGGL(gram_kernel<0>, dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
   else if (mode == LHF_GRAM_FP32)

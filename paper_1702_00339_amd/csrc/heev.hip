@@ -16,8 +16,9 @@
 //      the norm of A;
 //   4. eigenvalues sorted ascending, eigenvectors C^-H V.
 // Blocks j and -j are complex conjugates (real symmetric generators): only
-// the canonical block of each pair is solved (a plan table lists them) and
-// its results are written for both.
+// the canonical block of each pair is solved and its results are written for
+// both.  The plan lists the canonical (lattice, block) pairs of every lattice
+// per size class, so one launch per class serves the whole plan.
 //
 // Refinement (mixed precision): the FP32 solve leaves eigenvectors U; in FP64
 // the block pair is rebuilt accurately (from complex128 Fourier blocks, or
@@ -298,8 +299,8 @@ struct Shape {
 // Solve from Fourier blocks of precision R.  VMODE: 0 none, 1 write vectors
 // to V (caller, sorted columns), 2 write vectors to U (FP32 workspace).
 template <typename R, int M, int VMODE>
-__global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* __restrict__ lats, int li,
-                                                                 const int32_t* __restrict__ canon, int ncanon,
+__global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* __restrict__ lats,
+                                                                 const int2* __restrict__ canon, int ncanon,
                                                                  const typename Cx<R>::T* __restrict__ Hb,
                                                                  const typename Cx<R>::T* __restrict__ Sb,
                                                                  double* __restrict__ w,
@@ -309,12 +310,13 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
   constexpr int G = Shape<M>::G, TPM = Shape<M>::TPM;
   constexpr bool WANTV = VMODE != 0;
   __shared__ Smem<R, M, G, false, WANTV> sh;
-  const LatDev& L = lats[li];
-  const int m = L.m0;
   const int g = threadIdx.x / TPM, t = threadIdx.x % TPM;
   const int slot = blockIdx.x * G + g;
   const bool valid = slot < ncanon;
-  const int blk = valid ? canon[slot] : 0;
+  const int2 cb = canon[valid ? slot : ncanon - 1];   // a spare group repeats a block of its class, unwritten
+  const LatDev& L = lats[cb.x];
+  const int m = L.m0;
+  const int blk = cb.y;
   const int cblk = conj_block(L, blk);
   const int64_t base = L.gen_off + (int64_t)blk * m * m;
   if (t < 4) sh.flag[g][t] = 0;
@@ -371,8 +373,8 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
 // Refinement in FP64 from FP32 eigenvectors U (layout [blk][row][col]).
 // Blocks from H64/S64 (complex128) or regenerated from the FP64 generator band.
 template <int M, bool WANTV>
-__global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev* __restrict__ lats, int li,
-                                                                   const int32_t* __restrict__ canon, int ncanon,
+__global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev* __restrict__ lats,
+                                                                   const int2* __restrict__ canon, int ncanon,
                                                                    const double2* __restrict__ tw,
                                                                    const double2* __restrict__ H64,
                                                                    const double2* __restrict__ S64,
@@ -386,12 +388,13 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
   typedef double R;
   constexpr int G = Shape<M>::G, TPM = Shape<M>::TPM;
   __shared__ Smem<R, M, G, true, true> sh;
-  const LatDev& L = lats[li];
-  const int m = L.m0;
   const int g = threadIdx.x / TPM, t = threadIdx.x % TPM;
   const int slot = blockIdx.x * G + g;
   const bool valid = slot < ncanon;
-  const int blk = valid ? canon[slot] : 0;
+  const int2 cb = canon[valid ? slot : ncanon - 1];   // a spare group repeats a block of its class, unwritten
+  const LatDev& L = lats[cb.x];
+  const int m = L.m0;
+  const int blk = cb.y;
   const int cblk = conj_block(L, blk);
   const int64_t base = L.gen_off + (int64_t)blk * m * m;
   if (t < 4) sh.flag[g][t] = 0;
@@ -609,57 +612,63 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
 }
 
 template <typename R, int M>
-hipError_t launch_heev_m(const lhf_plan_s* p, int li, int vmode, const void* Hb, const void* Sb, double* w,
-                         void* V, int32_t* info, int maxsw, R tol, hipStream_t s) {
+hipError_t launch_heev_m(const lhf_plan_s* p, int vmode, const void* Hb, const void* Sb, double* w, void* V,
+                         int32_t* info, int maxsw, R tol, hipStream_t s) {
   typedef typename Cx<R>::T C;
-  const int nc = p->ncanon[li];
-  const int32_t* canon = p->d_canon + p->canon_off[li];
+  const int cls = M == 4 ? 0 : M == 8 ? 1 : M == 16 ? 2 : 3;
+  const int nc = p->ncanon[cls];
+  if (nc == 0) return hipSuccess;
+  const int2* canon = p->d_canon[cls];
   const dim3 grid((nc + Shape<M>::G - 1) / Shape<M>::G), block(Shape<M>::THREADS);
   const C* h = (const C*)Hb;
   const C* sm = (const C*)Sb;
   if (vmode == 0)
-    hipLaunchKernelGGL((heev_kernel<R, M, 0>), grid, block, 0, s, p->d_lat, li, canon, nc, h, sm, w, (C*)V, info, maxsw, tol);
+    hipLaunchKernelGGL((heev_kernel<R, M, 0>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info, maxsw, tol);
   else if (vmode == 1)
-    hipLaunchKernelGGL((heev_kernel<R, M, 1>), grid, block, 0, s, p->d_lat, li, canon, nc, h, sm, w, (C*)V, info, maxsw, tol);
+    hipLaunchKernelGGL((heev_kernel<R, M, 1>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info, maxsw, tol);
   else
-    hipLaunchKernelGGL((heev_kernel<R, M, 2>), grid, block, 0, s, p->d_lat, li, canon, nc, h, sm, w, (C*)V, info, maxsw, tol);
+    hipLaunchKernelGGL((heev_kernel<R, M, 2>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info, maxsw, tol);
   return hipGetLastError();
 }
 
 template <int M>
-hipError_t launch_refine_m(const lhf_plan_s* p, int li, bool wantv, const void* H64, const void* S64,
-                           const double* Hg, const double* Sg, const float2* U, const int32_t* info32,
-                           double* w, void* V, int32_t* info, hipStream_t s) {
-  const int nc = p->ncanon[li];
-  const int32_t* canon = p->d_canon + p->canon_off[li];
+hipError_t launch_refine_m(const lhf_plan_s* p, bool wantv, const void* H64, const void* S64, const double* Hg,
+                           const double* Sg, const float2* U, const int32_t* info32, double* w, void* V,
+                           int32_t* info, hipStream_t s) {
+  const int cls = M == 4 ? 0 : M == 8 ? 1 : M == 16 ? 2 : 3;
+  const int nc = p->ncanon[cls];
+  if (nc == 0) return hipSuccess;
+  const int2* canon = p->d_canon[cls];
   const dim3 grid((nc + Shape<M>::G - 1) / Shape<M>::G), block(Shape<M>::THREADS);
   const double tol = 4.0 * M * 1.1102230246251565e-16;
   if (wantv)
-    hipLaunchKernelGGL((refine_kernel<M, true>), grid, block, 0, s, p->d_lat, li, canon, nc, p->d_tw64,
+    hipLaunchKernelGGL((refine_kernel<M, true>), grid, block, 0, s, p->d_lat, canon, nc, p->d_tw64,
                        (const double2*)H64, (const double2*)S64, Hg, Sg, U, info32, w, (double2*)V, info, 30, tol);
   else
-    hipLaunchKernelGGL((refine_kernel<M, false>), grid, block, 0, s, p->d_lat, li, canon, nc, p->d_tw64,
+    hipLaunchKernelGGL((refine_kernel<M, false>), grid, block, 0, s, p->d_lat, canon, nc, p->d_tw64,
                        (const double2*)H64, (const double2*)S64, Hg, Sg, U, info32, w, (double2*)V, info, 30, tol);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_heev(const lhf_plan_s* p, int li, uint32_t flags, const void* Hbar, const void* Sbar,
+int heev_class(int m0) { return m0 <= 4 ? 0 : m0 <= 8 ? 1 : m0 <= 16 ? 2 : 3; }
+
+// One launch per size class M = 4, 8, 16, 32 that has blocks; in the mixed
+// pipeline all FP32 solves run before the FP64 refinements.
+hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, const void* Sbar,
                        const void* Hbar64, const void* Sbar64, const double* Hgen64, const double* Sgen64,
                        double* w, void* V, int32_t* info, float2* U, int32_t* info32, hipStream_t s) {
-  const LatDev& L = p->lat[li];
-  const int m = L.m0;
   const bool wantv = (flags & LHF_HEEV_VECTORS) != 0;
   const bool refine = p->prec == LHF_PREC_MIXED && (flags & LHF_HEEV_REFINE_FP64);
-  hipError_t e;
+  hipError_t e = hipSuccess;
   if (p->prec == LHF_PREC_FP64) {
     const int vm = wantv ? 1 : 0;
     const double eps = 1.1102230246251565e-16;
-    if (m <= 4) e = launch_heev_m<double, 4>(p, li, vm, Hbar, Sbar, w, V, info, 30, 16 * eps, s);
-    else if (m <= 8) e = launch_heev_m<double, 8>(p, li, vm, Hbar, Sbar, w, V, info, 30, 32 * eps, s);
-    else if (m <= 16) e = launch_heev_m<double, 16>(p, li, vm, Hbar, Sbar, w, V, info, 30, 64 * eps, s);
-    else e = launch_heev_m<double, 32>(p, li, vm, Hbar, Sbar, w, V, info, 30, 128 * eps, s);
+    if (e == hipSuccess) e = launch_heev_m<double, 4>(p, vm, Hbar, Sbar, w, V, info, 30, 16 * eps, s);
+    if (e == hipSuccess) e = launch_heev_m<double, 8>(p, vm, Hbar, Sbar, w, V, info, 30, 32 * eps, s);
+    if (e == hipSuccess) e = launch_heev_m<double, 16>(p, vm, Hbar, Sbar, w, V, info, 30, 64 * eps, s);
+    if (e == hipSuccess) e = launch_heev_m<double, 32>(p, vm, Hbar, Sbar, w, V, info, 30, 128 * eps, s);
     return e;
   }
   // mixed: FP32 solve, then FP64 refinement
@@ -667,15 +676,16 @@ hipError_t launch_heev(const lhf_plan_s* p, int li, uint32_t flags, const void* 
   void* vdst = refine ? (void*)U : V;
   int32_t* i32 = refine ? info32 : info;
   const float eps = 5.9604645e-08f;
-  if (m <= 4) e = launch_heev_m<float, 4>(p, li, vm, Hbar, Sbar, w, vdst, i32, 20, 16 * eps, s);
-  else if (m <= 8) e = launch_heev_m<float, 8>(p, li, vm, Hbar, Sbar, w, vdst, i32, 20, 32 * eps, s);
-  else if (m <= 16) e = launch_heev_m<float, 16>(p, li, vm, Hbar, Sbar, w, vdst, i32, 20, 64 * eps, s);
-  else e = launch_heev_m<float, 32>(p, li, vm, Hbar, Sbar, w, vdst, i32, 20, 128 * eps, s);
+  if (e == hipSuccess) e = launch_heev_m<float, 4>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 16 * eps, s);
+  if (e == hipSuccess) e = launch_heev_m<float, 8>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 32 * eps, s);
+  if (e == hipSuccess) e = launch_heev_m<float, 16>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 64 * eps, s);
+  if (e == hipSuccess) e = launch_heev_m<float, 32>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 128 * eps, s);
   if (e != hipSuccess || !refine) return e;
-  if (m <= 4) return launch_refine_m<4>(p, li, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
-  if (m <= 8) return launch_refine_m<8>(p, li, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
-  if (m <= 16) return launch_refine_m<16>(p, li, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
-  return launch_refine_m<32>(p, li, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
+  if (e == hipSuccess) e = launch_refine_m<4>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
+  if (e == hipSuccess) e = launch_refine_m<8>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
+  if (e == hipSuccess) e = launch_refine_m<16>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
+  if (e == hipSuccess) e = launch_refine_m<32>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
+  return e;
 }
 
 }  // namespace lhf

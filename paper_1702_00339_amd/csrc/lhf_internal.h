@@ -68,4 +68,33 @@ struct GramItem {
   int32_t li, d, tm, tn, ks, pad;
 };
 
+// Grouped factor work: nodes [256 chunk, 256 chunk + 256) of one row (basis
+// function, or potential term of a one-cell dimension) of one lattice dim.
+struct FacItem {
+  int32_t li, d, row, chunk;
+};
+
+// One lattice's share of one pass of the grouped block DFT: transform
+// dimension d of X[O][B][I] (B band slots) into Y[O][L_d][I], JC outputs along
+// the axis per thread (njc = ceil(L_d / JC) chunks), over the pass threads
+// [tbase, tbase + O njc I); tbase is a multiple of 256 so that a workgroup
+// serves one task.  The first pass reads the real generator stack of the
+// lattice; later passes read an intermediate; the last writes the Fourier
+// blocks.
+struct DftTask {
+  int32_t li, d, O, I, JC, njc, B, out_final;
+  int64_t in_off, in_half;     // intermediate input: H part at in_off, S part in_half later
+  int64_t out_off, out_half;   // intermediate output (when not final)
+  int64_t tbase;
+};
+
+// Host-side record of one grouped DFT launch: tasks [t0, t0 + nt) of one pass
+// and one band-width class, `threads` threads (a multiple of 256), twiddles of
+// axes up to `lds_tw` entries staged in LDS.
+struct DftLaunch {
+  int32_t pass, cls, t0, nt;
+  int64_t threads;
+  int32_t lds_tw;
+};
+
 }  // namespace lhf

@@ -27,8 +27,7 @@ Ws ws_view(const lhf_plan_s* p, void* base) {
   w.grams32 = reinterpret_cast<float*>(b + p->ws_grams32);
   w.part64 = reinterpret_cast<double*>(b + p->ws_part64);
   w.part32 = reinterpret_cast<float*>(b + p->ws_part32);
-  w.dft_a = b + p->ws_dft_a;
-  w.dft_b = b + p->ws_dft_b;
+  w.dft = b + p->ws_dft;
   w.U = reinterpret_cast<float2*>(b + p->ws_U);
   w.info32 = reinterpret_cast<int32_t*>(b + p->ws_info);
   return w;
@@ -208,7 +207,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->prec = prec; p->gram = gram; p->nlat = nlat;
   p->lat.resize(nlat);
   std::string err;
-  int64_t fac = 0, grams = 0, part = 0, tw = 0, gen = 0, w = 0, blk = 0, dtmp = 0;
+  int64_t fac = 0, grams = 0, part = 0, tw = 0, gen = 0, w = 0, blk = 0;
   for (int i = 0; i < nlat; ++i) {
     int32_t st = derive_lattice(lats[i], i, p->lat[i], err);
     if (st != LHF_OK) { set_error(err); delete p; return st; }
@@ -224,8 +223,10 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
     L.gen_off = gen; gen += (int64_t)L.nblk * L.m0 * L.m0;
     L.w_off = w; w += (int64_t)L.nblk * L.m0;
     L.blk_off = blk; blk += L.nblk;
-    dtmp = std::max(dtmp, block_dft_tmp_elems(L));
   }
+  std::vector<DftTask> dft_tasks;
+  int64_t dtmp = 0;
+  plan_block_dft(p->lat, p->dft_target_threads, dft_tasks, p->dft_launches, dtmp);
   p->sizes.nlat = nlat;
   p->sizes.nblocks = blk;
   p->sizes.gen_elems = gen;
@@ -244,13 +245,11 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
     p->ws_U = off; off = align256(off + (size_t)gen * 8);
     p->ws_info = off; off = align256(off + (size_t)blk * 4);
   }
-  p->ws_dft_a = off; off = align256(off + (size_t)dtmp * 16);
-  p->ws_dft_b = off; off = align256(off + (size_t)dtmp * 16);
+  p->ws_dft = off; off = align256(off + (size_t)dtmp * 16);   // complex128 (either precision)
   p->sizes.ws_bytes = off;
 
   // grouped Gram work: one item per (lattice, dimension, 64x64 tile, split)
   std::vector<GramItem> items;
-  std::vector<int32_t> red_items;   // (lattice, dimension) pairs, 2 ints each
   for (int i = 0; i < nlat; ++i) {
     const LatDev& L = p->lat[i];
     for (int d = 0; d < 3; ++d) {
@@ -263,21 +262,34 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   }
   p->n_gram_items = (int32_t)items.size();
 
-  // canonical blocks: j with (-j mod L) >= j in linear order
-  std::vector<int32_t> canon;
-  p->canon_off.resize(nlat);
-  p->ncanon.resize(nlat);
+  // grouped factor work
+  std::vector<FacItem> fac_items;
+  plan_factors(p->lat, fac_items);
+  p->n_fac_items = (int32_t)fac_items.size();
+
+  // combine: thread range of each lattice starts at a multiple of 256
+  std::vector<int64_t> elem_start(nlat);
+  int64_t ct = 0;
+  for (int i = 0; i < nlat; ++i) {
+    elem_start[i] = ct;
+    ct += ((int64_t)p->lat[i].nblk * p->lat[i].m0 * p->lat[i].m0 + 255) / 256 * 256;
+  }
+  p->combine_threads = ct;
+
+  // canonical blocks per eigensolver size class: j with (-j mod L) >= j in
+  // linear order, as (lattice, block)
+  std::vector<int2> canon[4];
   for (int i = 0; i < nlat; ++i) {
     const LatDev& L = p->lat[i];
-    p->canon_off[i] = (int64_t)canon.size();
+    std::vector<int2>& cl = canon[heev_class(L.m0)];
     for (int b = 0; b < L.nblk; ++b) {
       const int k3 = b % L.L[2], k2 = (b / L.L[2]) % L.L[1], k1 = b / (L.L[2] * L.L[1]);
       const int c1 = k1 ? L.L[0] - k1 : 0, c2 = k2 ? L.L[1] - k2 : 0, c3 = k3 ? L.L[2] - k3 : 0;
       const int cb = (c1 * L.L[1] + c2) * L.L[2] + c3;
-      if (cb >= b) canon.push_back(b);
+      if (cb >= b) cl.push_back(make_int2(i, b));
     }
-    p->ncanon[i] = (int32_t)((int64_t)canon.size() - p->canon_off[i]);
   }
+  for (int c = 0; c < 4; ++c) p->ncanon[c] = (int32_t)canon[c].size();
 
   // twiddle tables exp(-2 pi i m / L)
   std::vector<double2> tw64(tw);
@@ -292,24 +304,25 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
       }
     }
   }
-  if (hipGetDevice(&p->device) != hipSuccess ||
-      hipMalloc(&p->d_lat, sizeof(LatDev) * nlat) != hipSuccess ||
-      hipMalloc(&p->d_tw64, sizeof(double2) * tw) != hipSuccess ||
-      hipMalloc(&p->d_tw32, sizeof(float2) * tw) != hipSuccess ||
-      hipMalloc(&p->d_canon, sizeof(int32_t) * canon.size()) != hipSuccess ||
-      hipMalloc(&p->d_gram_items, sizeof(GramItem) * items.size()) != hipSuccess) {
-    set_error("device allocation of the plan tables failed");
+  bool ok = hipGetDevice(&p->device) == hipSuccess;
+  auto upload = [&](auto*& dst, const auto* src, size_t count) {
+    if (!ok || count == 0) return;
+    const size_t bytes = sizeof(*src) * count;
+    ok = hipMalloc(reinterpret_cast<void**>(&dst), bytes) == hipSuccess &&
+         hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  upload(p->d_lat, p->lat.data(), (size_t)nlat);
+  upload(p->d_tw64, tw64.data(), (size_t)tw);
+  upload(p->d_tw32, tw32.data(), (size_t)tw);
+  upload(p->d_gram_items, items.data(), items.size());
+  upload(p->d_fac_items, fac_items.data(), fac_items.size());
+  upload(p->d_elem_start, elem_start.data(), elem_start.size());
+  upload(p->d_dft_tasks, dft_tasks.data(), dft_tasks.size());
+  for (int c = 0; c < 4; ++c) upload(p->d_canon[c], canon[c].data(), canon[c].size());
+  if (!ok) {
+    set_error("allocation or upload of the plan tables failed");
     lhf_plan_destroy(p);
     return LHF_ERR_ALLOC;
-  }
-  if (hipMemcpy(p->d_lat, p->lat.data(), sizeof(LatDev) * nlat, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->d_tw64, tw64.data(), sizeof(double2) * tw, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->d_tw32, tw32.data(), sizeof(float2) * tw, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->d_canon, canon.data(), sizeof(int32_t) * canon.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(p->d_gram_items, items.data(), sizeof(GramItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess) {
-    set_error("upload of the plan tables failed");
-    lhf_plan_destroy(p);
-    return LHF_ERR_HIP;
   }
   *out = p;
   return LHF_OK;
@@ -339,11 +352,11 @@ size_t lhf_workspace_size(lhf_plan_t plan) { return plan ? plan->sizes.ws_bytes 
 
 int32_t lhf_plan_destroy(lhf_plan_t plan) {
   if (!plan) return LHF_OK;
-  if (plan->d_lat) (void)hipFree(plan->d_lat);
-  if (plan->d_tw64) (void)hipFree(plan->d_tw64);
-  if (plan->d_tw32) (void)hipFree(plan->d_tw32);
-  if (plan->d_canon) (void)hipFree(plan->d_canon);
-  if (plan->d_gram_items) (void)hipFree(plan->d_gram_items);
+  void* tables[] = {plan->d_lat, plan->d_tw64, plan->d_tw32, plan->d_gram_items, plan->d_fac_items,
+                    plan->d_elem_start, plan->d_dft_tasks, plan->d_canon[0], plan->d_canon[1],
+                    plan->d_canon[2], plan->d_canon[3]};
+  for (void* t : tables)
+    if (t) (void)hipFree(t);
   delete plan;
   return LHF_OK;
 }

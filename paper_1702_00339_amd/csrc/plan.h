@@ -19,19 +19,28 @@ struct lhf_plan_s {
   lhf::LatDev* d_lat = nullptr;         // device table [nlat]
   double2* d_tw64 = nullptr;            // twiddles, complex128
   float2* d_tw32 = nullptr;             // twiddles, complex64
-  int32_t* d_canon = nullptr;           // canonical block of each conjugate pair, per lattice
-  lhf::GramItem* d_gram_items = nullptr;  // grouped Gram work list
+  // grouped work tables (device), built once by lhf_plan_create
+  lhf::GramItem* d_gram_items = nullptr;
   int32_t n_gram_items = 0;
-  std::vector<int64_t> canon_off;       // offset of each lattice's list in d_canon
-  std::vector<int32_t> ncanon;          // list length per lattice
+  lhf::FacItem* d_fac_items = nullptr;
+  int32_t n_fac_items = 0;
+  int64_t* d_elem_start = nullptr;      // [nlat] first combine thread of each lattice (multiple of 256)
+  int64_t combine_threads = 0;          // padded total
+  lhf::DftTask* d_dft_tasks = nullptr;  // every task of every pass
+  std::vector<lhf::DftLaunch> dft_launches;
+  int2* d_canon[4] = {nullptr, nullptr, nullptr, nullptr};  // (lattice, block) per size class M = 4, 8, 16, 32
+  int32_t ncanon[4] = {0, 0, 0, 0};
+  // tunables (set by the planner, refined by lhf_plan_autotune)
+  int32_t dft_target_threads = 131072;  // threads one DFT pass aims to run
+  int32_t gram_grid = 4096;             // workgroups of the grouped Gram launch
   lhf_sizes sizes{};
   // element counts of the workspace sections
   int64_t fac_doubles = 0;
   int64_t part_elems = 0;
-  int64_t dft_tmp_elems = 0;            // complex elements of one DFT ping-pong buffer
+  int64_t dft_tmp_elems = 0;            // complex elements of the DFT intermediates
   // byte offsets of the workspace sections
   size_t ws_fac = 0, ws_grams64 = 0, ws_grams32 = 0, ws_part64 = 0, ws_part32 = 0;
-  size_t ws_dft_a = 0, ws_dft_b = 0, ws_U = 0, ws_info = 0;
+  size_t ws_dft = 0, ws_U = 0, ws_info = 0;
 };
 
 namespace lhf {
@@ -45,30 +54,32 @@ struct Ws {
   float* grams32;
   double* part64;
   float* part32;
-  void* dft_a;
-  void* dft_b;
+  void* dft;
   float2* U;
   int32_t* info32;
 };
 Ws ws_view(const lhf_plan_s* p, void* base);
 
-// factors.hip
-hipError_t launch_factors(const lhf_plan_s* p, int li, double* fac, hipStream_t s);
+// factors.hip: nodal factors and lattice-window potential factors of every lattice
+void plan_factors(const std::vector<LatDev>& lats, std::vector<FacItem>& items);
+hipError_t launch_factors(const lhf_plan_s* p, double* fac, hipStream_t s);
 // gram.hip: every lattice and dimension of the plan in one grouped launch
 // (mode LHF_GRAM_*), then one grouped split-K reduction into the Gram layout
 hipError_t launch_grams(const lhf_plan_s* p, int mode, const double* fac, void* part, void* grams,
                         hipStream_t s);
-// combine.hip
-hipError_t launch_combine(const lhf_plan_s* p, int li, const double* g64, const float* g32,
-                          double* H64, double* S64, float* H32, float* S32, hipStream_t s);
-// blockdft.hip
-hipError_t launch_block_dft(const lhf_plan_s* p, int li, int prec, const void* gen_h, const void* gen_s,
-                            void* bar_h, void* bar_s, void* tmp_a, void* tmp_b, hipStream_t s);
-int64_t block_dft_tmp_elems(const LatDev& L);
-// heev.hip
-hipError_t launch_heev(const lhf_plan_s* p, int li, uint32_t flags, const void* Hbar,
-                       const void* Sbar, const void* Hbar64, const void* Sbar64,
-                       const double* Hgen64, const double* Sgen64, double* w, void* V,
-                       int32_t* info, float2* U, int32_t* info32, hipStream_t s);
+// combine.hip: generator stacks of every lattice
+hipError_t launch_combine(const lhf_plan_s* p, const double* g64, const float* g32, double* H64,
+                          double* S64, float* H32, float* S32, hipStream_t s);
+// blockdft.hip: planner of the grouped passes (task table, launch list and
+// intermediate size in complex elements), and their launch
+void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std::vector<DftTask>& tasks,
+                    std::vector<DftLaunch>& launches, int64_t& tmp_elems);
+hipError_t launch_block_dft(const lhf_plan_s* p, int prec, const void* gen_h, const void* gen_s,
+                            void* bar_h, void* bar_s, void* tmp, hipStream_t s);
+// heev.hip: every canonical block of every lattice, one launch per size class
+int heev_class(int m0);
+hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, const void* Sbar,
+                       const void* Hbar64, const void* Sbar64, const double* Hgen64, const double* Sgen64,
+                       double* w, void* V, int32_t* info, float2* U, int32_t* info32, hipStream_t s);
 
 }  // namespace lhf

@@ -141,6 +141,28 @@ def test_several_lattices_in_one_plan():
             assert (np.abs(got - ref) <= tol).all()
 
 
+def test_grouped_plan_mixes_every_class():
+    """One plan whose lattices differ in everything the grouped launches split
+    on: eigensolver size class (m0 = 1, 5, 6, 15), DFT band class and number
+    of DFT passes (1 to 3, the one-cell lattice being a copy).  The band
+    half-width 17 is forced on every lattice (it only adds zero generators),
+    so the chain's band has 35 slots and takes the wide kernel."""
+    insts = [tiny_instance(L=(40, 1, 1), n=(320, 12, 12), n_s=1, seed=151, exp_range=(0.3, 0.6)),
+             tiny_instance(L=(3, 2, 2), n=(24, 16, 16), n_s=3, n_p=1, seed=152),
+             tiny_instance(L=(1, 1, 1), n=(20, 16, 16), n_s=2, seed=153),
+             tiny_instance(L=(5, 4, 1), n=(40, 32, 12), n_s=2, n_p=1, seed=154),
+             tiny_instance(L=(9, 1, 1), n=(72, 12, 12), n_s=3, n_p=4, R=6, seed=155)]
+    for prec, tol_abs in ((lhf.LHF_PREC_FP64, None), (lhf.LHF_PREC_MIXED, 1e-8)):
+        pipe = _run(insts, prec, L0=(17, 17, 17))
+        nshift, _, full = pipe.plan.lhf_plan_band(0)
+        assert nshift[0] == 35 and full[0] == 0
+        assert (pipe.info.cpu().numpy() == 0).all()
+        for inst, got in zip(insts, pipe.eigenvalues()):
+            _, ref = _eig_ref(inst)
+            tol = tol_abs if tol_abs else 1e-10 * np.maximum(np.abs(ref), 1.0)
+            assert (np.abs(got - ref) <= tol).all(), inst.name
+
+
 def test_eigenvectors_fp64_and_refined():
     inst = tiny_instance(L=(5, 2, 1), n=(40, 16, 14), n_s=2, n_p=1, R=6, seed=131)
     res, ref = _eig_ref(inst)
