@@ -1,14 +1,17 @@
 """Throughput of the periodic hot path on one MI355X: k-point blocks per second.
 
-One step is one full pass of the hot path over the lattice: assemble the
-generator blocks (factors, lattice sums, 1D Grams, combination), block DFT
-over the lattice index, and the generalized eigensolve of every Fourier block
-(with FP64 refinement on the mixed path).  Inputs (the lattice description)
-live in the plan; all buffers are resident in HBM before timing starts.
+One step is one full pass of the hot path over every lattice of the plan:
+assemble the generator blocks (factors, lattice sums, 1D Grams, combination),
+block DFT over the lattice index, and the generalized eigensolve of every
+Fourier block (with FP64 refinement on the mixed path).  Inputs (the lattice
+descriptions) live in the plan; all buffers are resident in HBM before timing
+starts.  Each plan is autotuned first, then one step is captured into a
+hipGraph and the timed steps are graph replays.
 
 Prints one JSON line.  ``value`` is the mixed-precision path's blocks/s; the
 FP64 path is timed the same way and reported beside it.  Both are gated on
-accuracy against the CPU oracle (run once, untimed for the GPU).
+accuracy against the CPU oracle (run once, untimed for the GPU; for the
+64-lattice mix, on one lattice of each basis size).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
 """
@@ -29,7 +32,11 @@ WORKLOADS = {
     "c1": "periodic 8x1x1 chain, m0=4 s, n=128^3, R=20",
     "c2": "periodic 256x1x1 tube, m0=16 (4 s + 4 p shells), n=2048x256x256, R=30",
     "c3": "periodic 32x32x32 lattice, m0=8 s, n=512^3, R=24",
+    "c4": "64 periodic lattices in one grouped plan, L1 in [16,512], L2,L3 in {1,2,4}, m0 in {4,8,16,32}, "
+          "n=16 L (128 across one-cell dims), R=24",
 }
+# lattices of the 64-lattice mix checked against the oracle: the cheapest of each basis size
+C4_CHECK = (28, 41, 52, 2)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -43,40 +50,70 @@ def parse():
     return ap.parse_args()
 
 
-def time_steps(pipe, steps, torch):
+def time_graph(graph, steps, torch):
+    """Wall time per step of `steps` graph replays, bracketed by device
+    synchronisations."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        pipe.step()
+        graph.lhf_graph_launch()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
 
 
-def dft_roofline(pipe, steps, torch, inst):
-    """Average duration of the block-DFT call, timed with events on the stream
-    its kernels run on, and its algorithmic HBM bytes per launch: every
-    Fourier block written once (H and S, complex) plus every band generator
-    read once (H and S, real)."""
-    from paper_1702_00339_amd import lhf
-    p = pipe.plan
-    prec = pipe.prec
-    cbytes = 16 if prec == lhf.LHF_PREC_FP64 else 8
-    rbytes = cbytes // 2
-    m2 = inst.m0 * inst.m0
-    nshift, _, _ = p.lhf_plan_band(0)
-    band = 1
-    for d in range(3):
-        band *= nshift[d]
-    bytes_alg = 2 * inst.ncells * m2 * cbytes + 2 * band * m2 * rbytes
+def event_ms(fn, steps, torch):
+    """Average duration of fn()'s launches, timed with events recorded on the
+    torch current stream (the stream the library launches on)."""
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     for a, b in ev:
         a.record()
-        p.lhf_block_fft(prec, pipe.H_gen, pipe.S_gen, pipe.H_bar, pipe.S_bar, pipe.ws)
+        fn()
         b.record()
     torch.cuda.synchronize()
-    ms = sum(a.elapsed_time(b) for a, b in ev) / steps
-    return bytes_alg, ms
+    return sum(a.elapsed_time(b) for a, b in ev) / steps
+
+
+def dft_bytes(pipe, insts):
+    """Algorithmic HBM bytes of one lhf_block_fft call: every Fourier block
+    written once (H and S, complex) plus every band generator read once (H and
+    S, real)."""
+    from paper_1702_00339_amd import lhf
+    cbytes = 16 if pipe.prec == lhf.LHF_PREC_FP64 else 8
+    rbytes = cbytes // 2
+    total = 0
+    for i, inst in enumerate(insts):
+        m2 = inst.m0 * inst.m0
+        nshift, _, _ = pipe.plan.lhf_plan_band(i)
+        band = 1
+        for d in range(3):
+            band *= nshift[d] if inst.L[d] > 1 else 1
+        total += 2 * inst.ncells * m2 * cbytes + 2 * band * m2 * rbytes
+    return total
+
+
+def canonical_blocks(L):
+    """Blocks solved once per conjugate pair j, -j."""
+    self_conj = 1
+    for x in L:
+        self_conj *= 2 if x % 2 == 0 else 1
+    n = L[0] * L[1] * L[2]
+    return (n + self_conj) // 2
+
+
+def heev_flops(insts, prec, R):
+    """Algorithmic flops of one lhf_heev_batched call: per distinct block
+    150 m0^3 (Cholesky reduction and 6-10 Jacobi sweeps), plus on the mixed
+    path the FP64 refinement, (R + 4) m0^2 8 + 36 m0^3."""
+    from paper_1702_00339_amd import lhf
+    total = 0.0
+    for inst in insts:
+        m = inst.m0
+        per = 150.0 * m ** 3
+        if prec == lhf.LHF_PREC_MIXED:
+            per += (R + 4) * m * m * 8 + 36.0 * m ** 3
+        total += canonical_blocks(inst.L) * per
+    return total
 
 
 def main():
@@ -90,45 +127,68 @@ def main():
 
     from paper_1702_00339_amd import lhf
     from paper_1702_00339_amd.pipeline import Pipeline
-    from synth import make_config
+    from synth import config_c4_lattices, make_config
 
     torch.cuda.set_device(0)
-    inst = make_config(args.config)
-    pipes = {"mixed": Pipeline(inst, prec=lhf.LHF_PREC_MIXED), "fp64": Pipeline(inst, prec=lhf.LHF_PREC_FP64)}
-    for p in pipes.values():
+    if args.config == "c4":
+        insts = config_c4_lattices()
+        checked = [insts[i] for i in C4_CHECK]
+    else:
+        insts = [make_config(args.config)]
+        checked = insts
+    pipes = {"mixed": Pipeline(insts, prec=lhf.LHF_PREC_MIXED), "fp64": Pipeline(insts, prec=lhf.LHF_PREC_FP64)}
+    tuning = {name: p.autotune().as_dict() for name, p in pipes.items()}
+    graphs = {name: p.capture() for name, p in pipes.items()}
+    for g in graphs.values():
         for _ in range(args.warmup):
-            p.step()
+            g.lhf_graph_launch()
     torch.cuda.synchronize()
 
     # accuracy gate against the CPU oracle (also the CPU baseline's first run)
     from oracle import separable
     t0 = time.perf_counter()
-    ref = np.sort(separable.solve(inst)["eig"], axis=-1)
+    refs = [np.sort(separable.solve(inst)["eig"], axis=-1) for inst in checked]
     t_oracle_first = time.perf_counter() - t0
     errs = {}
     for name, p in pipes.items():
-        p.step()
+        graphs[name].lhf_graph_launch()
         torch.cuda.synchronize()
-        got = p.eigenvalues()[0]
-        info_ok = bool((p.info.cpu().numpy() == 0).all())
-        errs[name] = (float(np.abs(got - ref).max()),
-                      float((np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)).max()), info_ok)
+        all_w = p.eigenvalues()
+        got = {inst.name: w for inst, w in zip(insts, all_w)}
+        ea, er = 0.0, 0.0
+        for inst, ref in zip(checked, refs):
+            w = got[inst.name]
+            ea = max(ea, float(np.abs(w - ref).max()))
+            er = max(er, float((np.abs(w - ref) / np.maximum(np.abs(ref), 1.0)).max()))
+        errs[name] = (ea, er, bool((p.info.cpu().numpy() == 0).all()))
 
-    # timed region
-    sec = {name: time_steps(p, args.steps, torch) for name, p in pipes.items()}
-    nblk = inst.ncells
+    # timed region: graph replays
+    sec = {name: time_graph(graphs[name], args.steps, torch) for name in pipes}
+    nblk = sum(inst.ncells for inst in insts)
     value = nblk / sec["mixed"]
 
-    # roofline of the block DFT (HBM-bound) on the mixed path
-    bytes_alg, ms_dft = dft_roofline(pipes["mixed"], args.steps, torch, inst)
+    # rooflines, event-timed on the stream the kernels run on
+    pm = pipes["mixed"]
+    ms_dft = event_ms(lambda: pm.plan.lhf_block_fft(pm.prec, pm.H_gen, pm.S_gen, pm.H_bar, pm.S_bar, pm.ws),
+                      args.steps, torch)
+    bytes_alg = dft_bytes(pm, insts)
     achieved = bytes_alg / (ms_dft * 1e-3) / 1e9
+    flags = lhf.LHF_HEEV_REFINE_FP64
+    ms_heev = event_ms(lambda: pm.plan.lhf_heev_batched(flags, pm.H_bar, pm.S_bar, pm.w, pm.info, pm.ws,
+                                                         H_bar64=pm.H_bar64, S_bar64=pm.S_bar64,
+                                                         H_gen64=pm.H_gen64, S_gen64=pm.S_gen64),
+                       args.steps, torch)
+    R = insts[0].R
+    flops = heev_flops(insts, pm.prec, R)
+    tflops = flops / (ms_heev * 1e-3) / 1e12
 
     cpu = None
     if not args.no_cpu_baseline:
         runs = [t_oracle_first]
         while sum(runs) < 10.0 and len(runs) < 8:
             t0 = time.perf_counter()
-            separable.solve(inst)
+            for inst in checked:
+                separable.solve(inst)
             runs.append(time.perf_counter() - t0)
         try:
             from threadpoolctl import threadpool_info
@@ -136,25 +196,35 @@ def main():
         except Exception:
             cores = os.cpu_count()
         tmed = float(np.median(runs))
-        cpu = {"value": nblk / tmed, "unit": "blocks/s", "cores": int(cores), "kind": "oracle",
-               "sample": f"the whole {args.config} lattice ({nblk} blocks) through the oracle's separable "
-                         f"route (1D Grams for every shift, combination, FFT, batched LAPACK eigensolves), "
-                         f"median of {len(runs)} runs of {tmed:.2f} s"}
+        nchk = sum(inst.ncells for inst in checked)
+        what = (f"the whole {args.config} lattice" if len(checked) == len(insts) else
+                f"{len(checked)} of the {len(insts)} lattices (one per basis size)")
+        cpu = {"value": nchk / tmed, "unit": "blocks/s", "cores": int(cores), "kind": "oracle",
+               "sample": f"{what} ({nchk} blocks) through the oracle's separable route (1D Grams for every "
+                         f"shift, combination, FFT, batched LAPACK eigensolves), median of {len(runs)} runs "
+                         f"of {tmed:.2f} s"}
 
+    m0s = sorted({inst.m0 for inst in insts})
     line = {
         "metric": METRIC, "value": value, "unit": "blocks/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": sec["mixed"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "k_point_blocks": nblk,
-                   "m0": inst.m0, "path": "mixed: bf16 hi+lo MFMA Grams, complex64 DFT, FP32 Jacobi, "
-                                          "FP64 Rayleigh-Ritz refinement"},
+        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "lattices": len(insts),
+                   "k_point_blocks": nblk, "m0": m0s if len(m0s) > 1 else m0s[0],
+                   "path": "mixed: bf16 hi+lo MFMA Grams, complex64 DFT, FP32 Jacobi, FP64 Rayleigh-Ritz "
+                           "refinement; one hipGraph replay per step"},
         "fp64_path": {"value": nblk / sec["fp64"], "ms_per_step": sec["fp64"] * 1e3, "dtype": "f64"},
-        "accuracy": {"mixed_max_abs_eig_err_ha": errs["mixed"][0], "mixed_info_ok": errs["mixed"][2],
+        "accuracy": {"lattices_checked": len(checked),
+                     "mixed_max_abs_eig_err_ha": errs["mixed"][0], "mixed_info_ok": errs["mixed"][2],
                      "fp64_max_rel_eig_err": errs["fp64"][1], "fp64_info_ok": errs["fp64"][2]},
-        "roofline": {"bound": "hbm", "kernel": "block DFT (lhf_block_fft, complex64)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_alg, "avg_launch_ms": ms_dft},
+        "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: FP32 Jacobi + FP64 refinement)",
+                     "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s", "frac": tflops / 157.3,
+                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": ms_heev},
+        "roofline_dft": {"bound": "hbm", "kernel": "block DFT (lhf_block_fft, complex64)",
+                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_launch": bytes_alg, "avg_launch_ms": ms_dft},
+        "tuning": tuning,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

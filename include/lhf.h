@@ -216,6 +216,86 @@ int32_t lhf_heev_batched(lhf_plan_t plan, uint32_t flags, const void* d_H_bar, c
                          double* d_w, void* d_V, int32_t* d_info,
                          void* d_ws, size_t ws_bytes, lhf_stream_t stream);
 
+/* ---------------------------------------------------------------- whole step
+ * The buffers of one step of the plan: assembly, block DFT and eigensolve.
+ * Same meaning, layout and precision as in the calls above.  Required:
+ * H_gen, S_gen, H_bar, S_bar, w, info, ws.  Mixed plans with
+ * LHF_HEEV_REFINE_FP64 also need H_gen64 and S_gen64 (written by the
+ * assembly); when H_bar64 and S_bar64 are given as well, the step fills them
+ * with a complex128 block DFT and refinement reads them, otherwise
+ * refinement regenerates each block from the FP64 band.  grams64 may be
+ * NULL (the workspace holds the Grams), V is needed with LHF_HEEV_VECTORS. */
+typedef struct {
+  void* H_gen;
+  void* S_gen;
+  double* grams64;
+  double* H_gen64;
+  double* S_gen64;
+  void* H_bar;
+  void* S_bar;
+  void* H_bar64;
+  void* S_bar64;
+  double* w;
+  void* V;
+  int32_t* info;
+  void* ws;
+  size_t ws_bytes;
+  uint32_t heev_flags;   /* LHF_HEEV_* */
+} lhf_step_args;
+
+/* Enqueue one whole step (the calls above in order) on `stream`.
+ * Errors: those of the calls above; nothing is enqueued after the first. */
+int32_t lhf_step(lhf_plan_t plan, const lhf_step_args* args, lhf_stream_t stream);
+
+/* A step captured once into a HIP graph (every launch of the plan, grouped
+ * over its lattices; no memset nodes) and replayed with one call.  The
+ * buffers named in `args` are baked into the graph: they must stay allocated
+ * while it exists, and a replay overwrites them as lhf_step would.
+ * lhf_graph_create allocates (graph and executable graph; capture runs on a
+ * private stream of default priority) and launches nothing; replays of one
+ * graph on several streams at once race on its buffers.
+ * Errors: those of lhf_step, LHF_ERR_HIP (capture or instantiation failed). */
+typedef struct lhf_graph_s* lhf_graph_t;
+int32_t lhf_graph_create(lhf_plan_t plan, const lhf_step_args* args, lhf_graph_t* out);
+int32_t lhf_graph_launch(lhf_graph_t graph, lhf_stream_t stream);
+int32_t lhf_graph_destroy(lhf_graph_t graph);
+
+/* ---------------------------------------------------------------- autotuner
+ * Launch shapes and sweep schedule of a plan:
+ *   dft_threads  threads one grouped block-DFT pass aims to run (sets the
+ *                outputs per thread along the transformed axis);
+ *   gram_split   split-K target of the Gram contraction, workgroups per
+ *                (lattice, dimension), <= 256;
+ *   gram_grid    workgroups of the persistent grouped Gram launch;
+ *   tol32_scale  mixed plans: multiplier of the FP32 Jacobi stopping
+ *                tolerance (the FP64 refinement converges to the same
+ *                tolerance whatever the FP32 schedule).
+ * None of them changes what is computed; the Gram split changes the order of
+ * the FP64 partial sums. */
+typedef struct {
+  int32_t dft_threads;
+  int32_t gram_split;
+  int32_t gram_grid;
+  int32_t tol32_scale;
+  double step_ms;        /* autotune: mean time of one step with these settings */
+  int32_t from_cache;    /* autotune: 1 when read from the cache file         */
+} lhf_tuning;
+
+int32_t lhf_plan_get_tuning(lhf_plan_t plan, lhf_tuning* out);
+/* Apply settings (fields outside their range -> LHF_ERR_INVALID).  Rebuilds
+ * and uploads the plan's work tables synchronously: no work of the plan may
+ * be pending. */
+int32_t lhf_plan_set_tuning(lhf_plan_t plan, const lhf_tuning* in);
+/* Time candidate settings stage by stage on `stream` with HIP events (runs
+ * steps with `args`, overwriting its buffers), keep the fastest, and report
+ * them in *out (may be NULL).  cache_path (may be NULL): a JSON file keyed by
+ * the plan's work signature and the device (architecture, compute units);
+ * a hit applies the stored settings without timing, a miss appends the
+ * result.  Synchronous; no other work of the plan may be pending.
+ * Errors: those of lhf_step, LHF_ERR_HIP. */
+int32_t lhf_plan_autotune(lhf_plan_t plan, const lhf_step_args* args, lhf_stream_t stream,
+                          const char* cache_path, lhf_tuning* out);
+
 /* ---------------------------------------------------------------- status */
 const char* lhf_status_string(int32_t status);
 const char* lhf_last_error(void);

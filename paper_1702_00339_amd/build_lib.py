@@ -24,7 +24,7 @@ FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
 
-SOURCES = ["plan.cpp", "api.cpp", "factors.hip", "gram.hip", "combine.hip", "blockdft.hip",
+SOURCES = ["plan.cpp", "api.cpp", "step.cpp", "factors.hip", "gram.hip", "combine.hip", "blockdft.hip",
            "heev.hip", "toeplitz.hip"]
 
 

@@ -675,7 +675,7 @@ hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, co
   const int vm = refine ? 2 : (wantv ? 1 : 0);
   void* vdst = refine ? (void*)U : V;
   int32_t* i32 = refine ? info32 : info;
-  const float eps = 5.9604645e-08f;
+  const float eps = 5.9604645e-08f * (float)p->tol32_scale;
   if (e == hipSuccess) e = launch_heev_m<float, 4>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 16 * eps, s);
   if (e == hipSuccess) e = launch_heev_m<float, 8>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 32 * eps, s);
   if (e == hipSuccess) e = launch_heev_m<float, 16>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 64 * eps, s);

@@ -19,6 +19,20 @@ bool finite(double x) { return std::isfinite(x); }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+// FNV-1a over the derived lattice tables and the precision choices: equal
+// signatures mean equal work, so tuned launch shapes carry over.
+uint64_t plan_signature(const lhf_plan_s* p) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* data, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  };
+  mix(&p->prec, sizeof(p->prec));
+  mix(&p->gram, sizeof(p->gram));
+  mix(p->lat.data(), sizeof(LatDev) * p->lat.size());
+  return h;
+}
+
 Ws ws_view(const lhf_plan_s* p, void* base) {
   char* b = static_cast<char*>(base);
   Ws w;
@@ -31,6 +45,36 @@ Ws ws_view(const lhf_plan_s* p, void* base) {
   w.U = reinterpret_cast<float2*>(b + p->ws_U);
   w.info32 = reinterpret_cast<int32_t*>(b + p->ws_info);
   return w;
+}
+
+// Split-K of the Gram contraction of dimension d over 64 x 64 workgroup
+// tiles: at least 64 window nodes per split, about `target` workgroups per
+// (lattice, dimension).  The split count is monotone in `target`, so a plan
+// sized with kGramSplitMax has room for every smaller target.
+void set_gram_split(LatDev& L, int d, int target) {
+  DimDev& D = L.dim[d];
+  const int M = L.T * L.m0, N = D.nshift * L.m0;
+  const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
+  int ks = (int)std::max<int64_t>(1, (target + tiles - 1) / tiles);
+  ks = std::min(ks, std::max(1, D.kwin / 64));
+  const int kchunk = ((D.kwin + ks - 1) / ks + 31) / 32 * 32;
+  D.kchunk = kchunk;
+  D.ksplit = (D.kwin + kchunk - 1) / kchunk;
+}
+
+// Grouped Gram work list: one item per (lattice, dimension, 64x64 tile, split).
+void plan_grams(const std::vector<LatDev>& lats, std::vector<GramItem>& items) {
+  items.clear();
+  for (int i = 0; i < (int)lats.size(); ++i) {
+    const LatDev& L = lats[i];
+    for (int d = 0; d < 3; ++d) {
+      const DimDev& D = L.dim[d];
+      const int M = L.T * L.m0, N = D.nshift * L.m0;
+      for (int tm = 0; tm < (M + 63) / 64; ++tm)
+        for (int tn = 0; tn < (N + 63) / 64; ++tn)
+          for (int ks = 0; ks < D.ksplit; ++ks) items.push_back(GramItem{i, d, tm, tn, ks, 0});
+    }
+  }
 }
 
 // Fill one lattice's device descriptor; returns LHF_OK or an error code.
@@ -155,15 +199,7 @@ static int32_t derive_lattice(const lhf_lattice& in, int idx, LatDev& L, std::st
         D.kstart = nd - W * D.nc;
       }
     }
-    // split-K of the Gram contraction over 64 x 64 workgroup tiles: at least
-    // 64 window nodes per split, ~256 workgroups per (lattice, dimension)
-    int M = L.T * L.m0, N = D.nshift * L.m0;
-    int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
-    int ks = (int)std::max<int64_t>(1, (256 + tiles - 1) / tiles);
-    ks = std::min(ks, std::max(1, D.kwin / 64));
-    int kchunk = ((D.kwin + ks - 1) / ks + 31) / 32 * 32;
-    D.kchunk = kchunk;
-    D.ksplit = (D.kwin + kchunk - 1) / kchunk;
+    set_gram_split(L, d, kGramSplitMax);
   }
   if (nblk * c.m0 * c.m0 >= ((int64_t)1 << 31)) {
     err = "lattice " + std::to_string(idx) + ": L1 L2 L3 m0^2 >= 2^31 unsupported";
@@ -224,6 +260,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
     L.w_off = w; w += (int64_t)L.nblk * L.m0;
     L.blk_off = blk; blk += L.nblk;
   }
+  p->signature = plan_signature(p);
   std::vector<DftTask> dft_tasks;
   int64_t dtmp = 0;
   plan_block_dft(p->lat, p->dft_target_threads, dft_tasks, p->dft_launches, dtmp);
@@ -248,18 +285,8 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->ws_dft = off; off = align256(off + (size_t)dtmp * 16);   // complex128 (either precision)
   p->sizes.ws_bytes = off;
 
-  // grouped Gram work: one item per (lattice, dimension, 64x64 tile, split)
   std::vector<GramItem> items;
-  for (int i = 0; i < nlat; ++i) {
-    const LatDev& L = p->lat[i];
-    for (int d = 0; d < 3; ++d) {
-      const DimDev& D = L.dim[d];
-      const int M = L.T * L.m0, N = D.nshift * L.m0;
-      for (int tm = 0; tm < (M + 63) / 64; ++tm)
-        for (int tn = 0; tn < (N + 63) / 64; ++tn)
-          for (int ks = 0; ks < D.ksplit; ++ks) items.push_back(GramItem{i, d, tm, tn, ks, 0});
-    }
-  }
+  plan_grams(p->lat, items);
   p->n_gram_items = (int32_t)items.size();
 
   // grouped factor work

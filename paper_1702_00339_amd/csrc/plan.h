@@ -30,9 +30,12 @@ struct lhf_plan_s {
   std::vector<lhf::DftLaunch> dft_launches;
   int2* d_canon[4] = {nullptr, nullptr, nullptr, nullptr};  // (lattice, block) per size class M = 4, 8, 16, 32
   int32_t ncanon[4] = {0, 0, 0, 0};
-  // tunables (set by the planner, refined by lhf_plan_autotune)
+  // tunables (planner defaults, refined by lhf_plan_autotune)
   int32_t dft_target_threads = 131072;  // threads one DFT pass aims to run
   int32_t gram_grid = 4096;             // workgroups of the grouped Gram launch
+  int32_t gram_split = 256;             // split-K target: workgroups per (lattice, dimension)
+  int32_t tol32_scale = 1;              // mixed plans: FP32 Jacobi tolerance multiplier
+  uint64_t signature = 0;               // plan_signature() at creation
   lhf_sizes sizes{};
   // element counts of the workspace sections
   int64_t fac_doubles = 0;
@@ -59,6 +62,11 @@ struct Ws {
   int32_t* info32;
 };
 Ws ws_view(const lhf_plan_s* p, void* base);
+
+constexpr int kGramSplitMax = 256;   // split-K target the workspace is sized for
+void set_gram_split(LatDev& L, int d, int target);
+void plan_grams(const std::vector<LatDev>& lats, std::vector<GramItem>& items);
+uint64_t plan_signature(const lhf_plan_s* p);
 
 // factors.hip: nodal factors and lattice-window potential factors of every lattice
 void plan_factors(const std::vector<LatDev>& lats, std::vector<FacItem>& items);

@@ -40,6 +40,21 @@ class lhf_sizes(C.Structure):
                 ("w_elems", C.c_int64), ("grams_elems", C.c_int64), ("ws_bytes", C.c_size_t)]
 
 
+class lhf_step_args(C.Structure):
+    _fields_ = [("H_gen", C.c_void_p), ("S_gen", C.c_void_p), ("grams64", C.c_void_p), ("H_gen64", C.c_void_p),
+                ("S_gen64", C.c_void_p), ("H_bar", C.c_void_p), ("S_bar", C.c_void_p), ("H_bar64", C.c_void_p),
+                ("S_bar64", C.c_void_p), ("w", C.c_void_p), ("V", C.c_void_p), ("info", C.c_void_p),
+                ("ws", C.c_void_p), ("ws_bytes", C.c_size_t), ("heev_flags", C.c_uint32)]
+
+
+class lhf_tuning(C.Structure):
+    _fields_ = [("dft_threads", C.c_int32), ("gram_split", C.c_int32), ("gram_grid", C.c_int32),
+                ("tol32_scale", C.c_int32), ("step_ms", C.c_double), ("from_cache", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class LhfError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"lhf status {status}: {message}")
@@ -70,6 +85,13 @@ def load(path: str = LIB_PATH):
         "lhf_assemble_blocks": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "lhf_block_fft": (i32, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),
         "lhf_heev_batched": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "lhf_step": (i32, [vp, C.POINTER(lhf_step_args), vp]),
+        "lhf_graph_create": (i32, [vp, C.POINTER(lhf_step_args), C.POINTER(vp)]),
+        "lhf_graph_launch": (i32, [vp, vp]),
+        "lhf_graph_destroy": (i32, [vp]),
+        "lhf_plan_get_tuning": (i32, [vp, C.POINTER(lhf_tuning)]),
+        "lhf_plan_set_tuning": (i32, [vp, C.POINTER(lhf_tuning)]),
+        "lhf_plan_autotune": (i32, [vp, C.POINTER(lhf_step_args), vp, C.c_char_p, C.POINTER(lhf_tuning)]),
         "lhf_status_string": (C.c_char_p, [i32]),
         "lhf_last_error": (C.c_char_p, []),
         "lhf_version": (i32, []),
@@ -85,8 +107,9 @@ def load(path: str = LIB_PATH):
 def exported_symbols():
     """Names the binding expects the library to export."""
     return ["lhf_plan_create", "lhf_plan_sizes", "lhf_plan_band", "lhf_workspace_size", "lhf_plan_destroy",
-            "lhf_assemble_blocks", "lhf_block_fft", "lhf_heev_batched", "lhf_status_string",
-            "lhf_last_error", "lhf_version"]
+            "lhf_assemble_blocks", "lhf_block_fft", "lhf_heev_batched", "lhf_step", "lhf_graph_create",
+            "lhf_graph_launch", "lhf_graph_destroy", "lhf_plan_get_tuning", "lhf_plan_set_tuning",
+            "lhf_plan_autotune", "lhf_status_string", "lhf_last_error", "lhf_version"]
 
 
 def _check(st):
@@ -194,3 +217,47 @@ class Plan:
         _check(load().lhf_heev_batched(self.handle, flags, _ptr(H_bar), _ptr(S_bar), _ptr(H_bar64),
                                        _ptr(S_bar64), _ptr(H_gen64), _ptr(S_gen64), _ptr(w), _ptr(V),
                                        _ptr(info), _ptr(ws), ws.numel(), _stream()))
+
+    def lhf_step(self, args):
+        _check(load().lhf_step(self.handle, C.byref(args), _stream()))
+
+    def lhf_plan_get_tuning(self):
+        t = lhf_tuning()
+        _check(load().lhf_plan_get_tuning(self.handle, C.byref(t)))
+        return t
+
+    def lhf_plan_set_tuning(self, tuning):
+        _check(load().lhf_plan_set_tuning(self.handle, C.byref(tuning)))
+
+    def lhf_plan_autotune(self, args, cache_path=None):
+        t = lhf_tuning()
+        path = cache_path.encode() if cache_path else None
+        _check(load().lhf_plan_autotune(self.handle, C.byref(args), _stream(), path, C.byref(t)))
+        return t
+
+    def lhf_graph_create(self, args):
+        return Graph(self, args)
+
+
+class Graph:
+    """A captured step (lhf_graph_create); keeps its plan and args alive."""
+
+    def __init__(self, plan, args):
+        self.plan, self.args = plan, args
+        h = C.c_void_p()
+        _check(load().lhf_graph_create(plan.handle, C.byref(args), C.byref(h)))
+        self.handle = h
+
+    def lhf_graph_launch(self):
+        _check(load().lhf_graph_launch(self.handle, _stream()))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().lhf_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -57,6 +57,30 @@ class Pipeline:
         else:
             self.refine_src = None
 
+    def step_args(self):
+        """The lhf_step_args of this pipeline's buffers (kept alive by self)."""
+        def ptr(t):
+            return None if t is None else t.data_ptr()
+
+        flags = lhf.LHF_HEEV_VECTORS if self.want_vectors else 0
+        if self.prec == lhf.LHF_PREC_MIXED:
+            flags |= lhf.LHF_HEEV_REFINE_FP64
+        return lhf.lhf_step_args(ptr(self.H_gen), ptr(self.S_gen), ptr(self.grams64), ptr(self.H_gen64),
+                                 ptr(self.S_gen64), ptr(self.H_bar), ptr(self.S_bar), ptr(self.H_bar64),
+                                 ptr(self.S_bar64), ptr(self.w), ptr(self.V), ptr(self.info), ptr(self.ws),
+                                 self.ws.numel(), flags)
+
+    def step_native(self):
+        """One step through the single lhf_step call."""
+        self.plan.lhf_step(self.step_args())
+
+    def capture(self):
+        """A hipGraph of one step over this pipeline's buffers (lhf.Graph)."""
+        return self.plan.lhf_graph_create(self.step_args())
+
+    def autotune(self, cache_path=None):
+        return self.plan.lhf_plan_autotune(self.step_args(), cache_path)
+
     def step(self):
         p = self.plan
         if self.prec == lhf.LHF_PREC_FP64:

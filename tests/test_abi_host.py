@@ -110,3 +110,17 @@ def test_hot_calls_reject_null_plan(lib):
     assert lib.lhf_block_fft(None, 0, None, None, None, None, None, 0, None) == lhf.LHF_ERR_INVALID
     assert lib.lhf_heev_batched(None, 0, None, None, None, None, None, None, None, None, None, None, 0,
                                 None) == lhf.LHF_ERR_INVALID
+
+
+def test_step_graph_and_tuning_reject_null(lib):
+    args = lhf.lhf_step_args()
+    assert lib.lhf_step(None, C.byref(args), None) == lhf.LHF_ERR_INVALID
+    h = C.c_void_p()
+    assert lib.lhf_graph_create(None, C.byref(args), C.byref(h)) == lhf.LHF_ERR_INVALID
+    assert h.value is None
+    assert lib.lhf_graph_launch(None, None) == lhf.LHF_ERR_INVALID
+    assert lib.lhf_graph_destroy(None) == lhf.LHF_OK
+    t = lhf.lhf_tuning()
+    assert lib.lhf_plan_get_tuning(None, C.byref(t)) == lhf.LHF_ERR_INVALID
+    assert lib.lhf_plan_set_tuning(None, C.byref(t)) == lhf.LHF_ERR_INVALID
+    assert lib.lhf_plan_autotune(None, C.byref(args), None, None, None) == lhf.LHF_ERR_INVALID
