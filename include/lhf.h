@@ -216,6 +216,88 @@ int32_t lhf_heev_batched(lhf_plan_t plan, uint32_t flags, const void* d_H_bar, c
                          double* d_w, void* d_V, int32_t* d_info,
                          void* d_ws, size_t ws_bytes, lhf_stream_t stream);
 
+/* ---------------------------------------------------------------- Dirichlet chain
+ * A box chain of L cells along dimension 1 (all dimensions Dirichlet, L2 = L3
+ * = 1) with defect cells, as a perturbed block-Toeplitz pair (Sec. 3, the
+ * box-case discussion of defects; Remark 3.2 for the circulant embedding):
+ *   * T: block-Toeplitz from the pristine cell, A_s = <g_(0,mu), H_rep g_(s,nu)>,
+ *     s = 0..L0, on the chain grid without walls; H_rep carries the central
+ *     cell's lattice-window potential (window of L cells) replicated to every
+ *     cell; T(k, m) = A_(m-k), A_(-s) = A_s^T, zero beyond the band L0;
+ *   * crosses: every block (k, m), |k - m| <= L0, with k or m in X = defect
+ *     cells and cells within L0 of a wall, is the block of the actual basis
+ *     (defect exponents scaled) on the box grid with its walls and potential
+ *     H_rep's plus, for each defect cell c in {k, m}, (Z_def - Z_nu) times the
+ *     rank-R potential of nucleus nu of cell c;
+ *   * L0 from the smallest exponent over pristine and defect cells (overlap
+ *     decay below 1e-22), capped at L - 1.
+ * The chain's nodes must be cell aligned: n1 = nc L and pad1 = a / (2 nc).
+ * The same model is built by the CPU oracle. */
+typedef struct {
+  lhf_lattice lat;          /* bc = LHF_BC_DIRICHLET, L = {L, 1, 1}; lat.L0 ignored   */
+  int32_t ndef;             /* defect cells, >= 0                                       */
+  const int32_t* def_cells; /* [ndef] distinct cell indices in [0, L)                   */
+  const double* def_Z;      /* [ndef] charge of every nucleus of the defect cell, > 0   */
+  const double* def_scale;  /* [ndef] factor on every exponent of the defect cell, > 0  */
+} lhf_box;
+
+typedef struct {
+  int32_t L, m0, L0;        /* cells, functions per cell, band half-width             */
+  int32_t N;                /* m0 L                                                   */
+  int32_t P;                /* circulant embedding length (power of two >= L + L0)    */
+  int32_t ncross;           /* cells in X                                             */
+  int32_t ncross_blocks;    /* cross blocks (k, m) with k <= m                         */
+  double sigma;             /* shift of the circulant preconditioner                  */
+} lhf_toeplitz_info;
+
+/* Validate, derive the model and assemble it on the current device
+ * (synchronous; allocates the operator's device tables: generators, cross
+ * blocks, the embedding's per-frequency blocks and the preconditioner).
+ * Errors: LHF_ERR_INVALID (descriptor), LHF_ERR_UNSUPPORTED (not a cell-aligned
+ * Dirichlet chain, m0 > 32, ...), LHF_ERR_ALLOC, LHF_ERR_HIP. */
+int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out);
+int32_t lhf_toeplitz_get_info(lhf_toeplitz_t tp, lhf_toeplitz_info* out);
+/* Copy the model's blocks to device buffers (each may be NULL):
+ * d_gen_H, d_gen_S: FP64 [L0 + 1][m0][m0], A_s row mu, column nu;
+ * d_cross_km: int32 [ncross_blocks][2] (k, m), k <= m, ascending;
+ * d_cross_H, d_cross_S: FP64 [ncross_blocks][m0][m0], the model's block (k, m).
+ * Synchronous.  Errors: LHF_ERR_INVALID. */
+int32_t lhf_toeplitz_blocks(lhf_toeplitz_t tp, double* d_gen_H, double* d_gen_S, int32_t* d_cross_km,
+                            double* d_cross_H, double* d_cross_S);
+/* Workspace bytes of lhf_toeplitz_matvec for up to ncols vectors. */
+size_t lhf_toeplitz_matvec_workspace(lhf_toeplitz_t tp, int32_t ncols);
+/* y_H = H_model x, y_S = S_model x for ncols vectors: T x through the block
+ * circulant embedding (forward FFT over the cell index, one m0 x m0 product
+ * per frequency, inverse FFT, first L blocks) plus the cross corrections.
+ * x, y_H, y_S: device FP64, row-major [N][ld] (ld >= ncols; column j is
+ * vector j; row k m0 + mu is function mu of cell k).  prec: LHF_PREC_FP64
+ * (complex128 transform) or LHF_PREC_MIXED (the Toeplitz part with FP32
+ * inputs and complex64 transform; the crosses in FP64).  y_S may be NULL.
+ * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE. */
+int32_t lhf_toeplitz_matvec(lhf_toeplitz_t tp, int32_t prec, int32_t ncols, const double* x, double* y_H,
+                            double* y_S, int32_t ld, void* d_ws, size_t ws_bytes, lhf_stream_t stream);
+/* Workspace bytes of lhf_toeplitz_eigs for nev wanted eigenpairs. */
+size_t lhf_toeplitz_eigs_workspace(lhf_toeplitz_t tp, int32_t nev);
+/* The nev lowest eigenpairs of (H_model, S_model) by block LOBPCG (Knyazev)
+ * with nev + 8 vectors: basis [X, W, P], W the residuals through the circulant
+ * preconditioner (H_c - sigma S_c)^-1 per frequency (H_c, S_c the embedding's
+ * blocks; sigma below their spectrum), images recomputed by matvecs every
+ * iteration, S-orthonormalised in FP64 (SVQB), FP64 Rayleigh-Ritz; matvecs in
+ * FP32 until the largest residual of the wanted pairs is below 1e-4, then in
+ * FP64 until it is below tol.  The start block is drawn from a counter-based
+ * generator (SplitMix64) with `seed`.  Runs on `stream` and synchronises it
+ * once per iteration (convergence test on the host).
+ * d_w: device FP64 [nev] ascending; d_V: device FP64 [N][nev] or NULL
+ * (S-orthonormal eigenvectors); *iters (host, may be NULL): iterations used.
+ * Returns LHF_OK also when maxit is reached (then *iters == maxit and the
+ * residual test failed; *resid (host, may be NULL) gets the largest residual).
+ * Errors: LHF_ERR_INVALID (nev < 1, nev + 8 > N, 3 (nev + 8) > 192),
+ * LHF_ERR_WORKSPACE, LHF_ERR_HIP. */
+int32_t lhf_toeplitz_eigs(lhf_toeplitz_t tp, int32_t nev, int32_t maxit, double tol, uint64_t seed,
+                          double* d_w, double* d_V, int32_t* iters, double* resid, void* d_ws,
+                          size_t ws_bytes, lhf_stream_t stream);
+int32_t lhf_toeplitz_destroy(lhf_toeplitz_t tp);
+
 /* ---------------------------------------------------------------- whole step
  * The buffers of one step of the plan: assembly, block DFT and eigensolve.
  * Same meaning, layout and precision as in the calls above.  Required:

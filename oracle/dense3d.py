@@ -15,6 +15,11 @@ on the 3D grid, and A_3 = A x S x S + S x A x S + S x S x A, S_3 = S x S x S
 act on the 3D nodal arrays (Kronecker action).  Then it solves H c = lambda S c
 densely (generalized problem of Sec. 2.1).
 
+Defect cells (Dirichlet chains): the functions of a defect cell have their
+exponents multiplied by its scale factor, and its nuclei carry the defect
+charge: the change Z_def - Z_nu is added as the potential of an isolated
+nucleus at its position, on every node (no window, no replication).
+
 Basis order: cell index (k1 L2 + k2) L3 + k3, then mu.
 Feasible for N * n1 n2 n3 up to ~1e9 (the 8-cell chain at 128^3 is the
 largest case used).
@@ -46,11 +51,13 @@ def basis_3d(inst, gs):
     X = np.meshgrid(gs[0].x, gs[1].x, gs[2].x, indexing="ij")
     L1, L2, L3 = inst.L
     out = np.empty((inst.m0 * L1 * L2 * L3, X[0].size))
+    scale = {int(c): float(f) for c, f in zip(inst.def_cells, inst.def_scale)}
     row = 0
     for k1, k2, k3 in itertools.product(range(L1), range(L2), range(L3)):
         kk = (k1, k2, k3)
+        f_cell = scale.get(cell_index(inst.L, kk), 1.0)
         for mu in range(inst.m0):
-            alpha = float(inst.alpha[mu])
+            alpha = float(inst.alpha[mu]) * f_cell
             ls = [angular_power(int(inst.ang[mu]), ell) for ell in range(3)]
             nrm = np.prod([gto_norm(alpha, ls[ell]) for ell in range(3)])
             c = [gs[ell].centres[kk[ell]] + inst.centre[mu, ell] for ell in range(3)]
@@ -95,6 +102,17 @@ def potential_3d(inst, gs):
                 f = [cell_integral_gauss(ys[ell], gs[ell].h, t[q], A[ell] + kk[ell] * gs[ell].a)
                      for ell in range(3)]
                 p += (inst.Z[nu] * w[q] * w1 * w2 * w3) * np.einsum("i,j,k->ijk", f[0], f[1], f[2])
+    # defect charges: isolated nuclei at their positions
+    L1, L2, L3 = inst.L
+    for c, zc in zip(inst.def_cells, inst.def_Z):
+        c = int(c)
+        kk = (c // (L2 * L3), (c // L3) % L2, c % L3)
+        for nu in range(inst.M0):
+            dz = float(zc) - float(inst.Z[nu])
+            A = [gs[ell].centres[kk[ell]] + inst.nuc[nu, ell] for ell in range(3)]
+            for q in range(inst.R):
+                f = [cell_integral_gauss(gs[ell].x, gs[ell].h, t[q], A[ell]) for ell in range(3)]
+                p += (dz * w[q]) * np.einsum("i,j,k->ijk", f[0], f[1], f[2])
     return p
 
 

@@ -1,0 +1,366 @@
+// Dense FP64 kernels of the block LOBPCG driver: Gram products of tall
+// blocks, block combinations, residuals, SVQB helpers and a one-workgroup
+// symmetric eigensolver for the Rayleigh-Ritz problems (size <= 128).
+//
+// Blocks of vectors are row-major [N][ld] (column j = vector j).  Reductions
+// over N are split into fixed chunks whose partial results are added in chunk
+// order, so every result is deterministic.
+#include <algorithm>
+
+#include "toeplitz.h"
+
+namespace lhf {
+namespace {
+
+constexpr int kGT = 32;      // Gram output tile
+constexpr int kGRows = 64;   // rows staged per step
+
+// part[c][i][j] = sum over rows n of chunk c of A[n][i] B[n][j]
+__global__ void __launch_bounds__(256) gram_part_kernel(int N, int k1, int k2, int chunk, const double* __restrict__ A,
+                                                        int lda, const double* __restrict__ B, int ldb,
+                                                        double* __restrict__ part) {
+  __shared__ double As[kGRows][kGT + 1];
+  __shared__ double Bs[kGRows][kGT + 1];
+  const int c = blockIdx.x, i0 = blockIdx.y * kGT, j0 = blockIdx.z * kGT;
+  const int ti = threadIdx.x % kGT, tj = threadIdx.x / kGT;   // outputs (ti, tj + 8 u)
+  double acc[4] = {0, 0, 0, 0};
+  const int n0 = c * chunk, n1 = min(N, n0 + chunk);
+  for (int nb = n0; nb < n1; nb += kGRows) {
+    for (int e = threadIdx.x; e < kGRows * kGT; e += 256) {
+      const int r = e / kGT, q = e % kGT, n = nb + r;
+      As[r][q] = (n < n1 && i0 + q < k1) ? A[(int64_t)n * lda + i0 + q] : 0.0;
+      Bs[r][q] = (n < n1 && j0 + q < k2) ? B[(int64_t)n * ldb + j0 + q] : 0.0;
+    }
+    __syncthreads();
+    for (int r = 0; r < kGRows; ++r) {
+      const double a = As[r][ti];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += a * Bs[r][tj + 8 * u];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = i0 + ti, j = j0 + tj + 8 * u;
+    if (i < k1 && j < k2) part[((int64_t)c * k1 + i) * k2 + j] = acc[u];
+  }
+}
+
+__global__ void __launch_bounds__(256) gram_reduce_kernel(int k1, int k2, int nchunk, const double* __restrict__ part,
+                                                          double* __restrict__ G, int ldg) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= k1 * k2) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * k1 * k2 + e];
+  G[(e / k2) * ldg + e % k2] = s;
+}
+
+constexpr int kCRows = 16;   // rows per combine workgroup
+
+// Y = beta Z + A T
+__global__ void __launch_bounds__(256) combine_kernel(int N, int k1, int k2, const double* __restrict__ A, int lda,
+                                                      const double* __restrict__ T, int ldt, double beta,
+                                                      const double* Z, int ldz, double* Y, int ldy) {
+  __shared__ double As[kCRows][kMaxSmall];
+  const int r0 = blockIdx.x * kCRows;
+  for (int e = threadIdx.x; e < kCRows * k1; e += 256) {
+    const int r = e / k1, i = e % k1;
+    As[r][i] = r0 + r < N ? A[(int64_t)(r0 + r) * lda + i] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kCRows * k2; e += 256) {
+    const int r = e / k2, j = e % k2, n = r0 + r;
+    if (n >= N) continue;
+    double s = 0.0;
+    for (int i = 0; i < k1; ++i) s += As[r][i] * T[(int64_t)i * ldt + j];
+    if (beta != 0.0) s += beta * Z[(int64_t)n * ldz + j];
+    Y[(int64_t)n * ldy + j] = s;
+  }
+}
+
+// R = HX - SX diag(theta); part[c][j] = sum over chunk rows of R^2
+__global__ void __launch_bounds__(256) residual_kernel(int N, int k, int chunk, const double* __restrict__ HX,
+                                                       const double* __restrict__ SX, int ld,
+                                                       const double* __restrict__ theta, double* __restrict__ R,
+                                                       int ldr, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  const int n0 = c * chunk, n1 = min(N, n0 + chunk);
+  for (int j = 0; j < k; ++j) {
+    double s = 0.0;
+    for (int n = n0 + threadIdx.x; n < n1; n += 256) {
+      const double r = HX[(int64_t)n * ld + j] - SX[(int64_t)n * ld + j] * theta[j];
+      R[(int64_t)n * ldr + j] = r;
+      s += r * r;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)c * k + j] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) norms_kernel(int k, int nchunk, const double* __restrict__ part,
+                                                    double* __restrict__ norms) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= k) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * k + j];
+  norms[j] = sqrt(s);
+}
+
+// SplitMix64 (Steele, Lea and Flood, 2014): a counter-based stream; values
+// uniform in [-1, 1).
+__global__ void __launch_bounds__(256) random_kernel(int N, int k, uint64_t seed, double* __restrict__ X, int ld) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)N * k) return;
+  uint64_t z = seed + (uint64_t)(e + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  X[(e / k) * ld + e % k] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void __launch_bounds__(256) copy_cols_kernel(int N, int k, const double* __restrict__ A, int lda,
+                                                        double* __restrict__ B, int ldb) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)N * k) return;
+  B[(e / k) * ldb + e % k] = A[(e / k) * lda + e % k];
+}
+
+__global__ void __launch_bounds__(256) scale_sym_kernel(int m, const double* __restrict__ G, int ldg,
+                                                        double* __restrict__ Gs, int lds, double* __restrict__ d) {
+  __shared__ double dv[kMaxSmall];
+  for (int i = threadIdx.x; i < m; i += 256) {
+    const double g = G[i * ldg + i];
+    dv[i] = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
+    d[i] = dv[i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * m; e += 256) {
+    const int i = e / m, j = e % m;
+    Gs[i * lds + j] = 0.5 * (G[i * ldg + j] + G[j * ldg + i]) * dv[i] * dv[j];
+  }
+}
+
+__global__ void __launch_bounds__(256) svqb_t_kernel(int m, int kk, int first, const double* __restrict__ U, int ldu,
+                                                     const double* __restrict__ lam, const double* __restrict__ d,
+                                                     double* __restrict__ T, int ldt) {
+  for (int e = threadIdx.x; e < m * kk; e += 256) {
+    const int i = e / kk, j = e % kk;
+    T[i * ldt + j] = d[i] * U[i * ldu + first + j] / sqrt(lam[first + j]);
+  }
+}
+
+__global__ void __launch_bounds__(256) symmetrize_kernel(int m, double* __restrict__ G, int ldg) {
+  for (int e = threadIdx.x; e < m * m; e += 256) {
+    const int i = e / m, j = e % m;
+    if (i < j) {
+      const double s = 0.5 * (G[i * ldg + j] + G[j * ldg + i]);
+      G[i * ldg + j] = s;
+      G[j * ldg + i] = s;
+    }
+  }
+}
+
+// Round-robin pair i of round s among Me indices (Me even).
+__device__ __forceinline__ void rr_pair(int i, int s, int Me, int& p, int& q) {
+  const int m = Me - 1;
+  if (i == 0) { p = 0; q = 1 + s; }
+  else { p = 1 + (s + i) % m; q = 1 + (s - i + m) % m; }
+}
+
+constexpr int kSyevThreads = 1024;
+
+// Real symmetric eigensolver, one workgroup: cyclic Jacobi in the parallel
+// round-robin order on A in LDS (size padded to even Me with a decoupled zero
+// index); thread b owns 2 x 2 blocks (b / H, b % H) of the pairs of a round,
+// rotations computed by the diagonal-block threads; V (global scratch) follows
+// the rotations.  Stops when the off-diagonal Frobenius norm is below
+// 4 Me eps of the norm of A.  Output: eigenvalues ascending in w, eigenvector
+// j in column j of Vout.
+__global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double* __restrict__ Ain, int lda,
+                                                            double* __restrict__ w, double* __restrict__ Vout,
+                                                            int ldv, double* __restrict__ V) {
+  extern __shared__ double A[];   // [Me][Me + 1]
+  __shared__ double cs[kMaxSmall / 2], sn[kMaxSmall / 2], dn[kMaxSmall], red[kSyevThreads / 64];
+  __shared__ int rank[kMaxSmall];
+  __shared__ int done;
+  const int Me = m + (m & 1), H = Me / 2, S = Me + 1;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < Me * Me; e += kSyevThreads) {
+    const int r = e / Me, c = e % Me;
+    A[r * S + c] = (r < m && c < m) ? Ain[r * lda + c] : 0.0;
+    V[r * Me + c] = r == c ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  auto block_sum = [&](double v) -> double {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int q = 0; q < kSyevThreads / 64; ++q) s += red[q];
+    __syncthreads();
+    return s;
+  };
+  double nl = 0.0;
+  for (int e = tid; e < Me * Me; e += kSyevThreads) {
+    const double a = A[(e / Me) * S + e % Me];
+    nl += a * a;
+  }
+  const double nrm2 = block_sum(nl);
+  const double tol = 4.0 * Me * 1.1102230246251565e-16;
+  for (int sw = 0; sw < 60; ++sw) {
+    double ol = 0.0;
+    for (int e = tid; e < Me * Me; e += kSyevThreads) {
+      const int r = e / Me, c = e % Me;
+      if (r != c) ol += A[r * S + c] * A[r * S + c];
+    }
+    const double off = block_sum(ol);
+    if (tid == 0) done = off <= tol * tol * nrm2;
+    __syncthreads();
+    if (done) break;
+    for (int s = 0; s < Me - 1; ++s) {
+      for (int i = tid; i < H; i += kSyevThreads) {
+        int p, q;
+        rr_pair(i, s, Me, p, q);
+        const double app = A[p * S + p], aqq = A[q * S + q], b = A[p * S + q];
+        const double ab = fabs(b);
+        double c = 1.0, sv = 0.0, dp = app, dq = aqq;
+        if (ab > 0.0) {
+          const double tau = (aqq - app) / (2.0 * ab);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sv = (b >= 0.0 ? 1.0 : -1.0) * t * c;
+          dp = app - t * ab;
+          dq = aqq + t * ab;
+        }
+        cs[i] = c;
+        sn[i] = sv;
+        dn[p] = dp;
+        dn[q] = dq;
+      }
+      __syncthreads();
+      for (int b = tid; b < H * H; b += kSyevThreads) {
+        const int bi = b / H, bj = b % H;
+        int pi, qi, pj, qj;
+        rr_pair(bi, s, Me, pi, qi);
+        rr_pair(bj, s, Me, pj, qj);
+        const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
+        double a00, a01, a10, a11;
+        if (bi == bj) {
+          a00 = dn[pi];
+          a11 = dn[qi];
+          a01 = a10 = 0.0;
+        } else {
+          const double b00 = A[pi * S + pj], b01 = A[pi * S + qj], b10 = A[qi * S + pj], b11 = A[qi * S + qj];
+          const double t00 = b00 * cj - b01 * sj, t01 = b00 * sj + b01 * cj;
+          const double t10 = b10 * cj - b11 * sj, t11 = b10 * sj + b11 * cj;
+          a00 = ci * t00 - si * t10;
+          a01 = ci * t01 - si * t11;
+          a10 = si * t00 + ci * t10;
+          a11 = si * t01 + ci * t11;
+        }
+        A[pi * S + pj] = a00;
+        A[pi * S + qj] = a01;
+        A[qi * S + pj] = a10;
+        A[qi * S + qj] = a11;
+        // V <- V J_j on rows {pi, qi}, columns {pj, qj}
+        double vp = V[pi * Me + pj], vq = V[pi * Me + qj];
+        V[pi * Me + pj] = vp * cj - vq * sj;
+        V[pi * Me + qj] = vp * sj + vq * cj;
+        vp = V[qi * Me + pj];
+        vq = V[qi * Me + qj];
+        V[qi * Me + pj] = vp * cj - vq * sj;
+        V[qi * Me + qj] = vp * sj + vq * cj;
+      }
+      __syncthreads();
+    }
+  }
+  // ascending ranks among the m real indices (ties by index)
+  for (int i = tid; i < m; i += kSyevThreads) {
+    const double li = A[i * S + i];
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      const double lj = A[j * S + j];
+      k += (lj < li || (lj == li && j < i)) ? 1 : 0;
+    }
+    rank[i] = k;
+  }
+  __syncthreads();
+  for (int i = tid; i < m; i += kSyevThreads) w[rank[i]] = A[i * S + i];
+  for (int e = tid; e < m * m; e += kSyevThreads) {
+    const int r = e / m, c = e % m;
+    Vout[r * ldv + rank[c]] = V[r * Me + c];
+  }
+}
+
+}  // namespace
+
+hipError_t dense_gram(int N, int k1, int k2, const double* A, int lda, const double* B, int ldb, double* part,
+                      int nchunk, double* G, int ldg, hipStream_t s) {
+  const int chunk = (N + nchunk - 1) / nchunk;
+  const dim3 grid(nchunk, (k1 + kGT - 1) / kGT, (k2 + kGT - 1) / kGT);
+  hipLaunchKernelGGL(gram_part_kernel, grid, dim3(256), 0, s, N, k1, k2, chunk, A, lda, B, ldb, part);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((k1 * k2 + 255) / 256), dim3(256), 0, s, k1, k2, nchunk, part, G,
+                     ldg);
+  return hipGetLastError();
+}
+
+hipError_t dense_combine(int N, int k1, int k2, const double* A, int lda, const double* T, int ldt, double beta,
+                         const double* Z, int ldz, double* Y, int ldy, hipStream_t s) {
+  hipLaunchKernelGGL(combine_kernel, dim3((N + kCRows - 1) / kCRows), dim3(256), 0, s, N, k1, k2, A, lda, T, ldt,
+                     beta, Z, ldz, Y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t dense_syev_w(int m, const double* A, int lda, double* w, double* V, int ldv, double* work,
+                        hipStream_t s) {
+  const int Me = m + (m & 1);
+  const size_t lds = sizeof(double) * (size_t)Me * (Me + 1);
+  (void)hipFuncSetAttribute((const void*)syev_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(kSyevThreads), lds, s, m, A, lda, w, V, ldv, work);
+  return hipGetLastError();
+}
+
+hipError_t dense_residual(int N, int k, const double* HX, const double* SX, int ld, const double* theta, double* R,
+                          int ldr, double* part, int nchunk, double* norms, hipStream_t s) {
+  const int chunk = (N + nchunk - 1) / nchunk;
+  hipLaunchKernelGGL(residual_kernel, dim3(nchunk), dim3(256), 0, s, N, k, chunk, HX, SX, ld, theta, R, ldr, part);
+  hipLaunchKernelGGL(norms_kernel, dim3((k + 255) / 256), dim3(256), 0, s, k, nchunk, part, norms);
+  return hipGetLastError();
+}
+
+hipError_t dense_random(int N, int k, uint64_t seed, double* X, int ld, hipStream_t s) {
+  const int64_t n = (int64_t)N * k;
+  hipLaunchKernelGGL(random_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, k, seed, X, ld);
+  return hipGetLastError();
+}
+
+hipError_t dense_copy_cols(int N, int k, const double* A, int lda, double* B, int ldb, hipStream_t s) {
+  const int64_t n = (int64_t)N * k;
+  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, k, A, lda, B, ldb);
+  return hipGetLastError();
+}
+
+hipError_t dense_scale_sym(int m, const double* G, int ldg, double* Gs, int lds, double* dvec, hipStream_t s) {
+  hipLaunchKernelGGL(scale_sym_kernel, dim3(1), dim3(256), 0, s, m, G, ldg, Gs, lds, dvec);
+  return hipGetLastError();
+}
+
+hipError_t dense_svqb_t(int m, int kk, int first, const double* U, int ldu, const double* lam, const double* dvec,
+                        double* T, int ldt, hipStream_t s) {
+  hipLaunchKernelGGL(svqb_t_kernel, dim3(1), dim3(256), 0, s, m, kk, first, U, ldu, lam, dvec, T, ldt);
+  return hipGetLastError();
+}
+
+hipError_t dense_symmetrize(int m, double* G, int ldg, hipStream_t s) {
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(1), dim3(256), 0, s, m, G, ldg);
+  return hipGetLastError();
+}
+
+}  // namespace lhf

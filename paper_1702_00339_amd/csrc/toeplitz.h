@@ -1,0 +1,99 @@
+// Internal descriptors and launch functions of the Dirichlet-chain operator
+// (perturbed block-Toeplitz model) and of the dense FP64 kernels its block
+// LOBPCG driver uses.  Plain-old-data only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "lhf_internal.h"
+
+namespace lhf {
+
+constexpr int kMaxSmall = 128;   // largest dense eigenproblem of the LOBPCG driver
+
+// The chain, its cell template and its grids.
+struct ToepDev {
+  int32_t L, nc, n, m0, M0, R, L0, P, ndef, margin;
+  double a, h, x0;                   // chain node i (any integer) at x0 + i h; box nodes i = 1..n
+  int32_t nt[2];                     // transverse nodes (dimensions 2, 3), i = 1..nt
+  double ht[2], t0[2];               // transverse spacing and origin
+  int32_t lpow[kMaxM0][3];
+  double alpha[kMaxM0];
+  double cen[kMaxM0][3];
+  double Z[kMaxNuc];
+  double nuc[kMaxNuc][3];
+  double tq[kMaxR];
+  double wq[kMaxR];
+};
+
+// One block of the model: rows = functions of cell k, columns = functions of
+// cell m.  mode 0: pristine generator on the wall-free grid; 1: cross block of
+// the actual basis on the box grid.  dk, dm: defect index of the cells or -1;
+// pair: index of the transverse Grams for the pair of exponent scales;
+// chain nodes [ilo, ihi] (inclusive) carry every non-negligible factor value.
+struct ToepJob {
+  int32_t k, m, mode, pair, ilo, ihi, dk, dm;
+};
+
+// A pair of exponent scales (defect index or -1 for the pristine cell).
+struct ScalePair {
+  int32_t dk, dm;
+};
+
+// One term of a cross correction of block row k: y_k += D x_m with
+// D = H_model(k, m) - T(k, m), built from cross block `blk` (transposed when
+// the block is stored as (m, k)).
+struct CrossEntry {
+  int32_t m, blk, trans, pad;
+};
+
+struct Defect {
+  int32_t cell, pad;
+  double Z, scale;
+};
+
+// assembly (toeplitz.hip)
+hipError_t toep_launch_vrep(const ToepDev* d, double* vrep, int M0R, int nc, hipStream_t s);
+hipError_t toep_launch_transverse(const ToepDev* d, const Defect* defs, const ScalePair* pairs, int npairs,
+                                  int m0, int M0R, double* trans, hipStream_t s);
+// wmax: largest chain window (ihi - ilo + 1) over the jobs
+hipError_t toep_launch_blocks(const ToepDev* d, const Defect* defs, const ToepJob* jobs, int njobs, int m0, int wmax,
+                              const double* vrep, const double* trans, double* outH, double* outS, hipStream_t s);
+hipError_t toep_launch_delta(const ToepDev* d, const int32_t* row_ptr, const int32_t* row_cell, int nrows,
+                             const CrossEntry* ent, const double* genH, const double* genS, const double* crossH,
+                             const double* crossS, double* dH, double* dS, int m0, hipStream_t s);
+hipError_t toep_launch_chat(const ToepDev* d, const double* genH, const double* genS, double2* cH, double2* cS,
+                            int m0, int P, int L0, hipStream_t s);
+hipError_t toep_launch_minv(const double2* V, const double* w, double sigma, double2* minv64, float2* minv32,
+                            int P, int m0, hipStream_t s);
+hipError_t toep_launch_to32(const double2* src, float2* dst, int64_t n, hipStream_t s);
+// y = T x (+ crosses); prec: LHF_PREC_FP64 or LHF_PREC_MIXED.  op2 may be NULL
+// (one operator: yS unused).  cross lists may be empty (nrows = 0).
+hipError_t toep_launch_apply(int prec, int L, int m0, int P, int ncols, const double* x, int ld,
+                             const void* opH, const void* opS, const void* tw, void* xhat, void* yhatH,
+                             void* yhatS, double* yH, double* yS, const int32_t* row_ptr, const int32_t* row_cell,
+                             int nrows, const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s);
+
+// dense FP64 kernels (lobpcg.hip); row-major [N][ld] blocks of vectors
+hipError_t dense_gram(int N, int k1, int k2, const double* A, int lda, const double* B, int ldb, double* part,
+                      int nchunk, double* G, int ldg, hipStream_t s);
+// Y = beta Z + A T   (Z may alias nothing; beta = 0 ignores Z)
+hipError_t dense_combine(int N, int k1, int k2, const double* A, int lda, const double* T, int ldt, double beta,
+                         const double* Z, int ldz, double* Y, int ldy, hipStream_t s);
+// eigenvalues ascending in w, eigenvectors in the columns of V; work: 128^2 doubles
+hipError_t dense_syev_w(int m, const double* A, int lda, double* w, double* V, int ldv, double* work, hipStream_t s);
+hipError_t dense_residual(int N, int k, const double* HX, const double* SX, int ld, const double* theta, double* R,
+                          int ldr, double* part, int nchunk, double* norms, hipStream_t s);
+hipError_t dense_random(int N, int k, uint64_t seed, double* X, int ld, hipStream_t s);
+hipError_t dense_copy_cols(int N, int k, const double* A, int lda, double* B, int ldb, hipStream_t s);
+// Gs = D G D with D = diag(G)^-1/2 (d written to dvec)
+hipError_t dense_scale_sym(int m, const double* G, int ldg, double* Gs, int lds, double* dvec, hipStream_t s);
+// T[:, j] = D U[:, first + j] / sqrt(lam[first + j]), j < kk
+hipError_t dense_svqb_t(int m, int kk, int first, const double* U, int ldu, const double* lam, const double* dvec,
+                        double* T, int ldt, hipStream_t s);
+hipError_t dense_symmetrize(int m, double* G, int ldg, hipStream_t s);
+
+}  // namespace lhf

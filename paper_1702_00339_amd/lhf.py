@@ -55,6 +55,16 @@ class lhf_tuning(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class lhf_box(C.Structure):
+    _fields_ = [("lat", lhf_lattice), ("ndef", C.c_int32), ("def_cells", C.POINTER(C.c_int32)),
+                ("def_Z", C.POINTER(C.c_double)), ("def_scale", C.POINTER(C.c_double))]
+
+
+class lhf_toeplitz_info(C.Structure):
+    _fields_ = [("L", C.c_int32), ("m0", C.c_int32), ("L0", C.c_int32), ("N", C.c_int32), ("P", C.c_int32),
+                ("ncross", C.c_int32), ("ncross_blocks", C.c_int32), ("sigma", C.c_double)]
+
+
 class LhfError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"lhf status {status}: {message}")
@@ -92,6 +102,15 @@ def load(path: str = LIB_PATH):
         "lhf_plan_get_tuning": (i32, [vp, C.POINTER(lhf_tuning)]),
         "lhf_plan_set_tuning": (i32, [vp, C.POINTER(lhf_tuning)]),
         "lhf_plan_autotune": (i32, [vp, C.POINTER(lhf_step_args), vp, C.c_char_p, C.POINTER(lhf_tuning)]),
+        "lhf_toeplitz_create": (i32, [C.POINTER(lhf_box), C.POINTER(vp)]),
+        "lhf_toeplitz_get_info": (i32, [vp, C.POINTER(lhf_toeplitz_info)]),
+        "lhf_toeplitz_blocks": (i32, [vp, vp, vp, vp, vp, vp]),
+        "lhf_toeplitz_matvec_workspace": (sz, [vp, i32]),
+        "lhf_toeplitz_matvec": (i32, [vp, i32, i32, vp, vp, vp, i32, vp, sz, vp]),
+        "lhf_toeplitz_eigs_workspace": (sz, [vp, i32]),
+        "lhf_toeplitz_eigs": (i32, [vp, i32, i32, C.c_double, C.c_uint64, vp, vp, C.POINTER(i32),
+                                    C.POINTER(C.c_double), vp, sz, vp]),
+        "lhf_toeplitz_destroy": (i32, [vp]),
         "lhf_status_string": (C.c_char_p, [i32]),
         "lhf_last_error": (C.c_char_p, []),
         "lhf_version": (i32, []),
@@ -109,7 +128,9 @@ def exported_symbols():
     return ["lhf_plan_create", "lhf_plan_sizes", "lhf_plan_band", "lhf_workspace_size", "lhf_plan_destroy",
             "lhf_assemble_blocks", "lhf_block_fft", "lhf_heev_batched", "lhf_step", "lhf_graph_create",
             "lhf_graph_launch", "lhf_graph_destroy", "lhf_plan_get_tuning", "lhf_plan_set_tuning",
-            "lhf_plan_autotune", "lhf_status_string", "lhf_last_error", "lhf_version"]
+            "lhf_plan_autotune", "lhf_toeplitz_create", "lhf_toeplitz_get_info", "lhf_toeplitz_blocks",
+            "lhf_toeplitz_matvec_workspace", "lhf_toeplitz_matvec", "lhf_toeplitz_eigs_workspace",
+            "lhf_toeplitz_eigs", "lhf_toeplitz_destroy", "lhf_status_string", "lhf_last_error", "lhf_version"]
 
 
 def _check(st):
@@ -261,3 +282,74 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def box_from_instance(inst):
+    """Fill an lhf_box from a synth Instance (Dirichlet chain with defects);
+    returns (struct, keepalive)."""
+    lat, keep = lattice_from_instance(inst)
+    box = lhf_box()
+    box.lat = lat
+    cells = np.ascontiguousarray(inst.def_cells, dtype=np.int32)
+    dz = np.ascontiguousarray(inst.def_Z, dtype=np.float64)
+    ds = np.ascontiguousarray(inst.def_scale, dtype=np.float64)
+    keep = list(keep) + [cells, dz, ds]
+    box.ndef = len(cells)
+    box.def_cells = cells.ctypes.data_as(C.POINTER(C.c_int32))
+    box.def_Z = dz.ctypes.data_as(C.POINTER(C.c_double))
+    box.def_scale = ds.ctypes.data_as(C.POINTER(C.c_double))
+    return box, keep
+
+
+class Toeplitz:
+    """The Dirichlet-chain operator (lhf_toeplitz_create / _destroy)."""
+
+    def __init__(self, inst):
+        self.inst = inst
+        box, self._keep = box_from_instance(inst)
+        h = C.c_void_p()
+        _check(load().lhf_toeplitz_create(C.byref(box), C.byref(h)))
+        self.handle = h
+        info = lhf_toeplitz_info()
+        _check(load().lhf_toeplitz_get_info(self.handle, C.byref(info)))
+        self.info = info
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().lhf_toeplitz_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def lhf_toeplitz_blocks(self, gen_H=None, gen_S=None, cross_km=None, cross_H=None, cross_S=None):
+        _check(load().lhf_toeplitz_blocks(self.handle, _ptr(gen_H), _ptr(gen_S), _ptr(cross_km), _ptr(cross_H),
+                                          _ptr(cross_S)))
+
+    def matvec_workspace(self, ncols, device="cuda"):
+        import torch
+        n = int(load().lhf_toeplitz_matvec_workspace(self.handle, ncols))
+        return torch.empty(max(1, n), dtype=torch.uint8, device=device)
+
+    def lhf_toeplitz_matvec(self, prec, x, y_H, y_S, ws):
+        ncols = x.shape[1]
+        _check(load().lhf_toeplitz_matvec(self.handle, prec, ncols, _ptr(x), _ptr(y_H), _ptr(y_S), x.stride(0),
+                                          _ptr(ws), ws.numel(), _stream()))
+
+    def eigs_workspace(self, nev, device="cuda"):
+        import torch
+        n = int(load().lhf_toeplitz_eigs_workspace(self.handle, nev))
+        if n == 0:
+            raise LhfError(LHF_ERR_INVALID, "unsupported nev")
+        return torch.empty(n, dtype=torch.uint8, device=device)
+
+    def lhf_toeplitz_eigs(self, nev, w, V=None, maxit=200, tol=1e-6, seed=1, ws=None):
+        ws = ws if ws is not None else self.eigs_workspace(nev, w.device)
+        it = C.c_int32()
+        res = C.c_double()
+        _check(load().lhf_toeplitz_eigs(self.handle, nev, maxit, tol, seed, _ptr(w), _ptr(V), C.byref(it),
+                                        C.byref(res), _ptr(ws), ws.numel(), _stream()))
+        return it.value, res.value

@@ -124,3 +124,45 @@ def test_step_graph_and_tuning_reject_null(lib):
     assert lib.lhf_plan_get_tuning(None, C.byref(t)) == lhf.LHF_ERR_INVALID
     assert lib.lhf_plan_set_tuning(None, C.byref(t)) == lhf.LHF_ERR_INVALID
     assert lib.lhf_plan_autotune(None, C.byref(args), None, None, None) == lhf.LHF_ERR_INVALID
+
+
+def _box(lib, inst, mutate=None):
+    box, keep = lhf.box_from_instance(inst)
+    if mutate:
+        mutate(box)
+    h = C.c_void_p()
+    st = lib.lhf_toeplitz_create(C.byref(box), C.byref(h))
+    return st, h
+
+
+def _chain(**kw):
+    from synth import make_instance
+    args = dict(name="box", L=(12, 1, 1), n=(96, 12, 12), bc="dirichlet", pad=(5.0 / 16, 4.0, 4.0), n_s=2,
+                exp_range=(0.8, 2.5), Z=2, R=8, seed=3)
+    args.update(kw)
+    return make_instance(**args)
+
+
+def test_toeplitz_create_rejects_bad_chains(lib):
+    st, h = _box(lib, _chain(bc="periodic"))
+    assert st == lhf.LHF_ERR_UNSUPPORTED and h.value is None
+    st, _ = _box(lib, _chain(pad=(1.0, 4.0, 4.0)))          # nodes not cell aligned
+    assert st == lhf.LHF_ERR_UNSUPPORTED
+    assert b"cell aligned" in lib.lhf_last_error()
+    st, _ = _box(lib, _chain(L=(12, 2, 1), n=(96, 24, 12)))
+    assert st == lhf.LHF_ERR_UNSUPPORTED
+    inst = _chain()
+    inst.def_cells = np.asarray([3, 3]); inst.def_Z = np.asarray([1.0, 2.0]); inst.def_scale = np.asarray([1.0, 1.0])
+    st, _ = _box(lib, inst)
+    assert st == lhf.LHF_ERR_INVALID and b"distinct" in lib.lhf_last_error()
+    inst.def_cells = np.asarray([12]); inst.def_Z = np.asarray([1.0]); inst.def_scale = np.asarray([1.0])
+    assert _box(lib, inst)[0] == lhf.LHF_ERR_INVALID
+    inst.def_cells = np.asarray([2]); inst.def_Z = np.asarray([1.0]); inst.def_scale = np.asarray([0.0])
+    assert _box(lib, inst)[0] == lhf.LHF_ERR_INVALID
+    h = C.c_void_p()
+    assert lib.lhf_toeplitz_create(None, C.byref(h)) == lhf.LHF_ERR_INVALID
+    info = lhf.lhf_toeplitz_info()
+    assert lib.lhf_toeplitz_get_info(None, C.byref(info)) == lhf.LHF_ERR_INVALID
+    assert lib.lhf_toeplitz_matvec_workspace(None, 4) == 0
+    assert lib.lhf_toeplitz_eigs_workspace(None, 4) == 0
+    assert lib.lhf_toeplitz_destroy(None) == lhf.LHF_OK
