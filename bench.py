@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the Dirichlet-chain (c5) measurement")
     return ap.parse_args()
 
 
@@ -116,6 +117,48 @@ def heev_flops(insts, prec, R):
     return total
 
 
+def bench_c5(torch, np, lhf, steps):
+    """Dirichlet 512-cell chain with 26 defect cells: time to the 32 lowest
+    eigenpairs (operator assembly, then block LOBPCG), their error against the
+    stored oracle values, and the event-timed matvec of a full LOBPCG basis
+    (120 vectors, H and S) with its algorithmic HBM bytes: x read once, y_H and
+    y_S written once (FP64), the two per-frequency operators and the cross
+    corrections read once."""
+    from synth import make_config
+    inst = make_config("c5")
+    gold = np.loadtxt(os.path.join(ROOT, "tests", "golden", "c5_lowest32.txt"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = lhf.Toeplitz(inst)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    w = torch.empty(32, dtype=torch.float64, device="cuda")
+    ws = op.eigs_workspace(32)
+    op.lhf_toeplitz_eigs(32, w, None, maxit=150, tol=1e-5, seed=1, ws=ws)     # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, res = op.lhf_toeplitz_eigs(32, w, None, maxit=150, tol=1e-5, seed=1, ws=ws)
+    torch.cuda.synchronize()
+    t_eigs = time.perf_counter() - t0
+    err = float(np.abs(w.cpu().numpy() - gold).max())
+    info = op.info
+    N, m0, P = info.N, info.m0, info.P
+    ncols = 120
+    x = torch.randn((N, ncols), dtype=torch.float64, device="cuda")
+    yH, yS = torch.empty_like(x), torch.empty_like(x)
+    mws = op.matvec_workspace(ncols)
+    mv = {}
+    nent = 2 * info.ncross_blocks - info.ncross   # correction entries: both orientations, diagonal once
+    for name, prec, csz in (("fp32", lhf.LHF_PREC_MIXED, 8), ("fp64", lhf.LHF_PREC_FP64, 16)):
+        ms = event_ms(lambda: op.lhf_toeplitz_matvec(prec, x, yH, yS, mws), steps, torch)
+        nbytes = 3 * N * ncols * 8 + 2 * P * m0 * m0 * csz + 2 * nent * m0 * m0 * 8
+        mv[name] = {"avg_launch_ms": ms, "bytes": nbytes, "GB/s": nbytes / (ms * 1e-3) / 1e9}
+    return {"workload": "c5: Dirichlet 512x1x1 chain, m0=16, n=4096x256x256, R=30, 26 defect cells",
+            "metric": "time to the 32 lowest eigenpairs", "create_ms": t_create * 1e3, "eigs_ms": t_eigs * 1e3,
+            "unit": "ms", "lobpcg_iterations": it, "residual": res, "max_abs_eig_err_ha": err,
+            "L0": info.L0, "cross_cells": info.ncross, "embedding": P, "matvec_120_vectors": mv}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -182,6 +225,8 @@ def main():
     flops = heev_flops(insts, pm.prec, R)
     tflops = flops / (ms_heev * 1e-3) / 1e12
 
+    c5 = None if args.no_c5 else bench_c5(torch, np, lhf, args.steps)
+
     cpu = None
     if not args.no_cpu_baseline:
         runs = [t_oracle_first]
@@ -225,6 +270,7 @@ def main():
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "bytes_per_launch": bytes_alg, "avg_launch_ms": ms_dft},
         "tuning": tuning,
+        "dirichlet_c5": c5,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
