@@ -75,13 +75,15 @@ def event_ms(fn, steps, torch):
     return sum(a.elapsed_time(b) for a, b in ev) / steps
 
 
-def dft_bytes(pipe, insts):
-    """Algorithmic HBM bytes of one lhf_block_fft call: every Fourier block
-    written once (H and S, complex) plus every band generator read once (H and
-    S, real)."""
+def dft_bytes(pipe, insts, dual=False):
+    """Algorithmic HBM bytes of one block-DFT call: every Fourier block written
+    once (H and S, complex; complex128 and complex64 for the dual transform of
+    the mixed path) plus every band generator read once (H and S, real)."""
     from paper_1702_00339_amd import lhf
     cbytes = 16 if pipe.prec == lhf.LHF_PREC_FP64 else 8
     rbytes = cbytes // 2
+    if dual:
+        cbytes, rbytes = 16 + 8, 8
     total = 0
     for i, inst in enumerate(insts):
         m2 = inst.m0 * inst.m0
@@ -179,7 +181,15 @@ def main():
     else:
         insts = [make_config(args.config)]
         checked = insts
-    pipes = {"mixed": Pipeline(insts, prec=lhf.LHF_PREC_MIXED), "fp64": Pipeline(insts, prec=lhf.LHF_PREC_FP64)}
+    # mixed: FP64 MFMA Grams (which the FP64 refinement needs anyway), FP64
+    # stacks, one FP64 block DFT writing complex128 blocks and their
+    # complex64 copies; mixed_bf16x3: FP32 stacks from separate bf16 hi+lo
+    # split Grams and a complex64 DFT, reported beside it
+    pipes = {"mixed": Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=lhf.LHF_GRAM_FP64),
+             "fp64": Pipeline(insts, prec=lhf.LHF_PREC_FP64),
+             "mixed_bf16x3": Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=lhf.LHF_GRAM_BF16X3,
+                                      refine_src="band" if all(i.L[1] == 1 and i.L[2] == 1 for i in insts)
+                                      else "bar64")}
     tuning = {name: p.autotune().as_dict() for name, p in pipes.items()}
     graphs = {name: p.capture() for name, p in pipes.items()}
     for g in graphs.values():
@@ -212,9 +222,9 @@ def main():
 
     # rooflines, event-timed on the stream the kernels run on
     pm = pipes["mixed"]
-    ms_dft = event_ms(lambda: pm.plan.lhf_block_fft(pm.prec, pm.H_gen, pm.S_gen, pm.H_bar, pm.S_bar, pm.ws),
-                      args.steps, torch)
-    bytes_alg = dft_bytes(pm, insts)
+    ms_dft = event_ms(lambda: pm.plan.lhf_block_fft_dual(pm.H_gen64, pm.S_gen64, pm.H_bar64, pm.S_bar64, pm.H_bar,
+                                                          pm.S_bar, pm.ws), args.steps, torch)
+    bytes_alg = dft_bytes(pm, insts, dual=True)
     achieved = bytes_alg / (ms_dft * 1e-3) / 1e9
     flags = lhf.LHF_HEEV_REFINE_FP64
     ms_heev = event_ms(lambda: pm.plan.lhf_heev_batched(flags, pm.H_bar, pm.S_bar, pm.w, pm.info, pm.ws,
@@ -256,16 +266,19 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "lattices": len(insts),
                    "k_point_blocks": nblk, "m0": m0s if len(m0s) > 1 else m0s[0],
-                   "path": "mixed: bf16 hi+lo MFMA Grams, complex64 DFT, FP32 Jacobi, FP64 Rayleigh-Ritz "
-                           "refinement; one hipGraph replay per step"},
+                   "path": "mixed: FP64 MFMA Grams, FP64 stacks, one block DFT writing complex128 blocks "
+                           "and their complex64 copies, FP32 Jacobi on complex64, FP64 Rayleigh-Ritz "
+                           "refinement on complex128; one hipGraph replay per step"},
         "fp64_path": {"value": nblk / sec["fp64"], "ms_per_step": sec["fp64"] * 1e3, "dtype": "f64"},
+        "mixed_bf16x3_path": {"value": nblk / sec["mixed_bf16x3"], "ms_per_step": sec["mixed_bf16x3"] * 1e3,
+                              "max_abs_eig_err_ha": errs["mixed_bf16x3"][0], "info_ok": errs["mixed_bf16x3"][2]},
         "accuracy": {"lattices_checked": len(checked),
                      "mixed_max_abs_eig_err_ha": errs["mixed"][0], "mixed_info_ok": errs["mixed"][2],
                      "fp64_max_rel_eig_err": errs["fp64"][1], "fp64_info_ok": errs["fp64"][2]},
         "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: FP32 Jacobi + FP64 refinement)",
                      "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s", "frac": tflops / 157.3,
                      "traffic": None, "flops_per_launch": flops, "avg_launch_ms": ms_heev},
-        "roofline_dft": {"bound": "hbm", "kernel": "block DFT (lhf_block_fft, complex64)",
+        "roofline_dft": {"bound": "hbm", "kernel": "block DFT (lhf_block_fft_dual: complex128 + complex64)",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                          "bytes_per_launch": bytes_alg, "avg_launch_ms": ms_dft},

@@ -173,6 +173,9 @@ int32_t lhf_plan_destroy(lhf_plan_t plan);
  *   FP64 generator stack of a mixed pipeline (see d_H_gen64).
  * d_H_gen64, d_S_gen64: device, optional FP64 stacks written in mixed mode
  *   (the FP64 generator band used by refinement); must be NULL in FP64 mode.
+ *   A mixed plan given the FP64 stacks may pass d_H_gen = d_S_gen = NULL:
+ *   then only the FP64 stacks are written (lhf_block_fft_dual makes the
+ *   complex64 blocks from them).
  * Errors: LHF_ERR_INVALID (NULL outputs, bad plan), LHF_ERR_WORKSPACE. */
 int32_t lhf_assemble_blocks(lhf_plan_t plan, void* d_H_gen, void* d_S_gen, double* d_grams64,
                             double* d_H_gen64, double* d_S_gen64,
@@ -190,6 +193,15 @@ int32_t lhf_assemble_blocks(lhf_plan_t plan, void* d_H_gen, void* d_S_gen, doubl
 int32_t lhf_block_fft(lhf_plan_t plan, int32_t prec, const void* d_H_gen, const void* d_S_gen,
                       void* d_H_bar, void* d_S_bar, void* d_ws, size_t ws_bytes,
                       lhf_stream_t stream);
+
+/* The FP64 block DFT of the mixed pipeline: reads the FP64 stacks, writes the
+ * complex128 blocks (d_H_bar64, d_S_bar64, for refinement) and their
+ * complex64 roundings (d_H_bar32, d_S_bar32, for the FP32 solve) in one pass.
+ * Same transform and layouts as lhf_block_fft; all six buffers required.
+ * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE. */
+int32_t lhf_block_fft_dual(lhf_plan_t plan, const double* d_H_gen64, const double* d_S_gen64,
+                           void* d_H_bar64, void* d_S_bar64, void* d_H_bar32, void* d_S_bar32,
+                           void* d_ws, size_t ws_bytes, lhf_stream_t stream);
 
 /* ---------------------------------------------------------------- eigensolve
  * For every block j: Hbar_j u = lambda Sbar_j u (eq. HF-FSpace-Block), by
@@ -305,7 +317,9 @@ int32_t lhf_toeplitz_destroy(lhf_toeplitz_t tp);
  * LHF_HEEV_REFINE_FP64 also need H_gen64 and S_gen64 (written by the
  * assembly); when H_bar64 and S_bar64 are given as well, the step fills them
  * with a complex128 block DFT and refinement reads them, otherwise
- * refinement regenerates each block from the FP64 band.  grams64 may be
+ * refinement regenerates each block from the FP64 band.  With H_bar64 given,
+ * H_gen and S_gen may be NULL: the step then skips the FP32 stacks and makes
+ * H_bar and S_bar with lhf_block_fft_dual.  grams64 may be
  * NULL (the workspace holds the Grams), V is needed with LHF_HEEV_VECTORS. */
 typedef struct {
   void* H_gen;

@@ -30,8 +30,12 @@ extern "C" {
 int32_t lhf_assemble_blocks(lhf_plan_t p, void* H_gen, void* S_gen, double* grams64, double* H_gen64,
                             double* S_gen64, void* ws, size_t ws_bytes, lhf_stream_t stream) {
   if (!p) { set_error("NULL plan"); return LHF_ERR_INVALID; }
-  if (!H_gen || !S_gen) { set_error("H_gen and S_gen are required"); return LHF_ERR_INVALID; }
+  if ((H_gen == nullptr) != (S_gen == nullptr)) { set_error("give both stacks H_gen and S_gen or neither"); return LHF_ERR_INVALID; }
   if ((H_gen64 == nullptr) != (S_gen64 == nullptr)) { set_error("give both FP64 stacks or neither"); return LHF_ERR_INVALID; }
+  if (!H_gen && !(p->prec == LHF_PREC_MIXED && H_gen64)) {
+    set_error("H_gen and S_gen are required (a mixed plan may omit them when it writes the FP64 stacks)");
+    return LHF_ERR_INVALID;
+  }
   if (p->prec == LHF_PREC_FP64 && H_gen64) { set_error("FP64 plans write their FP64 stacks to H_gen/S_gen"); return LHF_ERR_INVALID; }
   int32_t st = check_ws(p, ws, ws_bytes);
   if (st != LHF_OK) return st;
@@ -39,7 +43,8 @@ int32_t lhf_assemble_blocks(lhf_plan_t p, void* H_gen, void* S_gen, double* gram
   Ws w = ws_view(p, ws);
   double* g64 = grams64 ? grams64 : w.grams64;
   const bool mixed = p->prec == LHF_PREC_MIXED;
-  const bool split = mixed && p->gram != LHF_GRAM_FP64;
+  const bool want32 = !mixed || H_gen != nullptr;   // mixed plans: FP32 stacks only when asked for
+  const bool split = mixed && p->gram != LHF_GRAM_FP64 && want32;
   const bool need64 = !mixed || !split || grams64 || H_gen64;
   hipError_t e;
   e = launch_factors(p, w.fac, s);
@@ -55,7 +60,8 @@ int32_t lhf_assemble_blocks(lhf_plan_t p, void* H_gen, void* S_gen, double* gram
   if (!mixed)
     e = launch_combine(p, g64, nullptr, (double*)H_gen, (double*)S_gen, nullptr, nullptr, s);
   else
-    e = launch_combine(p, g64, split ? w.grams32 : nullptr, H_gen64, S_gen64, (float*)H_gen, (float*)S_gen, s);
+    e = launch_combine(p, g64, split ? w.grams32 : nullptr, H_gen64, S_gen64, want32 ? (float*)H_gen : nullptr,
+                       want32 ? (float*)S_gen : nullptr, s);
   return hip_status(e, "combine");
 }
 
@@ -68,7 +74,23 @@ int32_t lhf_block_fft(lhf_plan_t p, int32_t prec, const void* H_gen, const void*
   if (st != LHF_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = ws_view(p, ws);
-  return hip_status(launch_block_dft(p, prec, H_gen, S_gen, H_bar, S_bar, w.dft, s), "block dft");
+  return hip_status(launch_block_dft(p, prec, H_gen, S_gen, H_bar, S_bar, w.dft, nullptr, nullptr, s), "block dft");
+}
+
+int32_t lhf_block_fft_dual(lhf_plan_t p, const double* H_gen64, const double* S_gen64, void* H_bar64,
+                           void* S_bar64, void* H_bar32, void* S_bar32, void* ws, size_t ws_bytes,
+                           lhf_stream_t stream) {
+  if (!p) { set_error("NULL plan"); return LHF_ERR_INVALID; }
+  if (!H_gen64 || !S_gen64 || !H_bar64 || !S_bar64 || !H_bar32 || !S_bar32) {
+    set_error("all six stacks are required");
+    return LHF_ERR_INVALID;
+  }
+  int32_t st = check_ws(p, ws, ws_bytes);
+  if (st != LHF_OK) return st;
+  Ws w = ws_view(p, ws);
+  return hip_status(launch_block_dft(p, LHF_PREC_FP64, H_gen64, S_gen64, H_bar64, S_bar64, w.dft, (float2*)H_bar32,
+                                     (float2*)S_bar32, static_cast<hipStream_t>(stream)),
+                    "block dft");
 }
 
 int32_t lhf_heev_batched(lhf_plan_t p, uint32_t flags, const void* H_bar, const void* S_bar,

@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(256) dft_pass_kernel(const LatDev* __restrict_
                                                        const R* __restrict__ genH, const R* __restrict__ genS,
                                                        typename Cx<R>::T* __restrict__ tmp,
                                                        typename Cx<R>::T* __restrict__ barH,
-                                                       typename Cx<R>::T* __restrict__ barS) {
+                                                       typename Cx<R>::T* __restrict__ barS,
+                                                       float2* __restrict__ b32H, float2* __restrict__ b32S) {
   typedef typename Cx<R>::T C;
   const int64_t wg0 = (int64_t)blockIdx.x * 256;
   const DftTask T = tasks[find_task(tasks, ntasks, wg0)];
@@ -126,6 +127,8 @@ __global__ void __launch_bounds__(256) dft_pass_kernel(const LatDev* __restrict_
   const C* Tw = lds_tw ? sT : tw + D.tw_off;
   C* Y = T.out_final ? (isH ? barH : barS) + L.gen_off : tmp + T.out_off + (isH ? 0 : T.out_half);
   C* dst = Y + (int64_t)o * Ld * I + i;
+  // complex64 copy of final blocks (the FP64 transform of the mixed pipeline)
+  float2* d32 = (T.out_final && b32H) ? (isH ? b32H : b32S) + L.gen_off + (int64_t)o * Ld * I + i : nullptr;
   for (int j = j0; j < j1; ++j) {
     R re = 0, im = 0;
 #pragma unroll
@@ -142,6 +145,7 @@ __global__ void __launch_bounds__(256) dft_pass_kernel(const LatDev* __restrict_
     r.x = re;
     r.y = im;
     dst[(int64_t)j * I] = r;
+    if (d32) d32[(int64_t)j * I] = make_float2((float)re, (float)im);
   }
 }
 
@@ -153,7 +157,8 @@ __global__ void __launch_bounds__(256) dft_wide_kernel(const LatDev* __restrict_
                                                        const R* __restrict__ genH, const R* __restrict__ genS,
                                                        typename Cx<R>::T* __restrict__ tmp,
                                                        typename Cx<R>::T* __restrict__ barH,
-                                                       typename Cx<R>::T* __restrict__ barS) {
+                                                       typename Cx<R>::T* __restrict__ barS,
+                                                       float2* __restrict__ b32H, float2* __restrict__ b32S) {
   typedef typename Cx<R>::T C;
   const int64_t wg0 = (int64_t)blockIdx.x * 256;
   const DftTask T = tasks[find_task(tasks, ntasks, wg0)];
@@ -202,6 +207,145 @@ __global__ void __launch_bounds__(256) dft_wide_kernel(const LatDev* __restrict_
   r.x = re;
   r.y = im;
   Y[tid] = r;
+  if (T.out_final && b32H) ((isH ? b32H : b32S) + L.gen_off)[tid] = make_float2((float)re, (float)im);
+}
+
+constexpr int kFusedEC = 8;    // block entries per fused workgroup
+constexpr int kFusedJ2 = 16;   // j2 values per fused workgroup
+
+__device__ __forceinline__ int find_fused(const FusedTask* __restrict__ t, int n, int64_t wg) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t[mid].wg_base <= wg) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Fused transform of all three dimensions of a lattice (band-pruned):
+//   stage 1: T1[s1][s2][e] = sum_s3 w3^(j3 k3) A[k1][k2][k3][e]      (fixed j3)
+//   stage 2: T2[s1][j2][e] = sum_s2 w2^(j2 k2) T1[s1][s2][e]          (a chunk of j2)
+//   stage 3: Y[j1][j2][j3][e] = sum_s1 w1^(j1 k1) T2[s1][j2][e]      (every j1)
+// The intermediates stay in LDS; every Fourier block entry is written once,
+// in segments of EC consecutive entries.  In stage 3 a thread owns one
+// (j2, e) column with its B1 inputs in registers and walks j1 with
+// incrementally updated twiddle indices.
+template <typename R, int BM>
+__global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict__ lats,
+                                                        const FusedTask* __restrict__ tasks, int ntasks,
+                                                        const typename Cx<R>::T* __restrict__ tw,
+                                                        const R* __restrict__ genH, const R* __restrict__ genS,
+                                                        typename Cx<R>::T* __restrict__ barH,
+                                                        typename Cx<R>::T* __restrict__ barS,
+                                                        float2* __restrict__ b32H, float2* __restrict__ b32S) {
+  typedef typename Cx<R>::T C;
+  extern __shared__ char lds_raw[];
+  const int64_t wg = blockIdx.x;
+  const FusedTask T = tasks[find_fused(tasks, ntasks, wg)];
+  const LatDev& L = lats[T.li];
+  const DimDev& D0 = L.dim[0];
+  const DimDev& D1 = L.dim[1];
+  const DimDev& D2 = L.dim[2];
+  const int L1 = L.L[0], L2 = L.L[1], L3 = L.L[2];
+  const int B1 = nslot(D0), B2 = nslot(D1), B3 = nslot(D2);
+  const int E = L.m0 * L.m0, EC = T.EC, J2C = T.J2C;
+  int64_t loc = wg - T.wg_base;
+  const int eci = (int)(loc % T.nec);
+  loc /= T.nec;
+  const int j2c = (int)(loc % T.nj2c);
+  const int j3 = (int)(loc / T.nj2c);
+  const int e0 = eci * EC, ecn = min(EC, E - e0);
+  const int j2lo = j2c * J2C, j2n = min(J2C, L2 - j2lo);
+  C* T1 = reinterpret_cast<C*>(lds_raw);   // [B1][B2][EC]
+  C* T2 = T1 + B1 * B2 * EC;               // [B1][J2C][EC]
+  C* tw1 = T2 + B1 * J2C * EC;             // [L1]
+  C* tw2 = tw1 + L1;                       // [J2C][B2]
+  C* tw3 = tw2 + J2C * B2;                 // [B3]
+  const int tid = threadIdx.x;
+  for (int q = tid; q < L1; q += 256) tw1[q] = tw[D0.tw_off + q];
+  for (int q = tid; q < j2n * B2; q += 256) {
+    const int jj = q / B2, s2 = q % B2;
+    const int k2 = slot_cell(D1, s2);
+    tw2[jj * B2 + s2] = tw[D1.tw_off + (int)(((int64_t)(j2lo + jj) * k2) % L2)];
+  }
+  for (int q = tid; q < B3; q += 256) tw3[q] = tw[D2.tw_off + (int)(((int64_t)j3 * slot_cell(D2, q)) % L3)];
+  __syncthreads();
+  const R* X = (blockIdx.y == 0 ? genH : genS) + L.gen_off;
+  // stage 1
+  for (int it = tid; it < B1 * B2 * EC; it += 256) {
+    const int ec = it % EC, s12 = it / EC, s2 = s12 % B2, s1 = s12 / B2;
+    R re = 0, im = 0;
+    if (ec < ecn) {
+      const int k1 = slot_cell(D0, s1), k2 = slot_cell(D1, s2);
+      const R* xp = X + ((int64_t)(k1 * L2 + k2) * L3) * E + e0 + ec;
+      for (int s3 = 0; s3 < B3; ++s3) {
+        const R x = xp[(int64_t)slot_cell(D2, s3) * E];
+        const C w = tw3[s3];
+        re += w.x * x;
+        im += w.y * x;
+      }
+    }
+    C v;
+    v.x = re;
+    v.y = im;
+    T1[it] = v;
+  }
+  __syncthreads();
+  // stage 2
+  for (int it = tid; it < B1 * j2n * EC; it += 256) {
+    const int ec = it % EC, r = it / EC, jj = r % j2n, s1 = r / j2n;
+    R re = 0, im = 0;
+    for (int s2 = 0; s2 < B2; ++s2) {
+      const C w = tw2[jj * B2 + s2], x = T1[(s1 * B2 + s2) * EC + ec];
+      re += w.x * x.x - w.y * x.y;
+      im += w.x * x.y + w.y * x.x;
+    }
+    C v;
+    v.x = re;
+    v.y = im;
+    T2[(s1 * J2C + jj) * EC + ec] = v;
+  }
+  __syncthreads();
+  // stage 3
+  const int ncol = J2C * EC, nrep = 256 / ncol;
+  const int col = tid % ncol, rep = tid / ncol;
+  const int jj = col / EC, ec = col % EC;
+  if (rep >= nrep || jj >= j2n || ec >= ecn) return;
+  R xr[BM], xi[BM];
+  int idx[BM], stp[BM];
+#pragma unroll
+  for (int s1 = 0; s1 < BM; ++s1) {
+    if (s1 < B1) {
+      const C x = T2[(s1 * J2C + jj) * EC + ec];
+      xr[s1] = x.x;
+      xi[s1] = x.y;
+      const int k1 = slot_cell(D0, s1);
+      idx[s1] = (int)(((int64_t)rep * k1) % L1);
+      stp[s1] = (int)(((int64_t)nrep * k1) % L1);
+    }
+  }
+  const int64_t yoff = L.gen_off + ((int64_t)(j2lo + jj) * L3 + j3) * E + e0 + ec;
+  C* Y = (blockIdx.y == 0 ? barH : barS) + yoff;
+  float2* Y32 = b32H ? (blockIdx.y == 0 ? b32H : b32S) + yoff : nullptr;
+  const int64_t jstride = (int64_t)L2 * L3 * E;
+  for (int j1 = rep; j1 < L1; j1 += nrep) {
+    R re = 0, im = 0;
+#pragma unroll
+    for (int s1 = 0; s1 < BM; ++s1) {
+      if (s1 < B1) {
+        const C w = tw1[idx[s1]];
+        re += w.x * xr[s1] - w.y * xi[s1];
+        im += w.x * xi[s1] + w.y * xr[s1];
+        idx[s1] += stp[s1];
+        if (idx[s1] >= L1) idx[s1] -= L1;
+      }
+    }
+    C v;
+    v.x = re;
+    v.y = im;
+    Y[(int64_t)j1 * jstride] = v;
+    if (Y32) Y32[(int64_t)j1 * jstride] = make_float2((float)re, (float)im);
+  }
 }
 
 int band_class(int B) { return B <= 4 ? 0 : B <= 8 ? 1 : B <= 16 ? 2 : B <= 32 ? 3 : 4; }
@@ -209,8 +353,21 @@ int band_class(int B) { return B <= 4 ? 0 : B <= 8 ? 1 : B <= 16 ? 2 : B <= 32 ?
 template <typename R>
 hipError_t dft_launch_all(const lhf_plan_s* p, const R* gH, const R* gS, typename Cx<R>::T* bH,
                           typename Cx<R>::T* bS, typename Cx<R>::T* tmp, const typename Cx<R>::T* tw,
-                          hipStream_t s) {
+                          float2* b32H, float2* b32S, hipStream_t s) {
   typedef typename Cx<R>::T C;
+  if (p->n_fused > 0) {
+    const dim3 grid((unsigned)p->fused_wgs, 2);
+    const size_t shb = (size_t)p->fused_lds / 16 * sizeof(C);
+    if (p->fused_bmax <= 8)
+      hipLaunchKernelGGL((dft_fused_kernel<R, 8>), grid, dim3(256), shb, s, p->d_lat, p->d_fused, p->n_fused, tw, gH,
+                         gS, bH, bS, b32H, b32S);
+    else if (p->fused_bmax <= 16)
+      hipLaunchKernelGGL((dft_fused_kernel<R, 16>), grid, dim3(256), shb, s, p->d_lat, p->d_fused, p->n_fused, tw, gH,
+                         gS, bH, bS, b32H, b32S);
+    else
+      hipLaunchKernelGGL((dft_fused_kernel<R, 32>), grid, dim3(256), shb, s, p->d_lat, p->d_fused, p->n_fused, tw, gH,
+                         gS, bH, bS, b32H, b32S);
+  }
   for (const DftLaunch& l : p->dft_launches) {
     const dim3 grid((unsigned)(l.threads / 256), 2);
     const DftTask* tk = p->d_dft_tasks + l.t0;
@@ -219,10 +376,10 @@ hipError_t dft_launch_all(const lhf_plan_s* p, const R* gH, const R* gS, typenam
 #define LHF_PASS(BM)                                                                                      \
   if (first)                                                                                              \
     hipLaunchKernelGGL((dft_pass_kernel<R, BM, true>), grid, dim3(256), shb, s, p->d_lat, tk, l.nt, tw,   \
-                       gH, gS, tmp, bH, bS);                                                              \
+                       gH, gS, tmp, bH, bS, b32H, b32S);                                                              \
   else                                                                                                    \
     hipLaunchKernelGGL((dft_pass_kernel<R, BM, false>), grid, dim3(256), shb, s, p->d_lat, tk, l.nt, tw,  \
-                       gH, gS, tmp, bH, bS);
+                       gH, gS, tmp, bH, bS, b32H, b32S);
     switch (l.cls) {
       case 0: LHF_PASS(4) break;
       case 1: LHF_PASS(8) break;
@@ -231,10 +388,10 @@ hipError_t dft_launch_all(const lhf_plan_s* p, const R* gH, const R* gS, typenam
       default:
         if (first)
           hipLaunchKernelGGL((dft_wide_kernel<R, true>), grid, dim3(256), 0, s, p->d_lat, tk, l.nt, tw, gH, gS,
-                             tmp, bH, bS);
+                             tmp, bH, bS, b32H, b32S);
         else
           hipLaunchKernelGGL((dft_wide_kernel<R, false>), grid, dim3(256), 0, s, p->d_lat, tk, l.nt, tw, gH, gS,
-                             tmp, bH, bS);
+                             tmp, bH, bS, b32H, b32S);
     }
 #undef LHF_PASS
   }
@@ -243,15 +400,54 @@ hipError_t dft_launch_all(const lhf_plan_s* p, const R* gH, const R* gS, typenam
 
 }  // namespace
 
+// LDS bytes (complex128) of the fused kernel for a lattice, 0 when the
+// lattice does not qualify (one transformed dimension, a band wider than 32
+// slots, an axis longer than 4096, or more than 64 KiB).
+static int64_t fused_lds_bytes(const LatDev& L) {
+  int nd = 0;
+  for (int d = 0; d < 3; ++d) nd += L.L[d] > 1;
+  if (nd < 2 || L.L[0] > 4096) return 0;
+  const int B1 = nslot(L.dim[0]), B2 = nslot(L.dim[1]), B3 = nslot(L.dim[2]);
+  if (B1 > 32 || B2 > 32 || B3 > 32) return 0;
+  const int J2C = std::min(L.L[1], kFusedJ2);
+  const int64_t n = (int64_t)B1 * B2 * kFusedEC + (int64_t)B1 * J2C * kFusedEC + L.L[0] + (int64_t)J2C * B2 + B3;
+  return n * 16 > 65536 ? 0 : n * 16;
+}
+
 void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std::vector<DftTask>& tasks,
-                    std::vector<DftLaunch>& launches, int64_t& tmp_elems) {
+                    std::vector<DftLaunch>& launches, int64_t& tmp_elems, std::vector<FusedTask>& fused,
+                    int64_t& fused_wgs, int32_t& fused_bmax, int32_t& fused_lds) {
   tasks.clear();
   launches.clear();
+  fused.clear();
+  fused_wgs = 0;
+  fused_bmax = 0;
+  fused_lds = 0;
   const int nlat = (int)lats.size();
+  // lattices with two or three transformed dimensions take the fused kernel
+  std::vector<bool> is_fused(nlat, false);
+  for (int li = 0; li < nlat; ++li) {
+    const LatDev& L = lats[li];
+    const int64_t lb = fused_lds_bytes(L);
+    if (lb == 0) continue;
+    is_fused[li] = true;
+    FusedTask t{};
+    t.li = li;
+    t.EC = kFusedEC;
+    t.nec = (L.m0 * L.m0 + kFusedEC - 1) / kFusedEC;
+    t.J2C = std::min(L.L[1], kFusedJ2);
+    t.nj2c = (L.L[1] + t.J2C - 1) / t.J2C;
+    t.wg_base = fused_wgs;
+    fused_wgs += (int64_t)L.L[2] * t.nj2c * t.nec;
+    fused.push_back(t);
+    for (int d = 0; d < 3; ++d) fused_bmax = std::max(fused_bmax, nslot(L.dim[d]));
+    fused_lds = std::max<int32_t>(fused_lds, (int32_t)lb);
+  }
   // per lattice: the transformed dimensions, last non-trivial first (a
   // one-cell lattice is a single pass over dimension 3 that copies)
   std::vector<std::vector<int>> dims(nlat);
   for (int li = 0; li < nlat; ++li) {
+    if (is_fused[li]) continue;
     for (int d = 2; d >= 0; --d)
       if (lats[li].L[d] > 1) dims[li].push_back(d);
     if (dims[li].empty()) dims[li].push_back(2);
@@ -324,12 +520,12 @@ void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std
 }
 
 hipError_t launch_block_dft(const lhf_plan_s* p, int prec, const void* gen_h, const void* gen_s, void* bar_h,
-                            void* bar_s, void* tmp, hipStream_t s) {
+                            void* bar_s, void* tmp, float2* b32_h, float2* b32_s, hipStream_t s) {
   if (prec == LHF_PREC_FP64)
     return dft_launch_all<double>(p, (const double*)gen_h, (const double*)gen_s, (double2*)bar_h, (double2*)bar_s,
-                                  (double2*)tmp, p->d_tw64, s);
+                                  (double2*)tmp, p->d_tw64, b32_h, b32_s, s);
   return dft_launch_all<float>(p, (const float*)gen_h, (const float*)gen_s, (float2*)bar_h, (float2*)bar_s,
-                               (float2*)tmp, p->d_tw32, s);
+                               (float2*)tmp, p->d_tw32, nullptr, nullptr, s);
 }
 
 }  // namespace lhf

@@ -425,7 +425,9 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
   typedef double2 C;
   typedef double R;
   constexpr int G = Shape<M>::G, TPM = Shape<M>::TPM;
-  __shared__ Smem<R, M, G, true, true> sh;
+  // eigenvalues only: no V; the products' scratch is F (Rayleigh-Ritz) and
+  // the dead U (congruence), so four matrices per group instead of five
+  __shared__ Smem<R, M, G, true, WANTV> sh;
   const int g = threadIdx.x / TPM, t = threadIdx.x % TPM;
   const int slot = blockIdx.x * G + g;
   const bool valid = slot < ncanon;
@@ -504,20 +506,26 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     for (int k = 0; k < 4; ++k) {
       const int e = t + k * TPM, r = e / M, c = e % M;
       C a = cmk<C>(0.0, 0.0);
+      #pragma unroll 2
       for (int q = 0; q < M; ++q) a = cadd(a, cmul(which == 0 ? sh.A[g][r][q] : sh.B[g][r][q], sh.U[g][q][c]));
       acc[k] = a;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int e = t + k * TPM;
-      sh.V[g][e / M][e % M] = acc[k];
+      if constexpr (WANTV) sh.V[g][e / M][e % M] = acc[k]; else sh.F[g][e / M][e % M] = acc[k];
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int e = t + k * TPM, r = e / M, c = e % M;
       C a = cmk<C>(0.0, 0.0);
-      for (int q = 0; q < M; ++q) a = cadd(a, cmulc(sh.U[g][q][r], sh.V[g][q][c]));
+      #pragma unroll 2
+      for (int q = 0; q < M; ++q) {
+        C tq;
+        if constexpr (WANTV) tq = sh.V[g][q][c]; else tq = sh.F[g][q][c];
+        a = cadd(a, cmulc(sh.U[g][q][r], tq));
+      }
       acc[k] = a;
     }
 #pragma unroll
@@ -571,6 +579,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     for (int h = deg - 2; h >= 0; --h) {
       LHF_FOR_ENTRIES {
         C a = cmk<C>(0.0, 0.0);
+        #pragma unroll 2
         for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.B[g][r][q], sh.F[g][q][c]));
         if (r == c) a.x += cf(h);
         acc[k] = a;
@@ -582,19 +591,25 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     // V <- A X, then A <- X V (Hermitian), V <- I
     LHF_FOR_ENTRIES {
       C a = cmk<C>(0.0, 0.0);
+      #pragma unroll 2
       for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.A[g][r][q], sh.F[g][q][c]));
-      sh.V[g][r][c] = a;
+      if constexpr (WANTV) sh.V[g][r][c] = a; else sh.U[g][r][c] = a;
     }
     __syncthreads();
     LHF_FOR_ENTRIES {
       C a = cmk<C>(0.0, 0.0);
-      for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.F[g][r][q], sh.V[g][q][c]));
+      #pragma unroll 2
+      for (int q = 0; q < M; ++q) {
+        C vq;
+        if constexpr (WANTV) vq = sh.V[g][q][c]; else vq = sh.U[g][q][c];
+        a = cadd(a, cmul(sh.F[g][r][q], vq));
+      }
       acc[k] = a;
     }
     __syncthreads();
     LHF_FOR_ENTRIES {
       sh.A[g][r][c] = acc[k];
-      sh.V[g][r][c] = cmk<C>(r == c ? 1.0 : 0.0, 0.0);
+      if constexpr (WANTV) sh.V[g][r][c] = cmk<C>(r == c ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
     LHF_FOR_ENTRIES {
@@ -609,14 +624,15 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
   } else {
     chol_reduce(sh, g, t);
   }
-  const int cur = jacobi<R, M, G, true, true, WANTV>(sh, g, t, maxsw, tol);
+  const int cur = jacobi<R, M, G, true, WANTV, WANTV>(sh, g, t, maxsw, tol);
   eig_rank(sh, g, t, m, cur);
-  if (WANTV) {
+  if constexpr (WANTV) {
     if (series) {
       // A <- X V
       C acc[4];
       LHF_FOR_ENTRIES {
         C a = cmk<C>(0.0, 0.0);
+        #pragma unroll 2
         for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.F[g][r][q], sh.V[g][q][c]));
         acc[k] = a;
       }
@@ -627,9 +643,10 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     }
   }
   C vfin[4];
-  if (WANTV) {
+  if constexpr (WANTV) {
     LHF_FOR_ENTRIES {
       C a = cmk<C>(0.0, 0.0);
+      #pragma unroll 2
       for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.U[g][r][q], sh.A[g][q][c]));
       vfin[k] = a;
     }
@@ -640,7 +657,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     w[wb + sh.rank[g][t]] = sh.lam[g][t];
     if (cblk != blk) w[wc + sh.rank[g][t]] = sh.lam[g][t];
   }
-  if (WANTV) {
+  if constexpr (WANTV) {
     const int64_t cb0 = L.gen_off + (int64_t)cblk * m * m;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {

@@ -88,6 +88,15 @@ struct DftTask {
   int64_t tbase;
 };
 
+// One lattice of the fused multi-dimensional pass: workgroup w of the lattice
+// (w in [wg_base, wg_base + nwg)) transforms all three dimensions for one j3,
+// a chunk of J2C values of j2 and a chunk of EC block entries, writing the
+// Fourier blocks once.
+struct FusedTask {
+  int32_t li, J2C, nj2c, EC, nec, pad;
+  int64_t wg_base;
+};
+
 // Host-side record of one grouped DFT launch: tasks [t0, t0 + nt) of one pass
 // and one band-width class, `threads` threads (a multiple of 256), twiddles of
 // axes up to `lds_tw` entries staged in LDS.

@@ -263,7 +263,10 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->signature = plan_signature(p);
   std::vector<DftTask> dft_tasks;
   int64_t dtmp = 0;
-  plan_block_dft(p->lat, p->dft_target_threads, dft_tasks, p->dft_launches, dtmp);
+  std::vector<FusedTask> fused;
+  plan_block_dft(p->lat, p->dft_target_threads, dft_tasks, p->dft_launches, dtmp, fused, p->fused_wgs,
+                 p->fused_bmax, p->fused_lds);
+  p->n_fused = (int32_t)fused.size();
   p->sizes.nlat = nlat;
   p->sizes.nblocks = blk;
   p->sizes.gen_elems = gen;
@@ -345,6 +348,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   upload(p->d_fac_items, fac_items.data(), fac_items.size());
   upload(p->d_elem_start, elem_start.data(), elem_start.size());
   upload(p->d_dft_tasks, dft_tasks.data(), dft_tasks.size());
+  upload(p->d_fused, fused.data(), fused.size());
   for (int c = 0; c < 4; ++c) upload(p->d_canon[c], canon[c].data(), canon[c].size());
   if (!ok) {
     set_error("allocation or upload of the plan tables failed");
@@ -380,7 +384,7 @@ size_t lhf_workspace_size(lhf_plan_t plan) { return plan ? plan->sizes.ws_bytes 
 int32_t lhf_plan_destroy(lhf_plan_t plan) {
   if (!plan) return LHF_OK;
   void* tables[] = {plan->d_lat, plan->d_tw64, plan->d_tw32, plan->d_gram_items, plan->d_fac_items,
-                    plan->d_elem_start, plan->d_dft_tasks, plan->d_canon[0], plan->d_canon[1],
+                    plan->d_elem_start, plan->d_dft_tasks, plan->d_fused, plan->d_canon[0], plan->d_canon[1],
                     plan->d_canon[2], plan->d_canon[3]};
   for (void* t : tables)
     if (t) (void)hipFree(t);

@@ -28,6 +28,11 @@ struct lhf_plan_s {
   int64_t combine_threads = 0;          // padded total
   lhf::DftTask* d_dft_tasks = nullptr;  // every task of every pass
   std::vector<lhf::DftLaunch> dft_launches;
+  lhf::FusedTask* d_fused = nullptr;    // lattices transformed by the fused kernel
+  int32_t n_fused = 0;
+  int64_t fused_wgs = 0;
+  int32_t fused_bmax = 0;               // largest band over the fused lattices' dimensions
+  int32_t fused_lds = 0;                // bytes of LDS per workgroup for complex128
   int2* d_canon[4] = {nullptr, nullptr, nullptr, nullptr};  // (lattice, block) per size class M = 4, 8, 16, 32
   int32_t ncanon[4] = {0, 0, 0, 0};
   // tunables (planner defaults, refined by lhf_plan_autotune)
@@ -81,9 +86,11 @@ hipError_t launch_combine(const lhf_plan_s* p, const double* g64, const float* g
 // blockdft.hip: planner of the grouped passes (task table, launch list and
 // intermediate size in complex elements), and their launch
 void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std::vector<DftTask>& tasks,
-                    std::vector<DftLaunch>& launches, int64_t& tmp_elems);
+                    std::vector<DftLaunch>& launches, int64_t& tmp_elems, std::vector<FusedTask>& fused,
+                    int64_t& fused_wgs, int32_t& fused_bmax, int32_t& fused_lds);
+// b32_h, b32_s (FP64 transforms only, may be NULL): complex64 copies of the blocks
 hipError_t launch_block_dft(const lhf_plan_s* p, int prec, const void* gen_h, const void* gen_s,
-                            void* bar_h, void* bar_s, void* tmp, hipStream_t s);
+                            void* bar_h, void* bar_s, void* tmp, float2* b32_h, float2* b32_s, hipStream_t s);
 // heev.hip: every canonical block of every lattice, one launch per size class
 int heev_class(int m0);
 hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, const void* Sbar,

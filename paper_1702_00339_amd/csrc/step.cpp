@@ -36,6 +36,10 @@ int32_t check_args(const lhf_plan_s* p, const lhf_step_args* a) {
     set_error("give both complex128 block stacks or neither");
     return LHF_ERR_INVALID;
   }
+  if (!a->H_gen && !(refine && a->H_bar64)) {
+    set_error("H_gen may be NULL only in a refined mixed step that fills the complex128 blocks");
+    return LHF_ERR_INVALID;
+  }
   return LHF_OK;
 }
 
@@ -49,7 +53,12 @@ int32_t run_stages(lhf_plan_s* p, const lhf_step_args* a, hipStream_t s, int whi
                              mixed ? a->S_gen64 : nullptr, a->ws, a->ws_bytes, s);
     if (st != LHF_OK) return st;
   }
-  if (which & 2) {
+  if ((which & 2) && refine && a->H_bar64 && !a->H_gen) {
+    // one FP64 transform writes the complex128 blocks and their complex64 copies
+    st = lhf_block_fft_dual(p, a->H_gen64, a->S_gen64, a->H_bar64, a->S_bar64, a->H_bar, a->S_bar, a->ws,
+                            a->ws_bytes, s);
+    if (st != LHF_OK) return st;
+  } else if (which & 2) {
     st = lhf_block_fft(p, p->prec, a->H_gen, a->S_gen, a->H_bar, a->S_bar, a->ws, a->ws_bytes, s);
     if (st != LHF_OK) return st;
     if (refine && a->H_bar64) {
@@ -75,8 +84,10 @@ int32_t apply_tuning(lhf_plan_s* p) {
   plan_grams(p->lat, items);
   std::vector<DftTask> tasks;
   std::vector<DftLaunch> launches;
-  int64_t tmp = 0;
-  plan_block_dft(p->lat, p->dft_target_threads, tasks, launches, tmp);
+  std::vector<FusedTask> fused;
+  int64_t tmp = 0, fwgs = 0;
+  int32_t fbmax = 0, flds = 0;
+  plan_block_dft(p->lat, p->dft_target_threads, tasks, launches, tmp, fused, fwgs, fbmax, flds);
   if (tmp != p->dft_tmp_elems) { set_error("internal: DFT intermediate size changed"); return LHF_ERR_INVALID; }
   hipError_t e = hipMemcpy(p->d_lat, p->lat.data(), sizeof(LatDev) * p->lat.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && (int32_t)items.size() != p->n_gram_items) {

@@ -13,10 +13,15 @@ from . import lhf
 
 
 class Pipeline:
-    """prec: lhf.LHF_PREC_FP64 or lhf.LHF_PREC_MIXED.  For the mixed path the
-    refinement source is either the complex128 Fourier blocks (``refine_src``
-    = "bar64", general) or regeneration from the FP64 generator band
-    (``refine_src`` = "band", cheap for chains)."""
+    """prec: lhf.LHF_PREC_FP64 or lhf.LHF_PREC_MIXED.  For the mixed path
+    ``refine_src`` picks where the FP64 refinement gets its blocks:
+      "dual"  (default) the assembly writes only the FP64 stacks and one FP64
+              block DFT writes the complex128 blocks and their complex64
+              copies for the FP32 solve;
+      "bar64" FP32 stacks and a complex64 DFT for the FP32 solve, plus a
+              separate complex128 DFT of the FP64 stacks;
+      "band"  FP32 stacks and a complex64 DFT; refinement regenerates each
+              block from the FP64 generator band."""
 
     def __init__(self, instances, prec=lhf.LHF_PREC_FP64, gram=lhf.LHF_GRAM_BF16X3, refine_src="auto",
                  want_vectors=False, device="cuda", L0=None):
@@ -47,11 +52,12 @@ class Pipeline:
         self.H_gen64 = self.S_gen64 = self.H_bar64 = self.S_bar64 = None
         if prec == lhf.LHF_PREC_MIXED:
             if refine_src == "auto":
-                refine_src = "band" if all(inst.L[1] == 1 and inst.L[2] == 1 for inst in instances) else "bar64"
+                refine_src = "dual"
+            assert refine_src in ("dual", "bar64", "band")
             self.refine_src = refine_src
             self.H_gen64 = torch.empty(G, dtype=torch.float64, device=dev)
             self.S_gen64 = torch.empty(G, dtype=torch.float64, device=dev)
-            if refine_src == "bar64":
+            if refine_src in ("bar64", "dual"):
                 self.H_bar64 = torch.empty(G, dtype=torch.complex128, device=dev)
                 self.S_bar64 = torch.empty(G, dtype=torch.complex128, device=dev)
         else:
@@ -65,7 +71,9 @@ class Pipeline:
         flags = lhf.LHF_HEEV_VECTORS if self.want_vectors else 0
         if self.prec == lhf.LHF_PREC_MIXED:
             flags |= lhf.LHF_HEEV_REFINE_FP64
-        return lhf.lhf_step_args(ptr(self.H_gen), ptr(self.S_gen), ptr(self.grams64), ptr(self.H_gen64),
+        dual = self.prec == lhf.LHF_PREC_MIXED and self.refine_src == "dual"
+        return lhf.lhf_step_args(None if dual else ptr(self.H_gen), None if dual else ptr(self.S_gen),
+                                 ptr(self.grams64), ptr(self.H_gen64),
                                  ptr(self.S_gen64), ptr(self.H_bar), ptr(self.S_bar), ptr(self.H_bar64),
                                  ptr(self.S_bar64), ptr(self.w), ptr(self.V), ptr(self.info), ptr(self.ws),
                                  self.ws.numel(), flags)
@@ -89,9 +97,14 @@ class Pipeline:
             flags = lhf.LHF_HEEV_VECTORS if self.want_vectors else 0
             p.lhf_heev_batched(flags, self.H_bar, self.S_bar, self.w, self.info, self.ws, V=self.V)
             return
-        p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws, H_gen64=self.H_gen64,
-                              S_gen64=self.S_gen64)
-        p.lhf_block_fft(lhf.LHF_PREC_MIXED, self.H_gen, self.S_gen, self.H_bar, self.S_bar, self.ws)
+        if self.refine_src == "dual":
+            p.lhf_assemble_blocks(None, None, self.grams64, self.ws, H_gen64=self.H_gen64, S_gen64=self.S_gen64)
+            p.lhf_block_fft_dual(self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.H_bar, self.S_bar,
+                                 self.ws)
+        else:
+            p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws, H_gen64=self.H_gen64,
+                                  S_gen64=self.S_gen64)
+            p.lhf_block_fft(lhf.LHF_PREC_MIXED, self.H_gen, self.S_gen, self.H_bar, self.S_bar, self.ws)
         if self.refine_src == "bar64":
             p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.ws)
         flags = lhf.LHF_HEEV_REFINE_FP64 | (lhf.LHF_HEEV_VECTORS if self.want_vectors else 0)

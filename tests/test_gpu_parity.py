@@ -86,13 +86,18 @@ def test_mixed_pipeline_matches_oracle(case, gram):
     inst = tiny_instance(**{"R": 8, **case})
     print(inst.summary(), "gram", gram, flush=True)
     res, ref = _eig_ref(inst)
-    for src in ("band", "bar64"):
+    for src in ("band", "bar64", "dual"):
         pipe = _run(inst, lhf.LHF_PREC_MIXED, gram=gram, refine_src=src)
         info = pipe.info.cpu().numpy()
         assert (info == 0).all(), (src, info)
         got = pipe.eigenvalues()[0]
         err = np.abs(got - ref).max()
         assert err <= 1e-8, (src, err)
+        if src == "dual":
+            # the complex64 blocks are the roundings of the complex128 ones
+            assert torch.equal(pipe.H_bar, pipe.H_bar64.to(torch.complex64))
+            assert torch.equal(pipe.S_bar, pipe.S_bar64.to(torch.complex64))
+            continue
         Hg = pipe.stacks("H_gen")[0]
         rel = np.abs(Hg - res["H_gen"]).max() / np.abs(res["H_gen"]).max()
         assert rel <= (1e-4 if gram != lhf.LHF_GRAM_FP64 else 1e-6), rel
