@@ -38,6 +38,12 @@ WORKLOADS = {
 # lattices of the 64-lattice mix checked against the oracle: the cheapest of each basis size
 C4_CHECK = (28, 41, 52, 2)
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per call (FETCH_SIZE + WRITE_SIZE, KiB, scaled by a plain 512 MiB copy) of the mixed path's
+# eigensolve call (FP32 Jacobi + FP64 refinement kernels) and dual block DFT, from two rocprofv3 --pmc
+# runs of `bench.py --probe-traffic` (profiles/traffic_per_dispatch.md).  Valid for the kernels as they
+# were when counted; None where not counted.
+TRAFFIC_KIB = {"c2": {"eig": 1480.9, "dft": 3383.3}, "c3": {"eig": 42733.5, "dft": 99237.4},
+               "c4": {"eig": 695882.6, "dft": 1792882.1}}
 
 
 def parse():
@@ -48,6 +54,9 @@ def parse():
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the Dirichlet-chain (c5) measurement")
+    ap.add_argument("--probe-traffic", action="store_true",
+                    help="for hardware-counter runs: a device copy of 512 MiB (the counters' scale), then three "
+                         "eager steps of each path; prints nothing else")
     return ap.parse_args()
 
 
@@ -161,6 +170,23 @@ def bench_c5(torch, np, lhf, steps):
             "L0": info.L0, "cross_cells": info.ncross, "embedding": P, "matvec_120_vectors": mv}
 
 
+def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
+    """Kernels for a FETCH_SIZE / WRITE_SIZE counter run: a plain copy of
+    512 MiB (reads and writes exactly that many bytes: the scale of the
+    counters), then three eager steps of the mixed and the FP64 paths."""
+    src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    insts = config_c4_lattices() if args.config == "c4" else [make_config(args.config)]
+    for prec in (lhf.LHF_PREC_MIXED, lhf.LHF_PREC_FP64):
+        kw = {"gram": lhf.LHF_GRAM_FP64} if prec == lhf.LHF_PREC_MIXED else {}
+        pipe = Pipeline(insts, prec=prec, **kw)
+        for _ in range(3):
+            pipe.step_native()
+    torch.cuda.synchronize()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -175,6 +201,9 @@ def main():
     from synth import config_c4_lattices, make_config
 
     torch.cuda.set_device(0)
+    if args.probe_traffic:
+        probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices)
+        return
     if args.config == "c4":
         insts = config_c4_lattices()
         checked = [insts[i] for i in C4_CHECK]
@@ -259,6 +288,10 @@ def main():
                          f"shift, combination, FFT, batched LAPACK eigensolves), median of {len(runs)} runs "
                          f"of {tmed:.2f} s"}
 
+    def traffic(kind):
+        t = TRAFFIC_KIB.get(args.config, {}).get(kind)
+        return None if t is None else t * 1024.0
+
     m0s = sorted({inst.m0 for inst in insts})
     line = {
         "metric": METRIC, "value": value, "unit": "blocks/s", "n_gpus": 1, "steps": args.steps,
@@ -277,10 +310,10 @@ def main():
                      "fp64_max_rel_eig_err": errs["fp64"][1], "fp64_info_ok": errs["fp64"][2]},
         "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: FP32 Jacobi + FP64 refinement)",
                      "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s", "frac": tflops / 157.3,
-                     "traffic": None, "flops_per_launch": flops, "avg_launch_ms": ms_heev},
+                     "traffic": traffic("eig"), "flops_per_launch": flops, "avg_launch_ms": ms_heev},
         "roofline_dft": {"bound": "hbm", "kernel": "block DFT (lhf_block_fft_dual: complex128 + complex64)",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("dft"),
                          "bytes_per_launch": bytes_alg, "avg_launch_ms": ms_dft},
         "tuning": tuning,
         "dirichlet_c5": c5,
