@@ -291,7 +291,7 @@ int32_t lhf_toeplitz_matvec(lhf_toeplitz_t tp, int32_t prec, int32_t ncols, cons
 /* Workspace bytes of lhf_toeplitz_eigs for nev wanted eigenpairs. */
 size_t lhf_toeplitz_eigs_workspace(lhf_toeplitz_t tp, int32_t nev);
 /* The nev lowest eigenpairs of (H_model, S_model) by block LOBPCG (Knyazev)
- * with nev + 8 vectors: basis [X, W, P], W the residuals through the circulant
+ * with nev + 4 vectors: basis [X, W, P], W the residuals through the circulant
  * preconditioner (H_c - sigma S_c)^-1 per frequency (H_c, S_c the embedding's
  * blocks; sigma below their spectrum), images recomputed by matvecs every
  * iteration, S-orthonormalised in FP64 (SVQB), FP64 Rayleigh-Ritz; matvecs in
@@ -303,7 +303,7 @@ size_t lhf_toeplitz_eigs_workspace(lhf_toeplitz_t tp, int32_t nev);
  * (S-orthonormal eigenvectors); *iters (host, may be NULL): iterations used.
  * Returns LHF_OK also when maxit is reached (then *iters == maxit and the
  * residual test failed; *resid (host, may be NULL) gets the largest residual).
- * Errors: LHF_ERR_INVALID (nev < 1, nev + 8 > N, 3 (nev + 8) > 192),
+ * Errors: LHF_ERR_INVALID (nev < 1, nev + 4 > N, 3 (nev + 4) > 112),
  * LHF_ERR_WORKSPACE, LHF_ERR_HIP. */
 int32_t lhf_toeplitz_eigs(lhf_toeplitz_t tp, int32_t nev, int32_t maxit, double tol, uint64_t seed,
                           double* d_w, double* d_V, int32_t* iters, double* resid, void* d_ws,

@@ -1,6 +1,6 @@
 // Dense FP64 kernels of the block LOBPCG driver: Gram products of tall
 // blocks, block combinations, residuals, SVQB helpers and a one-workgroup
-// symmetric eigensolver for the Rayleigh-Ritz problems (size <= 128).
+// symmetric eigensolver for the Rayleigh-Ritz problems (size <= 112).
 //
 // Blocks of vectors are row-major [N][ld] (column j = vector j).  Reductions
 // over N are split into fixed chunks whose partial results are added in chunk
@@ -167,35 +167,53 @@ __global__ void __launch_bounds__(256) symmetrize_kernel(int m, double* __restri
   }
 }
 
-// Round-robin pair i of round s among Me indices (Me even).
+// Round-robin pair i of round s among Me indices (Me even; 0 <= s, i < Me - 1).
 __device__ __forceinline__ void rr_pair(int i, int s, int Me, int& p, int& q) {
   const int m = Me - 1;
-  if (i == 0) { p = 0; q = 1 + s; }
-  else { p = 1 + (s + i) % m; q = 1 + (s - i + m) % m; }
+  if (i == 0) {
+    p = 0;
+    q = 1 + s;
+  } else {
+    int a = s + i, b = s - i + m;   // both in (0, 2m)
+    if (a >= m) a -= m;
+    if (b >= m) b -= m;
+    p = 1 + a;
+    q = 1 + b;
+  }
 }
 
 constexpr int kSyevThreads = 1024;
 
 // Real symmetric eigensolver, one workgroup: cyclic Jacobi in the parallel
-// round-robin order on A in LDS (size padded to even Me with a decoupled zero
-// index); thread b owns 2 x 2 blocks (b / H, b % H) of the pairs of a round,
-// rotations computed by the diagonal-block threads; V (global scratch) follows
-// the rotations.  Stops when the off-diagonal Frobenius norm is below
-// 4 Me eps of the norm of A.  Output: eigenvalues ascending in w, eigenvector
-// j in column j of Vout.
+// round-robin order (size padded to even Me with a decoupled zero index).
+// Everything lives in LDS: A as its packed upper triangle (the rotations keep
+// it symmetric, so each unordered 2 x 2 block pair is rotated once) and V
+// transposed (column c of V contiguous).  Rotations are computed by one
+// thread per pair; blocks (bi <= bj) of A and rows of the pairs' V columns
+// are spread over the threads.  Stops when the off-diagonal Frobenius norm
+// is below 4 Me eps of the norm of A.  Output: eigenvalues ascending in w,
+// eigenvector j in column j of Vout.
+__device__ __forceinline__ int tri_index(int r, int c, int Me) {
+  if (r > c) { const int x = r; r = c; c = x; }
+  return r * Me - (r * (r - 1)) / 2 + (c - r);
+}
+
 __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double* __restrict__ Ain, int lda,
                                                             double* __restrict__ w, double* __restrict__ Vout,
-                                                            int ldv, double* __restrict__ V) {
-  extern __shared__ double A[];   // [Me][Me + 1]
+                                                            int ldv) {
+  extern __shared__ double lds[];
   __shared__ double cs[kMaxSmall / 2], sn[kMaxSmall / 2], dn[kMaxSmall], red[kSyevThreads / 64];
   __shared__ int rank[kMaxSmall];
   __shared__ int done;
-  const int Me = m + (m & 1), H = Me / 2, S = Me + 1;
+  const int Me = m + (m & 1), H = Me / 2;
+  double* A = lds;                         // packed upper triangle, Me (Me + 1) / 2
+  double* V = lds + Me * (Me + 1) / 2;     // transposed: V[c * Me + r] is entry (r, c)
   const int tid = threadIdx.x;
+  const int ntri = Me * (Me + 1) / 2, nblk = H * (H + 1) / 2;
   for (int e = tid; e < Me * Me; e += kSyevThreads) {
     const int r = e / Me, c = e % Me;
-    A[r * S + c] = (r < m && c < m) ? Ain[r * lda + c] : 0.0;
-    V[r * Me + c] = r == c ? 1.0 : 0.0;
+    if (r <= c) A[tri_index(r, c, Me)] = (r < m && c < m) ? 0.5 * (Ain[r * lda + c] + Ain[c * lda + r]) : 0.0;
+    V[e] = r == c ? 1.0 : 0.0;
   }
   __syncthreads();
   auto block_sum = [&](double v) -> double {
@@ -207,18 +225,50 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
     __syncthreads();
     return s;
   };
+  // norms: diagonal once, off-diagonal twice; row r of the packed triangle
+  // starts at r Me - r (r - 1) / 2
+  auto row_of = [&](int e) {
+    int r = (int)((2.0 * Me + 1.0 - sqrt((2.0 * Me + 1.0) * (2.0 * Me + 1.0) - 8.0 * e)) * 0.5);
+    while (r > 0 && r * Me - (r * (r - 1)) / 2 > e) --r;
+    while ((r + 1) * Me - ((r + 1) * r) / 2 <= e) ++r;
+    return r;
+  };
   double nl = 0.0;
-  for (int e = tid; e < Me * Me; e += kSyevThreads) {
-    const double a = A[(e / Me) * S + e % Me];
-    nl += a * a;
+  for (int e = tid; e < ntri; e += kSyevThreads) {
+    const int r = row_of(e), c = r + (e - (r * Me - (r * (r - 1)) / 2));
+    nl += (r == c ? 1.0 : 2.0) * A[e] * A[e];
   }
   const double nrm2 = block_sum(nl);
   const double tol = 4.0 * Me * 1.1102230246251565e-16;
+  // this thread's blocks (bi <= bj) and eigenvector items (pair, row): fixed
+  // for every round
+  constexpr int kMaxBlk = (kMaxSmall / 2) * (kMaxSmall / 2 + 1) / 2 / kSyevThreads + 1;
+  constexpr int kMaxItem = (kMaxSmall / 2) * kMaxSmall / kSyevThreads + 1;
+  int blk_i[kMaxBlk], blk_j[kMaxBlk], item_i[kMaxItem], item_r[kMaxItem];
+#pragma unroll
+  for (int k = 0; k < kMaxBlk; ++k) {
+    const int bb = tid + k * kSyevThreads;
+    blk_i[k] = -1;
+    blk_j[k] = -1;
+    if (bb < nblk) {
+      int bi = (int)((2.0 * H + 1.0 - sqrt((2.0 * H + 1.0) * (2.0 * H + 1.0) - 8.0 * bb)) * 0.5);
+      while (bi > 0 && bi * H - (bi * (bi - 1)) / 2 > bb) --bi;
+      while ((bi + 1) * H - ((bi + 1) * bi) / 2 <= bb) ++bi;
+      blk_i[k] = bi;
+      blk_j[k] = bi + (bb - (bi * H - (bi * (bi - 1)) / 2));
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxItem; ++k) {
+    const int it = tid + k * kSyevThreads;
+    item_i[k] = it < H * Me ? it / Me : -1;
+    item_r[k] = it < H * Me ? it - (it / Me) * Me : 0;
+  }
   for (int sw = 0; sw < 60; ++sw) {
     double ol = 0.0;
-    for (int e = tid; e < Me * Me; e += kSyevThreads) {
-      const int r = e / Me, c = e % Me;
-      if (r != c) ol += A[r * S + c] * A[r * S + c];
+    for (int e = tid; e < ntri; e += kSyevThreads) {
+      const int r = row_of(e), c = r + (e - (r * Me - (r * (r - 1)) / 2));
+      if (r != c) ol += 2.0 * A[e] * A[e];
     }
     const double off = block_sum(ol);
     if (tid == 0) done = off <= tol * tol * nrm2;
@@ -228,10 +278,18 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
       for (int i = tid; i < H; i += kSyevThreads) {
         int p, q;
         rr_pair(i, s, Me, p, q);
-        const double app = A[p * S + p], aqq = A[q * S + q], b = A[p * S + q];
-        const double ab = fabs(b);
+        const double app = A[tri_index(p, p, Me)], aqq = A[tri_index(q, q, Me)], b = A[tri_index(p, q, Me)];
+        const double ab = fabs(b), d = aqq - app;
         double c = 1.0, sv = 0.0, dp = app, dq = aqq;
-        if (ab > 0.0) {
+        if (b * b < 1e-8 * d * d) {
+          // small angle: t = (b / d)(1 - x + 2 x^2), x = b^2 / d^2; one division
+          const double id = 1.0 / d, x = b * b * id * id;
+          const double f = 1.0 - x + 2.0 * x * x, t2 = x * f * f;
+          c = 1.0 - 0.5 * t2 + 0.375 * t2 * t2;
+          sv = b * id * f * c;
+          dp = app - b * b * id * f;
+          dq = aqq + b * b * id * f;
+        } else if (ab > 0.0) {
           const double tau = (aqq - app) / (2.0 * ab);
           const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + t * t);
@@ -245,57 +303,61 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
         dn[q] = dq;
       }
       __syncthreads();
-      for (int b = tid; b < H * H; b += kSyevThreads) {
-        const int bi = b / H, bj = b % H;
+      // A <- J^T A J on the blocks bi <= bj of the pairs
+#pragma unroll
+      for (int k = 0; k < kMaxBlk; ++k) {
+        const int bi = blk_i[k], bj = blk_j[k];
+        if (bi < 0) continue;
         int pi, qi, pj, qj;
         rr_pair(bi, s, Me, pi, qi);
         rr_pair(bj, s, Me, pj, qj);
-        const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
-        double a00, a01, a10, a11;
         if (bi == bj) {
-          a00 = dn[pi];
-          a11 = dn[qi];
-          a01 = a10 = 0.0;
+          A[tri_index(pi, pi, Me)] = dn[pi];
+          A[tri_index(qi, qi, Me)] = dn[qi];
+          A[tri_index(pi, qi, Me)] = 0.0;
         } else {
-          const double b00 = A[pi * S + pj], b01 = A[pi * S + qj], b10 = A[qi * S + pj], b11 = A[qi * S + qj];
+          const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
+          const int i00 = tri_index(pi, pj, Me), i01 = tri_index(pi, qj, Me);
+          const int i10 = tri_index(qi, pj, Me), i11 = tri_index(qi, qj, Me);
+          const double b00 = A[i00], b01 = A[i01], b10 = A[i10], b11 = A[i11];
           const double t00 = b00 * cj - b01 * sj, t01 = b00 * sj + b01 * cj;
           const double t10 = b10 * cj - b11 * sj, t11 = b10 * sj + b11 * cj;
-          a00 = ci * t00 - si * t10;
-          a01 = ci * t01 - si * t11;
-          a10 = si * t00 + ci * t10;
-          a11 = si * t01 + ci * t11;
+          A[i00] = ci * t00 - si * t10;
+          A[i01] = ci * t01 - si * t11;
+          A[i10] = si * t00 + ci * t10;
+          A[i11] = si * t01 + ci * t11;
         }
-        A[pi * S + pj] = a00;
-        A[pi * S + qj] = a01;
-        A[qi * S + pj] = a10;
-        A[qi * S + qj] = a11;
-        // V <- V J_j on rows {pi, qi}, columns {pj, qj}
-        double vp = V[pi * Me + pj], vq = V[pi * Me + qj];
-        V[pi * Me + pj] = vp * cj - vq * sj;
-        V[pi * Me + qj] = vp * sj + vq * cj;
-        vp = V[qi * Me + pj];
-        vq = V[qi * Me + qj];
-        V[qi * Me + pj] = vp * cj - vq * sj;
-        V[qi * Me + qj] = vp * sj + vq * cj;
+      }
+      // V <- V J: columns p, q of every pair, one row per thread
+#pragma unroll
+      for (int k = 0; k < kMaxItem; ++k) {
+        const int i = item_i[k], r = item_r[k];
+        if (i < 0) continue;
+        int p, q;
+        rr_pair(i, s, Me, p, q);
+        const double c = cs[i], sv = sn[i];
+        const double vp = V[p * Me + r], vq = V[q * Me + r];
+        V[p * Me + r] = vp * c - vq * sv;
+        V[q * Me + r] = vp * sv + vq * c;
       }
       __syncthreads();
     }
   }
   // ascending ranks among the m real indices (ties by index)
   for (int i = tid; i < m; i += kSyevThreads) {
-    const double li = A[i * S + i];
+    const double li = A[tri_index(i, i, Me)];
     int k = 0;
     for (int j = 0; j < m; ++j) {
-      const double lj = A[j * S + j];
+      const double lj = A[tri_index(j, j, Me)];
       k += (lj < li || (lj == li && j < i)) ? 1 : 0;
     }
     rank[i] = k;
   }
   __syncthreads();
-  for (int i = tid; i < m; i += kSyevThreads) w[rank[i]] = A[i * S + i];
+  for (int i = tid; i < m; i += kSyevThreads) w[rank[i]] = A[tri_index(i, i, Me)];
   for (int e = tid; e < m * m; e += kSyevThreads) {
     const int r = e / m, c = e % m;
-    Vout[r * ldv + rank[c]] = V[r * Me + c];
+    Vout[r * ldv + rank[c]] = V[c * Me + r];
   }
 }
 
@@ -320,10 +382,12 @@ hipError_t dense_combine(int N, int k1, int k2, const double* A, int lda, const 
 
 hipError_t dense_syev_w(int m, const double* A, int lda, double* w, double* V, int ldv, double* work,
                         hipStream_t s) {
+  (void)work;
+  if (m < 1 || m > kMaxSmall) return hipErrorInvalidValue;
   const int Me = m + (m & 1);
-  const size_t lds = sizeof(double) * (size_t)Me * (Me + 1);
+  const size_t lds = sizeof(double) * ((size_t)Me * (Me + 1) / 2 + (size_t)Me * Me);
   (void)hipFuncSetAttribute((const void*)syev_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(kSyevThreads), lds, s, m, A, lda, w, V, ldv, work);
+  hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(kSyevThreads), lds, s, m, A, lda, w, V, ldv);
   return hipGetLastError();
 }
 

@@ -389,7 +389,7 @@ int32_t lhf_toeplitz_matvec(lhf_toeplitz_t t, int32_t prec, int32_t ncols, const
                             int32_t ld, void* ws, size_t ws_bytes, lhf_stream_t stream) {
   if (!t) { set_error("NULL operator"); return LHF_ERR_INVALID; }
   if (prec != LHF_PREC_FP64 && prec != LHF_PREC_MIXED) { set_error("bad precision"); return LHF_ERR_INVALID; }
-  if (ncols < 1 || ncols > kMaxSmall || ld < ncols) { set_error("need 1 <= ncols <= 128 and ld >= ncols"); return LHF_ERR_INVALID; }
+  if (ncols < 1 || ncols > kMaxCols || ld < ncols) { set_error("need 1 <= ncols <= 128 and ld >= ncols"); return LHF_ERR_INVALID; }
   if (!x || !yH) { set_error("x and y_H are required"); return LHF_ERR_INVALID; }
   const size_t need = lhf_toeplitz_matvec_workspace(t, ncols);
   if (!ws || ws_bytes < need) {
@@ -412,7 +412,7 @@ int32_t lhf_toeplitz_matvec(lhf_toeplitz_t t, int32_t prec, int32_t ncols, const
 
 namespace {
 
-constexpr int kGuard = 8;     // block vectors beyond the wanted ones
+constexpr int kGuard = 4;     // block vectors beyond the wanted ones
 constexpr int kChunks = 32;   // row chunks of the tall reductions
 
 struct EigWs {
@@ -460,7 +460,7 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t t, int32_t nev, int32_t maxit, double t
   if (!t) { set_error("NULL operator"); return LHF_ERR_INVALID; }
   const int nb = nev + kGuard;
   if (nev < 1 || nb > t->N || 3 * nb > kMaxSmall) {
-    set_error("need nev >= 1, nev + 8 <= N and 3 (nev + 8) <= 128");
+    set_error("need nev >= 1, nev + 4 <= N and 3 (nev + 4) <= 112");
     return LHF_ERR_INVALID;
   }
   if (maxit < 1 || !(tol > 0)) { set_error("maxit >= 1 and tol > 0 required"); return LHF_ERR_INVALID; }

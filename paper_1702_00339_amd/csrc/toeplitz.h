@@ -12,7 +12,8 @@
 
 namespace lhf {
 
-constexpr int kMaxSmall = 128;   // largest dense eigenproblem of the LOBPCG driver
+constexpr int kMaxSmall = 112;   // largest dense eigenproblem of the LOBPCG driver (LDS bound)
+constexpr int kMaxCols = 128;    // vectors per matvec call
 
 // The chain, its cell template and its grids.
 struct ToepDev {
@@ -83,7 +84,7 @@ hipError_t dense_gram(int N, int k1, int k2, const double* A, int lda, const dou
 // Y = beta Z + A T   (Z may alias nothing; beta = 0 ignores Z)
 hipError_t dense_combine(int N, int k1, int k2, const double* A, int lda, const double* T, int ldt, double beta,
                          const double* Z, int ldz, double* Y, int ldy, hipStream_t s);
-// eigenvalues ascending in w, eigenvectors in the columns of V; work: 128^2 doubles
+// eigenvalues ascending in w, eigenvectors in the columns of V (m <= kMaxSmall); work unused
 hipError_t dense_syev_w(int m, const double* A, int lda, double* w, double* V, int ldv, double* work, hipStream_t s);
 hipError_t dense_residual(int N, int k, const double* HX, const double* SX, int ld, const double* theta, double* R,
                           int ldr, double* part, int nchunk, double* norms, hipStream_t s);
