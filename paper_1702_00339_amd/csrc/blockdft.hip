@@ -278,11 +278,17 @@ __global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict
     if (ec < ecn) {
       const int k1 = slot_cell(D0, s1), k2 = slot_cell(D1, s2);
       const R* xp = X + ((int64_t)(k1 * L2 + k2) * L3) * E + e0 + ec;
-      for (int s3 = 0; s3 < B3; ++s3) {
-        const R x = xp[(int64_t)slot_cell(D2, s3) * E];
-        const C w = tw3[s3];
-        re += w.x * x;
-        im += w.y * x;
+      // all band loads first (unrolled to the band bound), then the sums
+      R xv[BM];
+#pragma unroll
+      for (int s3 = 0; s3 < BM; ++s3) xv[s3] = s3 < B3 ? xp[(int64_t)slot_cell(D2, s3) * E] : R(0);
+#pragma unroll
+      for (int s3 = 0; s3 < BM; ++s3) {
+        if (s3 < B3) {
+          const C w = tw3[s3];
+          re += w.x * xv[s3];
+          im += w.y * xv[s3];
+        }
       }
     }
     C v;
