@@ -89,7 +89,6 @@ struct Smem {
   R dn[G][M];                    // rotated diagonal
   int rank[G][M];
   int flag[G][4];                // 0: Cholesky failure column, 1: non-finite, 2: converged
-  C tw[HASU ? G : 1][HASU ? 32 : 1];   // refinement: twiddles of up to 32 band cells
 };
 
 // Sum over the TPM threads of one matrix; all threads of the workgroup call it.
@@ -117,6 +116,96 @@ __device__ __forceinline__ R group_sum(Smem<R, M, G, HASU, HASV>& sh, int g, int
 #define LHF_FOR_ENTRIES                                   \
   _Pragma("unroll") for (int k = 0; k < 4; ++k)           \
     if (const int e = t + k * TPM, r = e / M, c = e % M; true)
+
+// Register-tiled products of the refinement: thread t of a matrix owns the
+// 2 x 2 tile of rows {ti, ti + M/2} and columns {tj, tj + M/2},
+// ti = t / (M/2), tj = t % (M/2); every operand entry loaded from LDS feeds
+// two products (four when two products share an operand).
+template <int M> struct Tile {
+  static constexpr int H = M / 2;
+  static constexpr int UR = M <= 8 ? M : 4;   // q-loop unroll
+};
+
+// P1 = X1 Y, P2 = X2 Y
+template <int M, typename C>
+__device__ __forceinline__ void mm_shared_right(const C (&X1)[M][M + 1], const C (&X2)[M][M + 1],
+                                                const C (&Y)[M][M + 1], int ti, int tj, C (&p1)[2][2],
+                                                C (&p2)[2][2]) {
+  constexpr int H = M / 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) { p1[a][b] = cmk<C>(0, 0); p2[a][b] = cmk<C>(0, 0); }
+#pragma unroll Tile<M>::UR
+  for (int q = 0; q < M; ++q) {
+    const C y0 = Y[q][tj], y1 = Y[q][tj + H];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const C x1 = X1[ti + a * H][q], x2 = X2[ti + a * H][q];
+      p1[a][0] = cadd(p1[a][0], cmul(x1, y0));
+      p1[a][1] = cadd(p1[a][1], cmul(x1, y1));
+      p2[a][0] = cadd(p2[a][0], cmul(x2, y0));
+      p2[a][1] = cadd(p2[a][1], cmul(x2, y1));
+    }
+  }
+}
+
+// P1 = X^H Y1, P2 = X^H Y2
+template <int M, typename C>
+__device__ __forceinline__ void mm_shared_left_h(const C (&X)[M][M + 1], const C (&Y1)[M][M + 1],
+                                                 const C (&Y2)[M][M + 1], int ti, int tj, C (&p1)[2][2],
+                                                 C (&p2)[2][2]) {
+  constexpr int H = M / 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) { p1[a][b] = cmk<C>(0, 0); p2[a][b] = cmk<C>(0, 0); }
+#pragma unroll Tile<M>::UR
+  for (int q = 0; q < M; ++q) {
+    const C x0 = X[q][ti], x1 = X[q][ti + H];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const C y1 = Y1[q][tj + b * H], y2 = Y2[q][tj + b * H];
+      p1[0][b] = cadd(p1[0][b], cmulc(x0, y1));
+      p1[1][b] = cadd(p1[1][b], cmulc(x1, y1));
+      p2[0][b] = cadd(p2[0][b], cmulc(x0, y2));
+      p2[1][b] = cadd(p2[1][b], cmulc(x1, y2));
+    }
+  }
+}
+
+// P = X Y (+ d I when ADDI)
+template <int M, bool ADDI, typename C, typename R>
+__device__ __forceinline__ void mm_tile(const C (&X)[M][M + 1], const C (&Y)[M][M + 1], int ti, int tj, R d,
+                                        C (&p)[2][2]) {
+  constexpr int H = M / 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) p[a][b] = cmk<C>(0, 0);
+#pragma unroll Tile<M>::UR
+  for (int q = 0; q < M; ++q) {
+    const C y0 = Y[q][tj], y1 = Y[q][tj + H];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const C x = X[ti + a * H][q];
+      p[a][0] = cadd(p[a][0], cmul(x, y0));
+      p[a][1] = cadd(p[a][1], cmul(x, y1));
+    }
+  }
+  if constexpr (ADDI) {
+    if (ti == tj) { p[0][0].x += d; p[1][1].x += d; }
+  }
+}
+
+template <int M, typename C>
+__device__ __forceinline__ void store_tile(C (&Z)[M][M + 1], int ti, int tj, const C (&p)[2][2]) {
+  constexpr int H = M / 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) Z[ti + a * H][tj + b * H] = p[a][b];
+}
 
 // 1-2. Cholesky of B into F (B is overwritten), A <- F^-1 A F^-H (Hermitian);
 // V <- I when HASV.
@@ -450,13 +539,15 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
   const int ns3 = L.dim[2].L == 1 ? 1 : L.dim[2].nshift;
   // band-cell twiddles w^(j.k) of this block (regeneration path)
   const int ncell = ns1 * ns2 * ns3;
-  const bool twl = ncell <= 32;
+  // cached in the storage of F, which is free until the refinement's series
+  C* twc = &sh.F[g][0][0];
+  const bool twl = ncell <= M * (M + 1);
   if (!H64 && twl) {
     for (int q = t; q < ncell; q += TPM) {
       const int t3 = q % ns3, t2 = (q / ns3) % ns2, t1 = q / (ns3 * ns2);
       const int k1 = cell_of(L.dim[0], t1), k2 = cell_of(L.dim[1], t2), k3 = cell_of(L.dim[2], t3);
       C ww = cmul(tw[L.dim[0].tw_off + (j1 * k1) % L.L[0]], tw[L.dim[1].tw_off + (j2 * k2) % L.L[1]]);
-      sh.tw[g][q] = cmul(ww, tw[L.dim[2].tw_off + (j3 * k3) % L.L[2]]);
+      twc[q] = cmul(ww, tw[L.dim[2].tw_off + (j3 * k3) % L.L[2]]);
     }
   }
   __syncthreads();
@@ -478,7 +569,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
           const int k1 = cell_of(L.dim[0], t1), k2 = cell_of(L.dim[1], t2), k3 = cell_of(L.dim[2], t3);
           C ww;
           if (twl) {
-            ww = sh.tw[g][q];
+            ww = twc[q];
           } else {
             ww = cmul(cmul(tw[L.dim[0].tw_off + (j1 * k1) % L.L[0]], tw[L.dim[1].tw_off + (j2 * k2) % L.L[1]]),
                       tw[L.dim[2].tw_off + (j3 * k3) % L.L[2]]);
@@ -498,48 +589,26 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     sh.U[g][r][c] = u;
   }
   __syncthreads();
-  // Rayleigh-Ritz pair: A <- U^H Hbar U, B <- U^H Sbar U
-#pragma unroll 1
-  for (int which = 0; which < 2; ++which) {
-    C acc[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = t + k * TPM, r = e / M, c = e % M;
-      C a = cmk<C>(0.0, 0.0);
-      #pragma unroll 2
-      for (int q = 0; q < M; ++q) a = cadd(a, cmul(which == 0 ? sh.A[g][r][q] : sh.B[g][r][q], sh.U[g][q][c]));
-      acc[k] = a;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = t + k * TPM;
-      if constexpr (WANTV) sh.V[g][e / M][e % M] = acc[k]; else sh.F[g][e / M][e % M] = acc[k];
-    }
+  // Rayleigh-Ritz pair: A <- U^H Hbar U, B <- U^H Sbar U (two fused passes)
+  const int ti = t / (M / 2), tj = t % (M / 2);
+  {
+    C p1[2][2], p2[2][2];
+    mm_shared_right<M>(sh.A[g], sh.B[g], sh.U[g], ti, tj, p1, p2);
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = t + k * TPM, r = e / M, c = e % M;
-      C a = cmk<C>(0.0, 0.0);
-      #pragma unroll 2
-      for (int q = 0; q < M; ++q) {
-        C tq;
-        if constexpr (WANTV) tq = sh.V[g][q][c]; else tq = sh.F[g][q][c];
-        a = cadd(a, cmulc(sh.U[g][q][r], tq));
-      }
-      acc[k] = a;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = t + k * TPM;
-      if (which == 0) sh.A[g][e / M][e % M] = acc[k]; else sh.B[g][e / M][e % M] = acc[k];
-    }
+    store_tile<M>(sh.A[g], ti, tj, p1);
+    store_tile<M>(sh.B[g], ti, tj, p2);
+    __syncthreads();
+    mm_shared_left_h<M>(sh.U[g], sh.A[g], sh.B[g], ti, tj, p1, p2);
+    __syncthreads();
+    store_tile<M>(sh.A[g], ti, tj, p1);
+    store_tile<M>(sh.B[g], ti, tj, p2);
     __syncthreads();
   }
   // B = I + E with E small when U is S-orthonormal to FP32 accuracy (E is
   // about kappa(Sbar) times the FP32 rounding): then
   // X = (I + E)^-1/2 = I - E/2 + 3/8 E^2 - 5/16 E^3 + 35/128 E^4 - 63/256 E^5
-  // + O(E^6), summed by Horner's rule, and A <- X A X (all products parallel).
-  // Otherwise Cholesky reduction.
+  // + O(E^6), summed by Horner's rule, and A <- X A X.  Otherwise Cholesky
+  // reduction.
   R eloc = R(0);
   LHF_FOR_ENTRIES {
     const C b = sh.B[g][r][c];
@@ -557,9 +626,8 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     series = series && sh.flag[gg][3] != 0;
     deg = max(deg, sh.flag[gg][3]);
   }
-  __syncthreads();
   if (series) {
-    C acc[4];
+    C p[2][2];
     // coefficients of (1 + E)^-1/2 = sum_k cf(k) E^k
     auto cf = [](int k) -> R {
       return k == 0 ? R(1.0) : k == 1 ? R(-0.5) : k == 2 ? R(0.375) : k == 3 ? R(-0.3125)
@@ -577,79 +645,45 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     __syncthreads();
 #pragma unroll 1
     for (int h = deg - 2; h >= 0; --h) {
-      LHF_FOR_ENTRIES {
-        C a = cmk<C>(0.0, 0.0);
-        #pragma unroll 2
-        for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.B[g][r][q], sh.F[g][q][c]));
-        if (r == c) a.x += cf(h);
-        acc[k] = a;
-      }
+      mm_tile<M, true>(sh.B[g], sh.F[g], ti, tj, cf(h), p);
       __syncthreads();
-      LHF_FOR_ENTRIES { sh.F[g][r][c] = acc[k]; }
+      store_tile<M>(sh.F[g], ti, tj, p);
       __syncthreads();
     }
-    // V <- A X, then A <- X V (Hermitian), V <- I
-    LHF_FOR_ENTRIES {
-      C a = cmk<C>(0.0, 0.0);
-      #pragma unroll 2
-      for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.A[g][r][q], sh.F[g][q][c]));
-      if constexpr (WANTV) sh.V[g][r][c] = a; else sh.U[g][r][c] = a;
-    }
+    // T <- A X (into the dead U, or V with vectors), then B <- X T (E is
+    // dead), then A <- the Hermitian part of B and V <- I
+    mm_tile<M, false>(sh.A[g], sh.F[g], ti, tj, R(0), p);
+    if constexpr (WANTV) store_tile<M>(sh.V[g], ti, tj, p); else store_tile<M>(sh.U[g], ti, tj, p);
+    __syncthreads();
+    if constexpr (WANTV) mm_tile<M, false>(sh.F[g], sh.V[g], ti, tj, R(0), p);
+    else mm_tile<M, false>(sh.F[g], sh.U[g], ti, tj, R(0), p);
+    store_tile<M>(sh.B[g], ti, tj, p);
     __syncthreads();
     LHF_FOR_ENTRIES {
-      C a = cmk<C>(0.0, 0.0);
-      #pragma unroll 2
-      for (int q = 0; q < M; ++q) {
-        C vq;
-        if constexpr (WANTV) vq = sh.V[g][q][c]; else vq = sh.U[g][q][c];
-        a = cadd(a, cmul(sh.F[g][r][q], vq));
-      }
-      acc[k] = a;
-    }
-    __syncthreads();
-    LHF_FOR_ENTRIES {
-      sh.A[g][r][c] = acc[k];
-      if constexpr (WANTV) sh.V[g][r][c] = cmk<C>(r == c ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
-    LHF_FOR_ENTRIES {
-      const C x = sh.A[g][r][c], y = sh.A[g][c][r];
+      const C x = sh.B[g][r][c], y = sh.B[g][c][r];
       C s2 = cmk<C>(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
       if (r == c) s2.y = 0.0;
-      acc[k] = s2;
+      sh.A[g][r][c] = s2;
+      if constexpr (WANTV) sh.V[g][r][c] = cmk<C>(r == c ? 1.0 : 0.0, 0.0);
     }
-    __syncthreads();
-    LHF_FOR_ENTRIES { sh.A[g][r][c] = acc[k]; }
     __syncthreads();
   } else {
     chol_reduce(sh, g, t);
   }
   const int cur = jacobi<R, M, G, true, WANTV, WANTV>(sh, g, t, maxsw, tol);
   eig_rank(sh, g, t, m, cur);
+  C vfin[2][2];
   if constexpr (WANTV) {
     if (series) {
       // A <- X V
-      C acc[4];
-      LHF_FOR_ENTRIES {
-        C a = cmk<C>(0.0, 0.0);
-        #pragma unroll 2
-        for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.F[g][r][q], sh.V[g][q][c]));
-        acc[k] = a;
-      }
-      LHF_FOR_ENTRIES { sh.A[g][r][c] = acc[k]; }
+      C p[2][2];
+      mm_tile<M, false>(sh.F[g], sh.V[g], ti, tj, R(0), p);
+      store_tile<M>(sh.A[g], ti, tj, p);
       __syncthreads();
     } else {
       backsub_vectors(sh, g, t);
     }
-  }
-  C vfin[4];
-  if constexpr (WANTV) {
-    LHF_FOR_ENTRIES {
-      C a = cmk<C>(0.0, 0.0);
-      #pragma unroll 2
-      for (int q = 0; q < M; ++q) a = cadd(a, cmul(sh.U[g][r][q], sh.A[g][q][c]));
-      vfin[k] = a;
-    }
+    mm_tile<M, false>(sh.U[g], sh.A[g], ti, tj, R(0), vfin);
   }
   if (!valid) return;
   const int64_t wb = L.w_off + (int64_t)blk * m, wc = L.w_off + (int64_t)cblk * m;
@@ -660,13 +694,15 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
   if constexpr (WANTV) {
     const int64_t cb0 = L.gen_off + (int64_t)cblk * m * m;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int e = t + k * TPM, r = e / M, c = e % M;
-      if (r < m && c < m) {
-        Vout[base + r * m + sh.rank[g][c]] = vfin[k];
-        if (cblk != blk) Vout[cb0 + r * m + sh.rank[g][c]] = cconj(vfin[k]);
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int r = ti + a * (M / 2), c = tj + b * (M / 2);
+        if (r < m && c < m) {
+          Vout[base + r * m + sh.rank[g][c]] = vfin[a][b];
+          if (cblk != blk) Vout[cb0 + r * m + sh.rank[g][c]] = cconj(vfin[a][b]);
+        }
       }
-    }
   }
   if (t == 0) {
     const int st = sh.flag[g][1] ? -2 : (sh.flag[g][0] ? sh.flag[g][0] : (sh.flag[g][2] ? 0 : -1));
