@@ -327,12 +327,64 @@ __device__ int jacobi(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int maxsw, R 
       if (r != c) oloc += a.x * a.x + a.y * a.y;
     }
     const R off = group_sum(sh, g, t, oloc);
-    if (t == 0) sh.flag[g][2] = off <= tol * tol * nrm2 ? 1 : 0;
+    int st = off <= tol * tol * nrm2 ? 1 : 0;
+    R corr[4];
+    if constexpr (!WANTV) {
+      // Second-order closure for eigenvalues only.  With D = diag(A), E the
+      // off-diagonal part and rho_pq = |e_pq| / |d_p - d_q|, the eigenvalue
+      // of D + E next to d_p is d_p + sum_q |e_pq|^2 / (d_p - d_q) + r_p with
+      // the third-order term bounded by max|e| (sum_q rho_pq)^2 (higher orders
+      // by a geometric factor when sum_q rho_pq <= 1/8).  When that bound is
+      // below the stopping bound tol ||A||_F for every row, the corrected
+      // diagonal is the result and the remaining sweep is skipped.
+      // Tried only once (off / ||A||^2)^3 <= M^4 tol^2, which every accepted
+      // case satisfies (rho of the largest entry >= sqrt(off) / (2 M ||A||_F)).
+      const R x = off / nrm2;
+      bool rowok = false;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) corr[k] = R(0);
+      if (x * x * x <= R(M * M) * R(M * M) * tol * tol) {
+        const R dc = sh.A[g][t % M][t % M].x;
+        const R emax = sqrt(off);
+        rowok = true;
+        LHF_FOR_ENTRIES {
+          const C a = sh.A[g][r][c];
+          const R d = sh.A[g][r][r].x - dc;
+          const R ab2 = a.x * a.x + a.y * a.y;
+          R term = R(0), rho = R(0);
+          if (r != c) {
+            const R ad = fabs(d);
+            rho = ad > R(0) ? sqrt(ab2) / ad : R(1e30);
+            term = ad > R(0) ? ab2 / d : R(0);
+          }
+#pragma unroll
+          for (int o = M / 2; o > 0; o >>= 1) {
+            term += __shfl_xor(term, o, 64);
+            rho += __shfl_xor(rho, o, 64);
+          }
+          corr[k] = term;
+          rowok = rowok && rho <= R(0.125) && emax * rho * rho <= R(0.25) * tol * sqrt(nrm2);
+        }
+      }
+      const R nbad = group_sum(sh, g, t, rowok ? R(0) : R(1));
+      if (st == 0 && nbad == R(0)) st = 2;
+    }
+    if (t == 0) sh.flag[g][2] = st;
     __syncthreads();
     bool all = true;
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) all = all && sh.flag[gg][2] != 0;
-    if (all || sw == maxsw) break;
+    if (all || sw == maxsw) {
+      if constexpr (!WANTV) {
+        if (sh.flag[g][2] == 2) {
+          LHF_FOR_ENTRIES {
+            if (r == c) sh.A[g][r][r].x += corr[k];
+          }
+        }
+        __syncthreads();
+      }
+      break;
+    }
 #pragma unroll 1
     for (int s = 0; s < M - 1; ++s) {
       int pi, qi, pj, qj;
@@ -446,6 +498,16 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
   const int blk = cb.y;
   const int cblk = conj_block(L, blk);
   const int64_t base = L.gen_off + (int64_t)blk * m * m;
+  // every global load first (padding entries read entry 0 and discard it;
+  // a spare group reads a valid block)
+  C av[4], bv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = t + k * TPM, r = e / M, c = e % M;
+    const int64_t o = base + (r < m && c < m ? r * m + c : 0);
+    av[k] = Hb[o];
+    bv[k] = Sb[o];
+  }
   if (t < 4) sh.flag[g][t] = 0;
   __syncthreads();
   bool bad = false;
@@ -454,8 +516,8 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
     const int e = t + k * TPM, r = e / M, c = e % M;
     C a = cmk<C>(R(0), R(0)), b = cmk<C>(r == c ? R(1) : R(0), R(0));
     if (valid && r < m && c < m) {
-      a = Hb[base + r * m + c];
-      b = Sb[base + r * m + c];
+      a = av[k];
+      b = bv[k];
       if (!(isfinite(a.x) && isfinite(a.y) && isfinite(b.x) && isfinite(b.y))) {
         bad = true;
         a = cmk<C>(R(0), R(0));
@@ -500,7 +562,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
 // Refinement in FP64 from FP32 eigenvectors U (layout [blk][row][col]).
 // Blocks from H64/S64 (complex128) or regenerated from the FP64 generator band.
 template <int M, bool WANTV>
-__global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev* __restrict__ lats,
+__global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves_per_eu(2))) refine_kernel(const LatDev* __restrict__ lats,
                                                                    const int2* __restrict__ canon, int ncanon,
                                                                    const double2* __restrict__ tw,
                                                                    const double2* __restrict__ H64,
@@ -526,28 +588,52 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
   const int blk = cb.y;
   const int cblk = conj_block(L, blk);
   const int64_t base = L.gen_off + (int64_t)blk * m * m;
+  // every global load of the block first (padding entries read entry 0 and
+  // discard it; a spare group reads a valid block; U of a block whose FP32
+  // solve failed is discarded)
+  C hv[4], sv[4];
+  float2 uv[4];
+  const int32_t st32 = info32[L.blk_off + blk];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = t + k * TPM, r = e / M, c = e % M;
+    const int64_t o = base + (r < m && c < m ? r * m + c : 0);
+    if (H64) {
+      hv[k] = H64[o];
+      sv[k] = S64[o];
+    }
+    uv[k] = U32[o];
+  }
   if (t < 4) sh.flag[g][t] = 0;
-  const bool fresh = !valid || info32[L.blk_off + blk] != 0;
-  const int j3 = blk % L.L[2], j2 = (blk / L.L[2]) % L.L[1], j1 = blk / (L.L[2] * L.L[1]);
+  const bool fresh = !valid || st32 != 0;
   auto cell_of = [&](const DimDev& D, int s) -> int {
     if (D.full) return s;
     const int k = s - D.L0;
     return k < 0 ? k + D.L : k;
   };
-  const int ns1 = L.dim[0].L == 1 ? 1 : L.dim[0].nshift;
-  const int ns2 = L.dim[1].L == 1 ? 1 : L.dim[1].nshift;
-  const int ns3 = L.dim[2].L == 1 ? 1 : L.dim[2].nshift;
-  // band-cell twiddles w^(j.k) of this block (regeneration path)
-  const int ncell = ns1 * ns2 * ns3;
-  // cached in the storage of F, which is free until the refinement's series
+  // regeneration path only (a uniform branch: with complex128 blocks none of
+  // the band descriptors is read, so no load waits behind the block loads)
+  int j1 = 0, j2 = 0, j3 = 0, ns1 = 1, ns2 = 1, ns3 = 1, ncell = 0;
+  bool twl = false;
+  // band-cell twiddles w^(j.k) of this block, cached in the storage of F,
+  // which is free until the refinement's series
   C* twc = &sh.F[g][0][0];
-  const bool twl = ncell <= M * (M + 1);
-  if (!H64 && twl) {
-    for (int q = t; q < ncell; q += TPM) {
-      const int t3 = q % ns3, t2 = (q / ns3) % ns2, t1 = q / (ns3 * ns2);
-      const int k1 = cell_of(L.dim[0], t1), k2 = cell_of(L.dim[1], t2), k3 = cell_of(L.dim[2], t3);
-      C ww = cmul(tw[L.dim[0].tw_off + (j1 * k1) % L.L[0]], tw[L.dim[1].tw_off + (j2 * k2) % L.L[1]]);
-      twc[q] = cmul(ww, tw[L.dim[2].tw_off + (j3 * k3) % L.L[2]]);
+  if (!H64) {
+    j3 = blk % L.L[2];
+    j2 = (blk / L.L[2]) % L.L[1];
+    j1 = blk / (L.L[2] * L.L[1]);
+    ns1 = L.dim[0].L == 1 ? 1 : L.dim[0].nshift;
+    ns2 = L.dim[1].L == 1 ? 1 : L.dim[1].nshift;
+    ns3 = L.dim[2].L == 1 ? 1 : L.dim[2].nshift;
+    ncell = ns1 * ns2 * ns3;
+    twl = ncell <= M * (M + 1);
+    if (twl) {
+      for (int q = t; q < ncell; q += TPM) {
+        const int t3 = q % ns3, t2 = (q / ns3) % ns2, t1 = q / (ns3 * ns2);
+        const int k1 = cell_of(L.dim[0], t1), k2 = cell_of(L.dim[1], t2), k3 = cell_of(L.dim[2], t3);
+        C ww = cmul(tw[L.dim[0].tw_off + (j1 * k1) % L.L[0]], tw[L.dim[1].tw_off + (j2 * k2) % L.L[1]]);
+        twc[q] = cmul(ww, tw[L.dim[2].tw_off + (j3 * k3) % L.L[2]]);
+      }
     }
   }
   __syncthreads();
@@ -557,8 +643,8 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
     C h = cmk<C>(0.0, 0.0), s = cmk<C>(r == c ? 1.0 : 0.0, 0.0), u = cmk<C>(r == c ? 1.0 : 0.0, 0.0);
     if (valid && r < m && c < m) {
       if (H64) {
-        h = H64[base + r * m + c];
-        s = S64[base + r * m + c];
+        h = hv[k];
+        s = sv[k];
       } else {
         // regenerate: sum over band cells k of w^(j.k) A_k
         h = cmk<C>(0.0, 0.0);
@@ -579,10 +665,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) refine_kernel(const LatDev*
           s = cadd(s, cscale(ww, Sg[o]));
         }
       }
-      if (!fresh) {
-        const float2 uf = U32[base + r * m + c];
-        u = cmk<C>((double)uf.x, (double)uf.y);
-      }
+      if (!fresh) u = cmk<C>((double)uv[k].x, (double)uv[k].y);
     }
     sh.A[g][r][c] = h;
     sh.B[g][r][c] = s;
