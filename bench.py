@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a device copy of 512 MiB (the counters' scale), then three "
                          "eager steps of each path; prints nothing else")
+    ap.add_argument("--probe-mfma", action="store_true",
+                    help="for MFMA counter runs: three eager mixed steps with each Gram arithmetic (FP64, FP32, "
+                         "bf16 hi+lo); prints nothing else")
     return ap.parse_args()
 
 
@@ -187,6 +190,17 @@ def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
     torch.cuda.synchronize()
 
 
+def probe_mfma(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
+    """Kernels for an MFMA counter run: three eager steps of the mixed path
+    with each Gram arithmetic (the assembly's MFMA kernels)."""
+    insts = config_c4_lattices() if args.config == "c4" else [make_config(args.config)]
+    for gram, src in ((lhf.LHF_GRAM_FP64, "dual"), (lhf.LHF_GRAM_FP32, "bar64"), (lhf.LHF_GRAM_BF16X3, "bar64")):
+        pipe = Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=gram, refine_src=src)
+        for _ in range(3):
+            pipe.step()
+    torch.cuda.synchronize()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -203,6 +217,9 @@ def main():
     torch.cuda.set_device(0)
     if args.probe_traffic:
         probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices)
+        return
+    if args.probe_mfma:
+        probe_mfma(args, torch, lhf, Pipeline, make_config, config_c4_lattices)
         return
     if args.config == "c4":
         insts = config_c4_lattices()

@@ -11,7 +11,8 @@
 //
 // Grouped launch: one work list covers every lattice, dimension, 64 x 64
 // output tile and split of the window.  A workgroup (4 waves) stages 32-node
-// chunks of both operands in LDS -- the left operand formed from the factors
+// chunks of both operands in LDS (the next chunk's global loads, held in
+// registers, overlap the current chunk's MFMAs) -- the left operand formed from the factors
 // (stencil or potential product), the right one a cyclic window of G, so the
 // shifted copies are never materialised -- and each wave accumulates a
 // 32 x 32 sub-tile with MFMA.  Partial tiles of the splits are summed by a
@@ -48,9 +49,12 @@ template <int MODE>
 __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ lats,
                                                    const GramItem* __restrict__ items, int nitems,
                                                    const double* __restrict__ fac, void* __restrict__ part_) {
+  // one chunk buffer; the global loads of chunk c+1 go to registers and are
+  // in flight while the MFMAs of chunk c run
   __shared__ double As[KC][TILE + 1];
   __shared__ double Bs[KC][TILE + 1];
   typedef typename std::conditional<MODE == 0, d4, f4>::type Acc;
+  constexpr int NV = KC / 4;   // nodes staged per thread and chunk
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GramItem item = items[it];
@@ -82,34 +86,50 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
     }
     const double* Pt = P + (int64_t)(t >= 2 ? t - 2 : 0) * D.npot;
     const double h6 = D.h / 6.0, hinv = 1.0 / D.h;
-    for (int kc0 = k_beg; kc0 < k_end; kc0 += KC) {
+    // raw operand values of one chunk: g0, (g-, g+) or (P, -), and the right operand
+    double x0[NV], x1[NV], x2[NV], y[NV];
+    auto load_chunk = [&](int kc0) {
 #pragma unroll
-      for (int v = 0; v < KC / 4; ++v) {
-        const int kk = kq + 4 * v;
-        const int k = kc0 + kk;
-        double av = 0.0, bv = 0.0;
+      for (int v = 0; v < NV; ++v) {
+        const int k = kc0 + kq + 4 * v;
+        x0[v] = 0.0; x1[v] = 0.0; x2[v] = 0.0; y[v] = 0.0;
         if (k < k_end) {
           int i = D.kstart + k;
           if (i >= D.n) i -= D.n;
           if (rok) {
-            const double g0 = G[(int64_t)i * m0 + nu];
+            x0[v] = G[(int64_t)i * m0 + nu];
             if (t >= 2) {
-              av = Pt[D.replicate ? i % D.nc : i] * g0;
+              x1[v] = Pt[D.replicate ? i % D.nc : i];
             } else {
-              const double gm = gval(G, D, m0, i - 1, nu), gp = gval(G, D, m0, i + 1, nu);
-              av = t == 0 ? h6 * (gm + 4.0 * g0 + gp) : hinv * (2.0 * g0 - gm - gp);
+              x1[v] = gval(G, D, m0, i - 1, nu);
+              x2[v] = gval(G, D, m0, i + 1, nu);
             }
           }
           if (cok) {
             int j = i - sn;
             if (j < 0) j += D.n;
-            bv = G[(int64_t)j * m0 + mu];
+            y[v] = G[(int64_t)j * m0 + mu];
           }
         }
-        As[kk][col] = av;
-        Bs[kk][col] = bv;
       }
-      __syncthreads();
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int kk = kq + 4 * v;
+        As[kk][col] = t >= 2 ? x1[v] * x0[v]
+                          : t == 0 ? h6 * (x1[v] + 4.0 * x0[v] + x2[v]) : hinv * (2.0 * x0[v] - x1[v] - x2[v]);
+        Bs[kk][col] = y[v];
+      }
+    };
+    if (k_beg < k_end) {
+      load_chunk(k_beg);
+      store_chunk();
+    }
+    __syncthreads();
+    for (int kc0 = k_beg; kc0 < k_end; kc0 += KC) {
+      const bool more = kc0 + KC < k_end;
+      if (more) load_chunk(kc0 + KC);
       if constexpr (MODE == 2) {
         bf8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
@@ -145,15 +165,19 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
               const double x = As[kk + lk][wr + a * 16 + lr];
-              const double y = Bs[kk + lk][wc + b * 16 + lr];
+              const double yy = Bs[kk + lk][wc + b * 16 + lr];
               if constexpr (MODE == 0)
-                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, yy, acc[a][b], 0, 0, 0);
               else
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)x, (float)y, acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)x, (float)yy, acc[a][b], 0, 0, 0);
             }
         }
       }
       __syncthreads();
+      if (more) {
+        store_chunk();
+        __syncthreads();
+      }
     }
     // result layout: f64 MFMA row lk + 4 v; f32 / bf16 MFMA row 4 lk + v; column lr
     typedef typename std::conditional<MODE == 0, double, float>::type T;
