@@ -2,10 +2,10 @@
 // (eq. HF-FSpace-Block; union of block spectra, Prop. 5.1 eq. lambdAbc).
 //
 // Per block j (one matrix = (M/2)^2 threads, matrices in LDS):
-//   1. Cholesky  Sbar = C C^H  (right-looking; the factor goes to its own
-//      array so each column costs one barrier);
-//   2. reduction A = C^-1 Hbar C^-H by two forward substitutions (each row's
-//      result goes to a second array: one barrier per row);
+//   1. Gaussian elimination on Sbar (no pivoting; it is Hermitian positive
+//      definite) carrying W = L^-1 along, Sbar = L D L^H, one barrier per
+//      column; the Cholesky factor is C = L D^1/2, so C^-1 = D^-1/2 W;
+//   2. reduction A = C^-1 Hbar C^-H by two register-tiled products;
 //   3. cyclic Jacobi sweeps in the parallel round-robin ordering: in each of
 //      the M-1 rounds of a sweep the M/2 index pairs (p, q) are disjoint and a
 //      thread owns the 2 x 2 block {p_i, q_i} x {p_j, q_j} of pairs (i, j):
@@ -13,8 +13,9 @@
 //      J = [[c, s b/|b|], [-s conj(b)/|b|, c]] (b = A_pq; c, s from the stable
 //      tangent formula), and the columns {p_j, q_j} of rows {p_i, q_i} of V;
 //      sweeps stop when the off-diagonal Frobenius norm is below 4 M eps of
-//      the norm of A;
-//   4. eigenvalues sorted ascending, eigenvectors C^-H V.
+//      the norm of A (eigenvalues only: or earlier, when a second-order
+//      closure is within that bound);
+//   4. eigenvalues sorted ascending, eigenvectors C^-H V = W^H D^-1/2 V.
 // Blocks j and -j are complex conjugates (real symmetric generators): only
 // the canonical block of each pair is solved and its results are written for
 // both.  The plan lists the canonical (lattice, block) pairs of every lattice
@@ -23,8 +24,9 @@
 // Refinement (mixed precision): the FP32 solve leaves eigenvectors U; in FP64
 // the block pair is rebuilt accurately (from complex128 Fourier blocks, or
 // regenerated from the FP64 generator band) and the Rayleigh-Ritz pair
-// (U^H Hbar U, U^H Sbar U) -- nearly diagonal -- goes through the same FP64
-// steps, which converge in one or two sweeps.  If the FP32 solve failed for a
+// (U^H Hbar U, U^H Sbar U) -- nearly diagonal -- is reduced with the series
+// (I + E)^-1/2 of the overlap and goes through the FP64 sweeps, which stop
+// after one sweep or none.  If the FP32 solve failed for a
 // block, U = I and the FP64 solve does the whole work.
 //
 // Sizes: M in {4, 8, 16, 32} >= m0; padded rows/columns are decoupled (unit
@@ -87,6 +89,7 @@ struct Smem {
   R jc[G][M / 2];                // rotation cosine per pair
   C js[G][M / 2];                // s b / |b| per pair
   R dn[G][M];                    // rotated diagonal
+  R dsc[G][M];                   // D^-1/2 of the overlap's L D L^H
   int rank[G][M];
   int flag[G][4];                // 0: Cholesky failure column, 1: non-finite, 2: converged
 };
@@ -207,51 +210,114 @@ __device__ __forceinline__ void store_tile(C (&Z)[M][M + 1], int ti, int tj, con
     for (int b = 0; b < 2; ++b) Z[ti + a * H][tj + b * H] = p[a][b];
 }
 
-// 1-2. Cholesky of B into F (B is overwritten), A <- F^-1 A F^-H (Hermitian);
-// V <- I when HASV.
+// P = X Y^H
+template <int M, typename C>
+__device__ __forceinline__ void mm_tile_rh(const C (&X)[M][M + 1], const C (&Y)[M][M + 1], int ti, int tj,
+                                           C (&p)[2][2]) {
+  constexpr int H = M / 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) p[a][b] = cmk<C>(0, 0);
+#pragma unroll Tile<M>::UR
+  for (int q = 0; q < M; ++q) {
+    const C y0 = Y[tj][q], y1 = Y[tj + H][q];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const C x = X[ti + a * H][q];
+      p[a][0] = cadd(p[a][0], cmk<C>(x.x * y0.x + x.y * y0.y, x.y * y0.x - x.x * y0.y));
+      p[a][1] = cadd(p[a][1], cmk<C>(x.x * y1.x + x.y * y1.y, x.y * y1.x - x.x * y1.y));
+    }
+  }
+}
+
+// P = X^H diag(d) Y
+template <int M, typename C, typename R>
+__device__ __forceinline__ void mm_tile_lh_diag(const C (&X)[M][M + 1], const R (&d)[M], const C (&Y)[M][M + 1],
+                                                int ti, int tj, C (&p)[2][2]) {
+  constexpr int H = M / 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) p[a][b] = cmk<C>(0, 0);
+#pragma unroll Tile<M>::UR
+  for (int q = 0; q < M; ++q) {
+    const R dq = d[q];
+    const C y0 = cscale(Y[q][tj], dq), y1 = cscale(Y[q][tj + H], dq);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const C x = X[q][ti + a * H];
+      p[a][0] = cadd(p[a][0], cmulc(x, y0));
+      p[a][1] = cadd(p[a][1], cmulc(x, y1));
+    }
+  }
+}
+
+// 1-2. Reduction to standard form.  Gaussian elimination without pivoting on
+// the overlap B (Hermitian positive definite: the pivots are those of its
+// L D L^H factorisation), applying the same row operations to W = I, leaves
+// W = L^-1 (unit lower triangular, in F) and D on the diagonal of B; with the
+// Cholesky factor C = L D^1/2, C^-1 = D^-1/2 W (D^-1/2 in dsc), and
+// A <- C^-1 A C^-H = D^-1/2 (W A W^H) D^-1/2 by two tiled products, made
+// Hermitian.  One barrier per column; V <- I when HASV.  A non-positive
+// pivot j is reported as j + 1 in flag 0.
 template <typename R, int M, int G, bool HASU, bool HASV>
 __device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
   typedef typename Cx<R>::T C;
   constexpr int TPM = (M / 2) * (M / 2);
+  LHF_FOR_ENTRIES { sh.F[g][r][c] = cmk<C>(r == c ? R(1) : R(0), R(0)); }
+  __syncthreads();
 #pragma unroll 1
-  for (int j = 0; j < M; ++j) {
+  for (int j = 0; j < M - 1; ++j) {
     const R d = sh.B[g][j][j].x;
     const bool ok = d > R(0);
-    const R rp = ok ? rsq_(d) : R(1);    // 1 / pivot
-    const R piv = ok ? d * rp : R(1);
-    const R dinv = ok ? rp * rp : R(1);
+    const R dinv = ok ? rcp_(d) : R(1);
     if (t == 0 && !ok && sh.flag[g][0] == 0) sh.flag[g][0] = j + 1;
+    C xv[4], wv[4];
     LHF_FOR_ENTRIES {
-      if (c == j && r >= j) sh.F[g][r][j] = r == j ? cmk<C>(piv, R(0)) : cscale(sh.B[g][r][j], rp);
-      else if (c > j && r >= c)
-        sh.B[g][r][c] = csub(sh.B[g][r][c], cscale(cmulc(sh.B[g][c][j], sh.B[g][r][j]), dinv));
-    }
-    __syncthreads();
-  }
-#pragma unroll 1
-  for (int pass = 0; pass < 2; ++pass) {
-#pragma unroll 1
-    for (int j = 0; j < M; ++j) {
-      const R fj = rcp_(sh.F[g][j][j].x);
-      LHF_FOR_ENTRIES {
-        if (r == j) sh.B[g][j][c] = cscale(sh.A[g][j][c], fj);
-        else if (r > j) sh.A[g][r][c] = csub(sh.A[g][r][c], cmul(cscale(sh.F[g][r][j], fj), sh.A[g][j][c]));
+      xv[k] = sh.B[g][r][c];
+      wv[k] = sh.F[g][r][c];
+      if (r > j) {
+        const C f = cscale(sh.B[g][r][j], dinv);
+        if (c > j) xv[k] = csub(xv[k], cmul(f, sh.B[g][j][c]));
+        else wv[k] = csub(wv[k], cmul(f, sh.F[g][j][c]));
       }
-      __syncthreads();
     }
     LHF_FOR_ENTRIES {
-      if (pass == 0) {
-        sh.A[g][r][c] = cconj(sh.B[g][c][r]);
-      } else {
-        const C x = sh.B[g][r][c], y = sh.B[g][c][r];
-        C s = cmk<C>(R(0.5) * (x.x + y.x), R(0.5) * (x.y - y.y));
-        if (r == c) s.y = R(0);
-        sh.A[g][r][c] = s;
-        if constexpr (HASV) sh.V[g][r][c] = cmk<C>(r == c ? R(1) : R(0), R(0));
+      if (r > j) {
+        if (c > j) sh.B[g][r][c] = xv[k];
+        else sh.F[g][r][c] = wv[k];
       }
     }
     __syncthreads();
   }
+  if (t < M) {
+    const R d = sh.B[g][t][t].x;
+    sh.dsc[g][t] = d > R(0) ? rsq_(d) : R(1);
+    if (t == M - 1 && !(d > R(0)) && sh.flag[g][0] == 0) sh.flag[g][0] = M;
+  }
+  const int ti = t / (M / 2), tj = t % (M / 2);
+  C p[2][2];
+  mm_tile_rh<M>(sh.A[g], sh.F[g], ti, tj, p);   // T = A W^H
+  __syncthreads();
+  store_tile<M>(sh.A[g], ti, tj, p);
+  __syncthreads();
+  mm_tile<M, false>(sh.F[g], sh.A[g], ti, tj, R(0), p);   // W T, scaled by D^-1/2 on both sides
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      p[a][b] = cscale(p[a][b], sh.dsc[g][ti + a * (M / 2)] * sh.dsc[g][tj + b * (M / 2)]);
+  store_tile<M>(sh.B[g], ti, tj, p);
+  __syncthreads();
+  LHF_FOR_ENTRIES {
+    const C x = sh.B[g][r][c], y = sh.B[g][c][r];
+    C s = cmk<C>(R(0.5) * (x.x + y.x), R(0.5) * (x.y - y.y));
+    if (r == c) s.y = R(0);
+    sh.A[g][r][c] = s;
+    if constexpr (HASV) sh.V[g][r][c] = cmk<C>(r == c ? R(1) : R(0), R(0));
+  }
+  __syncthreads();
 }
 
 // Jacobi rotation of the Hermitian 2 x 2 block [[app, b], [conj b, aqq]]:
@@ -453,19 +519,15 @@ __device__ void eig_rank(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int m, int
   __syncthreads();
 }
 
-// Eigenvectors F^-H V into A (back substitution, one barrier per row).
+// Eigenvectors C^-H V = W^H D^-1/2 V into A (one tiled product).
 template <typename R, int M, int G, bool HASU, bool HASV>
 __device__ void backsub_vectors(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
-  constexpr int TPM = (M / 2) * (M / 2);
-#pragma unroll 1
-  for (int j = M - 1; j >= 0; --j) {
-    const R fj = rcp_(sh.F[g][j][j].x);
-    LHF_FOR_ENTRIES {
-      if (r == j) sh.A[g][j][c] = cscale(sh.V[g][j][c], fj);
-      else if (r < j) sh.V[g][r][c] = csub(sh.V[g][r][c], cmulc(cscale(sh.F[g][j][r], fj), sh.V[g][j][c]));
-    }
-    __syncthreads();
-  }
+  typedef typename Cx<R>::T C;
+  const int ti = t / (M / 2), tj = t % (M / 2);
+  C p[2][2];
+  mm_tile_lh_diag<M>(sh.F[g], sh.dsc[g], sh.V[g], ti, tj, p);
+  store_tile<M>(sh.A[g], ti, tj, p);
+  __syncthreads();
 }
 
 template <int M>
