@@ -228,8 +228,9 @@ __device__ __forceinline__ int find_fused(const FusedTask* __restrict__ t, int n
 //   stage 3: Y[j1][j2][j3][e] = sum_s1 w1^(j1 k1) T2[s1][j2][e]      (every j1)
 // The intermediates stay in LDS; every Fourier block entry is written once,
 // in segments of EC consecutive entries.  In stage 3 a thread owns one
-// (j2, e) column with its B1 inputs in registers and walks j1 with
-// incrementally updated twiddle indices.
+// (j2, e) column with its B1 inputs in registers and walks groups of R1
+// outputs j1 (radix-R1 output symmetry) with incrementally updated twiddle
+// indices.
 template <typename R, int BM>
 __global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict__ lats,
                                                         const FusedTask* __restrict__ tasks, int ntasks,
@@ -248,7 +249,9 @@ __global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict
   const DimDev& D2 = L.dim[2];
   const int L1 = L.L[0], L2 = L.L[1], L3 = L.L[2];
   const int B1 = nslot(D0), B2 = nslot(D1), B3 = nslot(D2);
-  const int E = L.m0 * L.m0, EC = T.EC, J2C = T.J2C;
+  constexpr int EC = kFusedEC;   // the planner's entry chunk
+  constexpr int PS = 256 / EC;     // (s1, s2) or (s1, j2) rows per pass of the workgroup
+  const int E = L.m0 * L.m0, J2C = T.J2C;
   int64_t loc = wg - T.wg_base;
   const int eci = (int)(loc % T.nec);
   loc /= T.nec;
@@ -266,57 +269,80 @@ __global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict
   for (int q = tid; q < j2n * B2; q += 256) {
     const int jj = q / B2, s2 = q % B2;
     const int k2 = slot_cell(D1, s2);
-    tw2[jj * B2 + s2] = tw[D1.tw_off + (int)(((int64_t)(j2lo + jj) * k2) % L2)];
+    tw2[jj * B2 + s2] = tw[D1.tw_off + ((j2lo + jj) * k2) % L2];
   }
-  for (int q = tid; q < B3; q += 256) tw3[q] = tw[D2.tw_off + (int)(((int64_t)j3 * slot_cell(D2, q)) % L3)];
+  for (int q = tid; q < B3; q += 256) tw3[q] = tw[D2.tw_off + (j3 * slot_cell(D2, q)) % L3];
   __syncthreads();
   const R* X = (blockIdx.y == 0 ? genH : genS) + L.gen_off;
-  // stage 1
-  for (int it = tid; it < B1 * B2 * EC; it += 256) {
-    const int ec = it % EC, s12 = it / EC, s2 = s12 % B2, s1 = s12 / B2;
-    R re = 0, im = 0;
-    if (ec < ecn) {
-      const int k1 = slot_cell(D0, s1), k2 = slot_cell(D1, s2);
-      const R* xp = X + ((int64_t)(k1 * L2 + k2) * L3) * E + e0 + ec;
-      // all band loads first (unrolled to the band bound), then the sums
-      R xv[BM];
+  // stage 1: a thread keeps entry ec = tid mod EC and steps its (s1, s2)
+  // row by PS (no divisions in the loop)
+  const int ec = tid & (EC - 1);
+  {
+    int s1 = (tid / EC) / B2, s2 = (tid / EC) % B2;
+    const int d1 = PS / B2, d2 = PS % B2;
+    for (int row = tid / EC; row < B1 * B2; row += PS) {
+      R re = 0, im = 0;
+      if (ec < ecn) {
+        const int k1 = slot_cell(D0, s1), k2 = slot_cell(D1, s2);
+        const R* xp = X + ((int64_t)(k1 * L2 + k2) * L3) * E + e0 + ec;
+        // all band loads first (unrolled to the band bound), then the sums
+        R xv[BM];
 #pragma unroll
-      for (int s3 = 0; s3 < BM; ++s3) xv[s3] = s3 < B3 ? xp[(int64_t)slot_cell(D2, s3) * E] : R(0);
+        for (int s3 = 0; s3 < BM; ++s3) xv[s3] = s3 < B3 ? xp[(int64_t)slot_cell(D2, s3) * E] : R(0);
 #pragma unroll
-      for (int s3 = 0; s3 < BM; ++s3) {
-        if (s3 < B3) {
-          const C w = tw3[s3];
-          re += w.x * xv[s3];
-          im += w.y * xv[s3];
+        for (int s3 = 0; s3 < BM; ++s3) {
+          if (s3 < B3) {
+            const C w = tw3[s3];
+            re += w.x * xv[s3];
+            im += w.y * xv[s3];
+          }
         }
       }
+      C v;
+      v.x = re;
+      v.y = im;
+      T1[row * EC + ec] = v;
+      s2 += d2;
+      s1 += d1;
+      if (s2 >= B2) { s2 -= B2; ++s1; }
     }
-    C v;
-    v.x = re;
-    v.y = im;
-    T1[it] = v;
   }
   __syncthreads();
-  // stage 2
-  for (int it = tid; it < B1 * j2n * EC; it += 256) {
-    const int ec = it % EC, r = it / EC, jj = r % j2n, s1 = r / j2n;
-    R re = 0, im = 0;
-    for (int s2 = 0; s2 < B2; ++s2) {
-      const C w = tw2[jj * B2 + s2], x = T1[(s1 * B2 + s2) * EC + ec];
-      re += w.x * x.x - w.y * x.y;
-      im += w.x * x.y + w.y * x.x;
+  // stage 2: rows (s1, jj) stepped the same way
+  {
+    int s1 = (tid / EC) / j2n, jj = (tid / EC) % j2n;
+    const int d1 = PS / j2n, d2 = PS % j2n;
+    for (int row = tid / EC; row < B1 * j2n; row += PS) {
+      R re = 0, im = 0;
+      const C* wp = tw2 + jj * B2;
+      const C* xp = T1 + s1 * B2 * EC + ec;
+      for (int s2 = 0; s2 < B2; ++s2) {
+        const C w = wp[s2], x = xp[s2 * EC];
+        re += w.x * x.x - w.y * x.y;
+        im += w.x * x.y + w.y * x.x;
+      }
+      C v;
+      v.x = re;
+      v.y = im;
+      T2[(s1 * J2C + jj) * EC + ec] = v;
+      jj += d2;
+      s1 += d1;
+      if (jj >= j2n) { jj -= j2n; ++s1; }
     }
-    C v;
-    v.x = re;
-    v.y = im;
-    T2[(s1 * J2C + jj) * EC + ec] = v;
   }
   __syncthreads();
-  // stage 3
+  // stage 3: the outputs j1 = j + q Q (q < R1, Q = L1 / R1, R1 = 4, 2 or 1
+  // as L1 allows) share the twiddles w1^(j k1) up to zeta^(q k1), zeta =
+  // w1^Q = +-i or -1.  The inputs are summed by slot residue a = s1 mod 4
+  // (k1 = s1 + off mod R1), and Y_q = zeta^(q off) sum_a zeta^(q a) S_a: one
+  // complex multiply-add per input for R1 outputs.
   const int ncol = J2C * EC, nrep = 256 / ncol;
   const int col = tid % ncol, rep = tid / ncol;
-  const int jj = col / EC, ec = col % EC;
+  const int jj = col / EC;
   if (rep >= nrep || jj >= j2n || ec >= ecn) return;
+  const int R1 = (L1 & 3) == 0 ? 4 : (L1 & 1) == 0 ? 2 : 1;
+  const int Q = L1 / R1;
+  const int off = slot_cell(D0, 0) % R1;
   R xr[BM], xi[BM];
   int idx[BM], stp[BM];
 #pragma unroll
@@ -326,31 +352,61 @@ __global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict
       xr[s1] = x.x;
       xi[s1] = x.y;
       const int k1 = slot_cell(D0, s1);
-      idx[s1] = (int)(((int64_t)rep * k1) % L1);
-      stp[s1] = (int)(((int64_t)nrep * k1) % L1);
+      idx[s1] = (rep * k1) % L1;
+      stp[s1] = (nrep * k1) % L1;
     }
   }
   const int64_t yoff = L.gen_off + ((int64_t)(j2lo + jj) * L3 + j3) * E + e0 + ec;
   C* Y = (blockIdx.y == 0 ? barH : barS) + yoff;
   float2* Y32 = b32H ? (blockIdx.y == 0 ? b32H : b32S) + yoff : nullptr;
   const int64_t jstride = (int64_t)L2 * L3 * E;
-  for (int j1 = rep; j1 < L1; j1 += nrep) {
-    R re = 0, im = 0;
+  const R zs = tw1[Q % L1].y < R(0) ? R(-1) : R(1);   // zeta = zs i when R1 = 4
+  // output j1 = j + q Q sits (j1 - j) jstride past the base output j
+  const int64_t ystep = (int64_t)nrep * jstride, qstep = (int64_t)Q * jstride;
+  int64_t ybase = (int64_t)rep * jstride;
+  auto put = [&](int q, R re, R im) {
+    C v;
+    v.x = re;
+    v.y = im;
+    const int64_t o = ybase + q * qstep;
+    Y[o] = v;
+    if (Y32) Y32[o] = make_float2((float)re, (float)im);
+  };
+  for (int j = rep; j < Q; j += nrep, ybase += ystep) {
+    R sr[4] = {R(0), R(0), R(0), R(0)}, si[4] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
     for (int s1 = 0; s1 < BM; ++s1) {
       if (s1 < B1) {
         const C w = tw1[idx[s1]];
-        re += w.x * xr[s1] - w.y * xi[s1];
-        im += w.x * xi[s1] + w.y * xr[s1];
+        sr[s1 & 3] += w.x * xr[s1] - w.y * xi[s1];
+        si[s1 & 3] += w.x * xi[s1] + w.y * xr[s1];
         idx[s1] += stp[s1];
         if (idx[s1] >= L1) idx[s1] -= L1;
       }
     }
-    C v;
-    v.x = re;
-    v.y = im;
-    Y[(int64_t)j1 * jstride] = v;
-    if (Y32) Y32[(int64_t)j1 * jstride] = make_float2((float)re, (float)im);
+    if (R1 == 4) {
+      // U_q = sum_a zeta^(q a) S_a; zeta (x + i y) = zs (-y + i x); Y_q = zeta^(q off) U_q
+      const R ar = sr[0] + sr[2], ai = si[0] + si[2], br = sr[0] - sr[2], bi = si[0] - si[2];
+      const R cr = sr[1] + sr[3], ci = si[1] + si[3], dr = sr[1] - sr[3], di = si[1] - si[3];
+      auto rot = [&](int q, R yr, R yi) {
+        const int m = (q * off) & 3;
+        if (m == 1) { const R tr = -zs * yi; yi = zs * yr; yr = tr; }
+        else if (m == 2) { yr = -yr; yi = -yi; }
+        else if (m == 3) { const R tr = zs * yi; yi = -zs * yr; yr = tr; }
+        put(q, yr, yi);
+      };
+      rot(0, ar + cr, ai + ci);
+      rot(1, br - zs * di, bi + zs * dr);
+      rot(2, ar - cr, ai - ci);
+      rot(3, br + zs * di, bi - zs * dr);
+    } else if (R1 == 2) {
+      const R er = sr[0] + sr[2], ei = si[0] + si[2], orr = sr[1] + sr[3], oi = si[1] + si[3];
+      put(0, er + orr, ei + oi);
+      const R sg = (off & 1) ? R(-1) : R(1);
+      put(1, sg * (er - orr), sg * (ei - oi));
+    } else {
+      put(0, sr[0] + sr[1] + sr[2] + sr[3], si[0] + si[1] + si[2] + si[3]);
+    }
   }
 }
 

@@ -53,6 +53,8 @@ TINY = [
     dict(L=(7, 1, 1), n=(70, 12, 12), n_s=5, n_p=0, seed=107),                   # m0 = 5 (padded to 8), ragged K
     dict(L=(9, 2, 1), n=(90, 18, 12), n_s=3, n_p=4, seed=108, R=6),              # m0 = 15 (padded to 16)
     dict(L=(4, 1, 1), n=(32, 12, 12), n_s=8, n_p=8, seed=109, R=4),              # m0 = 32
+    dict(L=(6, 3, 1), n=(48, 24, 12), n_s=2, n_p=0, seed=110),                   # 2D, L1 = 2 mod 4
+    dict(L=(12, 2, 2), n=(96, 16, 16), n_s=3, n_p=0, seed=111, exp_range=(0.8, 3.0)),  # 3D, banded L1 = 0 mod 4
 ]
 
 
