@@ -365,14 +365,20 @@ int32_t lhf_graph_destroy(lhf_graph_t graph);
  *   gram_grid    workgroups of the persistent grouped Gram launch;
  *   tol32_scale  mixed plans: multiplier of the FP32 Jacobi stopping
  *                tolerance (the FP64 refinement converges to the same
- *                tolerance whatever the FP32 schedule).
+ *                tolerance whatever the FP32 schedule);
+ *   heev_wide    bit c (size class M = 4 << c): the eigensolver runs one
+ *                matrix entry per thread instead of four (for batches too
+ *                small to fill the device); 0..15, the planner sets the
+ *                classes whose four-entry launch has fewer wavefronts than
+ *                the device has SIMDs.
  * None of them changes what is computed; the Gram split changes the order of
- * the FP64 partial sums. */
+ * the FP64 partial sums and the eigensolver layout the order of its sums. */
 typedef struct {
   int32_t dft_threads;
   int32_t gram_split;
   int32_t gram_grid;
   int32_t tol32_scale;
+  int32_t heev_wide;
   double step_ms;        /* autotune: mean time of one step with these settings */
   int32_t from_cache;    /* autotune: 1 when read from the cache file         */
 } lhf_tuning;

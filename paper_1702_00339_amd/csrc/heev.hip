@@ -84,7 +84,7 @@ struct Smem {
   C F[G][M][M + 1];              // Cholesky factor
   C V[HASV ? G : 1][HASV ? M : 1][M + 1];
   C U[HASU ? G : 1][HASU ? M : 1][M + 1];
-  R red[G][4];                   // cross-wave partial sums
+  R red[G][16];                  // cross-wave partial sums
   R lam[G][M];
   R jc[G][M / 2];                // rotation cosine per pair
   C js[G][M / 2];                // s b / |b| per pair
@@ -94,10 +94,11 @@ struct Smem {
   int flag[G][4];                // 0: Cholesky failure column, 1: non-finite, 2: converged
 };
 
-// Sum over the TPM threads of one matrix; all threads of the workgroup call it.
-template <typename R, int M, int G, bool HASU, bool HASV>
+// Sum over the TPM = M^2 / W threads of one matrix (W entries per thread);
+// all threads of the workgroup call it.
+template <int W, typename R, int M, int G, bool HASU, bool HASV>
 __device__ __forceinline__ R group_sum(Smem<R, M, G, HASU, HASV>& sh, int g, int t, R v) {
-  constexpr int TPM = (M / 2) * (M / 2);
+  constexpr int TPM = M * M / W;
   if constexpr (TPM <= 64) {
 #pragma unroll
     for (int o = TPM / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -115,140 +116,165 @@ __device__ __forceinline__ R group_sum(Smem<R, M, G, HASU, HASV>& sh, int g, int
   }
 }
 
-// Entries owned by thread t of a matrix in the O(M^3) phases: t + k TPM, k < 4.
+// Entries owned by thread t of a matrix in the elementwise phases:
+// t + k TPM, k < W (W = 4 entries per thread, or 1 in the wide layout).
 #define LHF_FOR_ENTRIES                                   \
-  _Pragma("unroll") for (int k = 0; k < 4; ++k)           \
+  _Pragma("unroll") for (int k = 0; k < W; ++k)           \
     if (const int e = t + k * TPM, r = e / M, c = e % M; true)
 
-// Register-tiled products of the refinement: thread t of a matrix owns the
-// 2 x 2 tile of rows {ti, ti + M/2} and columns {tj, tj + M/2},
-// ti = t / (M/2), tj = t % (M/2); every operand entry loaded from LDS feeds
-// two products (four when two products share an operand).
+// Register-tiled products: thread t of a matrix owns the NT x NT tile of
+// rows {ti + a S} and columns {tj + b S}, S = M / NT, ti = t / S, tj = t % S
+// (NT = 2 with four entries per thread, where every operand entry loaded
+// from LDS feeds two products, four when two products share an operand;
+// NT = 1 in the wide layout).
 template <int M> struct Tile {
-  static constexpr int H = M / 2;
   static constexpr int UR = M <= 8 ? M : 4;   // q-loop unroll
 };
+template <int W> struct TileOf {
+  static constexpr int NT = W == 4 ? 2 : 1;
+};
+template <int M, int NT>
+__device__ __forceinline__ void tile_coords(int t, int& ti, int& tj) {
+  ti = t / (M / NT);
+  tj = t % (M / NT);
+}
 
 // P1 = X1 Y, P2 = X2 Y
-template <int M, typename C>
+template <int M, int NT, typename C>
 __device__ __forceinline__ void mm_shared_right(const C (&X1)[M][M + 1], const C (&X2)[M][M + 1],
-                                                const C (&Y)[M][M + 1], int ti, int tj, C (&p1)[2][2],
-                                                C (&p2)[2][2]) {
-  constexpr int H = M / 2;
+                                                const C (&Y)[M][M + 1], int ti, int tj, C (&p1)[NT][NT],
+                                                C (&p2)[NT][NT]) {
+  constexpr int S = M / NT;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) { p1[a][b] = cmk<C>(0, 0); p2[a][b] = cmk<C>(0, 0); }
+    for (int b = 0; b < NT; ++b) { p1[a][b] = cmk<C>(0, 0); p2[a][b] = cmk<C>(0, 0); }
 #pragma unroll Tile<M>::UR
   for (int q = 0; q < M; ++q) {
-    const C y0 = Y[q][tj], y1 = Y[q][tj + H];
+    C y[NT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const C x1 = X1[ti + a * H][q], x2 = X2[ti + a * H][q];
-      p1[a][0] = cadd(p1[a][0], cmul(x1, y0));
-      p1[a][1] = cadd(p1[a][1], cmul(x1, y1));
-      p2[a][0] = cadd(p2[a][0], cmul(x2, y0));
-      p2[a][1] = cadd(p2[a][1], cmul(x2, y1));
+    for (int b = 0; b < NT; ++b) y[b] = Y[q][tj + b * S];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const C x1 = X1[ti + a * S][q], x2 = X2[ti + a * S][q];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) {
+        p1[a][b] = cadd(p1[a][b], cmul(x1, y[b]));
+        p2[a][b] = cadd(p2[a][b], cmul(x2, y[b]));
+      }
     }
   }
 }
 
 // P1 = X^H Y1, P2 = X^H Y2
-template <int M, typename C>
+template <int M, int NT, typename C>
 __device__ __forceinline__ void mm_shared_left_h(const C (&X)[M][M + 1], const C (&Y1)[M][M + 1],
-                                                 const C (&Y2)[M][M + 1], int ti, int tj, C (&p1)[2][2],
-                                                 C (&p2)[2][2]) {
-  constexpr int H = M / 2;
+                                                 const C (&Y2)[M][M + 1], int ti, int tj, C (&p1)[NT][NT],
+                                                 C (&p2)[NT][NT]) {
+  constexpr int S = M / NT;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) { p1[a][b] = cmk<C>(0, 0); p2[a][b] = cmk<C>(0, 0); }
+    for (int b = 0; b < NT; ++b) { p1[a][b] = cmk<C>(0, 0); p2[a][b] = cmk<C>(0, 0); }
 #pragma unroll Tile<M>::UR
   for (int q = 0; q < M; ++q) {
-    const C x0 = X[q][ti], x1 = X[q][ti + H];
+    C x[NT];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const C y1 = Y1[q][tj + b * H], y2 = Y2[q][tj + b * H];
-      p1[0][b] = cadd(p1[0][b], cmulc(x0, y1));
-      p1[1][b] = cadd(p1[1][b], cmulc(x1, y1));
-      p2[0][b] = cadd(p2[0][b], cmulc(x0, y2));
-      p2[1][b] = cadd(p2[1][b], cmulc(x1, y2));
+    for (int a = 0; a < NT; ++a) x[a] = X[q][ti + a * S];
+#pragma unroll
+    for (int b = 0; b < NT; ++b) {
+      const C y1 = Y1[q][tj + b * S], y2 = Y2[q][tj + b * S];
+#pragma unroll
+      for (int a = 0; a < NT; ++a) {
+        p1[a][b] = cadd(p1[a][b], cmulc(x[a], y1));
+        p2[a][b] = cadd(p2[a][b], cmulc(x[a], y2));
+      }
     }
   }
 }
 
 // P = X Y (+ d I when ADDI)
-template <int M, bool ADDI, typename C, typename R>
+template <int M, int NT, bool ADDI, typename C, typename R>
 __device__ __forceinline__ void mm_tile(const C (&X)[M][M + 1], const C (&Y)[M][M + 1], int ti, int tj, R d,
-                                        C (&p)[2][2]) {
-  constexpr int H = M / 2;
+                                        C (&p)[NT][NT]) {
+  constexpr int S = M / NT;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) p[a][b] = cmk<C>(0, 0);
+    for (int b = 0; b < NT; ++b) p[a][b] = cmk<C>(0, 0);
 #pragma unroll Tile<M>::UR
   for (int q = 0; q < M; ++q) {
-    const C y0 = Y[q][tj], y1 = Y[q][tj + H];
+    C y[NT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const C x = X[ti + a * H][q];
-      p[a][0] = cadd(p[a][0], cmul(x, y0));
-      p[a][1] = cadd(p[a][1], cmul(x, y1));
+    for (int b = 0; b < NT; ++b) y[b] = Y[q][tj + b * S];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const C x = X[ti + a * S][q];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) p[a][b] = cadd(p[a][b], cmul(x, y[b]));
     }
   }
   if constexpr (ADDI) {
-    if (ti == tj) { p[0][0].x += d; p[1][1].x += d; }
+    if (ti == tj) {
+#pragma unroll
+      for (int a = 0; a < NT; ++a) p[a][a].x += d;
+    }
   }
 }
 
-template <int M, typename C>
-__device__ __forceinline__ void store_tile(C (&Z)[M][M + 1], int ti, int tj, const C (&p)[2][2]) {
-  constexpr int H = M / 2;
+template <int M, int NT, typename C>
+__device__ __forceinline__ void store_tile(C (&Z)[M][M + 1], int ti, int tj, const C (&p)[NT][NT]) {
+  constexpr int S = M / NT;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) Z[ti + a * H][tj + b * H] = p[a][b];
+    for (int b = 0; b < NT; ++b) Z[ti + a * S][tj + b * S] = p[a][b];
 }
 
 // P = X Y^H
-template <int M, typename C>
+template <int M, int NT, typename C>
 __device__ __forceinline__ void mm_tile_rh(const C (&X)[M][M + 1], const C (&Y)[M][M + 1], int ti, int tj,
-                                           C (&p)[2][2]) {
-  constexpr int H = M / 2;
+                                           C (&p)[NT][NT]) {
+  constexpr int S = M / NT;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) p[a][b] = cmk<C>(0, 0);
+    for (int b = 0; b < NT; ++b) p[a][b] = cmk<C>(0, 0);
 #pragma unroll Tile<M>::UR
   for (int q = 0; q < M; ++q) {
-    const C y0 = Y[tj][q], y1 = Y[tj + H][q];
+    C y[NT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const C x = X[ti + a * H][q];
-      p[a][0] = cadd(p[a][0], cmk<C>(x.x * y0.x + x.y * y0.y, x.y * y0.x - x.x * y0.y));
-      p[a][1] = cadd(p[a][1], cmk<C>(x.x * y1.x + x.y * y1.y, x.y * y1.x - x.x * y1.y));
+    for (int b = 0; b < NT; ++b) y[b] = Y[tj + b * S][q];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const C x = X[ti + a * S][q];
+#pragma unroll
+      for (int b = 0; b < NT; ++b)
+        p[a][b] = cadd(p[a][b], cmk<C>(x.x * y[b].x + x.y * y[b].y, x.y * y[b].x - x.x * y[b].y));
     }
   }
 }
 
 // P = X^H diag(d) Y
-template <int M, typename C, typename R>
+template <int M, int NT, typename C, typename R>
 __device__ __forceinline__ void mm_tile_lh_diag(const C (&X)[M][M + 1], const R (&d)[M], const C (&Y)[M][M + 1],
-                                                int ti, int tj, C (&p)[2][2]) {
-  constexpr int H = M / 2;
+                                                int ti, int tj, C (&p)[NT][NT]) {
+  constexpr int S = M / NT;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) p[a][b] = cmk<C>(0, 0);
+    for (int b = 0; b < NT; ++b) p[a][b] = cmk<C>(0, 0);
 #pragma unroll Tile<M>::UR
   for (int q = 0; q < M; ++q) {
     const R dq = d[q];
-    const C y0 = cscale(Y[q][tj], dq), y1 = cscale(Y[q][tj + H], dq);
+    C y[NT];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const C x = X[q][ti + a * H];
-      p[a][0] = cadd(p[a][0], cmulc(x, y0));
-      p[a][1] = cadd(p[a][1], cmulc(x, y1));
+    for (int b = 0; b < NT; ++b) y[b] = cscale(Y[q][tj + b * S], dq);
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const C x = X[q][ti + a * S];
+#pragma unroll
+      for (int b = 0; b < NT; ++b) p[a][b] = cadd(p[a][b], cmulc(x, y[b]));
     }
   }
 }
@@ -261,10 +287,10 @@ __device__ __forceinline__ void mm_tile_lh_diag(const C (&X)[M][M + 1], const R 
 // A <- C^-1 A C^-H = D^-1/2 (W A W^H) D^-1/2 by two tiled products, made
 // Hermitian.  One barrier per column; V <- I when HASV.  A non-positive
 // pivot j is reported as j + 1 in flag 0.
-template <typename R, int M, int G, bool HASU, bool HASV>
+template <int W, typename R, int M, int G, bool HASU, bool HASV>
 __device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
   typedef typename Cx<R>::T C;
-  constexpr int TPM = (M / 2) * (M / 2);
+  constexpr int TPM = M * M / W, NT = TileOf<W>::NT, S = M / NT;
   LHF_FOR_ENTRIES { sh.F[g][r][c] = cmk<C>(r == c ? R(1) : R(0), R(0)); }
   __syncthreads();
 #pragma unroll 1
@@ -273,7 +299,7 @@ __device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
     const bool ok = d > R(0);
     const R dinv = ok ? rcp_(d) : R(1);
     if (t == 0 && !ok && sh.flag[g][0] == 0) sh.flag[g][0] = j + 1;
-    C xv[4], wv[4];
+    C xv[W], wv[W];
     LHF_FOR_ENTRIES {
       xv[k] = sh.B[g][r][c];
       wv[k] = sh.F[g][r][c];
@@ -296,19 +322,19 @@ __device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
     sh.dsc[g][t] = d > R(0) ? rsq_(d) : R(1);
     if (t == M - 1 && !(d > R(0)) && sh.flag[g][0] == 0) sh.flag[g][0] = M;
   }
-  const int ti = t / (M / 2), tj = t % (M / 2);
-  C p[2][2];
-  mm_tile_rh<M>(sh.A[g], sh.F[g], ti, tj, p);   // T = A W^H
+  int ti, tj;
+  tile_coords<M, NT>(t, ti, tj);
+  C p[NT][NT];
+  mm_tile_rh<M, NT>(sh.A[g], sh.F[g], ti, tj, p);   // T = A W^H
   __syncthreads();
-  store_tile<M>(sh.A[g], ti, tj, p);
+  store_tile<M, NT>(sh.A[g], ti, tj, p);
   __syncthreads();
-  mm_tile<M, false>(sh.F[g], sh.A[g], ti, tj, R(0), p);   // W T, scaled by D^-1/2 on both sides
+  mm_tile<M, NT, false>(sh.F[g], sh.A[g], ti, tj, R(0), p);   // W T, scaled by D^-1/2 on both sides
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-      p[a][b] = cscale(p[a][b], sh.dsc[g][ti + a * (M / 2)] * sh.dsc[g][tj + b * (M / 2)]);
-  store_tile<M>(sh.B[g], ti, tj, p);
+    for (int b = 0; b < NT; ++b) p[a][b] = cscale(p[a][b], sh.dsc[g][ti + a * S] * sh.dsc[g][tj + b * S]);
+  store_tile<M, NT>(sh.B[g], ti, tj, p);
   __syncthreads();
   LHF_FOR_ENTRIES {
     const C x = sh.B[g][r][c], y = sh.B[g][c][r];
@@ -373,18 +399,24 @@ __device__ __forceinline__ void rotation(R app, R aqq, C b, R& c, C& s, R& dp, R
 // owning a diagonal pair block computes that pair's rotation and publishes it
 // in LDS; after a barrier every thread rotates its own 2 x 2 block in
 // registers and writes it back in place (each entry belongs to exactly one
-// block per round).  Returns the buffer holding the result (always A here).
-template <typename R, int M, int G, bool HASU, bool HASV, bool WANTV>
+// block per round).  Wide layout (W = 1): lane 4 blk + 2 a + b owns entry
+// (a ? q_i : p_i, b ? q_j : p_j) of pair block blk = (i, j); every lane of
+// the block reads the block's four entries before the round's first barrier
+// and writes its own after it.  Returns the buffer holding the result
+// (always A here).
+template <int W, typename R, int M, int G, bool HASU, bool HASV, bool WANTV>
 __device__ int jacobi(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int maxsw, R tol) {
   typedef typename Cx<R>::T C;
-  constexpr int H = M / 2, TPM = H * H;
+  constexpr int H = M / 2, TPM = M * M / W;
   R nloc = R(0);
   LHF_FOR_ENTRIES {
     const C a = sh.A[g][r][c];
     nloc += a.x * a.x + a.y * a.y;
   }
-  const R nrm2 = group_sum(sh, g, t, nloc);
-  const int bi = t / H, bj = t % H;
+  const R nrm2 = group_sum<W>(sh, g, t, nloc);
+  const int blk = W == 4 ? t : t >> 2;
+  const int bi = blk / H, bj = blk % H;
+  const int ea = W == 4 ? 0 : (t >> 1) & 1, eb = W == 4 ? 0 : t & 1;   // wide: entry within the block
 #pragma unroll 1
   for (int sw = 0;; ++sw) {
     R oloc = R(0);
@@ -392,9 +424,9 @@ __device__ int jacobi(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int maxsw, R 
       const C a = sh.A[g][r][c];
       if (r != c) oloc += a.x * a.x + a.y * a.y;
     }
-    const R off = group_sum(sh, g, t, oloc);
+    const R off = group_sum<W>(sh, g, t, oloc);
     int st = off <= tol * tol * nrm2 ? 1 : 0;
-    R corr[4];
+    R corr[W];
     if constexpr (!WANTV) {
       // Second-order closure for eigenvalues only.  With D = diag(A), E the
       // off-diagonal part and rho_pq = |e_pq| / |d_p - d_q|, the eigenvalue
@@ -408,7 +440,7 @@ __device__ int jacobi(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int maxsw, R 
       const R x = off / nrm2;
       bool rowok = false;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) corr[k] = R(0);
+      for (int k = 0; k < W; ++k) corr[k] = R(0);
       if (x * x * x <= R(M * M) * R(M * M) * tol * tol) {
         const R dc = sh.A[g][t % M][t % M].x;
         const R emax = sqrt(off);
@@ -432,7 +464,7 @@ __device__ int jacobi(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int maxsw, R 
           rowok = rowok && rho <= R(0.125) && emax * rho * rho <= R(0.25) * tol * sqrt(nrm2);
         }
       }
-      const R nbad = group_sum(sh, g, t, rowok ? R(0) : R(1));
+      const R nbad = group_sum<W>(sh, g, t, rowok ? R(0) : R(1));
       if (st == 0 && nbad == R(0)) st = 2;
     }
     if (t == 0) sh.flag[g][2] = st;
@@ -457,7 +489,13 @@ __device__ int jacobi(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int maxsw, R 
       pair_of<M>(bi, s, pi, qi);
       pair_of<M>(bj, s, pj, qj);
       C a00 = sh.A[g][pi][pj], a01 = sh.A[g][pi][qj], a10 = sh.A[g][qi][pj], a11 = sh.A[g][qi][qj];
-      if (bi == bj) {
+      C vp, vq;   // wide layout: V entries (row, p_j), (row, q_j) of this lane's row
+      const int row = ea ? qi : pi;
+      if constexpr (W == 1 && WANTV) {
+        vp = sh.V[g][row][pj];
+        vq = sh.V[g][row][qj];
+      }
+      if (bi == bj && ea == 0 && eb == 0) {
         R cs, dp, dq;
         C sv;
         rotation<R, C>(a00.x, a11.x, a01, cs, sv, dp, dq);
@@ -470,31 +508,49 @@ __device__ int jacobi(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int maxsw, R 
       const R ci = sh.jc[g][bi], cj = sh.jc[g][bj];
       const C si = sh.js[g][bi], sj = sh.js[g][bj];
       const C msj = cmk<C>(-sj.x, sj.y);   // J_qp of pair j = -conj(s_j)
-      if (bi == bj) {
-        a00 = cmk<C>(sh.dn[g][pi], R(0));
-        a11 = cmk<C>(sh.dn[g][qi], R(0));
-        a01 = cmk<C>(R(0), R(0));
-        a10 = cmk<C>(R(0), R(0));
+      if constexpr (W == 4) {
+        if (bi == bj) {
+          a00 = cmk<C>(sh.dn[g][pi], R(0));
+          a11 = cmk<C>(sh.dn[g][qi], R(0));
+          a01 = cmk<C>(R(0), R(0));
+          a10 = cmk<C>(R(0), R(0));
+        } else {
+          // T = A J_j, then A' = J_i^H T
+          const C t00 = cadd(cscale(a00, cj), cmul(a01, msj));
+          const C t01 = cadd(cmul(a00, sj), cscale(a01, cj));
+          const C t10 = cadd(cscale(a10, cj), cmul(a11, msj));
+          const C t11 = cadd(cmul(a10, sj), cscale(a11, cj));
+          a00 = csub(cscale(t00, ci), cmul(si, t10));
+          a01 = csub(cscale(t01, ci), cmul(si, t11));
+          a10 = cadd(cmulc(si, t00), cscale(t10, ci));
+          a11 = cadd(cmulc(si, t01), cscale(t11, ci));
+        }
+        sh.A[g][pi][pj] = a00; sh.A[g][pi][qj] = a01; sh.A[g][qi][pj] = a10; sh.A[g][qi][qj] = a11;
+        if constexpr (WANTV) {
+          // columns {pj, qj} of rows {pi, qi}: V <- V J_j
+          C up = sh.V[g][pi][pj], uq = sh.V[g][pi][qj];
+          sh.V[g][pi][pj] = cadd(cscale(up, cj), cmul(uq, msj));
+          sh.V[g][pi][qj] = cadd(cmul(up, sj), cscale(uq, cj));
+          up = sh.V[g][qi][pj]; uq = sh.V[g][qi][qj];
+          sh.V[g][qi][pj] = cadd(cscale(up, cj), cmul(uq, msj));
+          sh.V[g][qi][qj] = cadd(cmul(up, sj), cscale(uq, cj));
+        }
       } else {
-        // T = A J_j, then A' = J_i^H T
-        const C t00 = cadd(cscale(a00, cj), cmul(a01, msj));
-        const C t01 = cadd(cmul(a00, sj), cscale(a01, cj));
-        const C t10 = cadd(cscale(a10, cj), cmul(a11, msj));
-        const C t11 = cadd(cmul(a10, sj), cscale(a11, cj));
-        a00 = csub(cscale(t00, ci), cmul(si, t10));
-        a01 = csub(cscale(t01, ci), cmul(si, t11));
-        a10 = cadd(cmulc(si, t00), cscale(t10, ci));
-        a11 = cadd(cmulc(si, t01), cscale(t11, ci));
-      }
-      sh.A[g][pi][pj] = a00; sh.A[g][pi][qj] = a01; sh.A[g][qi][pj] = a10; sh.A[g][qi][qj] = a11;
-      if constexpr (WANTV) {
-        // columns {pj, qj} of rows {pi, qi}: V <- V J_j
-        C vp = sh.V[g][pi][pj], vq = sh.V[g][pi][qj];
-        sh.V[g][pi][pj] = cadd(cscale(vp, cj), cmul(vq, msj));
-        sh.V[g][pi][qj] = cadd(cmul(vp, sj), cscale(vq, cj));
-        vp = sh.V[g][qi][pj]; vq = sh.V[g][qi][qj];
-        sh.V[g][qi][pj] = cadd(cscale(vp, cj), cmul(vq, msj));
-        sh.V[g][qi][qj] = cadd(cmul(vp, sj), cscale(vq, cj));
+        // this lane's entry (ea, eb) of J_i^H A J_j: column eb of J_j is
+        // (j0, j1) = (cj, -conj(sj)) or (sj, cj); row ea of J_i^H is
+        // (ci, -si) or (conj(si), ci)
+        const C j0 = cmk<C>(eb ? sj.x : cj, eb ? sj.y : R(0));
+        const C j1 = cmk<C>(eb ? cj : msj.x, eb ? R(0) : msj.y);
+        const C t0 = cadd(cmul(a00, j0), cmul(a01, j1)), t1 = cadd(cmul(a10, j0), cmul(a11, j1));
+        const C r0 = cmk<C>(ea ? si.x : ci, ea ? -si.y : R(0));   // coefficient of t0
+        const C r1 = cmk<C>(ea ? ci : -si.x, ea ? R(0) : -si.y);  // coefficient of t1
+        C res = cadd(cmul(r0, t0), cmul(r1, t1));
+        if (bi == bj) {
+          const R dv = sh.dn[g][row];
+          res = cmk<C>(ea == eb ? dv : R(0), R(0));
+        }
+        sh.A[g][row][eb ? qj : pj] = res;
+        if constexpr (WANTV) sh.V[g][row][eb ? qj : pj] = cadd(cmul(vp, j0), cmul(vq, j1));
       }
       __syncthreads();
     }
@@ -520,27 +576,32 @@ __device__ void eig_rank(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int m, int
 }
 
 // Eigenvectors C^-H V = W^H D^-1/2 V into A (one tiled product).
-template <typename R, int M, int G, bool HASU, bool HASV>
+template <int W, typename R, int M, int G, bool HASU, bool HASV>
 __device__ void backsub_vectors(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
   typedef typename Cx<R>::T C;
-  const int ti = t / (M / 2), tj = t % (M / 2);
-  C p[2][2];
-  mm_tile_lh_diag<M>(sh.F[g], sh.dsc[g], sh.V[g], ti, tj, p);
-  store_tile<M>(sh.A[g], ti, tj, p);
+  constexpr int NT = TileOf<W>::NT;
+  int ti, tj;
+  tile_coords<M, NT>(t, ti, tj);
+  C p[NT][NT];
+  mm_tile_lh_diag<M, NT>(sh.F[g], sh.dsc[g], sh.V[g], ti, tj, p);
+  store_tile<M, NT>(sh.A[g], ti, tj, p);
   __syncthreads();
 }
 
-template <int M>
+// Threads per matrix TPM = M^2 / W (W = 4 entries per thread, or 1: the
+// wide layout for batches too small to fill the device), G matrices per
+// workgroup (one wavefront when TPM < 64).
+template <int M, int W>
 struct Shape {
-  static constexpr int TPM = (M / 2) * (M / 2);
+  static constexpr int TPM = M * M / W;
   static constexpr int G = TPM >= 64 ? 1 : 64 / TPM;
   static constexpr int THREADS = G * TPM;
 };
 
 // Solve from Fourier blocks of precision R.  VMODE: 0 none, 1 write vectors
 // to V (caller, sorted columns), 2 write vectors to U (FP32 workspace).
-template <typename R, int M, int VMODE>
-__global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* __restrict__ lats,
+template <typename R, int M, int VMODE, int W>
+__global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatDev* __restrict__ lats,
                                                                  const int2* __restrict__ canon, int ncanon,
                                                                  const typename Cx<R>::T* __restrict__ Hb,
                                                                  const typename Cx<R>::T* __restrict__ Sb,
@@ -548,7 +609,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
                                                                  typename Cx<R>::T* __restrict__ Vout,
                                                                  int32_t* __restrict__ info, int maxsw, R tol) {
   typedef typename Cx<R>::T C;
-  constexpr int G = Shape<M>::G, TPM = Shape<M>::TPM;
+  constexpr int G = Shape<M, W>::G, TPM = Shape<M, W>::TPM;
   constexpr bool WANTV = VMODE != 0;
   __shared__ Smem<R, M, G, false, WANTV> sh;
   const int g = threadIdx.x / TPM, t = threadIdx.x % TPM;
@@ -562,9 +623,9 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
   const int64_t base = L.gen_off + (int64_t)blk * m * m;
   // every global load first (padding entries read entry 0 and discard it;
   // a spare group reads a valid block)
-  C av[4], bv[4];
+  C av[W], bv[W];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < W; ++k) {
     const int e = t + k * TPM, r = e / M, c = e % M;
     const int64_t o = base + (r < m && c < m ? r * m + c : 0);
     av[k] = Hb[o];
@@ -574,7 +635,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
   __syncthreads();
   bool bad = false;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < W; ++k) {
     const int e = t + k * TPM, r = e / M, c = e % M;
     C a = cmk<C>(R(0), R(0)), b = cmk<C>(r == c ? R(1) : R(0), R(0));
     if (valid && r < m && c < m) {
@@ -591,10 +652,10 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
   }
   if (bad) sh.flag[g][1] = 1;
   __syncthreads();
-  chol_reduce(sh, g, t);
-  const int cur = jacobi<R, M, G, false, WANTV, WANTV>(sh, g, t, maxsw, tol);
+  chol_reduce<W>(sh, g, t);
+  const int cur = jacobi<W, R, M, G, false, WANTV, WANTV>(sh, g, t, maxsw, tol);
   eig_rank(sh, g, t, m, cur);
-  if constexpr (WANTV) backsub_vectors(sh, g, t);
+  if constexpr (WANTV) backsub_vectors<W>(sh, g, t);
   if (!valid) return;   // no barrier follows
   const int64_t wb = L.w_off + (int64_t)blk * m, wc = L.w_off + (int64_t)cblk * m;
   if (t < m) {
@@ -605,7 +666,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
   if (WANTV) {
     const int64_t cb0 = L.gen_off + (int64_t)cblk * m * m;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < W; ++k) {
       const int e = t + k * TPM, r = e / M, c = e % M;
       if (r < m && c < m) {
         const C v = sh.A[g][r][c];
@@ -623,8 +684,8 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) heev_kernel(const LatDev* _
 
 // Refinement in FP64 from FP32 eigenvectors U (layout [blk][row][col]).
 // Blocks from H64/S64 (complex128) or regenerated from the FP64 generator band.
-template <int M, bool WANTV>
-__global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves_per_eu(2))) refine_kernel(const LatDev* __restrict__ lats,
+template <int M, bool WANTV, int W>
+__global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_waves_per_eu(2))) refine_kernel(const LatDev* __restrict__ lats,
                                                                    const int2* __restrict__ canon, int ncanon,
                                                                    const double2* __restrict__ tw,
                                                                    const double2* __restrict__ H64,
@@ -637,7 +698,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
                                                                    int32_t* __restrict__ info, int maxsw, double tol) {
   typedef double2 C;
   typedef double R;
-  constexpr int G = Shape<M>::G, TPM = Shape<M>::TPM;
+  constexpr int G = Shape<M, W>::G, TPM = Shape<M, W>::TPM;
   // eigenvalues only: no V; the products' scratch is F (Rayleigh-Ritz) and
   // the dead U (congruence), so four matrices per group instead of five
   __shared__ Smem<R, M, G, true, WANTV> sh;
@@ -653,11 +714,11 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
   // every global load of the block first (padding entries read entry 0 and
   // discard it; a spare group reads a valid block; U of a block whose FP32
   // solve failed is discarded)
-  C hv[4], sv[4];
-  float2 uv[4];
+  C hv[W], sv[W];
+  float2 uv[W];
   const int32_t st32 = info32[L.blk_off + blk];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < W; ++k) {
     const int e = t + k * TPM, r = e / M, c = e % M;
     const int64_t o = base + (r < m && c < m ? r * m + c : 0);
     if (H64) {
@@ -700,7 +761,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < W; ++k) {
     const int e = t + k * TPM, r = e / M, c = e % M;
     C h = cmk<C>(0.0, 0.0), s = cmk<C>(r == c ? 1.0 : 0.0, 0.0), u = cmk<C>(r == c ? 1.0 : 0.0, 0.0);
     if (valid && r < m && c < m) {
@@ -735,18 +796,20 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
   }
   __syncthreads();
   // Rayleigh-Ritz pair: A <- U^H Hbar U, B <- U^H Sbar U (two fused passes)
-  const int ti = t / (M / 2), tj = t % (M / 2);
+  constexpr int NT = TileOf<W>::NT;
+  int ti, tj;
+  tile_coords<M, NT>(t, ti, tj);
   {
-    C p1[2][2], p2[2][2];
-    mm_shared_right<M>(sh.A[g], sh.B[g], sh.U[g], ti, tj, p1, p2);
+    C p1[NT][NT], p2[NT][NT];
+    mm_shared_right<M, NT>(sh.A[g], sh.B[g], sh.U[g], ti, tj, p1, p2);
     __syncthreads();
-    store_tile<M>(sh.A[g], ti, tj, p1);
-    store_tile<M>(sh.B[g], ti, tj, p2);
+    store_tile<M, NT>(sh.A[g], ti, tj, p1);
+    store_tile<M, NT>(sh.B[g], ti, tj, p2);
     __syncthreads();
-    mm_shared_left_h<M>(sh.U[g], sh.A[g], sh.B[g], ti, tj, p1, p2);
+    mm_shared_left_h<M, NT>(sh.U[g], sh.A[g], sh.B[g], ti, tj, p1, p2);
     __syncthreads();
-    store_tile<M>(sh.A[g], ti, tj, p1);
-    store_tile<M>(sh.B[g], ti, tj, p2);
+    store_tile<M, NT>(sh.A[g], ti, tj, p1);
+    store_tile<M, NT>(sh.B[g], ti, tj, p2);
     __syncthreads();
   }
   // B = I + E with E small when U is S-orthonormal to FP32 accuracy (E is
@@ -760,7 +823,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
     const R br = b.x - (r == c ? R(1) : R(0));
     eloc += br * br + b.y * b.y;
   }
-  const R e2 = group_sum(sh, g, t, eloc);
+  const R e2 = group_sum<W>(sh, g, t, eloc);
   // series degree: the first neglected term ||E||^(deg+1) stays below ~1e-16
   if (t == 0) sh.flag[g][3] = e2 <= R(1e-12) ? 2 : e2 <= R(1e-9) ? 3 : e2 <= R(1e-7) ? 4 : e2 <= R(4e-6) ? 5 : 0;
   __syncthreads();
@@ -772,7 +835,7 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
     deg = max(deg, sh.flag[gg][3]);
   }
   if (series) {
-    C p[2][2];
+    C p[NT][NT];
     // coefficients of (1 + E)^-1/2 = sum_k cf(k) E^k
     auto cf = [](int k) -> R {
       return k == 0 ? R(1.0) : k == 1 ? R(-0.5) : k == 2 ? R(0.375) : k == 3 ? R(-0.3125)
@@ -790,19 +853,19 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
     __syncthreads();
 #pragma unroll 1
     for (int h = deg - 2; h >= 0; --h) {
-      mm_tile<M, true>(sh.B[g], sh.F[g], ti, tj, cf(h), p);
+      mm_tile<M, NT, true>(sh.B[g], sh.F[g], ti, tj, cf(h), p);
       __syncthreads();
-      store_tile<M>(sh.F[g], ti, tj, p);
+      store_tile<M, NT>(sh.F[g], ti, tj, p);
       __syncthreads();
     }
     // T <- A X (into the dead U, or V with vectors), then B <- X T (E is
     // dead), then A <- the Hermitian part of B and V <- I
-    mm_tile<M, false>(sh.A[g], sh.F[g], ti, tj, R(0), p);
-    if constexpr (WANTV) store_tile<M>(sh.V[g], ti, tj, p); else store_tile<M>(sh.U[g], ti, tj, p);
+    mm_tile<M, NT, false>(sh.A[g], sh.F[g], ti, tj, R(0), p);
+    if constexpr (WANTV) store_tile<M, NT>(sh.V[g], ti, tj, p); else store_tile<M, NT>(sh.U[g], ti, tj, p);
     __syncthreads();
-    if constexpr (WANTV) mm_tile<M, false>(sh.F[g], sh.V[g], ti, tj, R(0), p);
-    else mm_tile<M, false>(sh.F[g], sh.U[g], ti, tj, R(0), p);
-    store_tile<M>(sh.B[g], ti, tj, p);
+    if constexpr (WANTV) mm_tile<M, NT, false>(sh.F[g], sh.V[g], ti, tj, R(0), p);
+    else mm_tile<M, NT, false>(sh.F[g], sh.U[g], ti, tj, R(0), p);
+    store_tile<M, NT>(sh.B[g], ti, tj, p);
     __syncthreads();
     LHF_FOR_ENTRIES {
       const C x = sh.B[g][r][c], y = sh.B[g][c][r];
@@ -813,22 +876,22 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
     }
     __syncthreads();
   } else {
-    chol_reduce(sh, g, t);
+    chol_reduce<W>(sh, g, t);
   }
-  const int cur = jacobi<R, M, G, true, WANTV, WANTV>(sh, g, t, maxsw, tol);
+  const int cur = jacobi<W, R, M, G, true, WANTV, WANTV>(sh, g, t, maxsw, tol);
   eig_rank(sh, g, t, m, cur);
-  C vfin[2][2];
+  C vfin[NT][NT];
   if constexpr (WANTV) {
     if (series) {
       // A <- X V
-      C p[2][2];
-      mm_tile<M, false>(sh.F[g], sh.V[g], ti, tj, R(0), p);
-      store_tile<M>(sh.A[g], ti, tj, p);
+      C p[NT][NT];
+      mm_tile<M, NT, false>(sh.F[g], sh.V[g], ti, tj, R(0), p);
+      store_tile<M, NT>(sh.A[g], ti, tj, p);
       __syncthreads();
     } else {
-      backsub_vectors(sh, g, t);
+      backsub_vectors<W>(sh, g, t);
     }
-    mm_tile<M, false>(sh.U[g], sh.A[g], ti, tj, R(0), vfin);
+    mm_tile<M, NT, false>(sh.U[g], sh.A[g], ti, tj, R(0), vfin);
   }
   if (!valid) return;
   const int64_t wb = L.w_off + (int64_t)blk * m, wc = L.w_off + (int64_t)cblk * m;
@@ -839,10 +902,10 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
   if constexpr (WANTV) {
     const int64_t cb0 = L.gen_off + (int64_t)cblk * m * m;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NT; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int r = ti + a * (M / 2), c = tj + b * (M / 2);
+      for (int b = 0; b < NT; ++b) {
+        const int r = ti + a * (M / NT), c = tj + b * (M / NT);
         if (r < m && c < m) {
           Vout[base + r * m + sh.rank[g][c]] = vfin[a][b];
           if (cblk != blk) Vout[cb0 + r * m + sh.rank[g][c]] = cconj(vfin[a][b]);
@@ -856,23 +919,57 @@ __global__ void __launch_bounds__(Shape<M>::THREADS) __attribute__((amdgpu_waves
   }
 }
 
-template <typename R, int M>
-hipError_t launch_heev_m(const lhf_plan_s* p, int vmode, const void* Hb, const void* Sb, double* w, void* V,
-                         int32_t* info, int maxsw, R tol, hipStream_t s) {
+template <typename R, int M, int W>
+hipError_t launch_heev_mw(const lhf_plan_s* p, int vmode, const void* Hb, const void* Sb, double* w, void* V,
+                          int32_t* info, int maxsw, R tol, hipStream_t s) {
   typedef typename Cx<R>::T C;
   const int cls = M == 4 ? 0 : M == 8 ? 1 : M == 16 ? 2 : 3;
   const int nc = p->ncanon[cls];
-  if (nc == 0) return hipSuccess;
   const int2* canon = p->d_canon[cls];
-  const dim3 grid((nc + Shape<M>::G - 1) / Shape<M>::G), block(Shape<M>::THREADS);
+  const dim3 grid((nc + Shape<M, W>::G - 1) / Shape<M, W>::G), block(Shape<M, W>::THREADS);
   const C* h = (const C*)Hb;
   const C* sm = (const C*)Sb;
   if (vmode == 0)
-    hipLaunchKernelGGL((heev_kernel<R, M, 0>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info, maxsw, tol);
+    hipLaunchKernelGGL((heev_kernel<R, M, 0, W>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info,
+                       maxsw, tol);
   else if (vmode == 1)
-    hipLaunchKernelGGL((heev_kernel<R, M, 1>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info, maxsw, tol);
+    hipLaunchKernelGGL((heev_kernel<R, M, 1, W>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info,
+                       maxsw, tol);
   else
-    hipLaunchKernelGGL((heev_kernel<R, M, 2>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info, maxsw, tol);
+    hipLaunchKernelGGL((heev_kernel<R, M, 2, W>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info,
+                       maxsw, tol);
+  return hipGetLastError();
+}
+
+// One launch for the class of size M, in the wide layout when the plan
+// chose it for that class.
+template <typename R, int M>
+hipError_t launch_heev_m(const lhf_plan_s* p, int vmode, const void* Hb, const void* Sb, double* w, void* V,
+                         int32_t* info, int maxsw, R tol, hipStream_t s) {
+  const int cls = M == 4 ? 0 : M == 8 ? 1 : M == 16 ? 2 : 3;
+  if (p->ncanon[cls] == 0) return hipSuccess;
+  if (p->heev_wide[cls]) return launch_heev_mw<R, M, 1>(p, vmode, Hb, Sb, w, V, info, maxsw, tol, s);
+  return launch_heev_mw<R, M, 4>(p, vmode, Hb, Sb, w, V, info, maxsw, tol, s);
+}
+
+template <int M, int W>
+hipError_t launch_refine_mw(const lhf_plan_s* p, bool wantv, const void* H64, const void* S64, const double* Hg,
+                            const double* Sg, const float2* U, const int32_t* info32, double* w, void* V,
+                            int32_t* info, hipStream_t s) {
+  const int cls = M == 4 ? 0 : M == 8 ? 1 : M == 16 ? 2 : 3;
+  const int nc = p->ncanon[cls];
+  const int2* canon = p->d_canon[cls];
+  const dim3 grid((nc + Shape<M, W>::G - 1) / Shape<M, W>::G), block(Shape<M, W>::THREADS);
+  // eigenvalues only: stop at an off-diagonal norm of 1e-11 of the norm (the
+  // eigenvalue error is at most that, even for a degenerate pair); with
+  // vectors: 4 M eps
+  const double tol = wantv ? 4.0 * M * 1.1102230246251565e-16 : 1e-11;
+  if (wantv)
+    hipLaunchKernelGGL((refine_kernel<M, true, W>), grid, block, 0, s, p->d_lat, canon, nc, p->d_tw64,
+                       (const double2*)H64, (const double2*)S64, Hg, Sg, U, info32, w, (double2*)V, info, 30, tol);
+  else
+    hipLaunchKernelGGL((refine_kernel<M, false, W>), grid, block, 0, s, p->d_lat, canon, nc, p->d_tw64,
+                       (const double2*)H64, (const double2*)S64, Hg, Sg, U, info32, w, (double2*)V, info, 30, tol);
   return hipGetLastError();
 }
 
@@ -881,21 +978,9 @@ hipError_t launch_refine_m(const lhf_plan_s* p, bool wantv, const void* H64, con
                            const double* Sg, const float2* U, const int32_t* info32, double* w, void* V,
                            int32_t* info, hipStream_t s) {
   const int cls = M == 4 ? 0 : M == 8 ? 1 : M == 16 ? 2 : 3;
-  const int nc = p->ncanon[cls];
-  if (nc == 0) return hipSuccess;
-  const int2* canon = p->d_canon[cls];
-  const dim3 grid((nc + Shape<M>::G - 1) / Shape<M>::G), block(Shape<M>::THREADS);
-  // eigenvalues only: stop at an off-diagonal norm of 1e-11 of the norm (the
-  // eigenvalue error is at most that, even for a degenerate pair); with
-  // vectors: 4 M eps
-  const double tol = wantv ? 4.0 * M * 1.1102230246251565e-16 : 1e-11;
-  if (wantv)
-    hipLaunchKernelGGL((refine_kernel<M, true>), grid, block, 0, s, p->d_lat, canon, nc, p->d_tw64,
-                       (const double2*)H64, (const double2*)S64, Hg, Sg, U, info32, w, (double2*)V, info, 30, tol);
-  else
-    hipLaunchKernelGGL((refine_kernel<M, false>), grid, block, 0, s, p->d_lat, canon, nc, p->d_tw64,
-                       (const double2*)H64, (const double2*)S64, Hg, Sg, U, info32, w, (double2*)V, info, 30, tol);
-  return hipGetLastError();
+  if (p->ncanon[cls] == 0) return hipSuccess;
+  if (p->heev_wide[cls]) return launch_refine_mw<M, 1>(p, wantv, H64, S64, Hg, Sg, U, info32, w, V, info, s);
+  return launch_refine_mw<M, 4>(p, wantv, H64, S64, Hg, Sg, U, info32, w, V, info, s);
 }
 
 }  // namespace

@@ -319,7 +319,14 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
       if (cb >= b) cl.push_back(make_int2(i, b));
     }
   }
-  for (int c = 0; c < 4; ++c) p->ncanon[c] = (int32_t)canon[c].size();
+  for (int c = 0; c < 4; ++c) {
+    p->ncanon[c] = (int32_t)canon[c].size();
+    // wavefronts of the four-entries-per-thread launch: (M/2)^2 threads per
+    // matrix, 64 / that many matrices per wavefront when below 64
+    const int m = 4 << c, tpm = (m / 2) * (m / 2);
+    const int64_t waves = tpm >= 64 ? (int64_t)p->ncanon[c] * (tpm / 64) : ((int64_t)p->ncanon[c] * tpm + 63) / 64;
+    p->heev_wide[c] = p->ncanon[c] > 0 && waves < lhf_plan_s::kWideWaves;
+  }
 
   // twiddle tables exp(-2 pi i m / L)
   std::vector<double2> tw64(tw);

@@ -35,6 +35,10 @@ struct lhf_plan_s {
   int32_t fused_lds = 0;                // bytes of LDS per workgroup for complex128
   int2* d_canon[4] = {nullptr, nullptr, nullptr, nullptr};  // (lattice, block) per size class M = 4, 8, 16, 32
   int32_t ncanon[4] = {0, 0, 0, 0};
+  // eigensolver layout per class: one matrix entry per thread (wide) when the
+  // four-entries-per-thread launch would leave SIMDs without a wavefront
+  bool heev_wide[4] = {false, false, false, false};
+  static constexpr int64_t kWideWaves = 1024;   // one wavefront per SIMD of the device
   // tunables (planner defaults, refined by lhf_plan_autotune)
   int32_t dft_target_threads = 131072;  // threads one DFT pass aims to run
   int32_t gram_grid = 4096;             // workgroups of the grouped Gram launch

@@ -111,11 +111,14 @@ void get_tuning(const lhf_plan_s* p, lhf_tuning* t) {
   t->gram_split = p->gram_split;
   t->gram_grid = p->gram_grid;
   t->tol32_scale = p->tol32_scale;
+  t->heev_wide = 0;
+  for (int c = 0; c < 4; ++c) t->heev_wide |= p->heev_wide[c] ? 1 << c : 0;
 }
 
 int32_t set_tuning(lhf_plan_s* p, const lhf_tuning* t) {
   if (t->dft_threads < 1024 || t->dft_threads > (1 << 24) || t->gram_split < 1 || t->gram_split > kGramSplitMax ||
-      t->gram_grid < 1 || t->gram_grid > (1 << 20) || t->tol32_scale < 1 || t->tol32_scale > (1 << 16)) {
+      t->gram_grid < 1 || t->gram_grid > (1 << 20) || t->tol32_scale < 1 || t->tol32_scale > (1 << 16) ||
+      t->heev_wide < 0 || t->heev_wide > 15) {
     set_error("tuning value out of range");
     return LHF_ERR_INVALID;
   }
@@ -124,6 +127,7 @@ int32_t set_tuning(lhf_plan_s* p, const lhf_tuning* t) {
   p->gram_split = t->gram_split;
   p->gram_grid = t->gram_grid;
   p->tol32_scale = t->tol32_scale;
+  for (int c = 0; c < 4; ++c) p->heev_wide[c] = (t->heev_wide >> c) & 1;
   return tables ? apply_tuning(p) : LHF_OK;
 }
 
@@ -176,6 +180,8 @@ bool parse_entry(const std::string& body, lhf_tuning& t) {
       !field(body, "tol32_scale", d))
     return false;
   field(body, "step_ms", e);
+  double w = -1.0;
+  t.heev_wide = field(body, "heev_wide", w) && w >= 0.0 ? (int32_t)w : t.heev_wide;
   t.dft_threads = (int32_t)a;
   t.gram_split = (int32_t)b;
   t.gram_grid = (int32_t)c;
@@ -188,8 +194,9 @@ void write_cache(const char* path, std::map<std::string, std::string> entries, c
                  const lhf_tuning& t) {
   char buf[256];
   std::snprintf(buf, sizeof(buf),
-                "{\"dft_threads\": %d, \"gram_split\": %d, \"gram_grid\": %d, \"tol32_scale\": %d, \"step_ms\": %.6f}",
-                t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.step_ms);
+                "{\"dft_threads\": %d, \"gram_split\": %d, \"gram_grid\": %d, \"tol32_scale\": %d, "
+                "\"heev_wide\": %d, \"step_ms\": %.6f}",
+                t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.step_ms);
   entries[key] = buf;
   std::ofstream f(path, std::ios::trunc);
   f << "{\n";
@@ -272,6 +279,7 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
     cache = read_cache(cache_path);
     auto it = cache.find(key);
     lhf_tuning t{};
+    get_tuning(p, &t);   // entries without a field keep the plan's value
     if (it != cache.end() && parse_entry(it->second, t)) {
       if ((st = set_tuning(p, &t)) != LHF_OK) return st;
       if (out) { get_tuning(p, out); out->step_ms = t.step_ms; out->from_cache = 1; }
@@ -321,6 +329,14 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
   if (st == LHF_OK) st = search(1, &lhf_tuning::gram_split, split_c, 3);
   if (st == LHF_OK) st = search(1, &lhf_tuning::gram_grid, grid_c, 4);
   if (st == LHF_OK) st = search(2, &lhf_tuning::dft_threads, dft_c, 5);
+  // eigensolver layout, one size class at a time
+  for (int c = 0; c < 4 && st == LHF_OK; ++c) {
+    if (p->ncanon[c] == 0) continue;
+    lhf_tuning cur{};
+    get_tuning(p, &cur);
+    const int32_t lay_c[2] = {cur.heev_wide & ~(1 << c), cur.heev_wide | (1 << c)};
+    st = search(4, &lhf_tuning::heev_wide, lay_c, 2);
+  }
   if (st == LHF_OK && p->prec == LHF_PREC_MIXED) st = search(4, &lhf_tuning::tol32_scale, tol_c, 4);
   if (st == LHF_OK) st = timed(7, 10, step_ms);
   (void)hipEventDestroy(e0);

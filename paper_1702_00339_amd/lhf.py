@@ -49,7 +49,8 @@ class lhf_step_args(C.Structure):
 
 class lhf_tuning(C.Structure):
     _fields_ = [("dft_threads", C.c_int32), ("gram_split", C.c_int32), ("gram_grid", C.c_int32),
-                ("tol32_scale", C.c_int32), ("step_ms", C.c_double), ("from_cache", C.c_int32)]
+                ("tol32_scale", C.c_int32), ("heev_wide", C.c_int32), ("step_ms", C.c_double),
+                ("from_cache", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -105,8 +105,9 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     assert t.gram_split in (64, 128, 256) and t.gram_grid in (1024, 2048, 4096, 8192)
     assert t.dft_threads in (32768, 65536, 131072, 262144, 524288) and t.tol32_scale in (1, 16, 256, 4096)
     got = pipe.plan.lhf_plan_get_tuning()
-    assert (got.dft_threads, got.gram_split, got.gram_grid, got.tol32_scale) == \
-        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale)
+    assert (got.dft_threads, got.gram_split, got.gram_grid, got.tol32_scale, got.heev_wide) == \
+        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide)
+    assert 0 <= t.heev_wide <= 15
     entries = json.load(open(cache))
     assert len(entries) == 1
     pipe.step_native()
@@ -119,8 +120,8 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     again = Pipeline(insts, prec=lhf.LHF_PREC_MIXED)
     t2 = again.autotune(cache)
     assert t2.from_cache == 1
-    assert (t2.dft_threads, t2.gram_split, t2.gram_grid, t2.tol32_scale) == \
-        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale)
+    assert (t2.dft_threads, t2.gram_split, t2.gram_grid, t2.tol32_scale, t2.heev_wide) == \
+        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide)
     # a different plan adds its own entry
     Pipeline(insts[:2], prec=lhf.LHF_PREC_FP64).autotune(cache)
     assert len(json.load(open(cache))) == 2
@@ -130,10 +131,10 @@ def test_set_tuning_extremes_keep_parity():
     """The smallest and largest launch shapes still give the oracle's eigenvalues."""
     insts = _mix()
     refs = [np.sort(separable.solve(i)["eig"], axis=-1) for i in insts]
-    for dft, split, grid in ((32768, 1, 1), (1 << 24, 256, 1 << 20)):
+    for dft, split, grid, wide in ((32768, 1, 1, 0), (1 << 24, 256, 1 << 20, 15)):
         pipe = Pipeline(insts, prec=lhf.LHF_PREC_FP64)
         t = pipe.plan.lhf_plan_get_tuning()
-        t.dft_threads, t.gram_split, t.gram_grid = dft, split, grid
+        t.dft_threads, t.gram_split, t.gram_grid, t.heev_wide = dft, split, grid, wide
         pipe.plan.lhf_plan_set_tuning(t)
         pipe.step_native()
         torch.cuda.synchronize()
@@ -141,5 +142,9 @@ def test_set_tuning_extremes_keep_parity():
             assert (np.abs(w - ref) <= 1e-10 * np.maximum(np.abs(ref), 1.0)).all()
     bad = pipe.plan.lhf_plan_get_tuning()
     bad.gram_split = 257
+    with pytest.raises(lhf.LhfError):
+        pipe.plan.lhf_plan_set_tuning(bad)
+    bad = pipe.plan.lhf_plan_get_tuning()
+    bad.heev_wide = 16
     with pytest.raises(lhf.LhfError):
         pipe.plan.lhf_plan_set_tuning(bad)

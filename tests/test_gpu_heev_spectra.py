@@ -82,12 +82,17 @@ SIZES = {4: (4, 0), 8: (2, 2), 16: (4, 4), 32: (8, 8)}
 
 @pytest.mark.parametrize("m0", sorted(SIZES))
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_known_spectra(m0, prec):
+@pytest.mark.parametrize("layout", ["wide", "four"])
+def test_known_spectra(m0, prec, layout):
     n_s, n_p = SIZES[m0]
     inst = tiny_instance(L=(NBLK, 1, 1), n=(64, 12, 12), n_s=n_s, n_p=n_p, seed=170 + m0, R=4)
     assert inst.m0 == m0
     p = lhf.LHF_PREC_FP64 if prec == "fp64" else lhf.LHF_PREC_MIXED
     pipe = Pipeline(inst, prec=p, gram=lhf.LHF_GRAM_FP64)
+    # both eigensolver layouts: one matrix entry per thread, or four
+    t = pipe.plan.lhf_plan_get_tuning()
+    t.heev_wide = 15 if layout == "wide" else 0
+    pipe.plan.lhf_plan_set_tuning(t)
     lam, h, s = _blocks(m0, seed=1000 + m0)
     dev = pipe.H_bar.device
     h128 = torch.from_numpy(h.reshape(-1)).to(dev)

@@ -170,12 +170,18 @@ def test_grouped_plan_mixes_every_class():
             assert (np.abs(got - ref) <= tol).all(), inst.name
 
 
-def test_eigenvectors_fp64_and_refined():
+@pytest.mark.parametrize("wide", [15, 0], ids=["wide", "four"])
+def test_eigenvectors_fp64_and_refined(wide):
     inst = tiny_instance(L=(5, 2, 1), n=(40, 16, 14), n_s=2, n_p=1, R=6, seed=131)
     res, ref = _eig_ref(inst)
     m0 = inst.m0
     for prec in (lhf.LHF_PREC_FP64, lhf.LHF_PREC_MIXED):
-        pipe = _run(inst, prec, want_vectors=True)
+        pipe = Pipeline(inst, prec=prec, want_vectors=True)
+        t = pipe.plan.lhf_plan_get_tuning()
+        t.heev_wide = wide
+        pipe.plan.lhf_plan_set_tuning(t)
+        pipe.step()
+        torch.cuda.synchronize()
         V = pipe.stacks("V")[0]
         w = pipe.eigenvalues()[0]
         Hb, Sb = res["H_bar"], res["S_bar"]
