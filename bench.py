@@ -39,11 +39,10 @@ WORKLOADS = {
 C4_CHECK = (28, 41, 52, 2)
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per call (FETCH_SIZE + WRITE_SIZE, KiB, scaled by a plain 512 MiB copy) of the mixed path's
-# eigensolve call (FP32 Jacobi + FP64 refinement kernels) and dual block DFT, from two rocprofv3 --pmc
-# runs of `bench.py --probe-traffic` (profiles/traffic_per_dispatch.md).  Valid for the kernels as they
-# were when counted; None where not counted.
-TRAFFIC_KIB = {"c2": {"eig": 1480.9, "dft": 3383.3}, "c3": {"eig": 42733.5, "dft": 99237.4},
-               "c4": {"eig": 695882.6, "dft": 1792882.1}}
+# eigensolve call (FP32 Jacobi + FP64 refinement kernels) and block DFT, from two rocprofv3 --pmc runs of
+# `bench.py --probe-traffic` (profiles/traffic_per_dispatch.md).  Valid for the kernels as they were when
+# counted; absent (reported as null) where not counted.
+TRAFFIC_KIB = {}
 
 
 def parse():
@@ -87,14 +86,17 @@ def event_ms(fn, steps, torch):
     return sum(a.elapsed_time(b) for a, b in ev) / steps
 
 
-def dft_bytes(pipe, insts, dual=False):
+def dft_bytes(pipe, insts, kind="plan"):
     """Algorithmic HBM bytes of one block-DFT call: every Fourier block written
-    once (H and S, complex; complex128 and complex64 for the dual transform of
-    the mixed path) plus every band generator read once (H and S, real)."""
+    once (H and S, complex) plus every band generator read once (H and S,
+    real).  kind "plan": in the plan's precision; "fp64": complex128 from FP64
+    stacks (the mixed path's transform); "dual": complex128 and complex64."""
     from paper_1702_00339_amd import lhf
     cbytes = 16 if pipe.prec == lhf.LHF_PREC_FP64 else 8
     rbytes = cbytes // 2
-    if dual:
+    if kind == "fp64":
+        cbytes, rbytes = 16, 8
+    elif kind == "dual":
         cbytes, rbytes = 16 + 8, 8
     total = 0
     for i, inst in enumerate(insts):
@@ -228,9 +230,9 @@ def main():
         insts = [make_config(args.config)]
         checked = insts
     # mixed: FP64 MFMA Grams (which the FP64 refinement needs anyway), FP64
-    # stacks, one FP64 block DFT writing complex128 blocks and their
-    # complex64 copies; mixed_bf16x3: FP32 stacks from separate bf16 hi+lo
-    # split Grams and a complex64 DFT, reported beside it
+    # stacks, one FP64 block DFT writing complex128 blocks, which the FP32
+    # solve reads and rounds; mixed_bf16x3: FP32 stacks from separate bf16
+    # hi+lo split Grams and a complex64 DFT, reported beside it
     pipes = {"mixed": Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=lhf.LHF_GRAM_FP64),
              "fp64": Pipeline(insts, prec=lhf.LHF_PREC_FP64),
              "mixed_bf16x3": Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=lhf.LHF_GRAM_BF16X3,
@@ -268,12 +270,12 @@ def main():
 
     # rooflines, event-timed on the stream the kernels run on
     pm = pipes["mixed"]
-    ms_dft = event_ms(lambda: pm.plan.lhf_block_fft_dual(pm.H_gen64, pm.S_gen64, pm.H_bar64, pm.S_bar64, pm.H_bar,
-                                                          pm.S_bar, pm.ws), args.steps, torch)
-    bytes_alg = dft_bytes(pm, insts, dual=True)
+    ms_dft = event_ms(lambda: pm.plan.lhf_block_fft(lhf.LHF_PREC_FP64, pm.H_gen64, pm.S_gen64, pm.H_bar64,
+                                                     pm.S_bar64, pm.ws), args.steps, torch)
+    bytes_alg = dft_bytes(pm, insts, kind="fp64")
     achieved = bytes_alg / (ms_dft * 1e-3) / 1e9
     flags = lhf.LHF_HEEV_REFINE_FP64
-    ms_heev = event_ms(lambda: pm.plan.lhf_heev_batched(flags, pm.H_bar, pm.S_bar, pm.w, pm.info, pm.ws,
+    ms_heev = event_ms(lambda: pm.plan.lhf_heev_batched(flags, None, None, pm.w, pm.info, pm.ws,
                                                          H_bar64=pm.H_bar64, S_bar64=pm.S_bar64,
                                                          H_gen64=pm.H_gen64, S_gen64=pm.S_gen64),
                        args.steps, torch)
@@ -316,9 +318,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "lattices": len(insts),
                    "k_point_blocks": nblk, "m0": m0s if len(m0s) > 1 else m0s[0],
-                   "path": "mixed: FP64 MFMA Grams, FP64 stacks, one block DFT writing complex128 blocks "
-                           "and their complex64 copies, FP32 Jacobi on complex64, FP64 Rayleigh-Ritz "
-                           "refinement on complex128; one hipGraph replay per step"},
+                   "path": "mixed: FP64 MFMA Grams, FP64 stacks, one block DFT writing complex128 blocks, "
+                           "FP32 Jacobi on their roundings, FP64 Rayleigh-Ritz refinement on complex128; "
+                           "one hipGraph replay per step"},
         "fp64_path": {"value": nblk / sec["fp64"], "ms_per_step": sec["fp64"] * 1e3, "dtype": "f64"},
         "mixed_bf16x3_path": {"value": nblk / sec["mixed_bf16x3"], "ms_per_step": sec["mixed_bf16x3"] * 1e3,
                               "max_abs_eig_err_ha": errs["mixed_bf16x3"][0], "info_ok": errs["mixed_bf16x3"][2]},
@@ -328,7 +330,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: FP32 Jacobi + FP64 refinement)",
                      "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s", "frac": tflops / 157.3,
                      "traffic": traffic("eig"), "flops_per_launch": flops, "avg_launch_ms": ms_heev},
-        "roofline_dft": {"bound": "hbm", "kernel": "block DFT (lhf_block_fft_dual: complex128 + complex64)",
+        "roofline_dft": {"bound": "hbm", "kernel": "block DFT (lhf_block_fft, FP64 stacks to complex128)",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("dft"),
                          "bytes_per_launch": bytes_alg, "avg_launch_ms": ms_dft},

@@ -208,7 +208,10 @@ int32_t lhf_block_fft_dual(lhf_plan_t plan, const double* d_H_gen64, const doubl
  * Cholesky reduction and cyclic parallel-order complex Jacobi sweeps; the
  * union over j is the spectrum of the full matrix pair (eq. lambdAbc).
  * Conjugate blocks j and -j share their spectrum; each pair is solved once.
- * d_H_bar, d_S_bar: device, complex128 (FP64 plan) or complex64 (mixed plan).
+ * d_H_bar, d_S_bar: device, complex128 (FP64 plan) or complex64 (mixed plan);
+ *   mixed plans with LHF_HEEV_REFINE_FP64 may pass both NULL together with
+ *   d_H_bar64 and d_S_bar64: the FP32 solve then reads the complex128 blocks
+ *   and rounds them itself (no complex64 copy is needed).
  * flags: LHF_HEEV_VECTORS, LHF_HEEV_REFINE_FP64 (mixed plans: after the FP32
  *   solve, form U^H Hbar U and U^H Sbar U in FP64 with FP64-accurate blocks
  *   and re-solve them in FP64).
@@ -319,7 +322,9 @@ int32_t lhf_toeplitz_destroy(lhf_toeplitz_t tp);
  * with a complex128 block DFT and refinement reads them, otherwise
  * refinement regenerates each block from the FP64 band.  With H_bar64 given,
  * H_gen and S_gen may be NULL: the step then skips the FP32 stacks and makes
- * H_bar and S_bar with lhf_block_fft_dual.  grams64 may be
+ * H_bar and S_bar with lhf_block_fft_dual; if H_bar and S_bar are NULL too,
+ * the step runs the FP64 block DFT only and the FP32 solve reads H_bar64 and
+ * S_bar64.  grams64 may be
  * NULL (the workspace holds the Grams), V is needed with LHF_HEEV_VECTORS. */
 typedef struct {
   void* H_gen;

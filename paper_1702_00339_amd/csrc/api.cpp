@@ -98,7 +98,12 @@ int32_t lhf_heev_batched(lhf_plan_t p, uint32_t flags, const void* H_bar, const 
                          const double* S_gen64, double* w_out, void* V, int32_t* info, void* ws,
                          size_t ws_bytes, lhf_stream_t stream) {
   if (!p) { set_error("NULL plan"); return LHF_ERR_INVALID; }
-  if (!H_bar || !S_bar || !w_out || !info) { set_error("H_bar, S_bar, w and info are required"); return LHF_ERR_INVALID; }
+  const bool direct = p->prec == LHF_PREC_MIXED && (flags & LHF_HEEV_REFINE_FP64) && !H_bar && !S_bar &&
+                      H_bar64 && S_bar64;   // the FP32 solve reads the complex128 blocks
+  if ((!direct && (!H_bar || !S_bar)) || !w_out || !info) {
+    set_error("H_bar, S_bar (or, refining a mixed plan, H_bar64 and S_bar64 alone), w and info are required");
+    return LHF_ERR_INVALID;
+  }
   if (flags & ~(uint32_t)(LHF_HEEV_VECTORS | LHF_HEEV_REFINE_FP64)) { set_error("unknown flags"); return LHF_ERR_INVALID; }
   if ((flags & LHF_HEEV_VECTORS) && !V) { set_error("LHF_HEEV_VECTORS needs V"); return LHF_ERR_INVALID; }
   const bool refine = p->prec == LHF_PREC_MIXED && (flags & LHF_HEEV_REFINE_FP64);

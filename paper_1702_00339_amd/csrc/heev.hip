@@ -598,13 +598,14 @@ struct Shape {
   static constexpr int THREADS = G * TPM;
 };
 
-// Solve from Fourier blocks of precision R.  VMODE: 0 none, 1 write vectors
-// to V (caller, sorted columns), 2 write vectors to U (FP32 workspace).
-template <typename R, int M, int VMODE, int W>
+// Solve in precision R from Fourier blocks of complex type CIN (rounded to R
+// on load).  VMODE: 0 none, 1 write vectors to V (caller, sorted columns),
+// 2 write vectors to U (FP32 workspace).
+template <typename R, int M, int VMODE, int W, typename CIN>
 __global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatDev* __restrict__ lats,
                                                                  const int2* __restrict__ canon, int ncanon,
-                                                                 const typename Cx<R>::T* __restrict__ Hb,
-                                                                 const typename Cx<R>::T* __restrict__ Sb,
+                                                                 const CIN* __restrict__ Hb,
+                                                                 const CIN* __restrict__ Sb,
                                                                  double* __restrict__ w,
                                                                  typename Cx<R>::T* __restrict__ Vout,
                                                                  int32_t* __restrict__ info, int maxsw, R tol) {
@@ -628,8 +629,9 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatD
   for (int k = 0; k < W; ++k) {
     const int e = t + k * TPM, r = e / M, c = e % M;
     const int64_t o = base + (r < m && c < m ? r * m + c : 0);
-    av[k] = Hb[o];
-    bv[k] = Sb[o];
+    const CIN hx = Hb[o], sx = Sb[o];
+    av[k] = cmk<C>((R)hx.x, (R)hx.y);
+    bv[k] = cmk<C>((R)sx.x, (R)sx.y);
   }
   if (t < 4) sh.flag[g][t] = 0;
   __syncthreads();
@@ -919,7 +921,7 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
   }
 }
 
-template <typename R, int M, int W>
+template <typename R, int M, int W, typename CIN>
 hipError_t launch_heev_mw(const lhf_plan_s* p, int vmode, const void* Hb, const void* Sb, double* w, void* V,
                           int32_t* info, int maxsw, R tol, hipStream_t s) {
   typedef typename Cx<R>::T C;
@@ -927,29 +929,37 @@ hipError_t launch_heev_mw(const lhf_plan_s* p, int vmode, const void* Hb, const 
   const int nc = p->ncanon[cls];
   const int2* canon = p->d_canon[cls];
   const dim3 grid((nc + Shape<M, W>::G - 1) / Shape<M, W>::G), block(Shape<M, W>::THREADS);
-  const C* h = (const C*)Hb;
-  const C* sm = (const C*)Sb;
+  const CIN* h = (const CIN*)Hb;
+  const CIN* sm = (const CIN*)Sb;
   if (vmode == 0)
-    hipLaunchKernelGGL((heev_kernel<R, M, 0, W>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info,
-                       maxsw, tol);
+    hipLaunchKernelGGL((heev_kernel<R, M, 0, W, CIN>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V,
+                       info, maxsw, tol);
   else if (vmode == 1)
-    hipLaunchKernelGGL((heev_kernel<R, M, 1, W>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info,
-                       maxsw, tol);
+    hipLaunchKernelGGL((heev_kernel<R, M, 1, W, CIN>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V,
+                       info, maxsw, tol);
   else
-    hipLaunchKernelGGL((heev_kernel<R, M, 2, W>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V, info,
-                       maxsw, tol);
+    hipLaunchKernelGGL((heev_kernel<R, M, 2, W, CIN>), grid, block, 0, s, p->d_lat, canon, nc, h, sm, w, (C*)V,
+                       info, maxsw, tol);
   return hipGetLastError();
 }
 
 // One launch for the class of size M, in the wide layout when the plan
 // chose it for that class.
+// (in64: the FP32 solve reads complex128 blocks)
 template <typename R, int M>
 hipError_t launch_heev_m(const lhf_plan_s* p, int vmode, const void* Hb, const void* Sb, double* w, void* V,
-                         int32_t* info, int maxsw, R tol, hipStream_t s) {
+                         int32_t* info, int maxsw, R tol, hipStream_t s, bool in64 = false) {
+  typedef typename Cx<R>::T C;
   const int cls = M == 4 ? 0 : M == 8 ? 1 : M == 16 ? 2 : 3;
   if (p->ncanon[cls] == 0) return hipSuccess;
-  if (p->heev_wide[cls]) return launch_heev_mw<R, M, 1>(p, vmode, Hb, Sb, w, V, info, maxsw, tol, s);
-  return launch_heev_mw<R, M, 4>(p, vmode, Hb, Sb, w, V, info, maxsw, tol, s);
+  if constexpr (sizeof(R) == 4) {
+    if (in64) {
+      if (p->heev_wide[cls]) return launch_heev_mw<R, M, 1, double2>(p, vmode, Hb, Sb, w, V, info, maxsw, tol, s);
+      return launch_heev_mw<R, M, 4, double2>(p, vmode, Hb, Sb, w, V, info, maxsw, tol, s);
+    }
+  }
+  if (p->heev_wide[cls]) return launch_heev_mw<R, M, 1, C>(p, vmode, Hb, Sb, w, V, info, maxsw, tol, s);
+  return launch_heev_mw<R, M, 4, C>(p, vmode, Hb, Sb, w, V, info, maxsw, tol, s);
 }
 
 template <int M, int W>
@@ -1009,10 +1019,14 @@ hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, co
   void* vdst = refine ? (void*)U : V;
   int32_t* i32 = refine ? info32 : info;
   const float eps = 5.9604645e-08f * (float)p->tol32_scale;
-  if (e == hipSuccess) e = launch_heev_m<float, 4>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 16 * eps, s);
-  if (e == hipSuccess) e = launch_heev_m<float, 8>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 32 * eps, s);
-  if (e == hipSuccess) e = launch_heev_m<float, 16>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 64 * eps, s);
-  if (e == hipSuccess) e = launch_heev_m<float, 32>(p, vm, Hbar, Sbar, w, vdst, i32, 20, 128 * eps, s);
+  // without complex64 blocks the FP32 solve reads the complex128 ones
+  const bool in64 = refine && !Hbar;
+  const void* h32 = in64 ? Hbar64 : Hbar;
+  const void* s32 = in64 ? Sbar64 : Sbar;
+  if (e == hipSuccess) e = launch_heev_m<float, 4>(p, vm, h32, s32, w, vdst, i32, 20, 16 * eps, s, in64);
+  if (e == hipSuccess) e = launch_heev_m<float, 8>(p, vm, h32, s32, w, vdst, i32, 20, 32 * eps, s, in64);
+  if (e == hipSuccess) e = launch_heev_m<float, 16>(p, vm, h32, s32, w, vdst, i32, 20, 64 * eps, s, in64);
+  if (e == hipSuccess) e = launch_heev_m<float, 32>(p, vm, h32, s32, w, vdst, i32, 20, 128 * eps, s, in64);
   if (e != hipSuccess || !refine) return e;
   if (e == hipSuccess) e = launch_refine_m<4>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
   if (e == hipSuccess) e = launch_refine_m<8>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);

@@ -40,6 +40,10 @@ int32_t check_args(const lhf_plan_s* p, const lhf_step_args* a) {
     set_error("H_gen may be NULL only in a refined mixed step that fills the complex128 blocks");
     return LHF_ERR_INVALID;
   }
+  if ((a->H_bar == nullptr) != (a->S_bar == nullptr) || (!a->H_bar && (a->H_gen || !a->H_bar64))) {
+    set_error("H_bar and S_bar may be NULL only together, in a refined mixed step without H_gen");
+    return LHF_ERR_INVALID;
+  }
   return LHF_OK;
 }
 
@@ -53,7 +57,11 @@ int32_t run_stages(lhf_plan_s* p, const lhf_step_args* a, hipStream_t s, int whi
                              mixed ? a->S_gen64 : nullptr, a->ws, a->ws_bytes, s);
     if (st != LHF_OK) return st;
   }
-  if ((which & 2) && refine && a->H_bar64 && !a->H_gen) {
+  if ((which & 2) && refine && a->H_bar64 && !a->H_gen && !a->H_bar) {
+    // the FP32 solve reads the complex128 blocks: one FP64 transform
+    st = lhf_block_fft(p, LHF_PREC_FP64, a->H_gen64, a->S_gen64, a->H_bar64, a->S_bar64, a->ws, a->ws_bytes, s);
+    if (st != LHF_OK) return st;
+  } else if ((which & 2) && refine && a->H_bar64 && !a->H_gen) {
     // one FP64 transform writes the complex128 blocks and their complex64 copies
     st = lhf_block_fft_dual(p, a->H_gen64, a->S_gen64, a->H_bar64, a->S_bar64, a->H_bar, a->S_bar, a->ws,
                             a->ws_bytes, s);

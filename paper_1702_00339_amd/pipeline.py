@@ -15,9 +15,12 @@ from . import lhf
 class Pipeline:
     """prec: lhf.LHF_PREC_FP64 or lhf.LHF_PREC_MIXED.  For the mixed path
     ``refine_src`` picks where the FP64 refinement gets its blocks:
-      "dual"  (default) the assembly writes only the FP64 stacks and one FP64
-              block DFT writes the complex128 blocks and their complex64
-              copies for the FP32 solve;
+      "direct" (default) the assembly writes only the FP64 stacks, one FP64
+              block DFT writes the complex128 blocks, and the FP32 solve
+              reads them (rounding on load);
+      "dual"  the assembly writes only the FP64 stacks and one FP64 block
+              DFT writes the complex128 blocks and their complex64 copies
+              for the FP32 solve;
       "bar64" FP32 stacks and a complex64 DFT for the FP32 solve, plus a
               separate complex128 DFT of the FP64 stacks;
       "band"  FP32 stacks and a complex64 DFT; refinement regenerates each
@@ -52,12 +55,12 @@ class Pipeline:
         self.H_gen64 = self.S_gen64 = self.H_bar64 = self.S_bar64 = None
         if prec == lhf.LHF_PREC_MIXED:
             if refine_src == "auto":
-                refine_src = "dual"
-            assert refine_src in ("dual", "bar64", "band")
+                refine_src = "direct"
+            assert refine_src in ("direct", "dual", "bar64", "band")
             self.refine_src = refine_src
             self.H_gen64 = torch.empty(G, dtype=torch.float64, device=dev)
             self.S_gen64 = torch.empty(G, dtype=torch.float64, device=dev)
-            if refine_src in ("bar64", "dual"):
+            if refine_src in ("bar64", "dual", "direct"):
                 self.H_bar64 = torch.empty(G, dtype=torch.complex128, device=dev)
                 self.S_bar64 = torch.empty(G, dtype=torch.complex128, device=dev)
         else:
@@ -71,10 +74,12 @@ class Pipeline:
         flags = lhf.LHF_HEEV_VECTORS if self.want_vectors else 0
         if self.prec == lhf.LHF_PREC_MIXED:
             flags |= lhf.LHF_HEEV_REFINE_FP64
-        dual = self.prec == lhf.LHF_PREC_MIXED and self.refine_src == "dual"
+        dual = self.prec == lhf.LHF_PREC_MIXED and self.refine_src in ("dual", "direct")
+        direct = self.prec == lhf.LHF_PREC_MIXED and self.refine_src == "direct"
         return lhf.lhf_step_args(None if dual else ptr(self.H_gen), None if dual else ptr(self.S_gen),
-                                 ptr(self.grams64), ptr(self.H_gen64),
-                                 ptr(self.S_gen64), ptr(self.H_bar), ptr(self.S_bar), ptr(self.H_bar64),
+                                 ptr(self.grams64), ptr(self.H_gen64), ptr(self.S_gen64),
+                                 None if direct else ptr(self.H_bar), None if direct else ptr(self.S_bar),
+                                 ptr(self.H_bar64),
                                  ptr(self.S_bar64), ptr(self.w), ptr(self.V), ptr(self.info), ptr(self.ws),
                                  self.ws.numel(), flags)
 
@@ -97,7 +102,10 @@ class Pipeline:
             flags = lhf.LHF_HEEV_VECTORS if self.want_vectors else 0
             p.lhf_heev_batched(flags, self.H_bar, self.S_bar, self.w, self.info, self.ws, V=self.V)
             return
-        if self.refine_src == "dual":
+        if self.refine_src == "direct":
+            p.lhf_assemble_blocks(None, None, self.grams64, self.ws, H_gen64=self.H_gen64, S_gen64=self.S_gen64)
+            p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.ws)
+        elif self.refine_src == "dual":
             p.lhf_assemble_blocks(None, None, self.grams64, self.ws, H_gen64=self.H_gen64, S_gen64=self.S_gen64)
             p.lhf_block_fft_dual(self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.H_bar, self.S_bar,
                                  self.ws)
@@ -108,7 +116,9 @@ class Pipeline:
         if self.refine_src == "bar64":
             p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.ws)
         flags = lhf.LHF_HEEV_REFINE_FP64 | (lhf.LHF_HEEV_VECTORS if self.want_vectors else 0)
-        p.lhf_heev_batched(flags, self.H_bar, self.S_bar, self.w, self.info, self.ws, V=self.V,
+        direct = self.refine_src == "direct"
+        p.lhf_heev_batched(flags, None if direct else self.H_bar, None if direct else self.S_bar, self.w,
+                           self.info, self.ws, V=self.V,
                            H_bar64=self.H_bar64, S_bar64=self.S_bar64, H_gen64=self.H_gen64, S_gen64=self.S_gen64)
 
     def eigenvalues(self):

@@ -41,8 +41,16 @@ def _mix():
             tiny_instance(L=(1, 1, 1), n=(20, 16, 16), n_s=2, seed=164)]
 
 
+def _blocks(pipe):
+    """The Fourier block buffers the pipeline's step writes."""
+    out = [] if pipe.refine_src == "direct" else [pipe.H_bar, pipe.S_bar]
+    if pipe.H_bar64 is not None:
+        out += [pipe.H_bar64, pipe.S_bar64]
+    return out
+
+
 def _outputs(pipe):
-    out = [pipe.w.clone(), pipe.info.clone(), pipe.H_bar.clone(), pipe.S_bar.clone()]
+    out = [pipe.w.clone(), pipe.info.clone()] + [b.clone() for b in _blocks(pipe)]
     if pipe.V is not None:
         out.append(pipe.V.clone())
     return out
@@ -51,8 +59,8 @@ def _outputs(pipe):
 def _poison(pipe):
     pipe.w.fill_(float("nan"))
     pipe.info.fill_(99)
-    pipe.H_bar.zero_()
-    pipe.S_bar.zero_()
+    for b in _blocks(pipe):
+        b.zero_()
     if pipe.V is not None:
         pipe.V.zero_()
 
