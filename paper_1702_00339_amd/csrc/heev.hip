@@ -79,9 +79,14 @@ __device__ __forceinline__ int conj_block(const LatDev& L, int b) {
 template <typename R, int M, int G, bool HASU, bool HASV>
 struct Smem {
   typedef typename Cx<R>::T C;
+  // F (the reduction's W, the refinement's series) is absent in the
+  // refinement without vectors for M >= 16, which keeps those in the dead U
+  // instead (more resident matrices; at M <= 8 the fourth matrix costs less
+  // than the extra passes)
+  static constexpr bool HASF = HASV || !HASU || M <= 8;
   C A[G][M][M + 1];
   C B[G][M][M + 1];
-  C F[G][M][M + 1];              // Cholesky factor
+  C F[HASF ? G : 1][HASF ? M : 1][M + 1];
   C V[HASV ? G : 1][HASV ? M : 1][M + 1];
   C U[HASU ? G : 1][HASU ? M : 1][M + 1];
   R red[G][16];                  // cross-wave partial sums
@@ -287,11 +292,15 @@ __device__ __forceinline__ void mm_tile_lh_diag(const C (&X)[M][M + 1], const R 
 // A <- C^-1 A C^-H = D^-1/2 (W A W^H) D^-1/2 by two tiled products, made
 // Hermitian.  One barrier per column; V <- I when HASV.  A non-positive
 // pivot j is reported as j + 1 in flag 0.
-template <int W, typename R, int M, int G, bool HASU, bool HASV>
+// W goes to F, or to U where F is absent (WINU).
+template <int W, bool WINU, typename R, int M, int G, bool HASU, bool HASV>
 __device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
   typedef typename Cx<R>::T C;
+  auto& Wm = [&]() -> auto& {
+    if constexpr (WINU) return sh.U[g]; else return sh.F[g];
+  }();
   constexpr int TPM = M * M / W, NT = TileOf<W>::NT, S = M / NT;
-  LHF_FOR_ENTRIES { sh.F[g][r][c] = cmk<C>(r == c ? R(1) : R(0), R(0)); }
+  LHF_FOR_ENTRIES { Wm[r][c] = cmk<C>(r == c ? R(1) : R(0), R(0)); }
   __syncthreads();
 #pragma unroll 1
   for (int j = 0; j < M - 1; ++j) {
@@ -302,17 +311,17 @@ __device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
     C xv[W], wv[W];
     LHF_FOR_ENTRIES {
       xv[k] = sh.B[g][r][c];
-      wv[k] = sh.F[g][r][c];
+      wv[k] = Wm[r][c];
       if (r > j) {
         const C f = cscale(sh.B[g][r][j], dinv);
         if (c > j) xv[k] = csub(xv[k], cmul(f, sh.B[g][j][c]));
-        else wv[k] = csub(wv[k], cmul(f, sh.F[g][j][c]));
+        else wv[k] = csub(wv[k], cmul(f, Wm[j][c]));
       }
     }
     LHF_FOR_ENTRIES {
       if (r > j) {
         if (c > j) sh.B[g][r][c] = xv[k];
-        else sh.F[g][r][c] = wv[k];
+        else Wm[r][c] = wv[k];
       }
     }
     __syncthreads();
@@ -325,11 +334,11 @@ __device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
   int ti, tj;
   tile_coords<M, NT>(t, ti, tj);
   C p[NT][NT];
-  mm_tile_rh<M, NT>(sh.A[g], sh.F[g], ti, tj, p);   // T = A W^H
+  mm_tile_rh<M, NT>(sh.A[g], Wm, ti, tj, p);   // T = A W^H
   __syncthreads();
   store_tile<M, NT>(sh.A[g], ti, tj, p);
   __syncthreads();
-  mm_tile<M, NT, false>(sh.F[g], sh.A[g], ti, tj, R(0), p);   // W T, scaled by D^-1/2 on both sides
+  mm_tile<M, NT, false>(Wm, sh.A[g], ti, tj, R(0), p);   // W T, scaled by D^-1/2 on both sides
 #pragma unroll
   for (int a = 0; a < NT; ++a)
 #pragma unroll
@@ -654,7 +663,7 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatD
   }
   if (bad) sh.flag[g][1] = 1;
   __syncthreads();
-  chol_reduce<W>(sh, g, t);
+  chol_reduce<W, false>(sh, g, t);
   const int cur = jacobi<W, R, M, G, false, WANTV, WANTV>(sh, g, t, maxsw, tol);
   eig_rank(sh, g, t, m, cur);
   if constexpr (WANTV) backsub_vectors<W>(sh, g, t);
@@ -682,6 +691,11 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatD
     info[L.blk_off + blk] = st;
     if (cblk != blk) info[L.blk_off + cblk] = st;
   }
+}
+
+template <typename SM>
+__device__ __forceinline__ auto& xbuf(SM& sh, int g) {
+  if constexpr (SM::HASF) return sh.F[g]; else return sh.U[g];
 }
 
 // Refinement in FP64 from FP32 eigenvectors U (layout [blk][row][col]).
@@ -740,9 +754,10 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
   // the band descriptors is read, so no load waits behind the block loads)
   int j1 = 0, j2 = 0, j3 = 0, ns1 = 1, ns2 = 1, ns3 = 1, ncell = 0;
   bool twl = false;
-  // band-cell twiddles w^(j.k) of this block, cached in the storage of F,
-  // which is free until the refinement's series
-  C* twc = &sh.F[g][0][0];
+  // band-cell twiddles w^(j.k) of this block, cached in the storage of F
+  // (free until the series) or, without F, of A until every lane has formed
+  // its block entries
+  C* twc = Smem<R, M, G, true, WANTV>::HASF ? &xbuf(sh, g)[0][0] : &sh.A[g][0][0];
   if (!H64) {
     j3 = blk % L.L[2];
     j2 = (blk / L.L[2]) % L.L[1];
@@ -762,6 +777,7 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
     }
   }
   __syncthreads();
+  C ue[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) {
     const int e = t + k * TPM, r = e / M, c = e % M;
@@ -792,15 +808,35 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
       }
       if (!fresh) u = cmk<C>((double)uv[k].x, (double)uv[k].y);
     }
-    sh.A[g][r][c] = h;
-    sh.B[g][r][c] = s;
-    sh.U[g][r][c] = u;
+    if constexpr (Smem<R, M, G, true, WANTV>::HASF) {
+      sh.A[g][r][c] = h;
+      sh.B[g][r][c] = s;
+      sh.U[g][r][c] = u;
+    } else {
+      hv[k] = h;
+      sv[k] = s;
+      ue[k] = u;
+    }
+  }
+  if constexpr (!Smem<R, M, G, true, WANTV>::HASF) {
+    __syncthreads();   // the twiddle cache in A is no longer read
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int e = t + k * TPM, r = e / M, c = e % M;
+      sh.A[g][r][c] = hv[k];
+      sh.B[g][r][c] = sv[k];
+      sh.U[g][r][c] = ue[k];
+    }
   }
   __syncthreads();
   // Rayleigh-Ritz pair: A <- U^H Hbar U, B <- U^H Sbar U (two fused passes)
   constexpr int NT = TileOf<W>::NT;
   int ti, tj;
   tile_coords<M, NT>(t, ti, tj);
+  // X = (I + E)^-1/2, or the reduction's W: F where it exists, else U, dead
+  // after the Rayleigh-Ritz products
+  constexpr bool HASF = Smem<R, M, G, true, WANTV>::HASF;
+  auto& Xm = xbuf(sh, g);
   {
     C p1[NT][NT], p2[NT][NT];
     mm_shared_right<M, NT>(sh.A[g], sh.B[g], sh.U[g], ti, tj, p1, p2);
@@ -843,42 +879,74 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
       return k == 0 ? R(1.0) : k == 1 ? R(-0.5) : k == 2 ? R(0.375) : k == 3 ? R(-0.3125)
              : k == 4 ? R(0.2734375) : R(-0.24609375);
     };
-    // E in B; F <- cf_deg E + cf_(deg-1) I, then F <- E F + cf_k I for k = deg-2 .. 0
+    // E in B; X <- cf_deg E + cf_(deg-1) I, then X <- E X + cf_k I for k = deg-2 .. 0
     LHF_FOR_ENTRIES {
       C ev = sh.B[g][r][c];
       if (r == c) ev.x -= R(1);
       sh.B[g][r][c] = ev;
       C f = cscale(ev, cf(deg));
       if (r == c) f.x += cf(deg - 1);
-      sh.F[g][r][c] = f;
+      Xm[r][c] = f;
     }
     __syncthreads();
 #pragma unroll 1
     for (int h = deg - 2; h >= 0; --h) {
-      mm_tile<M, NT, true>(sh.B[g], sh.F[g], ti, tj, cf(h), p);
+      mm_tile<M, NT, true>(sh.B[g], Xm, ti, tj, cf(h), p);
       __syncthreads();
-      store_tile<M, NT>(sh.F[g], ti, tj, p);
+      store_tile<M, NT>(Xm, ti, tj, p);
       __syncthreads();
     }
-    // T <- A X (into the dead U, or V with vectors), then B <- X T (E is
-    // dead), then A <- the Hermitian part of B and V <- I
-    mm_tile<M, NT, false>(sh.A[g], sh.F[g], ti, tj, R(0), p);
-    if constexpr (WANTV) store_tile<M, NT>(sh.V[g], ti, tj, p); else store_tile<M, NT>(sh.U[g], ti, tj, p);
-    __syncthreads();
-    if constexpr (WANTV) mm_tile<M, NT, false>(sh.F[g], sh.V[g], ti, tj, R(0), p);
-    else mm_tile<M, NT, false>(sh.F[g], sh.U[g], ti, tj, R(0), p);
-    store_tile<M, NT>(sh.B[g], ti, tj, p);
-    __syncthreads();
-    LHF_FOR_ENTRIES {
-      const C x = sh.B[g][r][c], y = sh.B[g][c][r];
-      C s2 = cmk<C>(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
-      if (r == c) s2.y = 0.0;
-      sh.A[g][r][c] = s2;
-      if constexpr (WANTV) sh.V[g][r][c] = cmk<C>(r == c ? 1.0 : 0.0, 0.0);
+    if constexpr (WANTV) {
+      // T <- A X into V, then B <- X T (E is dead), then A <- the Hermitian
+      // part of B and V <- I
+      mm_tile<M, NT, false>(sh.A[g], Xm, ti, tj, R(0), p);
+      store_tile<M, NT>(sh.V[g], ti, tj, p);
+      __syncthreads();
+      mm_tile<M, NT, false>(Xm, sh.V[g], ti, tj, R(0), p);
+      store_tile<M, NT>(sh.B[g], ti, tj, p);
+      __syncthreads();
+      LHF_FOR_ENTRIES {
+        const C x = sh.B[g][r][c], y = sh.B[g][c][r];
+        C s2 = cmk<C>(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+        if (r == c) s2.y = 0.0;
+        sh.A[g][r][c] = s2;
+        sh.V[g][r][c] = cmk<C>(r == c ? 1.0 : 0.0, 0.0);
+      }
+      __syncthreads();
+    } else if constexpr (HASF) {
+      // T <- A X into the dead U, then B <- X T (E is dead), then A <- the
+      // Hermitian part of B
+      mm_tile<M, NT, false>(sh.A[g], Xm, ti, tj, R(0), p);
+      store_tile<M, NT>(sh.U[g], ti, tj, p);
+      __syncthreads();
+      mm_tile<M, NT, false>(Xm, sh.U[g], ti, tj, R(0), p);
+      store_tile<M, NT>(sh.B[g], ti, tj, p);
+      __syncthreads();
+      LHF_FOR_ENTRIES {
+        const C x = sh.B[g][r][c], y = sh.B[g][c][r];
+        sh.A[g][r][c] = cmk<C>(0.5 * (x.x + y.x), r == c ? 0.0 : 0.5 * (x.y - y.y));
+      }
+      __syncthreads();
+    } else {
+      // X is in U: T <- A X into B (E is dead), A <- X T, then A <- its
+      // Hermitian part
+      mm_tile<M, NT, false>(sh.A[g], Xm, ti, tj, R(0), p);
+      store_tile<M, NT>(sh.B[g], ti, tj, p);
+      __syncthreads();
+      mm_tile<M, NT, false>(Xm, sh.B[g], ti, tj, R(0), p);
+      store_tile<M, NT>(sh.A[g], ti, tj, p);
+      __syncthreads();
+      C hs[W];
+      LHF_FOR_ENTRIES {
+        const C x = sh.A[g][r][c], y = sh.A[g][c][r];
+        hs[k] = cmk<C>(0.5 * (x.x + y.x), r == c ? 0.0 : 0.5 * (x.y - y.y));
+      }
+      __syncthreads();
+      LHF_FOR_ENTRIES { sh.A[g][r][c] = hs[k]; }
+      __syncthreads();
     }
-    __syncthreads();
   } else {
-    chol_reduce<W>(sh, g, t);
+    chol_reduce<W, !HASF>(sh, g, t);
   }
   const int cur = jacobi<W, R, M, G, true, WANTV, WANTV>(sh, g, t, maxsw, tol);
   eig_rank(sh, g, t, m, cur);
