@@ -42,7 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # eigensolve call (FP32 Jacobi + FP64 refinement kernels) and block DFT, from two rocprofv3 --pmc runs of
 # `bench.py --probe-traffic` (profiles/traffic_per_dispatch.md).  Valid for the kernels as they were when
 # counted; absent (reported as null) where not counted.
-TRAFFIC_KIB = {}
+TRAFFIC_KIB = {"c2": {"eig": 1671.7, "dft": 2357.6},
+               "c3": {"eig": 51024.1, "dft": 66783.3},
+               "c4": {"eig": 843254.8, "dft": 1204188.1}}
 
 
 def parse():
