@@ -297,7 +297,9 @@ size_t lhf_toeplitz_eigs_workspace(lhf_toeplitz_t tp, int32_t nev);
  * with nev + 4 vectors: basis [X, W, P], W the residuals through the circulant
  * preconditioner (H_c - sigma S_c)^-1 per frequency (H_c, S_c the embedding's
  * blocks; sigma below their spectrum), images recomputed by matvecs every
- * iteration, S-orthonormalised in FP64 (SVQB), FP64 Rayleigh-Ritz; matvecs in
+ * iteration, S-orthonormalised in FP64 (Cholesky-QR in the column order
+ * [X, W, P], dropping columns whose squared distance from the span of the
+ * ones before them is below 1e-10), FP64 Rayleigh-Ritz; matvecs in
  * FP32 until the largest residual of the wanted pairs is below 1e-4, then in
  * FP64 until it is below tol.  The start block is drawn from a counter-based
  * generator (SplitMix64) with `seed`.  Runs on `stream` and synchronises it

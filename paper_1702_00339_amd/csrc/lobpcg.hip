@@ -1,5 +1,5 @@
 // Dense FP64 kernels of the block LOBPCG driver: Gram products of tall
-// blocks, block combinations, residuals, SVQB helpers and a one-workgroup
+// blocks, block combinations, residuals, Cholesky-QR orthonormalisation and a one-workgroup
 // symmetric eigensolver for the Rayleigh-Ritz problems (size <= 112).
 //
 // Blocks of vectors are row-major [N][ld] (column j = vector j).  Reductions
@@ -147,12 +147,77 @@ __global__ void __launch_bounds__(256) scale_sym_kernel(int m, const double* __r
   }
 }
 
-__global__ void __launch_bounds__(256) svqb_t_kernel(int m, int kk, int first, const double* __restrict__ U, int ldu,
-                                                     const double* __restrict__ lam, const double* __restrict__ d,
-                                                     double* __restrict__ T, int ldt) {
-  for (int e = threadIdx.x; e < m * kk; e += 256) {
-    const int i = e / kk, j = e % kk;
-    T[i * ldt + j] = d[i] * U[i * ldu + first + j] / sqrt(lam[first + j]);
+constexpr int kCholThreads = 1024;   // 8 row groups x 128 columns
+constexpr int kCholCols = 128;
+static_assert(kMaxSmall <= kCholCols, "one column per lane of a row group");
+
+// S-orthonormalisation by Cholesky-QR with deflation, one workgroup.  Gs is
+// the scaled Gram matrix D G D (unit diagonal) of the basis columns in the
+// order [X W P].  Gaussian elimination of [Gs | I] by rows yields the unit
+// lower triangular L^-1 =: E and the pivots p_j (Schur complements: the
+// squared S-distance of scaled column j from the span of the kept columns
+// before it), with E Gs E^T = diag(p).  A column whose pivot is at most
+// `drop` is not used to eliminate and gets no output column, so the kept
+// set K satisfies E_KK Gs_KK E_KK^T = diag(p_K).  Output: the kk kept columns
+// of T = D E^T diag(p)^-1/2 (m x kk, upper triangular in the kept indices;
+// T^T G T = I), and kk in *kk_out (as a double).
+//
+// E and the eliminated Gs share one m x m array in LDS: before step j, row
+// i > j holds E[i][c] in slots c < j and the partially eliminated Gs in
+// slots c >= j.  Step j reads row j and a snapshot of column j (written by
+// the previous step into a double-buffered vector), so one barrier per step.
+__global__ void __launch_bounds__(kCholThreads) cholqr_t_kernel(int m, const double* __restrict__ Gs, int ldg,
+                                                                const double* __restrict__ d, double drop,
+                                                                double* __restrict__ T, int ldt,
+                                                                double* __restrict__ kk_out) {
+  extern __shared__ double a[];   // m x m, row stride m
+  __shared__ double colv[2][kMaxSmall], rs[kMaxSmall];
+  __shared__ int src[kMaxSmall];
+  __shared__ int nkeep;
+  const int tid = threadIdx.x, c = tid % kCholCols, rg = tid / kCholCols;
+  constexpr int kRG = kCholThreads / kCholCols;
+  for (int e = tid; e < m * m; e += kCholThreads) {
+    const int i = e / m, k = e - i * m;
+    a[e] = Gs[i * ldg + k];
+    if (k == 0) colv[0][i] = a[e];
+  }
+  __syncthreads();
+  for (int j = 0; j + 1 < m; ++j) {
+    const double* cj = colv[j & 1];
+    double* cn = colv[(j + 1) & 1];
+    const double p = cj[j];
+    const double rp = p > drop ? 1.0 / p : 0.0;   // dropped: f = 0 leaves the rows as they are
+    if (c < m) {
+      const double rj = a[j * m + c];
+      for (int i = j + 1 + rg; i < m; i += kRG) {
+        const double f = cj[i] * rp;
+        // c < j: E[i][c] -= f E[j][c]; c == j: E[i][j] = -f (E[j][j] = 1); c > j: Schur update
+        const double v = c == j ? -f : a[i * m + c] - f * rj;
+        a[i * m + c] = v;
+        if (c == j + 1) cn[i] = v;
+      }
+    }
+    __syncthreads();
+  }
+  // slot (j, j) holds p_j, slots (j, c < j) hold E[j][c]
+  if (tid == 0) {
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      const double p = a[j * m + j];
+      if (p > drop) {
+        rs[k] = 1.0 / sqrt(p);
+        src[k++] = j;
+      }
+    }
+    nkeep = k;
+    *kk_out = (double)k;
+  }
+  __syncthreads();
+  const int kk = nkeep;
+  for (int e = tid; e < m * kk; e += kCholThreads) {
+    const int r = e / kk, k = e - r * kk, j = src[k];
+    const double ejr = r < j ? a[j * m + r] : (r == j ? 1.0 : 0.0);
+    T[r * ldt + k] = d[r] * ejr * rs[k];
   }
 }
 
@@ -416,9 +481,12 @@ hipError_t dense_scale_sym(int m, const double* G, int ldg, double* Gs, int lds,
   return hipGetLastError();
 }
 
-hipError_t dense_svqb_t(int m, int kk, int first, const double* U, int ldu, const double* lam, const double* dvec,
-                        double* T, int ldt, hipStream_t s) {
-  hipLaunchKernelGGL(svqb_t_kernel, dim3(1), dim3(256), 0, s, m, kk, first, U, ldu, lam, dvec, T, ldt);
+hipError_t dense_cholqr_t(int m, const double* Gs, int ldg, const double* dvec, double drop, double* T, int ldt,
+                          double* kk_out, hipStream_t s) {
+  if (m < 1 || m > kMaxSmall) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * (size_t)m * m;
+  (void)hipFuncSetAttribute((const void*)cholqr_t_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(cholqr_t_kernel, dim3(1), dim3(kCholThreads), lds, s, m, Gs, ldg, dvec, drop, T, ldt, kk_out);
   return hipGetLastError();
 }
 

@@ -414,10 +414,11 @@ namespace {
 
 constexpr int kGuard = 4;     // block vectors beyond the wanted ones
 constexpr int kChunks = 32;   // row chunks of the tall reductions
+constexpr double kDropPivot = 1e-10;   // Cholesky-QR: squared relative distance below which a column is dropped
 
 struct EigWs {
   double *X, *HX, *SX, *P, *R, *W, *Q, *HQ, *SQ, *Q2, *HQ2, *SQ2;
-  double *G, *Gs, *U, *lam, *dvec, *T, *GH, *th, *C, *C2, *norms, *syw, *part, *rpart;
+  double *G, *Gs, *lam, *dvec, *T, *GH, *th, *C, *C2, *norms, *syw, *part, *rpart;
   char* mv;
   size_t mv_bytes;
 };
@@ -436,7 +437,7 @@ size_t eigs_layout(const lhf_toeplitz_s* t, int nev, EigWs* w, char* base) {
   take(d.Q, N * mx); take(d.HQ, N * mx); take(d.SQ, N * mx);
   take(d.Q2, N * mx); take(d.HQ2, N * mx); take(d.SQ2, N * mx);
   const size_t sq = (size_t)kMaxSmall * kMaxSmall;
-  take(d.G, sq); take(d.Gs, sq); take(d.U, sq); take(d.lam, kMaxSmall); take(d.dvec, kMaxSmall);
+  take(d.G, sq); take(d.Gs, sq); take(d.lam, kMaxSmall); take(d.dvec, kMaxSmall);
   take(d.T, sq); take(d.GH, sq); take(d.th, kMaxSmall); take(d.C, sq); take(d.C2, sq); take(d.norms, kMaxSmall);
   take(d.syw, sq); take(d.part, (size_t)kChunks * sq); take(d.rpart, (size_t)kChunks * kMaxSmall);
   d.mv_bytes = lhf_toeplitz_matvec_workspace(const_cast<lhf_toeplitz_s*>(t), mx);
@@ -515,20 +516,18 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t t, int32_t nev, int32_t maxit, double t
         m = 3 * nb;
       }
     }
-    // images of the basis, then its S-orthonormalisation (SVQB)
+    // images of the basis, then its S-orthonormalisation: Cholesky-QR of the
+    // scaled Gram matrix in the column order [X W P], dropping columns that
+    // are numerically in the span of the ones before them
     matvec(prec, m, w.Q, mx, w.HQ, w.SQ);
     ck(dense_gram(N, m, m, w.Q, mx, w.SQ, mx, w.part, kChunks, w.G, S, s));
     ck(dense_scale_sym(m, w.G, S, w.Gs, S, w.dvec, s));
-    ck(dense_syev_w(m, w.Gs, S, w.lam, w.U, S, w.syw, s));
-    ck(hipMemcpyAsync(hl.data(), w.lam, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    ck(dense_cholqr_t(m, w.Gs, S, w.dvec, kDropPivot, w.T, S, w.lam, s));
+    ck(hipMemcpyAsync(hl.data(), w.lam, sizeof(double), hipMemcpyDeviceToHost, s));
     ck(hipStreamSynchronize(s));
     if (e != hipSuccess) break;
-    const double lmax = hl[m - 1];
-    int first = 0;
-    while (first < m && !(hl[first] > 1e-10 * lmax)) ++first;
-    const int kk = m - first;
+    const int kk = (int)hl[0];
     if (kk < nb) { st = LHF_ERR_INVALID; set_error("LOBPCG basis lost rank"); break; }
-    ck(dense_svqb_t(m, kk, first, w.U, S, w.lam, w.dvec, w.T, S, s));
     ck(dense_combine(N, m, kk, w.Q, mx, w.T, S, 0.0, nullptr, 0, w.Q2, mx, s));
     ck(dense_combine(N, m, kk, w.HQ, mx, w.T, S, 0.0, nullptr, 0, w.HQ2, mx, s));
     ck(dense_combine(N, m, kk, w.SQ, mx, w.T, S, 0.0, nullptr, 0, w.SQ2, mx, s));

@@ -92,9 +92,12 @@ hipError_t dense_random(int N, int k, uint64_t seed, double* X, int ld, hipStrea
 hipError_t dense_copy_cols(int N, int k, const double* A, int lda, double* B, int ldb, hipStream_t s);
 // Gs = D G D with D = diag(G)^-1/2 (d written to dvec)
 hipError_t dense_scale_sym(int m, const double* G, int ldg, double* Gs, int lds, double* dvec, hipStream_t s);
-// T[:, j] = D U[:, first + j] / sqrt(lam[first + j]), j < kk
-hipError_t dense_svqb_t(int m, int kk, int first, const double* U, int ldu, const double* lam, const double* dvec,
-                        double* T, int ldt, hipStream_t s);
+// Cholesky-QR of the scaled Gram Gs (unit diagonal) with deflation: columns
+// whose pivot (squared distance from the span of the kept columns before
+// them) is <= drop are dropped; T (m x kk) = D L^-T diag(p)^-1/2 on the kept
+// columns, so T^T G T = I; kk written to *kk_out as a double
+hipError_t dense_cholqr_t(int m, const double* Gs, int ldg, const double* dvec, double drop, double* T, int ldt,
+                          double* kk_out, hipStream_t s);
 hipError_t dense_symmetrize(int m, double* G, int ldg, hipStream_t s);
 
 }  // namespace lhf
