@@ -232,52 +232,100 @@ __global__ void __launch_bounds__(256) symmetrize_kernel(int m, double* __restri
   }
 }
 
-// Round-robin pair i of round s among Me indices (Me even; 0 <= s, i < Me - 1).
-__device__ __forceinline__ void rr_pair(int i, int s, int Me, int& p, int& q) {
-  const int m = Me - 1;
-  if (i == 0) {
-    p = 0;
-    q = 1 + s;
-  } else {
-    int a = s + i, b = s - i + m;   // both in (0, 2m)
-    if (a >= m) a -= m;
-    if (b >= m) b -= m;
-    p = 1 + a;
-    q = 1 + b;
+// Real symmetric eigensolver, one workgroup: cyclic Jacobi in the parallel
+// round-robin order (size padded to even Me with a decoupled zero index),
+// everything in LDS.
+//
+// A is kept in "slot space": the Me indices occupy Me storage slots, and the
+// pairs of every round are the same slot pairs, (0, 1) and (1 + i, Me - i)
+// for i = 1 .. Me/2 - 1.  After each round the contents of slots 2 .. Me-1
+// move down one slot, slot 1 moves to slot Me-1 and slot 0 stays (the
+// circle method of the round-robin tournament), so after the Me - 1 rounds
+// of a sweep every slot holds its own index again.  Storage follows the
+// pairs: the diagonal 2 x 2 block of pair i as three arrays (first-first,
+// second-second, first-second), and the blocks of pairs bi < bj as four
+// arrays (entry first/second of bi times first/second of bj) indexed by the
+// block's rank in the strict upper triangle.  A thread owns fixed blocks and
+// reads and writes fixed addresses every round: consecutive threads own
+// consecutive blocks of a block row, so loads and stores are contiguous, and
+// the loop has no index arithmetic.  A round is two phases: the first wave
+// computes the rotations of the pairs from their diagonal blocks while the
+// other threads load their blocks; after a barrier the rotated blocks are
+// written to the shifted slots and the eigenvector items are rotated.
+//
+// V (eigenvectors, column j contiguous) stays in index space: an item (pair,
+// row) updates its two entries in place; the column addresses advance by one
+// index per round along the circle.
+//
+// Stops at a sweep boundary once the off-diagonal Frobenius norm is below
+// 4 Me eps of the norm of A.  Output: eigenvalues ascending in w,
+// eigenvector j in column j of Vout.
+__device__ __forceinline__ int slot_first(int i) { return i == 0 ? 0 : 1 + i; }
+__device__ __forceinline__ int slot_second(int i, int Me) { return i == 0 ? 1 : Me - i; }
+__device__ __forceinline__ int slot_shift(int x, int Me) { return x == 0 ? 0 : (x == 1 ? Me - 1 : x - 1); }
+// pair holding slot x; first = whether x is the pair's first slot
+__device__ __forceinline__ int slot_pair(int x, int Me, bool& first) {
+  if (x <= 1) {
+    first = x == 0;
+    return 0;
+  }
+  first = x <= Me / 2;
+  return first ? x - 1 : Me - x;
+}
+// rank of the block of pairs bi < bj in the strict upper triangle (row-major)
+__device__ __forceinline__ int offblk(int bi, int bj, int H) { return bi * H - (bi * (bi + 1)) / 2 + (bj - bi - 1); }
+// storage offset of the entry of slots (x, y) (symmetric)
+__device__ __forceinline__ int jstore(int x, int y, int Me) {
+  const int H = Me / 2, nob = H * (H - 1) / 2;
+  bool fx, fy;
+  int px = slot_pair(x, Me, fx), py = slot_pair(y, Me, fy);
+  if (px == py) return x == y ? (fx ? px : H + px) : 2 * H + px;
+  if (px > py) {
+    const int t = px; px = py; py = t;
+    const bool u = fx; fx = fy; fy = u;
+  }
+  return 3 * H + ((fx ? 0 : 2) + (fy ? 0 : 1)) * nob + offblk(px, py, H);
+}
+
+// Rotation annihilating b = A(p, q): with d = aqq - app, r = sqrt(d^2 + 4 b^2)
+// and u = |d| + r, the classical t = sign(d) 2|b| / u gives c = u rho and
+// s = sign(d) 2 b rho with rho = (2 r u)^-1/2, and t |b| = 2 b^2 / u =
+// 4 b^2 r rho^2 (no division; no cancellation for small or large angles).
+// dp, dq: the rotated diagonal entries.
+__device__ __forceinline__ void jacobi_rot(double app, double aqq, double b, double& c, double& s, double& dp,
+                                           double& dq) {
+  c = 1.0;
+  s = 0.0;
+  dp = app;
+  dq = aqq;
+  if (b != 0.0) {
+    const double d = aqq - app, sd = d >= 0.0 ? 1.0 : -1.0;
+    const double r = sqrt(d * d + 4.0 * b * b), u = fabs(d) + r, rho = rsqrt(2.0 * r * u);
+    c = u * rho;
+    s = sd * 2.0 * b * rho;
+    const double del = 4.0 * b * b * r * rho * rho;
+    dp = app - sd * del;
+    dq = aqq + sd * del;
   }
 }
 
 constexpr int kSyevThreads = 1024;
 
-// Real symmetric eigensolver, one workgroup: cyclic Jacobi in the parallel
-// round-robin order (size padded to even Me with a decoupled zero index).
-// Everything lives in LDS: A as its packed upper triangle (the rotations keep
-// it symmetric, so each unordered 2 x 2 block pair is rotated once) and V
-// transposed (column c of V contiguous).  Rotations are computed by one
-// thread per pair; blocks (bi <= bj) of A and rows of the pairs' V columns
-// are spread over the threads.  Stops when the off-diagonal Frobenius norm
-// is below 4 Me eps of the norm of A.  Output: eigenvalues ascending in w,
-// eigenvector j in column j of Vout.
-__device__ __forceinline__ int tri_index(int r, int c, int Me) {
-  if (r > c) { const int x = r; r = c; c = x; }
-  return r * Me - (r * (r - 1)) / 2 + (c - r);
-}
-
 __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double* __restrict__ Ain, int lda,
                                                             double* __restrict__ w, double* __restrict__ Vout,
                                                             int ldv) {
   extern __shared__ double lds[];
-  __shared__ double cs[kMaxSmall / 2], sn[kMaxSmall / 2], dn[kMaxSmall], red[kSyevThreads / 64];
+  __shared__ double rc[kMaxSmall / 2], rs[kMaxSmall / 2];   // this round's rotations
+  __shared__ double red[kSyevThreads / 64];
   __shared__ int rank[kMaxSmall];
   __shared__ int done;
-  const int Me = m + (m & 1), H = Me / 2;
-  double* A = lds;                         // packed upper triangle, Me (Me + 1) / 2
-  double* V = lds + Me * (Me + 1) / 2;     // transposed: V[c * Me + r] is entry (r, c)
+  const int Me = m + (m & 1), H = Me / 2, Mc = Me - 1, nob = H * (H - 1) / 2;
+  double* A = lds;                   // pair-block storage over slots, Me (Me + 1) / 2
+  double* V = lds + 2 * H * H + H;   // V[c * Me + r] is entry (r, c)
   const int tid = threadIdx.x;
-  const int ntri = Me * (Me + 1) / 2, nblk = H * (H + 1) / 2;
   for (int e = tid; e < Me * Me; e += kSyevThreads) {
     const int r = e / Me, c = e % Me;
-    if (r <= c) A[tri_index(r, c, Me)] = (r < m && c < m) ? 0.5 * (Ain[r * lda + c] + Ain[c * lda + r]) : 0.0;
+    if (r <= c) A[jstore(r, c, Me)] = (r < m && c < m) ? 0.5 * (Ain[r * lda + c] + Ain[c * lda + r]) : 0.0;
     V[e] = r == c ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -290,136 +338,157 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
     __syncthreads();
     return s;
   };
-  // norms: diagonal once, off-diagonal twice; row r of the packed triangle
-  // starts at r Me - r (r - 1) / 2
-  auto row_of = [&](int e) {
-    int r = (int)((2.0 * Me + 1.0 - sqrt((2.0 * Me + 1.0) * (2.0 * Me + 1.0) - 8.0 * e)) * 0.5);
-    while (r > 0 && r * Me - (r * (r - 1)) / 2 > e) --r;
-    while ((r + 1) * Me - ((r + 1) * r) / 2 <= e) ++r;
-    return r;
-  };
-  double nl = 0.0;
-  for (int e = tid; e < ntri; e += kSyevThreads) {
-    const int r = row_of(e), c = r + (e - (r * Me - (r * (r - 1)) / 2));
-    nl += (r == c ? 1.0 : 2.0) * A[e] * A[e];
+  // the pair this thread rotates (first wave) and its diagonal block's
+  // shifted write addresses (first-first, second-second, first-second)
+  const bool rotor = tid < H;
+  int dw[3] = {0, 0, 0};
+  if (rotor) {
+    const int f = slot_shift(slot_first(tid), Me), sc = slot_shift(slot_second(tid, Me), Me);
+    dw[0] = jstore(f, f, Me);
+    dw[1] = jstore(sc, sc, Me);
+    dw[2] = jstore(f, sc, Me);
   }
-  const double nrm2 = block_sum(nl);
-  const double tol = 4.0 * Me * 1.1102230246251565e-16;
-  // this thread's blocks (bi <= bj) and eigenvector items (pair, row): fixed
-  // for every round
-  constexpr int kMaxBlk = (kMaxSmall / 2) * (kMaxSmall / 2 + 1) / 2 / kSyevThreads + 1;
+  // this thread's off-diagonal blocks (bi < bj, fixed): entry q = first/second
+  // of bi (q >> 1) times first/second of bj (q & 1) at 3H + q nob + rank,
+  // written to the storage of the shifted slots
+  constexpr int kMaxBlk = (kMaxSmall / 2) * (kMaxSmall / 2 - 1) / 2 / kSyevThreads + 1;
   constexpr int kMaxItem = (kMaxSmall / 2) * kMaxSmall / kSyevThreads + 1;
-  int blk_i[kMaxBlk], blk_j[kMaxBlk], item_i[kMaxItem], item_r[kMaxItem];
+  int bpi[kMaxBlk], bpj[kMaxBlk], rda[kMaxBlk], wra[kMaxBlk][4];
 #pragma unroll
   for (int k = 0; k < kMaxBlk; ++k) {
-    const int bb = tid + k * kSyevThreads;
-    blk_i[k] = -1;
-    blk_j[k] = -1;
-    if (bb < nblk) {
-      int bi = (int)((2.0 * H + 1.0 - sqrt((2.0 * H + 1.0) * (2.0 * H + 1.0) - 8.0 * bb)) * 0.5);
-      while (bi > 0 && bi * H - (bi * (bi - 1)) / 2 > bb) --bi;
-      while ((bi + 1) * H - ((bi + 1) * bi) / 2 <= bb) ++bi;
-      blk_i[k] = bi;
-      blk_j[k] = bi + (bb - (bi * H - (bi * (bi - 1)) / 2));
+    const int ob = tid + k * kSyevThreads;
+    bpi[k] = -1;
+    bpj[k] = -1;
+    rda[k] = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wra[k][q] = 0;
+    if (ob < nob) {
+      const double hb = H - 0.5;
+      int bi = (int)(hb - sqrt(hb * hb - 2.0 * ob));
+      if (bi < 0) bi = 0;
+      while (bi > 0 && offblk(bi, bi + 1, H) > ob) --bi;
+      while (bi + 1 < H && offblk(bi + 1, bi + 2, H) <= ob) ++bi;
+      const int bj = ob - offblk(bi, bi + 1, H) + bi + 1;
+      bpi[k] = bi;
+      bpj[k] = bj;
+      rda[k] = 3 * H + ob;
+      const int xs[2] = {slot_shift(slot_first(bi), Me), slot_shift(slot_second(bi, Me), Me)};
+      const int ys[2] = {slot_shift(slot_first(bj), Me), slot_shift(slot_second(bj, Me), Me)};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) wra[k][q] = jstore(xs[q >> 1], ys[q & 1], Me);
     }
   }
+  // this thread's eigenvector items (pair, row): column addresses of the
+  // pair's two indices at round 0 (index = slot)
+  int va[kMaxItem], vb[kMaxItem], vpair[kMaxItem];
 #pragma unroll
   for (int k = 0; k < kMaxItem; ++k) {
     const int it = tid + k * kSyevThreads;
-    item_i[k] = it < H * Me ? it / Me : -1;
-    item_r[k] = it < H * Me ? it - (it / Me) * Me : 0;
-  }
-  for (int sw = 0; sw < 60; ++sw) {
-    double ol = 0.0;
-    for (int e = tid; e < ntri; e += kSyevThreads) {
-      const int r = row_of(e), c = r + (e - (r * Me - (r * (r - 1)) / 2));
-      if (r != c) ol += 2.0 * A[e] * A[e];
+    vpair[k] = -1;
+    va[k] = vb[k] = 0;
+    if (it < H * Me) {
+      const int i = it / Me, r = it - i * Me;
+      vpair[k] = i;
+      va[k] = slot_first(i) * Me + r;
+      vb[k] = slot_second(i, Me) * Me + r;
     }
-    const double off = block_sum(ol);
+  }
+  // column address of the next index along the circle (index 0 stays)
+  const int vwrap = Mc * Me;
+  auto vnext = [&](int a) {
+    if (a >= Me) {
+      a += Me;
+      if (a >= Me * Me) a -= vwrap;
+    }
+    return a;
+  };
+  // squared norms over this thread's blocks: diagonal once, off-diagonal twice
+  auto block_norms = [&](double& dg, double& od) {
+    dg = 0.0;
+    od = 0.0;
+    if (rotor) {
+      const double a0 = A[tid], a1 = A[H + tid], a2 = A[2 * H + tid];
+      dg = a0 * a0 + a1 * a1;
+      od = 2.0 * a2 * a2;
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxBlk; ++k) {
+      if (bpi[k] < 0) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) od += 2.0 * A[rda[k] + q * nob] * A[rda[k] + q * nob];
+    }
+  };
+  double dg0, od0;
+  block_norms(dg0, od0);
+  const double nrm2 = block_sum(dg0 + od0);
+  const double tol = 4.0 * Me * 1.1102230246251565e-16;
+  for (int sw = 0; sw < 60; ++sw) {
+    double dg, od;
+    block_norms(dg, od);
+    const double off = block_sum(od);
     if (tid == 0) done = off <= tol * tol * nrm2;
     __syncthreads();
     if (done) break;
-    for (int s = 0; s < Me - 1; ++s) {
-      for (int i = tid; i < H; i += kSyevThreads) {
-        int p, q;
-        rr_pair(i, s, Me, p, q);
-        const double app = A[tri_index(p, p, Me)], aqq = A[tri_index(q, q, Me)], b = A[tri_index(p, q, Me)];
-        const double ab = fabs(b), d = aqq - app;
-        double c = 1.0, sv = 0.0, dp = app, dq = aqq;
-        if (b * b < 1e-8 * d * d) {
-          // small angle: t = (b / d)(1 - x + 2 x^2), x = b^2 / d^2; one division
-          const double id = 1.0 / d, x = b * b * id * id;
-          const double f = 1.0 - x + 2.0 * x * x, t2 = x * f * f;
-          c = 1.0 - 0.5 * t2 + 0.375 * t2 * t2;
-          sv = b * id * f * c;
-          dp = app - b * b * id * f;
-          dq = aqq + b * b * id * f;
-        } else if (ab > 0.0) {
-          const double tau = (aqq - app) / (2.0 * ab);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sv = (b >= 0.0 ? 1.0 : -1.0) * t * c;
-          dp = app - t * ab;
-          dq = aqq + t * ab;
-        }
-        cs[i] = c;
-        sn[i] = sv;
-        dn[p] = dp;
-        dn[q] = dq;
+    for (int s = 0; s < Mc; ++s) {
+      // rotations of this round's pairs; blocks into registers
+      double dp = 0.0, dq = 0.0;
+      if (rotor) {
+        double c, sv;
+        jacobi_rot(A[tid], A[H + tid], A[2 * H + tid], c, sv, dp, dq);
+        rc[tid] = c;
+        rs[tid] = sv;
       }
-      __syncthreads();
-      // A <- J^T A J on the blocks bi <= bj of the pairs
+      double a[kMaxBlk][4];
 #pragma unroll
       for (int k = 0; k < kMaxBlk; ++k) {
-        const int bi = blk_i[k], bj = blk_j[k];
-        if (bi < 0) continue;
-        int pi, qi, pj, qj;
-        rr_pair(bi, s, Me, pi, qi);
-        rr_pair(bj, s, Me, pj, qj);
-        if (bi == bj) {
-          A[tri_index(pi, pi, Me)] = dn[pi];
-          A[tri_index(qi, qi, Me)] = dn[qi];
-          A[tri_index(pi, qi, Me)] = 0.0;
-        } else {
-          const double ci = cs[bi], si = sn[bi], cj = cs[bj], sj = sn[bj];
-          const int i00 = tri_index(pi, pj, Me), i01 = tri_index(pi, qj, Me);
-          const int i10 = tri_index(qi, pj, Me), i11 = tri_index(qi, qj, Me);
-          const double b00 = A[i00], b01 = A[i01], b10 = A[i10], b11 = A[i11];
-          const double t00 = b00 * cj - b01 * sj, t01 = b00 * sj + b01 * cj;
-          const double t10 = b10 * cj - b11 * sj, t11 = b10 * sj + b11 * cj;
-          A[i00] = ci * t00 - si * t10;
-          A[i01] = ci * t01 - si * t11;
-          A[i10] = si * t00 + ci * t10;
-          A[i11] = si * t01 + ci * t11;
-        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[k][q] = bpi[k] >= 0 ? A[rda[k] + q * nob] : 0.0;
       }
-      // V <- V J: columns p, q of every pair, one row per thread
+      __syncthreads();
+      // A <- J^T A J, written to the shifted slots
+      if (rotor) {
+        A[dw[0]] = dp;
+        A[dw[1]] = dq;
+        A[dw[2]] = 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxBlk; ++k) {
+        const int bi = bpi[k], bj = bpj[k];
+        if (bi < 0) continue;
+        const double ci = rc[bi], si = rs[bi], cj = rc[bj], sj = rs[bj];
+        const double t00 = a[k][0] * cj - a[k][1] * sj, t01 = a[k][0] * sj + a[k][1] * cj;
+        const double t10 = a[k][2] * cj - a[k][3] * sj, t11 = a[k][2] * sj + a[k][3] * cj;
+        A[wra[k][0]] = ci * t00 - si * t10;
+        A[wra[k][1]] = ci * t01 - si * t11;
+        A[wra[k][2]] = si * t00 + ci * t10;
+        A[wra[k][3]] = si * t01 + ci * t11;
+      }
+      // V <- V J: the two columns of every pair, one row per item, in place
 #pragma unroll
       for (int k = 0; k < kMaxItem; ++k) {
-        const int i = item_i[k], r = item_r[k];
-        if (i < 0) continue;
-        int p, q;
-        rr_pair(i, s, Me, p, q);
-        const double c = cs[i], sv = sn[i];
-        const double vp = V[p * Me + r], vq = V[q * Me + r];
-        V[p * Me + r] = vp * c - vq * sv;
-        V[q * Me + r] = vp * sv + vq * c;
+        if (vpair[k] < 0) continue;
+        const double c = rc[vpair[k]], sv = rs[vpair[k]];
+        const double vp = V[va[k]], vq = V[vb[k]];
+        V[va[k]] = vp * c - vq * sv;
+        V[vb[k]] = vp * sv + vq * c;
+        va[k] = vnext(va[k]);
+        vb[k] = vnext(vb[k]);
       }
       __syncthreads();
     }
   }
-  // ascending ranks among the m real indices (ties by index)
+  // ascending ranks among the m real indices (ties by index); slot = index here
   for (int i = tid; i < m; i += kSyevThreads) {
-    const double li = A[tri_index(i, i, Me)];
+    const double li = A[jstore(i, i, Me)];
     int k = 0;
     for (int j = 0; j < m; ++j) {
-      const double lj = A[tri_index(j, j, Me)];
+      const double lj = A[jstore(j, j, Me)];
       k += (lj < li || (lj == li && j < i)) ? 1 : 0;
     }
     rank[i] = k;
   }
   __syncthreads();
-  for (int i = tid; i < m; i += kSyevThreads) w[rank[i]] = A[tri_index(i, i, Me)];
+  for (int i = tid; i < m; i += kSyevThreads) w[rank[i]] = A[jstore(i, i, Me)];
   for (int e = tid; e < m * m; e += kSyevThreads) {
     const int r = e / m, c = e % m;
     Vout[r * ldv + rank[c]] = V[c * Me + r];
