@@ -232,34 +232,33 @@ __global__ void __launch_bounds__(256) symmetrize_kernel(int m, double* __restri
   }
 }
 
-// Real symmetric eigensolver, one workgroup: cyclic Jacobi in the parallel
-// round-robin order (size padded to even Me with a decoupled zero index),
-// everything in LDS.
+// Real symmetric eigensolver: cyclic Jacobi in the parallel round-robin
+// order (size padded to even Me with a decoupled zero index).
 //
-// A is kept in "slot space": the Me indices occupy Me storage slots, and the
-// pairs of every round are the same slot pairs, (0, 1) and (1 + i, Me - i)
-// for i = 1 .. Me/2 - 1.  After each round the contents of slots 2 .. Me-1
-// move down one slot, slot 1 moves to slot Me-1 and slot 0 stays (the
-// circle method of the round-robin tournament), so after the Me - 1 rounds
-// of a sweep every slot holds its own index again.  Storage follows the
-// pairs: the diagonal 2 x 2 block of pair i as three arrays (first-first,
-// second-second, first-second), and the blocks of pairs bi < bj as four
-// arrays (entry first/second of bi times first/second of bj) indexed by the
-// block's rank in the strict upper triangle.  A thread owns fixed blocks and
-// reads and writes fixed addresses every round: consecutive threads own
-// consecutive blocks of a block row, so loads and stores are contiguous, and
-// the loop has no index arithmetic.  A round is two phases: the first wave
-// computes the rotations of the pairs from their diagonal blocks while the
-// other threads load their blocks; after a barrier the rotated blocks are
-// written to the shifted slots and the eigenvector items are rotated.
+// The matrix lives in the LDS of one workgroup in "slot space": the Me
+// indices occupy Me storage slots, and the pairs of every round are the
+// same slot pairs, (0, 1) and (1 + i, Me - i) for i = 1 .. Me/2 - 1.  After
+// each round the contents of slots 2 .. Me-1 move down one slot, slot 1
+// moves to slot Me-1 and slot 0 stays (the circle method of the round-robin
+// tournament), so after the Me - 1 rounds of a sweep every slot holds its
+// own index again.  Storage follows the pairs: the diagonal 2 x 2 block of
+// pair i as three arrays (first-first, second-second, first-second), and the
+// blocks of pairs bi < bj as four arrays (entry first/second of bi times
+// first/second of bj) indexed by the block's rank in the strict upper
+// triangle.  A thread owns fixed blocks and reads and writes fixed
+// addresses every round: consecutive threads own consecutive blocks of a
+// block row, so loads and stores are contiguous, and the loop has no index
+// arithmetic.  A round is two phases: the first wave computes the rotations
+// of the pairs from their diagonal blocks while the other threads load
+// their blocks; after a barrier the rotated blocks are written to the
+// shifted slots.  Stops at a sweep boundary once the off-diagonal Frobenius
+// norm is below 4 Me eps of the norm of A.
 //
-// V (eigenvectors, column j contiguous) stays in index space: an item (pair,
-// row) updates its two entries in place; the column addresses advance by one
-// index per round along the circle.
-//
-// Stops at a sweep boundary once the off-diagonal Frobenius norm is below
-// 4 Me eps of the norm of A.  Output: eigenvalues ascending in w,
-// eigenvector j in column j of Vout.
+// Eigenvectors: the rotations of every round are recorded in global memory,
+// and a second kernel replays them on the rows of V = I, one wavefront per
+// row (the rows are independent): lane i holds the row's entries in the
+// two slots of pair i and the slot shift is a one-lane shuffle.  Output:
+// eigenvalues ascending in w, eigenvector j in column j of Vout.
 __device__ __forceinline__ int slot_first(int i) { return i == 0 ? 0 : 1 + i; }
 __device__ __forceinline__ int slot_second(int i, int Me) { return i == 0 ? 1 : Me - i; }
 __device__ __forceinline__ int slot_shift(int x, int Me) { return x == 0 ? 0 : (x == 1 ? Me - 1 : x - 1); }
@@ -312,21 +311,19 @@ __device__ __forceinline__ void jacobi_rot(double app, double aqq, double b, dou
 constexpr int kSyevThreads = 1024;
 
 __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double* __restrict__ Ain, int lda,
-                                                            double* __restrict__ w, double* __restrict__ Vout,
-                                                            int ldv) {
+                                                            double* __restrict__ w, double2* __restrict__ rec,
+                                                            int* __restrict__ hdr) {
   extern __shared__ double lds[];
   __shared__ double rc[kMaxSmall / 2], rs[kMaxSmall / 2];   // this round's rotations
   __shared__ double red[kSyevThreads / 64];
   __shared__ int rank[kMaxSmall];
   __shared__ int done;
   const int Me = m + (m & 1), H = Me / 2, Mc = Me - 1, nob = H * (H - 1) / 2;
-  double* A = lds;                   // pair-block storage over slots, Me (Me + 1) / 2
-  double* V = lds + 2 * H * H + H;   // V[c * Me + r] is entry (r, c)
+  double* A = lds;   // pair-block storage over slots, Me (Me + 1) / 2
   const int tid = threadIdx.x;
   for (int e = tid; e < Me * Me; e += kSyevThreads) {
     const int r = e / Me, c = e % Me;
     if (r <= c) A[jstore(r, c, Me)] = (r < m && c < m) ? 0.5 * (Ain[r * lda + c] + Ain[c * lda + r]) : 0.0;
-    V[e] = r == c ? 1.0 : 0.0;
   }
   __syncthreads();
   auto block_sum = [&](double v) -> double {
@@ -352,7 +349,6 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
   // of bi (q >> 1) times first/second of bj (q & 1) at 3H + q nob + rank,
   // written to the storage of the shifted slots
   constexpr int kMaxBlk = (kMaxSmall / 2) * (kMaxSmall / 2 - 1) / 2 / kSyevThreads + 1;
-  constexpr int kMaxItem = (kMaxSmall / 2) * kMaxSmall / kSyevThreads + 1;
   int bpi[kMaxBlk], bpj[kMaxBlk], rda[kMaxBlk], wra[kMaxBlk][4];
 #pragma unroll
   for (int k = 0; k < kMaxBlk; ++k) {
@@ -378,30 +374,6 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
       for (int q = 0; q < 4; ++q) wra[k][q] = jstore(xs[q >> 1], ys[q & 1], Me);
     }
   }
-  // this thread's eigenvector items (pair, row): column addresses of the
-  // pair's two indices at round 0 (index = slot)
-  int va[kMaxItem], vb[kMaxItem], vpair[kMaxItem];
-#pragma unroll
-  for (int k = 0; k < kMaxItem; ++k) {
-    const int it = tid + k * kSyevThreads;
-    vpair[k] = -1;
-    va[k] = vb[k] = 0;
-    if (it < H * Me) {
-      const int i = it / Me, r = it - i * Me;
-      vpair[k] = i;
-      va[k] = slot_first(i) * Me + r;
-      vb[k] = slot_second(i, Me) * Me + r;
-    }
-  }
-  // column address of the next index along the circle (index 0 stays)
-  const int vwrap = Mc * Me;
-  auto vnext = [&](int a) {
-    if (a >= Me) {
-      a += Me;
-      if (a >= Me * Me) a -= vwrap;
-    }
-    return a;
-  };
   // squared norms over this thread's blocks: diagonal once, off-diagonal twice
   auto block_norms = [&](double& dg, double& od) {
     dg = 0.0;
@@ -422,7 +394,8 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
   block_norms(dg0, od0);
   const double nrm2 = block_sum(dg0 + od0);
   const double tol = 4.0 * Me * 1.1102230246251565e-16;
-  for (int sw = 0; sw < 60; ++sw) {
+  int sw = 0;
+  for (; sw < kSyevMaxSweeps; ++sw) {
     double dg, od;
     block_norms(dg, od);
     const double off = block_sum(od);
@@ -437,6 +410,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
         jacobi_rot(A[tid], A[H + tid], A[2 * H + tid], c, sv, dp, dq);
         rc[tid] = c;
         rs[tid] = sv;
+        if (rec) rec[(sw * Mc + s) * H + tid] = make_double2(c, sv);
       }
       double a[kMaxBlk][4];
 #pragma unroll
@@ -463,17 +437,6 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
         A[wra[k][2]] = si * t00 + ci * t10;
         A[wra[k][3]] = si * t01 + ci * t11;
       }
-      // V <- V J: the two columns of every pair, one row per item, in place
-#pragma unroll
-      for (int k = 0; k < kMaxItem; ++k) {
-        if (vpair[k] < 0) continue;
-        const double c = rc[vpair[k]], sv = rs[vpair[k]];
-        const double vp = V[va[k]], vq = V[vb[k]];
-        V[va[k]] = vp * c - vq * sv;
-        V[vb[k]] = vp * sv + vq * c;
-        va[k] = vnext(va[k]);
-        vb[k] = vnext(vb[k]);
-      }
       __syncthreads();
     }
   }
@@ -488,10 +451,51 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
     rank[i] = k;
   }
   __syncthreads();
-  for (int i = tid; i < m; i += kSyevThreads) w[rank[i]] = A[jstore(i, i, Me)];
-  for (int e = tid; e < m * m; e += kSyevThreads) {
-    const int r = e / m, c = e % m;
-    Vout[r * ldv + rank[c]] = V[c * Me + r];
+  for (int i = tid; i < m; i += kSyevThreads) {
+    w[rank[i]] = A[jstore(i, i, Me)];
+    if (hdr) hdr[1 + i] = rank[i];
+  }
+  if (hdr && tid == 0) hdr[0] = sw * Mc;   // rounds recorded (whole sweeps)
+}
+
+constexpr int kReplayBatch = 8;   // recorded rounds loaded ahead
+
+// V = I J_1 J_2 ... (the recorded rotations), row r of V per workgroup of one
+// wavefront; lane i holds the row's entries in the slots of pair i (first
+// slot in F, second in S).  The shift after each round: F takes lane i+1's
+// F (lane 0 keeps slot 0, lane H-1 takes its own S), S takes lane i-1's S
+// (lane 0 takes lane 1's F).  Entry (r, c) is written to column perm[c].
+__global__ void __launch_bounds__(64) syev_vectors_kernel(int m, const double2* __restrict__ rec,
+                                                          const int* __restrict__ hdr, double* __restrict__ Vout,
+                                                          int ldv) {
+  const int r = blockIdx.x, i = threadIdx.x;
+  const int Me = m + (m & 1), H = Me / 2, R = hdr[0];
+  const int f = slot_first(i), sc = slot_second(i, Me);
+  const bool act = i < H;
+  double F = (act && f == r) ? 1.0 : 0.0, S = (act && sc == r) ? 1.0 : 0.0;
+  double2 cur[kReplayBatch], nxt[kReplayBatch];
+  auto load = [&](int k0, double2* b) {
+#pragma unroll
+    for (int j = 0; j < kReplayBatch; ++j) b[j] = (act && k0 + j < R) ? rec[(k0 + j) * H + i] : make_double2(1.0, 0.0);
+  };
+  load(0, cur);
+  for (int k0 = 0; k0 < R; k0 += kReplayBatch) {
+    load(k0 + kReplayBatch, nxt);
+#pragma unroll
+    for (int j = 0; j < kReplayBatch; ++j) {
+      if (k0 + j >= R) break;
+      const double nF = F * cur[j].x - S * cur[j].y, nS = F * cur[j].y + S * cur[j].x;
+      const double Fd = __shfl_down(nF, 1, 64), Su = __shfl_up(nS, 1, 64);
+      F = i == 0 ? nF : (i == H - 1 ? nS : Fd);
+      S = i == 0 ? (H > 1 ? Fd : nS) : Su;
+    }
+#pragma unroll
+    for (int j = 0; j < kReplayBatch; ++j) cur[j] = nxt[j];
+  }
+  if (act && r < m) {
+    const int* perm = hdr + 1;
+    if (f < m) Vout[r * ldv + perm[f]] = F;
+    if (sc < m) Vout[r * ldv + perm[sc]] = S;
   }
 }
 
@@ -516,12 +520,14 @@ hipError_t dense_combine(int N, int k1, int k2, const double* A, int lda, const 
 
 hipError_t dense_syev_w(int m, const double* A, int lda, double* w, double* V, int ldv, double* work,
                         hipStream_t s) {
-  (void)work;
-  if (m < 1 || m > kMaxSmall) return hipErrorInvalidValue;
+  if (m < 1 || m > kMaxSmall || (V && !work)) return hipErrorInvalidValue;
   const int Me = m + (m & 1);
-  const size_t lds = sizeof(double) * ((size_t)Me * (Me + 1) / 2 + (size_t)Me * Me);
+  const size_t lds = sizeof(double) * ((size_t)Me * (Me + 1) / 2);
+  int* hdr = V ? reinterpret_cast<int*>(work) : nullptr;
+  double2* rec = V ? reinterpret_cast<double2*>(work + kSyevHeaderDoubles) : nullptr;
   (void)hipFuncSetAttribute((const void*)syev_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(kSyevThreads), lds, s, m, A, lda, w, V, ldv);
+  hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(kSyevThreads), lds, s, m, A, lda, w, rec, hdr);
+  if (V) hipLaunchKernelGGL(syev_vectors_kernel, dim3(m), dim3(64), 0, s, m, rec, hdr, V, ldv);
   return hipGetLastError();
 }
 

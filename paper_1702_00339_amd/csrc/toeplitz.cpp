@@ -439,7 +439,7 @@ size_t eigs_layout(const lhf_toeplitz_s* t, int nev, EigWs* w, char* base) {
   const size_t sq = (size_t)kMaxSmall * kMaxSmall;
   take(d.G, sq); take(d.Gs, sq); take(d.lam, kMaxSmall); take(d.dvec, kMaxSmall);
   take(d.T, sq); take(d.GH, sq); take(d.th, kMaxSmall); take(d.C, sq); take(d.C2, sq); take(d.norms, kMaxSmall);
-  take(d.syw, sq); take(d.part, (size_t)kChunks * sq); take(d.rpart, (size_t)kChunks * kMaxSmall);
+  take(d.syw, kSyevWorkDoubles); take(d.part, (size_t)kChunks * sq); take(d.rpart, (size_t)kChunks * kMaxSmall);
   d.mv_bytes = lhf_toeplitz_matvec_workspace(const_cast<lhf_toeplitz_s*>(t), mx);
   d.mv = base ? base + off : nullptr;
   off += d.mv_bytes;

@@ -84,7 +84,15 @@ hipError_t dense_gram(int N, int k1, int k2, const double* A, int lda, const dou
 // Y = beta Z + A T   (Z may alias nothing; beta = 0 ignores Z)
 hipError_t dense_combine(int N, int k1, int k2, const double* A, int lda, const double* T, int ldt, double beta,
                          const double* Z, int ldz, double* Y, int ldy, hipStream_t s);
-// eigenvalues ascending in w, eigenvectors in the columns of V (m <= kMaxSmall); work unused
+// Jacobi of the dense eigensolver: sweep cap, and the workspace for the
+// eigenvectors (a header with the round count and the ascending order, then
+// the (c, s) of every pair of every recorded round)
+constexpr int kSyevMaxSweeps = 60;
+constexpr size_t kSyevHeaderDoubles = (kMaxSmall + 2) / 2 + 1;
+constexpr size_t kSyevWorkDoubles =
+    kSyevHeaderDoubles + 2 * (size_t)kSyevMaxSweeps * (kMaxSmall - 1) * (kMaxSmall / 2);
+// eigenvalues ascending in w, eigenvectors in the columns of V (m <= kMaxSmall;
+// V may be NULL); work: kSyevWorkDoubles doubles when V is given
 hipError_t dense_syev_w(int m, const double* A, int lda, double* w, double* V, int ldv, double* work, hipStream_t s);
 hipError_t dense_residual(int N, int k, const double* HX, const double* SX, int ld, const double* theta, double* R,
                           int ldr, double* part, int nchunk, double* norms, hipStream_t s);
