@@ -12,37 +12,76 @@
 namespace lhf {
 namespace {
 
-constexpr int kGT = 32;      // Gram output tile
-constexpr int kGRows = 64;   // rows staged per step
+constexpr int kGT = 56;      // Gram output tile (rows and columns)
+constexpr int kGM = 4;       // outputs per thread along each side
+constexpr int kGL = kGT / kGM;   // 14 x 14 threads own a tile
+constexpr int kGRows = 32;   // rows staged per step
 
-// part[c][i][j] = sum over rows n of chunk c of A[n][i] B[n][j]
+// part[c][i][j] = sum over rows n of chunk c of A[n][i] B[n][j] on one output
+// tile; thread (ti, tj) owns rows ti + 14 u and columns tj + 14 v of the tile
+// (consecutive lanes read consecutive staged entries)
 __global__ void __launch_bounds__(256) gram_part_kernel(int N, int k1, int k2, int chunk, const double* __restrict__ A,
                                                         int lda, const double* __restrict__ B, int ldb,
                                                         double* __restrict__ part) {
-  __shared__ double As[kGRows][kGT + 1];
-  __shared__ double Bs[kGRows][kGT + 1];
+  __shared__ double As[kGRows][kGT];
+  __shared__ double Bs[kGRows][kGT];
   const int c = blockIdx.x, i0 = blockIdx.y * kGT, j0 = blockIdx.z * kGT;
-  const int ti = threadIdx.x % kGT, tj = threadIdx.x / kGT;   // outputs (ti, tj + 8 u)
-  double acc[4] = {0, 0, 0, 0};
+  const int t = threadIdx.x, ti = t / kGL, tj = t % kGL;
+  const bool act = t < kGL * kGL;
+  double acc[kGM][kGM];
+#pragma unroll
+  for (int u = 0; u < kGM; ++u)
+#pragma unroll
+    for (int v = 0; v < kGM; ++v) acc[u][v] = 0.0;
   const int n0 = c * chunk, n1 = min(N, n0 + chunk);
+  // the next rows are fetched into registers while the current ones are used
+  constexpr int kS = (kGRows * kGT + 255) / 256;
+  double ra[kS], rb[kS];
+  auto fetch = [&](int nb) {
+#pragma unroll
+    for (int u = 0; u < kS; ++u) {
+      const int e = t + 256 * u, r = e / kGT, q = e % kGT, n = nb + r;
+      const bool in = e < kGRows * kGT && n < n1;
+      ra[u] = (in && i0 + q < k1) ? A[(int64_t)n * lda + i0 + q] : 0.0;
+      rb[u] = (in && j0 + q < k2) ? B[(int64_t)n * ldb + j0 + q] : 0.0;
+    }
+  };
+  if (n0 < n1) fetch(n0);
   for (int nb = n0; nb < n1; nb += kGRows) {
-    for (int e = threadIdx.x; e < kGRows * kGT; e += 256) {
-      const int r = e / kGT, q = e % kGT, n = nb + r;
-      As[r][q] = (n < n1 && i0 + q < k1) ? A[(int64_t)n * lda + i0 + q] : 0.0;
-      Bs[r][q] = (n < n1 && j0 + q < k2) ? B[(int64_t)n * ldb + j0 + q] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kS; ++u) {
+      const int e = t + 256 * u;
+      if (e < kGRows * kGT) {
+        As[e / kGT][e % kGT] = ra[u];
+        Bs[e / kGT][e % kGT] = rb[u];
+      }
     }
     __syncthreads();
-    for (int r = 0; r < kGRows; ++r) {
-      const double a = As[r][ti];
+    if (nb + kGRows < n1) fetch(nb + kGRows);
+    if (act) {
+      for (int r = 0; r < kGRows; ++r) {
+        double av[kGM], bv[kGM];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += a * Bs[r][tj + 8 * u];
+        for (int u = 0; u < kGM; ++u) {
+          av[u] = As[r][ti + kGL * u];
+          bv[u] = Bs[r][tj + kGL * u];
+        }
+#pragma unroll
+        for (int u = 0; u < kGM; ++u)
+#pragma unroll
+          for (int v = 0; v < kGM; ++v) acc[u][v] += av[u] * bv[v];
+      }
     }
     __syncthreads();
   }
+  if (act) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int i = i0 + ti, j = j0 + tj + 8 * u;
-    if (i < k1 && j < k2) part[((int64_t)c * k1 + i) * k2 + j] = acc[u];
+    for (int u = 0; u < kGM; ++u)
+#pragma unroll
+      for (int v = 0; v < kGM; ++v) {
+        const int i = i0 + ti + kGL * u, j = j0 + tj + kGL * v;
+        if (i < k1 && j < k2) part[((int64_t)c * k1 + i) * k2 + j] = acc[u][v];
+      }
   }
 }
 
@@ -50,31 +89,101 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(int k1, int k2, int nc
                                                           double* __restrict__ G, int ldg) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= k1 * k2) return;
+  // chunk order kept; loads of 8 chunks in flight together
+  constexpr int kU = 8;
+  const int64_t st = (int64_t)k1 * k2;
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * k1 * k2 + e];
+  int c = 0;
+  for (; c + kU <= nchunk; c += kU) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = part[(c + u) * st + e];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) s += v[u];
+  }
+  for (; c < nchunk; ++c) s += part[c * st + e];
   G[(e / k2) * ldg + e % k2] = s;
 }
 
-constexpr int kCRows = 16;   // rows per combine workgroup
+constexpr int kCbR = 32;                              // rows per combine workgroup
+constexpr int kCbK = 16;                              // inner-dimension chunk staged per step
+constexpr int kCbC = 8;                               // columns per thread
+constexpr int kCbG = (kMaxSmall + kCbC - 1) / kCbC;   // 14 column groups
 
-// Y = beta Z + A T
-__global__ void __launch_bounds__(256) combine_kernel(int N, int k1, int k2, const double* __restrict__ A, int lda,
-                                                      const double* __restrict__ T, int ldt, double beta,
-                                                      const double* Z, int ldz, double* Y, int ldy) {
-  __shared__ double As[kCRows][kMaxSmall];
-  const int r0 = blockIdx.x * kCRows;
-  for (int e = threadIdx.x; e < kCRows * k1; e += 256) {
-    const int r = e / k1, i = e % k1;
-    As[r][i] = r0 + r < N ? A[(int64_t)(r0 + r) * lda + i] : 0.0;
+// Y_a = beta Z + A_a T for a = blockIdx.y (beta only with one product).  A
+// workgroup owns kCbR rows; thread (rg, cg) owns rows 2 rg, 2 rg + 1 and
+// columns cg + 14 c, c < 8 (consecutive lanes read consecutive staged T).
+__global__ void __launch_bounds__(256) combine_kernel(int N, int k1, int k2, const double* __restrict__ A0,
+                                                      const double* __restrict__ A1, const double* __restrict__ A2,
+                                                      int lda, const double* __restrict__ T, int ldt, double beta,
+                                                      const double* Z, int ldz, double* Y0, double* Y1, double* Y2,
+                                                      int ldy) {
+  __shared__ double As[kCbR][kCbK + 1];
+  __shared__ double Ts[kCbK][kCbG * kCbC];
+  const double* A = blockIdx.y == 0 ? A0 : (blockIdx.y == 1 ? A1 : A2);
+  double* Y = blockIdx.y == 0 ? Y0 : (blockIdx.y == 1 ? Y1 : Y2);
+  const int r0 = blockIdx.x * kCbR, t = threadIdx.x;
+  const int rg = t / kCbG, cg = t % kCbG;
+  const bool act = rg < kCbR / 2;
+  double acc[2][kCbC];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int c = 0; c < kCbC; ++c) acc[u][c] = 0.0;
+  // the next chunk is fetched into registers while the current one is used
+  constexpr int kSA = (kCbR * kCbK + 255) / 256, kST = (kCbK * kCbG * kCbC + 255) / 256;
+  double ra[kSA], rt[kST];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int u = 0; u < kSA; ++u) {
+      const int e = t + 256 * u, r = e / kCbK, kk = e % kCbK;
+      ra[u] = (e < kCbR * kCbK && r0 + r < N && kc + kk < k1) ? A[(int64_t)(r0 + r) * lda + kc + kk] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kST; ++u) {
+      const int e = t + 256 * u, kk = e / (kCbG * kCbC), j = e % (kCbG * kCbC);
+      rt[u] = (e < kCbK * kCbG * kCbC && kc + kk < k1 && j < k2) ? T[(int64_t)(kc + kk) * ldt + j] : 0.0;
+    }
+  };
+  fetch(0);
+  for (int kc = 0; kc < k1; kc += kCbK) {
+#pragma unroll
+    for (int u = 0; u < kSA; ++u) {
+      const int e = t + 256 * u;
+      if (e < kCbR * kCbK) As[e / kCbK][e % kCbK] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kST; ++u) {
+      const int e = t + 256 * u;
+      if (e < kCbK * kCbG * kCbC) Ts[e / (kCbG * kCbC)][e % (kCbG * kCbC)] = rt[u];
+    }
+    __syncthreads();
+    if (kc + kCbK < k1) fetch(kc + kCbK);
+    if (act) {
+#pragma unroll 4
+      for (int kk = 0; kk < kCbK; ++kk) {
+        const double a0 = As[2 * rg][kk], a1 = As[2 * rg + 1][kk];
+#pragma unroll
+        for (int c = 0; c < kCbC; ++c) {
+          const double tv = Ts[kk][cg + kCbG * c];
+          acc[0][c] += a0 * tv;
+          acc[1][c] += a1 * tv;
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < kCRows * k2; e += 256) {
-    const int r = e / k2, j = e % k2, n = r0 + r;
-    if (n >= N) continue;
-    double s = 0.0;
-    for (int i = 0; i < k1; ++i) s += As[r][i] * T[(int64_t)i * ldt + j];
-    if (beta != 0.0) s += beta * Z[(int64_t)n * ldz + j];
-    Y[(int64_t)n * ldy + j] = s;
+  if (act) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int n = r0 + 2 * rg + u;
+      if (n >= N) continue;
+#pragma unroll
+      for (int c = 0; c < kCbC; ++c) {
+        const int j = cg + kCbG * c;
+        if (j < k2) Y[(int64_t)n * ldy + j] = beta != 0.0 ? acc[u][c] + beta * Z[(int64_t)n * ldz + j] : acc[u][c];
+      }
+    }
   }
 }
 
@@ -149,6 +258,7 @@ __global__ void __launch_bounds__(256) scale_sym_kernel(int m, const double* __r
 
 constexpr int kCholThreads = 1024;   // 8 row groups x 128 columns
 constexpr int kCholCols = 128;
+constexpr int kCholB = 4;           // rows per batch of a thread
 static_assert(kMaxSmall <= kCholCols, "one column per lane of a row group");
 
 // S-orthonormalisation by Cholesky-QR with deflation, one workgroup.  Gs is
@@ -189,12 +299,27 @@ __global__ void __launch_bounds__(kCholThreads) cholqr_t_kernel(int m, const dou
     const double rp = p > drop ? 1.0 / p : 0.0;   // dropped: f = 0 leaves the rows as they are
     if (c < m) {
       const double rj = a[j * m + c];
-      for (int i = j + 1 + rg; i < m; i += kRG) {
-        const double f = cj[i] * rp;
-        // c < j: E[i][c] -= f E[j][c]; c == j: E[i][j] = -f (E[j][j] = 1); c > j: Schur update
-        const double v = c == j ? -f : a[i * m + c] - f * rj;
-        a[i * m + c] = v;
-        if (c == j + 1) cn[i] = v;
+      // rows in batches of kCholB (loads of a batch in flight together)
+      for (int i0 = j + 1 + rg; i0 < m; i0 += kCholB * kRG) {
+        // unconditional loads (rows clamped into range) so that they issue together
+        double f[kCholB], v[kCholB];
+#pragma unroll
+        for (int u = 0; u < kCholB; ++u) {
+          const int i = min(i0 + u * kRG, m - 1);
+          f[u] = cj[i];
+          v[u] = a[i * m + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kCholB; ++u) {
+          const int i = i0 + u * kRG;
+          if (i < m) {
+            // c < j: E[i][c] -= f E[j][c]; c == j: E[i][j] = -f (E[j][j] = 1); c > j: Schur update
+            const double fu = f[u] * rp;
+            const double nv = c == j ? -fu : v[u] - fu * rj;
+            a[i * m + c] = nv;
+            if (c == j + 1) cn[i] = nv;
+          }
+        }
       }
     }
     __syncthreads();
@@ -257,7 +382,7 @@ __global__ void __launch_bounds__(256) symmetrize_kernel(int m, double* __restri
 // Eigenvectors: the rotations of every round are recorded in global memory,
 // and a second kernel replays them on the rows of V = I, one wavefront per
 // row (the rows are independent): lane i holds the row's entries in the
-// two slots of pair i and the slot shift is a one-lane shuffle.  Output:
+// two slots of pair i and the slot shift is a one-lane DPP move.  Output:
 // eigenvalues ascending in w, eigenvector j in column j of Vout.
 __device__ __forceinline__ int slot_first(int i) { return i == 0 ? 0 : 1 + i; }
 __device__ __forceinline__ int slot_second(int i, int Me) { return i == 0 ? 1 : Me - i; }
@@ -416,7 +541,7 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
 #pragma unroll
       for (int k = 0; k < kMaxBlk; ++k) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[k][q] = bpi[k] >= 0 ? A[rda[k] + q * nob] : 0.0;
+        for (int q = 0; q < 4; ++q) a[k][q] = A[rda[k] + q * nob];   // in range for unused blocks too (rda 0)
       }
       __syncthreads();
       // A <- J^T A J, written to the shifted slots
@@ -460,6 +585,20 @@ __global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double*
 
 constexpr int kReplayBatch = 8;   // recorded rounds loaded ahead
 
+// Wavefront-wide one-lane shifts of a double (DPP wave_shl:1 / wave_shr:1 on
+// both halves): lane i receives lane i + 1's value, resp. lane i - 1's; the
+// lane without a source receives 0.
+__device__ __forceinline__ double from_next_lane(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double from_prev_lane(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 // V = I J_1 J_2 ... (the recorded rotations), row r of V per workgroup of one
 // wavefront; lane i holds the row's entries in the slots of pair i (first
 // slot in F, second in S).  The shift after each round: F takes lane i+1's
@@ -485,7 +624,7 @@ __global__ void __launch_bounds__(64) syev_vectors_kernel(int m, const double2* 
     for (int j = 0; j < kReplayBatch; ++j) {
       if (k0 + j >= R) break;
       const double nF = F * cur[j].x - S * cur[j].y, nS = F * cur[j].y + S * cur[j].x;
-      const double Fd = __shfl_down(nF, 1, 64), Su = __shfl_up(nS, 1, 64);
+      const double Fd = from_next_lane(nF), Su = from_prev_lane(nS);
       F = i == 0 ? nF : (i == H - 1 ? nS : Fd);
       S = i == 0 ? (H > 1 ? Fd : nS) : Su;
     }
@@ -513,8 +652,17 @@ hipError_t dense_gram(int N, int k1, int k2, const double* A, int lda, const dou
 
 hipError_t dense_combine(int N, int k1, int k2, const double* A, int lda, const double* T, int ldt, double beta,
                          const double* Z, int ldz, double* Y, int ldy, hipStream_t s) {
-  hipLaunchKernelGGL(combine_kernel, dim3((N + kCRows - 1) / kCRows), dim3(256), 0, s, N, k1, k2, A, lda, T, ldt,
-                     beta, Z, ldz, Y, ldy);
+  if (k2 > kMaxSmall) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(combine_kernel, dim3((N + kCbR - 1) / kCbR, 1), dim3(256), 0, s, N, k1, k2, A, A, A, lda, T, ldt,
+                     beta, Z, ldz, Y, Y, Y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t dense_combine3(int N, int k1, int k2, const double* A0, const double* A1, const double* A2, int lda,
+                          const double* T, int ldt, double* Y0, double* Y1, double* Y2, int ldy, hipStream_t s) {
+  if (k2 > kMaxSmall) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(combine_kernel, dim3((N + kCbR - 1) / kCbR, 3), dim3(256), 0, s, N, k1, k2, A0, A1, A2, lda, T,
+                     ldt, 0.0, nullptr, 0, Y0, Y1, Y2, ldy);
   return hipGetLastError();
 }
 

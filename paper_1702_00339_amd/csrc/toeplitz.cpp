@@ -413,7 +413,8 @@ int32_t lhf_toeplitz_matvec(lhf_toeplitz_t t, int32_t prec, int32_t ncols, const
 namespace {
 
 constexpr int kGuard = 4;     // block vectors beyond the wanted ones
-constexpr int kChunks = 32;   // row chunks of the tall reductions
+constexpr int kChunks = 32;   // row chunks of the residual norms
+constexpr int kGramChunks = 64;   // row chunks of the Gram products
 constexpr double kDropPivot = 1e-10;   // Cholesky-QR: squared relative distance below which a column is dropped
 
 struct EigWs {
@@ -439,7 +440,7 @@ size_t eigs_layout(const lhf_toeplitz_s* t, int nev, EigWs* w, char* base) {
   const size_t sq = (size_t)kMaxSmall * kMaxSmall;
   take(d.G, sq); take(d.Gs, sq); take(d.lam, kMaxSmall); take(d.dvec, kMaxSmall);
   take(d.T, sq); take(d.GH, sq); take(d.th, kMaxSmall); take(d.C, sq); take(d.C2, sq); take(d.norms, kMaxSmall);
-  take(d.syw, kSyevWorkDoubles); take(d.part, (size_t)kChunks * sq); take(d.rpart, (size_t)kChunks * kMaxSmall);
+  take(d.syw, kSyevWorkDoubles); take(d.part, (size_t)kGramChunks * sq); take(d.rpart, (size_t)kChunks * kMaxSmall);
   d.mv_bytes = lhf_toeplitz_matvec_workspace(const_cast<lhf_toeplitz_s*>(t), mx);
   d.mv = base ? base + off : nullptr;
   off += d.mv_bytes;
@@ -520,7 +521,7 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t t, int32_t nev, int32_t maxit, double t
     // scaled Gram matrix in the column order [X W P], dropping columns that
     // are numerically in the span of the ones before them
     matvec(prec, m, w.Q, mx, w.HQ, w.SQ);
-    ck(dense_gram(N, m, m, w.Q, mx, w.SQ, mx, w.part, kChunks, w.G, S, s));
+    ck(dense_gram(N, m, m, w.Q, mx, w.SQ, mx, w.part, kGramChunks, w.G, S, s));
     ck(dense_scale_sym(m, w.G, S, w.Gs, S, w.dvec, s));
     ck(dense_cholqr_t(m, w.Gs, S, w.dvec, kDropPivot, w.T, S, w.lam, s));
     ck(hipMemcpyAsync(hl.data(), w.lam, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -528,19 +529,15 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t t, int32_t nev, int32_t maxit, double t
     if (e != hipSuccess) break;
     const int kk = (int)hl[0];
     if (kk < nb) { st = LHF_ERR_INVALID; set_error("LOBPCG basis lost rank"); break; }
-    ck(dense_combine(N, m, kk, w.Q, mx, w.T, S, 0.0, nullptr, 0, w.Q2, mx, s));
-    ck(dense_combine(N, m, kk, w.HQ, mx, w.T, S, 0.0, nullptr, 0, w.HQ2, mx, s));
-    ck(dense_combine(N, m, kk, w.SQ, mx, w.T, S, 0.0, nullptr, 0, w.SQ2, mx, s));
+    ck(dense_combine3(N, m, kk, w.Q, w.HQ, w.SQ, mx, w.T, S, w.Q2, w.HQ2, w.SQ2, mx, s));
     // Rayleigh-Ritz in FP64
-    ck(dense_gram(N, kk, kk, w.Q2, mx, w.HQ2, mx, w.part, kChunks, w.GH, S, s));
+    ck(dense_gram(N, kk, kk, w.Q2, mx, w.HQ2, mx, w.part, kGramChunks, w.GH, S, s));
     ck(dense_symmetrize(kk, w.GH, S, s));
     ck(dense_syev_w(kk, w.GH, S, w.th, w.C, S, w.syw, s));
-    ck(dense_combine(N, kk, nb, w.Q2, mx, w.C, S, 0.0, nullptr, 0, w.W, nb, s));     // X_new
-    ck(dense_combine(N, kk, nb, w.HQ2, mx, w.C, S, 0.0, nullptr, 0, w.HX, nb, s));
-    ck(dense_combine(N, kk, nb, w.SQ2, mx, w.C, S, 0.0, nullptr, 0, w.SX, nb, s));
+    ck(dense_combine3(N, kk, nb, w.Q2, w.HQ2, w.SQ2, mx, w.C, S, w.W, w.HX, w.SX, nb, s));   // X_new, HX, SX
     if (it > 0) {
       // P = X_new - X (X^T S X_new)
-      ck(dense_gram(N, nb, nb, w.X, nb, w.SX, nb, w.part, kChunks, w.C2, S, s));
+      ck(dense_gram(N, nb, nb, w.X, nb, w.SX, nb, w.part, kGramChunks, w.C2, S, s));
       ck(dense_combine(N, nb, nb, w.X, nb, w.C2, S, -1.0, w.W, nb, w.P, nb, s));
       // P currently holds X C2 - X_new; its sign does not matter for the span
       haveP = true;

@@ -84,6 +84,9 @@ hipError_t dense_gram(int N, int k1, int k2, const double* A, int lda, const dou
 // Y = beta Z + A T   (Z may alias nothing; beta = 0 ignores Z)
 hipError_t dense_combine(int N, int k1, int k2, const double* A, int lda, const double* T, int ldt, double beta,
                          const double* Z, int ldz, double* Y, int ldy, hipStream_t s);
+// Y_a = A_a T for three blocks sharing T (one launch); k2 <= kMaxSmall
+hipError_t dense_combine3(int N, int k1, int k2, const double* A0, const double* A1, const double* A2, int lda,
+                          const double* T, int ldt, double* Y0, double* Y1, double* Y2, int ldy, hipStream_t s);
 // Jacobi of the dense eigensolver: sweep cap, and the workspace for the
 // eigenvectors (a header with the round count and the ascending order, then
 // the (c, s) of every pair of every recorded round)

@@ -452,7 +452,15 @@ __global__ void __launch_bounds__(256) fft_inv_kernel(int L, int m0, int P, int 
   }
 }
 
-// y_k += sum_entries D x_m for every affected block row k (grid y: H, S).
+constexpr int kCrossJ = 32;                    // columns per workgroup
+constexpr int kCrossMG = 8;                    // row groups: thread group g owns rows g, g + 8, ...
+constexpr int kCrossAcc = kMaxM0 / kCrossMG;   // rows per thread
+
+// y_k += sum over the entries q of row r of D_q x_{m_q} for the affected block
+// row k = row_cell[r] (grid: rows, column chunks of kCrossJ, H / S).  Per entry
+// the workgroup stages D_q (m0 x m0) and the chunk's columns of the m0 rows of
+// block m_q of x in LDS; thread (j, g) accumulates rows g, g + 8, ... of
+// column j over the entries in order.
 __global__ void __launch_bounds__(256) cross_apply_kernel(int m0, int ncols, const double* __restrict__ x, int ld,
                                                           const int32_t* __restrict__ row_ptr,
                                                           const int32_t* __restrict__ row_cell,
@@ -460,20 +468,41 @@ __global__ void __launch_bounds__(256) cross_apply_kernel(int m0, int ncols, con
                                                           const double* __restrict__ dH,
                                                           const double* __restrict__ dS, double* __restrict__ yH,
                                                           double* __restrict__ yS) {
-  const int r = blockIdx.x, k = row_cell[r];
-  const double* Dm = blockIdx.y == 0 ? dH : dS;
-  double* y = blockIdx.y == 0 ? yH : yS;
+  __shared__ double xs[kMaxM0][kCrossJ];
+  __shared__ double ds[kMaxM0][kMaxM0 + 1];
+  const int r = blockIdx.x, k = row_cell[r], j0 = blockIdx.y * kCrossJ;
+  const double* Dm = blockIdx.z == 0 ? dH : dS;
+  double* y = blockIdx.z == 0 ? yH : yS;
+  const int jl = threadIdx.x % kCrossJ, g = threadIdx.x / kCrossJ, j = j0 + jl;
   const int mm = m0 * m0;
-  for (int e = threadIdx.x; e < m0 * ncols; e += 256) {
-    const int mu = e / ncols, j = e % ncols;
-    double acc = 0.0;
-    for (int q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
-      const int m = ent[q].m;
-      const double* d = Dm + (int64_t)q * mm + mu * m0;
-      const double* xm = x + (int64_t)m * m0 * ld + j;
-      for (int nu = 0; nu < m0; ++nu) acc += d[nu] * xm[(int64_t)nu * ld];
+  double acc[kCrossAcc];
+#pragma unroll
+  for (int t = 0; t < kCrossAcc; ++t) acc[t] = 0.0;
+  for (int q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
+    const int m = ent[q].m;
+    const double* d = Dm + (int64_t)q * mm;
+    for (int e = threadIdx.x; e < mm; e += 256) ds[e / m0][e % m0] = d[e];
+    for (int e = threadIdx.x; e < m0 * kCrossJ; e += 256) {
+      const int nu = e / kCrossJ, jj = e % kCrossJ;
+      xs[nu][jj] = j0 + jj < ncols ? x[((int64_t)m * m0 + nu) * ld + j0 + jj] : 0.0;
     }
-    y[((int64_t)k * m0 + mu) * ld + j] += acc;
+    __syncthreads();
+    for (int nu = 0; nu < m0; ++nu) {
+      const double xv = xs[nu][jl];
+#pragma unroll
+      for (int t = 0; t < kCrossAcc; ++t) {
+        const int mu = g + kCrossMG * t;
+        if (mu < m0) acc[t] += ds[mu][nu] * xv;
+      }
+    }
+    __syncthreads();
+  }
+  if (j < ncols) {
+#pragma unroll
+    for (int t = 0; t < kCrossAcc; ++t) {
+      const int mu = g + kCrossMG * t;
+      if (mu < m0) y[((int64_t)k * m0 + mu) * ld + j] += acc[t];
+    }
   }
 }
 
@@ -561,8 +590,8 @@ hipError_t toep_launch_apply(int prec, int L, int m0, int P, int ncols, const do
                      ? apply_t<double>(L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS, s)
                      : apply_t<float>(L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS, s);
   if (e != hipSuccess || nrows == 0) return e;
-  hipLaunchKernelGGL(cross_apply_kernel, dim3(nrows, opS ? 2 : 1), dim3(256), 0, s, m0, ncols, x, ld, row_ptr,
-                     row_cell, ent, dH, dS, yH, yS);
+  hipLaunchKernelGGL(cross_apply_kernel, dim3(nrows, (ncols + kCrossJ - 1) / kCrossJ, opS ? 2 : 1), dim3(256), 0, s, m0,
+                     ncols, x, ld, row_ptr, row_cell, ent, dH, dS, yH, yS);
   return hipGetLastError();
 }
 
