@@ -111,6 +111,22 @@ def dft_bytes(pipe, insts, kind="plan"):
     return total
 
 
+def sep_bytes(pipe, insts):
+    """Algorithmic HBM bytes of one lhf_fourier_blocks call: every Fourier
+    block written once (H and S, complex128), every FP64 1D Gram read once,
+    and the 1D-transformed Grams of dimensions 2 and 3 (complex128) written
+    once and read once."""
+    total = 0
+    for i, inst in enumerate(insts):
+        m2 = inst.m0 * inst.m0
+        T = 2 + inst.M0 * inst.R
+        nshift, _, _ = pipe.plan.lhf_plan_band(i)
+        total += 2 * inst.ncells * m2 * 16
+        total += sum(T * nshift[d] * m2 * 8 for d in range(3))
+        total += 2 * sum(T * inst.L[d] * m2 * 16 for d in (1, 2))
+    return total
+
+
 def canonical_blocks(L):
     """Blocks solved once per conjugate pair j, -j."""
     self_conj = 1
@@ -272,9 +288,15 @@ def main():
 
     # rooflines, event-timed on the stream the kernels run on
     pm = pipes["mixed"]
-    ms_dft = event_ms(lambda: pm.plan.lhf_block_fft(lhf.LHF_PREC_FP64, pm.H_gen64, pm.S_gen64, pm.H_bar64,
-                                                     pm.S_bar64, pm.ws), args.steps, torch)
-    bytes_alg = dft_bytes(pm, insts, kind="fp64")
+    sep = pm.separable()   # the Fourier-block route the tuned step takes
+    if sep:
+        ms_dft = event_ms(lambda: pm.plan.lhf_fourier_blocks(pm.grams64, pm.H_bar64, pm.S_bar64, pm.ws),
+                          args.steps, torch)
+        bytes_alg = sep_bytes(pm, insts)
+    else:
+        ms_dft = event_ms(lambda: pm.plan.lhf_block_fft(lhf.LHF_PREC_FP64, pm.H_gen64, pm.S_gen64, pm.H_bar64,
+                                                         pm.S_bar64, pm.ws), args.steps, torch)
+        bytes_alg = dft_bytes(pm, insts, kind="fp64")
     achieved = bytes_alg / (ms_dft * 1e-3) / 1e9
     flags = lhf.LHF_HEEV_REFINE_FP64
     ms_heev = event_ms(lambda: pm.plan.lhf_heev_batched(flags, None, None, pm.w, pm.info, pm.ws,
@@ -320,9 +342,11 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64", "data": "synthetic",
         "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "lattices": len(insts),
                    "k_point_blocks": nblk, "m0": m0s if len(m0s) > 1 else m0s[0],
-                   "path": "mixed: FP64 MFMA Grams, FP64 stacks, one block DFT writing complex128 blocks, "
-                           "FP32 Jacobi on their roundings, FP64 Rayleigh-Ritz refinement on complex128; "
-                           "one hipGraph replay per step"},
+                   "path": ("mixed: FP64 MFMA Grams, " +
+                            ("Fourier blocks formed separably from the Grams (complex128, no generator stacks)"
+                             if sep else "FP64 stacks, one block DFT writing complex128 blocks") +
+                            ", FP32 Jacobi on their roundings, FP64 Rayleigh-Ritz refinement on complex128; "
+                            "one hipGraph replay per step")},
         "fp64_path": {"value": nblk / sec["fp64"], "ms_per_step": sec["fp64"] * 1e3, "dtype": "f64"},
         "mixed_bf16x3_path": {"value": nblk / sec["mixed_bf16x3"], "ms_per_step": sec["mixed_bf16x3"] * 1e3,
                               "max_abs_eig_err_ha": errs["mixed_bf16x3"][0], "info_ok": errs["mixed_bf16x3"][2]},
@@ -332,9 +356,11 @@ def main():
         "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: FP32 Jacobi + FP64 refinement)",
                      "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s", "frac": tflops / 157.3,
                      "traffic": traffic("eig"), "flops_per_launch": flops, "avg_launch_ms": ms_heev},
-        "roofline_dft": {"bound": "hbm", "kernel": "block DFT (lhf_block_fft, FP64 stacks to complex128)",
+        "roofline_dft": {"bound": "hbm",
+                         "kernel": ("separable Fourier blocks (lhf_fourier_blocks: gram_dft + sep_fused, FP64 Grams "
+                                    "to complex128)" if sep else "block DFT (lhf_block_fft, FP64 stacks to complex128)"),
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("dft"),
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("sep" if sep else "dft"),
                          "bytes_per_launch": bytes_alg, "avg_launch_ms": ms_dft},
         "tuning": tuning,
         "dirichlet_c5": c5,

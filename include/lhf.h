@@ -176,7 +176,10 @@ int32_t lhf_plan_destroy(lhf_plan_t plan);
  *   A mixed plan given the FP64 stacks may pass d_H_gen = d_S_gen = NULL:
  *   then only the FP64 stacks are written (lhf_block_fft_dual makes the
  *   complex64 blocks from them).
- * Errors: LHF_ERR_INVALID (NULL outputs, bad plan), LHF_ERR_WORKSPACE. */
+ * With all four stacks NULL only the factors and the FP64 Grams are computed
+ * (into d_grams64, or the workspace when it is NULL), for
+ * lhf_fourier_blocks.
+ * Errors: LHF_ERR_INVALID (bad plan, one of a pair NULL), LHF_ERR_WORKSPACE. */
 int32_t lhf_assemble_blocks(lhf_plan_t plan, void* d_H_gen, void* d_S_gen, double* d_grams64,
                             double* d_H_gen64, double* d_S_gen64,
                             void* d_ws, size_t ws_bytes, lhf_stream_t stream);
@@ -201,6 +204,26 @@ int32_t lhf_block_fft(lhf_plan_t plan, int32_t prec, const void* d_H_gen, const 
  * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE. */
 int32_t lhf_block_fft_dual(lhf_plan_t plan, const double* d_H_gen64, const double* d_S_gen64,
                            void* d_H_bar64, void* d_S_bar64, void* d_H_bar32, void* d_S_bar32,
+                           void* d_ws, size_t ws_bytes, lhf_stream_t stream);
+
+/* Separable formation of the Fourier blocks (Theorem 3.3, Remark 3.5): the
+ * same Hbar_j, Sbar_j as lhf_block_fft of the FP64 stacks, without generator
+ * stacks.  The generator is a sum of Hadamard products of 1D Grams, so its
+ * transform over dimensions 2 and 3 is the same sum of products of the
+ * 1D-transformed Grams G^_l[j_l] = sum_s w_l^(j_l k_s) G_l[s]:
+ *   Sbar_j = S^1[j1] o S^2[j2] o S^3[j3],
+ *   Hbar_j = 1/2 (K^1 o S^2 o S^3 + S^1 o K^2 o S^3 + S^1 o S^2 o K^3)
+ *            - sum_r M^1_r o M^2_r o M^3_r,
+ * with the band-pruned transform over dimension 1 done last; every block is
+ * written once.  FP64 arithmetic on either plan precision.
+ * d_grams64: the FP64 Grams written by lhf_assemble_blocks (any mode), or
+ *   NULL for the copy in the workspace from the last assembly on it.
+ * d_H_bar64, d_S_bar64: device complex128 [gen_elems], layout as
+ *   lhf_block_fft.
+ * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE, LHF_ERR_UNSUPPORTED (a lattice
+ * whose first-dimension band is wider than 32 slots, or whose first axis
+ * and band need more than 64 KiB of LDS per workgroup). */
+int32_t lhf_fourier_blocks(lhf_plan_t plan, const double* d_grams64, void* d_H_bar64, void* d_S_bar64,
                            void* d_ws, size_t ws_bytes, lhf_stream_t stream);
 
 /* ---------------------------------------------------------------- eigensolve
@@ -377,7 +400,13 @@ int32_t lhf_graph_destroy(lhf_graph_t graph);
  *                matrix entry per thread instead of four (for batches too
  *                small to fill the device); 0..15, the planner sets the
  *                classes whose four-entry launch has fewer wavefronts than
- *                the device has SIMDs.
+ *                the device has SIMDs;
+ *   fourier_sep  1: whole steps (lhf_step, graphs) form the complex128
+ *                Fourier blocks separably from the FP64 Grams
+ *                (lhf_fourier_blocks) instead of generator stacks and a block
+ *                DFT, on FP64 plans and on mixed plans whose FP32 solve reads
+ *                the complex128 blocks; the generator stacks are then not
+ *                written.  Reads 0 when the plan does not qualify.
  * None of them changes what is computed; the Gram split changes the order of
  * the FP64 partial sums and the eigensolver layout the order of its sums. */
 typedef struct {
@@ -386,6 +415,7 @@ typedef struct {
   int32_t gram_grid;
   int32_t tol32_scale;
   int32_t heev_wide;
+  int32_t fourier_sep;
   double step_ms;        /* autotune: mean time of one step with these settings */
   int32_t from_cache;    /* autotune: 1 when read from the cache file         */
 } lhf_tuning;

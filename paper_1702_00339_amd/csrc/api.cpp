@@ -32,7 +32,8 @@ int32_t lhf_assemble_blocks(lhf_plan_t p, void* H_gen, void* S_gen, double* gram
   if (!p) { set_error("NULL plan"); return LHF_ERR_INVALID; }
   if ((H_gen == nullptr) != (S_gen == nullptr)) { set_error("give both stacks H_gen and S_gen or neither"); return LHF_ERR_INVALID; }
   if ((H_gen64 == nullptr) != (S_gen64 == nullptr)) { set_error("give both FP64 stacks or neither"); return LHF_ERR_INVALID; }
-  if (!H_gen && !(p->prec == LHF_PREC_MIXED && H_gen64)) {
+  const bool grams_only = !H_gen && !H_gen64;   // factors and FP64 Grams only (for lhf_fourier_blocks)
+  if (!H_gen && H_gen64 && p->prec != LHF_PREC_MIXED) {
     set_error("H_gen and S_gen are required (a mixed plan may omit them when it writes the FP64 stacks)");
     return LHF_ERR_INVALID;
   }
@@ -42,11 +43,16 @@ int32_t lhf_assemble_blocks(lhf_plan_t p, void* H_gen, void* S_gen, double* gram
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = ws_view(p, ws);
   double* g64 = grams64 ? grams64 : w.grams64;
+  hipError_t e;
   const bool mixed = p->prec == LHF_PREC_MIXED;
+  if (grams_only) {
+    e = launch_factors(p, w.fac, s);
+    if ((st = hip_status(e, "factors")) != LHF_OK) return st;
+    return hip_status(launch_grams(p, LHF_GRAM_FP64, w.fac, w.part64, g64, s), "gram fp64");
+  }
   const bool want32 = !mixed || H_gen != nullptr;   // mixed plans: FP32 stacks only when asked for
   const bool split = mixed && p->gram != LHF_GRAM_FP64 && want32;
   const bool need64 = !mixed || !split || grams64 || H_gen64;
-  hipError_t e;
   e = launch_factors(p, w.fac, s);
   if ((st = hip_status(e, "factors")) != LHF_OK) return st;
   if (need64) {
@@ -91,6 +97,22 @@ int32_t lhf_block_fft_dual(lhf_plan_t p, const double* H_gen64, const double* S_
   return hip_status(launch_block_dft(p, LHF_PREC_FP64, H_gen64, S_gen64, H_bar64, S_bar64, w.dft, (float2*)H_bar32,
                                      (float2*)S_bar32, static_cast<hipStream_t>(stream)),
                     "block dft");
+}
+
+int32_t lhf_fourier_blocks(lhf_plan_t p, const double* grams64, void* H_bar64, void* S_bar64, void* ws,
+                           size_t ws_bytes, lhf_stream_t stream) {
+  if (!p) { set_error("NULL plan"); return LHF_ERR_INVALID; }
+  if (!H_bar64 || !S_bar64) { set_error("H_bar64 and S_bar64 are required"); return LHF_ERR_INVALID; }
+  if (!p->sep_ok) {
+    set_error("separable formation needs every lattice's first-dimension band within 32 slots and 64 KiB of LDS");
+    return LHF_ERR_UNSUPPORTED;
+  }
+  int32_t st = check_ws(p, ws, ws_bytes);
+  if (st != LHF_OK) return st;
+  Ws w = ws_view(p, ws);
+  return hip_status(launch_fourier_sep(p, grams64 ? grams64 : w.grams64, w.gh, static_cast<double2*>(H_bar64),
+                                       static_cast<double2*>(S_bar64), static_cast<hipStream_t>(stream)),
+                    "separable fourier blocks");
 }
 
 int32_t lhf_heev_batched(lhf_plan_t p, uint32_t flags, const void* H_bar, const void* S_bar,

@@ -222,6 +222,98 @@ __device__ __forceinline__ int find_fused(const FusedTask* __restrict__ t, int n
   return lo;
 }
 
+// Last stage of the fused transforms: the outputs j1 = j + q Q (q < R1,
+// Q = L1 / R1, R1 = 4, 2 or 1 as L1 allows) share the twiddles w1^(j k1) up
+// to zeta^(q k1), zeta = w1^Q = +-i or -1.  The inputs T2[s1][jj][ec] (LDS)
+// are summed by slot residue a = s1 mod 4 (k1 = s1 + off mod R1), and Y_q =
+// zeta^(q off) sum_a zeta^(q a) S_a: one complex multiply-add per input for R1
+// outputs.  A thread owns one (j2, e) column with its B1 inputs in registers
+// and walks groups of R1 outputs j1 with incrementally updated twiddle indices.
+template <typename R, int BM>
+__device__ __forceinline__ void fused_last_stage(const LatDev& L, int J2C, int j2lo, int j2n, int j3, int e0, int ecn,
+                                                 const typename Cx<R>::T* T2, const typename Cx<R>::T* tw1, bool isH,
+                                                 typename Cx<R>::T* __restrict__ barH,
+                                                 typename Cx<R>::T* __restrict__ barS, float2* __restrict__ b32H,
+                                                 float2* __restrict__ b32S) {
+  typedef typename Cx<R>::T C;
+  constexpr int EC = kFusedEC;
+  const DimDev& D0 = L.dim[0];
+  const int L1 = L.L[0], L2 = L.L[1], L3 = L.L[2], B1 = nslot(D0), E = L.m0 * L.m0;
+  const int tid = threadIdx.x, ec = tid & (EC - 1);
+  const int ncol = J2C * EC, nrep = 256 / ncol;
+  const int col = tid % ncol, rep = tid / ncol;
+  const int jj = col / EC;
+  if (rep >= nrep || jj >= j2n || ec >= ecn) return;
+  const int R1 = (L1 & 3) == 0 ? 4 : (L1 & 1) == 0 ? 2 : 1;
+  const int Q = L1 / R1;
+  const int off = slot_cell(D0, 0) % R1;
+  R xr[BM], xi[BM];
+  int idx[BM], stp[BM];
+#pragma unroll
+  for (int s1 = 0; s1 < BM; ++s1) {
+    if (s1 < B1) {
+      const C x = T2[(s1 * J2C + jj) * EC + ec];
+      xr[s1] = x.x;
+      xi[s1] = x.y;
+      const int k1 = slot_cell(D0, s1);
+      idx[s1] = (rep * k1) % L1;
+      stp[s1] = (nrep * k1) % L1;
+    }
+  }
+  const int64_t yoff = L.gen_off + ((int64_t)(j2lo + jj) * L3 + j3) * E + e0 + ec;
+  C* Y = (isH ? barH : barS) + yoff;
+  float2* Y32 = b32H ? (isH ? b32H : b32S) + yoff : nullptr;
+  const int64_t jstride = (int64_t)L2 * L3 * E;
+  const R zs = tw1[Q % L1].y < R(0) ? R(-1) : R(1);   // zeta = zs i when R1 = 4
+  // output j1 = j + q Q sits (j1 - j) jstride past the base output j
+  const int64_t ystep = (int64_t)nrep * jstride, qstep = (int64_t)Q * jstride;
+  int64_t ybase = (int64_t)rep * jstride;
+  auto put = [&](int q, R re, R im) {
+    C v;
+    v.x = re;
+    v.y = im;
+    const int64_t o = ybase + q * qstep;
+    Y[o] = v;
+    if (Y32) Y32[o] = make_float2((float)re, (float)im);
+  };
+  for (int j = rep; j < Q; j += nrep, ybase += ystep) {
+    R sr[4] = {R(0), R(0), R(0), R(0)}, si[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int s1 = 0; s1 < BM; ++s1) {
+      if (s1 < B1) {
+        const C w = tw1[idx[s1]];
+        sr[s1 & 3] += w.x * xr[s1] - w.y * xi[s1];
+        si[s1 & 3] += w.x * xi[s1] + w.y * xr[s1];
+        idx[s1] += stp[s1];
+        if (idx[s1] >= L1) idx[s1] -= L1;
+      }
+    }
+    if (R1 == 4) {
+      // U_q = sum_a zeta^(q a) S_a; zeta (x + i y) = zs (-y + i x); Y_q = zeta^(q off) U_q
+      const R ar = sr[0] + sr[2], ai = si[0] + si[2], br = sr[0] - sr[2], bi = si[0] - si[2];
+      const R cr = sr[1] + sr[3], ci = si[1] + si[3], dr = sr[1] - sr[3], di = si[1] - si[3];
+      auto rot = [&](int q, R yr, R yi) {
+        const int m = (q * off) & 3;
+        if (m == 1) { const R tr = -zs * yi; yi = zs * yr; yr = tr; }
+        else if (m == 2) { yr = -yr; yi = -yi; }
+        else if (m == 3) { const R tr = zs * yi; yi = -zs * yr; yr = tr; }
+        put(q, yr, yi);
+      };
+      rot(0, ar + cr, ai + ci);
+      rot(1, br - zs * di, bi + zs * dr);
+      rot(2, ar - cr, ai - ci);
+      rot(3, br + zs * di, bi - zs * dr);
+    } else if (R1 == 2) {
+      const R er = sr[0] + sr[2], ei = si[0] + si[2], orr = sr[1] + sr[3], oi = si[1] + si[3];
+      put(0, er + orr, ei + oi);
+      const R sg = (off & 1) ? R(-1) : R(1);
+      put(1, sg * (er - orr), sg * (ei - oi));
+    } else {
+      put(0, sr[0] + sr[1] + sr[2] + sr[3], si[0] + si[1] + si[2] + si[3]);
+    }
+  }
+}
+
 // Fused transform of all three dimensions of a lattice (band-pruned):
 //   stage 1: T1[s1][s2][e] = sum_s3 w3^(j3 k3) A[k1][k2][k3][e]      (fixed j3)
 //   stage 2: T2[s1][j2][e] = sum_s2 w2^(j2 k2) T1[s1][s2][e]          (a chunk of j2)
@@ -460,6 +552,160 @@ hipError_t dft_launch_all(const lhf_plan_s* p, const R* gH, const R* gS, typenam
   return hipGetLastError();
 }
 
+// Separable formation of the Fourier blocks (Theorem 3.3, Remark 3.5).  The
+// generator is a sum of Hadamard products of 1D Grams (eqs. BC-Core,
+// BC-mass, BC-Laplace),
+//   S_k = S1[k1] o S2[k2] o S3[k3],
+//   H_k = 1/2 (K1 o S2 o S3 + S1 o K2 o S3 + S1 o S2 o K3) - sum_t M1_t o M2_t o M3_t,
+// so its transform over dimensions 2 and 3 is the same expression in the
+// 1D-transformed Grams G^_l[j] = sum_s w_l^(j k_s) G_l[s] (complex, small):
+//   T2[s1](j2, j3) = 1/2 (K1[s1] P_ss + S1[s1] P_ks) - sum_t M1_t[s1] P_t,
+//   P_ss = S^2 S^3,  P_ks = K^2 S^3 + S^2 K^3,  P_t = M^2_t M^3_t,
+// and the last stage transforms dimension 1 as in the fused kernel.  No
+// generator stack is formed or read; every Fourier block is written once.
+
+// G^ along dimensions 2 and 3: gh[t][j][e] = sum over slots s of w^(j k_s) G[t][s][e]
+__global__ void __launch_bounds__(256) gram_dft_kernel(const LatDev* __restrict__ lats,
+                                                       const GhItem* __restrict__ items, int nitems,
+                                                       const double* __restrict__ grams,
+                                                       const double2* __restrict__ tw, double2* __restrict__ gh) {
+  const int64_t wg0 = (int64_t)blockIdx.x * 256;
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].start <= wg0) lo = mid; else hi = mid - 1;
+  }
+  const GhItem it = items[lo];
+  const LatDev& L = lats[it.li];
+  const DimDev& D = L.dim[it.d];
+  const int m2 = L.m0 * L.m0;
+  const int64_t idx = wg0 - it.start + threadIdx.x;
+  if (idx >= (int64_t)L.T * D.L * m2) return;
+  const int e = (int)(idx % m2);
+  const int j = (int)((idx / m2) % D.L);
+  const int t = (int)(idx / ((int64_t)m2 * D.L));
+  double re = 0.0, im = 0.0;
+  const int ns = nslot(D);
+#pragma unroll 4
+  for (int s = 0; s < ns; ++s) {
+    const double2 w = tw[D.tw_off + (int)(((int64_t)j * slot_cell(D, s)) % D.L)];
+    const double g = grams[D.gram_off + ((int64_t)t * D.nshift + s) * m2 + e];
+    re += w.x * g;
+    im += w.y * g;
+  }
+  gh[D.gh_off + idx] = make_double2(re, im);
+}
+
+constexpr int kSepTC = 8;   // Gram terms staged in LDS per step
+
+// Workgroup (lattice, entry chunk, j2 chunk, j3) as in dft_fused_kernel;
+// grid y: H, S.  With Q_0 = P_ks / 2, Q_1 = P_ss / 2 and Q_t = -P_t (t >= 2)
+// for H, and Q_0 = P_ss for S (one term), T2[s1] = sum_t G1_t[s1] Q_t.  The
+// terms go in steps of kSepTC: the workgroup stages G1_t[s1][ec] and
+// Q_t[jj][ec] in LDS, then thread (column (jj, ec), part sp) accumulates the
+// slots s1 = sp, sp + nsp, ... of its column.
+template <int BM>
+__global__ void __launch_bounds__(256) sep_fused_kernel(const LatDev* __restrict__ lats,
+                                                        const FusedTask* __restrict__ tasks, int ntasks,
+                                                        const double2* __restrict__ tw,
+                                                        const double* __restrict__ grams,
+                                                        const double2* __restrict__ gh, double2* __restrict__ barH,
+                                                        double2* __restrict__ barS) {
+  typedef double2 C;
+  extern __shared__ char lds_raw[];
+  const int64_t wg = blockIdx.x;
+  const FusedTask T = tasks[find_fused(tasks, ntasks, wg)];
+  const LatDev& L = lats[T.li];
+  const DimDev& D0 = L.dim[0];
+  const DimDev& D1 = L.dim[1];
+  const DimDev& D2 = L.dim[2];
+  const int L1 = L.L[0], L2 = L.L[1], L3 = L.L[2], B1 = nslot(D0);
+  constexpr int EC = kFusedEC;
+  const int m2 = L.m0 * L.m0, J2C = T.J2C;
+  int64_t loc = wg - T.wg_base;
+  const int eci = (int)(loc % T.nec);
+  loc /= T.nec;
+  const int j2c = (int)(loc % T.nj2c);
+  const int j3 = (int)(loc / T.nj2c);
+  const int e0 = eci * EC, ecn = min(EC, m2 - e0);
+  const int j2lo = j2c * J2C, j2n = min(J2C, L2 - j2lo);
+  C* T2 = reinterpret_cast<C*>(lds_raw);             // [B1][J2C][EC]
+  C* tw1 = T2 + B1 * J2C * EC;                       // [L1]
+  C* Qs = tw1 + L1;                                  // [kSepTC][J2C][EC]
+  double* G1s = reinterpret_cast<double*>(Qs + kSepTC * J2C * EC);   // [kSepTC][B1][EC]
+  const int tid = threadIdx.x;
+  for (int q = tid; q < L1; q += 256) tw1[q] = tw[D0.tw_off + q];
+  const bool isH = blockIdx.y == 0;
+  const int nterm = isH ? L.T : 1;
+  const int ncol = J2C * EC, nsp = 256 / ncol;
+  const int col = tid % ncol, sp = tid / ncol;
+  const int jj = col / EC, ec = col % EC;
+  constexpr int NA = (BM + 1) / 2;   // slots per thread (nsp >= 2)
+  double ar[NA], ai[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) ar[u] = ai[u] = 0.0;
+  const double2* g2 = gh + D1.gh_off;   // [t][L2][m2]
+  const double2* g3 = gh + D2.gh_off;   // [t][L3][m2]
+  const int64_t st2 = (int64_t)L2 * m2, st3 = (int64_t)L3 * m2;
+  for (int t0 = 0; t0 < nterm; t0 += kSepTC) {
+    const int tc = min(kSepTC, nterm - t0);
+    // Q_t for this step's terms, one (term, column) per thread
+    for (int q = tid; q < tc * ncol; q += 256) {
+      const int tt = q / ncol, c2 = q % ncol, qj = c2 / EC, qe = c2 % EC;
+      C v = make_double2(0.0, 0.0);
+      if (qj < j2n && qe < ecn) {
+        const int t = t0 + tt;
+        const int64_t o2 = (int64_t)(j2lo + qj) * m2 + e0 + qe, o3 = (int64_t)j3 * m2 + e0 + qe;
+        if (t >= 2) {
+          const C a2 = g2[t * st2 + o2], a3 = g3[t * st3 + o3];
+          v = make_double2(-(a2.x * a3.x - a2.y * a3.y), -(a2.x * a3.y + a2.y * a3.x));
+        } else {
+          const C s2 = g2[o2], s3 = g3[o3];
+          if (t == 1 || !isH) {
+            const double h = isH ? 0.5 : 1.0;   // Q_1 = P_ss / 2 (H), Q_0 = P_ss (S)
+            v = make_double2(h * (s2.x * s3.x - s2.y * s3.y), h * (s2.x * s3.y + s2.y * s3.x));
+          } else {
+            const C k2 = g2[st2 + o2], k3 = g3[st3 + o3];   // Q_0 = P_ks / 2
+            v = make_double2(0.5 * ((k2.x * s3.x - k2.y * s3.y) + (s2.x * k3.x - s2.y * k3.y)),
+                             0.5 * ((k2.x * s3.y + k2.y * s3.x) + (s2.x * k3.y + s2.y * k3.x)));
+          }
+        }
+      }
+      Qs[q] = v;
+    }
+    // G1_t[s1][ec] for this step's terms
+    for (int q = tid; q < tc * B1 * EC; q += 256) {
+      const int tt = q / (B1 * EC), r = q % (B1 * EC), s1 = r / EC, qe = r % EC;
+      G1s[q] = qe < ecn ? grams[D0.gram_off + ((int64_t)(t0 + tt) * D0.nshift + s1) * m2 + e0 + qe] : 0.0;
+    }
+    __syncthreads();
+    if (sp < nsp) {
+      for (int tt = 0; tt < tc; ++tt) {
+        const C qv = Qs[tt * ncol + col];
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+          const int s1 = sp + nsp * u;
+          if (s1 < B1) {
+            const double g = G1s[(tt * B1 + s1) * EC + ec];
+            ar[u] += g * qv.x;
+            ai[u] += g * qv.y;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (sp < nsp) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int s1 = sp + nsp * u;
+      if (s1 < B1) T2[(s1 * J2C + jj) * EC + ec] = make_double2(ar[u], ai[u]);
+    }
+  }
+  __syncthreads();
+  fused_last_stage<double, BM>(L, J2C, j2lo, j2n, j3, e0, ecn, T2, tw1, isH, barH, barS, nullptr, nullptr);
+}
+
 }  // namespace
 
 // LDS bytes (complex128) of the fused kernel for a lattice, 0 when the
@@ -579,6 +825,62 @@ void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std
       launches.push_back(l);
     }
   }
+}
+
+// Separable formation: one task per lattice (workgroups as in the fused
+// kernel; every lattice shape, chains included), and the transforms of the
+// Grams along dimensions 2 and 3.  ok = false when a lattice has a first
+// dimension band wider than 32 slots or needs more than 64 KiB of LDS.
+void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tasks, std::vector<GhItem>& items,
+                    int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, bool& ok) {
+  tasks.clear();
+  items.clear();
+  wgs = 0;
+  bmax = 0;
+  lds = 0;
+  gh_threads = 0;
+  ok = !lats.empty();
+  for (int li = 0; li < (int)lats.size(); ++li) {
+    const LatDev& L = lats[li];
+    const int B1 = nslot(L.dim[0]);
+    FusedTask t{};
+    t.li = li;
+    t.EC = kFusedEC;
+    t.nec = (L.m0 * L.m0 + kFusedEC - 1) / kFusedEC;
+    t.J2C = std::min(L.L[1], kFusedJ2);
+    t.nj2c = (L.L[1] + t.J2C - 1) / t.J2C;
+    const int64_t bytes = ((int64_t)B1 * t.J2C * kFusedEC + L.L[0] + (int64_t)kSepTC * t.J2C * kFusedEC) * 16 +
+                          (int64_t)kSepTC * B1 * kFusedEC * 8;
+    if (B1 > 32 || bytes > 65536) ok = false;
+    t.wg_base = wgs;
+    wgs += (int64_t)L.L[2] * t.nj2c * t.nec;
+    tasks.push_back(t);
+    bmax = std::max(bmax, B1);
+    lds = std::max<int32_t>(lds, (int32_t)bytes);
+    for (int d = 1; d < 3; ++d) {
+      items.push_back(GhItem{li, d, gh_threads});
+      gh_threads += ((int64_t)L.T * L.L[d] * L.m0 * L.m0 + 255) / 256 * 256;
+    }
+  }
+}
+
+hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* gh, double2* bar_h, double2* bar_s,
+                              hipStream_t s) {
+  if (!p->sep_ok || !gh) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gram_dft_kernel, dim3((unsigned)(p->gh_threads / 256)), dim3(256), 0, s, p->d_lat,
+                     p->d_gh_items, p->n_gh_items, g64, p->d_tw64, gh);
+  const dim3 grid((unsigned)p->sep_wgs, 2);
+  const size_t shb = (size_t)p->sep_lds;
+  if (p->sep_bmax <= 8)
+    hipLaunchKernelGGL(sep_fused_kernel<8>, grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, p->d_tw64, g64,
+                       gh, bar_h, bar_s);
+  else if (p->sep_bmax <= 16)
+    hipLaunchKernelGGL(sep_fused_kernel<16>, grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, p->d_tw64, g64,
+                       gh, bar_h, bar_s);
+  else
+    hipLaunchKernelGGL(sep_fused_kernel<32>, grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, p->d_tw64, g64,
+                       gh, bar_h, bar_s);
+  return hipGetLastError();
 }
 
 hipError_t launch_block_dft(const lhf_plan_s* p, int prec, const void* gen_h, const void* gen_s, void* bar_h,

@@ -41,6 +41,7 @@ struct DimDev {
   int64_t gram_off;   // elements: Grams [T][nshift][m0][m0]
   int64_t part_off;   // elements: split-K partials [ksplit][T m0][nshift m0]
   int64_t tw_off;     // complex elements: twiddles exp(-2 pi i m / L), m < L
+  int64_t gh_off;     // complex elements: 1D-transformed Grams [T][L][m0][m0] (dimensions 2, 3)
 };
 
 struct LatDev {
@@ -95,6 +96,13 @@ struct DftTask {
 struct FusedTask {
   int32_t li, J2C, nj2c, EC, nec, pad;
   int64_t wg_base;
+};
+
+// One (lattice, dimension) of the 1D transform of the Grams along dimensions
+// 2 and 3: outputs [T][L][m0^2] from thread `start` on (a multiple of 256).
+struct GhItem {
+  int32_t li, d;
+  int64_t start;
 };
 
 // Host-side record of one grouped DFT launch: tasks [t0, t0 + nt) of one pass

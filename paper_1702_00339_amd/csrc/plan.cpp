@@ -44,6 +44,7 @@ Ws ws_view(const lhf_plan_s* p, void* base) {
   w.dft = b + p->ws_dft;
   w.U = reinterpret_cast<float2*>(b + p->ws_U);
   w.info32 = reinterpret_cast<int32_t*>(b + p->ws_info);
+  w.gh = p->sep_ok ? reinterpret_cast<double2*>(b + p->ws_gh) : nullptr;
   return w;
 }
 
@@ -243,7 +244,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->prec = prec; p->gram = gram; p->nlat = nlat;
   p->lat.resize(nlat);
   std::string err;
-  int64_t fac = 0, grams = 0, part = 0, tw = 0, gen = 0, w = 0, blk = 0;
+  int64_t fac = 0, grams = 0, part = 0, tw = 0, gen = 0, w = 0, blk = 0, gh = 0;
   for (int i = 0; i < nlat; ++i) {
     int32_t st = derive_lattice(lats[i], i, p->lat[i], err);
     if (st != LHF_OK) { set_error(err); delete p; return st; }
@@ -255,6 +256,8 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
       D.gram_off = grams; grams += (int64_t)L.T * D.nshift * L.m0 * L.m0;
       D.part_off = part; part += (int64_t)D.ksplit * (L.T * L.m0) * (D.nshift * L.m0);
       D.tw_off = tw; tw += D.L;
+      D.gh_off = -1;
+      if (d > 0) { D.gh_off = gh; gh += (int64_t)L.T * D.L * L.m0 * L.m0; }
     }
     L.gen_off = gen; gen += (int64_t)L.nblk * L.m0 * L.m0;
     L.w_off = w; w += (int64_t)L.nblk * L.m0;
@@ -267,6 +270,12 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   plan_block_dft(p->lat, p->dft_target_threads, dft_tasks, p->dft_launches, dtmp, fused, p->fused_wgs,
                  p->fused_bmax, p->fused_lds);
   p->n_fused = (int32_t)fused.size();
+  std::vector<FusedTask> sep;
+  std::vector<GhItem> gh_items;
+  plan_separable(p->lat, sep, gh_items, p->sep_wgs, p->sep_bmax, p->sep_lds, p->gh_threads, p->sep_ok);
+  p->n_sep = (int32_t)sep.size();
+  p->n_gh_items = (int32_t)gh_items.size();
+  p->gh_elems = gh;
   p->sizes.nlat = nlat;
   p->sizes.nblocks = blk;
   p->sizes.gen_elems = gen;
@@ -286,6 +295,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
     p->ws_info = off; off = align256(off + (size_t)blk * 4);
   }
   p->ws_dft = off; off = align256(off + (size_t)dtmp * 16);   // complex128 (either precision)
+  if (p->sep_ok) { p->ws_gh = off; off = align256(off + (size_t)gh * 16); }
   p->sizes.ws_bytes = off;
 
   std::vector<GramItem> items;
@@ -356,6 +366,10 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   upload(p->d_elem_start, elem_start.data(), elem_start.size());
   upload(p->d_dft_tasks, dft_tasks.data(), dft_tasks.size());
   upload(p->d_fused, fused.data(), fused.size());
+  if (p->sep_ok) {
+    upload(p->d_sep, sep.data(), sep.size());
+    upload(p->d_gh_items, gh_items.data(), gh_items.size());
+  }
   for (int c = 0; c < 4; ++c) upload(p->d_canon[c], canon[c].data(), canon[c].size());
   if (!ok) {
     set_error("allocation or upload of the plan tables failed");
@@ -392,7 +406,7 @@ int32_t lhf_plan_destroy(lhf_plan_t plan) {
   if (!plan) return LHF_OK;
   void* tables[] = {plan->d_lat, plan->d_tw64, plan->d_tw32, plan->d_gram_items, plan->d_fac_items,
                     plan->d_elem_start, plan->d_dft_tasks, plan->d_fused, plan->d_canon[0], plan->d_canon[1],
-                    plan->d_canon[2], plan->d_canon[3]};
+                    plan->d_canon[2], plan->d_canon[3], plan->d_sep, plan->d_gh_items};
   for (void* t : tables)
     if (t) (void)hipFree(t);
   delete plan;

@@ -33,6 +33,17 @@ struct lhf_plan_s {
   int64_t fused_wgs = 0;
   int32_t fused_bmax = 0;               // largest band over the fused lattices' dimensions
   int32_t fused_lds = 0;                // bytes of LDS per workgroup for complex128
+  // separable Fourier-block formation (every lattice, when each qualifies)
+  bool sep_ok = false;
+  lhf::FusedTask* d_sep = nullptr;      // one task per lattice
+  int32_t n_sep = 0;
+  int64_t sep_wgs = 0;
+  int32_t sep_bmax = 0;                 // largest first-dimension band
+  int32_t sep_lds = 0;                  // bytes of LDS per workgroup
+  lhf::GhItem* d_gh_items = nullptr;    // 1D transforms of the Grams along dimensions 2, 3
+  int32_t n_gh_items = 0;
+  int64_t gh_threads = 0;
+  int64_t gh_elems = 0;                 // complex elements of the transformed Grams
   int2* d_canon[4] = {nullptr, nullptr, nullptr, nullptr};  // (lattice, block) per size class M = 4, 8, 16, 32
   int32_t ncanon[4] = {0, 0, 0, 0};
   // eigensolver layout per class: one matrix entry per thread (wide) when the
@@ -44,6 +55,7 @@ struct lhf_plan_s {
   int32_t gram_grid = 4096;             // workgroups of the grouped Gram launch
   int32_t gram_split = 256;             // split-K target: workgroups per (lattice, dimension)
   int32_t tol32_scale = 1;              // mixed plans: FP32 Jacobi tolerance multiplier
+  int32_t fourier_sep = 1;              // whole steps form the Fourier blocks separably (when sep_ok)
   uint64_t signature = 0;               // plan_signature() at creation
   lhf_sizes sizes{};
   // element counts of the workspace sections
@@ -52,7 +64,7 @@ struct lhf_plan_s {
   int64_t dft_tmp_elems = 0;            // complex elements of the DFT intermediates
   // byte offsets of the workspace sections
   size_t ws_fac = 0, ws_grams64 = 0, ws_grams32 = 0, ws_part64 = 0, ws_part32 = 0;
-  size_t ws_dft = 0, ws_U = 0, ws_info = 0;
+  size_t ws_dft = 0, ws_U = 0, ws_info = 0, ws_gh = 0;
 };
 
 namespace lhf {
@@ -69,6 +81,7 @@ struct Ws {
   void* dft;
   float2* U;
   int32_t* info32;
+  double2* gh;
 };
 Ws ws_view(const lhf_plan_s* p, void* base);
 
@@ -95,6 +108,11 @@ void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std
 // b32_h, b32_s (FP64 transforms only, may be NULL): complex64 copies of the blocks
 hipError_t launch_block_dft(const lhf_plan_s* p, int prec, const void* gen_h, const void* gen_s,
                             void* bar_h, void* bar_s, void* tmp, float2* b32_h, float2* b32_s, hipStream_t s);
+// blockdft.hip: separable Fourier blocks from the FP64 Grams (complex128 out)
+void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tasks, std::vector<GhItem>& items,
+                    int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, bool& ok);
+hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* gh, double2* bar_h, double2* bar_s,
+                              hipStream_t s);
 // heev.hip: every canonical block of every lattice, one launch per size class
 int heev_class(int m0);
 hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, const void* Sbar,

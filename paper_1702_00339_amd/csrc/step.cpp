@@ -52,12 +52,23 @@ int32_t run_stages(lhf_plan_s* p, const lhf_step_args* a, hipStream_t s, int whi
   int32_t st = LHF_OK;
   const bool mixed = p->prec == LHF_PREC_MIXED;
   const bool refine = mixed && (a->heev_flags & LHF_HEEV_REFINE_FP64);
-  if (which & 1) {
+  const bool direct = refine && a->H_bar64 && !a->H_gen && !a->H_bar;
+  // separable formation of the complex128 blocks from the FP64 Grams (FP64
+  // plans, and mixed plans whose FP32 solve reads the complex128 blocks)
+  const bool sep = p->sep_ok && p->fourier_sep && (!mixed || direct);
+  if ((which & 1) && sep) {
+    st = lhf_assemble_blocks(p, nullptr, nullptr, a->grams64, nullptr, nullptr, a->ws, a->ws_bytes, s);
+    if (st != LHF_OK) return st;
+  } else if (which & 1) {
     st = lhf_assemble_blocks(p, a->H_gen, a->S_gen, a->grams64, mixed ? a->H_gen64 : nullptr,
                              mixed ? a->S_gen64 : nullptr, a->ws, a->ws_bytes, s);
     if (st != LHF_OK) return st;
   }
-  if ((which & 2) && refine && a->H_bar64 && !a->H_gen && !a->H_bar) {
+  if ((which & 2) && sep) {
+    st = lhf_fourier_blocks(p, a->grams64, mixed ? a->H_bar64 : a->H_bar, mixed ? a->S_bar64 : a->S_bar, a->ws,
+                            a->ws_bytes, s);
+    if (st != LHF_OK) return st;
+  } else if ((which & 2) && direct) {
     // the FP32 solve reads the complex128 blocks: one FP64 transform
     st = lhf_block_fft(p, LHF_PREC_FP64, a->H_gen64, a->S_gen64, a->H_bar64, a->S_bar64, a->ws, a->ws_bytes, s);
     if (st != LHF_OK) return st;
@@ -121,12 +132,13 @@ void get_tuning(const lhf_plan_s* p, lhf_tuning* t) {
   t->tol32_scale = p->tol32_scale;
   t->heev_wide = 0;
   for (int c = 0; c < 4; ++c) t->heev_wide |= p->heev_wide[c] ? 1 << c : 0;
+  t->fourier_sep = p->fourier_sep && p->sep_ok ? 1 : 0;
 }
 
 int32_t set_tuning(lhf_plan_s* p, const lhf_tuning* t) {
   if (t->dft_threads < 1024 || t->dft_threads > (1 << 24) || t->gram_split < 1 || t->gram_split > kGramSplitMax ||
       t->gram_grid < 1 || t->gram_grid > (1 << 20) || t->tol32_scale < 1 || t->tol32_scale > (1 << 16) ||
-      t->heev_wide < 0 || t->heev_wide > 15) {
+      t->heev_wide < 0 || t->heev_wide > 15 || t->fourier_sep < 0 || t->fourier_sep > 1) {
     set_error("tuning value out of range");
     return LHF_ERR_INVALID;
   }
@@ -136,6 +148,7 @@ int32_t set_tuning(lhf_plan_s* p, const lhf_tuning* t) {
   p->gram_grid = t->gram_grid;
   p->tol32_scale = t->tol32_scale;
   for (int c = 0; c < 4; ++c) p->heev_wide[c] = (t->heev_wide >> c) & 1;
+  p->fourier_sep = t->fourier_sep;
   return tables ? apply_tuning(p) : LHF_OK;
 }
 
@@ -190,6 +203,8 @@ bool parse_entry(const std::string& body, lhf_tuning& t) {
   field(body, "step_ms", e);
   double w = -1.0;
   t.heev_wide = field(body, "heev_wide", w) && w >= 0.0 ? (int32_t)w : t.heev_wide;
+  w = -1.0;
+  t.fourier_sep = field(body, "fourier_sep", w) && w >= 0.0 ? (int32_t)w : t.fourier_sep;
   t.dft_threads = (int32_t)a;
   t.gram_split = (int32_t)b;
   t.gram_grid = (int32_t)c;
@@ -203,8 +218,8 @@ void write_cache(const char* path, std::map<std::string, std::string> entries, c
   char buf[256];
   std::snprintf(buf, sizeof(buf),
                 "{\"dft_threads\": %d, \"gram_split\": %d, \"gram_grid\": %d, \"tol32_scale\": %d, "
-                "\"heev_wide\": %d, \"step_ms\": %.6f}",
-                t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.step_ms);
+                "\"heev_wide\": %d, \"fourier_sep\": %d, \"step_ms\": %.6f}",
+                t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.step_ms);
   entries[key] = buf;
   std::ofstream f(path, std::ios::trunc);
   f << "{\n";
@@ -336,6 +351,9 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
   st = timed(7, 1, step_ms);   // fills every buffer the later stages read
   if (st == LHF_OK) st = search(1, &lhf_tuning::gram_split, split_c, 3);
   if (st == LHF_OK) st = search(1, &lhf_tuning::gram_grid, grid_c, 4);
+  // Fourier blocks: separable formation or generator stacks and block DFT (assembly and transform timed together)
+  static const int32_t sep_c[] = {0, 1};
+  if (st == LHF_OK && p->sep_ok) st = search(3, &lhf_tuning::fourier_sep, sep_c, 2);
   if (st == LHF_OK) st = search(2, &lhf_tuning::dft_threads, dft_c, 5);
   // eigensolver layout, one size class at a time
   for (int c = 0; c < 4 && st == LHF_OK; ++c) {

@@ -49,7 +49,8 @@ class lhf_step_args(C.Structure):
 
 class lhf_tuning(C.Structure):
     _fields_ = [("dft_threads", C.c_int32), ("gram_split", C.c_int32), ("gram_grid", C.c_int32),
-                ("tol32_scale", C.c_int32), ("heev_wide", C.c_int32), ("step_ms", C.c_double),
+                ("tol32_scale", C.c_int32), ("heev_wide", C.c_int32), ("fourier_sep", C.c_int32),
+                ("step_ms", C.c_double),
                 ("from_cache", C.c_int32)]
 
     def as_dict(self):
@@ -96,6 +97,7 @@ def load(path: str = LIB_PATH):
         "lhf_assemble_blocks": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "lhf_block_fft": (i32, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),
         "lhf_block_fft_dual": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "lhf_fourier_blocks": (i32, [vp, vp, vp, vp, vp, sz, vp]),
         "lhf_heev_batched": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "lhf_step": (i32, [vp, C.POINTER(lhf_step_args), vp]),
         "lhf_graph_create": (i32, [vp, C.POINTER(lhf_step_args), C.POINTER(vp)]),
@@ -128,7 +130,7 @@ def load(path: str = LIB_PATH):
 def exported_symbols():
     """Names the binding expects the library to export."""
     return ["lhf_plan_create", "lhf_plan_sizes", "lhf_plan_band", "lhf_workspace_size", "lhf_plan_destroy",
-            "lhf_assemble_blocks", "lhf_block_fft", "lhf_block_fft_dual", "lhf_heev_batched", "lhf_step", "lhf_graph_create",
+            "lhf_assemble_blocks", "lhf_block_fft", "lhf_block_fft_dual", "lhf_fourier_blocks", "lhf_heev_batched", "lhf_step", "lhf_graph_create",
             "lhf_graph_launch", "lhf_graph_destroy", "lhf_plan_get_tuning", "lhf_plan_set_tuning",
             "lhf_plan_autotune", "lhf_toeplitz_create", "lhf_toeplitz_get_info", "lhf_toeplitz_blocks",
             "lhf_toeplitz_matvec_workspace", "lhf_toeplitz_matvec", "lhf_toeplitz_eigs_workspace",
@@ -238,6 +240,10 @@ class Plan:
     def lhf_block_fft_dual(self, H_gen64, S_gen64, H_bar64, S_bar64, H_bar32, S_bar32, ws):
         _check(load().lhf_block_fft_dual(self.handle, _ptr(H_gen64), _ptr(S_gen64), _ptr(H_bar64), _ptr(S_bar64),
                                          _ptr(H_bar32), _ptr(S_bar32), _ptr(ws), ws.numel(), _stream()))
+
+    def lhf_fourier_blocks(self, grams64, H_bar64, S_bar64, ws):
+        _check(load().lhf_fourier_blocks(self.handle, _ptr(grams64), _ptr(H_bar64), _ptr(S_bar64), _ptr(ws),
+                                         ws.numel(), _stream()))
 
     def lhf_heev_batched(self, flags, H_bar, S_bar, w, info, ws, V=None, H_bar64=None, S_bar64=None,
                          H_gen64=None, S_gen64=None):

@@ -24,10 +24,16 @@ class Pipeline:
       "bar64" FP32 stacks and a complex64 DFT for the FP32 solve, plus a
               separate complex128 DFT of the FP64 stacks;
       "band"  FP32 stacks and a complex64 DFT; refinement regenerates each
-              block from the FP64 generator band."""
+              block from the FP64 generator band.
+    ``fourier`` picks how the complex128 Fourier blocks of FP64 plans and of
+    the "direct" mixed path are made: "sep" separably from the FP64 Grams
+    (lhf_fourier_blocks; no generator stacks are written), "dft" generator
+    stacks and a block DFT, "auto" the plan's setting (separable where the
+    plan qualifies; the autotuner may change it).  The choice is the plan's
+    tuning field fourier_sep, which lhf_step follows as well."""
 
     def __init__(self, instances, prec=lhf.LHF_PREC_FP64, gram=lhf.LHF_GRAM_BF16X3, refine_src="auto",
-                 want_vectors=False, device="cuda", L0=None):
+                 want_vectors=False, device="cuda", L0=None, fourier="auto"):
         if not isinstance(instances, (list, tuple)):
             instances = [instances]
         self.plan = lhf.Plan(instances, prec=prec, gram=gram if prec == lhf.LHF_PREC_MIXED else lhf.LHF_GRAM_FP64,
@@ -65,6 +71,19 @@ class Pipeline:
                 self.S_bar64 = torch.empty(G, dtype=torch.complex128, device=dev)
         else:
             self.refine_src = None
+        assert fourier in ("auto", "sep", "dft")
+        if fourier != "auto":
+            t = self.plan.lhf_plan_get_tuning()
+            t.fourier_sep = 1 if fourier == "sep" else 0
+            self.plan.lhf_plan_set_tuning(t)
+            if fourier == "sep" and self.plan.lhf_plan_get_tuning().fourier_sep != 1:
+                raise ValueError("this plan does not qualify for the separable Fourier blocks")
+
+    def separable(self):
+        """Whether a step forms the complex128 blocks separably (as lhf_step does)."""
+        if self.prec == lhf.LHF_PREC_MIXED and self.refine_src != "direct":
+            return False
+        return self.plan.lhf_plan_get_tuning().fourier_sep == 1
 
     def step_args(self):
         """The lhf_step_args of this pipeline's buffers (kept alive by self)."""
@@ -96,13 +115,21 @@ class Pipeline:
 
     def step(self):
         p = self.plan
+        sep = self.separable()
         if self.prec == lhf.LHF_PREC_FP64:
-            p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws)
-            p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen, self.S_gen, self.H_bar, self.S_bar, self.ws)
+            if sep:
+                p.lhf_assemble_blocks(None, None, self.grams64, self.ws)
+                p.lhf_fourier_blocks(self.grams64, self.H_bar, self.S_bar, self.ws)
+            else:
+                p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws)
+                p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen, self.S_gen, self.H_bar, self.S_bar, self.ws)
             flags = lhf.LHF_HEEV_VECTORS if self.want_vectors else 0
             p.lhf_heev_batched(flags, self.H_bar, self.S_bar, self.w, self.info, self.ws, V=self.V)
             return
-        if self.refine_src == "direct":
+        if self.refine_src == "direct" and sep:
+            p.lhf_assemble_blocks(None, None, self.grams64, self.ws)
+            p.lhf_fourier_blocks(self.grams64, self.H_bar64, self.S_bar64, self.ws)
+        elif self.refine_src == "direct":
             p.lhf_assemble_blocks(None, None, self.grams64, self.ws, H_gen64=self.H_gen64, S_gen64=self.S_gen64)
             p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.ws)
         elif self.refine_src == "dual":

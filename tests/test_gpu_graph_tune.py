@@ -68,9 +68,10 @@ def _poison(pipe):
 PRECS = [(lhf.LHF_PREC_FP64, False), (lhf.LHF_PREC_MIXED, False), (lhf.LHF_PREC_MIXED, True)]
 
 
+@pytest.mark.parametrize("fourier", ["dft", "sep"])
 @pytest.mark.parametrize("prec,vec", PRECS, ids=["fp64", "mixed", "mixed_vectors"])
-def test_native_step_matches_stage_calls(prec, vec):
-    pipe = Pipeline(_mix(), prec=prec, want_vectors=vec)
+def test_native_step_matches_stage_calls(prec, vec, fourier):
+    pipe = Pipeline(_mix(), prec=prec, want_vectors=vec, fourier=fourier)
     pipe.step()
     torch.cuda.synchronize()
     ref = _outputs(pipe)
@@ -81,9 +82,10 @@ def test_native_step_matches_stage_calls(prec, vec):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("fourier", ["dft", "sep"])
 @pytest.mark.parametrize("prec,vec", PRECS, ids=["fp64", "mixed", "mixed_vectors"])
-def test_graph_replays_match_eager(prec, vec):
-    pipe = Pipeline(_mix(), prec=prec, want_vectors=vec)
+def test_graph_replays_match_eager(prec, vec, fourier):
+    pipe = Pipeline(_mix(), prec=prec, want_vectors=vec, fourier=fourier)
     pipe.step_native()
     torch.cuda.synchronize()
     ref = _outputs(pipe)
@@ -113,9 +115,9 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     assert t.gram_split in (64, 128, 256) and t.gram_grid in (1024, 2048, 4096, 8192)
     assert t.dft_threads in (32768, 65536, 131072, 262144, 524288) and t.tol32_scale in (1, 16, 256, 4096)
     got = pipe.plan.lhf_plan_get_tuning()
-    assert (got.dft_threads, got.gram_split, got.gram_grid, got.tol32_scale, got.heev_wide) == \
-        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide)
-    assert 0 <= t.heev_wide <= 15
+    assert (got.dft_threads, got.gram_split, got.gram_grid, got.tol32_scale, got.heev_wide, got.fourier_sep) == \
+        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep)
+    assert 0 <= t.heev_wide <= 15 and t.fourier_sep in (0, 1)
     entries = json.load(open(cache))
     assert len(entries) == 1
     pipe.step_native()
@@ -128,8 +130,8 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     again = Pipeline(insts, prec=lhf.LHF_PREC_MIXED)
     t2 = again.autotune(cache)
     assert t2.from_cache == 1
-    assert (t2.dft_threads, t2.gram_split, t2.gram_grid, t2.tol32_scale, t2.heev_wide) == \
-        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide)
+    assert (t2.dft_threads, t2.gram_split, t2.gram_grid, t2.tol32_scale, t2.heev_wide, t2.fourier_sep) == \
+        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep)
     # a different plan adds its own entry
     Pipeline(insts[:2], prec=lhf.LHF_PREC_FP64).autotune(cache)
     assert len(json.load(open(cache))) == 2
@@ -139,10 +141,10 @@ def test_set_tuning_extremes_keep_parity():
     """The smallest and largest launch shapes still give the oracle's eigenvalues."""
     insts = _mix()
     refs = [np.sort(separable.solve(i)["eig"], axis=-1) for i in insts]
-    for dft, split, grid, wide in ((32768, 1, 1, 0), (1 << 24, 256, 1 << 20, 15)):
+    for dft, split, grid, wide, sep in ((32768, 1, 1, 0, 0), (1 << 24, 256, 1 << 20, 15, 1)):
         pipe = Pipeline(insts, prec=lhf.LHF_PREC_FP64)
         t = pipe.plan.lhf_plan_get_tuning()
-        t.dft_threads, t.gram_split, t.gram_grid, t.heev_wide = dft, split, grid, wide
+        t.dft_threads, t.gram_split, t.gram_grid, t.heev_wide, t.fourier_sep = dft, split, grid, wide, sep
         pipe.plan.lhf_plan_set_tuning(t)
         pipe.step_native()
         torch.cuda.synchronize()
@@ -154,5 +156,9 @@ def test_set_tuning_extremes_keep_parity():
         pipe.plan.lhf_plan_set_tuning(bad)
     bad = pipe.plan.lhf_plan_get_tuning()
     bad.heev_wide = 16
+    with pytest.raises(lhf.LhfError):
+        pipe.plan.lhf_plan_set_tuning(bad)
+    bad = pipe.plan.lhf_plan_get_tuning()
+    bad.fourier_sep = 2
     with pytest.raises(lhf.LhfError):
         pipe.plan.lhf_plan_set_tuning(bad)

@@ -63,17 +63,20 @@ def _ids(c):
 
 
 @pytest.mark.parametrize("case", TINY, ids=_ids)
-def test_fp64_pipeline_matches_oracle(case):
+@pytest.mark.parametrize("fourier", ["dft", "sep"])
+def test_fp64_pipeline_matches_oracle(case, fourier):
     inst = tiny_instance(**{"R": 8, **case})
-    print(inst.summary(), flush=True)
+    print(inst.summary(), fourier, flush=True)
     res, ref = _eig_ref(inst)
-    pipe = _run(inst, lhf.LHF_PREC_FP64)
+    pipe = _run(inst, lhf.LHF_PREC_FP64, fourier=fourier)
+    assert pipe.separable() == (fourier == "sep")
     info = pipe.info.cpu().numpy()
     assert (info == 0).all(), info
-    # generator stacks and Fourier blocks
-    Hg, Sg = pipe.stacks("H_gen")[0], pipe.stacks("S_gen")[0]
-    assert np.abs(Hg - res["H_gen"]).max() <= 1e-12 * np.abs(res["H_gen"]).max()
-    assert np.abs(Sg - res["S_gen"]).max() <= 1e-12 * np.abs(res["S_gen"]).max()
+    # generator stacks (block DFT route) and Fourier blocks
+    if fourier == "dft":
+        Hg, Sg = pipe.stacks("H_gen")[0], pipe.stacks("S_gen")[0]
+        assert np.abs(Hg - res["H_gen"]).max() <= 1e-12 * np.abs(res["H_gen"]).max()
+        assert np.abs(Sg - res["S_gen"]).max() <= 1e-12 * np.abs(res["S_gen"]).max()
     Hb, Sb = pipe.stacks("H_bar")[0], pipe.stacks("S_bar")[0]
     assert np.abs(Hb - res["H_bar"]).max() <= 1e-12 * np.abs(res["H_bar"]).max()
     assert np.abs(Sb - res["S_bar"]).max() <= 1e-12 * np.abs(res["S_bar"]).max()
@@ -88,8 +91,8 @@ def test_mixed_pipeline_matches_oracle(case, gram):
     inst = tiny_instance(**{"R": 8, **case})
     print(inst.summary(), "gram", gram, flush=True)
     res, ref = _eig_ref(inst)
-    for src in ("band", "bar64", "dual", "direct"):
-        pipe = _run(inst, lhf.LHF_PREC_MIXED, gram=gram, refine_src=src)
+    for src, fourier in (("band", "auto"), ("bar64", "auto"), ("dual", "auto"), ("direct", "dft"), ("direct", "sep")):
+        pipe = _run(inst, lhf.LHF_PREC_MIXED, gram=gram, refine_src=src, fourier=fourier)
         info = pipe.info.cpu().numpy()
         assert (info == 0).all(), (src, info)
         got = pipe.eigenvalues()[0]
@@ -170,6 +173,33 @@ def test_grouped_plan_mixes_every_class():
             _, ref = _eig_ref(inst)
             tol = tol_abs if tol_abs else 1e-10 * np.maximum(np.abs(ref), 1.0)
             assert (np.abs(got - ref) <= tol).all(), inst.name
+
+
+def test_separable_blocks_match_block_dft():
+    """lhf_fourier_blocks (separable formation from the Grams, Theorem 3.3)
+    against the block DFT of the FP64 generator stacks, on one plan holding
+    every TINY shape (chains, 2D, 3D, one cell, full and banded axes, odd and
+    even lengths, m0 from 1 to 32); a plan with a 35-slot band is refused."""
+    insts = [tiny_instance(**{"R": 8, **c}) for c in TINY]
+    pipe = Pipeline(insts, prec=lhf.LHF_PREC_FP64, fourier="dft")
+    pipe.step()
+    Hd, Sd = pipe.H_bar.clone(), pipe.S_bar.clone()
+    pipe.H_bar.zero_()
+    pipe.S_bar.zero_()
+    pipe.plan.lhf_fourier_blocks(pipe.grams64, pipe.H_bar, pipe.S_bar, pipe.ws)
+    torch.cuda.synchronize()
+    for a, b in ((pipe.H_bar, Hd), (pipe.S_bar, Sd)):
+        off = 0
+        for inst in insts:
+            n = inst.ncells * inst.m0 * inst.m0
+            x, y = a[off:off + n], b[off:off + n]
+            assert (x - y).abs().max().item() <= 1e-13 * y.abs().max().item(), inst.name
+            off += n
+    wide = Pipeline(tiny_instance(L=(40, 1, 1), n=(320, 12, 12), n_s=1, seed=151, exp_range=(0.3, 0.6)),
+                    prec=lhf.LHF_PREC_FP64, L0=(17, 17, 17))
+    assert not wide.separable()
+    with pytest.raises(lhf.LhfError):
+        wide.plan.lhf_fourier_blocks(wide.grams64, wide.H_bar, wide.S_bar, wide.ws)
 
 
 @pytest.mark.parametrize("wide", [15, 0], ids=["wide", "four"])
