@@ -39,12 +39,13 @@ WORKLOADS = {
 C4_CHECK = (28, 41, 52, 2)
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per call (FETCH_SIZE + WRITE_SIZE, KiB, scaled by a plain 512 MiB copy) of the mixed path's
-# eigensolve call (FP32 Jacobi + FP64 refinement kernels) and block DFT, from two rocprofv3 --pmc runs of
+# eigensolve call (FP32 Jacobi + FP64 refinement kernels), block DFT and separable Fourier-block formation,
+# from two rocprofv3 --pmc runs of
 # `bench.py --probe-traffic` (profiles/traffic_per_dispatch.md).  Valid for the kernels as they were when
 # counted; absent (reported as null) where not counted.
 TRAFFIC_KIB = {"c2": {"eig": 1671.7, "dft": 2357.6},
-               "c3": {"eig": 51024.1, "dft": 66783.3},
-               "c4": {"eig": 843254.8, "dft": 1204188.1}}
+               "c3": {"eig": 51023.2, "dft": 66783.3, "sep": 69268.2},
+               "c4": {"eig": 843233.0, "dft": 1204188.1, "sep": 1344483.6}}
 
 
 def parse():
