@@ -351,9 +351,10 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
   st = timed(7, 1, step_ms);   // fills every buffer the later stages read
   if (st == LHF_OK) st = search(1, &lhf_tuning::gram_split, split_c, 3);
   if (st == LHF_OK) st = search(1, &lhf_tuning::gram_grid, grid_c, 4);
-  // Fourier blocks: separable formation or generator stacks and block DFT (assembly and transform timed together)
+  // Fourier blocks: separable formation or generator stacks and block DFT, timed over whole steps (the
+  // route also changes where the blocks sit when the eigensolver reads them)
   static const int32_t sep_c[] = {0, 1};
-  if (st == LHF_OK && p->sep_ok) st = search(3, &lhf_tuning::fourier_sep, sep_c, 2);
+  if (st == LHF_OK && p->sep_ok) st = search(7, &lhf_tuning::fourier_sep, sep_c, 2);
   if (st == LHF_OK) st = search(2, &lhf_tuning::dft_threads, dft_c, 5);
   // eigensolver layout, one size class at a time
   for (int c = 0; c < 4 && st == LHF_OK; ++c) {
