@@ -343,13 +343,13 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
     int32_t r = hip_status(hipStreamSynchronize(s), "synchronize");
     return r == LHF_OK ? set_tuning(p, &best) : r;
   };
-  static const int32_t split_c[] = {64, 128, 256};
+  static const int32_t split_c[] = {16, 32, 64, 128, 256};
   static const int32_t grid_c[] = {1024, 2048, 4096, 8192};
   static const int32_t dft_c[] = {32768, 65536, 131072, 262144, 524288};
   static const int32_t tol_c[] = {1, 16, 256, 4096};
   double step_ms = 0.0;
   st = timed(7, 1, step_ms);   // fills every buffer the later stages read
-  if (st == LHF_OK) st = search(1, &lhf_tuning::gram_split, split_c, 3);
+  if (st == LHF_OK) st = search(1, &lhf_tuning::gram_split, split_c, 5);
   if (st == LHF_OK) st = search(1, &lhf_tuning::gram_grid, grid_c, 4);
   // Fourier blocks: separable formation or generator stacks and block DFT, timed over whole steps (the
   // route also changes where the blocks sit when the eigensolver reads them)

@@ -112,7 +112,7 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     pipe = Pipeline(insts, prec=lhf.LHF_PREC_MIXED)
     t = pipe.autotune(cache)
     assert t.from_cache == 0 and t.step_ms > 0
-    assert t.gram_split in (64, 128, 256) and t.gram_grid in (1024, 2048, 4096, 8192)
+    assert t.gram_split in (16, 32, 64, 128, 256) and t.gram_grid in (1024, 2048, 4096, 8192)
     assert t.dft_threads in (32768, 65536, 131072, 262144, 524288) and t.tol32_scale in (1, 16, 256, 4096)
     got = pipe.plan.lhf_plan_get_tuning()
     assert (got.dft_threads, got.gram_split, got.gram_grid, got.tol32_scale, got.heev_wide, got.fourier_sep) == \
