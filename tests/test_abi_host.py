@@ -38,7 +38,7 @@ def _declared_functions():
 
 def test_header_declares_the_hot_path():
     names = _declared_functions()
-    for required in ("lhf_assemble_blocks", "lhf_block_fft", "lhf_heev_batched",
+    for required in ("lhf_assemble_blocks", "lhf_block_fft", "lhf_fourier_blocks", "lhf_heev_batched",
                      "lhf_workspace_size", "lhf_plan_create", "lhf_status_string", "lhf_last_error"):
         assert required in names, required
 
@@ -108,6 +108,7 @@ def test_bad_precision_and_null_output(lib):
 def test_hot_calls_reject_null_plan(lib):
     assert lib.lhf_assemble_blocks(None, None, None, None, None, None, None, 0, None) == lhf.LHF_ERR_INVALID
     assert lib.lhf_block_fft(None, 0, None, None, None, None, None, 0, None) == lhf.LHF_ERR_INVALID
+    assert lib.lhf_fourier_blocks(None, None, None, None, None, 0, None) == lhf.LHF_ERR_INVALID
     assert lib.lhf_heev_batched(None, 0, None, None, None, None, None, None, None, None, None, None, 0,
                                 None) == lhf.LHF_ERR_INVALID
 
