@@ -228,6 +228,30 @@ def test_dense_equals_separable_generators(case):
             assert np.abs(dense3d.block(S, m0, bk, bm) - Sg[d]).max() < 1e-13 * scale_s
 
 
+@pytest.mark.parametrize("case", CASES + [dict(L=(6, 4, 3), n=(48, 32, 24), n_s=2, n_p=1, seed=45)],
+                         ids=lambda c: "L" + "x".join(map(str, c["L"])))
+def test_fourier_blocks_from_transformed_grams(case):
+    """Theorem 3.3 / Remark 3.5: the Fourier blocks are the same Hadamard
+    combination of the per-dimension 1D DFTs of the Grams,
+      Sbar_j = S^1 o S^2 o S^3,  Hbar_j = 1/2 (K^1 S^2 S^3 + S^1 K^2 S^3 + S^1 S^2 K^3) - sum_t c_t M^1_t M^2_t M^3_t,
+    as the 3D DFT of the generator stacks (a lost kinetic term, a transposed
+    factor or a wrong sign fails)."""
+    inst = tiny_instance(R=5, **case)
+    grams = [separable.gram_1d(inst, ell) for ell in range(3)]
+    Hg, Sg = separable.generator_stacks(inst, grams)
+    Hb, Sb = separable.fourier_blocks(Hg), separable.fourier_blocks(Sg)
+    c = separable.term_coefficients(inst)
+    hat = [{k: np.fft.fft(g[k], axis=-3) for k in ("S", "K", "M")} for g in grams]
+    S1, S2, S3 = (h["S"] for h in hat)
+    K1, K2, K3 = (h["K"] for h in hat)
+    Sb_sep = np.einsum("aij,bij,cij->abcij", S1, S2, S3)
+    Hb_sep = 0.5 * (np.einsum("aij,bij,cij->abcij", K1, S2, S3) + np.einsum("aij,bij,cij->abcij", S1, K2, S3)
+                    + np.einsum("aij,bij,cij->abcij", S1, S2, K3))
+    Hb_sep -= np.einsum("t,taij,tbij,tcij->abcij", c, hat[0]["M"], hat[1]["M"], hat[2]["M"])
+    assert np.abs(Sb_sep - Sb).max() <= 1e-13 * np.abs(Sb).max()
+    assert np.abs(Hb_sep - Hb).max() <= 1e-13 * np.abs(Hb).max()
+
+
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "L" + "x".join(map(str, c["L"])))
 def test_explicit_fourier_matrices_block_diagonalise(case):
     """(F_L x I) A (F_L^* x I) = bdiag(Abar_j), F_L = F_L1 x F_L2 x F_L3 unitary
