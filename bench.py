@@ -225,8 +225,8 @@ def probe_mfma(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is a design in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is designed but not built)"}))
         sys.exit(2)
     import numpy as np
     import torch

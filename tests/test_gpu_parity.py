@@ -1,6 +1,7 @@
 """GPU parity of the periodic hot path against the CPU oracle (through the C ABI).
 
-Tolerances (derived in the design doc from the arithmetic):
+Tolerances (from the arithmetic: FP64 rounding of O(1) terms, the FP32
+solve's error removed by the FP64 refinement):
   * FP64 pipeline: eigenvalues within 1e-10 max(|lambda|, 1 Ha) of the oracle;
     Grams / generator stacks / Fourier blocks within 1e-12 of the largest
     entry of their kind (the GPU band drops generators below 1e-22 relative).
