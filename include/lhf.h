@@ -49,7 +49,7 @@ typedef struct lhf_toeplitz_s* lhf_toeplitz_t;
 enum {
   LHF_OK = 0,
   LHF_ERR_INVALID = -1,      /* an argument or descriptor is invalid          */
-  LHF_ERR_UNSUPPORTED = -2,  /* valid input outside what this build supports  */
+  LHF_ERR_UNSUPPORTED = -2,  /* valid input outside what the library supports */
   LHF_ERR_WORKSPACE = -3,    /* workspace missing or smaller than required    */
   LHF_ERR_HIP = -4,          /* a HIP runtime call failed                     */
   LHF_ERR_ALLOC = -5         /* plan creation could not allocate              */
