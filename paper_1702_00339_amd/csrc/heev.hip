@@ -284,6 +284,58 @@ __device__ __forceinline__ void mm_tile_lh_diag(const C (&X)[M][M + 1], const R 
   }
 }
 
+// Complex M x M products on the FP64 matrix cores (v_mfma_f64_16x16x4f64)
+// for one matrix per workgroup (M >= 16): wavefront w < (M/16)^2 owns the
+// 16 x 16 output tile (w / (M/16), w % (M/16)), the others idle.  In each
+// 4-wide k step lane (lr, lk) = (lane % 16, lane / 16) supplies A[row lr][k lk]
+// and B[k lk][col lr]; it holds output rows lk + 4 v of column lr.  The real
+// and imaginary parts take four real products per step.
+typedef double mf4 __attribute__((ext_vector_type(4)));
+
+template <int M>
+struct MfTile {
+  static constexpr int NTL = M / 16;
+  int r0 = 0, c0 = 0, lr = 0, lk = 0;
+  bool on = false;
+  __device__ __forceinline__ MfTile() {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    on = wave < NTL * NTL;
+    r0 = on ? 16 * (wave / NTL) : 0;
+    c0 = on ? 16 * (wave % NTL) : 0;
+    lr = lane & 15;
+    lk = lane >> 4;
+  }
+};
+
+// (re, im) = op(X) Y with op(X) = X, or X^H when XH
+template <int M, bool XH>
+__device__ __forceinline__ void mf_product(const MfTile<M>& f, const double2 (&X)[M][M + 1],
+                                           const double2 (&Y)[M][M + 1], mf4& re, mf4& im) {
+  re = mf4{0.0, 0.0, 0.0, 0.0};
+  im = mf4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < M; k0 += 4) {
+    const double2 x = XH ? X[k0 + f.lk][f.r0 + f.lr] : X[f.r0 + f.lr][k0 + f.lk];
+    const double xi = XH ? -x.y : x.y;
+    const double2 y = Y[k0 + f.lk][f.c0 + f.lr];
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-xi, y.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(xi, y.x, im, 0, 0, 0);
+  }
+}
+
+// the tile into Z, plus d on the diagonal
+template <int M>
+__device__ __forceinline__ void mf_store(const MfTile<M>& f, double2 (&Z)[M][M + 1], const mf4& re, const mf4& im,
+                                         double d) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = f.r0 + f.lk + 4 * v, c = f.c0 + f.lr;
+    Z[r][c] = make_double2(re[v] + (r == c ? d : 0.0), im[v]);
+  }
+}
+
 // 1-2. Reduction to standard form.  Gaussian elimination without pivoting on
 // the overlap B (Hermitian positive definite: the pivots are those of its
 // L D L^H factorisation), applying the same row operations to W = I, leaves
@@ -837,7 +889,32 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
   // after the Rayleigh-Ritz products
   constexpr bool HASF = Smem<R, M, G, true, WANTV>::HASF;
   auto& Xm = xbuf(sh, g);
-  {
+  // products on the matrix cores for one matrix per workgroup of size >= 16
+  constexpr bool kMf = M >= 16 && G == 1;
+  const MfTile<M> mft;
+  if constexpr (kMf) {
+    mf4 ar, ai, br, bi;
+    if (mft.on) {
+      mf_product<M, false>(mft, sh.A[g], sh.U[g], ar, ai);
+      mf_product<M, false>(mft, sh.B[g], sh.U[g], br, bi);
+    }
+    __syncthreads();
+    if (mft.on) {
+      mf_store<M>(mft, sh.A[g], ar, ai, 0.0);
+      mf_store<M>(mft, sh.B[g], br, bi, 0.0);
+    }
+    __syncthreads();
+    if (mft.on) {
+      mf_product<M, true>(mft, sh.U[g], sh.A[g], ar, ai);
+      mf_product<M, true>(mft, sh.U[g], sh.B[g], br, bi);
+    }
+    __syncthreads();
+    if (mft.on) {
+      mf_store<M>(mft, sh.A[g], ar, ai, 0.0);
+      mf_store<M>(mft, sh.B[g], br, bi, 0.0);
+    }
+    __syncthreads();
+  } else {
     C p1[NT][NT], p2[NT][NT];
     mm_shared_right<M, NT>(sh.A[g], sh.B[g], sh.U[g], ti, tj, p1, p2);
     __syncthreads();
@@ -872,8 +949,23 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
     series = series && sh.flag[gg][3] != 0;
     deg = max(deg, sh.flag[gg][3]);
   }
+  // Z <- X Y + d I (X, Y, Z in LDS); when Z aliases X or Y (alias) every read
+  // of the product precedes a barrier before the store
+  auto prod_store = [&](const C (&X)[M][M + 1], const C (&Y)[M][M + 1], C (&Z)[M][M + 1], R d, bool alias) {
+    if constexpr (kMf) {
+      mf4 re, im;
+      if (mft.on) mf_product<M, false>(mft, X, Y, re, im);
+      if (alias) __syncthreads();
+      if (mft.on) mf_store<M>(mft, Z, re, im, d);
+    } else {
+      C q[NT][NT];
+      if (d != R(0)) mm_tile<M, NT, true>(X, Y, ti, tj, d, q); else mm_tile<M, NT, false>(X, Y, ti, tj, R(0), q);
+      if (alias) __syncthreads();
+      store_tile<M, NT>(Z, ti, tj, q);
+    }
+    __syncthreads();
+  };
   if (series) {
-    C p[NT][NT];
     // coefficients of (1 + E)^-1/2 = sum_k cf(k) E^k
     auto cf = [](int k) -> R {
       return k == 0 ? R(1.0) : k == 1 ? R(-0.5) : k == 2 ? R(0.375) : k == 3 ? R(-0.3125)
@@ -890,21 +982,12 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
     }
     __syncthreads();
 #pragma unroll 1
-    for (int h = deg - 2; h >= 0; --h) {
-      mm_tile<M, NT, true>(sh.B[g], Xm, ti, tj, cf(h), p);
-      __syncthreads();
-      store_tile<M, NT>(Xm, ti, tj, p);
-      __syncthreads();
-    }
+    for (int h = deg - 2; h >= 0; --h) prod_store(sh.B[g], Xm, Xm, cf(h), true);
     if constexpr (WANTV) {
       // T <- A X into V, then B <- X T (E is dead), then A <- the Hermitian
       // part of B and V <- I
-      mm_tile<M, NT, false>(sh.A[g], Xm, ti, tj, R(0), p);
-      store_tile<M, NT>(sh.V[g], ti, tj, p);
-      __syncthreads();
-      mm_tile<M, NT, false>(Xm, sh.V[g], ti, tj, R(0), p);
-      store_tile<M, NT>(sh.B[g], ti, tj, p);
-      __syncthreads();
+      prod_store(sh.A[g], Xm, sh.V[g], R(0), false);
+      prod_store(Xm, sh.V[g], sh.B[g], R(0), false);
       LHF_FOR_ENTRIES {
         const C x = sh.B[g][r][c], y = sh.B[g][c][r];
         C s2 = cmk<C>(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
@@ -916,12 +999,8 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
     } else if constexpr (HASF) {
       // T <- A X into the dead U, then B <- X T (E is dead), then A <- the
       // Hermitian part of B
-      mm_tile<M, NT, false>(sh.A[g], Xm, ti, tj, R(0), p);
-      store_tile<M, NT>(sh.U[g], ti, tj, p);
-      __syncthreads();
-      mm_tile<M, NT, false>(Xm, sh.U[g], ti, tj, R(0), p);
-      store_tile<M, NT>(sh.B[g], ti, tj, p);
-      __syncthreads();
+      prod_store(sh.A[g], Xm, sh.U[g], R(0), false);
+      prod_store(Xm, sh.U[g], sh.B[g], R(0), false);
       LHF_FOR_ENTRIES {
         const C x = sh.B[g][r][c], y = sh.B[g][c][r];
         sh.A[g][r][c] = cmk<C>(0.5 * (x.x + y.x), r == c ? 0.0 : 0.5 * (x.y - y.y));
@@ -930,12 +1009,8 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) __attribute__((amdgpu_
     } else {
       // X is in U: T <- A X into B (E is dead), A <- X T, then A <- its
       // Hermitian part
-      mm_tile<M, NT, false>(sh.A[g], Xm, ti, tj, R(0), p);
-      store_tile<M, NT>(sh.B[g], ti, tj, p);
-      __syncthreads();
-      mm_tile<M, NT, false>(Xm, sh.B[g], ti, tj, R(0), p);
-      store_tile<M, NT>(sh.A[g], ti, tj, p);
-      __syncthreads();
+      prod_store(sh.A[g], Xm, sh.B[g], R(0), false);
+      prod_store(Xm, sh.B[g], sh.A[g], R(0), false);
       C hs[W];
       LHF_FOR_ENTRIES {
         const C x = sh.A[g][r][c], y = sh.A[g][c][r];
