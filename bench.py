@@ -137,19 +137,33 @@ def canonical_blocks(L):
     return (n + self_conj) // 2
 
 
-def heev_flops(insts, prec, R):
+def heev_class(m0):
+    """Eigensolver size class of a basis size: M = 4, 8, 16, 32 -> 0..3."""
+    return 0 if m0 <= 4 else 1 if m0 <= 8 else 2 if m0 <= 16 else 3
+
+
+def heev_flops(insts, prec, R, fp64_mask=0):
     """Algorithmic flops of one lhf_heev_batched call: per distinct block
     150 m0^3 (Cholesky reduction and 6-10 Jacobi sweeps), plus on the mixed
-    path the FP64 refinement, (R + 4) m0^2 8 + 36 m0^3."""
+    path the FP64 refinement, (R + 4) m0^2 8 + 36 m0^3, except for the size
+    classes a mixed plan solves by FP64 Jacobi alone (bits of fp64_mask)."""
     from paper_1702_00339_amd import lhf
     total = 0.0
     for inst in insts:
         m = inst.m0
         per = 150.0 * m ** 3
-        if prec == lhf.LHF_PREC_MIXED:
+        if prec == lhf.LHF_PREC_MIXED and not (fp64_mask >> heev_class(m)) & 1:
             per += (R + 4) * m * m * 8 + 36.0 * m ** 3
         total += canonical_blocks(inst.L) * per
     return total
+
+
+def fp64_classes(m0s, mask):
+    """Path text for the size classes the tuned mixed plan solves by FP64 Jacobi alone."""
+    sizes = sorted({4 << heev_class(m) for m in m0s if (mask >> heev_class(m)) & 1})
+    if not sizes:
+        return ""
+    return " (blocks of size class M = " + ", ".join(str(x) for x in sizes) + ": FP64 Jacobi alone)"
 
 
 def bench_c5(torch, np, lhf, steps):
@@ -305,7 +319,8 @@ def main():
                                                          H_gen64=pm.H_gen64, S_gen64=pm.S_gen64),
                        args.steps, torch)
     R = insts[0].R
-    flops = heev_flops(insts, pm.prec, R)
+    fp64_mask = pm.plan.lhf_plan_get_tuning().heev_fp64
+    flops = heev_flops(insts, pm.prec, R, fp64_mask)
     tflops = flops / (ms_heev * 1e-3) / 1e12
 
     c5 = None if args.no_c5 else bench_c5(torch, np, lhf, args.steps)
@@ -346,15 +361,16 @@ def main():
                    "path": ("mixed: FP64 MFMA Grams, " +
                             ("Fourier blocks formed separably from the Grams (complex128, no generator stacks)"
                              if sep else "FP64 stacks, one block DFT writing complex128 blocks") +
-                            ", FP32 Jacobi on their roundings, FP64 Rayleigh-Ritz refinement on complex128; "
-                            "one hipGraph replay per step")},
+                            ", FP32 Jacobi on their roundings, FP64 Rayleigh-Ritz refinement on complex128" +
+                            fp64_classes(m0s, fp64_mask) + "; one hipGraph replay per step")},
         "fp64_path": {"value": nblk / sec["fp64"], "ms_per_step": sec["fp64"] * 1e3, "dtype": "f64"},
         "mixed_bf16x3_path": {"value": nblk / sec["mixed_bf16x3"], "ms_per_step": sec["mixed_bf16x3"] * 1e3,
                               "max_abs_eig_err_ha": errs["mixed_bf16x3"][0], "info_ok": errs["mixed_bf16x3"][2]},
         "accuracy": {"lattices_checked": len(checked),
                      "mixed_max_abs_eig_err_ha": errs["mixed"][0], "mixed_info_ok": errs["mixed"][2],
                      "fp64_max_rel_eig_err": errs["fp64"][1], "fp64_info_ok": errs["fp64"][2]},
-        "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: FP32 Jacobi + FP64 refinement)",
+        "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: FP32 Jacobi + FP64 refinement" +
+                     fp64_classes(m0s, fp64_mask) + ")",
                      "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s", "frac": tflops / 157.3,
                      "traffic": traffic("eig"), "flops_per_launch": flops, "avg_launch_ms": ms_heev},
         "roofline_dft": {"bound": "hbm",

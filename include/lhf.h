@@ -406,9 +406,17 @@ int32_t lhf_graph_destroy(lhf_graph_t graph);
  *                (lhf_fourier_blocks) instead of generator stacks and a block
  *                DFT, on FP64 plans and on mixed plans whose FP32 solve reads
  *                the complex128 blocks; the generator stacks are then not
- *                written.  Reads 0 when the plan does not qualify.
- * None of them changes what is computed; the Gram split changes the order of
- * the FP64 partial sums and the eigensolver layout the order of its sums. */
+ *                written.  Reads 0 when the plan does not qualify;
+ *   heev_fp64    mixed plans, bit c (size class M = 4 << c): a refined solve
+ *                that is given the complex128 blocks solves that class by the
+ *                FP64 Jacobi of FP64 plans alone, with no FP32 solve and no
+ *                refinement (for small blocks, where the cost of a rotation
+ *                does not depend on its precision); 0..15, default 0, reads 0
+ *                on FP64 plans.  The eigenvalues of such a class meet the FP64
+ *                tolerance, which is tighter than the refined one.
+ * Apart from heev_fp64, none of them changes what is computed; the Gram split
+ * changes the order of the FP64 partial sums and the eigensolver layout the
+ * order of its sums. */
 typedef struct {
   int32_t dft_threads;
   int32_t gram_split;
@@ -416,6 +424,7 @@ typedef struct {
   int32_t tol32_scale;
   int32_t heev_wide;
   int32_t fourier_sep;
+  int32_t heev_fp64;
   double step_ms;        /* autotune: mean time of one step with these settings */
   int32_t from_cache;    /* autotune: 1 when read from the cache file         */
 } lhf_tuning;

@@ -1157,7 +1157,18 @@ hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, co
     if (e == hipSuccess) e = launch_heev_m<double, 32>(p, vm, Hbar, Sbar, w, V, info, 30, 128 * eps, s);
     return e;
   }
-  // mixed: FP32 solve, then FP64 refinement
+  // mixed: FP32 solve, then FP64 refinement; with complex128 blocks, the
+  // classes the plan marks are solved by FP64 Jacobi alone instead
+  const bool f64[4] = {refine && Hbar64 && p->heev_fp64[0], refine && Hbar64 && p->heev_fp64[1],
+                       refine && Hbar64 && p->heev_fp64[2], refine && Hbar64 && p->heev_fp64[3]};
+  if (f64[0] || f64[1] || f64[2] || f64[3]) {
+    const int vm = wantv ? 1 : 0;
+    const double eps = 1.1102230246251565e-16;
+    if (e == hipSuccess && f64[0]) e = launch_heev_m<double, 4>(p, vm, Hbar64, Sbar64, w, V, info, 30, 16 * eps, s);
+    if (e == hipSuccess && f64[1]) e = launch_heev_m<double, 8>(p, vm, Hbar64, Sbar64, w, V, info, 30, 32 * eps, s);
+    if (e == hipSuccess && f64[2]) e = launch_heev_m<double, 16>(p, vm, Hbar64, Sbar64, w, V, info, 30, 64 * eps, s);
+    if (e == hipSuccess && f64[3]) e = launch_heev_m<double, 32>(p, vm, Hbar64, Sbar64, w, V, info, 30, 128 * eps, s);
+  }
   const int vm = refine ? 2 : (wantv ? 1 : 0);
   void* vdst = refine ? (void*)U : V;
   int32_t* i32 = refine ? info32 : info;
@@ -1166,15 +1177,15 @@ hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, co
   const bool in64 = refine && !Hbar;
   const void* h32 = in64 ? Hbar64 : Hbar;
   const void* s32 = in64 ? Sbar64 : Sbar;
-  if (e == hipSuccess) e = launch_heev_m<float, 4>(p, vm, h32, s32, w, vdst, i32, 20, 16 * eps, s, in64);
-  if (e == hipSuccess) e = launch_heev_m<float, 8>(p, vm, h32, s32, w, vdst, i32, 20, 32 * eps, s, in64);
-  if (e == hipSuccess) e = launch_heev_m<float, 16>(p, vm, h32, s32, w, vdst, i32, 20, 64 * eps, s, in64);
-  if (e == hipSuccess) e = launch_heev_m<float, 32>(p, vm, h32, s32, w, vdst, i32, 20, 128 * eps, s, in64);
+  if (e == hipSuccess && !f64[0]) e = launch_heev_m<float, 4>(p, vm, h32, s32, w, vdst, i32, 20, 16 * eps, s, in64);
+  if (e == hipSuccess && !f64[1]) e = launch_heev_m<float, 8>(p, vm, h32, s32, w, vdst, i32, 20, 32 * eps, s, in64);
+  if (e == hipSuccess && !f64[2]) e = launch_heev_m<float, 16>(p, vm, h32, s32, w, vdst, i32, 20, 64 * eps, s, in64);
+  if (e == hipSuccess && !f64[3]) e = launch_heev_m<float, 32>(p, vm, h32, s32, w, vdst, i32, 20, 128 * eps, s, in64);
   if (e != hipSuccess || !refine) return e;
-  if (e == hipSuccess) e = launch_refine_m<4>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
-  if (e == hipSuccess) e = launch_refine_m<8>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
-  if (e == hipSuccess) e = launch_refine_m<16>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
-  if (e == hipSuccess) e = launch_refine_m<32>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
+  if (e == hipSuccess && !f64[0]) e = launch_refine_m<4>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
+  if (e == hipSuccess && !f64[1]) e = launch_refine_m<8>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
+  if (e == hipSuccess && !f64[2]) e = launch_refine_m<16>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
+  if (e == hipSuccess && !f64[3]) e = launch_refine_m<32>(p, wantv, Hbar64, Sbar64, Hgen64, Sgen64, U, info32, w, V, info, s);
   return e;
 }
 

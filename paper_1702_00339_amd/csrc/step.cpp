@@ -133,12 +133,16 @@ void get_tuning(const lhf_plan_s* p, lhf_tuning* t) {
   t->heev_wide = 0;
   for (int c = 0; c < 4; ++c) t->heev_wide |= p->heev_wide[c] ? 1 << c : 0;
   t->fourier_sep = p->fourier_sep && p->sep_ok ? 1 : 0;
+  t->heev_fp64 = 0;
+  if (p->prec == LHF_PREC_MIXED)
+    for (int c = 0; c < 4; ++c) t->heev_fp64 |= p->heev_fp64[c] ? 1 << c : 0;
 }
 
 int32_t set_tuning(lhf_plan_s* p, const lhf_tuning* t) {
   if (t->dft_threads < 1024 || t->dft_threads > (1 << 24) || t->gram_split < 1 || t->gram_split > kGramSplitMax ||
       t->gram_grid < 1 || t->gram_grid > (1 << 20) || t->tol32_scale < 1 || t->tol32_scale > (1 << 16) ||
-      t->heev_wide < 0 || t->heev_wide > 15 || t->fourier_sep < 0 || t->fourier_sep > 1) {
+      t->heev_wide < 0 || t->heev_wide > 15 || t->fourier_sep < 0 || t->fourier_sep > 1 ||
+      t->heev_fp64 < 0 || t->heev_fp64 > 15) {
     set_error("tuning value out of range");
     return LHF_ERR_INVALID;
   }
@@ -149,6 +153,7 @@ int32_t set_tuning(lhf_plan_s* p, const lhf_tuning* t) {
   p->tol32_scale = t->tol32_scale;
   for (int c = 0; c < 4; ++c) p->heev_wide[c] = (t->heev_wide >> c) & 1;
   p->fourier_sep = t->fourier_sep;
+  for (int c = 0; c < 4; ++c) p->heev_fp64[c] = p->prec == LHF_PREC_MIXED && ((t->heev_fp64 >> c) & 1);
   return tables ? apply_tuning(p) : LHF_OK;
 }
 
@@ -205,6 +210,8 @@ bool parse_entry(const std::string& body, lhf_tuning& t) {
   t.heev_wide = field(body, "heev_wide", w) && w >= 0.0 ? (int32_t)w : t.heev_wide;
   w = -1.0;
   t.fourier_sep = field(body, "fourier_sep", w) && w >= 0.0 ? (int32_t)w : t.fourier_sep;
+  w = -1.0;
+  t.heev_fp64 = field(body, "heev_fp64", w) && w >= 0.0 ? (int32_t)w : t.heev_fp64;
   t.dft_threads = (int32_t)a;
   t.gram_split = (int32_t)b;
   t.gram_grid = (int32_t)c;
@@ -218,8 +225,9 @@ void write_cache(const char* path, std::map<std::string, std::string> entries, c
   char buf[256];
   std::snprintf(buf, sizeof(buf),
                 "{\"dft_threads\": %d, \"gram_split\": %d, \"gram_grid\": %d, \"tol32_scale\": %d, "
-                "\"heev_wide\": %d, \"fourier_sep\": %d, \"step_ms\": %.6f}",
-                t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.step_ms);
+                "\"heev_wide\": %d, \"fourier_sep\": %d, \"heev_fp64\": %d, \"step_ms\": %.6f}",
+                t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.heev_fp64,
+                t.step_ms);
   entries[key] = buf;
   std::ofstream f(path, std::ios::trunc);
   f << "{\n";
@@ -325,23 +333,28 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
     ms = (double)f / reps;
     return r;
   };
-  // coordinate search: each knob only moves the time of its own stage
-  auto search = [&](int which, int32_t lhf_tuning::*knob, const int32_t* cand, int ncand) -> int32_t {
-    lhf_tuning best{};
-    get_tuning(p, &best);
+  // keep the fastest of whole candidate settings, timed on the selected stages
+  auto pick = [&](int which, const lhf_tuning* cand, int ncand) -> int32_t {
+    int best = 0;
     double best_ms = 1e300;
     for (int i = 0; i < ncand; ++i) {
-      lhf_tuning t = best;
-      t.*knob = cand[i];
       int32_t r = hip_status(hipStreamSynchronize(s), "synchronize");
-      if (r == LHF_OK) r = set_tuning(p, &t);
+      if (r == LHF_OK) r = set_tuning(p, &cand[i]);
       double ms = 0.0;
       if (r == LHF_OK) r = timed(which, 20, ms);
       if (r != LHF_OK) return r;
-      if (ms < best_ms) { best_ms = ms; best.*knob = cand[i]; }
+      if (ms < best_ms) { best_ms = ms; best = i; }
     }
     int32_t r = hip_status(hipStreamSynchronize(s), "synchronize");
-    return r == LHF_OK ? set_tuning(p, &best) : r;
+    return r == LHF_OK ? set_tuning(p, &cand[best]) : r;
+  };
+  // coordinate search: each knob only moves the time of its own stage
+  auto search = [&](int which, int32_t lhf_tuning::*knob, const int32_t* cand, int ncand) -> int32_t {
+    lhf_tuning cur{};
+    get_tuning(p, &cur);
+    std::vector<lhf_tuning> c(ncand, cur);
+    for (int i = 0; i < ncand; ++i) c[i].*knob = cand[i];
+    return pick(which, c.data(), ncand);
   };
   static const int32_t split_c[] = {16, 32, 64, 128, 256};
   static const int32_t grid_c[] = {1024, 2048, 4096, 8192};
@@ -356,13 +369,23 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
   static const int32_t sep_c[] = {0, 1};
   if (st == LHF_OK && p->sep_ok) st = search(7, &lhf_tuning::fourier_sep, sep_c, 2);
   if (st == LHF_OK) st = search(2, &lhf_tuning::dft_threads, dft_c, 5);
-  // eigensolver layout, one size class at a time
+  // eigensolver, one size class at a time: layout, and on mixed plans given
+  // the complex128 blocks, FP32 solve + FP64 refinement or FP64 Jacobi alone
+  // (the latter wins where the cost of a rotation, not its arithmetic, sets
+  // the time); the two are searched together, since the best layout of one
+  // solver need not be that of the other
+  const bool alone = p->prec == LHF_PREC_MIXED && (a->heev_flags & LHF_HEEV_REFINE_FP64) && a->H_bar64;
   for (int c = 0; c < 4 && st == LHF_OK; ++c) {
     if (p->ncanon[c] == 0) continue;
     lhf_tuning cur{};
     get_tuning(p, &cur);
-    const int32_t lay_c[2] = {cur.heev_wide & ~(1 << c), cur.heev_wide | (1 << c)};
-    st = search(4, &lhf_tuning::heev_wide, lay_c, 2);
+    lhf_tuning cand[4];
+    for (int i = 0; i < 4; ++i) {
+      cand[i] = cur;
+      cand[i].heev_wide = (i & 1) ? cur.heev_wide | (1 << c) : cur.heev_wide & ~(1 << c);
+      cand[i].heev_fp64 = (i & 2) ? cur.heev_fp64 | (1 << c) : cur.heev_fp64 & ~(1 << c);
+    }
+    st = pick(4, cand, alone ? 4 : 2);
   }
   if (st == LHF_OK && p->prec == LHF_PREC_MIXED) st = search(4, &lhf_tuning::tol32_scale, tol_c, 4);
   if (st == LHF_OK) st = timed(7, 10, step_ms);

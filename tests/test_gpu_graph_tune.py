@@ -115,9 +115,10 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     assert t.gram_split in (16, 32, 64, 128, 256) and t.gram_grid in (1024, 2048, 4096, 8192)
     assert t.dft_threads in (32768, 65536, 131072, 262144, 524288) and t.tol32_scale in (1, 16, 256, 4096)
     got = pipe.plan.lhf_plan_get_tuning()
-    assert (got.dft_threads, got.gram_split, got.gram_grid, got.tol32_scale, got.heev_wide, got.fourier_sep) == \
-        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep)
-    assert 0 <= t.heev_wide <= 15 and t.fourier_sep in (0, 1)
+    assert (got.dft_threads, got.gram_split, got.gram_grid, got.tol32_scale, got.heev_wide, got.fourier_sep,
+            got.heev_fp64) == \
+        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.heev_fp64)
+    assert 0 <= t.heev_wide <= 15 and t.fourier_sep in (0, 1) and 0 <= t.heev_fp64 <= 15
     entries = json.load(open(cache))
     assert len(entries) == 1
     pipe.step_native()
@@ -130,8 +131,9 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     again = Pipeline(insts, prec=lhf.LHF_PREC_MIXED)
     t2 = again.autotune(cache)
     assert t2.from_cache == 1
-    assert (t2.dft_threads, t2.gram_split, t2.gram_grid, t2.tol32_scale, t2.heev_wide, t2.fourier_sep) == \
-        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep)
+    assert (t2.dft_threads, t2.gram_split, t2.gram_grid, t2.tol32_scale, t2.heev_wide, t2.fourier_sep,
+            t2.heev_fp64) == \
+        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.heev_fp64)
     # a different plan adds its own entry
     Pipeline(insts[:2], prec=lhf.LHF_PREC_FP64).autotune(cache)
     assert len(json.load(open(cache))) == 2
@@ -162,3 +164,12 @@ def test_set_tuning_extremes_keep_parity():
     bad.fourier_sep = 2
     with pytest.raises(lhf.LhfError):
         pipe.plan.lhf_plan_set_tuning(bad)
+    bad = pipe.plan.lhf_plan_get_tuning()
+    bad.heev_fp64 = 16
+    with pytest.raises(lhf.LhfError):
+        pipe.plan.lhf_plan_set_tuning(bad)
+    # an FP64 plan accepts the mask and reads 0: its classes all take FP64 Jacobi
+    t = pipe.plan.lhf_plan_get_tuning()
+    t.heev_fp64 = 15
+    pipe.plan.lhf_plan_set_tuning(t)
+    assert pipe.plan.lhf_plan_get_tuning().heev_fp64 == 0

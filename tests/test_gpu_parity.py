@@ -203,6 +203,33 @@ def test_separable_blocks_match_block_dft():
         wide.plan.lhf_fourier_blocks(wide.grams64, wide.H_bar, wide.S_bar, wide.ws)
 
 
+@pytest.mark.parametrize("mask", [0b0101, 0b1010, 0b1111])
+@pytest.mark.parametrize("src", ["direct", "bar64", "band"])
+def test_mixed_fp64_classes(mask, src):
+    """Mixed plans solving some size classes by FP64 Jacobi alone (tuning
+    field heev_fp64): every class meets the mixed bound, a class taken by
+    FP64 Jacobi meets the FP64 one, and a refined solve without complex128
+    blocks ("band") keeps the FP32 solve and refinement for every class."""
+    insts = [tiny_instance(**{"R": 8, **c}) for c in TINY]
+    pipe = Pipeline(insts, prec=lhf.LHF_PREC_MIXED, refine_src=src, want_vectors=True)
+    t = pipe.plan.lhf_plan_get_tuning()
+    t.heev_fp64 = mask
+    pipe.plan.lhf_plan_set_tuning(t)
+    assert pipe.plan.lhf_plan_get_tuning().heev_fp64 == mask
+    pipe.step()
+    torch.cuda.synchronize()
+    assert (pipe.info.cpu().numpy() == 0).all()
+    for inst, got, V in zip(insts, pipe.eigenvalues(), pipe.stacks("V")):
+        res, ref = _eig_ref(inst)
+        cls = 0 if inst.m0 <= 4 else 1 if inst.m0 <= 8 else 2 if inst.m0 <= 16 else 3
+        assert np.abs(got - ref).max() <= 1e-8, inst.name
+        if src != "band" and (mask >> cls) & 1:
+            assert (np.abs(got - ref) <= 1e-10 * np.maximum(np.abs(ref), 1.0)).all(), inst.name
+        Hb, Sb = res["H_bar"], res["S_bar"]
+        Rz = Hb @ V - (Sb @ V) * got[..., None, :]
+        assert np.abs(Rz).max() <= 1e-9 * max(1.0, np.abs(got).max()), inst.name
+
+
 @pytest.mark.parametrize("wide", [15, 0], ids=["wide", "four"])
 def test_eigenvectors_fp64_and_refined(wide):
     inst = tiny_instance(L=(5, 2, 1), n=(40, 16, 14), n_s=2, n_p=1, R=6, seed=131)
