@@ -39,13 +39,13 @@ WORKLOADS = {
 C4_CHECK = (28, 41, 52, 2)
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per call (FETCH_SIZE + WRITE_SIZE, KiB, scaled by a plain 512 MiB copy) of the mixed path's
-# eigensolve call (FP32 Jacobi + FP64 refinement kernels), block DFT and separable Fourier-block formation,
-# from two rocprofv3 --pmc runs of
-# `bench.py --probe-traffic` (profiles/traffic_per_dispatch.md).  Valid for the kernels as they were when
-# counted; absent (reported as null) where not counted.
-TRAFFIC_KIB = {"c2": {"eig": 1671.7, "dft": 2357.6},
-               "c3": {"eig": 51023.2, "dft": 66783.3, "sep": 69268.2},
-               "c4": {"eig": 843233.0, "dft": 1204188.1, "sep": 1344483.6}}
+# eigensolve call, block DFT and separable Fourier-block formation, from two rocprofv3 --pmc runs of
+# `bench.py --probe-traffic` (profiles/traffic_per_dispatch.md).  The eigensolve's kernels depend on the
+# tuned route, so its entry is keyed by the mixed plan's heev_fp64 and heev_wide masks.  Valid for the
+# kernels as they were when counted; absent (reported as null) where not counted.
+TRAFFIC_KIB = {"c2": {"eig": {}, "dft": 2357.6},
+               "c3": {"eig": {}, "dft": 66783.3, "sep": 69268.2},
+               "c4": {"eig": {}, "dft": 1204188.1, "sep": 1344483.6}}
 
 
 def parse():
@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a device copy of 512 MiB (the counters' scale), then three "
                          "eager steps of each path; prints nothing else")
+    ap.add_argument("--mixed-tuning", default="",
+                    help="with --probe-traffic: JSON object of tuning fields for the mixed plan")
     ap.add_argument("--probe-mfma", action="store_true",
                     help="for MFMA counter runs: three eager mixed steps with each Gram arithmetic (FP64, FP32, "
                          "bf16 hi+lo); prints nothing else")
@@ -143,27 +145,39 @@ def heev_class(m0):
 
 
 def heev_flops(insts, prec, R, fp64_mask=0):
-    """Algorithmic flops of one lhf_heev_batched call: per distinct block
-    150 m0^3 (Cholesky reduction and 6-10 Jacobi sweeps), plus on the mixed
-    path the FP64 refinement, (R + 4) m0^2 8 + 36 m0^3, except for the size
-    classes a mixed plan solves by FP64 Jacobi alone (bits of fp64_mask)."""
+    """Algorithmic flops of one eigenvalues-only lhf_heev_batched call, per
+    distinct block (8 flops per complex multiply-add).  FP64 solve: reduction
+    to standard form (overlap elimination m0^3 / 3 and two m0^3 products,
+    complex) and Householder tridiagonalisation (4/3 m0^3 complex), 29.3 m0^3,
+    plus bisection, m0 eigenvalues x 53 halvings x m0 rows x 4 flops.  A mixed
+    plan's FP32 classes: 150 m0^3 (reduction and 6-10 Jacobi sweeps) plus the
+    FP64 refinement, (R + 4) m0^2 8 + 36 m0^3; its FP64 classes (bits of
+    fp64_mask) count as the FP64 solve."""
     from paper_1702_00339_amd import lhf
     total = 0.0
     for inst in insts:
         m = inst.m0
-        per = 150.0 * m ** 3
         if prec == lhf.LHF_PREC_MIXED and not (fp64_mask >> heev_class(m)) & 1:
-            per += (R + 4) * m * m * 8 + 36.0 * m ** 3
+            per = 150.0 * m ** 3 + (R + 4) * m * m * 8 + 36.0 * m ** 3
+        else:
+            per = (8.0 / 3.0 + 16.0 + 32.0 / 3.0) * m ** 3 + 4.0 * 53.0 * m * m
         total += canonical_blocks(inst.L) * per
     return total
 
 
-def fp64_classes(m0s, mask):
-    """Path text for the size classes the tuned mixed plan solves by FP64 Jacobi alone."""
-    sizes = sorted({4 << heev_class(m) for m in m0s if (mask >> heev_class(m)) & 1})
-    if not sizes:
-        return ""
-    return " (blocks of size class M = " + ", ".join(str(x) for x in sizes) + ": FP64 Jacobi alone)"
+def eig_route(m0s, mask):
+    """The eigensolver route of the tuned mixed plan, per size class (bits of
+    mask: the FP64 solve alone)."""
+    f64 = sorted({4 << heev_class(m) for m in m0s if (mask >> heev_class(m)) & 1})
+    mix = sorted({4 << heev_class(m) for m in m0s if not (mask >> heev_class(m)) & 1})
+    def which(sizes):
+        return " (M = " + ", ".join(str(x) for x in sizes) + ")" if f64 and mix else ""
+    parts = []
+    if mix:
+        parts.append("FP32 Jacobi on the rounded blocks + FP64 Rayleigh-Ritz refinement" + which(mix))
+    if f64:
+        parts.append("FP64 Householder tridiagonalisation + bisection" + which(f64))
+    return "; ".join(parts)
 
 
 def bench_c5(torch, np, lhf, steps):
@@ -211,7 +225,9 @@ def bench_c5(torch, np, lhf, steps):
 def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
     """Kernels for a FETCH_SIZE / WRITE_SIZE counter run: a plain copy of
     512 MiB (reads and writes exactly that many bytes: the scale of the
-    counters), then three eager steps of the mixed and the FP64 paths."""
+    counters), then three eager steps of the mixed and the FP64 paths; the
+    mixed plan takes the tuning fields given by --mixed-tuning (a JSON object,
+    e.g. the autotuned route of a timed run), the FP64 plan its defaults."""
     src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -220,6 +236,11 @@ def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
     for prec in (lhf.LHF_PREC_MIXED, lhf.LHF_PREC_FP64):
         kw = {"gram": lhf.LHF_GRAM_FP64} if prec == lhf.LHF_PREC_MIXED else {}
         pipe = Pipeline(insts, prec=prec, **kw)
+        if prec == lhf.LHF_PREC_MIXED and args.mixed_tuning:
+            t = pipe.plan.lhf_plan_get_tuning()
+            for k, v in json.loads(args.mixed_tuning).items():
+                setattr(t, k, int(v))
+            pipe.plan.lhf_plan_set_tuning(t)
         for _ in range(3):
             pipe.step_native()
     torch.cuda.synchronize()
@@ -347,8 +368,12 @@ def main():
                          f"shift, combination, FFT, batched LAPACK eigensolves), median of {len(runs)} runs "
                          f"of {tmed:.2f} s"}
 
+    tuned = pm.plan.lhf_plan_get_tuning()
+
     def traffic(kind):
         t = TRAFFIC_KIB.get(args.config, {}).get(kind)
+        if kind == "eig":
+            t = (t or {}).get(f"fp64={tuned.heev_fp64},wide={tuned.heev_wide}")
         return None if t is None else t * 1024.0
 
     m0s = sorted({inst.m0 for inst in insts})
@@ -361,16 +386,14 @@ def main():
                    "path": ("mixed: FP64 MFMA Grams, " +
                             ("Fourier blocks formed separably from the Grams (complex128, no generator stacks)"
                              if sep else "FP64 stacks, one block DFT writing complex128 blocks") +
-                            ", FP32 Jacobi on their roundings, FP64 Rayleigh-Ritz refinement on complex128" +
-                            fp64_classes(m0s, fp64_mask) + "; one hipGraph replay per step")},
+                            "; " + eig_route(m0s, fp64_mask) + "; one hipGraph replay per step")},
         "fp64_path": {"value": nblk / sec["fp64"], "ms_per_step": sec["fp64"] * 1e3, "dtype": "f64"},
         "mixed_bf16x3_path": {"value": nblk / sec["mixed_bf16x3"], "ms_per_step": sec["mixed_bf16x3"] * 1e3,
                               "max_abs_eig_err_ha": errs["mixed_bf16x3"][0], "info_ok": errs["mixed_bf16x3"][2]},
         "accuracy": {"lattices_checked": len(checked),
                      "mixed_max_abs_eig_err_ha": errs["mixed"][0], "mixed_info_ok": errs["mixed"][2],
                      "fp64_max_rel_eig_err": errs["fp64"][1], "fp64_info_ok": errs["fp64"][2]},
-        "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: FP32 Jacobi + FP64 refinement" +
-                     fp64_classes(m0s, fp64_mask) + ")",
+        "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: " + eig_route(m0s, fp64_mask) + ")",
                      "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s", "frac": tflops / 157.3,
                      "traffic": traffic("eig"), "flops_per_launch": flops, "avg_launch_ms": ms_heev},
         "roofline_dft": {"bound": "hbm",

@@ -57,7 +57,7 @@ enum {
 
 /* Pipeline precision. */
 enum {
-  LHF_PREC_FP64 = 0,   /* FP64 Grams, FP64 stacks, complex128 blocks, FP64 Jacobi */
+  LHF_PREC_FP64 = 0,   /* FP64 Grams, FP64 stacks, complex128 blocks, FP64 solve */
   LHF_PREC_MIXED = 1   /* split-precision MFMA Grams, FP32 stacks, complex64 blocks,
                           FP32 Jacobi, FP64 eigenpair refinement                 */
 };
@@ -228,8 +228,11 @@ int32_t lhf_fourier_blocks(lhf_plan_t plan, const double* d_grams64, void* d_H_b
 
 /* ---------------------------------------------------------------- eigensolve
  * For every block j: Hbar_j u = lambda Sbar_j u (eq. HF-FSpace-Block), by
- * Cholesky reduction and cyclic parallel-order complex Jacobi sweeps; the
- * union over j is the spectrum of the full matrix pair (eq. lambdAbc).
+ * Cholesky reduction to a standard Hermitian problem, then, for FP64
+ * eigenvalues without vectors, Householder reduction to tridiagonal form and
+ * bisection on Sturm counts (eigenvalues to a few ulps of the block's norm),
+ * otherwise cyclic parallel-order complex Jacobi sweeps; the union over j is
+ * the spectrum of the full matrix pair (eq. lambdAbc).
  * Conjugate blocks j and -j share their spectrum; each pair is solved once.
  * d_H_bar, d_S_bar: device, complex128 (FP64 plan) or complex64 (mixed plan);
  *   mixed plans with LHF_HEEV_REFINE_FP64 may pass both NULL together with
@@ -246,7 +249,8 @@ int32_t lhf_fourier_blocks(lhf_plan_t plan, const double* d_grams64, void* d_H_b
  * d_V: device, optional, complex (plan precision; complex128 after
  *   refinement) [nblocks][m0][m0], column c = eigenvector c, S-orthonormal.
  * d_info: device int32 [nblocks]: 0 ok; k > 0 Sbar not positive definite at
- *   column k; -1 Jacobi did not converge; -2 non-finite input.
+ *   column k; -1 Jacobi did not converge; -2 non-finite input (the
+ *   bisection always ends within its bound and reports 0).
  * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE. */
 int32_t lhf_heev_batched(lhf_plan_t plan, uint32_t flags, const void* d_H_bar, const void* d_S_bar,
                          const void* d_H_bar64, const void* d_S_bar64,
@@ -409,10 +413,11 @@ int32_t lhf_graph_destroy(lhf_graph_t graph);
  *                written.  Reads 0 when the plan does not qualify;
  *   heev_fp64    mixed plans, bit c (size class M = 4 << c): a refined solve
  *                that is given the complex128 blocks solves that class by the
- *                FP64 Jacobi of FP64 plans alone, with no FP32 solve and no
- *                refinement (for small blocks, where the cost of a rotation
- *                does not depend on its precision); 0..15, default 0, reads 0
- *                on FP64 plans.  The eigenvalues of such a class meet the FP64
+ *                FP64 solver of FP64 plans alone, with no FP32 solve and no
+ *                refinement (tridiagonal reduction and bisection without
+ *                vectors, Jacobi with them: where rotation latency, not
+ *                arithmetic, sets the FP32 solve's time, or where bisection
+ *                beats Jacobi); 0..15, default 0, reads 0 on FP64 plans.  The eigenvalues of such a class meet the FP64
  *                tolerance, which is tighter than the refined one.
  * Apart from heev_fp64, none of them changes what is computed; the Gram split
  * changes the order of the FP64 partial sums and the eigensolver layout the

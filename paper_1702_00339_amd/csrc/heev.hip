@@ -636,6 +636,164 @@ __device__ void eig_rank(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int m, int
   __syncthreads();
 }
 
+// 3'-4'. Eigenvalues only: Householder reduction of the Hermitian A (its
+// leading n x n block) to tridiagonal form, then bisection on Sturm counts.
+// Step h reflects rows and columns h+1..n-1 with P = I - beta u u^H,
+// u = x + phase(x_0) |x| e_0 (x: column h below the diagonal), so the new
+// subdiagonal entry has modulus |x|; the trailing block is updated as
+// A <- A - u q^H - q u^H with p = beta A u, q = p - (beta u^H p / 2) u.  The
+// tridiagonal matrix with complex subdiagonal has the spectrum of the real one
+// with the moduli (a diagonal unitary similarity), so only d_i and e_i^2 are
+// kept.  Eigenvalue i (ascending) is found by the P = M / W lanes of row
+// group i: each counts the eigenvalues below one of P interior points of the
+// current interval (the Sturm sequence q_j = d_j - x - e_(j-1)^2 / q_(j-1),
+// small pivots replaced as in standard bisection) and the group keeps the
+// sub-interval holding it, until its width is a few ulps of the interval or of
+// the matrix norm.  Each lane runs two Sturm sequences at once (2 P + 1
+// sections per pass), with 1 / q_(j-1) from the hardware reciprocal refined by
+// two Newton steps r <- r + r (1 - q r); entries past n are padded with
+// d = 1e300, e = 0, which count nothing, so the sequence runs over all M rows.
+// The eigenvalues land sorted: rank i = i.
+template <int W, typename R, int M, int G, bool HASU, bool HASV>
+__device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n) {
+  typedef typename Cx<R>::T C;
+  constexpr int TPM = M * M / W, P = TPM / M;
+  static_assert(P >= 1 && (P & (P - 1)) == 0 && P <= 64, "row group of one wavefront");
+  C* uv = &sh.B[g][0][0];   // reflector u (B is free after the reduction)
+  C* qv = &sh.B[g][1][0];   // q
+  R* dg = sh.dsc[g];        // diagonal d
+  R* e2 = sh.dn[g];         // squared subdiagonal moduli
+  const int gi = t / P, gc = t % P;   // row group and lane within it
+#pragma unroll 1
+  for (int h = 0; h < M - 2; ++h) {
+    const bool act = h < n - 2;
+    R x2 = R(0);
+    if (act && t > h + 1 && t < n) {
+      const C x = sh.A[g][t][h];
+      x2 = x.x * x.x + x.y * x.y;
+    }
+    const R s2 = group_sum<W>(sh, g, t, x2);
+    const C al = act ? sh.A[g][h + 1][h] : cmk<C>(R(0), R(0));
+    const R a2 = al.x * al.x + al.y * al.y;
+    const R a = sqrt(a2), nrm = sqrt(a2 + s2);
+    const R beta = act && s2 > R(0) ? R(1) / (nrm * (nrm + a)) : R(0);
+    const C ph = a > R(0) ? cscale(al, R(1) / a) : cmk<C>(R(1), R(0));
+    if (act && t > h && t < n) uv[t] = t == h + 1 ? cscale(ph, a + nrm) : sh.A[g][t][h];
+    if (act && t == 0) e2[h] = a2 + s2;
+    __syncthreads();
+    // p_i = beta sum_j A_ij u_j, row i by the P lanes of group i
+    const bool row = beta != R(0) && gi > h && gi < n;
+    C acc = cmk<C>(R(0), R(0));
+    if (row) {
+#pragma unroll
+      for (int j = gc; j < M; j += P)
+        if (j > h && j < n) acc = cadd(acc, cmul(sh.A[g][gi][j], uv[j]));
+    }
+#pragma unroll
+    for (int o = P / 2; o > 0; o >>= 1) {
+      acc.x += __shfl_xor(acc.x, o, 64);
+      acc.y += __shfl_xor(acc.y, o, 64);
+    }
+    acc = cscale(acc, beta);
+    C ui = cmk<C>(R(0), R(0));
+    if (row) ui = uv[gi];
+    const R up = row && gc == 0 ? ui.x * acc.x + ui.y * acc.y : R(0);   // Re(conj(u_i) p_i)
+    const R kk = R(0.5) * beta * group_sum<W>(sh, g, t, up);
+    if (row && gc == 0) qv[gi] = csub(acc, cscale(ui, kk));
+    __syncthreads();
+    if (beta != R(0)) {
+      LHF_FOR_ENTRIES {
+        if (r > h && r < n && c > h && c < n) {
+          const C ur = uv[r], uc = uv[c], qr = qv[r], qc = qv[c];
+          // A_rc -= u_r conj(q_c) + q_r conj(u_c)
+          sh.A[g][r][c] = csub(sh.A[g][r][c], cadd(cmulc(qc, ur), cmulc(uc, qr)));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (t < M) dg[t] = t < n ? sh.A[g][t][t].x : R(1e300);
+  if (t < M - 1 && t >= n - 1) e2[t] = R(0);
+  if (t == 0 && n >= 2) {
+    const C b = sh.A[g][n - 1][n - 2];
+    e2[n - 2] = b.x * b.x + b.y * b.y;
+  }
+  __syncthreads();
+  // Gershgorin interval of the tridiagonal matrix
+  constexpr R eps = R(1.1102230246251565e-16);
+  R lo = R(0), hi = R(0), emax = R(0);
+  for (int j = 0; j < n; ++j) {
+    const R ej = j < n - 1 ? sqrt(e2[j]) : R(0), ejm = j > 0 ? sqrt(e2[j - 1]) : R(0);
+    const R l = dg[j] - ej - ejm, u = dg[j] + ej + ejm;
+    lo = j == 0 ? l : fmin(lo, l);
+    hi = j == 0 ? u : fmax(hi, u);
+    if (j < n - 1) emax = fmax(emax, e2[j]);
+  }
+  const R tnorm = fmax(fabs(lo), fabs(hi));
+  const R pivmin = R(2.2250738585072014e-308) * fmax(R(1), emax);
+  const R widen = R(4) * R(n) * eps * tnorm + R(2) * pivmin;
+  lo -= widen;
+  hi += widen;
+  const bool live = gi < n;
+  const R stepa = R(2 * gc + 1) / R(2 * P + 1), stepb = R(2 * gc + 2) / R(2 * P + 1);
+  auto rcp_nr = [](R q) -> R {
+    R r = __builtin_amdgcn_rcp(q);
+    R u = fma(-q, r, R(1));
+    r = fma(r, u, r);
+    u = fma(-q, r, R(1));
+    return fma(r, u, r);
+  };
+#pragma unroll 1
+  for (int it = 0; it < 96; ++it) {
+    const bool conv = !live || hi - lo <= R(2) * eps * fmax(fabs(lo), fabs(hi)) + eps * tnorm + R(4) * pivmin;
+    if (__all(conv)) break;
+    const R xa = lo + (hi - lo) * stepa, xb = lo + (hi - lo) * stepb;
+    int ca = 0, cb = 0;
+    if (live) {
+      R qa = dg[0] - xa, qb = dg[0] - xb;
+      if (fabs(qa) < pivmin) qa = -pivmin;
+      if (fabs(qb) < pivmin) qb = -pivmin;
+      ca += qa < R(0) ? 1 : 0;
+      cb += qb < R(0) ? 1 : 0;
+      auto row = [&](int j) {
+        const R dj = dg[j], ej = e2[j - 1];
+        qa = fma(-ej, rcp_nr(qa), dj - xa);
+        qb = fma(-ej, rcp_nr(qb), dj - xb);
+        if (fabs(qa) < pivmin) qa = -pivmin;
+        if (fabs(qb) < pivmin) qb = -pivmin;
+        ca += qa < R(0) ? 1 : 0;
+        cb += qb < R(0) ? 1 : 0;
+      };
+      if constexpr (M <= 16) {
+#pragma unroll
+        for (int j = 1; j < M; ++j) row(j);
+      } else {
+        // rolled: a fully unrolled pass would hold d and e in registers
+#pragma unroll 1
+        for (int j = 1; j < n; ++j) row(j);
+      }
+    }
+    R lc = lo, hc = hi;
+    if (ca <= gi) lc = xa; else hc = xa;
+    if (cb <= gi) lc = fmax(lc, xb); else hc = fmin(hc, xb);
+#pragma unroll
+    for (int o = P / 2; o > 0; o >>= 1) {
+      lc = fmax(lc, __shfl_xor(lc, o, 64));
+      hc = fmin(hc, __shfl_xor(hc, o, 64));
+    }
+    if (!conv) {
+      lo = lc;
+      hi = hc;
+    }
+  }
+  if (live && gc == 0) {
+    sh.lam[g][gi] = R(0.5) * (lo + hi);
+    sh.rank[g][gi] = gi;
+  }
+  if (t == 0) sh.flag[g][2] = 1;
+  __syncthreads();
+}
+
 // Eigenvectors C^-H V = W^H D^-1/2 V into A (one tiled product).
 template <int W, typename R, int M, int G, bool HASU, bool HASV>
 __device__ void backsub_vectors(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
@@ -716,8 +874,12 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatD
   if (bad) sh.flag[g][1] = 1;
   __syncthreads();
   chol_reduce<W, false>(sh, g, t);
-  const int cur = jacobi<W, R, M, G, false, WANTV, WANTV>(sh, g, t, maxsw, tol);
-  eig_rank(sh, g, t, m, cur);
+  if constexpr (VMODE == 0 && sizeof(R) == 8) {
+    tridiag_eigs<W>(sh, g, t, m);
+  } else {
+    const int cur = jacobi<W, R, M, G, false, WANTV, WANTV>(sh, g, t, maxsw, tol);
+    eig_rank(sh, g, t, m, cur);
+  }
   if constexpr (WANTV) backsub_vectors<W>(sh, g, t);
   if (!valid) return;   // no barrier follows
   const int64_t wb = L.w_off + (int64_t)blk * m, wc = L.w_off + (int64_t)cblk * m;
@@ -1158,7 +1320,7 @@ hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, co
     return e;
   }
   // mixed: FP32 solve, then FP64 refinement; with complex128 blocks, the
-  // classes the plan marks are solved by FP64 Jacobi alone instead
+  // classes the plan marks take the FP64 solve alone instead
   const bool f64[4] = {refine && Hbar64 && p->heev_fp64[0], refine && Hbar64 && p->heev_fp64[1],
                        refine && Hbar64 && p->heev_fp64[2], refine && Hbar64 && p->heev_fp64[3]};
   if (f64[0] || f64[1] || f64[2] || f64[3]) {

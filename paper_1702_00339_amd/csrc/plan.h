@@ -49,7 +49,7 @@ struct lhf_plan_s {
   // eigensolver layout per class: one matrix entry per thread (wide) when the
   // four-entries-per-thread launch would leave SIMDs without a wavefront
   bool heev_wide[4] = {false, false, false, false};
-  bool heev_fp64[4] = {false, false, false, false};   // mixed plans: class solved by FP64 Jacobi alone
+  bool heev_fp64[4] = {false, false, false, false};   // mixed plans: class takes the FP64 solve alone
   static constexpr int64_t kWideWaves = 1024;   // one wavefront per SIMD of the device
   // tunables (planner defaults, refined by lhf_plan_autotune)
   int32_t dft_target_threads = 131072;  // threads one DFT pass aims to run

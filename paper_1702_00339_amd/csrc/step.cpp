@@ -370,7 +370,7 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
   if (st == LHF_OK && p->sep_ok) st = search(7, &lhf_tuning::fourier_sep, sep_c, 2);
   if (st == LHF_OK) st = search(2, &lhf_tuning::dft_threads, dft_c, 5);
   // eigensolver, one size class at a time: layout, and on mixed plans given
-  // the complex128 blocks, FP32 solve + FP64 refinement or FP64 Jacobi alone
+  // the complex128 blocks, FP32 solve + FP64 refinement or the FP64 solve alone
   // (the latter wins where the cost of a rotation, not its arithmetic, sets
   // the time); the two are searched together, since the best layout of one
   // solver need not be that of the other

@@ -168,7 +168,7 @@ def test_set_tuning_extremes_keep_parity():
     bad.heev_fp64 = 16
     with pytest.raises(lhf.LhfError):
         pipe.plan.lhf_plan_set_tuning(bad)
-    # an FP64 plan accepts the mask and reads 0: its classes all take FP64 Jacobi
+    # an FP64 plan accepts the mask and reads 0: its classes all take the FP64 solve
     t = pipe.plan.lhf_plan_get_tuning()
     t.heev_fp64 = 15
     pipe.plan.lhf_plan_set_tuning(t)

@@ -206,9 +206,9 @@ def test_separable_blocks_match_block_dft():
 @pytest.mark.parametrize("mask", [0b0101, 0b1010, 0b1111])
 @pytest.mark.parametrize("src", ["direct", "bar64", "band"])
 def test_mixed_fp64_classes(mask, src):
-    """Mixed plans solving some size classes by FP64 Jacobi alone (tuning
+    """Mixed plans solving some size classes by the FP64 solve alone (tuning
     field heev_fp64): every class meets the mixed bound, a class taken by
-    FP64 Jacobi meets the FP64 one, and a refined solve without complex128
+    FP64 solve meets the FP64 one, and a refined solve without complex128
     blocks ("band") keeps the FP32 solve and refinement for every class."""
     insts = [tiny_instance(**{"R": 8, **c}) for c in TINY]
     pipe = Pipeline(insts, prec=lhf.LHF_PREC_MIXED, refine_src=src, want_vectors=True)
