@@ -645,42 +645,58 @@ __device__ void eig_rank(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int m, int
 // tridiagonal matrix with complex subdiagonal has the spectrum of the real one
 // with the moduli (a diagonal unitary similarity), so only d_i and e_i^2 are
 // kept.  Eigenvalue i (ascending) is found by the P = M / W lanes of row
-// group i: each counts the eigenvalues below one of P interior points of the
-// current interval (the Sturm sequence q_j = d_j - x - e_(j-1)^2 / q_(j-1),
-// small pivots replaced as in standard bisection) and the group keeps the
-// sub-interval holding it, until its width is a few ulps of the interval or of
-// the matrix norm.  Each lane runs two Sturm sequences at once (2 P + 1
-// sections per pass), with 1 / q_(j-1) from the hardware reciprocal refined by
-// two Newton steps r <- r + r (1 - q r); entries past n are padded with
-// d = 1e300, e = 0, which count nothing, so the sequence runs over all M rows.
-// The eigenvalues land sorted: rank i = i.
+// group i: each counts the eigenvalues below interior points of the current
+// interval and the group keeps the sub-interval holding it, until its width is
+// a few ulps of the interval or of the matrix norm.  The count at x is the
+// number of sign changes of the leading minors p_j of T - x I, from the
+// division-free recurrence p_j = (d_j - x) p_(j-1) - e_(j-1)^2 p_(j-2) (a zero
+// taken as positive, which counts as the ratio form with small pivots made
+// negative does), rescaled by 2^-+256 every fourth row against overflow and
+// underflow (exact, sign-preserving).  Each lane runs two sequences at once
+// (2 P + 1 sections per pass).  The eigenvalues land sorted: rank i = i.
 template <int W, typename R, int M, int G, bool HASU, bool HASV>
 __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n) {
   typedef typename Cx<R>::T C;
   constexpr int TPM = M * M / W, P = TPM / M;
   static_assert(P >= 1 && (P & (P - 1)) == 0 && P <= 64, "row group of one wavefront");
   C* uv = &sh.B[g][0][0];   // reflector u (B is free after the reduction)
-  C* qv = &sh.B[g][1][0];   // q
+  C* qv = &sh.B[g][1][0];   // p
   R* dg = sh.dsc[g];        // diagonal d
   R* e2 = sh.dn[g];         // squared subdiagonal moduli
+  C* de = &sh.B[g][2][0];   // (d_j, e_(j-1)^2) per row, one LDS word for the Sturm pass
   const int gi = t / P, gc = t % P;   // row group and lane within it
+  // reductions: over the TPM lanes of the matrix, or per wavefront of it
+  constexpr int WV = TPM < 64 ? TPM : 64, NWM = TPM < 64 ? 1 : TPM / 64;
+  static_assert(NWM <= 16, "per-wave partials fit the reduction array");
+  R* part = sh.red[g];      // per-wave partial sums of Re(u^H p)
+  R* bsh = &sh.lam[g][0];   // beta of the current step (lam is written after the loop)
+  // three barriers per step: u and beta published; p and the partials of
+  // u^H p published; trailing block updated with q = p - K u formed in place
 #pragma unroll 1
   for (int h = 0; h < M - 2; ++h) {
     const bool act = h < n - 2;
+    // the column below the diagonal sits in lanes t < n <= 32 of the first wave
     R x2 = R(0);
     if (act && t > h + 1 && t < n) {
       const C x = sh.A[g][t][h];
       x2 = x.x * x.x + x.y * x.y;
     }
-    const R s2 = group_sum<W>(sh, g, t, x2);
-    const C al = act ? sh.A[g][h + 1][h] : cmk<C>(R(0), R(0));
-    const R a2 = al.x * al.x + al.y * al.y;
-    const R a = sqrt(a2), nrm = sqrt(a2 + s2);
-    const R beta = act && s2 > R(0) ? R(1) / (nrm * (nrm + a)) : R(0);
-    const C ph = a > R(0) ? cscale(al, R(1) / a) : cmk<C>(R(1), R(0));
-    if (act && t > h && t < n) uv[t] = t == h + 1 ? cscale(ph, a + nrm) : sh.A[g][t][h];
-    if (act && t == 0) e2[h] = a2 + s2;
+#pragma unroll
+    for (int o = WV / 2; o > 0; o >>= 1) x2 += __shfl_xor(x2, o, 64);
+    if (t < WV) {
+      const C al = act ? sh.A[g][h + 1][h] : cmk<C>(R(0), R(0));
+      const R a2 = al.x * al.x + al.y * al.y;
+      const R a = sqrt(a2), nrm = sqrt(a2 + x2);
+      const R beta = act && x2 > R(0) ? R(1) / (nrm * (nrm + a)) : R(0);
+      const C ph = a > R(0) ? cscale(al, R(1) / a) : cmk<C>(R(1), R(0));
+      if (act && t > h && t < n) uv[t] = t == h + 1 ? cscale(ph, a + nrm) : sh.A[g][t][h];
+      if (t == 0) {
+        bsh[0] = beta;
+        if (act) e2[h] = a2 + x2;
+      }
+    }
     __syncthreads();
+    const R beta = bsh[0];
     // p_i = beta sum_j A_ij u_j, row i by the P lanes of group i
     const bool row = beta != R(0) && gi > h && gi < n;
     C acc = cmk<C>(R(0), R(0));
@@ -695,16 +711,25 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
       acc.y += __shfl_xor(acc.y, o, 64);
     }
     acc = cscale(acc, beta);
-    C ui = cmk<C>(R(0), R(0));
-    if (row) ui = uv[gi];
-    const R up = row && gc == 0 ? ui.x * acc.x + ui.y * acc.y : R(0);   // Re(conj(u_i) p_i)
-    const R kk = R(0.5) * beta * group_sum<W>(sh, g, t, up);
-    if (row && gc == 0) qv[gi] = csub(acc, cscale(ui, kk));
+    R up = R(0);
+    if (row && gc == 0) {
+      const C ui = uv[gi];
+      up = ui.x * acc.x + ui.y * acc.y;   // Re(conj(u_i) p_i)
+      qv[gi] = acc;                       // p
+    }
+#pragma unroll
+    for (int o = WV / 2; o > 0; o >>= 1) up += __shfl_xor(up, o, 64);
+    if ((t & (WV - 1)) == 0) part[t / WV] = up;
     __syncthreads();
     if (beta != R(0)) {
+      R ks = R(0);
+#pragma unroll
+      for (int w = 0; w < NWM; ++w) ks += part[w];
+      const R kk = R(0.5) * beta * ks;
       LHF_FOR_ENTRIES {
         if (r > h && r < n && c > h && c < n) {
-          const C ur = uv[r], uc = uv[c], qr = qv[r], qc = qv[c];
+          const C ur = uv[r], uc = uv[c];
+          const C qr = csub(qv[r], cscale(ur, kk)), qc = csub(qv[c], cscale(uc, kk));
           // A_rc -= u_r conj(q_c) + q_r conj(u_c)
           sh.A[g][r][c] = csub(sh.A[g][r][c], cadd(cmulc(qc, ur), cmulc(uc, qr)));
         }
@@ -712,13 +737,15 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
     }
     __syncthreads();
   }
-  if (t < M) dg[t] = t < n ? sh.A[g][t][t].x : R(1e300);
-  if (t < M - 1 && t >= n - 1) e2[t] = R(0);
+  if (t < n) dg[t] = sh.A[g][t][t].x;
   if (t == 0 && n >= 2) {
     const C b = sh.A[g][n - 1][n - 2];
     e2[n - 2] = b.x * b.x + b.y * b.y;
   }
   __syncthreads();
+  // rows past n (M <= 16 passes run over all M rows) get e^2 = 0 and, in
+  // the pass, the factor 1 in place of d_j - x: p_j = p_(j-1), no change
+  if (t < M) de[t] = t < n ? cmk<C>(dg[t], t > 0 ? e2[t - 1] : R(0)) : cmk<C>(R(0), R(0));
   // Gershgorin interval of the tridiagonal matrix
   constexpr R eps = R(1.1102230246251565e-16);
   R lo = R(0), hi = R(0), emax = R(0);
@@ -730,46 +757,54 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
     if (j < n - 1) emax = fmax(emax, e2[j]);
   }
   const R tnorm = fmax(fabs(lo), fabs(hi));
-  const R pivmin = R(2.2250738585072014e-308) * fmax(R(1), emax);
-  const R widen = R(4) * R(n) * eps * tnorm + R(2) * pivmin;
+  const R tiny = R(2.2250738585072014e-308) * fmax(R(1), emax);   // absolute floor of the widths
+  const R widen = R(4) * R(n) * eps * tnorm + R(2) * tiny;
   lo -= widen;
   hi += widen;
+  __syncthreads();
   const bool live = gi < n;
   const R stepa = R(2 * gc + 1) / R(2 * P + 1), stepb = R(2 * gc + 2) / R(2 * P + 1);
-  auto rcp_nr = [](R q) -> R {
-    R r = __builtin_amdgcn_rcp(q);
-    R u = fma(-q, r, R(1));
-    r = fma(r, u, r);
-    u = fma(-q, r, R(1));
-    return fma(r, u, r);
-  };
+  constexpr R kBig = R(1.157920892373162e77), kSmall = R(8.636168555094445e-78);   // 2^256, 2^-256
 #pragma unroll 1
   for (int it = 0; it < 96; ++it) {
-    const bool conv = !live || hi - lo <= R(2) * eps * fmax(fabs(lo), fabs(hi)) + eps * tnorm + R(4) * pivmin;
+    const bool conv = !live || hi - lo <= R(2) * eps * fmax(fabs(lo), fabs(hi)) + eps * tnorm + R(4) * tiny;
     if (__all(conv)) break;
     const R xa = lo + (hi - lo) * stepa, xb = lo + (hi - lo) * stepb;
     int ca = 0, cb = 0;
     if (live) {
-      R qa = dg[0] - xa, qb = dg[0] - xb;
-      if (fabs(qa) < pivmin) qa = -pivmin;
-      if (fabs(qb) < pivmin) qb = -pivmin;
-      ca += qa < R(0) ? 1 : 0;
-      cb += qb < R(0) ? 1 : 0;
+      const C d0 = de[0];
+      R pa2 = R(1), pb2 = R(1), pa1 = d0.x - xa, pb1 = d0.x - xb;
+      bool na = pa1 < R(0), nb = pb1 < R(0);
+      ca = na ? 1 : 0;
+      cb = nb ? 1 : 0;
       auto row = [&](int j) {
-        const R dj = dg[j], ej = e2[j - 1];
-        qa = fma(-ej, rcp_nr(qa), dj - xa);
-        qb = fma(-ej, rcp_nr(qb), dj - xb);
-        if (fabs(qa) < pivmin) qa = -pivmin;
-        if (fabs(qb) < pivmin) qb = -pivmin;
-        ca += qa < R(0) ? 1 : 0;
-        cb += qb < R(0) ? 1 : 0;
+        const C dj = de[j];
+        const bool in = j < n;
+        const R fa = in ? dj.x - xa : R(1), fb = in ? dj.x - xb : R(1);
+        const R pa = fma(fa, pa1, -dj.y * pa2), pb = fma(fb, pb1, -dj.y * pb2);
+        const bool ma = pa < R(0), mb = pb < R(0);
+        ca += ma != na ? 1 : 0;
+        cb += mb != nb ? 1 : 0;
+        na = ma;
+        nb = mb;
+        pa2 = pa1;
+        pb2 = pb1;
+        pa1 = pa;
+        pb1 = pb;
+        if ((j & 3) == 3) {
+          const R sa = fabs(pa1) > kBig ? kSmall : (fabs(pa1) < kSmall ? kBig : R(1));
+          const R sb = fabs(pb1) > kBig ? kSmall : (fabs(pb1) < kSmall ? kBig : R(1));
+          pa1 *= sa;
+          pa2 *= sa;
+          pb1 *= sb;
+          pb2 *= sb;
+        }
       };
       if constexpr (M <= 16) {
 #pragma unroll
         for (int j = 1; j < M; ++j) row(j);
       } else {
-        // rolled: a fully unrolled pass would hold d and e in registers
-#pragma unroll 1
+#pragma unroll 4
         for (int j = 1; j < n; ++j) row(j);
       }
     }
