@@ -360,20 +360,27 @@ __device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
     const bool ok = d > R(0);
     const R dinv = ok ? rcp_(d) : R(1);
     if (t == 0 && !ok && sh.flag[g][0] == 0) sh.flag[g][0] = j + 1;
-    C xv[W], wv[W];
-    LHF_FOR_ENTRIES {
-      xv[k] = sh.B[g][r][c];
-      wv[k] = Wm[r][c];
+    // entries right of column j update B, the others W; the W entries of a
+    // thread share column t % M (TPM is a multiple of M), so row j's entry of
+    // that column is read once
+    const int c = t % M;
+    const C pj = c > j ? sh.B[g][j][c] : Wm[j][c];
+    C xv[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int r = (t + k * TPM) / M;
+      xv[k] = cmk<C>(R(0), R(0));
       if (r > j) {
         const C f = cscale(sh.B[g][r][j], dinv);
-        if (c > j) xv[k] = csub(xv[k], cmul(f, sh.B[g][j][c]));
-        else wv[k] = csub(wv[k], cmul(f, Wm[j][c]));
+        xv[k] = csub(c > j ? sh.B[g][r][c] : Wm[r][c], cmul(f, pj));
       }
     }
-    LHF_FOR_ENTRIES {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int r = (t + k * TPM) / M;
       if (r > j) {
         if (c > j) sh.B[g][r][c] = xv[k];
-        else Wm[r][c] = wv[k];
+        else Wm[r][c] = xv[k];
       }
     }
     __syncthreads();
@@ -726,12 +733,18 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
 #pragma unroll
       for (int w = 0; w < NWM; ++w) ks += part[w];
       const R kk = R(0.5) * beta * ks;
-      LHF_FOR_ENTRIES {
-        if (r > h && r < n && c > h && c < n) {
-          const C ur = uv[r], uc = uv[c];
-          const C qr = csub(qv[r], cscale(ur, kk)), qc = csub(qv[c], cscale(uc, kk));
-          // A_rc -= u_r conj(q_c) + q_r conj(u_c)
-          sh.A[g][r][c] = csub(sh.A[g][r][c], cadd(cmulc(qc, ur), cmulc(uc, qr)));
+      // the W entries of a thread share column t % M (TPM is a multiple of M)
+      const int c = t % M;
+      if (c > h && c < n) {
+        const C uc = uv[c], qc = csub(qv[c], cscale(uc, kk));
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const int r = (t + k * TPM) / M;
+          if (r > h && r < n) {
+            const C ur = uv[r], qr = csub(qv[r], cscale(ur, kk));
+            // A_rc -= u_r conj(q_c) + q_r conj(u_c)
+            sh.A[g][r][c] = csub(sh.A[g][r][c], cadd(cmulc(qc, ur), cmulc(uc, qr)));
+          }
         }
       }
     }
