@@ -643,6 +643,27 @@ __device__ void eig_rank(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int m, int
   __syncthreads();
 }
 
+// FP64 lane moves within a 16-lane row (DPP control CTRL) and an all-reduce
+// over aligned groups of P lanes (P a power of two <= 64): quad permutes pair
+// i with i^1 and i^2, then the mirrors i <-> 7-i and i <-> 15-i join two
+// halves that are already reduced; lane shuffles only across rows.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int P, typename F>
+__device__ __forceinline__ double lane_reduce(double v, F op) {
+  if constexpr (P >= 2) v = op(v, dpp_move<0xB1>(v));    // quad_perm [1, 0, 3, 2]
+  if constexpr (P >= 4) v = op(v, dpp_move<0x4E>(v));    // quad_perm [2, 3, 0, 1]
+  if constexpr (P >= 8) v = op(v, dpp_move<0x141>(v));   // row_half_mirror
+  if constexpr (P >= 16) v = op(v, dpp_move<0x140>(v));  // row_mirror
+  if constexpr (P >= 32) v = op(v, __shfl_xor(v, 16, 64));
+  if constexpr (P >= 64) v = op(v, __shfl_xor(v, 32, 64));
+  return v;
+}
+
 // 3'-4'. Eigenvalues only: Householder reduction of the Hermitian A (its
 // leading n x n block) to tridiagonal form, then bisection on Sturm counts.
 // Step h reflects rows and columns h+1..n-1 with P = I - beta u u^H,
@@ -672,25 +693,28 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
   R* e2 = sh.dn[g];         // squared subdiagonal moduli
   C* de = &sh.B[g][2][0];   // (d_j, e_(j-1)^2) per row, one LDS word for the Sturm pass
   const int gi = t / P, gc = t % P;   // row group and lane within it
-  // reductions: over the TPM lanes of the matrix, or per wavefront of it
+  auto add = [](double x, double y) { return x + y; };
+  // u^H p: M <= 16 publishes Re(conj(u_i) p_i) per row and every thread sums
+  // the rows; M = 32 reduces per wavefront (fewer LDS reads for 256 threads)
+  constexpr bool kRows = M <= 16;
   constexpr int WV = TPM < 64 ? TPM : 64, NWM = TPM < 64 ? 1 : TPM / 64;
   static_assert(NWM <= 16, "per-wave partials fit the reduction array");
-  R* part = sh.red[g];      // per-wave partial sums of Re(u^H p)
+  R* upv = dg;              // per-row terms (d is written after the loop)
+  R* part = sh.red[g];      // per-wave partial sums
   R* bsh = &sh.lam[g][0];   // beta of the current step (lam is written after the loop)
-  // three barriers per step: u and beta published; p and the partials of
-  // u^H p published; trailing block updated with q = p - K u formed in place
+  // three barriers per step: u and beta published; p and Re(conj(u_i) p_i)
+  // published per row; trailing block updated with q = p - K u formed in place
 #pragma unroll 1
   for (int h = 0; h < M - 2; ++h) {
     const bool act = h < n - 2;
-    // the column below the diagonal sits in lanes t < n <= 32 of the first wave
+    // the column below the diagonal sits in lanes t < n <= M of the first wave
     R x2 = R(0);
     if (act && t > h + 1 && t < n) {
       const C x = sh.A[g][t][h];
       x2 = x.x * x.x + x.y * x.y;
     }
-#pragma unroll
-    for (int o = WV / 2; o > 0; o >>= 1) x2 += __shfl_xor(x2, o, 64);
-    if (t < WV) {
+    x2 = lane_reduce<M>(x2, add);
+    if (t < M) {
       const C al = act ? sh.A[g][h + 1][h] : cmk<C>(R(0), R(0));
       const R a2 = al.x * al.x + al.y * al.y;
       const R a = sqrt(a2), nrm = sqrt(a2 + x2);
@@ -712,26 +736,36 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
       for (int j = gc; j < M; j += P)
         if (j > h && j < n) acc = cadd(acc, cmul(sh.A[g][gi][j], uv[j]));
     }
-#pragma unroll
-    for (int o = P / 2; o > 0; o >>= 1) {
-      acc.x += __shfl_xor(acc.x, o, 64);
-      acc.y += __shfl_xor(acc.y, o, 64);
-    }
+    acc.x = lane_reduce<P>(acc.x, add);
+    acc.y = lane_reduce<P>(acc.y, add);
     acc = cscale(acc, beta);
     R up = R(0);
     if (row && gc == 0) {
       const C ui = uv[gi];
       up = ui.x * acc.x + ui.y * acc.y;   // Re(conj(u_i) p_i)
+      if constexpr (kRows) upv[gi] = up;
       qv[gi] = acc;                       // p
     }
-#pragma unroll
-    for (int o = WV / 2; o > 0; o >>= 1) up += __shfl_xor(up, o, 64);
-    if ((t & (WV - 1)) == 0) part[t / WV] = up;
+    if constexpr (!kRows) {
+      up = lane_reduce<WV>(up, add);
+      if ((t & (WV - 1)) == 0) part[t / WV] = up;
+    }
     __syncthreads();
     if (beta != R(0)) {
       R ks = R(0);
+      if constexpr (kRows) {
+        // every entry read (stale ones deselected), four partial sums
+        R ks4[4] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-      for (int w = 0; w < NWM; ++w) ks += part[w];
+        for (int i = 0; i < M; ++i) {
+          const R v = upv[i];
+          ks4[i & 3] += i > h && i < n ? v : R(0);
+        }
+        ks = (ks4[0] + ks4[1]) + (ks4[2] + ks4[3]);
+      } else {
+#pragma unroll
+        for (int w = 0; w < NWM; ++w) ks += part[w];
+      }
       const R kk = R(0.5) * beta * ks;
       // the W entries of a thread share column t % M (TPM is a multiple of M)
       const int c = t % M;
@@ -776,6 +810,16 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
   hi += widen;
   __syncthreads();
   const bool live = gi < n;
+  // (d_j, e_(j-1)^2) in registers for M <= 16, read from LDS per row for M = 32
+  constexpr int ND = M <= 16 ? M : 1;
+  C drr[ND];
+  if constexpr (M <= 16) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) drr[j] = de[j];
+  }
+  auto dr_at = [&](int j) -> C {
+    if constexpr (M <= 16) return drr[j]; else return de[j];
+  };
   const R stepa = R(2 * gc + 1) / R(2 * P + 1), stepb = R(2 * gc + 2) / R(2 * P + 1);
   constexpr R kBig = R(1.157920892373162e77), kSmall = R(8.636168555094445e-78);   // 2^256, 2^-256
 #pragma unroll 1
@@ -785,13 +829,13 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
     const R xa = lo + (hi - lo) * stepa, xb = lo + (hi - lo) * stepb;
     int ca = 0, cb = 0;
     if (live) {
-      const C d0 = de[0];
+      const C d0 = dr_at(0);
       R pa2 = R(1), pb2 = R(1), pa1 = d0.x - xa, pb1 = d0.x - xb;
       bool na = pa1 < R(0), nb = pb1 < R(0);
       ca = na ? 1 : 0;
       cb = nb ? 1 : 0;
       auto row = [&](int j) {
-        const C dj = de[j];
+        const C dj = dr_at(j);
         const bool in = j < n;
         const R fa = in ? dj.x - xa : R(1), fb = in ? dj.x - xb : R(1);
         const R pa = fma(fa, pa1, -dj.y * pa2), pb = fma(fb, pb1, -dj.y * pb2);
@@ -824,11 +868,8 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
     R lc = lo, hc = hi;
     if (ca <= gi) lc = xa; else hc = xa;
     if (cb <= gi) lc = fmax(lc, xb); else hc = fmin(hc, xb);
-#pragma unroll
-    for (int o = P / 2; o > 0; o >>= 1) {
-      lc = fmax(lc, __shfl_xor(lc, o, 64));
-      hc = fmin(hc, __shfl_xor(hc, o, 64));
-    }
+    lc = lane_reduce<P>(lc, [](double x, double y) { return fmax(x, y); });
+    hc = lane_reduce<P>(hc, [](double x, double y) { return fmin(x, y); });
     if (!conv) {
       lo = lc;
       hi = hc;
