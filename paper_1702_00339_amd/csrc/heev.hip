@@ -390,20 +390,48 @@ __device__ void chol_reduce(Smem<R, M, G, HASU, HASV>& sh, int g, int t) {
     sh.dsc[g][t] = d > R(0) ? rsq_(d) : R(1);
     if (t == M - 1 && !(d > R(0)) && sh.flag[g][0] == 0) sh.flag[g][0] = M;
   }
-  int ti, tj;
-  tile_coords<M, NT>(t, ti, tj);
-  C p[NT][NT];
-  mm_tile_rh<M, NT>(sh.A[g], Wm, ti, tj, p);   // T = A W^H
-  __syncthreads();
-  store_tile<M, NT>(sh.A[g], ti, tj, p);
-  __syncthreads();
-  mm_tile<M, NT, false>(Wm, sh.A[g], ti, tj, R(0), p);   // W T, scaled by D^-1/2 on both sides
+  if constexpr (sizeof(R) == 8 && M >= 16 && G == 1) {
+    // FP64 matrix cores, one 16 x 16 tile per wavefront: W A, stored as its
+    // conjugate transpose A W^H (A Hermitian), then W (A W^H) scaled by
+    // D^-1/2 on both sides
+    const MfTile<M> mft;
+    mf4 re, im;
+    if (mft.on) mf_product<M, false>(mft, Wm, sh.A[g], re, im);
+    __syncthreads();
+    if (mft.on) {
 #pragma unroll
-  for (int a = 0; a < NT; ++a)
+      for (int v = 0; v < 4; ++v) {
+        const int r = mft.r0 + mft.lk + 4 * v, c = mft.c0 + mft.lr;
+        sh.A[g][c][r] = cmk<C>(re[v], -im[v]);
+      }
+    }
+    __syncthreads();
+    if (mft.on) {
+      mf_product<M, false>(mft, Wm, sh.A[g], re, im);
 #pragma unroll
-    for (int b = 0; b < NT; ++b) p[a][b] = cscale(p[a][b], sh.dsc[g][ti + a * S] * sh.dsc[g][tj + b * S]);
-  store_tile<M, NT>(sh.B[g], ti, tj, p);
-  __syncthreads();
+      for (int v = 0; v < 4; ++v) {
+        const int r = mft.r0 + mft.lk + 4 * v, c = mft.c0 + mft.lr;
+        const R sc = sh.dsc[g][r] * sh.dsc[g][c];
+        sh.B[g][r][c] = cmk<C>(re[v] * sc, im[v] * sc);
+      }
+    }
+    __syncthreads();
+  } else {
+    int ti, tj;
+    tile_coords<M, NT>(t, ti, tj);
+    C p[NT][NT];
+    mm_tile_rh<M, NT>(sh.A[g], Wm, ti, tj, p);   // T = A W^H
+    __syncthreads();
+    store_tile<M, NT>(sh.A[g], ti, tj, p);
+    __syncthreads();
+    mm_tile<M, NT, false>(Wm, sh.A[g], ti, tj, R(0), p);   // W T, scaled by D^-1/2 on both sides
+#pragma unroll
+    for (int a = 0; a < NT; ++a)
+#pragma unroll
+      for (int b = 0; b < NT; ++b) p[a][b] = cscale(p[a][b], sh.dsc[g][ti + a * S] * sh.dsc[g][tj + b * S]);
+    store_tile<M, NT>(sh.B[g], ti, tj, p);
+    __syncthreads();
+  }
   LHF_FOR_ENTRIES {
     const C x = sh.B[g][r][c], y = sh.B[g][c][r];
     C s = cmk<C>(R(0.5) * (x.x + y.x), R(0.5) * (x.y - y.y));
