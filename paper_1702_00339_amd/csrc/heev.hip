@@ -33,6 +33,7 @@
 // overlap, zero Hamiltonian) and never written out.  Workgroups hold 64/(M/2)^2
 // matrices for M <= 16 (one wavefront) and one matrix for M = 32.
 #include <algorithm>
+#include <type_traits>
 
 #include "plan.h"
 
@@ -862,7 +863,10 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
       bool na = pa1 < R(0), nb = pb1 < R(0);
       ca = na ? 1 : 0;
       cb = nb ? 1 : 0;
-      auto row = [&](int j) {
+      // row j of the pass; rescale after rows 3, 7, 11, ... (RS: j % 4 == 3,
+      // known at compile time in every caller)
+      auto row = [&](int j, auto rs) {
+        constexpr bool RS = decltype(rs)::value;
         const C dj = dr_at(j);
         const bool in = j < n;
         const R fa = in ? dj.x - xa : R(1), fb = in ? dj.x - xb : R(1);
@@ -876,7 +880,7 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
         pb2 = pb1;
         pa1 = pa;
         pb1 = pb;
-        if ((j & 3) == 3) {
+        if constexpr (RS) {
           const R sa = fabs(pa1) > kBig ? kSmall : (fabs(pa1) < kSmall ? kBig : R(1));
           const R sb = fabs(pb1) > kBig ? kSmall : (fabs(pb1) < kSmall ? kBig : R(1));
           pa1 *= sa;
@@ -885,12 +889,29 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
           pb2 *= sb;
         }
       };
+      using RsYes = std::integral_constant<bool, true>;
+      using RsNo = std::integral_constant<bool, false>;
+      // rows 1-3, then blocks of four rows with the rescale after the last
+      row(1, RsNo{});
+      row(2, RsNo{});
+      row(3, RsYes{});
       if constexpr (M <= 16) {
 #pragma unroll
-        for (int j = 1; j < M; ++j) row(j);
+        for (int jb = 4; jb < M; jb += 4) {
+          row(jb, RsNo{});
+          row(jb + 1, RsNo{});
+          row(jb + 2, RsNo{});
+          row(jb + 3, RsYes{});
+        }
       } else {
-#pragma unroll 4
-        for (int j = 1; j < n; ++j) row(j);
+        // rolled over blocks (d and e come from LDS); rows past n count nothing
+#pragma unroll 1
+        for (int jb = 4; jb < M; jb += 4) {
+          row(jb, RsNo{});
+          row(jb + 1, RsNo{});
+          row(jb + 2, RsNo{});
+          row(jb + 3, RsYes{});
+        }
       }
     }
     R lc = lo, hc = hi;
