@@ -708,9 +708,10 @@ __device__ __forceinline__ double lane_reduce(double v, F op) {
 // number of sign changes of the leading minors p_j of T - x I, from the
 // division-free recurrence p_j = (d_j - x) p_(j-1) - e_(j-1)^2 p_(j-2) (a zero
 // taken as positive, which counts as the ratio form with small pivots made
-// negative does), rescaled by 2^-+256 every fourth row against overflow and
-// underflow (exact, sign-preserving).  Each lane runs two sequences at once
-// (2 P + 1 sections per pass).  The eigenvalues land sorted: rank i = i.
+// negative does), on T scaled by a power of two to norm below 1 and rescaled
+// by 2^-+256 every eighth row against overflow and underflow (exact,
+// sign-preserving).  Each lane runs two sequences at once (2 P + 1 sections
+// per pass).  The eigenvalues land sorted: rank i = i.
 template <int W, typename R, int M, int G, bool HASU, bool HASV>
 __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n) {
   typedef typename Cx<R>::T C;
@@ -819,9 +820,6 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
     e2[n - 2] = b.x * b.x + b.y * b.y;
   }
   __syncthreads();
-  // rows past n (M <= 16 passes run over all M rows) get e^2 = 0 and, in
-  // the pass, the factor 1 in place of d_j - x: p_j = p_(j-1), no change
-  if (t < M) de[t] = t < n ? cmk<C>(dg[t], t > 0 ? e2[t - 1] : R(0)) : cmk<C>(R(0), R(0));
   // Gershgorin interval of the tridiagonal matrix
   constexpr R eps = R(1.1102230246251565e-16);
   R lo = R(0), hi = R(0), emax = R(0);
@@ -832,11 +830,23 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
     hi = j == 0 ? u : fmax(hi, u);
     if (j < n - 1) emax = fmax(emax, e2[j]);
   }
+  // the pass runs on T scaled by sc = 2^-ex (exact), |T| < 1, so the minors
+  // grow at most 3x per row and a rescale every eighth row suffices
+  int ex = 0;
+  (void)frexp(fmax(fabs(lo), fabs(hi)), &ex);
+  const R sc = ldexp(R(1), -ex);
+  lo *= sc;
+  hi *= sc;
+  emax *= sc * sc;
   const R tnorm = fmax(fabs(lo), fabs(hi));
   const R tiny = R(2.2250738585072014e-308) * fmax(R(1), emax);   // absolute floor of the widths
   const R widen = R(4) * R(n) * eps * tnorm + R(2) * tiny;
   lo -= widen;
   hi += widen;
+  // rows past n: d beyond the interval (d - x > 0, bounded) and e = 0, so
+  // they change no sign and the pass runs over all M rows without selects
+  const R dpad = R(2) * fmax(fabs(lo), fabs(hi)) + R(1);
+  if (t < M) de[t] = t < n ? cmk<C>(dg[t] * sc, t > 0 ? e2[t - 1] * sc * sc : R(0)) : cmk<C>(dpad, R(0));
   __syncthreads();
   const bool live = gi < n;
   // (d_j, e_(j-1)^2) in registers for M <= 16, read from LDS per row for M = 32
@@ -863,14 +873,12 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
       bool na = pa1 < R(0), nb = pb1 < R(0);
       ca = na ? 1 : 0;
       cb = nb ? 1 : 0;
-      // row j of the pass; rescale after rows 3, 7, 11, ... (RS: j % 4 == 3,
+      // row j of the pass; rescale after rows 7, 15, 23, ... (RS: j % 8 == 7,
       // known at compile time in every caller)
       auto row = [&](int j, auto rs) {
         constexpr bool RS = decltype(rs)::value;
         const C dj = dr_at(j);
-        const bool in = j < n;
-        const R fa = in ? dj.x - xa : R(1), fb = in ? dj.x - xb : R(1);
-        const R pa = fma(fa, pa1, -dj.y * pa2), pb = fma(fb, pb1, -dj.y * pb2);
+        const R pa = fma(dj.x - xa, pa1, -dj.y * pa2), pb = fma(dj.x - xb, pb1, -dj.y * pb2);
         const bool ma = pa < R(0), mb = pb < R(0);
         ca += ma != na ? 1 : 0;
         cb += mb != nb ? 1 : 0;
@@ -891,27 +899,33 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
       };
       using RsYes = std::integral_constant<bool, true>;
       using RsNo = std::integral_constant<bool, false>;
-      // rows 1-3, then blocks of four rows with the rescale after the last
+      // rows 1 to min(M, 8) - 1, then blocks of eight rows with the rescale
+      // after the last (rows past n count nothing)
       row(1, RsNo{});
       row(2, RsNo{});
-      row(3, RsYes{});
-      if constexpr (M <= 16) {
-#pragma unroll
-        for (int jb = 4; jb < M; jb += 4) {
-          row(jb, RsNo{});
-          row(jb + 1, RsNo{});
-          row(jb + 2, RsNo{});
-          row(jb + 3, RsYes{});
-        }
-      } else {
-        // rolled over blocks (d and e come from LDS); rows past n count nothing
+      row(3, RsNo{});
+      if constexpr (M >= 8) {
+        row(4, RsNo{});
+        row(5, RsNo{});
+        row(6, RsNo{});
+        row(7, RsYes{});
+      }
+      auto block8 = [&](int jb) {
+        row(jb, RsNo{});
+        row(jb + 1, RsNo{});
+        row(jb + 2, RsNo{});
+        row(jb + 3, RsNo{});
+        row(jb + 4, RsNo{});
+        row(jb + 5, RsNo{});
+        row(jb + 6, RsNo{});
+        row(jb + 7, RsYes{});
+      };
+      if constexpr (M == 16) {
+        block8(8);
+      } else if constexpr (M > 16) {
+        // rolled over blocks (d and e come from LDS)
 #pragma unroll 1
-        for (int jb = 4; jb < M; jb += 4) {
-          row(jb, RsNo{});
-          row(jb + 1, RsNo{});
-          row(jb + 2, RsNo{});
-          row(jb + 3, RsYes{});
-        }
+        for (int jb = 8; jb < M; jb += 8) block8(jb);
       }
     }
     R lc = lo, hc = hi;
@@ -925,7 +939,7 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
     }
   }
   if (live && gc == 0) {
-    sh.lam[g][gi] = R(0.5) * (lo + hi);
+    sh.lam[g][gi] = ldexp(R(0.5) * (lo + hi), ex);
     sh.rank[g][gi] = gi;
   }
   if (t == 0) sh.flag[g][2] = 1;
