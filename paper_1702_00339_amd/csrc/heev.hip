@@ -737,41 +737,58 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
 #pragma unroll 1
   for (int h = 0; h < M - 2; ++h) {
     const bool act = h < n - 2;
-    // the column below the diagonal sits in lanes t < n <= M of the first wave
-    R x2 = R(0);
-    if (act && t > h + 1 && t < n) {
-      const C x = sh.A[g][t][h];
-      x2 = x.x * x.x + x.y * x.y;
-    }
+    // the column below the diagonal sits in lanes t < n <= M of the first
+    // wave; every LDS read of the phase is issued before any use
+    const C xv = sh.A[g][t < M ? t : 0][h];
+    const C al0 = sh.A[g][h + 1][h];
+    R x2 = act && t > h + 1 && t < n ? xv.x * xv.x + xv.y * xv.y : R(0);
     x2 = lane_reduce<M>(x2, add);
     if (t < M) {
-      const C al = act ? sh.A[g][h + 1][h] : cmk<C>(R(0), R(0));
+      const C al = act ? al0 : cmk<C>(R(0), R(0));
       const R a2 = al.x * al.x + al.y * al.y;
       const R a = sqrt(a2), nrm = sqrt(a2 + x2);
       const R beta = act && x2 > R(0) ? R(1) / (nrm * (nrm + a)) : R(0);
       const C ph = a > R(0) ? cscale(al, R(1) / a) : cmk<C>(R(1), R(0));
-      if (act && t > h && t < n) uv[t] = t == h + 1 ? cscale(ph, a + nrm) : sh.A[g][t][h];
+      if (act && t > h && t < n) uv[t] = t == h + 1 ? cscale(ph, a + nrm) : xv;
       if (t == 0) {
         bsh[0] = beta;
         if (act) e2[h] = a2 + x2;
       }
     }
     __syncthreads();
+    // p_i = beta sum_j A_ij u_j, row i by the P lanes of group i; the loads
+    // are issued with beta's (entries outside the block are masked after)
     const R beta = bsh[0];
-    // p_i = beta sum_j A_ij u_j, row i by the P lanes of group i
     const bool row = beta != R(0) && gi > h && gi < n;
     C acc = cmk<C>(R(0), R(0));
-    if (row) {
+    C ui = cmk<C>(R(0), R(0));
+    if constexpr (M <= 16) {
+      C arow[M / P], urow[M / P];
+#pragma unroll
+      for (int jj = 0; jj < M / P; ++jj) {
+        arow[jj] = sh.A[g][gi][gc + jj * P];
+        urow[jj] = uv[gc + jj * P];
+      }
+      ui = uv[gi];
+#pragma unroll
+      for (int jj = 0; jj < M / P; ++jj) {
+        const int j = gc + jj * P;
+        const C pr = cmul(arow[jj], urow[jj]);
+        if (j > h && j < n) acc = cadd(acc, pr);
+      }
+      if (!row) acc = cmk<C>(R(0), R(0));
+    } else if (row) {
+      // M = 32 keeps its registers for occupancy
 #pragma unroll
       for (int j = gc; j < M; j += P)
         if (j > h && j < n) acc = cadd(acc, cmul(sh.A[g][gi][j], uv[j]));
+      ui = uv[gi];
     }
     acc.x = lane_reduce<P>(acc.x, add);
     acc.y = lane_reduce<P>(acc.y, add);
     acc = cscale(acc, beta);
     R up = R(0);
     if (row && gc == 0) {
-      const C ui = uv[gi];
       up = ui.x * acc.x + ui.y * acc.y;   // Re(conj(u_i) p_i)
       if constexpr (kRows) upv[gi] = up;
       qv[gi] = acc;                       // p
@@ -799,14 +816,35 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n)
       const R kk = R(0.5) * beta * ks;
       // the W entries of a thread share column t % M (TPM is a multiple of M)
       const int c = t % M;
-      if (c > h && c < n) {
+      if constexpr (M <= 16) {
+        // every read issued first (M = 32 keeps its registers for occupancy)
+        const C uc = uv[c], qc = csub(qv[c], cscale(uc, kk));
+        C ur[W], pr[W], ar[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          const int r = (t + k * TPM) / M;
+          ur[k] = uv[r];
+          pr[k] = qv[r];
+          ar[k] = sh.A[g][r][c];
+        }
+        if (c > h && c < n) {
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            const int r = (t + k * TPM) / M;
+            if (r > h && r < n) {
+              const C qr = csub(pr[k], cscale(ur[k], kk));
+              // A_rc -= u_r conj(q_c) + q_r conj(u_c)
+              sh.A[g][r][c] = csub(ar[k], cadd(cmulc(qc, ur[k]), cmulc(uc, qr)));
+            }
+          }
+        }
+      } else if (c > h && c < n) {
         const C uc = uv[c], qc = csub(qv[c], cscale(uc, kk));
 #pragma unroll
         for (int k = 0; k < W; ++k) {
           const int r = (t + k * TPM) / M;
           if (r > h && r < n) {
             const C ur = uv[r], qr = csub(qv[r], cscale(ur, kk));
-            // A_rc -= u_r conj(q_c) + q_r conj(u_c)
             sh.A[g][r][c] = csub(sh.A[g][r][c], cadd(cmulc(qc, ur), cmulc(uc, qr)));
           }
         }
