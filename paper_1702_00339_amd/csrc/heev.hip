@@ -77,14 +77,15 @@ __device__ __forceinline__ int conj_block(const LatDev& L, int b) {
   return (c1 * L.L[1] + c2) * L.L[2] + c3;
 }
 
-template <typename R, int M, int G, bool HASU, bool HASV>
+template <typename R, int M, int G, bool HASU, bool HASV, bool NOF = false>
 struct Smem {
   typedef typename Cx<R>::T C;
   // F (the reduction's W, the refinement's series) is absent in the
   // refinement without vectors for M >= 16, which keeps those in the dead U
   // instead (more resident matrices; at M <= 8 the fourth matrix costs less
-  // than the extra passes)
-  static constexpr bool HASF = HASV || !HASU || M <= 8;
+  // than the extra passes), and in the FP64 eigenvalue solve at M = 32
+  // (NOF), which keeps W in the upper triangle of B
+  static constexpr bool HASF = !NOF && (HASV || !HASU || M <= 8);
   C A[G][M][M + 1];
   C B[G][M][M + 1];
   C F[HASF ? G : 1][HASF ? M : 1][M + 1];
@@ -693,6 +694,117 @@ __device__ __forceinline__ double lane_reduce(double v, F op) {
   return v;
 }
 
+// (re, im) = W Y with the unit lower triangular W held in the strictly upper
+// triangle of B (W_rk at B[k][r], r > k)
+template <int M>
+__device__ __forceinline__ void mf_product_wup(const MfTile<M>& f, const double2 (&B)[M][M + 1],
+                                               const double2 (&Y)[M][M + 1], mf4& re, mf4& im) {
+  re = mf4{0.0, 0.0, 0.0, 0.0};
+  im = mf4{0.0, 0.0, 0.0, 0.0};
+  const int r = f.r0 + f.lr;
+#pragma unroll
+  for (int k0 = 0; k0 < M; k0 += 4) {
+    const int k = k0 + f.lk;
+    const double2 b = B[k][r];
+    const double2 x = r == k ? make_double2(1.0, 0.0) : (r > k ? b : make_double2(0.0, 0.0));
+    const double2 y = Y[k][f.c0 + f.lr];
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-x.y, y.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, y.x, im, 0, 0, 0);
+  }
+}
+
+// 1-2'. Reduction to standard form without the W array (FP64, one matrix per
+// workgroup): the same elimination as chol_reduce, run on the lower triangle
+// of B (the trailing block stays Hermitian, so row j right of the diagonal is
+// the conjugate of column j below it), with W = L^-1 kept in the strictly
+// upper triangle of B (W_rc, r > c, at B[c][r]; the unit diagonal implied).
+// Within step j the lower entries of columns > j and the upper entries of
+// columns > j are written while column j is read: no entry is both.  Then
+// A <- D^-1/2 W A W^H D^-1/2 on the matrix cores as in chol_reduce, with a
+// barrier before B is overwritten by the product.
+template <int W, int M>
+__device__ void chol_reduce_wup(Smem<double, M, 1, false, false, true>& sh, int t) {
+  typedef double2 C;
+  typedef double R;
+  constexpr int TPM = M * M / W;
+  auto& B = sh.B[0];
+  auto& A = sh.A[0];
+  LHF_FOR_ENTRIES {
+    if (c > r) B[r][c] = cmk<C>(R(0), R(0));   // W = I below the diagonal
+  }
+  __syncthreads();
+  const int c = t % M;   // the W entries of a thread share this column
+#pragma unroll 1
+  for (int j = 0; j < M - 1; ++j) {
+    const R d = B[j][j].x;
+    const bool ok = d > R(0);
+    const R dinv = ok ? rcp_(d) : R(1);
+    if (t == 0 && !ok && sh.flag[0][0] == 0) sh.flag[0][0] = j + 1;
+    // row j of [B | W] in column c: conj(B[c][j]) right of the diagonal, W_jc left of it
+    const C bc = B[c][j];
+    const C pj = c > j ? cconj(bc) : (c == j ? cmk<C>(R(1), R(0)) : bc);
+    C xv[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int r = (t + k * TPM) / M;
+      xv[k] = cmk<C>(R(0), R(0));
+      if (r > j && (c <= j || c <= r)) {
+        const C f = cscale(B[r][j], dinv);
+        xv[k] = csub(c > j ? B[r][c] : B[c][r], cmul(f, pj));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int r = (t + k * TPM) / M;
+      if (r > j) {
+        if (c > j) {
+          if (c <= r) B[r][c] = xv[k];
+        } else {
+          B[c][r] = xv[k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (t < M) {
+    const R d = B[t][t].x;
+    sh.dsc[0][t] = d > R(0) ? rsq_(d) : R(1);
+    if (t == M - 1 && !(d > R(0)) && sh.flag[0][0] == 0) sh.flag[0][0] = M;
+  }
+  const MfTile<M> mft;
+  mf4 re, im;
+  if (mft.on) mf_product_wup<M>(mft, B, A, re, im);   // W A
+  __syncthreads();
+  if (mft.on) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = mft.r0 + mft.lk + 4 * v, cc = mft.c0 + mft.lr;
+      A[cc][r] = cmk<C>(re[v], -im[v]);   // (W A)^H = A W^H
+    }
+  }
+  __syncthreads();
+  if (mft.on) mf_product_wup<M>(mft, B, A, re, im);   // W A W^H
+  __syncthreads();                                   // every read of W in B done
+  if (mft.on) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = mft.r0 + mft.lk + 4 * v, cc = mft.c0 + mft.lr;
+      const R sc = sh.dsc[0][r] * sh.dsc[0][cc];
+      B[r][cc] = cmk<C>(re[v] * sc, im[v] * sc);
+    }
+  }
+  __syncthreads();
+  LHF_FOR_ENTRIES {
+    const C x = B[r][c], y = B[c][r];
+    C s2 = cmk<C>(R(0.5) * (x.x + y.x), R(0.5) * (x.y - y.y));
+    if (r == c) s2.y = R(0);
+    A[r][c] = s2;
+  }
+  __syncthreads();
+}
+
 // 3'-4'. Eigenvalues only: Householder reduction of the Hermitian A (its
 // leading n x n block) to tridiagonal form, then bisection on Sturm counts.
 // Step h reflects rows and columns h+1..n-1 with P = I - beta u u^H,
@@ -712,8 +824,8 @@ __device__ __forceinline__ double lane_reduce(double v, F op) {
 // by 2^-+256 every eighth row against overflow and underflow (exact,
 // sign-preserving).  Each lane runs two sequences at once (2 P + 1 sections
 // per pass).  The eigenvalues land sorted: rank i = i.
-template <int W, typename R, int M, int G, bool HASU, bool HASV>
-__device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int n) {
+template <int W, typename R, int M, int G, bool HASU, bool HASV, bool NOF>
+__device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, int n) {
   typedef typename Cx<R>::T C;
   constexpr int TPM = M * M / W, P = TPM / M;
   static_assert(P >= 1 && (P & (P - 1)) == 0 && P <= 64, "row group of one wavefront");
@@ -1021,7 +1133,10 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatD
   typedef typename Cx<R>::T C;
   constexpr int G = Shape<M, W>::G, TPM = Shape<M, W>::TPM;
   constexpr bool WANTV = VMODE != 0;
-  __shared__ Smem<R, M, G, false, WANTV> sh;
+  // FP64 eigenvalues at M = 32: W in the upper triangle of B (no F array), so
+  // four workgroups fit a CU's LDS instead of three
+  constexpr bool NOF = VMODE == 0 && sizeof(R) == 8 && M == 32 && G == 1;
+  __shared__ Smem<R, M, G, false, WANTV, NOF> sh;
   const int g = threadIdx.x / TPM, t = threadIdx.x % TPM;
   const int slot = blockIdx.x * G + g;
   const bool valid = slot < ncanon;
@@ -1063,7 +1178,7 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatD
   }
   if (bad) sh.flag[g][1] = 1;
   __syncthreads();
-  chol_reduce<W, false>(sh, g, t);
+  if constexpr (NOF) chol_reduce_wup<W, M>(sh, t); else chol_reduce<W, false>(sh, g, t);
   if constexpr (VMODE == 0 && sizeof(R) == 8) {
     tridiag_eigs<W>(sh, g, t, m);
   } else {
