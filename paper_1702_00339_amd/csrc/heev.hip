@@ -83,7 +83,7 @@ struct Smem {
   // F (the reduction's W, the refinement's series) is absent in the
   // refinement without vectors for M >= 16, which keeps those in the dead U
   // instead (more resident matrices; at M <= 8 the fourth matrix costs less
-  // than the extra passes), and in the FP64 eigenvalue solve at M = 32
+  // than the extra passes), and in the FP64 eigenvalue solve at M = 8, 32
   // (NOF), which keeps W in the upper triangle of B
   static constexpr bool HASF = !NOF && (HASV || !HASU || M <= 8);
   C A[G][M][M + 1];
@@ -715,22 +715,23 @@ __device__ __forceinline__ void mf_product_wup(const MfTile<M>& f, const double2
   }
 }
 
-// 1-2'. Reduction to standard form without the W array (FP64, one matrix per
-// workgroup): the same elimination as chol_reduce, run on the lower triangle
+// 1-2'. Reduction to standard form without the W array (FP64 eigenvalues):
+// the same elimination as chol_reduce, run on the lower triangle
 // of B (the trailing block stays Hermitian, so row j right of the diagonal is
 // the conjugate of column j below it), with W = L^-1 kept in the strictly
 // upper triangle of B (W_rc, r > c, at B[c][r]; the unit diagonal implied).
 // Within step j the lower entries of columns > j and the upper entries of
 // columns > j are written while column j is read: no entry is both.  Then
-// A <- D^-1/2 W A W^H D^-1/2 on the matrix cores as in chol_reduce, with a
-// barrier before B is overwritten by the product.
-template <int W, int M>
-__device__ void chol_reduce_wup(Smem<double, M, 1, false, false, true>& sh, int t) {
+// A <- D^-1/2 W A W^H D^-1/2, on the matrix cores as in chol_reduce when one
+// matrix fills the workgroup (M >= 16), else per entry on the vector units,
+// with a barrier before B is overwritten by the product.
+template <int W, int M, int G>
+__device__ void chol_reduce_wup(Smem<double, M, G, false, false, true>& sh, int g, int t) {
   typedef double2 C;
   typedef double R;
   constexpr int TPM = M * M / W;
-  auto& B = sh.B[0];
-  auto& A = sh.A[0];
+  auto& B = sh.B[g];
+  auto& A = sh.A[g];
   LHF_FOR_ENTRIES {
     if (c > r) B[r][c] = cmk<C>(R(0), R(0));   // W = I below the diagonal
   }
@@ -741,7 +742,7 @@ __device__ void chol_reduce_wup(Smem<double, M, 1, false, false, true>& sh, int 
     const R d = B[j][j].x;
     const bool ok = d > R(0);
     const R dinv = ok ? rcp_(d) : R(1);
-    if (t == 0 && !ok && sh.flag[0][0] == 0) sh.flag[0][0] = j + 1;
+    if (t == 0 && !ok && sh.flag[g][0] == 0) sh.flag[g][0] = j + 1;
     // row j of [B | W] in column c: conj(B[c][j]) right of the diagonal, W_jc left of it
     const C bc = B[c][j];
     const C pj = c > j ? cconj(bc) : (c == j ? cmk<C>(R(1), R(0)) : bc);
@@ -770,32 +771,57 @@ __device__ void chol_reduce_wup(Smem<double, M, 1, false, false, true>& sh, int 
   }
   if (t < M) {
     const R d = B[t][t].x;
-    sh.dsc[0][t] = d > R(0) ? rsq_(d) : R(1);
-    if (t == M - 1 && !(d > R(0)) && sh.flag[0][0] == 0) sh.flag[0][0] = M;
+    sh.dsc[g][t] = d > R(0) ? rsq_(d) : R(1);
+    if (t == M - 1 && !(d > R(0)) && sh.flag[g][0] == 0) sh.flag[g][0] = M;
   }
-  const MfTile<M> mft;
-  mf4 re, im;
-  if (mft.on) mf_product_wup<M>(mft, B, A, re, im);   // W A
-  __syncthreads();
-  if (mft.on) {
+  if constexpr (M >= 16 && G == 1) {
+    const MfTile<M> mft;
+    mf4 re, im;
+    if (mft.on) mf_product_wup<M>(mft, B, A, re, im);   // W A
+    __syncthreads();
+    if (mft.on) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = mft.r0 + mft.lk + 4 * v, cc = mft.c0 + mft.lr;
-      A[cc][r] = cmk<C>(re[v], -im[v]);   // (W A)^H = A W^H
+      for (int v = 0; v < 4; ++v) {
+        const int r = mft.r0 + mft.lk + 4 * v, cc = mft.c0 + mft.lr;
+        A[cc][r] = cmk<C>(re[v], -im[v]);   // (W A)^H = A W^H
+      }
     }
-  }
-  __syncthreads();
-  if (mft.on) mf_product_wup<M>(mft, B, A, re, im);   // W A W^H
-  __syncthreads();                                   // every read of W in B done
-  if (mft.on) {
+    __syncthreads();
+    if (mft.on) mf_product_wup<M>(mft, B, A, re, im);   // W A W^H
+    __syncthreads();                                   // every read of W in B done
+    if (mft.on) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = mft.r0 + mft.lk + 4 * v, cc = mft.c0 + mft.lr;
-      const R sc = sh.dsc[0][r] * sh.dsc[0][cc];
-      B[r][cc] = cmk<C>(re[v] * sc, im[v] * sc);
+      for (int v = 0; v < 4; ++v) {
+        const int r = mft.r0 + mft.lk + 4 * v, cc = mft.c0 + mft.lr;
+        const R sc = sh.dsc[g][r] * sh.dsc[g][cc];
+        B[r][cc] = cmk<C>(re[v] * sc, im[v] * sc);
+      }
     }
+    __syncthreads();
+  } else {
+    // T = A W^H (W_ck at B[k][c] for k < c), then W T (W_rk at B[k][r])
+    C tv[W];
+    LHF_FOR_ENTRIES {
+      C acc = A[r][c];
+#pragma unroll
+      for (int q = 0; q < M - 1; ++q)
+        if (q < c) acc = cadd(acc, cmul(A[r][q], cconj(B[q][c])));
+      tv[k] = acc;
+    }
+    __syncthreads();
+    LHF_FOR_ENTRIES { A[r][c] = tv[k]; }
+    __syncthreads();
+    LHF_FOR_ENTRIES {
+      C acc = A[r][c];
+#pragma unroll
+      for (int q = 0; q < M - 1; ++q)
+        if (q < r) acc = cadd(acc, cmul(B[q][r], A[q][c]));
+      tv[k] = cscale(acc, sh.dsc[g][r] * sh.dsc[g][c]);
+    }
+    __syncthreads();   // every read of W in B done
+    LHF_FOR_ENTRIES { B[r][c] = tv[k]; }
+    __syncthreads();
   }
-  __syncthreads();
   LHF_FOR_ENTRIES {
     const C x = B[r][c], y = B[c][r];
     C s2 = cmk<C>(R(0.5) * (x.x + y.x), R(0.5) * (x.y - y.y));
@@ -1133,9 +1159,10 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatD
   typedef typename Cx<R>::T C;
   constexpr int G = Shape<M, W>::G, TPM = Shape<M, W>::TPM;
   constexpr bool WANTV = VMODE != 0;
-  // FP64 eigenvalues at M = 32: W in the upper triangle of B (no F array), so
-  // four workgroups fit a CU's LDS instead of three
-  constexpr bool NOF = VMODE == 0 && sizeof(R) == 8 && M == 32 && G == 1;
+  // FP64 eigenvalues at M = 8 and 32: W in the upper triangle of B (no F
+  // array), so more workgroups fit a CU's LDS (at M = 16 registers, not LDS,
+  // bound the residency, and the full-matrix elimination is faster)
+  constexpr bool NOF = VMODE == 0 && sizeof(R) == 8 && (M == 8 || M == 32);
   __shared__ Smem<R, M, G, false, WANTV, NOF> sh;
   const int g = threadIdx.x / TPM, t = threadIdx.x % TPM;
   const int slot = blockIdx.x * G + g;
@@ -1178,7 +1205,7 @@ __global__ void __launch_bounds__((Shape<M, W>::THREADS)) heev_kernel(const LatD
   }
   if (bad) sh.flag[g][1] = 1;
   __syncthreads();
-  if constexpr (NOF) chol_reduce_wup<W, M>(sh, t); else chol_reduce<W, false>(sh, g, t);
+  if constexpr (NOF) chol_reduce_wup<W, M, G>(sh, g, t); else chol_reduce<W, false>(sh, g, t);
   if constexpr (VMODE == 0 && sizeof(R) == 8) {
     tridiag_eigs<W>(sh, g, t, m);
   } else {
