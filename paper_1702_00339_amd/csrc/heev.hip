@@ -737,13 +737,94 @@ __device__ void chol_reduce_wup(Smem<double, M, G, false, false, true>& sh, int 
   }
   __syncthreads();
   const int c = t % M;   // the W entries of a thread share this column
+  // Steps in pairs (j, j1 = j + 1), one barrier per pair: with f_r = B_rj / d_j,
+  // row j1 after step j is known to every thread from column j and j1
+  // (d1 = B_j1j1 - |B_j1j|^2 / d_j, g_r = (B_rj1 - f_r conj(B_j1j)) / d1), so
+  // rows r > j1 take both steps at once, x -= f_r p_j + g_r p_j1.  Row j1's
+  // own new entries (its W row and d1) are read in this pass by others, so
+  // they are written after the barrier, at the start of the next pass, when
+  // no one reads column j1 any more.
+  bool pend = false;
+  int pa = 0, pb = 0;
+  C pv = cmk<C>(R(0), R(0));
+  int j = 0;
 #pragma unroll 1
-  for (int j = 0; j < M - 1; ++j) {
+  for (; j + 1 < M - 1; j += 2) {
+    if (pend) {
+      B[pa][pb] = pv;
+      pend = false;
+    }
+    const int j1 = j + 1;
+    const R d = B[j][j].x;
+    const bool ok = d > R(0);
+    const R dinv = ok ? rcp_(d) : R(1);
+    const C bj1 = B[j1][j];
+    const C f1 = cscale(bj1, dinv);
+    const R d1 = B[j1][j1].x - (bj1.x * bj1.x + bj1.y * bj1.y) * dinv;
+    const bool ok1 = d1 > R(0);
+    const R d1inv = ok1 ? rcp_(d1) : R(1);
+    if (t == 0 && sh.flag[g][0] == 0) {
+      if (!ok) sh.flag[g][0] = j + 1;
+      else if (!ok1) sh.flag[g][0] = j1 + 1;
+    }
+    // rows j and j1 (after step j) of [B | W] in column c
+    const C bcj = B[c][j], bcj1 = B[c][j1];
+    C pj, pj1;
+    if (c > j1) {
+      pj = cconj(bcj);
+      pj1 = cconj(csub(bcj1, cmul(bcj, cconj(f1))));
+    } else if (c == j1) {
+      pj = cconj(bj1);
+      pj1 = cmk<C>(R(1), R(0));
+    } else if (c == j) {
+      pj = cmk<C>(R(1), R(0));
+      pj1 = cmk<C>(-f1.x, -f1.y);
+    } else {
+      pj = bcj;
+      pj1 = csub(bcj1, cmul(f1, bcj));
+    }
+    C xv[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int r = (t + k * TPM) / M;
+      xv[k] = cmk<C>(R(0), R(0));
+      if (r > j1 && (c <= j1 || c <= r)) {
+        const C fr = cscale(B[r][j], dinv);
+        const C gr = cscale(csub(B[r][j1], cmul(fr, cconj(bj1))), d1inv);
+        if (c == j1) {
+          xv[k] = cmk<C>(-gr.x, -gr.y);
+        } else {
+          xv[k] = csub(csub(c > j1 ? B[r][c] : B[c][r], cmul(fr, pj)), cmul(gr, pj1));
+        }
+      } else if (r == j1 && c <= j1) {
+        pend = true;
+        pa = c == j1 ? j1 : c;
+        pb = j1;
+        pv = c == j1 ? cmk<C>(d1, R(0)) : pj1;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const int r = (t + k * TPM) / M;
+      if (r > j1) {
+        if (c > j1) {
+          if (c <= r) B[r][c] = xv[k];
+        } else {
+          B[c][r] = xv[k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (pend) B[pa][pb] = pv;
+  __syncthreads();
+  // the last step when M - 1 is odd
+#pragma unroll 1
+  for (; j < M - 1; ++j) {
     const R d = B[j][j].x;
     const bool ok = d > R(0);
     const R dinv = ok ? rcp_(d) : R(1);
     if (t == 0 && !ok && sh.flag[g][0] == 0) sh.flag[g][0] = j + 1;
-    // row j of [B | W] in column c: conj(B[c][j]) right of the diagonal, W_jc left of it
     const C bc = B[c][j];
     const C pj = c > j ? cconj(bc) : (c == j ? cmk<C>(R(1), R(0)) : bc);
     C xv[W];
