@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # tuned route, so its entry is keyed by the mixed plan's heev_fp64 and heev_wide masks.  Valid for the
 # kernels as they were when counted; absent (reported as null) where not counted.
 TRAFFIC_KIB = {"c2": {"eig": {"fp64=4,wide=4": 655.2}, "dft": 2357.1},
-               "c3": {"eig": {"fp64=2,wide=0": 19195.7}, "sep": 69268.3},
-               "c4": {"eig": {"fp64=15,wide=1": 310853.3}, "sep": 1344549.8}}
+               "c3": {"eig": {"fp64=2,wide=0": 19202.7}, "sep": 69268.3},
+               "c4": {"eig": {"fp64=15,wide=1": 310894.1}, "sep": 1344417.7}}
 
 
 def parse():
