@@ -417,8 +417,12 @@ int32_t lhf_graph_destroy(lhf_graph_t graph);
  *                refinement (tridiagonal reduction and bisection without
  *                vectors, Jacobi with them: where rotation latency, not
  *                arithmetic, sets the FP32 solve's time, or where bisection
- *                beats Jacobi); 0..15, default 0, reads 0 on FP64 plans.  The eigenvalues of such a class meet the FP64
- *                tolerance, which is tighter than the refined one.
+ *                beats Jacobi); 0..15, default 0, reads 0 on FP64 plans.
+ *                The eigenvalues of such a class meet the FP64 tolerance,
+ *                which is tighter than the refined one;
+ *   gram_tile    output tile of one Gram work item, 64 (default) or 32 (for
+ *                launches with fewer items than the device has CUs: four
+ *                times the items).
  * Apart from heev_fp64, none of them changes what is computed; the Gram split
  * changes the order of the FP64 partial sums and the eigensolver layout the
  * order of its sums. */
@@ -430,6 +434,7 @@ typedef struct {
   int32_t heev_wide;
   int32_t fourier_sep;
   int32_t heev_fp64;
+  int32_t gram_tile;
   double step_ms;        /* autotune: mean time of one step with these settings */
   int32_t from_cache;    /* autotune: 1 when read from the cache file         */
 } lhf_tuning;

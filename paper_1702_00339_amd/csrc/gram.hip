@@ -34,7 +34,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int KC = 32;   // window nodes per LDS chunk
-constexpr int TILE = 64; // workgroup output tile (rows and columns)
 
 __device__ __forceinline__ double gval(const double* G, const DimDev& D, int m0, int j, int f) {
   if (D.periodic) {
@@ -45,16 +44,21 @@ __device__ __forceinline__ double gval(const double* G, const DimDev& D, int m0,
   return G[(int64_t)j * m0 + f];
 }
 
-template <int MODE>
+// TL: workgroup output tile (rows and columns), 64 or 32; the four wavefronts
+// each own a TL/2 x TL/2 quarter (2 x 2 or 1 x 1 MFMA tiles).  The 32 tile
+// gives launches with fewer work items than CUs four times the items.
+template <int MODE, int TL>
 __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ lats,
                                                    const GramItem* __restrict__ items, int nitems,
                                                    const double* __restrict__ fac, void* __restrict__ part_) {
   // one chunk buffer; the global loads of chunk c+1 go to registers and are
   // in flight while the MFMAs of chunk c run
-  __shared__ double As[KC][TILE + 1];
-  __shared__ double Bs[KC][TILE + 1];
+  __shared__ double As[KC][TL + 1];
+  __shared__ double Bs[KC][TL + 1];
   typedef typename std::conditional<MODE == 0, d4, f4>::type Acc;
-  constexpr int NV = KC / 4;   // nodes staged per thread and chunk
+  constexpr int NQ = 256 / TL;      // node groups of the staging threads
+  constexpr int NV = KC / NQ;       // nodes staged per thread and chunk
+  constexpr int WS = TL / 2, NA = WS / 16;   // wave quarter and its MFMA tiles per side
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const GramItem item = items[it];
@@ -63,17 +67,17 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
     const int m0 = L.m0, M = L.T * m0, N = D.nshift * m0;
     const double* G = fac + D.g_off;
     const double* P = fac + D.p_off;
-    const int row0 = item.tm * TILE, col0 = item.tn * TILE;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // wave sub-tile within the tile
-    Acc acc[2][2];
+    const int row0 = item.tm * TL, col0 = item.tn * TL;
+    const int wr = (wave >> 1) * WS, wc = (wave & 1) * WS;   // wave quarter within the tile
+    Acc acc[NA][NA];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NA; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+      for (int b = 0; b < NA; ++b) acc[a][b] = Acc{0, 0, 0, 0};
     const int k_beg = item.ks * D.kchunk;
     const int k_end = min(D.kwin, k_beg + D.kchunk);
-    // this thread stages column `col` of both operand tiles, nodes kq + 4 v
-    const int col = tid & (TILE - 1), kq = tid >> 6;
+    // this thread stages column `col` of both operand tiles, nodes kq + NQ v
+    const int col = tid & (TL - 1), kq = tid / TL;
     const int r = row0 + col, c = col0 + col;
     const bool rok = r < M, cok = c < N;
     const int t = r / m0, nu = r - t * m0;
@@ -91,7 +95,7 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
     auto load_chunk = [&](int kc0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const int k = kc0 + kq + 4 * v;
+        const int k = kc0 + kq + NQ * v;
         x0[v] = 0.0; x1[v] = 0.0; x2[v] = 0.0; y[v] = 0.0;
         if (k < k_end) {
           int i = D.kstart + k;
@@ -116,7 +120,7 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
     auto store_chunk = [&]() {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const int kk = kq + 4 * v;
+        const int kk = kq + NQ * v;
         As[kk][col] = t >= 2 ? x1[v] * x0[v]
                           : t == 0 ? h6 * (x1[v] + 4.0 * x0[v] + x2[v]) : hinv * (2.0 * x0[v] - x1[v] - x2[v]);
         Bs[kk][col] = y[v];
@@ -131,18 +135,18 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
       const bool more = kc0 + KC < k_end;
       if (more) load_chunk(kc0 + KC);
       if constexpr (MODE == 2) {
-        bf8 ah[2], al[2], bh[2], bl[2];
+        bf8 ah[NA], al[NA], bh[NA], bl[NA];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a) {
+          for (int a = 0; a < NA; ++a) {
             const float x = (float)As[8 * lk + e][wr + a * 16 + lr];
             const __bf16 hi = (__bf16)x;
             ah[a][e] = hi;
             al[a][e] = (__bf16)(x - (float)hi);
           }
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
+          for (int b = 0; b < NA; ++b) {
             const float x = (float)Bs[8 * lk + e][wc + b * 16 + lr];
             const __bf16 hi = (__bf16)x;
             bh[b][e] = hi;
@@ -150,9 +154,9 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
           }
         }
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < NA; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
+          for (int b = 0; b < NA; ++b) {
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
@@ -161,9 +165,9 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 4) {
 #pragma unroll
-          for (int a = 0; a < 2; ++a)
+          for (int a = 0; a < NA; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
+            for (int b = 0; b < NA; ++b) {
               const double x = As[kk + lk][wr + a * 16 + lr];
               const double yy = Bs[kk + lk][wc + b * 16 + lr];
               if constexpr (MODE == 0)
@@ -183,9 +187,9 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
     typedef typename std::conditional<MODE == 0, double, float>::type T;
     T* out = reinterpret_cast<T*>(part_) + D.part_off + (int64_t)item.ks * M * N;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NA; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < NA; ++b) {
         const int c = col0 + wc + b * 16 + lr;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -221,12 +225,17 @@ __global__ void __launch_bounds__(256) gram_reduce_kernel(const LatDev* __restri
 hipError_t launch_grams(const lhf_plan_s* p, int mode, const double* fac, void* part, void* grams,
                         hipStream_t s) {
   const int grid = std::min(p->n_gram_items, p->gram_grid);
-  if (mode == LHF_GRAM_FP64)
-    hipLaunchKernelGGL(gram_kernel<0>, dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
-  else if (mode == LHF_GRAM_FP32)
-    hipLaunchKernelGGL(gram_kernel<1>, dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
-  else
-    hipLaunchKernelGGL(gram_kernel<2>, dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+  const bool t32 = p->gram_tile == 32;
+  if (mode == LHF_GRAM_FP64) {
+    if (t32) hipLaunchKernelGGL((gram_kernel<0, 32>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+    else hipLaunchKernelGGL((gram_kernel<0, 64>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+  } else if (mode == LHF_GRAM_FP32) {
+    if (t32) hipLaunchKernelGGL((gram_kernel<1, 32>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+    else hipLaunchKernelGGL((gram_kernel<1, 64>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+  } else {
+    if (t32) hipLaunchKernelGGL((gram_kernel<2, 32>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+    else hipLaunchKernelGGL((gram_kernel<2, 64>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+  }
   int64_t maxmn = 0;
   for (const LatDev& L : p->lat)
     for (int d = 0; d < 3; ++d) maxmn = std::max<int64_t>(maxmn, (int64_t)L.T * L.m0 * L.dim[d].nshift * L.m0);

@@ -64,15 +64,15 @@ void set_gram_split(LatDev& L, int d, int target) {
 }
 
 // Grouped Gram work list: one item per (lattice, dimension, 64x64 tile, split).
-void plan_grams(const std::vector<LatDev>& lats, std::vector<GramItem>& items) {
+void plan_grams(const std::vector<LatDev>& lats, std::vector<GramItem>& items, int tile) {
   items.clear();
   for (int i = 0; i < (int)lats.size(); ++i) {
     const LatDev& L = lats[i];
     for (int d = 0; d < 3; ++d) {
       const DimDev& D = L.dim[d];
       const int M = L.T * L.m0, N = D.nshift * L.m0;
-      for (int tm = 0; tm < (M + 63) / 64; ++tm)
-        for (int tn = 0; tn < (N + 63) / 64; ++tn)
+      for (int tm = 0; tm < (M + tile - 1) / tile; ++tm)
+        for (int tn = 0; tn < (N + tile - 1) / tile; ++tn)
           for (int ks = 0; ks < D.ksplit; ++ks) items.push_back(GramItem{i, d, tm, tn, ks, 0});
     }
   }
@@ -299,7 +299,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->sizes.ws_bytes = off;
 
   std::vector<GramItem> items;
-  plan_grams(p->lat, items);
+  plan_grams(p->lat, items, p->gram_tile);
   p->n_gram_items = (int32_t)items.size();
 
   // grouped factor work

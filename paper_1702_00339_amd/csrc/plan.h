@@ -49,7 +49,8 @@ struct lhf_plan_s {
   // eigensolver layout per class: one matrix entry per thread (wide) when the
   // four-entries-per-thread launch would leave SIMDs without a wavefront
   bool heev_wide[4] = {false, false, false, false};
-  bool heev_fp64[4] = {false, false, false, false};   // mixed plans: class takes the FP64 solve alone
+  bool heev_fp64[4] = {false, false, false, false};
+  int32_t gram_tile = 64;               // Gram work-item output tile: 64 or 32   // mixed plans: class takes the FP64 solve alone
   static constexpr int64_t kWideWaves = 1024;   // one wavefront per SIMD of the device
   // tunables (planner defaults, refined by lhf_plan_autotune)
   int32_t dft_target_threads = 131072;  // threads one DFT pass aims to run
@@ -88,7 +89,7 @@ Ws ws_view(const lhf_plan_s* p, void* base);
 
 constexpr int kGramSplitMax = 256;   // split-K target the workspace is sized for
 void set_gram_split(LatDev& L, int d, int target);
-void plan_grams(const std::vector<LatDev>& lats, std::vector<GramItem>& items);
+void plan_grams(const std::vector<LatDev>& lats, std::vector<GramItem>& items, int tile);
 uint64_t plan_signature(const lhf_plan_s* p);
 
 // factors.hip: nodal factors and lattice-window potential factors of every lattice

@@ -100,7 +100,7 @@ int32_t apply_tuning(lhf_plan_s* p) {
   for (LatDev& L : p->lat)
     for (int d = 0; d < 3; ++d) set_gram_split(L, d, p->gram_split);
   std::vector<GramItem> items;
-  plan_grams(p->lat, items);
+  plan_grams(p->lat, items, p->gram_tile);
   std::vector<DftTask> tasks;
   std::vector<DftLaunch> launches;
   std::vector<FusedTask> fused;
@@ -133,6 +133,7 @@ void get_tuning(const lhf_plan_s* p, lhf_tuning* t) {
   t->heev_wide = 0;
   for (int c = 0; c < 4; ++c) t->heev_wide |= p->heev_wide[c] ? 1 << c : 0;
   t->fourier_sep = p->fourier_sep && p->sep_ok ? 1 : 0;
+  t->gram_tile = p->gram_tile;
   t->heev_fp64 = 0;
   if (p->prec == LHF_PREC_MIXED)
     for (int c = 0; c < 4; ++c) t->heev_fp64 |= p->heev_fp64[c] ? 1 << c : 0;
@@ -142,11 +143,13 @@ int32_t set_tuning(lhf_plan_s* p, const lhf_tuning* t) {
   if (t->dft_threads < 1024 || t->dft_threads > (1 << 24) || t->gram_split < 1 || t->gram_split > kGramSplitMax ||
       t->gram_grid < 1 || t->gram_grid > (1 << 20) || t->tol32_scale < 1 || t->tol32_scale > (1 << 16) ||
       t->heev_wide < 0 || t->heev_wide > 15 || t->fourier_sep < 0 || t->fourier_sep > 1 ||
-      t->heev_fp64 < 0 || t->heev_fp64 > 15) {
+      t->heev_fp64 < 0 || t->heev_fp64 > 15 || (t->gram_tile != 64 && t->gram_tile != 32)) {
     set_error("tuning value out of range");
     return LHF_ERR_INVALID;
   }
-  const bool tables = t->dft_threads != p->dft_target_threads || t->gram_split != p->gram_split;
+  const bool tables = t->dft_threads != p->dft_target_threads || t->gram_split != p->gram_split ||
+                      t->gram_tile != p->gram_tile;
+  p->gram_tile = t->gram_tile;
   p->dft_target_threads = t->dft_threads;
   p->gram_split = t->gram_split;
   p->gram_grid = t->gram_grid;
@@ -212,6 +215,8 @@ bool parse_entry(const std::string& body, lhf_tuning& t) {
   t.fourier_sep = field(body, "fourier_sep", w) && w >= 0.0 ? (int32_t)w : t.fourier_sep;
   w = -1.0;
   t.heev_fp64 = field(body, "heev_fp64", w) && w >= 0.0 ? (int32_t)w : t.heev_fp64;
+  w = -1.0;
+  t.gram_tile = field(body, "gram_tile", w) && w >= 0.0 ? (int32_t)w : t.gram_tile;
   t.dft_threads = (int32_t)a;
   t.gram_split = (int32_t)b;
   t.gram_grid = (int32_t)c;
@@ -225,9 +230,10 @@ void write_cache(const char* path, std::map<std::string, std::string> entries, c
   char buf[256];
   std::snprintf(buf, sizeof(buf),
                 "{\"dft_threads\": %d, \"gram_split\": %d, \"gram_grid\": %d, \"tol32_scale\": %d, "
-                "\"heev_wide\": %d, \"fourier_sep\": %d, \"heev_fp64\": %d, \"step_ms\": %.6f}",
+                "\"heev_wide\": %d, \"fourier_sep\": %d, \"heev_fp64\": %d, \"gram_tile\": %d, "
+                "\"step_ms\": %.6f}",
                 t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.heev_fp64,
-                t.step_ms);
+                t.gram_tile, t.step_ms);
   entries[key] = buf;
   std::ofstream f(path, std::ios::trunc);
   f << "{\n";
@@ -362,6 +368,8 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
   static const int32_t tol_c[] = {1, 16, 256, 4096};
   double step_ms = 0.0;
   st = timed(7, 1, step_ms);   // fills every buffer the later stages read
+  static const int32_t tile_c[] = {64, 32};
+  if (st == LHF_OK) st = search(1, &lhf_tuning::gram_tile, tile_c, 2);
   if (st == LHF_OK) st = search(1, &lhf_tuning::gram_split, split_c, 5);
   if (st == LHF_OK) st = search(1, &lhf_tuning::gram_grid, grid_c, 4);
   // Fourier blocks: separable formation or generator stacks and block DFT, timed over whole steps (the

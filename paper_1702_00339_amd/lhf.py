@@ -50,7 +50,7 @@ class lhf_step_args(C.Structure):
 class lhf_tuning(C.Structure):
     _fields_ = [("dft_threads", C.c_int32), ("gram_split", C.c_int32), ("gram_grid", C.c_int32),
                 ("tol32_scale", C.c_int32), ("heev_wide", C.c_int32), ("fourier_sep", C.c_int32),
-                ("heev_fp64", C.c_int32), ("step_ms", C.c_double),
+                ("heev_fp64", C.c_int32), ("gram_tile", C.c_int32), ("step_ms", C.c_double),
                 ("from_cache", C.c_int32)]
 
     def as_dict(self):

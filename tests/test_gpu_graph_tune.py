@@ -116,9 +116,10 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     assert t.dft_threads in (32768, 65536, 131072, 262144, 524288) and t.tol32_scale in (1, 16, 256, 4096)
     got = pipe.plan.lhf_plan_get_tuning()
     assert (got.dft_threads, got.gram_split, got.gram_grid, got.tol32_scale, got.heev_wide, got.fourier_sep,
-            got.heev_fp64) == \
-        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.heev_fp64)
-    assert 0 <= t.heev_wide <= 15 and t.fourier_sep in (0, 1) and 0 <= t.heev_fp64 <= 15
+            got.heev_fp64, got.gram_tile) == \
+        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.heev_fp64,
+         t.gram_tile)
+    assert 0 <= t.heev_wide <= 15 and t.fourier_sep in (0, 1) and 0 <= t.heev_fp64 <= 15 and t.gram_tile in (64, 32)
     entries = json.load(open(cache))
     assert len(entries) == 1
     pipe.step_native()
@@ -132,8 +133,9 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     t2 = again.autotune(cache)
     assert t2.from_cache == 1
     assert (t2.dft_threads, t2.gram_split, t2.gram_grid, t2.tol32_scale, t2.heev_wide, t2.fourier_sep,
-            t2.heev_fp64) == \
-        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.heev_fp64)
+            t2.heev_fp64, t2.gram_tile) == \
+        (t.dft_threads, t.gram_split, t.gram_grid, t.tol32_scale, t.heev_wide, t.fourier_sep, t.heev_fp64,
+         t.gram_tile)
     # a different plan adds its own entry
     Pipeline(insts[:2], prec=lhf.LHF_PREC_FP64).autotune(cache)
     assert len(json.load(open(cache))) == 2
@@ -143,15 +145,26 @@ def test_set_tuning_extremes_keep_parity():
     """The smallest and largest launch shapes still give the oracle's eigenvalues."""
     insts = _mix()
     refs = [np.sort(separable.solve(i)["eig"], axis=-1) for i in insts]
-    for dft, split, grid, wide, sep in ((32768, 1, 1, 0, 0), (1 << 24, 256, 1 << 20, 15, 1)):
+    for dft, split, grid, wide, sep, tile in ((32768, 1, 1, 0, 0, 32), (1 << 24, 256, 1 << 20, 15, 1, 64),
+                                              (32768, 256, 1 << 20, 15, 1, 32)):
         pipe = Pipeline(insts, prec=lhf.LHF_PREC_FP64)
         t = pipe.plan.lhf_plan_get_tuning()
-        t.dft_threads, t.gram_split, t.gram_grid, t.heev_wide, t.fourier_sep = dft, split, grid, wide, sep
+        t.dft_threads, t.gram_split, t.gram_grid, t.heev_wide, t.fourier_sep, t.gram_tile = dft, split, grid, wide, sep, tile
         pipe.plan.lhf_plan_set_tuning(t)
         pipe.step_native()
         torch.cuda.synchronize()
         for w, ref in zip(pipe.eigenvalues(), refs):
             assert (np.abs(w - ref) <= 1e-10 * np.maximum(np.abs(ref), 1.0)).all()
+    # the 32 tile in the FP32 and bf16 hi+lo Gram modes of mixed plans
+    for gram in (lhf.LHF_GRAM_FP32, lhf.LHF_GRAM_BF16X3):
+        mix = Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=gram, refine_src="band")
+        t = mix.plan.lhf_plan_get_tuning()
+        t.gram_tile = 32
+        mix.plan.lhf_plan_set_tuning(t)
+        mix.step()
+        torch.cuda.synchronize()
+        for w, ref in zip(mix.eigenvalues(), refs):
+            assert np.abs(w - ref).max() <= 1e-8
     bad = pipe.plan.lhf_plan_get_tuning()
     bad.gram_split = 257
     with pytest.raises(lhf.LhfError):
@@ -166,6 +179,10 @@ def test_set_tuning_extremes_keep_parity():
         pipe.plan.lhf_plan_set_tuning(bad)
     bad = pipe.plan.lhf_plan_get_tuning()
     bad.heev_fp64 = 16
+    with pytest.raises(lhf.LhfError):
+        pipe.plan.lhf_plan_set_tuning(bad)
+    bad = pipe.plan.lhf_plan_get_tuning()
+    bad.gram_tile = 48
     with pytest.raises(lhf.LhfError):
         pipe.plan.lhf_plan_set_tuning(bad)
     # an FP64 plan accepts the mask and reads 0: its classes all take the FP64 solve
