@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # tuned route, so its entry is keyed by the mixed plan's heev_fp64 and heev_wide masks.  Valid for the
 # kernels as they were when counted; absent (reported as null) where not counted.
 TRAFFIC_KIB = {"c2": {"eig": {"fp64=4,wide=4": 655.2}, "dft": 2357.1},
-               "c3": {"eig": {"fp64=2,wide=0": 19202.7}, "sep": 69268.3},
-               "c4": {"eig": {"fp64=15,wide=1": 310894.1}, "sep": 1344417.7}}
+               "c3": {"eig": {"fp64=2,wide=0": 19202.8}, "sep": 69268.3},
+               "c4": {"eig": {"fp64=15,wide=1": 310894.4}, "sep": 1344444.3}}
 
 
 def parse():
@@ -60,7 +60,7 @@ def parse():
                     help="for hardware-counter runs: a device copy of 512 MiB (the counters' scale), then three "
                          "eager steps of each path; prints nothing else")
     ap.add_argument("--mixed-tuning", default="",
-                    help="with --probe-traffic: JSON object of tuning fields for the mixed plan")
+                    help="with --probe-traffic or --probe-mfma: JSON object of tuning fields for the mixed plans")
     ap.add_argument("--probe-mfma", action="store_true",
                     help="for MFMA counter runs: three eager mixed steps with each Gram arithmetic (FP64, FP32, "
                          "bf16 hi+lo); prints nothing else")
@@ -222,6 +222,16 @@ def bench_c5(torch, np, lhf, steps):
             "L0": info.L0, "cross_cells": info.ncross, "embedding": P, "matvec_120_vectors": mv}
 
 
+def apply_tuning(pipe, spec):
+    """Set the tuning fields of a JSON object (--mixed-tuning) on a pipeline's plan."""
+    if not spec:
+        return
+    t = pipe.plan.lhf_plan_get_tuning()
+    for k, v in json.loads(spec).items():
+        setattr(t, k, int(v))
+    pipe.plan.lhf_plan_set_tuning(t)
+
+
 def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
     """Kernels for a FETCH_SIZE / WRITE_SIZE counter run: a plain copy of
     512 MiB (reads and writes exactly that many bytes: the scale of the
@@ -236,11 +246,8 @@ def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
     for prec in (lhf.LHF_PREC_MIXED, lhf.LHF_PREC_FP64):
         kw = {"gram": lhf.LHF_GRAM_FP64} if prec == lhf.LHF_PREC_MIXED else {}
         pipe = Pipeline(insts, prec=prec, **kw)
-        if prec == lhf.LHF_PREC_MIXED and args.mixed_tuning:
-            t = pipe.plan.lhf_plan_get_tuning()
-            for k, v in json.loads(args.mixed_tuning).items():
-                setattr(t, k, int(v))
-            pipe.plan.lhf_plan_set_tuning(t)
+        if prec == lhf.LHF_PREC_MIXED:
+            apply_tuning(pipe, args.mixed_tuning)
         for _ in range(3):
             pipe.step_native()
     torch.cuda.synchronize()
@@ -248,10 +255,12 @@ def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
 
 def probe_mfma(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
     """Kernels for an MFMA counter run: three eager steps of the mixed path
-    with each Gram arithmetic (the assembly's MFMA kernels)."""
+    with each Gram arithmetic (the assembly's MFMA kernels), with the tuning
+    fields of --mixed-tuning (e.g. the Gram tile of a timed run)."""
     insts = config_c4_lattices() if args.config == "c4" else [make_config(args.config)]
     for gram, src in ((lhf.LHF_GRAM_FP64, "dual"), (lhf.LHF_GRAM_FP32, "bar64"), (lhf.LHF_GRAM_BF16X3, "bar64")):
         pipe = Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=gram, refine_src=src)
+        apply_tuning(pipe, args.mixed_tuning)
         for _ in range(3):
             pipe.step()
     torch.cuda.synchronize()
