@@ -28,8 +28,9 @@
  *     anything is launched; numerical failures are reported per block in the
  *     device array `info` (LAPACK style).  lhf_last_error() gives a message
  *     for the last failing call of the calling thread.
- *   * Plans are immutable after creation and may be used from several streams
- *     at once, each with its own workspace.
+ *   * Plans are immutable after creation apart from their tuning
+ *     (lhf_plan_set_tuning, lhf_plan_autotune, which need the plan idle) and
+ *     may be used from several streams at once, each with its own workspace.
  */
 #ifndef LHF_H
 #define LHF_H
@@ -383,7 +384,11 @@ int32_t lhf_step(lhf_plan_t plan, const lhf_step_args* args, lhf_stream_t stream
  * while it exists, and a replay overwrites them as lhf_step would.
  * lhf_graph_create allocates (graph and executable graph; capture runs on a
  * private stream of default priority) and launches nothing; replays of one
- * graph on several streams at once race on its buffers.
+ * graph on several streams at once race on its buffers.  The plan's launch
+ * shapes and work tables are baked in too: the plan must outlive its graphs,
+ * and a change of its tuning (lhf_plan_set_tuning, lhf_plan_autotune) makes
+ * every graph captured before it stale: lhf_graph_launch then returns
+ * LHF_ERR_INVALID without launching, and the step must be captured again.
  * Errors: those of lhf_step, LHF_ERR_HIP (capture or instantiation failed). */
 typedef struct lhf_graph_s* lhf_graph_t;
 int32_t lhf_graph_create(lhf_plan_t plan, const lhf_step_args* args, lhf_graph_t* out);

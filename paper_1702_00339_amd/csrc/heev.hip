@@ -36,6 +36,7 @@
 #include <type_traits>
 
 #include "plan.h"
+#include "sturm.h"
 
 namespace lhf {
 namespace {
@@ -925,9 +926,8 @@ __device__ void chol_reduce_wup(Smem<double, M, G, false, false, true>& sh, int 
 // interval and the group keeps the sub-interval holding it, until its width is
 // a few ulps of the interval or of the matrix norm.  The count at x is the
 // number of sign changes of the leading minors p_j of T - x I, from the
-// division-free recurrence p_j = (d_j - x) p_(j-1) - e_(j-1)^2 p_(j-2) (a zero
-// taken as positive, which counts as the ratio form with small pivots made
-// negative does), on T scaled by a power of two to norm below 1 and rescaled
+// division-free recurrence p_j = (d_j - x) p_(j-1) - e_(j-1)^2 p_(j-2)
+// (sturm_row: a zero taken as positive, restarted where e_(j-1) = 0), on T scaled by a power of two to norm below 1 and rescaled
 // by 2^-+256 every eighth row against overflow and underflow (exact,
 // sign-preserving).  Each lane runs two sequences at once (2 P + 1 sections
 // per pass).  The eigenvalues land sorted: rank i = i.
@@ -1135,16 +1135,8 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
       auto row = [&](int j, auto rs) {
         constexpr bool RS = decltype(rs)::value;
         const C dj = dr_at(j);
-        const R pa = fma(dj.x - xa, pa1, -dj.y * pa2), pb = fma(dj.x - xb, pb1, -dj.y * pb2);
-        const bool ma = pa < R(0), mb = pb < R(0);
-        ca += ma != na ? 1 : 0;
-        cb += mb != nb ? 1 : 0;
-        na = ma;
-        nb = mb;
-        pa2 = pa1;
-        pb2 = pb1;
-        pa1 = pa;
-        pb1 = pb;
+        sturm_row(dj.x, dj.y, xa, pa1, pa2, na, ca);
+        sturm_row(dj.x, dj.y, xb, pb1, pb2, nb, cb);
         if constexpr (RS) {
           const R sa = fabs(pa1) > kBig ? kSmall : (fabs(pa1) < kSmall ? kBig : R(1));
           const R sb = fabs(pb1) > kBig ? kSmall : (fabs(pb1) < kSmall ? kBig : R(1));

@@ -49,8 +49,9 @@ struct lhf_plan_s {
   // eigensolver layout per class: one matrix entry per thread (wide) when the
   // four-entries-per-thread launch would leave SIMDs without a wavefront
   bool heev_wide[4] = {false, false, false, false};
-  bool heev_fp64[4] = {false, false, false, false};
-  int32_t gram_tile = 64;               // Gram work-item output tile: 64 or 32   // mixed plans: class takes the FP64 solve alone
+  bool heev_fp64[4] = {false, false, false, false};   // mixed plans: class takes the FP64 solve alone
+  int32_t gram_tile = 64;               // Gram work-item output tile: 64 or 32
+  uint64_t tuning_gen = 0;              // bumped by every change of tuning; graphs record it
   static constexpr int64_t kWideWaves = 1024;   // one wavefront per SIMD of the device
   // tunables (planner defaults, refined by lhf_plan_autotune)
   int32_t dft_target_threads = 131072;  // threads one DFT pass aims to run

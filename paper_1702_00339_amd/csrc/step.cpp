@@ -15,6 +15,8 @@ using namespace lhf;
 struct lhf_graph_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  const lhf_plan_s* plan = nullptr;
+  uint64_t tuning_gen = 0;   // the plan's tuning generation at capture
 };
 
 namespace {
@@ -149,6 +151,15 @@ int32_t set_tuning(lhf_plan_s* p, const lhf_tuning* t) {
   }
   const bool tables = t->dft_threads != p->dft_target_threads || t->gram_split != p->gram_split ||
                       t->gram_tile != p->gram_tile;
+  // launch shapes, kernels and work tables are baked into captured graphs:
+  // any change makes them stale
+  lhf_tuning was;
+  get_tuning(p, &was);
+  if (was.dft_threads != t->dft_threads || was.gram_split != t->gram_split || was.gram_grid != t->gram_grid ||
+      was.tol32_scale != t->tol32_scale || was.heev_wide != t->heev_wide ||
+      was.fourier_sep != (t->fourier_sep && p->sep_ok ? 1 : 0) ||
+      (p->prec == LHF_PREC_MIXED && was.heev_fp64 != t->heev_fp64) || was.gram_tile != t->gram_tile)
+    ++p->tuning_gen;
   p->gram_tile = t->gram_tile;
   p->dft_target_threads = t->dft_threads;
   p->gram_split = t->gram_split;
@@ -274,6 +285,8 @@ int32_t lhf_graph_create(lhf_plan_t p, const lhf_step_args* a, lhf_graph_t* out)
   auto* g = new (std::nothrow) lhf_graph_s();
   if (!g) { (void)hipGraphDestroy(graph); set_error("out of host memory"); return LHF_ERR_ALLOC; }
   g->graph = graph;
+  g->plan = p;
+  g->tuning_gen = p->tuning_gen;
   st = hip_status(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0), "graph instantiation");
   if (st != LHF_OK) { lhf_graph_destroy(g); return st; }
   *out = g;
@@ -282,6 +295,10 @@ int32_t lhf_graph_create(lhf_plan_t p, const lhf_step_args* a, lhf_graph_t* out)
 
 int32_t lhf_graph_launch(lhf_graph_t g, lhf_stream_t stream) {
   if (!g || !g->exec) { set_error("NULL graph"); return LHF_ERR_INVALID; }
+  if (g->plan->tuning_gen != g->tuning_gen) {
+    set_error("the plan's tuning changed after this graph was captured: capture it again");
+    return LHF_ERR_INVALID;
+  }
   return hip_status(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)), "graph launch");
 }
 

@@ -190,3 +190,31 @@ def test_set_tuning_extremes_keep_parity():
     t.heev_fp64 = 15
     pipe.plan.lhf_plan_set_tuning(t)
     assert pipe.plan.lhf_plan_get_tuning().heev_fp64 == 0
+
+
+def test_graph_is_stale_after_tuning_change():
+    """A graph bakes in the plan's launch shapes and work tables: after the
+    tuning changes, launching it is refused (no launch), a new capture runs
+    and matches the eager step, and setting the same tuning again keeps
+    graphs valid."""
+    pipe = Pipeline(_mix(), prec=lhf.LHF_PREC_FP64)
+    graph = pipe.capture()
+    t = pipe.plan.lhf_plan_get_tuning()
+    pipe.plan.lhf_plan_set_tuning(t)          # unchanged: still valid
+    graph.lhf_graph_launch()
+    torch.cuda.synchronize()
+    t.gram_tile = 32 if t.gram_tile == 64 else 64
+    pipe.plan.lhf_plan_set_tuning(t)
+    with pytest.raises(lhf.LhfError):
+        graph.lhf_graph_launch()
+    graph.close()
+    pipe.step_native()
+    torch.cuda.synchronize()
+    ref = _outputs(pipe)
+    _poison(pipe)
+    again = pipe.capture()
+    again.lhf_graph_launch()
+    torch.cuda.synchronize()
+    for a, b in zip(ref, _outputs(pipe)):
+        assert torch.equal(a, b)
+    again.close()
