@@ -227,6 +227,27 @@ int32_t lhf_block_fft_dual(lhf_plan_t plan, const double* d_H_gen64, const doubl
 int32_t lhf_fourier_blocks(lhf_plan_t plan, const double* d_grams64, void* d_H_bar64, void* d_S_bar64,
                            void* d_ws, size_t ws_bytes, lhf_stream_t stream);
 
+/* lhf_fourier_blocks for callers that cannot allocate device memory or pass
+ * a workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same transform, kernels, layouts and results as
+ * lhf_fourier_blocks; its one scratch buffer, the 1D-transformed Grams of
+ * dimensions 2 and 3 (complex128, sum over lattices and those dimensions of
+ * (2 + M0 R) L m0^2 elements), is a static device array of
+ * LHF_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends.  The call allocates nothing, launches only
+ * kernels (no memsets or copies), and uses the plan's device, which must be
+ * current.  Every call on one device shares that device's array and leaves
+ * its contents behind: calls that overlap on one device (several streams or
+ * threads) race and must be serialised by the caller.
+ * d_grams64: the FP64 Grams written by lhf_assemble_blocks (required here).
+ * d_H_bar64, d_S_bar64: device complex128 [gen_elems], as lhf_fourier_blocks.
+ * Errors: LHF_ERR_INVALID (NULL argument, another device current),
+ * LHF_ERR_UNSUPPORTED (plan not separable, as lhf_fourier_blocks, or its
+ * transformed Grams larger than the static array), LHF_ERR_HIP. */
+#define LHF_NOALLOC_SCRATCH_BYTES (32u * 1024u * 1024u)
+int32_t lhf_fourier_blocks_noalloc(lhf_plan_t plan, const double* d_grams64, void* d_H_bar64, void* d_S_bar64,
+                                   lhf_stream_t stream);
+
 /* ---------------------------------------------------------------- eigensolve
  * For every block j: Hbar_j u = lambda Sbar_j u (eq. HF-FSpace-Block), by
  * Cholesky reduction to a standard Hermitian problem, then, for FP64
