@@ -1,24 +1,33 @@
 """Throughput of the periodic hot path on one MI355X: k-point blocks per second.
 
-One step is one full pass of the hot path over every lattice of the plan:
+One step is one full pass of the hot path over every lattice of a plan:
 assemble the generator blocks (factors, lattice sums, 1D Grams, combination),
-block DFT over the lattice index, and the generalized eigensolve of every
-Fourier block (with FP64 refinement on the mixed path).  Inputs (the lattice
-descriptions) live in the plan; all buffers are resident in HBM before timing
-starts.  Each plan is autotuned first, then one step is captured into a
-hipGraph and the timed steps are graph replays.
+form the Fourier blocks (block DFT over the lattice index, or separably from
+the 1D Grams), and solve the generalized eigenproblem of every Fourier block.
+Inputs (the lattice descriptions) live in the plan; every buffer is resident
+in HBM before timing starts.  Each plan is autotuned, one step is captured
+into a hipGraph, and the timed steps are graph replays.
 
-Prints one JSON line.  ``value`` is the mixed-precision path's blocks/s; the
-FP64 path is timed the same way and reported beside it.  Both are gated on
-accuracy against the CPU oracle (run once, untimed for the GPU; for the
-64-lattice mix, on one lattice of each basis size).
+Every workload is run on three routes, each gated on accuracy against the CPU
+oracle (run untimed, in the same process):
+  * "tuned"  the mixed-precision plan with every choice left to its autotuner,
+             which may give a size class to the FP64 solve alone; its route
+             and dtype are reported as taken;
+  * "fp64"   the plain all-FP64 plan;
+  * "fp32"   the reduced-precision route: bf16 hi+lo split Grams on the
+             matrix cores, FP32 stacks, complex64 block DFT, FP32 Jacobi, and
+             FP64 refinement of every eigenpair (no class goes to the FP64
+             solve alone).
+``value`` is the tuned route on the headline workload (the 256-cell tube);
+the other two and the cube and the 64-lattice mix are reported beside it.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2] [--legs c3,c4]
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -38,33 +47,50 @@ WORKLOADS = {
 # lattices of the 64-lattice mix checked against the oracle: the cheapest of each basis size
 C4_CHECK = (28, 41, 52, 2)
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per call (FETCH_SIZE + WRITE_SIZE, KiB, scaled by a plain 512 MiB copy) of the mixed path's
-# eigensolve call, block DFT and separable Fourier-block formation, from two rocprofv3 --pmc runs of
-# `bench.py --probe-traffic` (profiles/traffic_per_dispatch.md).  The eigensolve's kernels depend on the
-# tuned route, so its entry is keyed by the mixed plan's heev_fp64 and heev_wide masks.  Valid for the
-# kernels as they were when counted; absent (reported as null) where not counted.
-TRAFFIC_KIB = {"c2": {"eig": {"fp64=4,wide=4": 655.2}, "dft": 2357.1},
-               "c3": {"eig": {"fp64=2,wide=0": 19202.8}, "sep": 69268.3},
-               "c4": {"eig": {"fp64=15,wide=1": 310894.4}, "sep": 1344444.3}}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}     # MI355X vector peaks
+HEEV_FLOPS_PER_M3 = 150.0                    # algorithmic eigensolve work per block: 150 m0^3
+
+# HBM bytes per call (FETCH_SIZE + WRITE_SIZE, KiB, each scaled by what the counter reads for a plain
+# 512 MiB device copy) of the headline kernels, from two rocprofv3 --pmc runs of `bench.py
+# --probe-traffic` (profiles/traffic_per_dispatch.md).  Each entry names the source files of its kernels
+# and their SHA-1 (first 16 hex digits) when counted, and the route it was counted on; an entry whose
+# sources have changed since, or whose route is not the one timed, is reported as null.
+TRAFFIC_KIB = {}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--legs", default="c3,c4", help="further workloads reported in the same line ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the Dirichlet-chain (c5) measurement")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a device copy of 512 MiB (the counters' scale), then three "
-                         "eager steps of each path; prints nothing else")
+                         "eager steps of the tuned and the FP64 paths; prints nothing else")
     ap.add_argument("--mixed-tuning", default="",
                     help="with --probe-traffic or --probe-mfma: JSON object of tuning fields for the mixed plans")
     ap.add_argument("--probe-mfma", action="store_true",
                     help="for MFMA counter runs: three eager mixed steps with each Gram arithmetic (FP64, FP32, "
                          "bf16 hi+lo); prints nothing else")
     return ap.parse_args()
+
+
+def src_sha(files):
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1702_00339_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(cfg, kernel, route):
+    e = TRAFFIC_KIB.get(cfg, {}).get(kernel)
+    if not e or e["route"] != route or src_sha(e["src"]) != e["sha"]:
+        return None
+    return e["kib"] * 1024.0
 
 
 def time_graph(graph, steps, torch):
@@ -78,31 +104,57 @@ def time_graph(graph, steps, torch):
     return (time.perf_counter() - t0) / steps
 
 
-def event_ms(fn, steps, torch):
-    """Average duration of fn()'s launches, timed with events recorded on the
-    torch current stream (the stream the library launches on)."""
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+def event_ms(fn, reps, torch):
+    """Average duration of one call of fn, from `reps` calls issued back to
+    back between two events on torch's current stream (the stream the library
+    launches on), after one untimed call."""
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    for a, b in ev:
-        a.record()
+    a.record()
+    for _ in range(reps):
         fn()
-        b.record()
+    b.record()
     torch.cuda.synchronize()
-    return sum(a.elapsed_time(b) for a, b in ev) / steps
+    return a.elapsed_time(b) / reps
 
 
-def dft_bytes(pipe, insts, kind="plan"):
+def canonical_blocks(L):
+    """Blocks solved once per conjugate pair j, -j."""
+    self_conj = 1
+    for x in L:
+        self_conj *= 2 if x % 2 == 0 else 1
+    n = L[0] * L[1] * L[2]
+    return (n + self_conj) // 2
+
+
+def heev_class(m0):
+    """Eigensolver size class of a basis size: M = 4, 8, 16, 32 -> 0..3."""
+    return 0 if m0 <= 4 else 1 if m0 <= 8 else 2 if m0 <= 16 else 3
+
+
+def heev_flops_kernel(insts, fp64_classes, R):
+    """The kernels' own operation count per call (8 flops per complex
+    multiply-add), per distinct block.  FP64 solve: reduction to standard
+    form (elimination m0^3 / 3 and two m0^3 products, complex) and Householder
+    tridiagonalisation (4/3 m0^3 complex), 29.3 m0^3, plus bisection, m0
+    eigenvalues x 53 halvings x m0 rows x 4.  FP32 solve: 150 m0^3 (reduction
+    and 6-10 Jacobi sweeps) plus the FP64 refinement, (R + 4) m0^2 8 + 36 m0^3."""
+    total = 0.0
+    for inst in insts:
+        m = inst.m0
+        if heev_class(m) in fp64_classes:
+            per = (8.0 / 3.0 + 16.0 + 32.0 / 3.0) * m ** 3 + 4.0 * 53.0 * m * m
+        else:
+            per = 150.0 * m ** 3 + (R + 4) * m * m * 8 + 36.0 * m ** 3
+        total += canonical_blocks(inst.L) * per
+    return total
+
+
+def dft_bytes(pipe, insts, cbytes):
     """Algorithmic HBM bytes of one block-DFT call: every Fourier block written
-    once (H and S, complex) plus every band generator read once (H and S,
-    real).  kind "plan": in the plan's precision; "fp64": complex128 from FP64
-    stacks (the mixed path's transform); "dual": complex128 and complex64."""
-    from paper_1702_00339_amd import lhf
-    cbytes = 16 if pipe.prec == lhf.LHF_PREC_FP64 else 8
-    rbytes = cbytes // 2
-    if kind == "fp64":
-        cbytes, rbytes = 16, 8
-    elif kind == "dual":
-        cbytes, rbytes = 16 + 8, 8
+    once (H and S, complex of cbytes) plus every band generator read once (H
+    and S, real of cbytes / 2)."""
     total = 0
     for i, inst in enumerate(insts):
         m2 = inst.m0 * inst.m0
@@ -110,7 +162,7 @@ def dft_bytes(pipe, insts, kind="plan"):
         band = 1
         for d in range(3):
             band *= nshift[d] if inst.L[d] > 1 else 1
-        total += 2 * inst.ncells * m2 * cbytes + 2 * band * m2 * rbytes
+        total += 2 * inst.ncells * m2 * cbytes + 2 * band * m2 * (cbytes // 2)
     return total
 
 
@@ -130,54 +182,192 @@ def sep_bytes(pipe, insts):
     return total
 
 
-def canonical_blocks(L):
-    """Blocks solved once per conjugate pair j, -j."""
-    self_conj = 1
-    for x in L:
-        self_conj *= 2 if x % 2 == 0 else 1
-    n = L[0] * L[1] * L[2]
-    return (n + self_conj) // 2
-
-
-def heev_class(m0):
-    """Eigensolver size class of a basis size: M = 4, 8, 16, 32 -> 0..3."""
-    return 0 if m0 <= 4 else 1 if m0 <= 8 else 2 if m0 <= 16 else 3
-
-
-def heev_flops(insts, prec, R, fp64_mask=0):
-    """Algorithmic flops of one eigenvalues-only lhf_heev_batched call, per
-    distinct block (8 flops per complex multiply-add).  FP64 solve: reduction
-    to standard form (overlap elimination m0^3 / 3 and two m0^3 products,
-    complex) and Householder tridiagonalisation (4/3 m0^3 complex), 29.3 m0^3,
-    plus bisection, m0 eigenvalues x 53 halvings x m0 rows x 4 flops.  A mixed
-    plan's FP32 classes: 150 m0^3 (reduction and 6-10 Jacobi sweeps) plus the
-    FP64 refinement, (R + 4) m0^2 8 + 36 m0^3; its FP64 classes (bits of
-    fp64_mask) count as the FP64 solve."""
+def route_of(pipe, insts):
+    """(description, dtype, FP64-solve classes) of the route a pipeline's step takes."""
     from paper_1702_00339_amd import lhf
-    total = 0.0
-    for inst in insts:
-        m = inst.m0
-        if prec == lhf.LHF_PREC_MIXED and not (fp64_mask >> heev_class(m)) & 1:
-            per = 150.0 * m ** 3 + (R + 4) * m * m * 8 + 36.0 * m ** 3
-        else:
-            per = (8.0 / 3.0 + 16.0 + 32.0 / 3.0) * m ** 3 + 4.0 * 53.0 * m * m
-        total += canonical_blocks(inst.L) * per
-    return total
-
-
-def eig_route(m0s, mask):
-    """The eigensolver route of the tuned mixed plan, per size class (bits of
-    mask: the FP64 solve alone)."""
-    f64 = sorted({4 << heev_class(m) for m in m0s if (mask >> heev_class(m)) & 1})
-    mix = sorted({4 << heev_class(m) for m in m0s if not (mask >> heev_class(m)) & 1})
-    def which(sizes):
-        return " (M = " + ", ".join(str(x) for x in sizes) + ")" if f64 and mix else ""
-    parts = []
-    if mix:
-        parts.append("FP32 Jacobi on the rounded blocks + FP64 Rayleigh-Ritz refinement" + which(mix))
+    t = pipe.plan.lhf_plan_get_tuning()
+    classes = sorted({heev_class(i.m0) for i in insts})
+    sep = pipe.separable()
+    if pipe.prec == lhf.LHF_PREC_FP64:
+        f64 = set(classes)
+        parts = ["FP64 MFMA Grams",
+                 "complex128 Fourier blocks " + ("formed separably from the Grams" if sep else "by block DFT"),
+                 "FP64 Householder tridiagonalisation + bisection"]
+        return "; ".join(parts), "f64", f64
+    f64 = set() if pipe.fp32_solve else {c for c in classes if (t.heev_fp64 >> c) & 1}
+    gram = {lhf.LHF_GRAM_FP64: "FP64 MFMA Grams", lhf.LHF_GRAM_FP32: "FP32 MFMA Grams + FP64 Grams",
+            lhf.LHF_GRAM_BF16X3: "bf16 hi+lo split MFMA Grams (FP32 stacks) + FP64 Grams for refinement"}
+    parts = [gram[pipe.plan.gram] if pipe.refine_src in ("bar64", "band") else "FP64 MFMA Grams"]
+    if pipe.refine_src == "direct":
+        parts.append("complex128 Fourier blocks " + ("formed separably" if sep else "by block DFT"))
+    elif pipe.refine_src == "dual":
+        parts.append("one FP64 block DFT writing complex128 + complex64 blocks")
+    else:
+        parts.append("complex64 block DFT of the FP32 stacks" +
+                     (" + complex128 block DFT of the FP64 stacks" if pipe.refine_src == "bar64" else ""))
+    size = lambda cs: ", ".join(f"M={4 << c}" for c in sorted(cs))
+    f32 = [c for c in classes if c not in f64]
+    if f32:
+        src = {"direct": "rounded complex128 blocks", "dual": "complex64 blocks", "bar64": "complex64 blocks",
+               "band": "complex64 blocks"}[pipe.refine_src]
+        ref = "regenerated from the FP64 generator band" if pipe.refine_src == "band" else "complex128 blocks"
+        parts.append(f"FP32 Jacobi on the {src} + FP64 Rayleigh-Ritz refinement with {ref}" +
+                     (f" ({size(f32)})" if f64 else ""))
     if f64:
-        parts.append("FP64 Householder tridiagonalisation + bisection" + which(f64))
-    return "; ".join(parts)
+        parts.append("FP64 Householder tridiagonalisation + bisection" + (f" ({size(f64)})" if f32 else ""))
+    only64 = not f32 and pipe.refine_src == "direct"
+    return "; ".join(parts), ("f64" if only64 else "fp32+fp64"), f64
+
+
+def block_errors(pipe, which, insts, checked_idx, refs):
+    """Largest absolute entry errors (Ha) of the Fourier blocks a route's
+    solve reads, against the oracle's, and relative to the largest entry."""
+    import numpy as np
+    out = {}
+    for name, key in (("H", which[0]), ("S", which[1])):
+        got = pipe.stacks(key)
+        ea, er = 0.0, 0.0
+        for i, ref in zip(checked_idx, refs):
+            want = ref[name + "_bar"]
+            d = float(np.abs(got[i].astype(np.complex128) - want).max())
+            ea = max(ea, d)
+            er = max(er, d / float(np.abs(want).max()))
+        out[f"max_abs_d{name}bar_ha"] = ea
+        out[f"max_rel_d{name}bar"] = er
+    return out
+
+
+def leg(cfg, args, torch, np, lhf, Pipeline, headline):
+    from synth import config_c4_lattices, make_config
+    from oracle import separable
+    if cfg == "c4":
+        insts = config_c4_lattices()
+        checked_idx = list(C4_CHECK)
+    else:
+        insts = [make_config(cfg)]
+        checked_idx = [0]
+    checked = [insts[i] for i in checked_idx]
+    chain = all(i.L[1] == 1 and i.L[2] == 1 for i in insts)
+    pipes = {"tuned": Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=lhf.LHF_GRAM_FP64),
+             "fp64": Pipeline(insts, prec=lhf.LHF_PREC_FP64),
+             "fp32": Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=lhf.LHF_GRAM_BF16X3,
+                              refine_src="band" if chain else "bar64", fp32_solve=True)}
+    tuning = {name: p.autotune().as_dict() for name, p in pipes.items()}
+    graphs = {name: p.capture() for name, p in pipes.items()}
+    for g in graphs.values():
+        for _ in range(args.warmup):
+            g.lhf_graph_launch()
+    torch.cuda.synchronize()
+
+    # accuracy against the oracle (its first run is also the CPU baseline's first run)
+    t0 = time.perf_counter()
+    refs = [separable.solve(inst) for inst in checked]
+    t_oracle = time.perf_counter() - t0
+    ref_eigs = [np.sort(r["eig"], axis=-1) for r in refs]
+    # condition numbers of the overlap blocks (they bound how the block errors reach the eigenvalues)
+    kappas = []
+    for r in refs:
+        ev = np.linalg.eigvalsh(r["S_bar"].reshape(-1, r["S_bar"].shape[-1], r["S_bar"].shape[-1]))
+        kappas.append(ev[:, -1] / ev[:, 0])
+    kap = np.concatenate(kappas)
+    acc = {}
+    for name, p in pipes.items():
+        graphs[name].lhf_graph_launch()
+        torch.cuda.synchronize()
+        all_w = p.eigenvalues()
+        ea, er, per_m0 = 0.0, 0.0, {}
+        for i, ref in zip(checked_idx, ref_eigs):
+            d = np.abs(all_w[i] - ref)
+            ea = max(ea, float(d.max()))
+            er = max(er, float((d / np.maximum(np.abs(ref), 1.0)).max()))
+            m0 = insts[i].m0
+            per_m0[m0] = max(per_m0.get(m0, 0.0), float(d.max()))
+        a = {"max_abs_eig_err_ha": ea, "max_rel_eig_err": er, "info_ok": bool((p.info.cpu().numpy() == 0).all())}
+        if len(per_m0) > 1:
+            a["max_abs_eig_err_ha_by_m0"] = {str(k): v for k, v in sorted(per_m0.items())}
+        # the Fourier blocks the route's solve reads
+        if p.prec == lhf.LHF_PREC_FP64:
+            a.update(block_errors(p, ("H_bar", "S_bar"), insts, checked_idx, refs))
+        elif p.refine_src == "direct":
+            a.update(block_errors(p, ("H_bar64", "S_bar64"), insts, checked_idx, refs))
+        else:
+            a.update({k + "_c64": v for k, v in block_errors(p, ("H_bar", "S_bar"), insts, checked_idx, refs).items()})
+        acc[name] = a
+
+    steps = args.steps if cfg != "c4" else max(5, min(args.steps, 10))
+    sec = {name: time_graph(graphs[name], steps, torch) for name in pipes}
+    nblk = sum(inst.ncells for inst in insts)
+    # stage times: each call of the step issued back to back between two events
+    stage_ms = {name: {st: event_ms(fn, steps, torch) for st, fn in p.stages()} for name, p in pipes.items()}
+
+    routes = {name: route_of(p, insts) for name, p in pipes.items()}
+    R = insts[0].R
+    pt = pipes["tuned"]
+    desc, dtype, f64 = routes["tuned"]
+    classes = sorted({heev_class(i.m0) for i in insts})
+    solve_dtype = "f64" if all(c in f64 for c in classes) else "f32"
+    ms_heev = stage_ms["tuned"]["eigensolve"]
+    flops = sum(canonical_blocks(i.L) * HEEV_FLOPS_PER_M3 * i.m0 ** 3 for i in insts)
+    flops_kernel = heev_flops_kernel(insts, f64, R)
+    achieved = flops / (ms_heev * 1e-3) / 1e12
+    tuned_t = pt.plan.lhf_plan_get_tuning()
+    eig_route = f"fp64={tuned_t.heev_fp64},wide={tuned_t.heev_wide}"
+    sep = pt.separable()
+    fourier_bytes = sep_bytes(pt, insts) if sep else dft_bytes(pt, insts, 16)
+    ms_fourier = stage_ms["tuned"]["fourier"]
+    fourier_gbs = fourier_bytes / (ms_fourier * 1e-3) / 1e9
+    out = {
+        "workload": f"{cfg}: {WORKLOADS[cfg]}", "lattices": len(insts), "k_point_blocks": nblk,
+        "m0": sorted({i.m0 for i in insts}),
+        "value": nblk / sec["tuned"], "ms_per_step": sec["tuned"] * 1e3, "dtype": dtype, "path": desc,
+        "fp64_path": {"value": nblk / sec["fp64"], "ms_per_step": sec["fp64"] * 1e3, "dtype": "f64",
+                      "path": routes["fp64"][0]},
+        "fp32_path": {"value": nblk / sec["fp32"], "ms_per_step": sec["fp32"] * 1e3, "dtype": routes["fp32"][1],
+                      "path": routes["fp32"][0], "vs_fp64": sec["fp64"] / sec["fp32"]},
+        "tuned_vs_fp64": sec["fp64"] / sec["tuned"],
+        "stage_ms": stage_ms,
+        "accuracy": {"lattices_checked": len(checked), "oracle_s": t_oracle,
+                     "kappa_Sbar": {"max": float(kap.max()), "median": float(np.median(kap))}, **acc},
+        "roofline": {"bound": "alu", "kernel": f"eigensolve (lhf_heev_batched: {desc.split('; ')[-1]})",
+                     "dtype": solve_dtype, "achieved": achieved, "peak": PEAK_TFLOPS[solve_dtype],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[solve_dtype],
+                     "traffic": traffic_bytes(cfg, "eigensolve", eig_route),
+                     "flops_per_launch": flops, "work_per_block": "150 m0^3 (distinct blocks)",
+                     "kernel_flops_per_launch": flops_kernel,
+                     "kernel_tflops": flops_kernel / (ms_heev * 1e-3) / 1e12, "avg_launch_ms": ms_heev},
+        "roofline_fourier": {"bound": "hbm",
+                             "kernel": ("separable Fourier blocks (lhf_fourier_blocks: gram_dft + sep_fused, FP64 "
+                                        "Grams to complex128)" if sep else
+                                        "block DFT (lhf_block_fft, FP64 stacks to complex128)"),
+                             "achieved": fourier_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": fourier_gbs / HBM_PEAK_GBS,
+                             "traffic": traffic_bytes(cfg, "fourier", "sep" if sep else "dft"),
+                             "bytes_per_launch": fourier_bytes, "avg_launch_ms": ms_fourier},
+        "tuning": tuning,
+    }
+    if headline and not args.no_cpu_baseline:
+        runs = [t_oracle]
+        while sum(runs) < 10.0 and len(runs) < 8:
+            t0 = time.perf_counter()
+            for inst in checked:
+                separable.solve(inst)
+            runs.append(time.perf_counter() - t0)
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        except Exception:
+            cores = os.cpu_count()
+        tmed = float(np.median(runs))
+        nchk = sum(inst.ncells for inst in checked)
+        what = (f"the whole {cfg} lattice" if len(checked) == len(insts) else
+                f"{len(checked)} of the {len(insts)} lattices (one per basis size)")
+        out["cpu_baseline"] = {
+            "value": nchk / tmed, "unit": "blocks/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{what} ({nchk} blocks) through the oracle's separable route (1D Grams for every shift, "
+                      f"combination, FFT, batched LAPACK eigensolves), median of {len(runs)} runs of {tmed:.2f} s"}
+    for g in graphs.values():
+        g.close()
+    return out
 
 
 def bench_c5(torch, np, lhf, steps):
@@ -235,9 +425,9 @@ def apply_tuning(pipe, spec):
 def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
     """Kernels for a FETCH_SIZE / WRITE_SIZE counter run: a plain copy of
     512 MiB (reads and writes exactly that many bytes: the scale of the
-    counters), then three eager steps of the mixed and the FP64 paths; the
-    mixed plan takes the tuning fields given by --mixed-tuning (a JSON object,
-    e.g. the autotuned route of a timed run), the FP64 plan its defaults."""
+    counters), then three eager steps of the tuned mixed plan (with the tuning
+    fields given by --mixed-tuning, e.g. the route of a timed run) and of the
+    FP64 plan with its defaults."""
     src = torch.ones(512 << 20, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
@@ -254,9 +444,9 @@ def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
 
 
 def probe_mfma(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
-    """Kernels for an MFMA counter run: three eager steps of the mixed path
-    with each Gram arithmetic (the assembly's MFMA kernels), with the tuning
-    fields of --mixed-tuning (e.g. the Gram tile of a timed run)."""
+    """Kernels for an MFMA counter run: three eager mixed steps with each Gram
+    arithmetic (the assembly's MFMA kernels), with the tuning fields of
+    --mixed-tuning (e.g. the Gram tile of a timed run)."""
     insts = config_c4_lattices() if args.config == "c4" else [make_config(args.config)]
     for gram, src in ((lhf.LHF_GRAM_FP64, "dual"), (lhf.LHF_GRAM_FP32, "bar64"), (lhf.LHF_GRAM_BF16X3, "bar64")):
         pipe = Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=gram, refine_src=src)
@@ -286,134 +476,25 @@ def main():
     if args.probe_mfma:
         probe_mfma(args, torch, lhf, Pipeline, make_config, config_c4_lattices)
         return
-    if args.config == "c4":
-        insts = config_c4_lattices()
-        checked = [insts[i] for i in C4_CHECK]
-    else:
-        insts = [make_config(args.config)]
-        checked = insts
-    # mixed: FP64 MFMA Grams (which the FP64 refinement needs anyway), FP64
-    # stacks, one FP64 block DFT writing complex128 blocks, which the FP32
-    # solve reads and rounds; mixed_bf16x3: FP32 stacks from separate bf16
-    # hi+lo split Grams and a complex64 DFT, reported beside it
-    pipes = {"mixed": Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=lhf.LHF_GRAM_FP64),
-             "fp64": Pipeline(insts, prec=lhf.LHF_PREC_FP64),
-             "mixed_bf16x3": Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=lhf.LHF_GRAM_BF16X3,
-                                      refine_src="band" if all(i.L[1] == 1 and i.L[2] == 1 for i in insts)
-                                      else "bar64")}
-    tuning = {name: p.autotune().as_dict() for name, p in pipes.items()}
-    graphs = {name: p.capture() for name, p in pipes.items()}
-    for g in graphs.values():
-        for _ in range(args.warmup):
-            g.lhf_graph_launch()
-    torch.cuda.synchronize()
-
-    # accuracy gate against the CPU oracle (also the CPU baseline's first run)
-    from oracle import separable
-    t0 = time.perf_counter()
-    refs = [np.sort(separable.solve(inst)["eig"], axis=-1) for inst in checked]
-    t_oracle_first = time.perf_counter() - t0
-    errs = {}
-    for name, p in pipes.items():
-        graphs[name].lhf_graph_launch()
-        torch.cuda.synchronize()
-        all_w = p.eigenvalues()
-        got = {inst.name: w for inst, w in zip(insts, all_w)}
-        ea, er = 0.0, 0.0
-        for inst, ref in zip(checked, refs):
-            w = got[inst.name]
-            ea = max(ea, float(np.abs(w - ref).max()))
-            er = max(er, float((np.abs(w - ref) / np.maximum(np.abs(ref), 1.0)).max()))
-        errs[name] = (ea, er, bool((p.info.cpu().numpy() == 0).all()))
-
-    # timed region: graph replays
-    sec = {name: time_graph(graphs[name], args.steps, torch) for name in pipes}
-    nblk = sum(inst.ncells for inst in insts)
-    value = nblk / sec["mixed"]
-
-    # rooflines, event-timed on the stream the kernels run on
-    pm = pipes["mixed"]
-    sep = pm.separable()   # the Fourier-block route the tuned step takes
-    if sep:
-        ms_dft = event_ms(lambda: pm.plan.lhf_fourier_blocks(pm.grams64, pm.H_bar64, pm.S_bar64, pm.ws),
-                          args.steps, torch)
-        bytes_alg = sep_bytes(pm, insts)
-    else:
-        ms_dft = event_ms(lambda: pm.plan.lhf_block_fft(lhf.LHF_PREC_FP64, pm.H_gen64, pm.S_gen64, pm.H_bar64,
-                                                         pm.S_bar64, pm.ws), args.steps, torch)
-        bytes_alg = dft_bytes(pm, insts, kind="fp64")
-    achieved = bytes_alg / (ms_dft * 1e-3) / 1e9
-    flags = lhf.LHF_HEEV_REFINE_FP64
-    ms_heev = event_ms(lambda: pm.plan.lhf_heev_batched(flags, None, None, pm.w, pm.info, pm.ws,
-                                                         H_bar64=pm.H_bar64, S_bar64=pm.S_bar64,
-                                                         H_gen64=pm.H_gen64, S_gen64=pm.S_gen64),
-                       args.steps, torch)
-    R = insts[0].R
-    fp64_mask = pm.plan.lhf_plan_get_tuning().heev_fp64
-    flops = heev_flops(insts, pm.prec, R, fp64_mask)
-    tflops = flops / (ms_heev * 1e-3) / 1e12
-
+    head = leg(args.config, args, torch, np, lhf, Pipeline, headline=True)
+    print(f"[bench] {args.config}: tuned {head['ms_per_step']:.4f} ms/step, fp64 {head['fp64_path']['ms_per_step']:.4f}, "
+          f"fp32 {head['fp32_path']['ms_per_step']:.4f}", file=sys.stderr, flush=True)
+    legs = {}
+    for cfg in [c for c in args.legs.split(",") if c and c != args.config]:
+        legs[cfg] = leg(cfg, args, torch, np, lhf, Pipeline, headline=False)
+        print(f"[bench] {cfg}: tuned {legs[cfg]['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     c5 = None if args.no_c5 else bench_c5(torch, np, lhf, args.steps)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        runs = [t_oracle_first]
-        while sum(runs) < 10.0 and len(runs) < 8:
-            t0 = time.perf_counter()
-            for inst in checked:
-                separable.solve(inst)
-            runs.append(time.perf_counter() - t0)
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-        except Exception:
-            cores = os.cpu_count()
-        tmed = float(np.median(runs))
-        nchk = sum(inst.ncells for inst in checked)
-        what = (f"the whole {args.config} lattice" if len(checked) == len(insts) else
-                f"{len(checked)} of the {len(insts)} lattices (one per basis size)")
-        cpu = {"value": nchk / tmed, "unit": "blocks/s", "cores": int(cores), "kind": "oracle",
-               "sample": f"{what} ({nchk} blocks) through the oracle's separable route (1D Grams for every "
-                         f"shift, combination, FFT, batched LAPACK eigensolves), median of {len(runs)} runs "
-                         f"of {tmed:.2f} s"}
-
-    tuned = pm.plan.lhf_plan_get_tuning()
-
-    def traffic(kind):
-        t = TRAFFIC_KIB.get(args.config, {}).get(kind)
-        if kind == "eig":
-            t = (t or {}).get(f"fp64={tuned.heev_fp64},wide={tuned.heev_wide}")
-        return None if t is None else t * 1024.0
-
-    m0s = sorted({inst.m0 for inst in insts})
+    cpu = head.pop("cpu_baseline", None)
     line = {
-        "metric": METRIC, "value": value, "unit": "blocks/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": sec["mixed"] * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "fp32+fp64", "data": "synthetic",
-        "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "lattices": len(insts),
-                   "k_point_blocks": nblk, "m0": m0s if len(m0s) > 1 else m0s[0],
-                   "path": ("mixed: FP64 MFMA Grams, " +
-                            ("Fourier blocks formed separably from the Grams (complex128, no generator stacks)"
-                             if sep else "FP64 stacks, one block DFT writing complex128 blocks") +
-                            "; " + eig_route(m0s, fp64_mask) + "; one hipGraph replay per step")},
-        "fp64_path": {"value": nblk / sec["fp64"], "ms_per_step": sec["fp64"] * 1e3, "dtype": "f64"},
-        "mixed_bf16x3_path": {"value": nblk / sec["mixed_bf16x3"], "ms_per_step": sec["mixed_bf16x3"] * 1e3,
-                              "max_abs_eig_err_ha": errs["mixed_bf16x3"][0], "info_ok": errs["mixed_bf16x3"][2]},
-        "accuracy": {"lattices_checked": len(checked),
-                     "mixed_max_abs_eig_err_ha": errs["mixed"][0], "mixed_info_ok": errs["mixed"][2],
-                     "fp64_max_rel_eig_err": errs["fp64"][1], "fp64_info_ok": errs["fp64"][2]},
-        "roofline": {"bound": "alu", "kernel": "eigensolve (lhf_heev_batched: " + eig_route(m0s, fp64_mask) + ")",
-                     "achieved": tflops, "peak": 157.3, "unit": "TFLOP/s", "frac": tflops / 157.3,
-                     "traffic": traffic("eig"), "flops_per_launch": flops, "avg_launch_ms": ms_heev},
-        "roofline_dft": {"bound": "hbm",
-                         "kernel": ("separable Fourier blocks (lhf_fourier_blocks: gram_dft + sep_fused, FP64 Grams "
-                                    "to complex128)" if sep else "block DFT (lhf_block_fft, FP64 stacks to complex128)"),
-                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic("sep" if sep else "dft"),
-                         "bytes_per_launch": bytes_alg, "avg_launch_ms": ms_dft},
-        "tuning": tuning,
-        "dirichlet_c5": c5,
-        "cpu_baseline": cpu,
+        "metric": METRIC, "value": head["value"], "unit": "blocks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": head["dtype"], "data": "synthetic",
+        "config": {"workload": head["workload"], "lattices": head["lattices"], "k_point_blocks": head["k_point_blocks"],
+                   "m0": head["m0"], "path": head["path"] + "; one hipGraph replay per step"},
+        "fp64_path": head["fp64_path"], "fp32_path": head["fp32_path"], "tuned_vs_fp64": head["tuned_vs_fp64"],
+        "accuracy": head["accuracy"], "stage_ms": head["stage_ms"],
+        "roofline": head["roofline"], "roofline_fourier": head["roofline_fourier"], "tuning": head["tuning"],
+        "legs": legs, "dirichlet_c5": c5, "cpu_baseline": cpu,
     }
     print(json.dumps(line))
 

@@ -79,7 +79,10 @@ enum { LHF_ANG_S = 0, LHF_ANG_PX = 1, LHF_ANG_PY = 2, LHF_ANG_PZ = 3 };
 /* heev flags. */
 enum {
   LHF_HEEV_VECTORS = 1u,      /* write eigenvectors to V                          */
-  LHF_HEEV_REFINE_FP64 = 2u   /* mixed precision: refine every eigenpair in FP64 */
+  LHF_HEEV_REFINE_FP64 = 2u,  /* mixed precision: refine every eigenpair in FP64 */
+  LHF_HEEV_FP32_SOLVE = 4u    /* mixed precision: every size class takes the FP32
+                                 solve + FP64 refinement, whatever the tuning's
+                                 heev_fp64 mask; the autotuner then keeps it 0 */
 };
 
 /*
@@ -262,7 +265,8 @@ int32_t lhf_fourier_blocks_noalloc(lhf_plan_t plan, const double* d_grams64, voi
  *   and rounds them itself (no complex64 copy is needed).
  * flags: LHF_HEEV_VECTORS, LHF_HEEV_REFINE_FP64 (mixed plans: after the FP32
  *   solve, form U^H Hbar U and U^H Sbar U in FP64 with FP64-accurate blocks
- *   and re-solve them in FP64).
+ *   and re-solve them in FP64), LHF_HEEV_FP32_SOLVE (mixed plans: no class
+ *   takes the FP64 solve alone).
  * d_H_bar64, d_S_bar64: device complex128 Fourier blocks used by refinement;
  *   may be NULL, then refinement regenerates each block from the FP64
  *   generator stacks d_H_gen64 / d_S_gen64 (band offsets only), which then

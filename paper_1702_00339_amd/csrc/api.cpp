@@ -126,7 +126,10 @@ int32_t lhf_heev_batched(lhf_plan_t p, uint32_t flags, const void* H_bar, const 
     set_error("H_bar, S_bar (or, refining a mixed plan, H_bar64 and S_bar64 alone), w and info are required");
     return LHF_ERR_INVALID;
   }
-  if (flags & ~(uint32_t)(LHF_HEEV_VECTORS | LHF_HEEV_REFINE_FP64)) { set_error("unknown flags"); return LHF_ERR_INVALID; }
+  if (flags & ~(uint32_t)(LHF_HEEV_VECTORS | LHF_HEEV_REFINE_FP64 | LHF_HEEV_FP32_SOLVE)) {
+    set_error("unknown flags");
+    return LHF_ERR_INVALID;
+  }
   if ((flags & LHF_HEEV_VECTORS) && !V) { set_error("LHF_HEEV_VECTORS needs V"); return LHF_ERR_INVALID; }
   const bool refine = p->prec == LHF_PREC_MIXED && (flags & LHF_HEEV_REFINE_FP64);
   if (p->prec == LHF_PREC_FP64 && (flags & LHF_HEEV_REFINE_FP64)) {

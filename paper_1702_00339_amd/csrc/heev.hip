@@ -1726,8 +1726,9 @@ hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, co
   }
   // mixed: FP32 solve, then FP64 refinement; with complex128 blocks, the
   // classes the plan marks take the FP64 solve alone instead
-  const bool f64[4] = {refine && Hbar64 && p->heev_fp64[0], refine && Hbar64 && p->heev_fp64[1],
-                       refine && Hbar64 && p->heev_fp64[2], refine && Hbar64 && p->heev_fp64[3]};
+  const bool any64 = refine && Hbar64 && !(flags & LHF_HEEV_FP32_SOLVE);
+  const bool f64[4] = {any64 && p->heev_fp64[0], any64 && p->heev_fp64[1], any64 && p->heev_fp64[2],
+                       any64 && p->heev_fp64[3]};
   if (f64[0] || f64[1] || f64[2] || f64[3]) {
     const int vm = wantv ? 1 : 0;
     const double eps = 1.1102230246251565e-16;

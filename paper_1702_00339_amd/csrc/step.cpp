@@ -399,7 +399,8 @@ int32_t lhf_plan_autotune(lhf_plan_t p, const lhf_step_args* a, lhf_stream_t str
   // (the latter wins where the cost of a rotation, not its arithmetic, sets
   // the time); the two are searched together, since the best layout of one
   // solver need not be that of the other
-  const bool alone = p->prec == LHF_PREC_MIXED && (a->heev_flags & LHF_HEEV_REFINE_FP64) && a->H_bar64;
+  const bool alone = p->prec == LHF_PREC_MIXED && (a->heev_flags & LHF_HEEV_REFINE_FP64) && a->H_bar64 &&
+                     !(a->heev_flags & LHF_HEEV_FP32_SOLVE);
   for (int c = 0; c < 4 && st == LHF_OK; ++c) {
     if (p->ncanon[c] == 0) continue;
     lhf_tuning cur{};

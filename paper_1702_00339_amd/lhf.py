@@ -20,7 +20,7 @@ LHF_OK, LHF_ERR_INVALID, LHF_ERR_UNSUPPORTED, LHF_ERR_WORKSPACE, LHF_ERR_HIP, LH
 LHF_PREC_FP64, LHF_PREC_MIXED = 0, 1
 LHF_GRAM_FP64, LHF_GRAM_FP32, LHF_GRAM_BF16X3 = 0, 1, 2
 LHF_BC_PERIODIC, LHF_BC_DIRICHLET = 0, 1
-LHF_HEEV_VECTORS, LHF_HEEV_REFINE_FP64 = 1, 2
+LHF_HEEV_VECTORS, LHF_HEEV_REFINE_FP64, LHF_HEEV_FP32_SOLVE = 1, 2, 4
 
 
 class lhf_cell(C.Structure):

@@ -30,10 +30,12 @@ class Pipeline:
     (lhf_fourier_blocks; no generator stacks are written), "dft" generator
     stacks and a block DFT, "auto" the plan's setting (separable where the
     plan qualifies; the autotuner may change it).  The choice is the plan's
-    tuning field fourier_sep, which lhf_step follows as well."""
+    tuning field fourier_sep, which lhf_step follows as well.
+    ``fp32_solve`` (mixed path): every size class takes the FP32 solve and
+    the FP64 refinement (LHF_HEEV_FP32_SOLVE), never the FP64 solve alone."""
 
     def __init__(self, instances, prec=lhf.LHF_PREC_FP64, gram=lhf.LHF_GRAM_BF16X3, refine_src="auto",
-                 want_vectors=False, device="cuda", L0=None, fourier="auto"):
+                 want_vectors=False, device="cuda", L0=None, fourier="auto", fp32_solve=False):
         if not isinstance(instances, (list, tuple)):
             instances = [instances]
         self.plan = lhf.Plan(instances, prec=prec, gram=gram if prec == lhf.LHF_PREC_MIXED else lhf.LHF_GRAM_FP64,
@@ -54,6 +56,7 @@ class Pipeline:
         self.w = torch.empty(int(sz.w_elems), dtype=torch.float64, device=dev)
         self.info = torch.empty(B, dtype=torch.int32, device=dev)
         self.want_vectors = want_vectors
+        self.fp32_solve = bool(fp32_solve) and prec == lhf.LHF_PREC_MIXED
         self.V = None
         if want_vectors:
             # FP64 solves and refined mixed solves both return complex128 vectors
@@ -93,6 +96,8 @@ class Pipeline:
         flags = lhf.LHF_HEEV_VECTORS if self.want_vectors else 0
         if self.prec == lhf.LHF_PREC_MIXED:
             flags |= lhf.LHF_HEEV_REFINE_FP64
+        if self.fp32_solve:
+            flags |= lhf.LHF_HEEV_FP32_SOLVE
         dual = self.prec == lhf.LHF_PREC_MIXED and self.refine_src in ("dual", "direct")
         direct = self.prec == lhf.LHF_PREC_MIXED and self.refine_src == "direct"
         return lhf.lhf_step_args(None if dual else ptr(self.H_gen), None if dual else ptr(self.S_gen),
@@ -113,40 +118,60 @@ class Pipeline:
     def autotune(self, cache_path=None):
         return self.plan.lhf_plan_autotune(self.step_args(), cache_path)
 
-    def step(self):
+    def stages(self):
+        """The step's C-ABI calls in order, as (name, callable) pairs: "assemble",
+        "fourier" (block DFT or separable formation; for the mixed "bar64"
+        route a second, FP64, transform "fourier64") and "eigensolve"."""
         p = self.plan
         sep = self.separable()
+        out = []
         if self.prec == lhf.LHF_PREC_FP64:
             if sep:
-                p.lhf_assemble_blocks(None, None, self.grams64, self.ws)
-                p.lhf_fourier_blocks(self.grams64, self.H_bar, self.S_bar, self.ws)
+                out.append(("assemble", lambda: p.lhf_assemble_blocks(None, None, self.grams64, self.ws)))
+                out.append(("fourier", lambda: p.lhf_fourier_blocks(self.grams64, self.H_bar, self.S_bar, self.ws)))
             else:
-                p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws)
-                p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen, self.S_gen, self.H_bar, self.S_bar, self.ws)
+                out.append(("assemble", lambda: p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws)))
+                out.append(("fourier", lambda: p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen, self.S_gen, self.H_bar,
+                                                               self.S_bar, self.ws)))
             flags = lhf.LHF_HEEV_VECTORS if self.want_vectors else 0
-            p.lhf_heev_batched(flags, self.H_bar, self.S_bar, self.w, self.info, self.ws, V=self.V)
-            return
+            out.append(("eigensolve", lambda: p.lhf_heev_batched(flags, self.H_bar, self.S_bar, self.w, self.info,
+                                                                 self.ws, V=self.V)))
+            return out
         if self.refine_src == "direct" and sep:
-            p.lhf_assemble_blocks(None, None, self.grams64, self.ws)
-            p.lhf_fourier_blocks(self.grams64, self.H_bar64, self.S_bar64, self.ws)
+            out.append(("assemble", lambda: p.lhf_assemble_blocks(None, None, self.grams64, self.ws)))
+            out.append(("fourier", lambda: p.lhf_fourier_blocks(self.grams64, self.H_bar64, self.S_bar64, self.ws)))
         elif self.refine_src == "direct":
-            p.lhf_assemble_blocks(None, None, self.grams64, self.ws, H_gen64=self.H_gen64, S_gen64=self.S_gen64)
-            p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.ws)
+            out.append(("assemble", lambda: p.lhf_assemble_blocks(None, None, self.grams64, self.ws,
+                                                                  H_gen64=self.H_gen64, S_gen64=self.S_gen64)))
+            out.append(("fourier", lambda: p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen64, self.S_gen64,
+                                                           self.H_bar64, self.S_bar64, self.ws)))
         elif self.refine_src == "dual":
-            p.lhf_assemble_blocks(None, None, self.grams64, self.ws, H_gen64=self.H_gen64, S_gen64=self.S_gen64)
-            p.lhf_block_fft_dual(self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.H_bar, self.S_bar,
-                                 self.ws)
+            out.append(("assemble", lambda: p.lhf_assemble_blocks(None, None, self.grams64, self.ws,
+                                                                  H_gen64=self.H_gen64, S_gen64=self.S_gen64)))
+            out.append(("fourier", lambda: p.lhf_block_fft_dual(self.H_gen64, self.S_gen64, self.H_bar64,
+                                                                self.S_bar64, self.H_bar, self.S_bar, self.ws)))
         else:
-            p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws, H_gen64=self.H_gen64,
-                                  S_gen64=self.S_gen64)
-            p.lhf_block_fft(lhf.LHF_PREC_MIXED, self.H_gen, self.S_gen, self.H_bar, self.S_bar, self.ws)
+            out.append(("assemble", lambda: p.lhf_assemble_blocks(self.H_gen, self.S_gen, self.grams64, self.ws,
+                                                                  H_gen64=self.H_gen64, S_gen64=self.S_gen64)))
+            out.append(("fourier", lambda: p.lhf_block_fft(lhf.LHF_PREC_MIXED, self.H_gen, self.S_gen, self.H_bar,
+                                                           self.S_bar, self.ws)))
         if self.refine_src == "bar64":
-            p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen64, self.S_gen64, self.H_bar64, self.S_bar64, self.ws)
+            out.append(("fourier64", lambda: p.lhf_block_fft(lhf.LHF_PREC_FP64, self.H_gen64, self.S_gen64,
+                                                              self.H_bar64, self.S_bar64, self.ws)))
         flags = lhf.LHF_HEEV_REFINE_FP64 | (lhf.LHF_HEEV_VECTORS if self.want_vectors else 0)
+        if self.fp32_solve:
+            flags |= lhf.LHF_HEEV_FP32_SOLVE
         direct = self.refine_src == "direct"
-        p.lhf_heev_batched(flags, None if direct else self.H_bar, None if direct else self.S_bar, self.w,
-                           self.info, self.ws, V=self.V,
-                           H_bar64=self.H_bar64, S_bar64=self.S_bar64, H_gen64=self.H_gen64, S_gen64=self.S_gen64)
+        out.append(("eigensolve", lambda: p.lhf_heev_batched(
+            flags, None if direct else self.H_bar, None if direct else self.S_bar, self.w, self.info, self.ws,
+            V=self.V, H_bar64=self.H_bar64, S_bar64=self.S_bar64, H_gen64=self.H_gen64, S_gen64=self.S_gen64)))
+        return out
+
+    def step(self):
+        """One step through the stage calls (lhf_assemble_blocks, the Fourier
+        blocks, lhf_heev_batched)."""
+        for _, fn in self.stages():
+            fn()
 
     def eigenvalues(self):
         """Per-lattice eigenvalue arrays [L1, L2, L3, m0] on the host."""
