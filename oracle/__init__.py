@@ -13,6 +13,8 @@ Modules
   separable  the paper's route: 1D Gram matrices, Hadamard combination into
              the generator blocks, Fourier blocks, per-block eigensolves
   toeplitz   dense block-Toeplitz operators and their circulant embedding
+  backtransform  eigenvectors of the full lattice problem from the
+             Fourier-block eigenvectors, U = (F^* x I) bdiag(Ubar_j)
 
 Every floating-point step is float64.  Readings of passages where the paper
 is silent or ambiguous are listed at the top of each module.
