@@ -284,6 +284,31 @@ int32_t lhf_heev_batched(lhf_plan_t plan, uint32_t flags, const void* d_H_bar, c
                          double* d_w, void* d_V, int32_t* d_info,
                          void* d_ws, size_t ws_bytes, lhf_stream_t stream);
 
+/* ---------------------------------------------------------------- eigenvectors
+ * Eigenvectors of the full lattice problem H u = lambda S u from the
+ * Fourier-block eigenvectors (Prop. 5.1, eq. eigvecA): U = (F^* x I_m0)
+ * bdiag(Ubar_j), F = F_L1 x F_L2 x F_L3 unitary, (F_L)_(j,k) = w^(j k) /
+ * sqrt(L), w = exp(-2 pi i / L).  Selection s = (j, c) -- Fourier block j =
+ * (j1 L2 + j2) L3 + j3 of lattice `lattice`, eigenvector column c -- gives the
+ * vector whose block on cell k = (k1 L2 + k2) L3 + k3 is
+ *   U[s][k][mu] = L^(-1/2) exp(+2 pi i (j1 k1/L1 + j2 k2/L2 + j3 k3/L3)) Ubar_j(mu, c),
+ * with eigenvalue lambda_(j, c); Sbar_j-orthonormal columns of Ubar_j give
+ * S-orthonormal vectors.  The conjugate block -j gives the complex conjugate
+ * vector (the same eigenvalue); Re and Im of the pair span the real
+ * eigenvectors of the real symmetric H.
+ * d_V: device complex128 [gen_elems], the eigenvectors lhf_heev_batched wrote
+ *   with LHF_HEEV_VECTORS (FP64 plans, or mixed plans with
+ *   LHF_HEEV_REFINE_FP64), column c of block j = eigenvector c (ascending).
+ * d_sel: device int32 [nsel][2] (j, c); a selection out of range gives a
+ *   vector of NaN (checked in the kernel, no out-of-range access).
+ * d_U: device complex128 [nsel][L1 L2 L3][m0], cell-major.
+ * nsel = 0 launches nothing.
+ * Errors: LHF_ERR_INVALID (NULL plan or pointer, lattice out of range,
+ * nsel < 0), LHF_ERR_UNSUPPORTED (more than 2^31 - 1 workgroups of 256
+ * outputs), LHF_ERR_HIP. */
+int32_t lhf_eigvecs_lattice(lhf_plan_t plan, int32_t lattice, const void* d_V, int32_t nsel, const int32_t* d_sel,
+                            void* d_U, lhf_stream_t stream);
+
 /* ---------------------------------------------------------------- Dirichlet chain
  * A box chain of L cells along dimension 1 (all dimensions Dirichlet, L2 = L3
  * = 1) with defect cells, as a perturbed block-Toeplitz pair (Sec. 3, the

@@ -116,6 +116,9 @@ void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tas
                     int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, bool& ok);
 hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* gh, double2* bar_h, double2* bar_s,
                               hipStream_t s);
+// eigvec.hip: full-lattice eigenvectors of selected (block, column) pairs of one lattice
+hipError_t launch_eigvecs(const lhf_plan_s* p, int li, const double2* V, int nsel, const int32_t* sel, double2* U,
+                          hipStream_t s);
 // heev.hip: every canonical block of every lattice, one launch per size class
 int heev_class(int m0);
 hipError_t launch_heev(const lhf_plan_s* p, uint32_t flags, const void* Hbar, const void* Sbar,

@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "lhf_fourier_blocks": (i32, [vp, vp, vp, vp, vp, sz, vp]),
         "lhf_fourier_blocks_noalloc": (i32, [vp, vp, vp, vp, vp]),
         "lhf_heev_batched": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "lhf_eigvecs_lattice": (i32, [vp, i32, vp, i32, vp, vp, vp]),
         "lhf_step": (i32, [vp, C.POINTER(lhf_step_args), vp]),
         "lhf_graph_create": (i32, [vp, C.POINTER(lhf_step_args), C.POINTER(vp)]),
         "lhf_graph_launch": (i32, [vp, vp]),
@@ -132,7 +133,7 @@ def exported_symbols():
     """Names the binding expects the library to export."""
     return ["lhf_plan_create", "lhf_plan_sizes", "lhf_plan_band", "lhf_workspace_size", "lhf_plan_destroy",
             "lhf_assemble_blocks", "lhf_block_fft", "lhf_block_fft_dual", "lhf_fourier_blocks",
-            "lhf_fourier_blocks_noalloc", "lhf_heev_batched", "lhf_step", "lhf_graph_create",
+            "lhf_fourier_blocks_noalloc", "lhf_heev_batched", "lhf_eigvecs_lattice", "lhf_step", "lhf_graph_create",
             "lhf_graph_launch", "lhf_graph_destroy", "lhf_plan_get_tuning", "lhf_plan_set_tuning",
             "lhf_plan_autotune", "lhf_toeplitz_create", "lhf_toeplitz_get_info", "lhf_toeplitz_blocks",
             "lhf_toeplitz_matvec_workspace", "lhf_toeplitz_matvec", "lhf_toeplitz_eigs_workspace",
@@ -250,6 +251,11 @@ class Plan:
     def lhf_fourier_blocks_noalloc(self, grams64, H_bar64, S_bar64):
         _check(load().lhf_fourier_blocks_noalloc(self.handle, _ptr(grams64), _ptr(H_bar64), _ptr(S_bar64),
                                                  _stream()))
+
+    def lhf_eigvecs_lattice(self, lattice, V, sel, U):
+        """sel: device int32 tensor [nsel, 2] of (block, column); U: complex128 [nsel, ncells, m0]."""
+        _check(load().lhf_eigvecs_lattice(self.handle, int(lattice), _ptr(V), int(sel.shape[0]), _ptr(sel), _ptr(U),
+                                          _stream()))
 
     def lhf_heev_batched(self, flags, H_bar, S_bar, w, info, ws, V=None, H_bar64=None, S_bar64=None,
                          H_gen64=None, S_gen64=None):
