@@ -253,12 +253,18 @@ def test_eigenvectors_fp64_and_refined(wide):
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_full_config_fp64_and_mixed(name):
-    """The configurations at full size: every block's eigenvalues."""
+    """The configurations at full size: every Fourier block entry and every
+    block's eigenvalues (the oracle's separable route equals the dense 3D
+    quadrature at the 8-cell chain's full size: test_oracle_pins)."""
     inst = make_config(name)
     print(inst.summary(), flush=True)
     res, ref = _eig_ref(inst)
     pipe = _run(inst, lhf.LHF_PREC_FP64)
     assert (pipe.info.cpu().numpy() == 0).all()
+    for key, want in (("H_bar", res["H_bar"]), ("S_bar", res["S_bar"])):
+        d = np.abs(pipe.stacks(key)[0] - want).max()
+        print(f"{name} fp64: max |d{key}| = {d:.2e} Ha", flush=True)
+        assert d <= 1e-12 * np.abs(want).max()
     got = pipe.eigenvalues()[0]
     err64 = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
     print(f"{name} fp64: max relative eig error {err64.max():.2e}", flush=True)
@@ -288,3 +294,84 @@ def test_heev_info_codes():
     assert got[1] == 1 and got[2] == -2 and got[0] == 0, got
     # blocks 1 and 3 are a conjugate pair: the pair is solved once, from block 1
     assert got[3] == got[1]
+
+
+# ----------------------------------------------------------------------------- the 64-lattice mix at full size
+
+# the cheapest lattice of every (L2, L3) pair (all four size classes, prime L1 = 23 and 61) and the
+# largest L1 (512 x 4 x 4)
+C4_COVER = (41, 59, 20, 28, 2, 47, 24, 62, 39, 31)
+
+
+@pytest.fixture(scope="module")
+def c4_plans():
+    from synth import config_c4_lattices
+    insts = config_c4_lattices()
+    out = {}
+    for prec in (lhf.LHF_PREC_FP64, lhf.LHF_PREC_MIXED):
+        pipe = _run(insts, prec)
+        info = pipe.info.cpu().numpy()
+        blocks = {k: pipe.stacks(k) for k in ("H_bar", "S_bar")} if prec == lhf.LHF_PREC_FP64 else None
+        out[prec] = (pipe.eigenvalues(), info, blocks)
+        del pipe
+    return insts, out
+
+
+@pytest.mark.parametrize("idx", C4_COVER)
+def test_c4_mix_lattice(c4_plans, idx):
+    """One grouped plan of all 64 lattices (one launch per stage and size
+    class); lattice idx against the oracle: Fourier blocks and eigenvalues
+    (FP64), eigenvalues (mixed).  The error is printed beside the condition
+    number of the overlap blocks, which bounds how block errors reach the
+    eigenvalues."""
+    insts, out = c4_plans
+    inst = insts[idx]
+    res, ref = _eig_ref(inst)
+    w64, info64, blocks = out[lhf.LHF_PREC_FP64]
+    wmx, infomx, _ = out[lhf.LHF_PREC_MIXED]
+    sb = res["S_bar"].reshape(-1, inst.m0, inst.m0)
+    ev = np.linalg.eigvalsh(sb)
+    kappa = float((ev[:, -1] / ev[:, 0]).max())
+    off = sum(i.ncells for i in insts[:idx])
+    assert (info64[off:off + inst.ncells] == 0).all() and (infomx[off:off + inst.ncells] == 0).all()
+    for key in ("H_bar", "S_bar"):
+        d = np.abs(blocks[key][idx] - res[key]).max()
+        assert d <= 1e-12 * np.abs(res[key]).max(), (key, d)
+    rel = (np.abs(w64[idx] - ref) / np.maximum(np.abs(ref), 1.0)).max()
+    err = np.abs(wmx[idx] - ref).max()
+    print(f"{inst.summary()}: fp64 rel {rel:.2e}, mixed abs {err:.2e} Ha, max kappa(Sbar) {kappa:.3g}", flush=True)
+    assert rel <= 1e-10
+    assert err <= 1e-8
+
+
+# ----------------------------------------------------------------------------- several nuclei per cell, off centre
+
+MULTI_NUC = [
+    (dict(L=(6, 1, 1), n=(48, 20, 20), n_s=3, n_p=1, seed=171), [1.0, 2.0], [[0.4, -0.3, 0.2], [-1.9, 0.5, -0.6]]),
+    (dict(L=(4, 3, 1), n=(32, 24, 16), n_s=2, n_p=1, seed=172), [3.0, 1.0, 1.0],
+     [[0.0, 0.0, 0.0], [2.2, -1.1, 0.4], [-2.3, 1.7, -0.9]]),
+    (dict(L=(3, 2, 2), n=(24, 16, 16), n_s=4, n_p=0, seed=173), [1.0, 1.0, 2.0, 0.5],
+     [[1.2, 1.2, -0.8], [-1.2, -1.2, 0.8], [2.4, 0.1, 2.4], [-0.2, -2.4, 0.3]]),
+]
+
+
+@pytest.mark.parametrize("case,Z,pos", MULTI_NUC, ids=["M0=2 chain", "M0=3 sheet", "M0=4 3D"])
+def test_several_off_centre_nuclei(case, Z, pos):
+    """M0 = 2, 3, 4 nuclei per cell at off-centre positions (up to 2.4 bohr of
+    the 2.5 bohr half-cell), through the ABI's lhf_cell.M0, Z and nuc: both
+    Fourier-block routes on the FP64 path, and the mixed path."""
+    inst = tiny_instance(**{"R": 8, **case})
+    inst.Z = np.asarray(Z, np.float64)
+    inst.nuc = np.asarray(pos, np.float64)
+    assert inst.M0 == len(Z)
+    res, ref = _eig_ref(inst)
+    for fourier in ("dft", "sep"):
+        pipe = _run(inst, lhf.LHF_PREC_FP64, fourier=fourier)
+        assert (pipe.info.cpu().numpy() == 0).all()
+        Hb = pipe.stacks("H_bar")[0]
+        assert np.abs(Hb - res["H_bar"]).max() <= 1e-12 * np.abs(res["H_bar"]).max(), fourier
+        got = pipe.eigenvalues()[0]
+        assert (np.abs(got - ref) <= 1e-10 * np.maximum(np.abs(ref), 1.0)).all(), fourier
+    pipe = _run(inst, lhf.LHF_PREC_MIXED)
+    assert (pipe.info.cpu().numpy() == 0).all()
+    assert np.abs(pipe.eigenvalues()[0] - ref).max() <= 1e-8
