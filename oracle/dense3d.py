@@ -15,6 +15,11 @@ on the 3D grid, and A_3 = A x S x S + S x A x S + S x S x A, S_3 = S x S x S
 act on the 3D nodal arrays (Kronecker action).  Then it solves H c = lambda S c
 densely (generalized problem of Sec. 2.1).
 
+With ``finite=True`` the potential is the finite lattice's own (eq.
+EwaldSumE, the exact box case (B) of Sec. 2.3): every nucleus of every cell
+k in {0..L1-1} x {0..L2-1} x {0..L3-1}, at its position, on every node, with
+no window and no replication.
+
 Defect cells (Dirichlet chains): the functions of a defect cell have their
 exponents multiplied by its scale factor, and its nuclei carry the defect
 charge: the change Z_def - Z_nu is added as the potential of an isolated
@@ -76,7 +81,7 @@ def basis_3d(inst, gs):
     return out
 
 
-def potential_3d(inst, gs):
+def potential_3d(inst, gs, finite=False):
     """Collocated lattice potential on every node, summed image by image.
 
     For each nucleus, sinc node and lattice image k (product of the 1D windows
@@ -87,11 +92,17 @@ def potential_3d(inst, gs):
     t, w = sinc_rule(inst)
     ys, wins = [], []
     for g in gs:
-        if g.L == 1:
+        if finite:
+            # every cell of the finite lattice: node positions relative to
+            # cell 0's centre, images at the other cells' centres
             ys.append(g.x - g.centres[0])
+            wins.append((np.arange(g.L), np.ones(g.L)))
+        elif g.L == 1:
+            ys.append(g.x - g.centres[0])
+            wins.append(window(g.L))
         else:
             ys.append(central_offsets(g)[0])
-        wins.append(window(g.L))
+            wins.append(window(g.L))
     p = np.zeros((gs[0].n, gs[1].n, gs[2].n))
     for nu in range(inst.M0):
         A = inst.nuc[nu]
@@ -116,8 +127,9 @@ def potential_3d(inst, gs):
     return p
 
 
-def dense_matrices(inst):
-    """Dense (H, S, T, V), each N x N, by 3D quadrature."""
+def dense_matrices(inst, finite=False):
+    """Dense (H, S, T, V), each N x N, by 3D quadrature (``finite``: the
+    finite lattice's own potential, eq. EwaldSumE)."""
     gs = grids(inst)
     G = basis_3d(inst, gs)
     shp = (gs[0].n, gs[1].n, gs[2].n)
@@ -135,7 +147,7 @@ def dense_matrices(inst):
         a = a + _apply_along(ops[2][1],
                              _apply_along(ops[1][1], _apply_along(ops[0][0], f, 0), 1), 2)  # A x S x S
         AG[r] = a.ravel()
-    p = potential_3d(inst, gs).ravel()
+    p = potential_3d(inst, gs, finite).ravel()
     S = G @ SG.T
     T = 0.5 * (G @ AG.T)
     V = G @ (G * p).T
