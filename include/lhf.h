@@ -349,6 +349,23 @@ typedef struct {
  * Errors: LHF_ERR_INVALID (descriptor), LHF_ERR_UNSUPPORTED (not a cell-aligned
  * Dirichlet chain, m0 > 32, ...), LHF_ERR_ALLOC, LHF_ERR_HIP. */
 int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out);
+/* The exact box operator of the same chain (Sec. 2.3, case (B)): the
+ * potential is the finite lattice's own, eq. EwaldSumE in the factor form of
+ * eq. EwaldTensorGl -- along the chain, sum over every cell c = 0..L-1 of
+ * Z_(nu, c) times the rank-R potential of nucleus nu of cell c, Z_(nu, c) =
+ * def_Z on defect cells, Z_nu elsewhere; no window, no replication -- and
+ * every block (k, m), |k - m| <= L0, is the block of the actual basis
+ * (defect exponents scaled) on the box grid with its walls.  It keeps the
+ * asymmetry of the finite lattice sum and the wall layer that the
+ * block-Toeplitz model of lhf_toeplitz_create replaces by the central cell.
+ * Returns a handle of the same kind: lhf_toeplitz_matvec applies the
+ * block-sparse operator (every block row in FP64, either precision),
+ * lhf_toeplitz_eigs runs block LOBPCG on it with the same circulant
+ * preconditioner (the embedding of the pristine generators),
+ * lhf_toeplitz_get_info reports ncross = L and ncross_blocks = every band
+ * block (k <= m), and lhf_toeplitz_blocks returns those blocks as the cross
+ * blocks.  Errors: as lhf_toeplitz_create. */
+int32_t lhf_box_exact_create(const lhf_box* box, lhf_toeplitz_t* out);
 int32_t lhf_toeplitz_get_info(lhf_toeplitz_t tp, lhf_toeplitz_info* out);
 /* Copy the model's blocks to device buffers (each may be NULL):
  * d_gen_H, d_gen_S: FP64 [L0 + 1][m0][m0], A_s row mu, column nu;

@@ -1,6 +1,7 @@
-// Dirichlet-chain operator: validation and derivation of the model, its
-// assembly on the device, the matvec entry point and the block LOBPCG driver
-// for the lowest eigenpairs.
+// Dirichlet-chain operators: validation and derivation of the perturbed
+// block-Toeplitz model or of the exact box operator, their assembly on the
+// device, the matvec entry point and the block LOBPCG driver for the lowest
+// eigenpairs.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -18,12 +19,15 @@ using namespace lhf;
 struct lhf_toeplitz_s {
   ToepDev host{};
   int device = 0;
+  bool exact = false;                   // the exact box operator: block-sparse, no Toeplitz part
   int L = 0, m0 = 0, L0 = 0, P = 0, N = 0, nX = 0, ncb = 0, njobs = 0, nrows = 0, nent = 0;
   double sigma = 0.0;
   std::vector<void*> allocs;            // every device allocation, freed by destroy
   ToepDev* d_desc = nullptr;
   Defect* d_defs = nullptr;
   double* d_vrep = nullptr;
+  double* d_vbox = nullptr;             // exact operator: finite-lattice potential [M0 R][n]
+  int32_t* d_cell_def = nullptr;        // exact operator: defect index per cell or -1
   double* d_trans = nullptr;
   ScalePair* d_pairs = nullptr;
   ToepJob* d_jobs = nullptr;
@@ -174,16 +178,16 @@ int32_t derive(const lhf_box& b, ToepDev& D, std::vector<Defect>& defs) {
 
 }  // namespace
 
-extern "C" {
-
-int32_t lhf_toeplitz_destroy(lhf_toeplitz_t t) {
+extern "C" int32_t lhf_toeplitz_destroy(lhf_toeplitz_t t) {
   if (!t) return LHF_OK;
   for (void* p : t->allocs) (void)hipFree(p);
   delete t;
   return LHF_OK;
 }
 
-int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out) {
+namespace {
+
+int32_t create(const lhf_box* box, bool exact, lhf_toeplitz_t* out) {
   if (!out) { set_error("out is NULL"); return LHF_ERR_INVALID; }
   *out = nullptr;
   if (!box) { set_error("box is NULL"); return LHF_ERR_INVALID; }
@@ -194,10 +198,11 @@ int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out) {
   const int L = D.L, m0 = D.m0, L0 = D.L0, nc = D.nc, mm = m0 * m0;
   std::vector<int> defect_of(L, -1);
   for (int i = 0; i < (int)defs.size(); ++i) defect_of[defs[i].cell] = i;
-  // X: defect cells and cells within L0 of a wall
+  // X: defect cells and cells within L0 of a wall; every cell for the exact
+  // operator, whose blocks are all computed
   std::set<int> X;
   for (int k = 0; k < L; ++k)
-    if (k < L0 || k > L - 1 - L0 || defect_of[k] >= 0) X.insert(k);
+    if (exact || k < L0 || k > L - 1 - L0 || defect_of[k] >= 0) X.insert(k);
   // scale pairs and jobs: generators first, then cross blocks (k <= m) ascending
   std::map<std::pair<int, int>, int> pair_id;
   std::vector<ScalePair> pairs;
@@ -220,7 +225,7 @@ int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out) {
   for (const auto& kmp : cross) {
     const int k = kmp.first, m = kmp.second;
     const int dk = defect_of[k], dm = defect_of[m];
-    jobs.push_back(ToepJob{k, m, 1, pid(dk, dm), std::max(1, (k - D.margin) * nc + 1),
+    jobs.push_back(ToepJob{k, m, exact ? 2 : 1, pid(dk, dm), std::max(1, (k - D.margin) * nc + 1),
                            std::min(D.n, (m + 1 + D.margin) * nc), dk, dm});
     km.push_back(k);
     km.push_back(m);
@@ -264,6 +269,7 @@ int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out) {
   if (!t) { set_error("out of host memory"); return LHF_ERR_ALLOC; }
   t->host = D;
   t->device = dev;
+  t->exact = exact;
   t->L = L; t->m0 = m0; t->L0 = L0; t->P = P; t->N = m0 * L; t->nX = (int)X.size();
   t->ncb = (int)cross.size();
   t->njobs = (int)jobs.size();
@@ -281,21 +287,25 @@ int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out) {
             dalloc(t, t->d_cH, (size_t)P * mm) && dalloc(t, t->d_cS, (size_t)P * mm) &&
             dalloc(t, t->d_cH32, (size_t)P * mm) && dalloc(t, t->d_cS32, (size_t)P * mm) &&
             dalloc(t, t->d_minv64, (size_t)P * mm) && dalloc(t, t->d_minv32, (size_t)P * mm);
+  if (ok && exact)
+    ok = upload(t, t->d_cell_def, defect_of.data(), defect_of.size()) && dalloc(t, t->d_vbox, (size_t)M0R * D.n);
   if (!ok) { lhf_toeplitz_destroy(t); set_error("lhf_toeplitz_create: device allocation failed"); return LHF_ERR_ALLOC; }
   hipStream_t s = nullptr;
   hipError_t e = toep_launch_vrep(t->d_desc, t->d_vrep, M0R, nc, s);
+  if (e == hipSuccess && exact) e = toep_launch_vbox(t->d_desc, t->d_defs, t->d_cell_def, t->d_vbox, M0R, D.n, s);
   if (e == hipSuccess)
     e = toep_launch_transverse(t->d_desc, t->d_defs, t->d_pairs, (int)pairs.size(), m0, M0R, t->d_trans, s);
   if (e == hipSuccess)
-    e = toep_launch_blocks(t->d_desc, t->d_defs, t->d_jobs, t->njobs, m0, wmax, t->d_vrep, t->d_trans, t->d_blkH,
-                           t->d_blkS, s);
+    e = toep_launch_blocks(t->d_desc, t->d_defs, t->d_jobs, t->njobs, m0, wmax, t->d_vrep, t->d_vbox, t->d_trans,
+                           t->d_blkH, t->d_blkS, s);
   const double* genH = t->d_blkH;
   const double* genS = t->d_blkS;
   const double* crH = t->d_blkH + (size_t)(L0 + 1) * mm;
   const double* crS = t->d_blkS + (size_t)(L0 + 1) * mm;
+  // correction entries D = H_model - T; for the exact operator the blocks themselves
   if (e == hipSuccess)
-    e = toep_launch_delta(t->d_desc, t->d_row_ptr, t->d_row_cell, t->nrows, t->d_ent, genH, genS, crH, crS, t->d_dH,
-                          t->d_dS, m0, s);
+    e = toep_launch_delta(t->d_desc, t->d_row_ptr, t->d_row_cell, t->nrows, t->d_ent, exact ? nullptr : genH,
+                          exact ? nullptr : genS, crH, crS, t->d_dH, t->d_dS, m0, s);
   if (e == hipSuccess) e = toep_launch_chat(t->d_desc, genH, genS, t->d_cH, t->d_cS, m0, P, L0, s);
   if (e == hipSuccess) e = toep_launch_to32(t->d_cH, t->d_cH32, (int64_t)P * mm, s);
   if (e == hipSuccess) e = toep_launch_to32(t->d_cS, t->d_cS32, (int64_t)P * mm, s);
@@ -355,6 +365,14 @@ int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out) {
   return LHF_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out) { return create(box, false, out); }
+
+int32_t lhf_box_exact_create(const lhf_box* box, lhf_toeplitz_t* out) { return create(box, true, out); }
+
 int32_t lhf_toeplitz_get_info(lhf_toeplitz_t t, lhf_toeplitz_info* out) {
   if (!t || !out) { set_error("NULL operator or output"); return LHF_ERR_INVALID; }
   out->L = t->L;
@@ -404,7 +422,7 @@ int32_t lhf_toeplitz_matvec(lhf_toeplitz_t t, int32_t prec, int32_t ncols, const
   hipError_t e = toep_launch_apply(prec, t->L, t->m0, t->P, ncols, x, ld, opH, opS,
                                    f64 ? (const void*)t->d_tw64 : (const void*)t->d_tw32, w, w + part, w + 2 * part,
                                    yH, yS, t->d_row_ptr, t->d_row_cell, t->nrows, t->d_ent, t->d_dH, t->d_dS,
-                                   static_cast<hipStream_t>(stream));
+                                   static_cast<hipStream_t>(stream), t->exact);
   return hip_status(e, "lhf_toeplitz_matvec");
 }
 

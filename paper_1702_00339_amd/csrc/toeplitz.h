@@ -32,7 +32,8 @@ struct ToepDev {
 
 // One block of the model: rows = functions of cell k, columns = functions of
 // cell m.  mode 0: pristine generator on the wall-free grid; 1: cross block of
-// the actual basis on the box grid.  dk, dm: defect index of the cells or -1;
+// the actual basis on the box grid; 2: block of the exact box operator (the
+// actual basis on the box grid, the finite lattice's own potential).  dk, dm: defect index of the cells or -1;
 // pair: index of the transverse Grams for the pair of exponent scales;
 // chain nodes [ilo, ihi] (inclusive) carry every non-negligible factor value.
 struct ToepJob {
@@ -58,11 +59,18 @@ struct Defect {
 
 // assembly (toeplitz.hip)
 hipError_t toep_launch_vrep(const ToepDev* d, double* vrep, int M0R, int nc, hipStream_t s);
+// the finite lattice's potential along the chain on every box node [M0 R][n]
+// (Z w_q folded in; cell_def[c]: defect index of cell c or -1)
+hipError_t toep_launch_vbox(const ToepDev* d, const Defect* defs, const int32_t* cell_def, double* vbox, int M0R,
+                            int n, hipStream_t s);
 hipError_t toep_launch_transverse(const ToepDev* d, const Defect* defs, const ScalePair* pairs, int npairs,
                                   int m0, int M0R, double* trans, hipStream_t s);
 // wmax: largest chain window (ihi - ilo + 1) over the jobs
+// vbox: the finite-lattice potential for mode-2 jobs (may be NULL without them)
 hipError_t toep_launch_blocks(const ToepDev* d, const Defect* defs, const ToepJob* jobs, int njobs, int m0, int wmax,
-                              const double* vrep, const double* trans, double* outH, double* outS, hipStream_t s);
+                              const double* vrep, const double* vbox, const double* trans, double* outH,
+                              double* outS, hipStream_t s);
+// genH, genS NULL: the entries are the model blocks themselves (no T to subtract)
 hipError_t toep_launch_delta(const ToepDev* d, const int32_t* row_ptr, const int32_t* row_cell, int nrows,
                              const CrossEntry* ent, const double* genH, const double* genS, const double* crossH,
                              const double* crossS, double* dH, double* dS, int m0, hipStream_t s);
@@ -72,11 +80,14 @@ hipError_t toep_launch_minv(const double2* V, const double* w, double sigma, dou
                             int P, int m0, hipStream_t s);
 hipError_t toep_launch_to32(const double2* src, float2* dst, int64_t n, hipStream_t s);
 // y = T x (+ crosses); prec: LHF_PREC_FP64 or LHF_PREC_MIXED.  op2 may be NULL
-// (one operator: yS unused).  cross lists may be empty (nrows = 0).
+// (one operator: yS unused).  cross lists may be empty (nrows = 0).  exact:
+// no Toeplitz part; y = the block rows' entries applied to x (every block row
+// must have entries).
 hipError_t toep_launch_apply(int prec, int L, int m0, int P, int ncols, const double* x, int ld,
                              const void* opH, const void* opS, const void* tw, void* xhat, void* yhatH,
                              void* yhatS, double* yH, double* yS, const int32_t* row_ptr, const int32_t* row_cell,
-                             int nrows, const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s);
+                             int nrows, const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s,
+                             bool exact = false);
 
 // dense FP64 kernels (lobpcg.hip); row-major [N][ld] blocks of vectors
 hipError_t dense_gram(int N, int k1, int k2, const double* A, int lda, const double* B, int ldb, double* part,

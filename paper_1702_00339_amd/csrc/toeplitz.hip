@@ -73,6 +73,33 @@ __global__ void __launch_bounds__(256) vrep_kernel(const ToepDev* __restrict__ d
   }
 }
 
+// The finite lattice's own potential along the chain (the exact box case,
+// eq. EwaldSumE in the factor form of eq. EwaldTensorGl): on box node i,
+// sum over cells c = 0..L-1 of Z_(nu, c) phi_q(x_i; X_c + a_nu), times w_q,
+// with the defect charge on defect cells.  Cells whose Gaussian term is below
+// exp(-1400) at the node are skipped (they add exactly zero); the sum runs in
+// ascending cell order.  Grid: (term, node chunk of 256).
+__global__ void __launch_bounds__(256) vbox_kernel(const ToepDev* __restrict__ dp, const Defect* __restrict__ defs,
+                                                   const int32_t* __restrict__ cell_def, double* __restrict__ vbox) {
+  const ToepDev& D = *dp;
+  const int r = blockIdx.x, nu = r / D.R, q = r % D.R;
+  const int i = blockIdx.y * 256 + threadIdx.x + 1;   // box node 1..n
+  if (i > D.n) return;
+  const double x = D.x0 + i * D.h, t = D.tq[q];
+  const double reach = 37.5 / t + D.h;                // t |x - A| > 37.4: term < exp(-1400)
+  const double X0 = -0.5 * D.L * D.a + 0.5 * D.a + D.nuc[nu][0];
+  int clo = (int)floor((x - reach - X0) / D.a), chi = (int)ceil((x + reach - X0) / D.a);
+  clo = max(clo, 0);
+  chi = min(chi, D.L - 1);
+  double acc = 0.0;
+  for (int c = clo; c <= chi; ++c) {
+    const int di = cell_def[c];
+    const double z = di >= 0 ? defs[di].Z : D.Z[nu];
+    acc += z * cell_gauss(x, D.h, t, X0 + c * D.a);
+  }
+  vbox[(int64_t)r * D.n + i - 1] = D.wq[q] * acc;
+}
+
 constexpr int kTChunk = 64;   // transverse nodes per LDS chunk
 
 // Transverse Grams of one pair of exponent scales and one dimension (2 or 3):
@@ -146,13 +173,16 @@ constexpr int kMaxEntries = 4;   // (mu, nu) entries per thread: m0^2 <= 1024
 
 // One block of the model per workgroup (see ToepJob).  The chain window
 // [ilo - 1, ihi + 1] of both cells' factors is staged in LDS (zero outside the
-// box for cross blocks); then the mass and stiffness Grams, and one potential
-// term at a time (V_rep terms, then the defect terms of the block's defect
-// cells) staged in LDS and contracted, times the transverse Grams.
+// box for cross and exact blocks); then the mass and stiffness Grams, and one
+// potential term at a time (V_rep terms, then the defect terms of the block's
+// defect cells; for exact blocks the finite-lattice terms, which hold the
+// defect charges already) staged in LDS and contracted, times the transverse
+// Grams.
 __global__ void __launch_bounds__(256) block_kernel(const ToepDev* __restrict__ dp,
                                                     const Defect* __restrict__ defs,
                                                     const ToepJob* __restrict__ jobs,
                                                     const double* __restrict__ vrep,
+                                                    const double* __restrict__ vbox,
                                                     const double* __restrict__ trans,
                                                     double* __restrict__ outH, double* __restrict__ outS) {
   extern __shared__ double lds[];
@@ -205,7 +235,12 @@ __global__ void __launch_bounds__(256) block_kernel(const ToepDev* __restrict__ 
     const int t = tt % M0R, src = tt / M0R;   // src 0: V_rep, 1: first defect, 2: second
     const int nu = t / D.R, q = t % D.R;
     __syncthreads();   // pot[] of the previous term has been consumed
-    if (src == 0) {
+    if (src == 0 && jb.mode == 2) {
+      for (int i = threadIdx.x; i < W; i += 256) {
+        const int node = jb.ilo + i;
+        pot[i] = node >= 1 && node <= D.n ? vbox[(int64_t)t * D.n + node - 1] : 0.0;
+      }
+    } else if (src == 0) {
       for (int i = threadIdx.x; i < W; i += 256) {
         int j = (jb.ilo + i - 1) % D.nc;
         if (j < 0) j += D.nc;
@@ -264,8 +299,10 @@ __global__ void __launch_bounds__(256) delta_kernel(const int32_t* __restrict__ 
       const int mu = e / m0, nu = e % m0;
       const int eb = ce.trans ? nu * m0 + mu : e;               // model block entry
       const int et = ce.m >= k ? e : nu * m0 + mu;              // T(k, m) = A_s or A_s^T
-      dH[(int64_t)j * mm + e] = crossH[(int64_t)ce.blk * mm + eb] - genH[(int64_t)s * mm + et];
-      dS[(int64_t)j * mm + e] = crossS[(int64_t)ce.blk * mm + eb] - genS[(int64_t)s * mm + et];
+      const double th = genH ? genH[(int64_t)s * mm + et] : 0.0;
+      const double ts = genS ? genS[(int64_t)s * mm + et] : 0.0;
+      dH[(int64_t)j * mm + e] = crossH[(int64_t)ce.blk * mm + eb] - th;
+      dS[(int64_t)j * mm + e] = crossS[(int64_t)ce.blk * mm + eb] - ts;
     }
   }
 }
@@ -457,10 +494,12 @@ constexpr int kCrossMG = 8;                    // row groups: thread group g own
 constexpr int kCrossAcc = kMaxM0 / kCrossMG;   // rows per thread
 
 // y_k += sum over the entries q of row r of D_q x_{m_q} for the affected block
-// row k = row_cell[r] (grid: rows, column chunks of kCrossJ, H / S).  Per entry
+// row k = row_cell[r] (grid: rows, column chunks of kCrossJ, H / S); SET: y_k =
+// the sum (the block-sparse product of the exact box operator).  Per entry
 // the workgroup stages D_q (m0 x m0) and the chunk's columns of the m0 rows of
 // block m_q of x in LDS; thread (j, g) accumulates rows g, g + 8, ... of
 // column j over the entries in order.
+template <bool SET>
 __global__ void __launch_bounds__(256) cross_apply_kernel(int m0, int ncols, const double* __restrict__ x, int ld,
                                                           const int32_t* __restrict__ row_ptr,
                                                           const int32_t* __restrict__ row_cell,
@@ -501,7 +540,10 @@ __global__ void __launch_bounds__(256) cross_apply_kernel(int m0, int ncols, con
 #pragma unroll
     for (int t = 0; t < kCrossAcc; ++t) {
       const int mu = g + kCrossMG * t;
-      if (mu < m0) y[((int64_t)k * m0 + mu) * ld + j] += acc[t];
+      if (mu < m0) {
+        double* yp = y + ((int64_t)k * m0 + mu) * ld + j;
+        *yp = SET ? acc[t] : *yp + acc[t];
+      }
     }
   }
 }
@@ -545,12 +587,18 @@ hipError_t toep_launch_transverse(const ToepDev* d, const Defect* defs, const Sc
   return hipGetLastError();
 }
 
+hipError_t toep_launch_vbox(const ToepDev* d, const Defect* defs, const int32_t* cell_def, double* vbox, int M0R,
+                            int n, hipStream_t s) {
+  hipLaunchKernelGGL(vbox_kernel, dim3(M0R, (n + 255) / 256), dim3(256), 0, s, d, defs, cell_def, vbox);
+  return hipGetLastError();
+}
+
 hipError_t toep_launch_blocks(const ToepDev* d, const Defect* defs, const ToepJob* jobs, int njobs, int m0,
-                                int wmax, const double* vrep, const double* trans, double* outH, double* outS,
-                                hipStream_t s) {
+                                int wmax, const double* vrep, const double* vbox, const double* trans, double* outH,
+                                double* outS, hipStream_t s) {
   const size_t lds = sizeof(double) * (2 * (size_t)m0 * (wmax + 2) + (size_t)wmax);
   (void)hipFuncSetAttribute((const void*)block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(block_kernel, dim3(njobs), dim3(256), lds, s, d, defs, jobs, vrep, trans, outH, outS);
+  hipLaunchKernelGGL(block_kernel, dim3(njobs), dim3(256), lds, s, d, defs, jobs, vrep, vbox, trans, outH, outS);
   return hipGetLastError();
 }
 
@@ -585,13 +633,19 @@ hipError_t toep_launch_to32(const double2* src, float2* dst, int64_t n, hipStrea
 hipError_t toep_launch_apply(int prec, int L, int m0, int P, int ncols, const double* x, int ld, const void* opH,
                              const void* opS, const void* tw, void* xhat, void* yhatH, void* yhatS, double* yH,
                              double* yS, const int32_t* row_ptr, const int32_t* row_cell, int nrows,
-                             const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s) {
+                             const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s, bool exact) {
+  const dim3 grid(nrows, (ncols + kCrossJ - 1) / kCrossJ, (exact ? yS : opS) ? 2 : 1);
+  if (exact) {
+    hipLaunchKernelGGL(cross_apply_kernel<true>, grid, dim3(256), 0, s, m0, ncols, x, ld, row_ptr, row_cell, ent, dH,
+                       dS, yH, yS);
+    return hipGetLastError();
+  }
   hipError_t e = prec == LHF_PREC_FP64
                      ? apply_t<double>(L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS, s)
                      : apply_t<float>(L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS, s);
   if (e != hipSuccess || nrows == 0) return e;
-  hipLaunchKernelGGL(cross_apply_kernel, dim3(nrows, (ncols + kCrossJ - 1) / kCrossJ, opS ? 2 : 1), dim3(256), 0, s, m0,
-                     ncols, x, ld, row_ptr, row_cell, ent, dH, dS, yH, yS);
+  hipLaunchKernelGGL(cross_apply_kernel<false>, grid, dim3(256), 0, s, m0, ncols, x, ld, row_ptr, row_cell, ent, dH,
+                     dS, yH, yS);
   return hipGetLastError();
 }
 
