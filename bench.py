@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--legs", default="c3,c4", help="further workloads reported in the same line ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the Dirichlet-chain (c5) measurement")
+    ap.add_argument("--no-box", action="store_true", help="skip the exact box-case measurements")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="for hardware-counter runs: a device copy of 512 MiB (the counters' scale), then three "
                          "eager steps of the tuned and the FP64 paths; prints nothing else")
@@ -412,6 +413,84 @@ def bench_c5(torch, np, lhf, steps):
             "L0": info.L0, "cross_cells": info.ncross, "embedding": P, "matvec_120_vectors": mv}
 
 
+def bench_box(torch, np, lhf, Pipeline, steps):
+    """The exact box operator (case (B): finite-lattice potential, every band
+    block) beside the block-Toeplitz model: time to the 32 lowest eigenpairs of
+    the 512-cell chain with 26 defect cells, and the largest difference of the
+    two spectra.  Then two qualitative comparisons of a chain in a box with the
+    periodic chain, on the 8-cell chain's cell (4 s functions, Z = 1; the
+    paper's hydrogen-chain workloads, stood in for), same grid spacing and
+    sinc rule in both: the 32 lowest eigenvalues at L = 128 and 256 (box by
+    LOBPCG, periodic from every Fourier block), and the mean energy of the
+    lowest band (L states) per cell against L (box: LOBPCG with nev = L, so
+    L <= 32; periodic up to 512)."""
+    from synth import make_config, make_instance
+    inst = make_config("c5")
+    out = {}
+    for name, exact in (("exact", True), ("model", False)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = lhf.Toeplitz(inst, exact=exact)
+        torch.cuda.synchronize()
+        t_create = time.perf_counter() - t0
+        w = torch.empty(32, dtype=torch.float64, device="cuda")
+        ws = op.eigs_workspace(32)
+        op.lhf_toeplitz_eigs(32, w, None, maxit=150, tol=1e-5, seed=1, ws=ws)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, res = op.lhf_toeplitz_eigs(32, w, None, maxit=150, tol=1e-5, seed=1, ws=ws)
+        torch.cuda.synchronize()
+        out[name] = {"create_ms": t_create * 1e3, "eigs_ms": (time.perf_counter() - t0) * 1e3,
+                     "lobpcg_iterations": it, "residual": res, "w": w.cpu().numpy()}
+        op.close()
+    d = np.abs(out["exact"]["w"] - out["model"]["w"])
+    res = {"workload": "c5 chain as the exact box operator (finite-lattice potential, every band block)",
+           "exact": {k: v for k, v in out["exact"].items() if k != "w"},
+           "model": {k: v for k, v in out["model"].items() if k != "w"},
+           "max_abs_diff_lowest32_ha": float(d.max()), "lowest_exact_ha": float(out["exact"]["w"][0]),
+           "lowest_model_ha": float(out["model"]["w"][0])}
+
+    def chain(L, bc):
+        pad = (6.0, 6.0, 6.0) if bc == "periodic" else (5.0 / 32, 6.0, 6.0)
+        i = make_instance(name=f"hchain_{bc}_{L}", L=(L, 1, 1), n=(16 * L, 128, 128), a=5.0, pad=pad, bc=bc,
+                          n_s=4, n_p=0, exp_range=(0.2, 8.0), Z=1, R=20, seed=1)
+        return i
+
+    def periodic_eigs(L):
+        pi = chain(L, "periodic")
+        pipe = Pipeline([pi], prec=lhf.LHF_PREC_FP64)
+        pipe.step()
+        torch.cuda.synchronize()
+        return pi, np.sort(pipe.eigenvalues()[0].ravel())
+
+    def box_eigs(L, nev, like):
+        bi = chain(L, "dirichlet")
+        bi.sinc_u0, bi.sinc_step = like.sinc_u0, like.sinc_step
+        op = lhf.Toeplitz(bi, exact=True)
+        w = torch.empty(nev, dtype=torch.float64, device="cuda")
+        op.lhf_toeplitz_eigs(nev, w, None, maxit=300, tol=1e-7, seed=2)
+        torch.cuda.synchronize()
+        op.close()
+        return w.cpu().numpy()
+
+    spectra = {}
+    for L in (128, 256):
+        pi, wp = periodic_eigs(L)
+        wb = box_eigs(L, 32, pi)
+        spectra[str(L)] = {"periodic_lowest": wp[:4].tolist(), "box_lowest": wb[:4].tolist(),
+                           "mean_shift_lowest32_ha": float(np.mean(wb - wp[:32])),
+                           "max_abs_shift_lowest32_ha": float(np.max(np.abs(wb - wp[:32])))}
+    per_cell = {"L": [], "periodic": [], "box": []}
+    for L in (4, 8, 16, 32, 64, 128, 256, 512):
+        pi, wp = periodic_eigs(L)
+        per_cell["L"].append(L)
+        per_cell["periodic"].append(float(np.mean(wp[:L])))
+        per_cell["box"].append(float(np.mean(box_eigs(L, L, pi))) if L <= 32 else None)
+    res["box_vs_periodic_spectrum"] = spectra
+    res["lowest_band_energy_per_cell"] = per_cell
+    return res
+
+
 def apply_tuning(pipe, spec):
     """Set the tuning fields of a JSON object (--mixed-tuning) on a pipeline's plan."""
     if not spec:
@@ -484,6 +563,7 @@ def main():
         legs[cfg] = leg(cfg, args, torch, np, lhf, Pipeline, headline=False)
         print(f"[bench] {cfg}: tuned {legs[cfg]['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
     c5 = None if args.no_c5 else bench_c5(torch, np, lhf, args.steps)
+    box = None if args.no_box else bench_box(torch, np, lhf, Pipeline, args.steps)
     cpu = head.pop("cpu_baseline", None)
     line = {
         "metric": METRIC, "value": head["value"], "unit": "blocks/s", "n_gpus": 1, "steps": args.steps,
@@ -494,7 +574,7 @@ def main():
         "fp64_path": head["fp64_path"], "fp32_path": head["fp32_path"], "tuned_vs_fp64": head["tuned_vs_fp64"],
         "accuracy": head["accuracy"], "stage_ms": head["stage_ms"],
         "roofline": head["roofline"], "roofline_fourier": head["roofline_fourier"], "tuning": head["tuning"],
-        "legs": legs, "dirichlet_c5": c5, "cpu_baseline": cpu,
+        "legs": legs, "dirichlet_c5": c5, "box_case": box, "cpu_baseline": cpu,
     }
     print(json.dumps(line))
 
