@@ -13,6 +13,8 @@ Modules
   separable  the paper's route: 1D Gram matrices, Hadamard combination into
              the generator blocks, Fourier blocks, per-block eigensolves
   toeplitz   dense block-Toeplitz operators and their circulant embedding
+  toeplitz3  three-level block-Toeplitz operator of a lattice in a box
+             (replicated central cell) and its three-level circulant embedding
   boxchain   the exact box case (B) of a Dirichlet chain: finite-lattice
              potential (eq. EwaldSumE), every block of the band computed
   backtransform  eigenvectors of the full lattice problem from the
