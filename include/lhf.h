@@ -366,6 +366,43 @@ int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out);
  * block (k <= m), and lhf_toeplitz_blocks returns those blocks as the cross
  * blocks.  Errors: as lhf_toeplitz_create. */
 int32_t lhf_box_exact_create(const lhf_box* box, lhf_toeplitz_t* out);
+/* The three-level block-Toeplitz operator of an L1 x L2 x L3 lattice in a box
+ * (Sec. 2.3, item (A): the central cell's potential replicated to every cell
+ * makes the box matrix shift invariant; Def. 5.4: a symmetric three-level
+ * block-Toeplitz matrix), applied through its three-level block-circulant
+ * embedding (Remark 3.2: about double size at each level):
+ *   T(k, m) = A_(m-k),  A_s(mu, nu) = <g_(0,mu), H_rep g_(s,nu)>,
+ * s signed in every dimension with |s_l| <= L0_l, zero beyond.  Readings:
+ *   * every dimension is a box dimension; a dimension with L >= 2 needs
+ *     cell-aligned nodes (n = nc L, pad = a / (2 nc)) and its generators are
+ *     taken on its node set extended without walls; a one-cell dimension is
+ *     an ordinary box dimension with its walls;
+ *   * H_rep carries, per multi-cell dimension, the lattice-window factors of
+ *     the central cell (window of L cells: odd L symmetric, even L with half
+ *     weights on the two end cells) repeated with period a; per one-cell
+ *     dimension the nucleus's own factor;
+ *   * L0_l from the smallest exponent (overlap decay below 1e-22), capped at
+ *     L_l - 1; embedding lengths P_l: smallest powers of two >= L_l + L0_l.
+ * The walls of multi-cell dimensions and defects are not modelled (the wall
+ * layer, item (B), is what the exact chain operator keeps).  The embedding's
+ * per-frequency blocks are Hadamard combinations of 1D-transformed Grams
+ * (Theorem 3.3 applied to the embedding), built without a 3D generator
+ * array.  Returns a handle of the same kind: lhf_toeplitz_matvec (x and y
+ * cell-major, cell (k1 L2 + k2) L3 + k3, complex128 or complex64 transform),
+ * lhf_toeplitz_eigs (preconditioner (C_H - sigma C_S)^-1 per frequency of the
+ * embedding), lhf_toeplitz_get_info (L = L1 L2 L3 cells, L0 = the largest
+ * L0_l, P = P1 P2 P3, ncross = ncross_blocks = 0); lhf_toeplitz_blocks is
+ * refused (LHF_ERR_UNSUPPORTED): use lhf_toeplitz3_generators.
+ * Synchronous; allocates the operator's device tables.
+ * Errors: LHF_ERR_INVALID (descriptor), LHF_ERR_UNSUPPORTED (not Dirichlet,
+ * nodes not cell aligned, m0 > 32, an embedding level longer than 4096 or
+ * more than 2^22 frequencies, ...), LHF_ERR_ALLOC, LHF_ERR_HIP. */
+int32_t lhf_toeplitz3_create(const lhf_lattice* lat, lhf_toeplitz_t* out);
+/* The generators A_s of a three-level operator: d_gen_H, d_gen_S device FP64
+ * [2 L0_1 + 1][2 L0_2 + 1][2 L0_3 + 1][m0][m0], index s_l + L0_l, row mu,
+ * column nu.  Synchronous.  Errors: LHF_ERR_INVALID (NULL pointer, not a
+ * three-level operator), LHF_ERR_HIP. */
+int32_t lhf_toeplitz3_generators(lhf_toeplitz_t tp, double* d_gen_H, double* d_gen_S);
 int32_t lhf_toeplitz_get_info(lhf_toeplitz_t tp, lhf_toeplitz_info* out);
 /* Copy the model's blocks to device buffers (each may be NULL):
  * d_gen_H, d_gen_S: FP64 [L0 + 1][m0][m0], A_s row mu, column nu;
@@ -395,8 +432,9 @@ size_t lhf_toeplitz_eigs_workspace(lhf_toeplitz_t tp, int32_t nev);
  * iteration, S-orthonormalised in FP64 (Cholesky-QR in the column order
  * [X, W, P], dropping columns whose squared distance from the span of the
  * ones before them is below 1e-10), FP64 Rayleigh-Ritz; matvecs in
- * FP32 until the largest residual of the wanted pairs is below 1e-4, then in
- * FP64 until it is below tol.  The start block is drawn from a counter-based
+ * FP32 until the largest residual of the wanted pairs is below 1e-4 or stops
+ * falling (no 30% drop over five iterations), then in FP64 until it is below
+ * tol.  The start block is drawn from a counter-based
  * generator (SplitMix64) with `seed`.  Runs on `stream` and synchronises it
  * once per iteration (convergence test on the host).
  * d_w: device FP64 [nev] ascending; d_V: device FP64 [N][nev] or NULL

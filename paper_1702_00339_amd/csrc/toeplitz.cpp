@@ -13,6 +13,7 @@
 
 #include "plan.h"
 #include "toeplitz.h"
+#include "toeplitz3.h"
 
 using namespace lhf;
 
@@ -20,6 +21,12 @@ struct lhf_toeplitz_s {
   ToepDev host{};
   int device = 0;
   bool exact = false;                   // the exact box operator: block-sparse, no Toeplitz part
+  bool three = false;                   // the three-level Toeplitz operator of a box lattice
+  Toep3Dev host3{};
+  Toep3Dev* d_desc3 = nullptr;
+  double* d_grams3 = nullptr;           // three-level: 1D Grams per dimension and shift
+  void* d_tw3_64[3] = {nullptr, nullptr, nullptr};
+  void* d_tw3_32[3] = {nullptr, nullptr, nullptr};
   int L = 0, m0 = 0, L0 = 0, P = 0, N = 0, nX = 0, ncb = 0, njobs = 0, nrows = 0, nent = 0;
   double sigma = 0.0;
   std::vector<void*> allocs;            // every device allocation, freed by destroy
@@ -187,6 +194,61 @@ extern "C" int32_t lhf_toeplitz_destroy(lhf_toeplitz_t t) {
 
 namespace {
 
+// Spectrum of the embedding's per-frequency pencils (C_H(f), C_S(f)) by the
+// batched Hermitian solver over the P = P1 P2 P3 frequency blocks (frequency
+// f and -f mod P per level are conjugate), the shift sigma below it (half its
+// width lower) and the preconditioner blocks (C_H(f) - sigma C_S(f))^-1.
+// Synchronous; on error the caller destroys t.
+int32_t build_preconditioner(lhf_toeplitz_s* t, int dev, hipStream_t s) {
+  const int m0 = t->m0, P = t->P;
+  const size_t mm = (size_t)m0 * m0;
+  const int P1 = t->three ? t->host3.P[0] : P, P2 = t->three ? t->host3.P[1] : 1, P3 = t->three ? t->host3.P[2] : 1;
+  lhf_plan_s fp;
+  fp.prec = LHF_PREC_FP64;
+  fp.nlat = 1;
+  fp.device = dev;
+  LatDev ld{};
+  ld.m0 = m0;
+  ld.L[0] = P1; ld.L[1] = P2; ld.L[2] = P3;
+  ld.nblk = P;
+  fp.lat.push_back(ld);
+  std::vector<int2> canon;
+  for (int f = 0; f < P; ++f) {
+    const int f1 = f / (P2 * P3), f2 = (f / P3) % P2, f3 = f % P3;
+    const int cf = (((P1 - f1) % P1) * P2 + (P2 - f2) % P2) * P3 + (P3 - f3) % P3;
+    if (cf >= f) canon.push_back(make_int2(0, f));
+  }
+  const int cls = heev_class(m0);
+  fp.ncanon[cls] = (int32_t)canon.size();
+  double* d_w = nullptr;
+  double2* d_V = nullptr;
+  int32_t* d_info = nullptr;
+  hipError_t e = hipSuccess;
+  const bool ok = upload(t, fp.d_lat, fp.lat.data(), 1) && upload(t, fp.d_canon[cls], canon.data(), canon.size()) &&
+                  dalloc(t, d_w, (size_t)P * m0) && dalloc(t, d_V, (size_t)P * mm) && dalloc(t, d_info, (size_t)P);
+  if (ok) e = launch_heev(&fp, LHF_HEEV_VECTORS, t->d_cH, t->d_cS, nullptr, nullptr, nullptr, nullptr, d_w, d_V,
+                          d_info, nullptr, nullptr, s);
+  fp.d_lat = nullptr;                 // owned by t->allocs
+  fp.d_canon[cls] = nullptr;
+  if (!ok) { set_error("lhf_toeplitz_create: device allocation failed"); return LHF_ERR_ALLOC; }
+  std::vector<double> w((size_t)P * m0);
+  std::vector<int32_t> info(P);
+  if (e == hipSuccess) e = hipMemcpy(w.data(), d_w, w.size() * sizeof(double), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(info.data(), d_info, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_status(e, "lhf_toeplitz_create");
+  for (int f = 0; f < P; ++f)
+    if (info[f] != 0) {
+      set_error("lhf_toeplitz_create: the embedding's overlap block of frequency " + std::to_string(f) +
+                " is not positive definite (status " + std::to_string(info[f]) + ")");
+      return LHF_ERR_INVALID;
+    }
+  const double wmin = *std::min_element(w.begin(), w.end()), wmax2 = *std::max_element(w.begin(), w.end());
+  t->sigma = wmin - 0.5 * std::max(wmax2 - wmin, 1.0);
+  e = toep_launch_minv(d_V, d_w, t->sigma, t->d_minv64, t->d_minv32, P, m0, s);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return hip_status(e, "lhf_toeplitz_create");
+}
+
 int32_t create(const lhf_box* box, bool exact, lhf_toeplitz_t* out) {
   if (!out) { set_error("out is NULL"); return LHF_ERR_INVALID; }
   *out = nullptr;
@@ -309,55 +371,174 @@ int32_t create(const lhf_box* box, bool exact, lhf_toeplitz_t* out) {
   if (e == hipSuccess) e = toep_launch_chat(t->d_desc, genH, genS, t->d_cH, t->d_cS, m0, P, L0, s);
   if (e == hipSuccess) e = toep_launch_to32(t->d_cH, t->d_cH32, (int64_t)P * mm, s);
   if (e == hipSuccess) e = toep_launch_to32(t->d_cS, t->d_cS32, (int64_t)P * mm, s);
-  // spectrum of the embedding's per-frequency pencils (the batched Hermitian
-  // solver over P blocks; frequencies f and P - f are conjugate)
-  lhf_plan_s fp;
-  fp.prec = LHF_PREC_FP64;
-  fp.nlat = 1;
-  fp.device = dev;
-  LatDev ld{};
-  ld.m0 = m0;
-  ld.L[0] = P; ld.L[1] = 1; ld.L[2] = 1;
-  ld.nblk = P;
-  fp.lat.push_back(ld);
-  std::vector<int2> canon;
-  for (int f = 0; f < P; ++f)
-    if ((P - f) % P >= f) canon.push_back(make_int2(0, f));
-  const int cls = heev_class(m0);
-  fp.ncanon[cls] = (int32_t)canon.size();
-  double* d_w = nullptr;
-  double2* d_V = nullptr;
-  int32_t* d_info = nullptr;
-  ok = e == hipSuccess && upload(t, fp.d_lat, fp.lat.data(), 1) && upload(t, fp.d_canon[cls], canon.data(), canon.size()) &&
-       dalloc(t, d_w, (size_t)P * m0) && dalloc(t, d_V, (size_t)P * mm) && dalloc(t, d_info, (size_t)P);
-  if (ok) e = launch_heev(&fp, LHF_HEEV_VECTORS, t->d_cH, t->d_cS, nullptr, nullptr, nullptr, nullptr, d_w, d_V,
-                          d_info, nullptr, nullptr, s);
-  fp.d_lat = nullptr;                 // owned by t->allocs
-  fp.d_canon[cls] = nullptr;
-  std::vector<double> w((size_t)P * m0);
-  std::vector<int32_t> info(P);
-  if (ok && e == hipSuccess) e = hipMemcpy(w.data(), d_w, w.size() * sizeof(double), hipMemcpyDeviceToHost);
-  if (ok && e == hipSuccess) e = hipMemcpy(info.data(), d_info, info.size() * sizeof(int32_t), hipMemcpyDeviceToHost);
-  if (!ok || e != hipSuccess) {
-    st = ok ? hip_status(e, "lhf_toeplitz_create") : LHF_ERR_ALLOC;
-    if (!ok) set_error("lhf_toeplitz_create: device allocation failed");
+  st = e == hipSuccess ? build_preconditioner(t, dev, s) : hip_status(e, "lhf_toeplitz_create");
+  if (st != LHF_OK) {
     lhf_toeplitz_destroy(t);
     return st;
   }
-  for (int f = 0; f < P; ++f)
-    if (info[f] != 0) {
-      lhf_toeplitz_destroy(t);
-      set_error("lhf_toeplitz_create: the embedding's overlap block of frequency " + std::to_string(f) +
-                " is not positive definite (status " + std::to_string(info[f]) + ")");
-      return LHF_ERR_INVALID;
+  *out = t;
+  return LHF_OK;
+}
+
+// The three-level block-Toeplitz operator of a box lattice (readings of
+// lhf_toeplitz3_create in the header): validation, grids and bands per
+// dimension, the 1D Grams, the embedding's per-frequency blocks and the
+// preconditioner.
+int32_t create3(const lhf_lattice* lat, lhf_toeplitz_t* out) {
+  if (!out) { set_error("out is NULL"); return LHF_ERR_INVALID; }
+  *out = nullptr;
+  if (!lat) { set_error("lattice is NULL"); return LHF_ERR_INVALID; }
+  const lhf_lattice& in = *lat;
+  const lhf_cell& c = in.cell;
+  auto bad3 = [](const std::string& m) { set_error("lhf_toeplitz3_create: " + m); return LHF_ERR_INVALID; };
+  auto uns3 = [](const std::string& m) { set_error("lhf_toeplitz3_create: " + m); return LHF_ERR_UNSUPPORTED; };
+  if (in.bc != LHF_BC_DIRICHLET) return uns3("the three-level operator is for a lattice in a box (Dirichlet)");
+  if (c.m0 < 1) return bad3("m0 must be >= 1");
+  if (c.m0 > kMaxM0) return uns3("m0 > 32");
+  if (!c.alpha || !c.centre) return bad3("alpha and centre are required");
+  if (c.M0 < 1 || !c.Z || !c.nuc) return bad3("at least one nucleus is required");
+  if (c.M0 > kMaxNuc) return uns3("more than 4 nuclei per cell");
+  if (in.R < 1) return bad3("R must be >= 1");
+  if (in.R > kMaxR || c.M0 * in.R > kMaxTerms - 2) return uns3("R > 64 or M0 R > 96");
+  if (!(in.a > 0) || !finite(in.a)) return bad3("lattice step a must be positive");
+  if (!(in.sinc_step > 0) || !finite(in.sinc_step) || !finite(in.sinc_u0)) return bad3("bad sinc parameters");
+  Toep3Dev D;
+  std::memset(&D, 0, sizeof(D));
+  D.m0 = c.m0;
+  D.M0 = c.M0;
+  D.R = in.R;
+  D.a = in.a;
+  double amin = 1e300, jmax = 0.0;
+  for (int mu = 0; mu < c.m0; ++mu) {
+    const double al = c.alpha[mu];
+    if (!(al > 0) || !finite(al)) return bad3("exponents must be positive");
+    const int ang = c.ang ? c.ang[mu] : LHF_ANG_S;
+    if (ang < 0 || ang > 3) return bad3("angular type must be 0..3");
+    D.alpha[mu] = al;
+    amin = std::min(amin, al);
+    for (int d = 0; d < 3; ++d) {
+      const double x = c.centre[3 * mu + d];
+      if (!finite(x)) return bad3("centres must be finite");
+      D.cen[mu][d] = x;
+      jmax = std::max(jmax, std::fabs(x));
+      D.lpow[mu][d] = ang == d + 1 ? 1 : 0;
     }
-  const double wmin = *std::min_element(w.begin(), w.end()), wmax2 = *std::max_element(w.begin(), w.end());
-  // shift below the embedding's spectrum, half its width lower
-  t->sigma = wmin - 0.5 * std::max(wmax2 - wmin, 1.0);
-  e = toep_launch_minv(d_V, d_w, t->sigma, t->d_minv64, t->d_minv32, P, m0, s);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    st = hip_status(e, "lhf_toeplitz_create");
+  }
+  for (int nu = 0; nu < c.M0; ++nu) {
+    if (!(c.Z[nu] > 0) || !finite(c.Z[nu])) return bad3("charges must be positive");
+    D.Z[nu] = c.Z[nu];
+    for (int d = 0; d < 3; ++d) {
+      if (!finite(c.nuc[3 * nu + d])) return bad3("nuclear positions must be finite");
+      D.nuc[nu][d] = c.nuc[3 * nu + d];
+    }
+  }
+  for (int q = 0; q < in.R; ++q) {
+    D.tq[q] = std::exp(in.sinc_u0 + q * in.sinc_step);
+    D.wq[q] = (2.0 / std::sqrt(M_PI)) * in.sinc_step * D.tq[q];
+  }
+  const int band = (int)std::ceil((2.0 * jmax + std::sqrt(101.4 / amin)) / in.a);
+  const int E = (int)std::ceil((std::sqrt(80.6 / amin) + jmax) / in.a) + 1;
+  const int T = 2 + c.M0 * in.R, m0 = c.m0;
+  const size_t mm = (size_t)m0 * m0;
+  std::vector<Gram3Job> jobs;
+  int64_t vpot = 0, grams = 0, gh = 0;
+  int64_t Ptot = 1, cells = 1;
+  int wmax = 0;
+  for (int d = 0; d < 3; ++d) {
+    const int L = in.L[d], n = in.n[d];
+    if (L < 1) return bad3("L must be >= 1");
+    if (n < 4) return bad3("n must be >= 4");
+    if (!(in.pad[d] >= 0) || !finite(in.pad[d])) return bad3("pad must be >= 0");
+    D.L[d] = L;
+    D.n[d] = n;
+    if (L >= 2) {
+      if (n % L) return uns3("multi-cell dimensions need n a multiple of L");
+      const int nc = n / L;
+      if (nc < 2) return bad3("need at least two nodes per cell");
+      if (nc > 256) return uns3("more than 256 nodes per cell");
+      if (std::fabs(in.pad[d] - 0.5 * in.a / nc) > 1e-12 * in.a)
+        return uns3("multi-cell dimensions need cell-aligned nodes: pad = a / (2 nc)");
+      D.h[d] = in.a / nc;
+      D.x0[d] = -0.5 * (L * in.a + 2.0 * in.pad[d]);
+      D.L0[d] = std::min(L - 1, band);
+      int P = 2;
+      while (P < L + D.L0[d]) P *= 2;
+      if (P > 4096) return uns3("embedding longer than 4096 cells in one dimension");
+      D.P[d] = P;
+      D.vpot_len[d] = nc;
+      for (int sh = 0; sh <= D.L0[d]; ++sh) {
+        const Gram3Job j{d, sh, 1 - E * nc, (sh + 1 + E) * nc};
+        jobs.push_back(j);
+        wmax = std::max(wmax, j.ihi - j.ilo + 1);
+      }
+    } else {
+      const double W = in.a + 2.0 * in.pad[d];
+      D.h[d] = W / (n + 1);
+      D.x0[d] = -0.5 * W;
+      D.L0[d] = 0;
+      D.P[d] = 1;
+      D.vpot_len[d] = n;
+      jobs.push_back(Gram3Job{d, 0, 1, n});
+      wmax = std::max(wmax, n);
+    }
+    D.vpot_off[d] = vpot; vpot += (int64_t)c.M0 * in.R * D.vpot_len[d];
+    D.gram_off[d] = grams; grams += (int64_t)(D.L0[d] + 1) * T * mm;
+    D.gh_off[d] = gh; gh += (int64_t)T * D.P[d] * mm;
+    Ptot *= D.P[d];
+    cells *= L;
+  }
+  if (Ptot > (1 << 22)) return uns3("embedding with more than 2^22 frequencies");
+  hipDeviceProp_t prop;
+  int dev = 0;
+  int32_t st;
+  if ((st = hip_status(hipGetDevice(&dev), "device")) != LHF_OK) return st;
+  if ((st = hip_status(hipGetDeviceProperties(&prop, dev), "device properties")) != LHF_OK) return st;
+  const size_t lds = sizeof(double) * (2 * (size_t)m0 * (wmax + 2) + (size_t)wmax);
+  if (lds > prop.sharedMemPerBlock) return uns3("node window of the Grams does not fit in LDS");
+  auto* t = new (std::nothrow) lhf_toeplitz_s();
+  if (!t) { set_error("out of host memory"); return LHF_ERR_ALLOC; }
+  t->three = true;
+  t->host3 = D;
+  t->device = dev;
+  t->L = (int)cells;
+  t->m0 = m0;
+  t->L0 = std::max(D.L0[0], std::max(D.L0[1], D.L0[2]));
+  t->P = (int)Ptot;
+  t->N = (int)(cells * m0);
+  std::vector<std::vector<double2>> tw64(3);
+  std::vector<std::vector<float2>> tw32(3);
+  bool ok = upload(t, t->d_desc3, &D, 1);
+  Gram3Job* d_jobs = nullptr;
+  double* d_vpot = nullptr;
+  double2* d_gh = nullptr;
+  ok = ok && upload(t, d_jobs, jobs.data(), jobs.size()) && dalloc(t, d_vpot, (size_t)vpot) &&
+       dalloc(t, t->d_grams3, (size_t)grams) && dalloc(t, d_gh, (size_t)gh) &&
+       dalloc(t, t->d_cH, (size_t)Ptot * mm) && dalloc(t, t->d_cS, (size_t)Ptot * mm) &&
+       dalloc(t, t->d_cH32, (size_t)Ptot * mm) && dalloc(t, t->d_cS32, (size_t)Ptot * mm) &&
+       dalloc(t, t->d_minv64, (size_t)Ptot * mm) && dalloc(t, t->d_minv32, (size_t)Ptot * mm);
+  for (int d = 0; d < 3 && ok; ++d) {
+    const int P = D.P[d], nh = std::max(1, P / 2);
+    tw64[d].resize(nh);
+    tw32[d].resize(nh);
+    for (int k = 0; k < nh; ++k) {
+      const double ang = -2.0 * M_PI * k / P;
+      tw64[d][k] = make_double2(std::cos(ang), std::sin(ang));
+      tw32[d][k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    double2* p64 = nullptr;
+    float2* p32 = nullptr;
+    ok = upload(t, p64, tw64[d].data(), nh) && upload(t, p32, tw32[d].data(), nh);
+    t->d_tw3_64[d] = p64;
+    t->d_tw3_32[d] = p32;
+  }
+  if (!ok) { lhf_toeplitz_destroy(t); set_error("lhf_toeplitz3_create: device allocation failed"); return LHF_ERR_ALLOC; }
+  hipStream_t s = nullptr;
+  hipError_t e = toep3_launch_assembly(t->d_desc3, D, d_jobs, (int)jobs.size(), wmax, d_vpot, t->d_grams3, d_gh,
+                                       t->d_cH, t->d_cS, s);
+  if (e == hipSuccess) e = toep_launch_to32(t->d_cH, t->d_cH32, Ptot * (int64_t)mm, s);
+  if (e == hipSuccess) e = toep_launch_to32(t->d_cS, t->d_cS32, Ptot * (int64_t)mm, s);
+  st = e == hipSuccess ? build_preconditioner(t, dev, s) : hip_status(e, "lhf_toeplitz3_create");
+  if (st != LHF_OK) {
     lhf_toeplitz_destroy(t);
     return st;
   }
@@ -372,6 +553,17 @@ extern "C" {
 int32_t lhf_toeplitz_create(const lhf_box* box, lhf_toeplitz_t* out) { return create(box, false, out); }
 
 int32_t lhf_box_exact_create(const lhf_box* box, lhf_toeplitz_t* out) { return create(box, true, out); }
+
+int32_t lhf_toeplitz3_create(const lhf_lattice* lat, lhf_toeplitz_t* out) { return create3(lat, out); }
+
+int32_t lhf_toeplitz3_generators(lhf_toeplitz_t t, double* gH, double* gS) {
+  if (!t) { set_error("NULL operator"); return LHF_ERR_INVALID; }
+  if (!t->three) { set_error("not a three-level operator (lhf_toeplitz3_create)"); return LHF_ERR_INVALID; }
+  if (!gH || !gS) { set_error("gen_H and gen_S are required"); return LHF_ERR_INVALID; }
+  hipError_t e = toep3_launch_generators(t->d_desc3, t->host3, t->d_grams3, gH, gS, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return hip_status(e, "lhf_toeplitz3_generators");
+}
 
 int32_t lhf_toeplitz_get_info(lhf_toeplitz_t t, lhf_toeplitz_info* out) {
   if (!t || !out) { set_error("NULL operator or output"); return LHF_ERR_INVALID; }
@@ -388,6 +580,7 @@ int32_t lhf_toeplitz_get_info(lhf_toeplitz_t t, lhf_toeplitz_info* out) {
 
 int32_t lhf_toeplitz_blocks(lhf_toeplitz_t t, double* gH, double* gS, int32_t* km, double* cH, double* cS) {
   if (!t) { set_error("NULL operator"); return LHF_ERR_INVALID; }
+  if (t->three) { set_error("a three-level operator: use lhf_toeplitz3_generators"); return LHF_ERR_UNSUPPORTED; }
   const size_t mm = (size_t)t->m0 * t->m0, ng = (size_t)(t->L0 + 1) * mm, nc = (size_t)t->ncb * mm;
   hipError_t e = hipSuccess;
   if (gH && e == hipSuccess) e = hipMemcpy(gH, t->d_blkH, ng * 8, hipMemcpyDeviceToDevice);
@@ -400,6 +593,7 @@ int32_t lhf_toeplitz_blocks(lhf_toeplitz_t t, double* gH, double* gS, int32_t* k
 
 size_t lhf_toeplitz_matvec_workspace(lhf_toeplitz_t t, int32_t ncols) {
   if (!t || ncols < 1) return 0;
+  if (t->three) return toep3_apply_ws_bytes(t->host3, ncols, true);
   return 3 * (size_t)t->P * t->m0 * ncols * sizeof(double2);
 }
 
@@ -414,9 +608,18 @@ int32_t lhf_toeplitz_matvec(lhf_toeplitz_t t, int32_t prec, int32_t ncols, const
     set_error("workspace of " + std::to_string(ws_bytes) + " bytes given, " + std::to_string(need) + " needed");
     return LHF_ERR_WORKSPACE;
   }
+  const bool f64 = prec == LHF_PREC_FP64;
+  if (t->three) {
+    const void* tw3[3] = {f64 ? t->d_tw3_64[0] : t->d_tw3_32[0], f64 ? t->d_tw3_64[1] : t->d_tw3_32[1],
+                          f64 ? t->d_tw3_64[2] : t->d_tw3_32[2]};
+    const void* o3H = f64 ? (const void*)t->d_cH : (const void*)t->d_cH32;
+    const void* o3S = yS ? (f64 ? (const void*)t->d_cS : (const void*)t->d_cS32) : nullptr;
+    return hip_status(toep3_launch_apply(t->host3, prec, tw3, ncols, x, ld, o3H, o3S, yH, yS, ws,
+                                         static_cast<hipStream_t>(stream)),
+                      "lhf_toeplitz_matvec");
+  }
   char* w = static_cast<char*>(ws);
   const size_t part = (size_t)t->P * t->m0 * ncols * sizeof(double2);
-  const bool f64 = prec == LHF_PREC_FP64;
   const void* opH = f64 ? (const void*)t->d_cH : (const void*)t->d_cH32;
   const void* opS = yS ? (f64 ? (const void*)t->d_cS : (const void*)t->d_cS32) : nullptr;
   hipError_t e = toep_launch_apply(prec, t->L, t->m0, t->P, ncols, x, ld, opH, opS,
@@ -502,7 +705,7 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t t, int32_t nev, int32_t maxit, double t
     const int32_t r = lhf_toeplitz_matvec(t, prec, ncols, x, yH, yS, ld, w.mv, w.mv_bytes, stream);
     if (r != LHF_OK) e = hipErrorUnknown;
   };
-  std::vector<double> hl(S), hn(S);
+  std::vector<double> hl(S), hn(S), hist;
   int prec = LHF_PREC_MIXED;
   bool haveP = false;
   int it = 0;
@@ -522,11 +725,26 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t t, int32_t nev, int32_t maxit, double t
       if (!std::isfinite(rmax)) { st = LHF_ERR_INVALID; set_error("LOBPCG residuals are not finite"); break; }
       if (prec == LHF_PREC_FP64 && rmax < tol) break;
       if (it == maxit) break;
-      if (prec == LHF_PREC_MIXED && rmax < 1e-4) prec = LHF_PREC_FP64;
+      // FP64 matvecs once the residual is below 1e-4, or once the FP32 ones
+      // stall (no 30% drop over the last five iterations: the complex64
+      // transform's error floor, which grows with the operator's norm)
+      bool stalled = false;
+      if (hist.size() >= 5) {
+        const double best = *std::min_element(hist.end() - 5, hist.end());
+        stalled = rmax > 0.7 * best;
+      }
+      hist.push_back(rmax);
+      if (prec == LHF_PREC_MIXED && (rmax < 1e-4 || stalled)) prec = LHF_PREC_FP64;
       // W = preconditioned residuals: (H_c - sigma S_c)^-1 per frequency of the embedding
-      ck(toep_launch_apply(LHF_PREC_MIXED, t->L, t->m0, t->P, nb, w.R, nb, t->d_minv32, nullptr, t->d_tw32, w.mv,
-                           w.mv + w.mv_bytes / 3, w.mv + 2 * (w.mv_bytes / 3), w.W, nullptr, nullptr, nullptr, 0,
-                           nullptr, nullptr, nullptr, s));
+      if (t->three) {
+        const void* tw3[3] = {t->d_tw3_32[0], t->d_tw3_32[1], t->d_tw3_32[2]};
+        ck(toep3_launch_apply(t->host3, LHF_PREC_MIXED, tw3, nb, w.R, nb, t->d_minv32, nullptr, w.W, nullptr, w.mv,
+                              s));
+      } else {
+        ck(toep_launch_apply(LHF_PREC_MIXED, t->L, t->m0, t->P, nb, w.R, nb, t->d_minv32, nullptr, t->d_tw32, w.mv,
+                             w.mv + w.mv_bytes / 3, w.mv + 2 * (w.mv_bytes / 3), w.W, nullptr, nullptr, nullptr, 0,
+                             nullptr, nullptr, nullptr, s));
+      }
       ck(dense_copy_cols(N, nb, w.X, nb, w.Q, mx, s));
       ck(dense_copy_cols(N, nb, w.W, nb, w.Q + nb, mx, s));
       m = 2 * nb;

@@ -110,6 +110,8 @@ def load(path: str = LIB_PATH):
         "lhf_plan_autotune": (i32, [vp, C.POINTER(lhf_step_args), vp, C.c_char_p, C.POINTER(lhf_tuning)]),
         "lhf_toeplitz_create": (i32, [C.POINTER(lhf_box), C.POINTER(vp)]),
         "lhf_box_exact_create": (i32, [C.POINTER(lhf_box), C.POINTER(vp)]),
+        "lhf_toeplitz3_create": (i32, [C.POINTER(lhf_lattice), C.POINTER(vp)]),
+        "lhf_toeplitz3_generators": (i32, [vp, vp, vp]),
         "lhf_toeplitz_get_info": (i32, [vp, C.POINTER(lhf_toeplitz_info)]),
         "lhf_toeplitz_blocks": (i32, [vp, vp, vp, vp, vp, vp]),
         "lhf_toeplitz_matvec_workspace": (sz, [vp, i32]),
@@ -136,7 +138,8 @@ def exported_symbols():
             "lhf_assemble_blocks", "lhf_block_fft", "lhf_block_fft_dual", "lhf_fourier_blocks",
             "lhf_fourier_blocks_noalloc", "lhf_heev_batched", "lhf_eigvecs_lattice", "lhf_step", "lhf_graph_create",
             "lhf_graph_launch", "lhf_graph_destroy", "lhf_plan_get_tuning", "lhf_plan_set_tuning",
-            "lhf_plan_autotune", "lhf_toeplitz_create", "lhf_box_exact_create", "lhf_toeplitz_get_info", "lhf_toeplitz_blocks",
+            "lhf_plan_autotune", "lhf_toeplitz_create", "lhf_box_exact_create", "lhf_toeplitz3_create",
+            "lhf_toeplitz3_generators", "lhf_toeplitz_get_info", "lhf_toeplitz_blocks",
             "lhf_toeplitz_matvec_workspace", "lhf_toeplitz_matvec", "lhf_toeplitz_eigs_workspace",
             "lhf_toeplitz_eigs", "lhf_toeplitz_destroy", "lhf_status_string", "lhf_last_error", "lhf_version"]
 
@@ -331,13 +334,17 @@ class Toeplitz:
     (lhf_toeplitz_create) or, with exact=True, the exact box operator
     (lhf_box_exact_create); freed by lhf_toeplitz_destroy."""
 
-    def __init__(self, inst, exact=False):
+    def __init__(self, inst, exact=False, levels=1):
         self.inst = inst
         self.exact = exact
-        box, self._keep = box_from_instance(inst)
         h = C.c_void_p()
-        create = load().lhf_box_exact_create if exact else load().lhf_toeplitz_create
-        _check(create(C.byref(box), C.byref(h)))
+        if levels == 3:
+            lat, self._keep = lattice_from_instance(inst)
+            _check(load().lhf_toeplitz3_create(C.byref(lat), C.byref(h)))
+        else:
+            box, self._keep = box_from_instance(inst)
+            create = load().lhf_box_exact_create if exact else load().lhf_toeplitz_create
+            _check(create(C.byref(box), C.byref(h)))
         self.handle = h
         info = lhf_toeplitz_info()
         _check(load().lhf_toeplitz_get_info(self.handle, C.byref(info)))
@@ -353,6 +360,9 @@ class Toeplitz:
             self.close()
         except Exception:
             pass
+
+    def lhf_toeplitz3_generators(self, gen_H, gen_S):
+        _check(load().lhf_toeplitz3_generators(self.handle, _ptr(gen_H), _ptr(gen_S)))
 
     def lhf_toeplitz_blocks(self, gen_H=None, gen_S=None, cross_km=None, cross_H=None, cross_S=None):
         _check(load().lhf_toeplitz_blocks(self.handle, _ptr(gen_H), _ptr(gen_S), _ptr(cross_km), _ptr(cross_H),
