@@ -927,10 +927,16 @@ __device__ void chol_reduce_wup(Smem<double, M, G, false, false, true>& sh, int 
 // a few ulps of the interval or of the matrix norm.  The count at x is the
 // number of sign changes of the leading minors p_j of T - x I, from the
 // division-free recurrence p_j = (d_j - x) p_(j-1) - e_(j-1)^2 p_(j-2)
-// (sturm_row: a zero taken as positive, restarted where e_(j-1) = 0), on T scaled by a power of two to norm below 1 and rescaled
-// by 2^-+256 every eighth row against overflow and underflow (exact,
-// sign-preserving).  Each lane runs two sequences at once (2 P + 1 sections
-// per pass).  The eigenvalues land sorted: rank i = i.
+// (sturm_row: a zero taken as positive; a matrix with a zero interior
+// coupling takes the row that restarts the recurrence there, the others the
+// plain one), on T scaled by a power of two to norm below 1 and rescaled by
+// 2^-+256 every eighth row against overflow and underflow (exact,
+// sign-preserving).  Each lane runs
+// two sequences at once (2 P + 1 sections per pass).  The points of a pass
+// increase along the group's lanes and the counts are monotone in x, so the
+// points with count <= i form a prefix: its length k, from two ballots, gives
+// the new interval [point k, point k + 1] directly.  The eigenvalues land
+// sorted: rank i = i.
 template <int W, typename R, int M, int G, bool HASU, bool HASV, bool NOF>
 __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, int n) {
   typedef typename Cx<R>::T C;
@@ -1077,16 +1083,20 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
     e2[n - 2] = b.x * b.x + b.y * b.y;
   }
   __syncthreads();
-  // Gershgorin interval of the tridiagonal matrix
+  // Gershgorin interval of the tridiagonal matrix, one row per lane t < M of
+  // the group's first wavefront (the M lanes are an aligned DPP group), then
+  // lo, hi and the largest e^2 by all-reduces over them; rows past n are
+  // neutral
   constexpr R eps = R(1.1102230246251565e-16);
-  R lo = R(0), hi = R(0), emax = R(0);
-  for (int j = 0; j < n; ++j) {
-    const R ej = j < n - 1 ? sqrt(e2[j]) : R(0), ejm = j > 0 ? sqrt(e2[j - 1]) : R(0);
-    const R l = dg[j] - ej - ejm, u = dg[j] + ej + ejm;
-    lo = j == 0 ? l : fmin(lo, l);
-    hi = j == 0 ? u : fmax(hi, u);
-    if (j < n - 1) emax = fmax(emax, e2[j]);
-  }
+  constexpr R kHuge = R(1.79e308);
+  const bool rowl = t < n;
+  const R er = rowl && t < n - 1 ? e2[t < M ? t : 0] : R(0);
+  const R erm = rowl && t > 0 ? e2[t > 0 && t <= M ? t - 1 : 0] : R(0);
+  const R dr = rowl ? dg[t < M ? t : 0] : R(0);
+  const R rad = sqrt(er) + sqrt(erm);
+  R lo = lane_reduce<M>(rowl ? dr - rad : kHuge, [](double x, double y) { return fmin(x, y); });
+  R hi = lane_reduce<M>(rowl ? dr + rad : -kHuge, [](double x, double y) { return fmax(x, y); });
+  R emax = lane_reduce<M>(er, [](double x, double y) { return fmax(x, y); });
   // the pass runs on T scaled by sc = 2^-ex (exact), |T| < 1, so the minors
   // grow at most 3x per row and a rescale every eighth row suffices
   int ex = 0;
@@ -1095,16 +1105,43 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
   lo *= sc;
   hi *= sc;
   emax *= sc * sc;
-  const R tnorm = fmax(fabs(lo), fabs(hi));
-  const R tiny = R(2.2250738585072014e-308) * fmax(R(1), emax);   // absolute floor of the widths
+  R tnorm = fmax(fabs(lo), fabs(hi));
+  R tiny = R(2.2250738585072014e-308) * fmax(R(1), emax);   // absolute floor of the widths
   const R widen = R(4) * R(n) * eps * tnorm + R(2) * tiny;
   lo -= widen;
   hi += widen;
   // rows past n: d beyond the interval (d - x > 0, bounded) and e = 0, so
   // they change no sign and the pass runs over all M rows without selects
+  // (the plain row keeps p_j = (d - x) p_(j-1) there, the restarting one
+  // starts a positive sequence)
   const R dpad = R(2) * fmax(fabs(lo), fabs(hi)) + R(1);
-  if (t < M) de[t] = t < n ? cmk<C>(dg[t] * sc, t > 0 ? e2[t - 1] * sc * sc : R(0)) : cmk<C>(dpad, R(0));
+  const R e2s = erm * sc * sc;
+  // a zero interior coupling after scaling (the same for the whole matrix)
+  const unsigned long long zb = __ballot(t >= 1 && t < n && e2s == R(0));
+  if (t < M) {
+    de[t] = t < n ? cmk<C>(dr * sc, e2s) : cmk<C>(dpad, R(0));
+    const int base = (int)(threadIdx.x & 63) - t;   // lane of row 0
+    const unsigned long long rmask = M >= 64 ? ~0ull : (((1ull << M) - 1ull) << base);
+    if (t == 0) {
+      R* b = sh.red[g];
+      b[0] = lo;
+      b[1] = hi;
+      b[2] = tnorm;
+      b[3] = tiny;
+      b[4] = R(ex);
+      b[5] = (zb & rmask) ? R(1) : R(0);
+    }
+  }
   __syncthreads();
+  {
+    const R* b = sh.red[g];
+    lo = b[0];
+    hi = b[1];
+    tnorm = b[2];
+    tiny = b[3];
+    ex = (int)b[4];
+  }
+  const bool split = sh.red[g][5] != R(0);
   const bool live = gi < n;
   // (d_j, e_(j-1)^2) in registers for M <= 16, read from LDS per row for M = 32
   constexpr int ND = M <= 16 ? M : 1;
@@ -1116,27 +1153,34 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
   auto dr_at = [&](int j) -> C {
     if constexpr (M <= 16) return drr[j]; else return de[j];
   };
-  const R stepa = R(2 * gc + 1) / R(2 * P + 1), stepb = R(2 * gc + 2) / R(2 * P + 1);
+  // point i (1..2P) of a pass: the same expression where it is evaluated and
+  // where it becomes an end of the new interval
+  const R inv = R(1) / R(2 * P + 1);
+  auto point = [&](int i) { return fma(hi - lo, R(i) * inv, lo); };
+  const int gbase = ((int)(threadIdx.x & 63) / P) * P;   // first lane of the group in its wavefront
+  const unsigned long long gmask = P >= 64 ? ~0ull : ((1ull << P) - 1ull);
   constexpr R kBig = R(1.157920892373162e77), kSmall = R(8.636168555094445e-78);   // 2^256, 2^-256
+  auto passes = [&](auto splitc) {
+  constexpr bool SPLIT = decltype(splitc)::value;
 #pragma unroll 1
   for (int it = 0; it < 96; ++it) {
     const bool conv = !live || hi - lo <= R(2) * eps * fmax(fabs(lo), fabs(hi)) + eps * tnorm + R(4) * tiny;
     if (__all(conv)) break;
-    const R xa = lo + (hi - lo) * stepa, xb = lo + (hi - lo) * stepb;
+    const R xa = point(2 * gc + 1), xb = point(2 * gc + 2);
     int ca = 0, cb = 0;
     if (live) {
       const C d0 = dr_at(0);
       R pa2 = R(1), pb2 = R(1), pa1 = d0.x - xa, pb1 = d0.x - xb;
-      bool na = pa1 < R(0), nb = pb1 < R(0);
-      ca = na ? 1 : 0;
-      cb = nb ? 1 : 0;
+      int na = sign_bit(pa1), nb = sign_bit(pb1);
+      ca = na;
+      cb = nb;
       // row j of the pass; rescale after rows 7, 15, 23, ... (RS: j % 8 == 7,
       // known at compile time in every caller)
       auto row = [&](int j, auto rs) {
         constexpr bool RS = decltype(rs)::value;
         const C dj = dr_at(j);
-        sturm_row(dj.x, dj.y, xa, pa1, pa2, na, ca);
-        sturm_row(dj.x, dj.y, xb, pb1, pb2, nb, cb);
+        sturm_row<SPLIT>(dj.x, dj.y, xa, pa1, pa2, na, ca);
+        sturm_row<SPLIT>(dj.x, dj.y, xb, pb1, pb2, nb, cb);
         if constexpr (RS) {
           const R sa = fabs(pa1) > kBig ? kSmall : (fabs(pa1) < kSmall ? kBig : R(1));
           const R sb = fabs(pb1) > kBig ? kSmall : (fabs(pb1) < kSmall ? kBig : R(1));
@@ -1177,16 +1221,17 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
         for (int jb = 8; jb < M; jb += 8) block8(jb);
       }
     }
-    R lc = lo, hc = hi;
-    if (ca <= gi) lc = xa; else hc = xa;
-    if (cb <= gi) lc = fmax(lc, xb); else hc = fmin(hc, xb);
-    lc = lane_reduce<P>(lc, [](double x, double y) { return fmax(x, y); });
-    hc = lane_reduce<P>(hc, [](double x, double y) { return fmin(x, y); });
+    const unsigned long long ba = __ballot(ca <= gi), bb = __ballot(cb <= gi);
+    const int k = __popcll((ba >> gbase) & gmask) + __popcll((bb >> gbase) & gmask);
     if (!conv) {
-      lo = lc;
-      hi = hc;
+      const R nlo = k == 0 ? lo : point(k);
+      const R nhi = k == 2 * P ? hi : point(k + 1);
+      lo = nlo;
+      hi = nhi;
     }
   }
+  };
+  if (split) passes(std::true_type{}); else passes(std::false_type{});
   if (live && gc == 0) {
     sh.lam[g][gi] = ldexp(R(0.5) * (lo + hi), ex);
     sh.rank[g][gi] = gi;

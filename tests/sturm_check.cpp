@@ -19,7 +19,8 @@ int main() {
     for (int i = 0; i < nx; ++i) {
       double x = 0;
       if (std::scanf("%lf", &x) != 1) return 1;
-      std::printf("%d\n", lhf::sturm_count(d.data(), e2.data(), n, x));
+      std::printf("%d %d\n", lhf::sturm_count<true>(d.data(), e2.data(), n, x),
+                  lhf::sturm_count<false>(d.data(), e2.data(), n, x));
     }
   }
   return 0;

@@ -1,13 +1,14 @@
-"""Sturm count of the FP64 bisection eigensolver, on the host.
+"""Sturm counts of the FP64 bisection eigensolver, on the host.
 
-The kernel's row recurrence (csrc/sturm.h) is compiled host-only by hipcc and
-run here.  Split tridiagonal matrices (a zero subdiagonal entry, as
+The kernel's row recurrences (csrc/sturm.h) are compiled host-only by hipcc
+and run here.  Split tridiagonal matrices (a zero subdiagonal entry, as
 Householder reduction produces for a block-diagonal Hermitian matrix) with
 shifts at eigenvalues of a leading block are where the plain product form
-loses every later sign change.  Away from eigenvalues the count must equal
-the number of eigenvalues below the shift; at an eigenvalue either the count
-below or the count at or below keeps bisection correct (the interval still
-brackets it), anything else does not.
+loses every later sign change; the kernel takes the restarting row for such
+matrices and the plain one otherwise.  Away from eigenvalues a count must
+equal the number of eigenvalues below the shift; at an eigenvalue either the
+count below or the count at or below keeps bisection correct (the interval
+still brackets it), anything else does not.
 """
 
 import os
@@ -33,7 +34,8 @@ def sturm_bin(tmp_path_factory):
 
 
 def run_counts(binary, cases):
-    """cases: list of (d, e2, xs); returns list of count arrays."""
+    """cases: list of (d, e2, xs); per case an array [len(xs), 2] of the
+    (restarting, plain) counts."""
     lines = [str(len(cases))]
     for d, e2, xs in cases:
         lines.append(str(len(d)))
@@ -43,24 +45,12 @@ def run_counts(binary, cases):
         lines.append(" ".join(repr(float(v)) for v in xs))
     r = subprocess.run([binary], input="\n".join(lines) + "\n", capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
-    vals = [int(v) for v in r.stdout.split()]
+    vals = np.array([int(v) for v in r.stdout.split()]).reshape(-1, 2)
     out, at = [], 0
     for _, _, xs in cases:
-        out.append(np.array(vals[at:at + len(xs)]))
+        out.append(vals[at:at + len(xs)])
         at += len(xs)
     return out
-
-
-def _product_form_without_restart(d, e2, x):
-    """The recurrence before the split restart (for contrast)."""
-    p1, p2 = d[0] - x, 1.0
-    neg = p1 < 0
-    cnt = int(neg)
-    for j in range(1, len(d)):
-        p = (d[j] - x) * p1 - e2[j] * p2
-        cnt += (p < 0) != neg
-        neg, p2, p1 = p < 0, p1, p
-    return cnt
 
 
 def _admissible(eig, x, got):
@@ -74,11 +64,9 @@ def test_split_at_leading_pivot(sturm_bin):
     xs = [1.5, 1.0, 3.0, 1.25, 2.0, 3.5, 0.5]
     (c,) = run_counts(sturm_bin, [(d, e2, xs)])
     eig = np.array(d)
-    for x, got in zip(xs, c):
+    for x, got in zip(xs, c[:, 0]):
         assert _admissible(eig, x, got), (x, got)
-    assert c.tolist()[3:] == [1, 2, 3, 0]
-    # the recurrence without the restart counts nothing below 1.5
-    assert _product_form_without_restart(d, e2, 1.5) == 0
+    assert c[3:, 0].tolist() == [1, 2, 3, 0]
 
 
 def _blocks_case(rng, nblocks):
@@ -109,9 +97,9 @@ def test_split_blocks_at_block_eigenvalues(sturm_bin):
         eigs.append(eig)
     missed = 0
     for (d, e2, xs), eig, got in zip(cases, eigs, run_counts(sturm_bin, cases)):
-        for x, g in zip(xs, got):
+        for x, (g, plain) in zip(xs, got):
             assert _admissible(eig, x, g), (d, e2, x, g)
-            missed += not _admissible(eig, x, _product_form_without_restart(d, e2, x))
+            missed += not _admissible(eig, x, plain)
     assert missed > 0   # the cases do reach the split-at-a-zero-minor situation
 
 
@@ -129,4 +117,5 @@ def test_unsplit_random_vs_lapack(sturm_bin):
         eigs.append(eig)
     for (d, e2, xs), eig, got in zip(cases, eigs, run_counts(sturm_bin, cases)):
         want = np.array([(eig < x).sum() for x in xs])
-        assert np.array_equal(got, want)
+        assert np.array_equal(got[:, 0], want)
+        assert np.array_equal(got[:, 1], want)   # without splits the plain row agrees
