@@ -14,44 +14,55 @@
 namespace lhf {
 namespace {
 
-// Grouped factor launch: one workgroup per work item, for every lattice.
-//  * item.chunk >= 0: 256 nodes of one row of dimension item.d -- a basis
-//    function (row < m0, every dimension) or a potential term (row - m0) of a
-//    one-cell dimension, evaluated on the cell's own nodes;
+// Grouped factor launch: one workgroup of FT threads per work item, for
+// every lattice.
+//  * item.row < 0: the nodal values of every basis function on nodes
+//    [chunk FT/m0, (chunk + 1) FT/m0) of dimension item.d; thread t takes
+//    function t % m0 of node t / m0, so the node-major store [i][m0] is
+//    contiguous across the workgroup;
+//  * item.row >= 0, item.chunk >= 0: FT nodes of the potential term item.row of
+//    a one-cell dimension, on the cell's own nodes;
 //  * item.chunk < 0: the lattice-window potential factor (eq. EwaldSumP) of
 //    term item.row of a replicated dimension.  Thread t sums the images
-//    k = klo + c, c = t / nc (mod 256 / nc), for node t % nc of the central
-//    cell; the chunk sums are added in a fixed order, so the result is
-//    deterministic.
-__global__ void __launch_bounds__(256) factors_kernel(const LatDev* __restrict__ lats,
-                                                      const FacItem* __restrict__ items, int nitems,
-                                                      double* __restrict__ fac) {
-  __shared__ double part[256];
+//    k = klo + c, c = t / nc (mod FT / nc), for node t % nc of the central
+//    cell; the image partial sums are folded in two fixed-order levels, so
+//    the result is deterministic.
+constexpr int FT = 1024;
+constexpr int kFold = 32;   // first-level fold width of the window partials
+
+__global__ void __launch_bounds__(FT) factors_kernel(const LatDev* __restrict__ lats,
+                                                     const FacItem* __restrict__ items, int nitems,
+                                                     double* __restrict__ fac) {
+  __shared__ double part[FT];
+  __shared__ double part2[FT];
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const FacItem item = items[it];
     const LatDev& L = lats[item.li];
     const DimDev& D = L.dim[item.d];
     const int d = item.d;
-    if (item.chunk >= 0) {
-      const int i = item.chunk * 256 + threadIdx.x;
-      const int row = item.row;
-      if (row < L.m0) {
-        if (i < D.n) {
-          const int mu = row;
-          const double al = L.alpha[mu];
-          const double c = D.X0 + L.cen[mu][d];
-          const double x = D.x0 + i * D.h;
-          const int pw = L.lpow[mu][d];
-          double acc = 0.0;
-          for (int s = -D.nimg; s <= D.nimg; ++s) {
-            const double u = x - c - s * D.period;
-            const double g = exp(-al * u * u);
-            acc += pw ? g * u : g;
-          }
-          fac[D.g_off + (int64_t)i * L.m0 + mu] = L.norm[mu][d] * acc;
+    const int tid = threadIdx.x;
+    if (item.row < 0) {
+      const int m0 = L.m0, per = FT / m0;
+      const int mu = tid % m0, i = item.chunk * per + tid / m0;
+      if (tid < per * m0 && i < D.n) {
+        const double al = L.alpha[mu];
+        const double c = D.X0 + L.cen[mu][d];
+        const double x = D.x0 + i * D.h;
+        const int pw = L.lpow[mu][d];
+        double acc = 0.0;
+        for (int s = -D.nimg; s <= D.nimg; ++s) {
+          const double u = x - c - s * D.period;
+          const double g = exp(-al * u * u);
+          acc += pw ? g * u : g;
         }
-      } else if (i < D.npot) {
-        const int r = row - L.m0;   // potential term nu R + q
+        fac[D.g_off + (int64_t)i * m0 + mu] = L.norm[mu][d] * acc;
+      }
+      continue;
+    }
+    if (item.chunk >= 0) {
+      const int i = item.chunk * FT + tid;
+      if (i < D.npot) {
+        const int r = item.row;   // potential term nu R + q
         const int nu = r / L.R, q = r % L.R;
         double v = cell_gauss(D.x0 + i * D.h, D.h, L.tq[q], D.X0 + L.nuc[nu][d]);
         if (d == 0) v *= L.Z[nu] * L.wq[q];
@@ -63,8 +74,7 @@ __global__ void __launch_bounds__(256) factors_kernel(const LatDev* __restrict__
     const int nu = r / L.R, q = r % L.R;
     const double t = L.tq[q], A = L.nuc[nu][d];
     const int nc = D.nc;
-    const int chunks = 256 / nc;
-    const int tid = threadIdx.x;
+    const int chunks = FT / nc;
     const int j = tid % nc, c = tid / nc;
     int klo, khi;
     if (D.L & 1) { klo = -(D.L - 1) / 2; khi = (D.L - 1) / 2; }
@@ -79,13 +89,21 @@ __global__ void __launch_bounds__(256) factors_kernel(const LatDev* __restrict__
     }
     part[tid] = acc;
     __syncthreads();
+    // level 1: partial g of node j sums chunks g, g + G1, g + 2 G1, ...
+    const int G1 = chunks < kFold ? chunks : kFold;
+    if (c < G1) {
+      double v = 0.0;
+      for (int cc = c; cc < chunks; cc += G1) v += part[cc * nc + j];
+      part2[c * nc + j] = v;
+    }
+    __syncthreads();
     if (tid < nc) {
       double v = 0.0;
-      for (int cc = 0; cc < chunks; ++cc) v += part[cc * nc + tid];
+      for (int g = 0; g < G1; ++g) v += part2[g * nc + tid];
       if (d == 0) v *= L.Z[nu] * L.wq[q];
       fac[D.p_off + (int64_t)r * D.npot + tid] = v;
     }
-    __syncthreads();   // part[] is reused by the next item
+    __syncthreads();   // part[] and part2[] are reused by the next item
   }
 }
 
@@ -101,18 +119,18 @@ void plan_factors(const std::vector<LatDev>& lats, std::vector<FacItem>& items) 
         for (int r = 0; r < L.M0 * L.R; ++r) items.push_back(FacItem{li, d, r, -1});
     for (int d = 0; d < 3; ++d) {
       const DimDev& D = L.dim[d];
-      for (int row = 0; row < L.m0; ++row)
-        for (int ch = 0; ch < (D.n + 255) / 256; ++ch) items.push_back(FacItem{li, d, row, ch});
+      const int per = FT / L.m0;   // nodes per basis chunk
+      for (int ch = 0; ch < (D.n + per - 1) / per; ++ch) items.push_back(FacItem{li, d, -1, ch});
       if (!D.replicate)
         for (int r = 0; r < L.M0 * L.R; ++r)
-          for (int ch = 0; ch < (D.npot + 255) / 256; ++ch) items.push_back(FacItem{li, d, L.m0 + r, ch});
+          for (int ch = 0; ch < (D.npot + FT - 1) / FT; ++ch) items.push_back(FacItem{li, d, r, ch});
     }
   }
 }
 
 hipError_t launch_factors(const lhf_plan_s* p, double* fac, hipStream_t s) {
   const int grid = std::min(p->n_fac_items, 8192);
-  hipLaunchKernelGGL(factors_kernel, dim3(grid), dim3(256), 0, s, p->d_lat, p->d_fac_items, p->n_fac_items, fac);
+  hipLaunchKernelGGL(factors_kernel, dim3(grid), dim3(FT), 0, s, p->d_lat, p->d_fac_items, p->n_fac_items, fac);
   return hipGetLastError();
 }
 

@@ -201,22 +201,66 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
 }
 
 // Sum the split partials and scatter C[(t, nu)][(s, mu)] to Gram[t][s][mu][nu];
-// blockIdx.y enumerates (lattice, dimension).
+// blockIdx.y enumerates (lattice, dimension).  Each workgroup step takes nb
+// whole m0 x m0 blocks (t, s) and transposes them through LDS: the partials
+// are read along mu (contiguous in C) and the Grams written along nu
+// (contiguous in the Gram layout).
 template <typename T>
 __global__ void __launch_bounds__(256) gram_reduce_kernel(const LatDev* __restrict__ lats,
                                                           const T* __restrict__ part, T* __restrict__ grams) {
+  __shared__ T tile[512];   // nb blocks of m0 x (m0 + 1) (m0^2 <= 256), or m0 x (256 / m0 + 1)
   const int li = blockIdx.y / 3, d = blockIdx.y % 3;
   const LatDev& L = lats[li];
   const DimDev& D = L.dim[d];
-  const int M = L.T * L.m0, N = D.nshift * L.m0;
-  const int MN = M * N;
-  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < MN; idx += gridDim.x * 256) {
-    const int r = idx / N, c = idx - r * N;
-    const T* src = part + D.part_off + idx;
-    T acc = 0;
-    for (int ks = 0; ks < D.ksplit; ++ks) acc += src[(int64_t)ks * MN];
-    const int t = r / L.m0, nu = r - t * L.m0, slot = c / L.m0, mu = c - slot * L.m0;
-    grams[D.gram_off + (((int64_t)t * D.nshift + slot) * L.m0 + mu) * L.m0 + nu] = acc;
+  const int m0 = L.m0, m2 = m0 * m0;
+  const int N = D.nshift * m0;
+  const int64_t MN = (int64_t)L.T * m0 * N;
+  const int nblocks = L.T * D.nshift;
+  const T* src0 = part + D.part_off;
+  if (m2 <= 256) {
+    const int nb = 256 / m2, tid = threadIdx.x;
+    const int bl = tid / m2, e = tid - bl * m2;
+    for (int b0 = blockIdx.x * nb; b0 < nblocks; b0 += gridDim.x * nb) {
+      const int b = b0 + bl;
+      const bool ok = bl < nb && b < nblocks;
+      if (ok) {
+        const int t = b / D.nshift, slot = b - t * D.nshift;
+        const int nu = e / m0, mu = e - nu * m0;
+        const T* src = src0 + (int64_t)(t * m0 + nu) * N + slot * m0 + mu;
+        T acc = 0;
+        for (int ks = 0; ks < D.ksplit; ++ks) acc += src[(int64_t)ks * MN];
+        tile[bl * (m2 + m0) + nu * (m0 + 1) + mu] = acc;
+      }
+      __syncthreads();
+      if (ok) {
+        const int mu = e / m0, nu = e - mu * m0;
+        grams[D.gram_off + (int64_t)b * m2 + e] = tile[bl * (m2 + m0) + nu * (m0 + 1) + mu];
+      }
+      __syncthreads();
+    }
+  } else {
+    // m0 > 16: one block per step, in row groups of 256 / m0 rows nu
+    const int rows = 256 / m0, tid = threadIdx.x;
+    const int rr = tid / m0, mu = tid - rr * m0;
+    for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+      const int t = b / D.nshift, slot = b - t * D.nshift;
+      for (int nu0 = 0; nu0 < m0; nu0 += rows) {
+        const int nu = nu0 + rr;
+        const bool ok = rr < rows && nu < m0;
+        if (ok) {
+          const T* src = src0 + (int64_t)(t * m0 + nu) * N + slot * m0 + mu;
+          T acc = 0;
+          for (int ks = 0; ks < D.ksplit; ++ks) acc += src[(int64_t)ks * MN];
+          tile[mu * (rows + 1) + rr] = acc;
+        }
+        __syncthreads();
+        // write rows mu, columns nu0 .. nu0 + rows - 1 (runs of `rows` doubles)
+        const int wmu = tid / rows, wr = tid - wmu * rows;
+        if (wmu < m0 && nu0 + wr < m0)
+          grams[D.gram_off + (int64_t)b * m2 + (int64_t)wmu * m0 + nu0 + wr] = tile[wmu * (rows + 1) + wr];
+        __syncthreads();
+      }
+    }
   }
 }
 
@@ -239,7 +283,8 @@ hipError_t launch_grams(const lhf_plan_s* p, int mode, const double* fac, void* 
   int64_t maxmn = 0;
   for (const LatDev& L : p->lat)
     for (int d = 0; d < 3; ++d) maxmn = std::max<int64_t>(maxmn, (int64_t)L.T * L.m0 * L.dim[d].nshift * L.m0);
-  const dim3 rgrid((unsigned)std::min<int64_t>((maxmn + 255) / 256, 1024), (unsigned)(3 * p->nlat));
+  // about one output element per thread (256 per workgroup step)
+  const dim3 rgrid((unsigned)std::max<int64_t>(1, std::min<int64_t>((maxmn + 255) / 256, 1024)), (unsigned)(3 * p->nlat));
   if (mode == LHF_GRAM_FP64)
     hipLaunchKernelGGL(gram_reduce_kernel<double>, rgrid, dim3(256), 0, s, p->d_lat, (const double*)part, (double*)grams);
   else

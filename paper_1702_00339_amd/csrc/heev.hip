@@ -678,10 +678,12 @@ __device__ void eig_rank(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int m, int
 // over aligned groups of P lanes (P a power of two <= 64): quad permutes pair
 // i with i^1 and i^2, then the mirrors i <-> 7-i and i <-> 15-i join two
 // halves that are already reduced; lane shuffles only across rows.
+// Every source lane of these patterns lies in the destination's own group
+// and is active whenever the group is, so the moves keep no old value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
   return __hiloint2double(hi, lo);
 }
 template <int P, typename F>
@@ -693,6 +695,24 @@ __device__ __forceinline__ double lane_reduce(double v, F op) {
   if constexpr (P >= 32) v = op(v, __shfl_xor(v, 16, 64));
   if constexpr (P >= 64) v = op(v, __shfl_xor(v, 32, 64));
   return v;
+}
+// Two independent all-reduces, level by level, so their latencies overlap.
+template <int P, typename F>
+__device__ __forceinline__ void lane_reduce2(double& a, double& b, F op) {
+  if constexpr (P >= 2) { const double x = dpp_move<0xB1>(a), y = dpp_move<0xB1>(b); a = op(a, x); b = op(b, y); }
+  if constexpr (P >= 4) { const double x = dpp_move<0x4E>(a), y = dpp_move<0x4E>(b); a = op(a, x); b = op(b, y); }
+  if constexpr (P >= 8) { const double x = dpp_move<0x141>(a), y = dpp_move<0x141>(b); a = op(a, x); b = op(b, y); }
+  if constexpr (P >= 16) { const double x = dpp_move<0x140>(a), y = dpp_move<0x140>(b); a = op(a, x); b = op(b, y); }
+  if constexpr (P >= 32) {
+    const double x = __shfl_xor(a, 16, 64), y = __shfl_xor(b, 16, 64);
+    a = op(a, x);
+    b = op(b, y);
+  }
+  if constexpr (P >= 64) {
+    const double x = __shfl_xor(a, 32, 64), y = __shfl_xor(b, 32, 64);
+    a = op(a, x);
+    b = op(b, y);
+  }
 }
 
 // (re, im) = W Y with the unit lower triangular W held in the strictly upper
@@ -942,145 +962,124 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
   typedef typename Cx<R>::T C;
   constexpr int TPM = M * M / W, P = TPM / M;
   static_assert(P >= 1 && (P & (P - 1)) == 0 && P <= 64, "row group of one wavefront");
-  C* uv = &sh.B[g][0][0];   // reflector u (B is free after the reduction)
-  C* qv = &sh.B[g][1][0];   // p
+  static_assert(M >= 4, "size classes start at 4");
   R* dg = sh.dsc[g];        // diagonal d
   R* e2 = sh.dn[g];         // squared subdiagonal moduli
   C* de = &sh.B[g][2][0];   // (d_j, e_(j-1)^2) per row, one LDS word for the Sturm pass
   const int gi = t / P, gc = t % P;   // row group and lane within it
   auto add = [](double x, double y) { return x + y; };
-  // u^H p: M <= 16 publishes Re(conj(u_i) p_i) per row and every thread sums
-  // the rows; M = 32 reduces per wavefront (fewer LDS reads for 256 threads)
-  constexpr bool kRows = M <= 16;
-  constexpr int WV = TPM < 64 ? TPM : 64, NWM = TPM < 64 ? 1 : TPM / 64;
-  static_assert(NWM <= 16, "per-wave partials fit the reduction array");
-  R* upv = dg;              // per-row terms (d is written after the loop)
-  R* part = sh.red[g];      // per-wave partial sums
-  R* bsh = &sh.lam[g][0];   // beta of the current step (lam is written after the loop)
-  // three barriers per step: u and beta published; p and Re(conj(u_i) p_i)
-  // published per row; trailing block updated with q = p - K u formed in place
+  // The reduction keeps the matrix in registers, column by column: lane gc of
+  // group gi holds column gi, rows gc + P k (k < W), so the column norm and
+  // (A^H u)_c are all-reduces over the group's P lanes (an aligned DPP
+  // group).  Per step h: the group owning column h forms u and beta; barrier;
+  // every group forms p_c = beta sum_r conj(A_rc) u_r (= (beta A u)_c, A
+  // Hermitian) and publishes p_c and Re(conj(u_c) p_c); barrier; every lane
+  // updates its entries, and the owner of column h + 1 goes straight on to
+  // the next reflector, its column being current.  u, p, those products and
+  // u^H u / 2 are double-buffered in LDS by the parity of h, so two barriers
+  // per step keep every read ahead of the next overwrite.
+  C* const lb = &sh.B[g][0][0];   // B is free after the reduction
+  C* const ubuf = lb;             // u: [2][M]
+  C* const pbuf = lb + 2 * M;     // p: [2][M]
+  R* const upbuf = reinterpret_cast<R*>(lb + 4 * M);   // Re(conj(u_i) p_i): [2][M]
+  R* const bbuf = sh.red[g];      // u^H u / 2: [2]
+  C a[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) a[k] = sh.A[g][gc + P * k][gi];
 #pragma unroll 1
   for (int h = 0; h < M - 2; ++h) {
+    const int bsel = h & 1;
     const bool act = h < n - 2;
-    // the column below the diagonal sits in lanes t < n <= M of the first
-    // wave; every LDS read of the phase is issued before any use
-    const C xv = sh.A[g][t < M ? t : 0][h];
-    const C al0 = sh.A[g][h + 1][h];
-    R x2 = act && t > h + 1 && t < n ? xv.x * xv.x + xv.y * xv.y : R(0);
-    x2 = lane_reduce<M>(x2, add);
-    if (t < M) {
-      const C al = act ? al0 : cmk<C>(R(0), R(0));
-      const R a2 = al.x * al.x + al.y * al.y;
-      const R a = sqrt(a2), nrm = sqrt(a2 + x2);
-      const R beta = act && x2 > R(0) ? R(1) / (nrm * (nrm + a)) : R(0);
-      const C ph = a > R(0) ? cscale(al, R(1) / a) : cmk<C>(R(1), R(0));
-      if (act && t > h && t < n) uv[t] = t == h + 1 ? cscale(ph, a + nrm) : xv;
-      if (t == 0) {
-        bsh[0] = beta;
+    C* const u = ubuf + bsel * M;
+    C* const pv = pbuf + bsel * M;
+    R* const upv = upbuf + bsel * M;
+    if (gi == h) {
+      // x: column h below the diagonal; a2 = |x_0|^2 (row h + 1), x2 the rest
+      R a2 = R(0), x2 = R(0);
+      C al = cmk<C>(R(0), R(0));
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        const int r = gc + P * k;
+        const R v = a[k].x * a[k].x + a[k].y * a[k].y;
+        if (r == h + 1) {
+          a2 += v;
+          al = a[k];
+        } else if (r > h + 1 && r < n) {
+          x2 += v;
+        }
+      }
+      lane_reduce2<P>(a2, x2, add);
+      const R ar = sqrt(a2), nrm = sqrt(a2 + x2);
+      // u = phase(x_0) (|x_0| + |x|) e_0 + x scaled by sc = |x_0| (1 when
+      // x_0 = 0), which needs no division: u_(h+1) = x_0 (|x_0| + |x|),
+      // u_r = |x_0| x_r below, zero elsewhere; hh = u^H u / 2 =
+      // sc^2 |x| (|x| + |x_0|), and beta = 1 / hh is formed by the readers
+      const R sc = ar > R(0) ? ar : R(1);
+      const C u1 = ar > R(0) ? cscale(al, ar + nrm) : cmk<C>(nrm, R(0));
+      const R hh = act && x2 > R(0) ? sc * sc * (nrm * (nrm + ar)) : R(0);
+#pragma unroll
+      for (int k = 0; k < W; ++k) {
+        const int r = gc + P * k;
+        const bool in = act && r > h && r < n;
+        u[r] = in ? (r == h + 1 ? u1 : cscale(a[k], sc)) : cmk<C>(R(0), R(0));
+      }
+      if (gc == 0) {
+        bbuf[bsel] = hh;
         if (act) e2[h] = a2 + x2;
       }
     }
     __syncthreads();
-    // p_i = beta sum_j A_ij u_j, row i by the P lanes of group i; the loads
-    // are issued with beta's (entries outside the block are masked after)
-    const R beta = bsh[0];
-    const bool row = beta != R(0) && gi > h && gi < n;
-    C acc = cmk<C>(R(0), R(0));
-    C ui = cmk<C>(R(0), R(0));
-    if constexpr (M <= 16) {
-      C arow[M / P], urow[M / P];
+    const R hh = bbuf[bsel];
+    const bool refl = hh != R(0);
+    const R beta = refl ? R(1) / hh : R(0);   // overlaps the loads and the reduction below
+    const bool colok = gi > h && gi < n;
+    C ur[W], pc = cmk<C>(R(0), R(0));
 #pragma unroll
-      for (int jj = 0; jj < M / P; ++jj) {
-        arow[jj] = sh.A[g][gi][gc + jj * P];
-        urow[jj] = uv[gc + jj * P];
+    for (int k = 0; k < W; ++k) ur[k] = u[gc + P * k];
+    const C uc = u[gi];
+    if (refl) {
+      C sacc = cmulc(a[0], ur[0]);   // conj(A_rc) u_r
+#pragma unroll
+      for (int k = 1; k < W; ++k) sacc = cadd(sacc, cmulc(a[k], ur[k]));
+      lane_reduce2<P>(sacc.x, sacc.y, add);
+      pc = cscale(sacc, beta);
+      if (gc == 0) {
+        pv[gi] = pc;
+        upv[gi] = colok ? uc.x * pc.x + uc.y * pc.y : R(0);
       }
-      ui = uv[gi];
-#pragma unroll
-      for (int jj = 0; jj < M / P; ++jj) {
-        const int j = gc + jj * P;
-        const C pr = cmul(arow[jj], urow[jj]);
-        if (j > h && j < n) acc = cadd(acc, pr);
-      }
-      if (!row) acc = cmk<C>(R(0), R(0));
-    } else if (row) {
-      // M = 32 keeps its registers for occupancy
-#pragma unroll
-      for (int j = gc; j < M; j += P)
-        if (j > h && j < n) acc = cadd(acc, cmul(sh.A[g][gi][j], uv[j]));
-      ui = uv[gi];
-    }
-    acc.x = lane_reduce<P>(acc.x, add);
-    acc.y = lane_reduce<P>(acc.y, add);
-    acc = cscale(acc, beta);
-    R up = R(0);
-    if (row && gc == 0) {
-      up = ui.x * acc.x + ui.y * acc.y;   // Re(conj(u_i) p_i)
-      if constexpr (kRows) upv[gi] = up;
-      qv[gi] = acc;                       // p
-    }
-    if constexpr (!kRows) {
-      up = lane_reduce<WV>(up, add);
-      if ((t & (WV - 1)) == 0) part[t / WV] = up;
     }
     __syncthreads();
-    if (beta != R(0)) {
-      R ks = R(0);
-      if constexpr (kRows) {
-        // every entry read (stale ones deselected), four partial sums
-        R ks4[4] = {R(0), R(0), R(0), R(0)};
+    if (refl) {
+      // K = beta u^H p / 2, four partial sums over the rows
+      R ks4[4];
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-          const R v = upv[i];
-          ks4[i & 3] += i > h && i < n ? v : R(0);
-        }
-        ks = (ks4[0] + ks4[1]) + (ks4[2] + ks4[3]);
-      } else {
+      for (int i = 0; i < 4; ++i) ks4[i] = upv[i];
 #pragma unroll
-        for (int w = 0; w < NWM; ++w) ks += part[w];
-      }
-      const R kk = R(0.5) * beta * ks;
-      // the W entries of a thread share column t % M (TPM is a multiple of M)
-      const int c = t % M;
-      if constexpr (M <= 16) {
-        // every read issued first (M = 32 keeps its registers for occupancy)
-        const C uc = uv[c], qc = csub(qv[c], cscale(uc, kk));
-        C ur[W], pr[W], ar[W];
+      for (int i = 4; i < M; ++i) ks4[i & 3] += upv[i];
+      const R kk = R(0.5) * beta * ((ks4[0] + ks4[1]) + (ks4[2] + ks4[3]));
+      C pr[W];
+#pragma unroll
+      for (int k = 0; k < W; ++k) pr[k] = pv[gc + P * k];
+      const C qc = csub(pc, cscale(uc, kk));
+      if (colok) {
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          const int r = (t + k * TPM) / M;
-          ur[k] = uv[r];
-          pr[k] = qv[r];
-          ar[k] = sh.A[g][r][c];
-        }
-        if (c > h && c < n) {
-#pragma unroll
-          for (int k = 0; k < W; ++k) {
-            const int r = (t + k * TPM) / M;
-            if (r > h && r < n) {
-              const C qr = csub(pr[k], cscale(ur[k], kk));
-              // A_rc -= u_r conj(q_c) + q_r conj(u_c)
-              sh.A[g][r][c] = csub(ar[k], cadd(cmulc(qc, ur[k]), cmulc(uc, qr)));
-            }
-          }
-        }
-      } else if (c > h && c < n) {
-        const C uc = uv[c], qc = csub(qv[c], cscale(uc, kk));
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-          const int r = (t + k * TPM) / M;
+          const int r = gc + P * k;
           if (r > h && r < n) {
-            const C ur = uv[r], qr = csub(qv[r], cscale(ur, kk));
-            sh.A[g][r][c] = csub(sh.A[g][r][c], cadd(cmulc(qc, ur), cmulc(uc, qr)));
+            const C qr = csub(pr[k], cscale(ur[k], kk));
+            // A_rc -= u_r conj(q_c) + q_r conj(u_c)
+            a[k] = csub(a[k], cadd(cmulc(qc, ur[k]), cmulc(uc, qr)));
           }
         }
       }
     }
-    __syncthreads();
   }
-  if (t < n) dg[t] = sh.A[g][t][t].x;
-  if (t == 0 && n >= 2) {
-    const C b = sh.A[g][n - 1][n - 2];
-    e2[n - 2] = b.x * b.x + b.y * b.y;
+  // d and the last squared coupling |A_(n-1, n-2)|^2 from the registers
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    const int r = gc + P * k;
+    if (r == gi && gi < n) dg[gi] = a[k].x;
+    if (n >= 2 && gi == n - 2 && r == n - 1) e2[n - 2] = a[k].x * a[k].x + a[k].y * a[k].y;
   }
   __syncthreads();
   // Gershgorin interval of the tridiagonal matrix, one row per lane t < M of

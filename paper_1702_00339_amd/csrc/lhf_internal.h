@@ -69,8 +69,10 @@ struct GramItem {
   int32_t li, d, tm, tn, ks, pad;
 };
 
-// Grouped factor work: nodes [256 chunk, 256 chunk + 256) of one row (basis
-// function, or potential term of a one-cell dimension) of one lattice dim.
+// Grouped factor work of one lattice dimension: row < 0, every basis function
+// on one chunk of nodes; row >= 0 with chunk >= 0, one chunk of nodes of the
+// potential term `row` of a one-cell dimension; chunk < 0, the lattice-window
+// potential factor of term `row` of a replicated dimension.
 struct FacItem {
   int32_t li, d, row, chunk;
 };
