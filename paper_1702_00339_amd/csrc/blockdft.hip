@@ -706,6 +706,105 @@ __global__ void __launch_bounds__(256) sep_fused_kernel(const LatDev* __restrict
   fused_last_stage<double, BM>(L, J2C, j2lo, j2n, j3, e0, ecn, T2, tw1, isH, barH, barS, nullptr, nullptr);
 }
 
+constexpr int kChainEC = 8;    // block entries per chain workgroup
+constexpr int kChainJC = 32;   // outputs j1 per chain workgroup
+constexpr int kChainTC = 32;   // Gram terms per step
+constexpr int kChainB = 32;    // widest band of a chain (as for the fused kernels)
+
+// Separable formation of a chain (L2 = L3 = 1).  Dimensions 2 and 3 are one
+// cell wide, their Grams single blocks, so per block entry e the products
+//   Q_0 = (K2 S3 + S2 K3) / 2,  Q_1 = S2 S3 / 2,  Q_t = -M2_t M3_t (t >= 2),
+// are plain numbers, the generator entries of slot s are
+//   A^H_s = sum_t G1_t[s] Q_t  (G1_0 = S1, G1_1 = K1),   A^S_s = S1[s] S2 S3,
+// and Hbar_j = sum_s w1^(j k_s) A_s.  Workgroup (lattice, kChainEC entries,
+// kChainJC outputs j), thread (slot, entry) while forming A, then (j, entry):
+// per step of kChainTC terms every thread issues its slot's Gram loads, the
+// workgroup stages the step's Q_t in LDS meanwhile, and the thread
+// accumulates; then the chunk's twiddles and one output of each operator per
+// thread.  No generator stack is formed.
+__global__ void __launch_bounds__(256) sep_chain_kernel(const LatDev* __restrict__ lats,
+                                                        const FusedTask* __restrict__ tasks, int ntasks,
+                                                        const double2* __restrict__ tw,
+                                                        const double* __restrict__ grams,
+                                                        double2* __restrict__ barH, double2* __restrict__ barS) {
+  constexpr int EC = kChainEC, JC = kChainJC, TC = kChainTC, BC = kChainB;
+  static_assert(BC * EC == 256 && JC * EC == 256, "one (slot, entry) and one (j, entry) pair per thread");
+  __shared__ double Qs[TC][EC];
+  __shared__ double As[2][BC][EC];
+  __shared__ double2 Ws[JC][BC];
+  const int64_t wg = blockIdx.x;
+  const FusedTask T = tasks[find_fused(tasks, ntasks, wg)];
+  const LatDev& L = lats[T.li];
+  const DimDev& D0 = L.dim[0];
+  const DimDev& D1 = L.dim[1];
+  const DimDev& D2 = L.dim[2];
+  const int L1 = L.L[0], B1 = nslot(D0), E = L.m0 * L.m0;
+  const int64_t loc = wg - T.wg_base;
+  const int eci = (int)(loc % T.nec), jci = (int)(loc / T.nec);
+  const int e0 = eci * EC, ecn = min(EC, E - e0);
+  const int j0 = jci * JC, jn = min(JC, L1 - j0);
+  const int tid = threadIdx.x;
+  const double* g0 = grams + D0.gram_off;   // [t][nshift][E]
+  const double* g1 = grams + D1.gram_off;   // [t][E] (one slot)
+  const double* g2 = grams + D2.gram_off;
+  const int sl = tid / EC, ec = tid % EC;
+  const bool mine = sl < B1 && ec < ecn;
+  const int64_t tstride = (int64_t)D0.nshift * E;
+  const double* src = g0 + (int64_t)sl * E + e0 + ec;
+  double acc = 0.0, s1 = 0.0;
+  for (int t0 = 0; t0 < L.T; t0 += TC) {
+    const int tc = min(TC, L.T - t0);
+    double x[TC];
+#pragma unroll
+    for (int v = 0; v < TC; ++v) x[v] = mine && v < tc ? src[(int64_t)(t0 + v) * tstride] : 0.0;
+    // Q_t of the step, one (term, entry) pair per thread
+    {
+      const int tt = tid / EC, qe = tid % EC;
+      const int t = t0 + tt;
+      double q = 0.0;
+      if (tt < tc && qe < ecn) {
+        const int e = e0 + qe;
+        if (t >= 2) q = -g1[(int64_t)t * E + e] * g2[(int64_t)t * E + e];
+        else if (t == 1) q = 0.5 * g1[e] * g2[e];
+        else q = 0.5 * (g1[E + e] * g2[e] + g1[e] * g2[E + e]);
+      }
+      Qs[tt][qe] = q;
+    }
+    __syncthreads();
+    if (t0 == 0) s1 = x[0];
+#pragma unroll
+    for (int v = 0; v < TC; ++v) acc += x[v] * Qs[v][ec];
+    __syncthreads();
+  }
+  // S2 S3 = 2 Q_1 (exact), and the twiddles w1^(j k_s) of the chunk
+  const int e = e0 + ec;
+  const double s23 = ec < ecn ? g1[e] * g2[e] : 0.0;
+  As[0][sl][ec] = mine ? acc : 0.0;
+  As[1][sl][ec] = mine ? s1 * s23 : 0.0;
+  for (int q = tid; q < JC * B1; q += 256) {
+    const int jj = q / B1, ss = q - jj * B1;
+    const int64_t m = (int64_t)(j0 + jj) * slot_cell(D0, ss) % L1;
+    Ws[jj][ss] = jj < jn ? tw[D0.tw_off + (int)m] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int jj = tid / EC;
+  if (jj < jn && ec < ecn) {
+    double hr = 0.0, hi = 0.0, sr = 0.0, si = 0.0;
+#pragma unroll 4
+    for (int ss = 0; ss < B1; ++ss) {
+      const double2 w = Ws[jj][ss];
+      const double ah = As[0][ss][ec], as = As[1][ss][ec];
+      hr += w.x * ah;
+      hi += w.y * ah;
+      sr += w.x * as;
+      si += w.y * as;
+    }
+    const int64_t o = L.gen_off + (int64_t)(j0 + jj) * E + e;
+    barH[o] = make_double2(hr, hi);
+    barS[o] = make_double2(sr, si);
+  }
+}
+
 }  // namespace
 
 // LDS bytes (complex128) of the fused kernel for a lattice, 0 when the
@@ -827,14 +926,18 @@ void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std
   }
 }
 
-// Separable formation: one task per lattice (workgroups as in the fused
-// kernel; every lattice shape, chains included), and the transforms of the
-// Grams along dimensions 2 and 3.  ok = false when a lattice has a first
-// dimension band wider than 32 slots or needs more than 64 KiB of LDS.
+// Separable formation: one task per chain for sep_chain_kernel, and for every
+// other lattice one task (workgroups as in the fused kernel) and the
+// transforms of its Grams along dimensions 2 and 3.  ok = false when a
+// lattice has a first-dimension band wider than 32 slots or needs more than
+// 64 KiB of LDS.
 void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tasks, std::vector<GhItem>& items,
-                    int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, bool& ok) {
+                    int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, std::vector<FusedTask>& chain,
+                    int64_t& chain_wgs, bool& ok) {
   tasks.clear();
   items.clear();
+  chain.clear();
+  chain_wgs = 0;
   wgs = 0;
   bmax = 0;
   lds = 0;
@@ -843,6 +946,20 @@ void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tas
   for (int li = 0; li < (int)lats.size(); ++li) {
     const LatDev& L = lats[li];
     const int B1 = nslot(L.dim[0]);
+    if (L.L[1] == 1 && L.L[2] == 1) {
+      // a chain: sep_chain_kernel, which needs no transformed Grams
+      if (B1 > kChainB) ok = false;
+      FusedTask c{};
+      c.li = li;
+      c.EC = kChainEC;
+      c.nec = (L.m0 * L.m0 + kChainEC - 1) / kChainEC;
+      c.J2C = kChainJC;
+      c.nj2c = (L.L[0] + kChainJC - 1) / kChainJC;
+      c.wg_base = chain_wgs;
+      chain_wgs += (int64_t)c.nec * c.nj2c;
+      chain.push_back(c);
+      continue;
+    }
     FusedTask t{};
     t.li = li;
     t.EC = kFusedEC;
@@ -866,7 +983,11 @@ void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tas
 
 hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* gh, double2* bar_h, double2* bar_s,
                               hipStream_t s) {
-  if (!p->sep_ok || !gh) return hipErrorInvalidValue;
+  if (!p->sep_ok || (p->n_sep > 0 && !gh)) return hipErrorInvalidValue;
+  if (p->n_sep_chain > 0)
+    hipLaunchKernelGGL(sep_chain_kernel, dim3((unsigned)p->sep_chain_wgs), dim3(256), 0, s, p->d_lat,
+                       p->d_sep_chain, p->n_sep_chain, p->d_tw64, g64, bar_h, bar_s);
+  if (p->n_sep == 0) return hipGetLastError();
   hipLaunchKernelGGL(gram_dft_kernel, dim3((unsigned)(p->gh_threads / 256)), dim3(256), 0, s, p->d_lat,
                      p->d_gh_items, p->n_gh_items, g64, p->d_tw64, gh);
   const dim3 grid((unsigned)p->sep_wgs, 2);

@@ -272,8 +272,11 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->n_fused = (int32_t)fused.size();
   std::vector<FusedTask> sep;
   std::vector<GhItem> gh_items;
-  plan_separable(p->lat, sep, gh_items, p->sep_wgs, p->sep_bmax, p->sep_lds, p->gh_threads, p->sep_ok);
+  std::vector<FusedTask> sep_chain;
+  plan_separable(p->lat, sep, gh_items, p->sep_wgs, p->sep_bmax, p->sep_lds, p->gh_threads, sep_chain,
+                 p->sep_chain_wgs, p->sep_ok);
   p->n_sep = (int32_t)sep.size();
+  p->n_sep_chain = (int32_t)sep_chain.size();
   p->n_gh_items = (int32_t)gh_items.size();
   p->gh_elems = gh;
   p->sizes.nlat = nlat;
@@ -368,6 +371,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   upload(p->d_fused, fused.data(), fused.size());
   if (p->sep_ok) {
     upload(p->d_sep, sep.data(), sep.size());
+    upload(p->d_sep_chain, sep_chain.data(), sep_chain.size());
     upload(p->d_gh_items, gh_items.data(), gh_items.size());
   }
   for (int c = 0; c < 4; ++c) upload(p->d_canon[c], canon[c].data(), canon[c].size());
@@ -406,7 +410,7 @@ int32_t lhf_plan_destroy(lhf_plan_t plan) {
   if (!plan) return LHF_OK;
   void* tables[] = {plan->d_lat, plan->d_tw64, plan->d_tw32, plan->d_gram_items, plan->d_fac_items,
                     plan->d_elem_start, plan->d_dft_tasks, plan->d_fused, plan->d_canon[0], plan->d_canon[1],
-                    plan->d_canon[2], plan->d_canon[3], plan->d_sep, plan->d_gh_items};
+                    plan->d_canon[2], plan->d_canon[3], plan->d_sep, plan->d_sep_chain, plan->d_gh_items};
   for (void* t : tables)
     if (t) (void)hipFree(t);
   delete plan;

@@ -35,8 +35,11 @@ struct lhf_plan_s {
   int32_t fused_lds = 0;                // bytes of LDS per workgroup for complex128
   // separable Fourier-block formation (every lattice, when each qualifies)
   bool sep_ok = false;
-  lhf::FusedTask* d_sep = nullptr;      // one task per lattice
+  lhf::FusedTask* d_sep = nullptr;      // one task per lattice that is not a chain
   int32_t n_sep = 0;
+  lhf::FusedTask* d_sep_chain = nullptr;  // one task per chain (L2 = L3 = 1)
+  int32_t n_sep_chain = 0;
+  int64_t sep_chain_wgs = 0;
   int64_t sep_wgs = 0;
   int32_t sep_bmax = 0;                 // largest first-dimension band
   int32_t sep_lds = 0;                  // bytes of LDS per workgroup
@@ -113,7 +116,8 @@ hipError_t launch_block_dft(const lhf_plan_s* p, int prec, const void* gen_h, co
                             void* bar_h, void* bar_s, void* tmp, float2* b32_h, float2* b32_s, hipStream_t s);
 // blockdft.hip: separable Fourier blocks from the FP64 Grams (complex128 out)
 void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tasks, std::vector<GhItem>& items,
-                    int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, bool& ok);
+                    int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, std::vector<FusedTask>& chain,
+                    int64_t& chain_wgs, bool& ok);
 hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* gh, double2* bar_h, double2* bar_s,
                               hipStream_t s);
 // eigvec.hip: full-lattice eigenvectors of selected (block, column) pairs of one lattice
