@@ -951,12 +951,12 @@ __device__ void chol_reduce_wup(Smem<double, M, G, false, false, true>& sh, int 
 // coupling takes the row that restarts the recurrence there, the others the
 // plain one), on T scaled by a power of two to norm below 1 and rescaled by
 // 2^-+256 every eighth row against overflow and underflow (exact,
-// sign-preserving).  Each lane runs
-// two sequences at once (2 P + 1 sections per pass).  The points of a pass
-// increase along the group's lanes and the counts are monotone in x, so the
-// points with count <= i form a prefix: its length k, from two ballots, gives
-// the new interval [point k, point k + 1] directly.  The eigenvalues land
-// sorted: rank i = i.
+// sign-preserving).  Each lane runs one
+// sequence (P + 1 sections per pass), or two in groups of one or two lanes.
+// The points of a pass increase along the group's lanes and the counts are
+// monotone in x, so the points with count <= i form a prefix: its length k,
+// from ballots, gives the new interval [point k, point k + 1] directly.  The
+// eigenvalues land sorted: rank i = i.
 template <int W, typename R, int M, int G, bool HASU, bool HASV, bool NOF>
 __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, int n) {
   typedef typename Cx<R>::T C;
@@ -1152,9 +1152,14 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
   auto dr_at = [&](int j) -> C {
     if constexpr (M <= 16) return drr[j]; else return de[j];
   };
-  // point i (1..2P) of a pass: the same expression where it is evaluated and
-  // where it becomes an end of the new interval
-  const R inv = R(1) / R(2 * P + 1);
+  // SH sequences per lane, NPT = SH P points per pass: one sequence when the
+  // group has four or more lanes (the passes are issue-bound, and one point
+  // per lane costs fewer row evaluations to the bit), two for smaller groups,
+  // where the fixed cost of a pass dominates.  Point i (1..NPT): the same
+  // expression where it is evaluated and where it becomes an end of the new
+  // interval
+  constexpr int SH = P >= 4 ? 1 : 2, NPT = SH * P;
+  const R inv = R(1) / R(NPT + 1);
   auto point = [&](int i) { return fma(hi - lo, R(i) * inv, lo); };
   const int gbase = ((int)(threadIdx.x & 63) / P) * P;   // first lane of the group in its wavefront
   const unsigned long long gmask = P >= 64 ? ~0ull : ((1ull << P) - 1ull);
@@ -1165,7 +1170,7 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
   for (int it = 0; it < 96; ++it) {
     const bool conv = !live || hi - lo <= R(2) * eps * fmax(fabs(lo), fabs(hi)) + eps * tnorm + R(4) * tiny;
     if (__all(conv)) break;
-    const R xa = point(2 * gc + 1), xb = point(2 * gc + 2);
+    const R xa = point(SH * gc + 1), xb = SH == 2 ? point(SH * gc + 2) : xa;
     int ca = 0, cb = 0;
     if (live) {
       const C d0 = dr_at(0);
@@ -1179,14 +1184,16 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
         constexpr bool RS = decltype(rs)::value;
         const C dj = dr_at(j);
         sturm_row<SPLIT>(dj.x, dj.y, xa, pa1, pa2, na, ca);
-        sturm_row<SPLIT>(dj.x, dj.y, xb, pb1, pb2, nb, cb);
+        if constexpr (SH == 2) sturm_row<SPLIT>(dj.x, dj.y, xb, pb1, pb2, nb, cb);
         if constexpr (RS) {
           const R sa = fabs(pa1) > kBig ? kSmall : (fabs(pa1) < kSmall ? kBig : R(1));
-          const R sb = fabs(pb1) > kBig ? kSmall : (fabs(pb1) < kSmall ? kBig : R(1));
           pa1 *= sa;
           pa2 *= sa;
-          pb1 *= sb;
-          pb2 *= sb;
+          if constexpr (SH == 2) {
+            const R sb = fabs(pb1) > kBig ? kSmall : (fabs(pb1) < kSmall ? kBig : R(1));
+            pb1 *= sb;
+            pb2 *= sb;
+          }
         }
       };
       using RsYes = std::integral_constant<bool, true>;
@@ -1220,11 +1227,12 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
         for (int jb = 8; jb < M; jb += 8) block8(jb);
       }
     }
-    const unsigned long long ba = __ballot(ca <= gi), bb = __ballot(cb <= gi);
-    const int k = __popcll((ba >> gbase) & gmask) + __popcll((bb >> gbase) & gmask);
+    const unsigned long long ba = __ballot(ca <= gi);
+    int k = __popcll((ba >> gbase) & gmask);
+    if constexpr (SH == 2) k += __popcll((__ballot(cb <= gi) >> gbase) & gmask);
     if (!conv) {
       const R nlo = k == 0 ? lo : point(k);
-      const R nhi = k == 2 * P ? hi : point(k + 1);
+      const R nhi = k == NPT ? hi : point(k + 1);
       lo = nlo;
       hi = nhi;
     }

@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "lib", "liblhf.so")
+# LHF_LIB selects another build of the same library (the host tests run the
+# sanitizer build through it)
+LIB_PATH = os.environ.get("LHF_LIB") or os.path.join(HERE, "lib", "liblhf.so")
 
 LHF_OK, LHF_ERR_INVALID, LHF_ERR_UNSUPPORTED, LHF_ERR_WORKSPACE, LHF_ERR_HIP, LHF_ERR_ALLOC = 0, -1, -2, -3, -4, -5
 LHF_PREC_FP64, LHF_PREC_MIXED = 0, 1
