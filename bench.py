@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--mixed-tuning", default="",
                     help="with --probe-traffic or --probe-mfma: JSON object of tuning fields for the mixed plans")
     ap.add_argument("--probe-mfma", action="store_true",
-                    help="for MFMA counter runs: three eager mixed steps with each Gram arithmetic (FP64, FP32, "
+                    help="for MFMA counter runs: three eager mixed steps with each Gram arithmetic (FP64, FP32, FP16 hi+lo, "
                          "bf16 hi+lo); prints nothing else")
     return ap.parse_args()
 
@@ -197,7 +197,8 @@ def route_of(pipe, insts):
         return "; ".join(parts), "f64", f64
     f64 = set() if pipe.fp32_solve else {c for c in classes if (t.heev_fp64 >> c) & 1}
     gram = {lhf.LHF_GRAM_FP64: "FP64 MFMA Grams", lhf.LHF_GRAM_FP32: "FP32 MFMA Grams + FP64 Grams",
-            lhf.LHF_GRAM_BF16X3: "bf16 hi+lo split MFMA Grams (FP32 stacks) + FP64 Grams for refinement"}
+            lhf.LHF_GRAM_BF16X3: "bf16 hi+lo split MFMA Grams (FP32 stacks) + FP64 Grams for refinement",
+            lhf.LHF_GRAM_FP16X3: "FP16 hi+lo split MFMA Grams (FP32 stacks) + FP64 Grams for refinement"}
     parts = [gram[pipe.plan.gram] if pipe.refine_src in ("bar64", "band") else "FP64 MFMA Grams"]
     if pipe.refine_src == "direct":
         parts.append("complex128 Fourier blocks " + ("formed separably" if sep else "by block DFT"))
@@ -524,10 +525,11 @@ def probe_traffic(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
 
 def probe_mfma(args, torch, lhf, Pipeline, make_config, config_c4_lattices):
     """Kernels for an MFMA counter run: three eager mixed steps with each Gram
-    arithmetic (the assembly's MFMA kernels), with the tuning fields of
+    arithmetic (FP64, FP32, bf16 and FP16 hi+lo), with the tuning fields of
     --mixed-tuning (e.g. the Gram tile of a timed run)."""
     insts = config_c4_lattices() if args.config == "c4" else [make_config(args.config)]
-    for gram, src in ((lhf.LHF_GRAM_FP64, "dual"), (lhf.LHF_GRAM_FP32, "bar64"), (lhf.LHF_GRAM_BF16X3, "bar64")):
+    for gram, src in ((lhf.LHF_GRAM_FP64, "dual"), (lhf.LHF_GRAM_FP32, "bar64"), (lhf.LHF_GRAM_BF16X3, "bar64"),
+                      (lhf.LHF_GRAM_FP16X3, "bar64")):
         pipe = Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=gram, refine_src=src)
         apply_tuning(pipe, args.mixed_tuning)
         for _ in range(3):

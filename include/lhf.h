@@ -67,7 +67,9 @@ enum {
 enum {
   LHF_GRAM_FP64 = 0,   /* FP64 MFMA (also what the FP64 pipeline always uses)  */
   LHF_GRAM_FP32 = 1,   /* FP32 MFMA on FP32-rounded operands                   */
-  LHF_GRAM_BF16X3 = 2  /* bf16 hi+lo split, hi*hi + hi*lo + lo*hi, FP32 accum.  */
+  LHF_GRAM_BF16X3 = 2, /* bf16 hi+lo split, hi*hi + hi*lo + lo*hi, FP32 accum.  */
+  LHF_GRAM_FP16X3 = 3  /* FP16 hi+lo split as above, operand rows and columns
+                          scaled by powers of two per work item (22 bits)     */
 };
 
 /* Boundary conditions. */

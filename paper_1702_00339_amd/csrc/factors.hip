@@ -23,12 +23,23 @@ namespace {
 //  * item.row >= 0, item.chunk >= 0: FT nodes of the potential term item.row of
 //    a one-cell dimension, on the cell's own nodes;
 //  * item.chunk < 0: the lattice-window potential factor (eq. EwaldSumP) of
-//    term item.row of a replicated dimension.  Thread t sums the images
-//    k = klo + c, c = t / nc (mod FT / nc), for node t % nc of the central
-//    cell; the image partial sums are folded in two fixed-order levels, so
-//    the result is deterministic.
+//    term item.row of a replicated dimension, for the central cell's nodes
+//    j0 .. j0 + nn - 1 (node group g = -1 - item.chunk of size nn, so that
+//    every thread sums about one image).  Thread t sums the images
+//    k = klo + c, c = t / nn (mod FT / nn), for node j0 + t % nn; the image
+//    partial sums are folded in two fixed-order levels, so the result is
+//    deterministic.
 constexpr int FT = 1024;
 constexpr int kFold = 32;   // first-level fold width of the window partials
+
+// Nodes per group of a window item: groups enough that the FT threads of a
+// workgroup cover every (node, image) pair about once, at most one per node.
+// The item count is ceil(nc / nn), every group non-empty.
+__host__ __device__ inline int window_nodes(int nc, int L) {
+  int ng = (nc * L + FT - 1) / FT;
+  ng = ng < 1 ? 1 : (ng > nc ? nc : ng);
+  return (nc + ng - 1) / ng;
+}
 
 __global__ void __launch_bounds__(FT) factors_kernel(const LatDev* __restrict__ lats,
                                                      const FacItem* __restrict__ items, int nitems,
@@ -73,7 +84,8 @@ __global__ void __launch_bounds__(FT) factors_kernel(const LatDev* __restrict__ 
     const int r = item.row;
     const int nu = r / L.R, q = r % L.R;
     const double t = L.tq[q], A = L.nuc[nu][d];
-    const int nc = D.nc;
+    const int nn = window_nodes(D.nc, D.L), j0 = (-1 - item.chunk) * nn;
+    const int nc = min(nn, D.nc - j0);   // nodes of this group (>= 1)
     const int chunks = FT / nc;
     const int j = tid % nc, c = tid / nc;
     int klo, khi;
@@ -81,7 +93,7 @@ __global__ void __launch_bounds__(FT) factors_kernel(const LatDev* __restrict__ 
     else { klo = -D.L / 2; khi = D.L / 2; }
     double acc = 0.0;
     if (c < chunks) {
-      const double y = D.y0 + j * D.h;
+      const double y = D.y0 + (j0 + j) * D.h;
       for (int k = klo + c; k <= khi; k += chunks) {
         const double wk = ((D.L & 1) == 0 && (k == klo || k == khi)) ? 0.5 : 1.0;
         acc += wk * cell_gauss(y, D.h, t, A + k * D.a);
@@ -101,7 +113,7 @@ __global__ void __launch_bounds__(FT) factors_kernel(const LatDev* __restrict__ 
       double v = 0.0;
       for (int g = 0; g < G1; ++g) v += part2[g * nc + tid];
       if (d == 0) v *= L.Z[nu] * L.wq[q];
-      fac[D.p_off + (int64_t)r * D.npot + tid] = v;
+      fac[D.p_off + (int64_t)r * D.npot + j0 + tid] = v;
     }
     __syncthreads();   // part[] and part2[] are reused by the next item
   }
@@ -115,8 +127,11 @@ void plan_factors(const std::vector<LatDev>& lats, std::vector<FacItem>& items) 
     const LatDev& L = lats[li];
     // window items first: they are the long ones
     for (int d = 0; d < 3; ++d)
-      if (L.dim[d].replicate)
-        for (int r = 0; r < L.M0 * L.R; ++r) items.push_back(FacItem{li, d, r, -1});
+      if (L.dim[d].replicate) {
+        const int nn = window_nodes(L.dim[d].nc, L.dim[d].L), ng = (L.dim[d].nc + nn - 1) / nn;
+        for (int r = 0; r < L.M0 * L.R; ++r)
+          for (int g = 0; g < ng; ++g) items.push_back(FacItem{li, d, r, -1 - g});
+      }
     for (int d = 0; d < 3; ++d) {
       const DimDev& D = L.dim[d];
       const int per = FT / L.m0;   // nodes per basis chunk

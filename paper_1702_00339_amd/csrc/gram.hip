@@ -19,8 +19,13 @@
 // grouped reduction that also scatters to the Gram layout [t][s][mu][nu].
 //
 // Arithmetic: FP64 (v_mfma_f64_16x16x4f64), FP32 operands
-// (v_mfma_f32_16x16x4f32), or bf16 hi+lo split products hi*hi + hi*lo + lo*hi
-// (v_mfma_f32_16x16x32_bf16), the last two with FP32 accumulation.
+// (v_mfma_f32_16x16x4f32), or hi+lo split products hi*hi + hi*lo + lo*hi in
+// bf16 (v_mfma_f32_16x16x32_bf16) or FP16 (v_mfma_f32_16x16x32_f16), the last
+// three with FP32 accumulation.  FP16 has five exponent bits, so each work
+// item first scales every operand row and column by a power of two that puts
+// its largest value over the item's nodes in [2^13, 2^14); the FP16 hi and lo
+// then carry 22 bits of each value, and the scales come off exactly when the
+// item's partial tile is written.
 #include <algorithm>
 #include <type_traits>
 
@@ -32,6 +37,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
 constexpr int KC = 32;   // window nodes per LDS chunk
 
@@ -55,6 +61,7 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
   // in flight while the MFMAs of chunk c run
   __shared__ double As[KC][TL + 1];
   __shared__ double Bs[KC][TL + 1];
+  __shared__ int scA[MODE == 3 ? TL : 1], scB[MODE == 3 ? TL : 1];   // FP16 scale exponents
   typedef typename std::conditional<MODE == 0, d4, f4>::type Acc;
   constexpr int NQ = 256 / TL;      // node groups of the staging threads
   constexpr int NV = KC / NQ;       // nodes staged per thread and chunk
@@ -126,6 +133,43 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
         Bs[kk][col] = y[v];
       }
     };
+    auto aval = [&](int v) {
+      return t >= 2 ? x1[v] * x0[v] : t == 0 ? h6 * (x1[v] + 4.0 * x0[v] + x2[v]) : hinv * (2.0 * x0[v] - x1[v] - x2[v]);
+    };
+    double fa[NA], fb[NA];   // FP16: this lane's row and column scales
+    if constexpr (MODE == 3) {
+      // largest |value| of every A row and B column over the item's nodes
+      double ma = 0.0, mb = 0.0;
+      for (int kc0 = k_beg; kc0 < k_end; kc0 += KC) {
+        load_chunk(kc0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          ma = fmax(ma, fabs(aval(v)));
+          mb = fmax(mb, fabs(y[v]));
+        }
+      }
+      As[kq][col] = ma;
+      Bs[kq][col] = mb;
+      __syncthreads();
+      if (tid < TL) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < NQ; ++q) {
+          a = fmax(a, As[q][tid]);
+          b = fmax(b, Bs[q][tid]);
+        }
+        int ea = 0, eb = 0;
+        (void)frexp(a, &ea);
+        (void)frexp(b, &eb);
+        scA[tid] = a > 0.0 ? 14 - ea : 0;
+        scB[tid] = b > 0.0 ? 14 - eb : 0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        fa[a] = ldexp(1.0, scA[wr + a * 16 + lr]);
+        fb[a] = ldexp(1.0, scB[wc + a * 16 + lr]);
+      }
+    }
     if (k_beg < k_end) {
       load_chunk(k_beg);
       store_chunk();
@@ -134,7 +178,34 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
     for (int kc0 = k_beg; kc0 < k_end; kc0 += KC) {
       const bool more = kc0 + KC < k_end;
       if (more) load_chunk(kc0 + KC);
-      if constexpr (MODE == 2) {
+      if constexpr (MODE == 3) {
+        h8 ah[NA], al[NA], bh[NA], bl[NA];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            const float x = (float)(As[8 * lk + e][wr + a * 16 + lr] * fa[a]);
+            const _Float16 hi = (_Float16)x;
+            ah[a][e] = hi;
+            al[a][e] = (_Float16)(x - (float)hi);
+          }
+#pragma unroll
+          for (int b = 0; b < NA; ++b) {
+            const float x = (float)(Bs[8 * lk + e][wc + b * 16 + lr] * fb[b]);
+            const _Float16 hi = (_Float16)x;
+            bh[b][e] = hi;
+            bl[b][e] = (_Float16)(x - (float)hi);
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int b = 0; b < NA; ++b) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          }
+      } else if constexpr (MODE == 2) {
         bf8 ah[NA], al[NA], bh[NA], bl[NA];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
@@ -193,8 +264,13 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
         const int c = col0 + wc + b * 16 + lr;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = row0 + wr + a * 16 + (MODE == 0 ? lk + 4 * v : 4 * lk + v);
-          if (r < M && c < N) out[(int64_t)r * N + c] = (T)acc[a][b][v];
+          const int rl = wr + a * 16 + (MODE == 0 ? lk + 4 * v : 4 * lk + v), r = row0 + rl;
+          if (r < M && c < N) {
+            if constexpr (MODE == 3)
+              out[(int64_t)r * N + c] = ldexpf(acc[a][b][v], -(scA[rl] + scB[wc + b * 16 + lr]));
+            else
+              out[(int64_t)r * N + c] = (T)acc[a][b][v];
+          }
         }
       }
   }
@@ -276,9 +352,12 @@ hipError_t launch_grams(const lhf_plan_s* p, int mode, const double* fac, void* 
   } else if (mode == LHF_GRAM_FP32) {
     if (t32) hipLaunchKernelGGL((gram_kernel<1, 32>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
     else hipLaunchKernelGGL((gram_kernel<1, 64>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
-  } else {
+  } else if (mode == LHF_GRAM_BF16X3) {
     if (t32) hipLaunchKernelGGL((gram_kernel<2, 32>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
     else hipLaunchKernelGGL((gram_kernel<2, 64>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+  } else {
+    if (t32) hipLaunchKernelGGL((gram_kernel<3, 32>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
+    else hipLaunchKernelGGL((gram_kernel<3, 64>), dim3(grid), dim3(256), 0, s, p->d_lat, p->d_gram_items, p->n_gram_items, fac, part);
   }
   int64_t maxmn = 0;
   for (const LatDev& L : p->lat)

@@ -238,7 +238,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   *out = nullptr;
   if (!lats || nlat < 1) { set_error("need at least one lattice"); return LHF_ERR_INVALID; }
   if (prec != LHF_PREC_FP64 && prec != LHF_PREC_MIXED) { set_error("bad precision"); return LHF_ERR_INVALID; }
-  if (gram < LHF_GRAM_FP64 || gram > LHF_GRAM_BF16X3) { set_error("bad gram mode"); return LHF_ERR_INVALID; }
+  if (gram < LHF_GRAM_FP64 || gram > LHF_GRAM_FP16X3) { set_error("bad gram mode"); return LHF_ERR_INVALID; }
   auto* p = new (std::nothrow) lhf_plan_s();
   if (!p) { set_error("out of host memory"); return LHF_ERR_ALLOC; }
   p->prec = prec; p->gram = gram; p->nlat = nlat;

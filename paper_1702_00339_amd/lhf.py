@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("LHF_LIB") or os.path.join(HERE, "lib", "liblhf.so")
 
 LHF_OK, LHF_ERR_INVALID, LHF_ERR_UNSUPPORTED, LHF_ERR_WORKSPACE, LHF_ERR_HIP, LHF_ERR_ALLOC = 0, -1, -2, -3, -4, -5
 LHF_PREC_FP64, LHF_PREC_MIXED = 0, 1
-LHF_GRAM_FP64, LHF_GRAM_FP32, LHF_GRAM_BF16X3 = 0, 1, 2
+LHF_GRAM_FP64, LHF_GRAM_FP32, LHF_GRAM_BF16X3, LHF_GRAM_FP16X3 = 0, 1, 2, 3
 LHF_BC_PERIODIC, LHF_BC_DIRICHLET = 0, 1
 LHF_HEEV_VECTORS, LHF_HEEV_REFINE_FP64, LHF_HEEV_FP32_SOLVE = 1, 2, 4
 

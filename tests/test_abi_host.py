@@ -101,6 +101,8 @@ def test_bad_precision_and_null_output(lib):
     h = C.c_void_p()
     assert lib.lhf_plan_create(arr, 1, 5, 0, C.byref(h)) == lhf.LHF_ERR_INVALID
     assert lib.lhf_plan_create(arr, 1, 0, 9, C.byref(h)) == lhf.LHF_ERR_INVALID
+    assert lib.lhf_plan_create(arr, 1, 1, lhf.LHF_GRAM_FP16X3 + 1, C.byref(h)) == lhf.LHF_ERR_INVALID
+    assert lib.lhf_plan_create(arr, 1, 1, -1, C.byref(h)) == lhf.LHF_ERR_INVALID
     assert lib.lhf_plan_create(arr, 0, 0, 0, C.byref(h)) == lhf.LHF_ERR_INVALID
     assert lib.lhf_plan_create(arr, 1, 0, 0, None) == lhf.LHF_ERR_INVALID
 

@@ -155,8 +155,8 @@ def test_set_tuning_extremes_keep_parity():
         torch.cuda.synchronize()
         for w, ref in zip(pipe.eigenvalues(), refs):
             assert (np.abs(w - ref) <= 1e-10 * np.maximum(np.abs(ref), 1.0)).all()
-    # the 32 tile in the FP32 and bf16 hi+lo Gram modes of mixed plans
-    for gram in (lhf.LHF_GRAM_FP32, lhf.LHF_GRAM_BF16X3):
+    # the 32 tile in the FP32, bf16 and FP16 hi+lo Gram modes of mixed plans
+    for gram in (lhf.LHF_GRAM_FP32, lhf.LHF_GRAM_BF16X3, lhf.LHF_GRAM_FP16X3):
         mix = Pipeline(insts, prec=lhf.LHF_PREC_MIXED, gram=gram, refine_src="band")
         t = mix.plan.lhf_plan_get_tuning()
         t.gram_tile = 32
