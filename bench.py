@@ -167,11 +167,15 @@ def dft_bytes(pipe, insts, cbytes):
     return total
 
 
+def is_chain(inst):
+    return inst.L[1] == 1 and inst.L[2] == 1
+
+
 def sep_bytes(pipe, insts):
     """Algorithmic HBM bytes of one lhf_fourier_blocks call: every Fourier
     block written once (H and S, complex128), every FP64 1D Gram read once,
-    and the 1D-transformed Grams of dimensions 2 and 3 (complex128) written
-    once and read once."""
+    and for lattices other than chains the 1D-transformed Grams of dimensions
+    2 and 3 (complex128) written once and read once."""
     total = 0
     for i, inst in enumerate(insts):
         m2 = inst.m0 * inst.m0
@@ -179,8 +183,19 @@ def sep_bytes(pipe, insts):
         nshift, _, _ = pipe.plan.lhf_plan_band(i)
         total += 2 * inst.ncells * m2 * 16
         total += sum(T * nshift[d] * m2 * 8 for d in range(3))
-        total += 2 * sum(T * inst.L[d] * m2 * 16 for d in (1, 2))
+        if not is_chain(inst):
+            total += 2 * sum(T * inst.L[d] * m2 * 16 for d in (1, 2))
     return total
+
+
+def sep_kernels(insts):
+    """The kernels of the separable route for these lattices."""
+    names = []
+    if any(is_chain(i) for i in insts):
+        names.append("sep_chain")
+    if not all(is_chain(i) for i in insts):
+        names.append("gram_dft + sep_fused")
+    return ", ".join(names)
 
 
 def route_of(pipe, insts):
@@ -338,7 +353,7 @@ def leg(cfg, args, torch, np, lhf, Pipeline, headline):
                      "kernel_flops_per_launch": flops_kernel,
                      "kernel_tflops": flops_kernel / (ms_heev * 1e-3) / 1e12, "avg_launch_ms": ms_heev},
         "roofline_fourier": {"bound": "hbm",
-                             "kernel": ("separable Fourier blocks (lhf_fourier_blocks: gram_dft + sep_fused, FP64 "
+                             "kernel": (f"separable Fourier blocks (lhf_fourier_blocks: {sep_kernels(insts)}, FP64 "
                                         "Grams to complex128)" if sep else
                                         "block DFT (lhf_block_fft, FP64 stacks to complex128)"),
                              "achieved": fourier_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
