@@ -49,15 +49,16 @@ Ws ws_view(const lhf_plan_s* p, void* base) {
 }
 
 // Split-K of the Gram contraction of dimension d over 64 x 64 workgroup
-// tiles: at least 64 window nodes per split, about `target` workgroups per
-// (lattice, dimension).  The split count is monotone in `target`, so a plan
-// sized with kGramSplitMax has room for every smaller target.
+// tiles: at least one 32-node chunk of the window per split, about `target`
+// workgroups per (lattice, dimension).  The split count is monotone in
+// `target`, so a plan sized with kGramSplitMax has room for every smaller
+// target.
 void set_gram_split(LatDev& L, int d, int target) {
   DimDev& D = L.dim[d];
   const int M = L.T * L.m0, N = D.nshift * L.m0;
   const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
   int ks = (int)std::max<int64_t>(1, (target + tiles - 1) / tiles);
-  ks = std::min(ks, std::max(1, D.kwin / 64));
+  ks = std::min(ks, std::max(1, (D.kwin + 31) / 32));
   const int kchunk = ((D.kwin + ks - 1) / ks + 31) / 32 * 32;
   D.kchunk = kchunk;
   D.ksplit = (D.kwin + kchunk - 1) / kchunk;
