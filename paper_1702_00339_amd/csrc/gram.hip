@@ -160,8 +160,11 @@ __global__ void __launch_bounds__(256) gram_kernel(const LatDev* __restrict__ la
         int ea = 0, eb = 0;
         (void)frexp(a, &ea);
         (void)frexp(b, &eb);
-        scA[tid] = a > 0.0 ? 14 - ea : 0;
-        scB[tid] = b > 0.0 ? 14 - eb : 0;
+        // capped so that 2^sc stays finite: a row or column whose largest
+        // value is below 2^-886 (a far tail of a Gaussian in this item's
+        // nodes) then underflows to zero in FP16, below any FP32 output
+        scA[tid] = a > 0.0 ? min(14 - ea, 900) : 0;
+        scB[tid] = b > 0.0 ? min(14 - eb, 900) : 0;
       }
       __syncthreads();
 #pragma unroll
