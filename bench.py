@@ -55,7 +55,20 @@ HEEV_FLOPS_PER_M3 = 150.0                    # algorithmic eigensolve work per b
 # --probe-traffic` (profiles/traffic_per_dispatch.md).  Each entry names the source files of its kernels
 # and their SHA-1 (first 16 hex digits) when counted, and the route it was counted on; an entry whose
 # sources have changed since, or whose route is not the one timed, is reported as null.
-TRAFFIC_KIB = {}
+TRAFFIC_KIB = {
+    "c2": {
+        "eigensolve": {"kib": 1229.6, "route": "fp64=4,wide=4", "src": ["heev.hip", "sturm.h"], "sha": "b9495542673ada50"},
+        "fourier": {"kib": 4127.2, "route": "sep", "src": ["blockdft.hip"], "sha": "47aefc9e22736b74"},
+    },
+    "c3": {
+        "eigensolve": {"kib": 35990.6, "route": "fp64=2,wide=0", "src": ["heev.hip", "sturm.h"], "sha": "b9495542673ada50"},
+        "fourier": {"kib": 71329.6, "route": "sep", "src": ["blockdft.hip"], "sha": "47aefc9e22736b74"},
+    },
+    "c4": {
+        "eigensolve": {"kib": 606643.2, "route": "fp64=15,wide=1", "src": ["heev.hip", "sturm.h"], "sha": "b9495542673ada50"},
+        "fourier": {"kib": 1466177.5, "route": "sep", "src": ["blockdft.hip"], "sha": "47aefc9e22736b74"},
+    },
+}
 
 
 def parse():
