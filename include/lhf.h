@@ -449,6 +449,21 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t tp, int32_t nev, int32_t maxit, double 
                           double* d_w, double* d_V, int32_t* iters, double* resid, void* d_ws,
                           size_t ws_bytes, lhf_stream_t stream);
 int32_t lhf_toeplitz_destroy(lhf_toeplitz_t tp);
+/* The k lowest eigenpairs of a dense real symmetric m x m matrix, the
+ * Rayleigh-Ritz problem of the block LOBPCG of lhf_toeplitz_eigs: Householder
+ * tridiagonalisation, bisection on Sturm counts for the k lowest eigenvalues,
+ * inverse iteration on the tridiagonal matrix (vectors of eigenvalues closer
+ * than 1e-8 of the matrix norm orthogonalised against each other; others
+ * orthogonal to about 1e-16 norm / gap), and the back-transform, in one
+ * workgroup.  d_A: device FP64 row-major, lda >= m, read as (A + A^T) / 2;
+ * d_w: device FP64 [k] ascending; d_V: device FP64 row-major m x k with
+ * ldv >= k (column i the unit eigenvector of w[i]); d_A may not overlap d_w
+ * or d_V.  Every intermediate (the reflectors included) stays in the
+ * workgroup's LDS: no workspace.  Asynchronous on `stream`; allocates nothing.
+ * Errors: LHF_ERR_INVALID (1 <= k <= m <= 112, lda, ldv, NULL pointers),
+ * LHF_ERR_HIP. */
+int32_t lhf_dense_syev(int32_t m, int32_t k, const double* d_A, int32_t lda, double* d_w, double* d_V, int32_t ldv,
+                       lhf_stream_t stream);
 
 /* ---------------------------------------------------------------- whole step
  * The buffers of one step of the plan: assembly, block DFT and eigensolve.

@@ -31,7 +31,7 @@ FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
          "-Wno-unused-command-line-argument"]
 
 SOURCES = ["plan.cpp", "api.cpp", "step.cpp", "factors.hip", "gram.hip", "combine.hip", "blockdft.hip",
-           "heev.hip", "toeplitz.hip", "toeplitz.cpp", "lobpcg.hip", "noalloc.hip", "eigvec.hip", "toeplitz3.hip"]
+           "heev.hip", "toeplitz.hip", "toeplitz.cpp", "lobpcg.hip", "noalloc.hip", "eigvec.hip", "toeplitz3.hip", "rrsyev.hip"]
 
 
 def _compile(src: str) -> str:

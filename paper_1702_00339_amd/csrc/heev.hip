@@ -37,6 +37,7 @@
 
 #include "plan.h"
 #include "sturm.h"
+#include "dpp.h"
 
 namespace lhf {
 namespace {
@@ -672,47 +673,6 @@ __device__ void eig_rank(Smem<R, M, G, HASU, HASV>& sh, int g, int t, int m, int
     sh.rank[g][t] = k;
   }
   __syncthreads();
-}
-
-// FP64 lane moves within a 16-lane row (DPP control CTRL) and an all-reduce
-// over aligned groups of P lanes (P a power of two <= 64): quad permutes pair
-// i with i^1 and i^2, then the mirrors i <-> 7-i and i <-> 15-i join two
-// halves that are already reduced; lane shuffles only across rows.
-// Every source lane of these patterns lies in the destination's own group
-// and is active whenever the group is, so the moves keep no old value.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
-  return __hiloint2double(hi, lo);
-}
-template <int P, typename F>
-__device__ __forceinline__ double lane_reduce(double v, F op) {
-  if constexpr (P >= 2) v = op(v, dpp_move<0xB1>(v));    // quad_perm [1, 0, 3, 2]
-  if constexpr (P >= 4) v = op(v, dpp_move<0x4E>(v));    // quad_perm [2, 3, 0, 1]
-  if constexpr (P >= 8) v = op(v, dpp_move<0x141>(v));   // row_half_mirror
-  if constexpr (P >= 16) v = op(v, dpp_move<0x140>(v));  // row_mirror
-  if constexpr (P >= 32) v = op(v, __shfl_xor(v, 16, 64));
-  if constexpr (P >= 64) v = op(v, __shfl_xor(v, 32, 64));
-  return v;
-}
-// Two independent all-reduces, level by level, so their latencies overlap.
-template <int P, typename F>
-__device__ __forceinline__ void lane_reduce2(double& a, double& b, F op) {
-  if constexpr (P >= 2) { const double x = dpp_move<0xB1>(a), y = dpp_move<0xB1>(b); a = op(a, x); b = op(b, y); }
-  if constexpr (P >= 4) { const double x = dpp_move<0x4E>(a), y = dpp_move<0x4E>(b); a = op(a, x); b = op(b, y); }
-  if constexpr (P >= 8) { const double x = dpp_move<0x141>(a), y = dpp_move<0x141>(b); a = op(a, x); b = op(b, y); }
-  if constexpr (P >= 16) { const double x = dpp_move<0x140>(a), y = dpp_move<0x140>(b); a = op(a, x); b = op(b, y); }
-  if constexpr (P >= 32) {
-    const double x = __shfl_xor(a, 16, 64), y = __shfl_xor(b, 16, 64);
-    a = op(a, x);
-    b = op(b, y);
-  }
-  if constexpr (P >= 64) {
-    const double x = __shfl_xor(a, 32, 64), y = __shfl_xor(b, 32, 64);
-    a = op(a, x);
-    b = op(b, y);
-  }
 }
 
 // (re, im) = W Y with the unit lower triangular W held in the strictly upper

@@ -1,6 +1,6 @@
 // Dense FP64 kernels of the block LOBPCG driver: Gram products of tall
-// blocks, block combinations, residuals, Cholesky-QR orthonormalisation and a one-workgroup
-// symmetric eigensolver for the Rayleigh-Ritz problems (size <= 112).
+// blocks, block combinations, residuals and Cholesky-QR orthonormalisation
+// (the Rayleigh-Ritz eigensolver is in rrsyev.hip).
 //
 // Blocks of vectors are row-major [N][ld] (column j = vector j).  Reductions
 // over N are split into fixed chunks whose partial results are added in chunk
@@ -357,287 +357,6 @@ __global__ void __launch_bounds__(256) symmetrize_kernel(int m, double* __restri
   }
 }
 
-// Real symmetric eigensolver: cyclic Jacobi in the parallel round-robin
-// order (size padded to even Me with a decoupled zero index).
-//
-// The matrix lives in the LDS of one workgroup in "slot space": the Me
-// indices occupy Me storage slots, and the pairs of every round are the
-// same slot pairs, (0, 1) and (1 + i, Me - i) for i = 1 .. Me/2 - 1.  After
-// each round the contents of slots 2 .. Me-1 move down one slot, slot 1
-// moves to slot Me-1 and slot 0 stays (the circle method of the round-robin
-// tournament), so after the Me - 1 rounds of a sweep every slot holds its
-// own index again.  Storage follows the pairs: the diagonal 2 x 2 block of
-// pair i as three arrays (first-first, second-second, first-second), and the
-// blocks of pairs bi < bj as four arrays (entry first/second of bi times
-// first/second of bj) indexed by the block's rank in the strict upper
-// triangle.  A thread owns fixed blocks and reads and writes fixed
-// addresses every round: consecutive threads own consecutive blocks of a
-// block row, so loads and stores are contiguous, and the loop has no index
-// arithmetic.  A round is two phases: the first wave computes the rotations
-// of the pairs from their diagonal blocks while the other threads load
-// their blocks; after a barrier the rotated blocks are written to the
-// shifted slots.  Stops at a sweep boundary once the off-diagonal Frobenius
-// norm is below 4 Me eps of the norm of A.
-//
-// Eigenvectors: the rotations of every round are recorded in global memory,
-// and a second kernel replays them on the rows of V = I, one wavefront per
-// row (the rows are independent): lane i holds the row's entries in the
-// two slots of pair i and the slot shift is a one-lane DPP move.  Output:
-// eigenvalues ascending in w, eigenvector j in column j of Vout.
-__device__ __forceinline__ int slot_first(int i) { return i == 0 ? 0 : 1 + i; }
-__device__ __forceinline__ int slot_second(int i, int Me) { return i == 0 ? 1 : Me - i; }
-__device__ __forceinline__ int slot_shift(int x, int Me) { return x == 0 ? 0 : (x == 1 ? Me - 1 : x - 1); }
-// pair holding slot x; first = whether x is the pair's first slot
-__device__ __forceinline__ int slot_pair(int x, int Me, bool& first) {
-  if (x <= 1) {
-    first = x == 0;
-    return 0;
-  }
-  first = x <= Me / 2;
-  return first ? x - 1 : Me - x;
-}
-// rank of the block of pairs bi < bj in the strict upper triangle (row-major)
-__device__ __forceinline__ int offblk(int bi, int bj, int H) { return bi * H - (bi * (bi + 1)) / 2 + (bj - bi - 1); }
-// storage offset of the entry of slots (x, y) (symmetric)
-__device__ __forceinline__ int jstore(int x, int y, int Me) {
-  const int H = Me / 2, nob = H * (H - 1) / 2;
-  bool fx, fy;
-  int px = slot_pair(x, Me, fx), py = slot_pair(y, Me, fy);
-  if (px == py) return x == y ? (fx ? px : H + px) : 2 * H + px;
-  if (px > py) {
-    const int t = px; px = py; py = t;
-    const bool u = fx; fx = fy; fy = u;
-  }
-  return 3 * H + ((fx ? 0 : 2) + (fy ? 0 : 1)) * nob + offblk(px, py, H);
-}
-
-// Rotation annihilating b = A(p, q): with d = aqq - app, r = sqrt(d^2 + 4 b^2)
-// and u = |d| + r, the classical t = sign(d) 2|b| / u gives c = u rho and
-// s = sign(d) 2 b rho with rho = (2 r u)^-1/2, and t |b| = 2 b^2 / u =
-// 4 b^2 r rho^2 (no division; no cancellation for small or large angles).
-// dp, dq: the rotated diagonal entries.
-__device__ __forceinline__ void jacobi_rot(double app, double aqq, double b, double& c, double& s, double& dp,
-                                           double& dq) {
-  c = 1.0;
-  s = 0.0;
-  dp = app;
-  dq = aqq;
-  if (b != 0.0) {
-    const double d = aqq - app, sd = d >= 0.0 ? 1.0 : -1.0;
-    const double r = sqrt(d * d + 4.0 * b * b), u = fabs(d) + r, rho = rsqrt(2.0 * r * u);
-    c = u * rho;
-    s = sd * 2.0 * b * rho;
-    const double del = 4.0 * b * b * r * rho * rho;
-    dp = app - sd * del;
-    dq = aqq + sd * del;
-  }
-}
-
-constexpr int kSyevThreads = 1024;
-
-__global__ void __launch_bounds__(kSyevThreads) syev_kernel(int m, const double* __restrict__ Ain, int lda,
-                                                            double* __restrict__ w, double2* __restrict__ rec,
-                                                            int* __restrict__ hdr) {
-  extern __shared__ double lds[];
-  __shared__ double rc[kMaxSmall / 2], rs[kMaxSmall / 2];   // this round's rotations
-  __shared__ double red[kSyevThreads / 64];
-  __shared__ int rank[kMaxSmall];
-  __shared__ int done;
-  const int Me = m + (m & 1), H = Me / 2, Mc = Me - 1, nob = H * (H - 1) / 2;
-  double* A = lds;   // pair-block storage over slots, Me (Me + 1) / 2
-  const int tid = threadIdx.x;
-  for (int e = tid; e < Me * Me; e += kSyevThreads) {
-    const int r = e / Me, c = e % Me;
-    if (r <= c) A[jstore(r, c, Me)] = (r < m && c < m) ? 0.5 * (Ain[r * lda + c] + Ain[c * lda + r]) : 0.0;
-  }
-  __syncthreads();
-  auto block_sum = [&](double v) -> double {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int q = 0; q < kSyevThreads / 64; ++q) s += red[q];
-    __syncthreads();
-    return s;
-  };
-  // the pair this thread rotates (first wave) and its diagonal block's
-  // shifted write addresses (first-first, second-second, first-second)
-  const bool rotor = tid < H;
-  int dw[3] = {0, 0, 0};
-  if (rotor) {
-    const int f = slot_shift(slot_first(tid), Me), sc = slot_shift(slot_second(tid, Me), Me);
-    dw[0] = jstore(f, f, Me);
-    dw[1] = jstore(sc, sc, Me);
-    dw[2] = jstore(f, sc, Me);
-  }
-  // this thread's off-diagonal blocks (bi < bj, fixed): entry q = first/second
-  // of bi (q >> 1) times first/second of bj (q & 1) at 3H + q nob + rank,
-  // written to the storage of the shifted slots
-  constexpr int kMaxBlk = (kMaxSmall / 2) * (kMaxSmall / 2 - 1) / 2 / kSyevThreads + 1;
-  int bpi[kMaxBlk], bpj[kMaxBlk], rda[kMaxBlk], wra[kMaxBlk][4];
-#pragma unroll
-  for (int k = 0; k < kMaxBlk; ++k) {
-    const int ob = tid + k * kSyevThreads;
-    bpi[k] = -1;
-    bpj[k] = -1;
-    rda[k] = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) wra[k][q] = 0;
-    if (ob < nob) {
-      const double hb = H - 0.5;
-      int bi = (int)(hb - sqrt(hb * hb - 2.0 * ob));
-      if (bi < 0) bi = 0;
-      while (bi > 0 && offblk(bi, bi + 1, H) > ob) --bi;
-      while (bi + 1 < H && offblk(bi + 1, bi + 2, H) <= ob) ++bi;
-      const int bj = ob - offblk(bi, bi + 1, H) + bi + 1;
-      bpi[k] = bi;
-      bpj[k] = bj;
-      rda[k] = 3 * H + ob;
-      const int xs[2] = {slot_shift(slot_first(bi), Me), slot_shift(slot_second(bi, Me), Me)};
-      const int ys[2] = {slot_shift(slot_first(bj), Me), slot_shift(slot_second(bj, Me), Me)};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) wra[k][q] = jstore(xs[q >> 1], ys[q & 1], Me);
-    }
-  }
-  // squared norms over this thread's blocks: diagonal once, off-diagonal twice
-  auto block_norms = [&](double& dg, double& od) {
-    dg = 0.0;
-    od = 0.0;
-    if (rotor) {
-      const double a0 = A[tid], a1 = A[H + tid], a2 = A[2 * H + tid];
-      dg = a0 * a0 + a1 * a1;
-      od = 2.0 * a2 * a2;
-    }
-#pragma unroll
-    for (int k = 0; k < kMaxBlk; ++k) {
-      if (bpi[k] < 0) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) od += 2.0 * A[rda[k] + q * nob] * A[rda[k] + q * nob];
-    }
-  };
-  double dg0, od0;
-  block_norms(dg0, od0);
-  const double nrm2 = block_sum(dg0 + od0);
-  const double tol = 4.0 * Me * 1.1102230246251565e-16;
-  int sw = 0;
-  for (; sw < kSyevMaxSweeps; ++sw) {
-    double dg, od;
-    block_norms(dg, od);
-    const double off = block_sum(od);
-    if (tid == 0) done = off <= tol * tol * nrm2;
-    __syncthreads();
-    if (done) break;
-    for (int s = 0; s < Mc; ++s) {
-      // rotations of this round's pairs; blocks into registers
-      double dp = 0.0, dq = 0.0;
-      if (rotor) {
-        double c, sv;
-        jacobi_rot(A[tid], A[H + tid], A[2 * H + tid], c, sv, dp, dq);
-        rc[tid] = c;
-        rs[tid] = sv;
-        if (rec) rec[(sw * Mc + s) * H + tid] = make_double2(c, sv);
-      }
-      double a[kMaxBlk][4];
-#pragma unroll
-      for (int k = 0; k < kMaxBlk; ++k) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[k][q] = A[rda[k] + q * nob];   // in range for unused blocks too (rda 0)
-      }
-      __syncthreads();
-      // A <- J^T A J, written to the shifted slots
-      if (rotor) {
-        A[dw[0]] = dp;
-        A[dw[1]] = dq;
-        A[dw[2]] = 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < kMaxBlk; ++k) {
-        const int bi = bpi[k], bj = bpj[k];
-        if (bi < 0) continue;
-        const double ci = rc[bi], si = rs[bi], cj = rc[bj], sj = rs[bj];
-        const double t00 = a[k][0] * cj - a[k][1] * sj, t01 = a[k][0] * sj + a[k][1] * cj;
-        const double t10 = a[k][2] * cj - a[k][3] * sj, t11 = a[k][2] * sj + a[k][3] * cj;
-        A[wra[k][0]] = ci * t00 - si * t10;
-        A[wra[k][1]] = ci * t01 - si * t11;
-        A[wra[k][2]] = si * t00 + ci * t10;
-        A[wra[k][3]] = si * t01 + ci * t11;
-      }
-      __syncthreads();
-    }
-  }
-  // ascending ranks among the m real indices (ties by index); slot = index here
-  for (int i = tid; i < m; i += kSyevThreads) {
-    const double li = A[jstore(i, i, Me)];
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      const double lj = A[jstore(j, j, Me)];
-      k += (lj < li || (lj == li && j < i)) ? 1 : 0;
-    }
-    rank[i] = k;
-  }
-  __syncthreads();
-  for (int i = tid; i < m; i += kSyevThreads) {
-    w[rank[i]] = A[jstore(i, i, Me)];
-    if (hdr) hdr[1 + i] = rank[i];
-  }
-  if (hdr && tid == 0) hdr[0] = sw * Mc;   // rounds recorded (whole sweeps)
-}
-
-constexpr int kReplayBatch = 8;   // recorded rounds loaded ahead
-
-// Wavefront-wide one-lane shifts of a double (DPP wave_shl:1 / wave_shr:1 on
-// both halves): lane i receives lane i + 1's value, resp. lane i - 1's; the
-// lane without a source receives 0.
-__device__ __forceinline__ double from_next_lane(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double from_prev_lane(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
-// V = I J_1 J_2 ... (the recorded rotations), row r of V per workgroup of one
-// wavefront; lane i holds the row's entries in the slots of pair i (first
-// slot in F, second in S).  The shift after each round: F takes lane i+1's
-// F (lane 0 keeps slot 0, lane H-1 takes its own S), S takes lane i-1's S
-// (lane 0 takes lane 1's F).  Entry (r, c) is written to column perm[c].
-__global__ void __launch_bounds__(64) syev_vectors_kernel(int m, const double2* __restrict__ rec,
-                                                          const int* __restrict__ hdr, double* __restrict__ Vout,
-                                                          int ldv) {
-  const int r = blockIdx.x, i = threadIdx.x;
-  const int Me = m + (m & 1), H = Me / 2, R = hdr[0];
-  const int f = slot_first(i), sc = slot_second(i, Me);
-  const bool act = i < H;
-  double F = (act && f == r) ? 1.0 : 0.0, S = (act && sc == r) ? 1.0 : 0.0;
-  double2 cur[kReplayBatch], nxt[kReplayBatch];
-  auto load = [&](int k0, double2* b) {
-#pragma unroll
-    for (int j = 0; j < kReplayBatch; ++j) b[j] = (act && k0 + j < R) ? rec[(k0 + j) * H + i] : make_double2(1.0, 0.0);
-  };
-  load(0, cur);
-  for (int k0 = 0; k0 < R; k0 += kReplayBatch) {
-    load(k0 + kReplayBatch, nxt);
-#pragma unroll
-    for (int j = 0; j < kReplayBatch; ++j) {
-      if (k0 + j >= R) break;
-      const double nF = F * cur[j].x - S * cur[j].y, nS = F * cur[j].y + S * cur[j].x;
-      const double Fd = from_next_lane(nF), Su = from_prev_lane(nS);
-      F = i == 0 ? nF : (i == H - 1 ? nS : Fd);
-      S = i == 0 ? (H > 1 ? Fd : nS) : Su;
-    }
-#pragma unroll
-    for (int j = 0; j < kReplayBatch; ++j) cur[j] = nxt[j];
-  }
-  if (act && r < m) {
-    const int* perm = hdr + 1;
-    if (f < m) Vout[r * ldv + perm[f]] = F;
-    if (sc < m) Vout[r * ldv + perm[sc]] = S;
-  }
-}
-
 }  // namespace
 
 hipError_t dense_gram(int N, int k1, int k2, const double* A, int lda, const double* B, int ldb, double* part,
@@ -663,19 +382,6 @@ hipError_t dense_combine3(int N, int k1, int k2, const double* A0, const double*
   if (k2 > kMaxSmall) return hipErrorInvalidValue;
   hipLaunchKernelGGL(combine_kernel, dim3((N + kCbR - 1) / kCbR, 3), dim3(256), 0, s, N, k1, k2, A0, A1, A2, lda, T,
                      ldt, 0.0, nullptr, 0, Y0, Y1, Y2, ldy);
-  return hipGetLastError();
-}
-
-hipError_t dense_syev_w(int m, const double* A, int lda, double* w, double* V, int ldv, double* work,
-                        hipStream_t s) {
-  if (m < 1 || m > kMaxSmall || (V && !work)) return hipErrorInvalidValue;
-  const int Me = m + (m & 1);
-  const size_t lds = sizeof(double) * ((size_t)Me * (Me + 1) / 2);
-  int* hdr = V ? reinterpret_cast<int*>(work) : nullptr;
-  double2* rec = V ? reinterpret_cast<double2*>(work + kSyevHeaderDoubles) : nullptr;
-  (void)hipFuncSetAttribute((const void*)syev_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(syev_kernel, dim3(1), dim3(kSyevThreads), lds, s, m, A, lda, w, rec, hdr);
-  if (V) hipLaunchKernelGGL(syev_vectors_kernel, dim3(m), dim3(64), 0, s, m, rec, hdr, V, ldv);
   return hipGetLastError();
 }
 

@@ -640,7 +640,7 @@ constexpr double kDropPivot = 1e-10;   // Cholesky-QR: squared relative distance
 
 struct EigWs {
   double *X, *HX, *SX, *P, *R, *W, *Q, *HQ, *SQ, *Q2, *HQ2, *SQ2;
-  double *G, *Gs, *lam, *dvec, *T, *GH, *th, *C, *C2, *norms, *syw, *part, *rpart;
+  double *G, *Gs, *lam, *dvec, *T, *GH, *th, *C, *C2, *norms, *part, *rpart;
   char* mv;
   size_t mv_bytes;
 };
@@ -661,7 +661,7 @@ size_t eigs_layout(const lhf_toeplitz_s* t, int nev, EigWs* w, char* base) {
   const size_t sq = (size_t)kMaxSmall * kMaxSmall;
   take(d.G, sq); take(d.Gs, sq); take(d.lam, kMaxSmall); take(d.dvec, kMaxSmall);
   take(d.T, sq); take(d.GH, sq); take(d.th, kMaxSmall); take(d.C, sq); take(d.C2, sq); take(d.norms, kMaxSmall);
-  take(d.syw, kSyevWorkDoubles); take(d.part, (size_t)kGramChunks * sq); take(d.rpart, (size_t)kChunks * kMaxSmall);
+  take(d.part, (size_t)kGramChunks * sq); take(d.rpart, (size_t)kChunks * kMaxSmall);
   d.mv_bytes = lhf_toeplitz_matvec_workspace(const_cast<lhf_toeplitz_s*>(t), mx);
   d.mv = base ? base + off : nullptr;
   off += d.mv_bytes;
@@ -769,7 +769,7 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t t, int32_t nev, int32_t maxit, double t
     // Rayleigh-Ritz in FP64
     ck(dense_gram(N, kk, kk, w.Q2, mx, w.HQ2, mx, w.part, kGramChunks, w.GH, S, s));
     ck(dense_symmetrize(kk, w.GH, S, s));
-    ck(dense_syev_w(kk, w.GH, S, w.th, w.C, S, w.syw, s));
+    ck(dense_syev_low(kk, nb, w.GH, S, w.th, w.C, S, s));
     ck(dense_combine3(N, kk, nb, w.Q2, w.HQ2, w.SQ2, mx, w.C, S, w.W, w.HX, w.SX, nb, s));   // X_new, HX, SX
     if (it > 0) {
       // P = X_new - X (X^T S X_new)

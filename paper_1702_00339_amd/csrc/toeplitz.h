@@ -98,16 +98,10 @@ hipError_t dense_combine(int N, int k1, int k2, const double* A, int lda, const 
 // Y_a = A_a T for three blocks sharing T (one launch); k2 <= kMaxSmall
 hipError_t dense_combine3(int N, int k1, int k2, const double* A0, const double* A1, const double* A2, int lda,
                           const double* T, int ldt, double* Y0, double* Y1, double* Y2, int ldy, hipStream_t s);
-// Jacobi of the dense eigensolver: sweep cap, and the workspace for the
-// eigenvectors (a header with the round count and the ascending order, then
-// the (c, s) of every pair of every recorded round)
-constexpr int kSyevMaxSweeps = 60;
-constexpr size_t kSyevHeaderDoubles = (kMaxSmall + 2) / 2 + 1;
-constexpr size_t kSyevWorkDoubles =
-    kSyevHeaderDoubles + 2 * (size_t)kSyevMaxSweeps * (kMaxSmall - 1) * (kMaxSmall / 2);
-// eigenvalues ascending in w, eigenvectors in the columns of V (m <= kMaxSmall;
-// V may be NULL); work: kSyevWorkDoubles doubles when V is given
-hipError_t dense_syev_w(int m, const double* A, int lda, double* w, double* V, int ldv, double* work, hipStream_t s);
+// the k lowest eigenpairs (ascending in w, eigenvector i in column i of V,
+// row-major, ldv >= k; 1 <= k <= m <= kMaxSmall): tridiagonalisation,
+// bisection, inverse iteration, back-transform (rrsyev.hip), in LDS
+hipError_t dense_syev_low(int m, int k, const double* A, int lda, double* w, double* V, int ldv, hipStream_t s);
 hipError_t dense_residual(int N, int k, const double* HX, const double* SX, int ld, const double* theta, double* R,
                           int ldr, double* part, int nchunk, double* norms, hipStream_t s);
 hipError_t dense_random(int N, int k, uint64_t seed, double* X, int ld, hipStream_t s);

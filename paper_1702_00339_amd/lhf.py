@@ -122,6 +122,7 @@ def load(path: str = LIB_PATH):
         "lhf_toeplitz_eigs": (i32, [vp, i32, i32, C.c_double, C.c_uint64, vp, vp, C.POINTER(i32),
                                     C.POINTER(C.c_double), vp, sz, vp]),
         "lhf_toeplitz_destroy": (i32, [vp]),
+        "lhf_dense_syev": (i32, [i32, i32, vp, i32, vp, vp, i32, vp]),
         "lhf_status_string": (C.c_char_p, [i32]),
         "lhf_last_error": (C.c_char_p, []),
         "lhf_version": (i32, []),
@@ -143,7 +144,8 @@ def exported_symbols():
             "lhf_plan_autotune", "lhf_toeplitz_create", "lhf_box_exact_create", "lhf_toeplitz3_create",
             "lhf_toeplitz3_generators", "lhf_toeplitz_get_info", "lhf_toeplitz_blocks",
             "lhf_toeplitz_matvec_workspace", "lhf_toeplitz_matvec", "lhf_toeplitz_eigs_workspace",
-            "lhf_toeplitz_eigs", "lhf_toeplitz_destroy", "lhf_status_string", "lhf_last_error", "lhf_version"]
+            "lhf_toeplitz_eigs", "lhf_toeplitz_destroy", "lhf_dense_syev",
+            "lhf_status_string", "lhf_last_error", "lhf_version"]
 
 
 def _check(st):
@@ -190,6 +192,13 @@ def _ptr(t):
 def _stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def lhf_dense_syev(m, k, A, lda, w, V, ldv):
+    """The k lowest eigenpairs of the symmetric m x m matrix A (device FP64
+    tensors; V row-major m x k)."""
+    lib = load()
+    _check(lib.lhf_dense_syev(m, k, _ptr(A), lda, _ptr(w), _ptr(V), ldv, _stream()))
 
 
 class Plan:
