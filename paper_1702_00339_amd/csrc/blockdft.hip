@@ -810,6 +810,27 @@ __global__ void __launch_bounds__(256) sep_chain_kernel(const LatDev* __restrict
 // LDS bytes (complex128) of the fused kernel for a lattice, 0 when the
 // lattice does not qualify (one transformed dimension, a band wider than 32
 // slots, an axis longer than 4096, or more than 64 KiB).
+// Workgroup ranges of a grouped Fourier launch, longest first (LPT): a
+// workgroup of lattice L does about B1 (J + T) complex multiply-adds per
+// column (J outputs along dimension 1, T Gram terms), and workgroups start in
+// index order, so the costly lattices go first and the cheap ones fill the
+// tail.  wg_base follows the new order; the kernels find their task by it.
+static void order_fused_tasks(const std::vector<LatDev>& lats, std::vector<FusedTask>& tasks, bool chain) {
+  auto cost = [&](const FusedTask& t) {
+    const LatDev& L = lats[t.li];
+    return (int64_t)nslot(L.dim[0]) * ((chain ? t.J2C : L.L[0]) + L.T);
+  };
+  auto nwg = [&](const FusedTask& t) {
+    return chain ? (int64_t)t.nec * t.nj2c : (int64_t)lats[t.li].L[2] * t.nj2c * t.nec;
+  };
+  std::stable_sort(tasks.begin(), tasks.end(), [&](const FusedTask& a, const FusedTask& b) { return cost(a) > cost(b); });
+  int64_t base = 0;
+  for (FusedTask& t : tasks) {
+    t.wg_base = base;
+    base += nwg(t);
+  }
+}
+
 static int64_t fused_lds_bytes(const LatDev& L) {
   int nd = 0;
   for (int d = 0; d < 3; ++d) nd += L.L[d] > 1;
@@ -850,6 +871,7 @@ void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std
     for (int d = 0; d < 3; ++d) fused_bmax = std::max(fused_bmax, nslot(L.dim[d]));
     fused_lds = std::max<int32_t>(fused_lds, (int32_t)lb);
   }
+  order_fused_tasks(lats, fused, false);
   // per lattice: the transformed dimensions, last non-trivial first (a
   // one-cell lattice is a single pass over dimension 3 that copies)
   std::vector<std::vector<int>> dims(nlat);
@@ -979,6 +1001,8 @@ void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tas
       gh_threads += ((int64_t)L.T * L.L[d] * L.m0 * L.m0 + 255) / 256 * 256;
     }
   }
+  order_fused_tasks(lats, tasks, false);
+  order_fused_tasks(lats, chain, true);
 }
 
 hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* gh, double2* bar_h, double2* bar_s,

@@ -141,6 +141,15 @@ void plan_factors(const std::vector<LatDev>& lats, std::vector<FacItem>& items) 
           for (int ch = 0; ch < (D.npot + FT - 1) / FT; ++ch) items.push_back(FacItem{li, d, r, ch});
     }
   }
+  // longest first over the whole plan (LPT): a window item sums its node
+  // group over the L + 1 images, the others evaluate one chunk of FT values
+  auto cost = [&](const FacItem& it) -> int64_t {
+    if (it.chunk >= 0) return FT;
+    const DimDev& D = lats[it.li].dim[it.d];
+    return (int64_t)window_nodes(D.nc, D.L) * (D.L + 1);
+  };
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const FacItem& a, const FacItem& b) { return cost(a) > cost(b); });
 }
 
 hipError_t launch_factors(const lhf_plan_s* p, double* fac, hipStream_t s) {

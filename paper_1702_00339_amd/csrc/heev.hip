@@ -62,6 +62,14 @@ __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq_(double x) { return 1.0 / sqrt(x); }
+// 1 / x for a normal x to within a few ulps: the hardware estimate, refined
+// by two Newton steps in FP64.
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_fast(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
 
 // Round-robin schedule: pair i of round s (0 <= s < M-1).
 template <int M>
@@ -935,14 +943,15 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
   // every group forms p_c = beta sum_r conj(A_rc) u_r (= (beta A u)_c, A
   // Hermitian) and publishes p_c and Re(conj(u_c) p_c); barrier; every lane
   // updates its entries, and the owner of column h + 1 goes straight on to
-  // the next reflector, its column being current.  u, p, those products and
-  // u^H u / 2 are double-buffered in LDS by the parity of h, so two barriers
-  // per step keep every read ahead of the next overwrite.
+  // the next reflector, its column being current (with several wavefronts
+  // per matrix its wavefront updates at raised priority).  u, p, those
+  // products and beta are double-buffered in LDS by the parity of h, so two
+  // barriers per step keep every read ahead of the next overwrite.
   C* const lb = &sh.B[g][0][0];   // B is free after the reduction
   C* const ubuf = lb;             // u: [2][M]
   C* const pbuf = lb + 2 * M;     // p: [2][M]
   R* const upbuf = reinterpret_cast<R*>(lb + 4 * M);   // Re(conj(u_i) p_i): [2][M]
-  R* const bbuf = sh.red[g];      // u^H u / 2: [2]
+  R* const bbuf = sh.red[g];      // beta = 2 / u^H u (0: no reflection): [2]
   C a[W];
 #pragma unroll
   for (int k = 0; k < W; ++k) a[k] = sh.A[g][gc + P * k][gi];
@@ -973,7 +982,7 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
       // u = phase(x_0) (|x_0| + |x|) e_0 + x scaled by sc = |x_0| (1 when
       // x_0 = 0), which needs no division: u_(h+1) = x_0 (|x_0| + |x|),
       // u_r = |x_0| x_r below, zero elsewhere; hh = u^H u / 2 =
-      // sc^2 |x| (|x| + |x_0|), and beta = 1 / hh is formed by the readers
+      // sc^2 |x| (|x| + |x_0|), published as beta = 1 / hh
       const R sc = ar > R(0) ? ar : R(1);
       const C u1 = ar > R(0) ? cscale(al, ar + nrm) : cmk<C>(nrm, R(0));
       const R hh = act && x2 > R(0) ? sc * sc * (nrm * (nrm + ar)) : R(0);
@@ -984,14 +993,14 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
         u[r] = in ? (r == h + 1 ? u1 : cscale(a[k], sc)) : cmk<C>(R(0), R(0));
       }
       if (gc == 0) {
-        bbuf[bsel] = hh;
+        bbuf[bsel] = hh != R(0) ? rcp_fast(hh) : R(0);
         if (act) e2[h] = a2 + x2;
       }
     }
+    if constexpr (TPM > 64) __builtin_amdgcn_s_setprio(0);
     __syncthreads();
-    const R hh = bbuf[bsel];
-    const bool refl = hh != R(0);
-    const R beta = refl ? R(1) / hh : R(0);   // overlaps the loads and the reduction below
+    const R beta = bbuf[bsel];
+    const bool refl = beta != R(0);
     const bool colok = gi > h && gi < n;
     C ur[W], pc = cmk<C>(R(0), R(0));
 #pragma unroll
@@ -1010,6 +1019,11 @@ __device__ void tridiag_eigs(Smem<R, M, G, HASU, HASV, NOF>& sh, int g, int t, i
     }
     __syncthreads();
     if (refl) {
+      // several wavefronts per matrix: the one owning the next column goes
+      // first, so that its reflector work overlaps the others' updates
+      if constexpr (TPM > 64) {
+        if ((t >> 6) == ((h + 1) * P >> 6)) __builtin_amdgcn_s_setprio(1);
+      }
       // K = beta u^H p / 2, four partial sums over the rows
       R ks4[4];
 #pragma unroll

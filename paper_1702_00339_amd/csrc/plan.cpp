@@ -77,6 +77,16 @@ void plan_grams(const std::vector<LatDev>& lats, std::vector<GramItem>& items, i
           for (int ks = 0; ks < D.ksplit; ++ks) items.push_back(GramItem{i, d, tm, tn, ks, 0});
     }
   }
+  // longest first (LPT): an item's work is its share of the window (the
+  // tiles are equal); workgroups take items grid-stride in this order, so
+  // the long ones start first and the short ones fill the tail.  The kernel
+  // reads every output location from the item, so the order is free.
+  auto cost = [&](const GramItem& it) {
+    const DimDev& D = lats[it.li].dim[it.d];
+    return std::min(D.kchunk, D.kwin - it.ks * D.kchunk);
+  };
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const GramItem& a, const GramItem& b) { return cost(a) > cost(b); });
 }
 
 // Fill one lattice's device descriptor; returns LHF_OK or an error code.
