@@ -138,6 +138,8 @@ typedef struct {
   int64_t w_elems;       /* sum L1 L2 L3 m0: eigenvalues                           */
   int64_t grams_elems;   /* FP64 elements of the 1D Gram buffer                    */
   size_t ws_bytes;       /* workspace bytes every hot call of this plan needs      */
+  int64_t half_elems;    /* sum L1 L2 (L3/2 + 1) m0^2: a Fourier-block stack in the
+                            Hermitian half-space along k3 (lhf_block_fft_half)     */
 } lhf_sizes;
 
 /* ---------------------------------------------------------------- plans
@@ -203,6 +205,20 @@ int32_t lhf_block_fft(lhf_plan_t plan, int32_t prec, const void* d_H_gen, const 
                       void* d_H_bar, void* d_S_bar, void* d_ws, size_t ws_bytes,
                       lhf_stream_t stream);
 
+/* lhf_block_fft restricted to the Hermitian half-space along k3: the
+ * generators are real symmetric, so Hbar_(-j) = conj(Hbar_j) (Prop. 5.1) and
+ * the blocks j3 > L3/2 carry no information beyond the kept ones (their
+ * conjugates at (-j1, -j2, L3 - j3) mod L).  Same transform and arithmetic as
+ * lhf_block_fft; only the blocks 0 <= j3 <= L3/2 are formed and written, in
+ * the layout per lattice [j1][j2][j3 <= L3/2][mu][nu] at the lattice's
+ * offset in a stack of half_elems elements (lhf_plan_sizes; a one-cell third
+ * dimension keeps every block).  The fused and separable kernels run no
+ * workgroup for j3 > L3/2.  d_H_half, d_S_half: device, half_elems complex
+ * elements each (complex128 for LHF_PREC_FP64, complex64 for LHF_PREC_MIXED).
+ * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE. */
+int32_t lhf_block_fft_half(lhf_plan_t plan, int32_t prec, const void* d_H_gen, const void* d_S_gen,
+                           void* d_H_half, void* d_S_half, void* d_ws, size_t ws_bytes, lhf_stream_t stream);
+
 /* The FP64 block DFT of the mixed pipeline: reads the FP64 stacks, writes the
  * complex128 blocks (d_H_bar64, d_S_bar64, for refinement) and their
  * complex64 roundings (d_H_bar32, d_S_bar32, for the FP32 solve) in one pass.
@@ -231,6 +247,12 @@ int32_t lhf_block_fft_dual(lhf_plan_t plan, const double* d_H_gen64, const doubl
  * and band need more than 64 KiB of LDS per workgroup). */
 int32_t lhf_fourier_blocks(lhf_plan_t plan, const double* d_grams64, void* d_H_bar64, void* d_S_bar64,
                            void* d_ws, size_t ws_bytes, lhf_stream_t stream);
+/* lhf_fourier_blocks restricted to the Hermitian half-space along k3, in the
+ * half layout of lhf_block_fft_half (d_H_half64, d_S_half64: device
+ * complex128 [half_elems]); workgroups of the blocks j3 > L3/2 are not run.
+ * Errors: as lhf_fourier_blocks. */
+int32_t lhf_fourier_blocks_half(lhf_plan_t plan, const double* d_grams64, void* d_H_half64, void* d_S_half64,
+                                void* d_ws, size_t ws_bytes, lhf_stream_t stream);
 
 /* lhf_fourier_blocks for callers that cannot allocate device memory or pass
  * a workspace (code under HIP graph capture, tight serving loops, harnesses

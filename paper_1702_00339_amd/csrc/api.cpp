@@ -71,8 +71,8 @@ int32_t lhf_assemble_blocks(lhf_plan_t p, void* H_gen, void* S_gen, double* gram
   return hip_status(e, "combine");
 }
 
-int32_t lhf_block_fft(lhf_plan_t p, int32_t prec, const void* H_gen, const void* S_gen, void* H_bar,
-                      void* S_bar, void* ws, size_t ws_bytes, lhf_stream_t stream) {
+static int32_t block_fft(lhf_plan_t p, int32_t prec, const void* H_gen, const void* S_gen, void* H_bar,
+                         void* S_bar, void* ws, size_t ws_bytes, lhf_stream_t stream, bool half) {
   if (!p) { set_error("NULL plan"); return LHF_ERR_INVALID; }
   if (prec != LHF_PREC_FP64 && prec != LHF_PREC_MIXED) { set_error("bad precision"); return LHF_ERR_INVALID; }
   if (!H_gen || !S_gen || !H_bar || !S_bar) { set_error("all four stacks are required"); return LHF_ERR_INVALID; }
@@ -80,7 +80,18 @@ int32_t lhf_block_fft(lhf_plan_t p, int32_t prec, const void* H_gen, const void*
   if (st != LHF_OK) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
   Ws w = ws_view(p, ws);
-  return hip_status(launch_block_dft(p, prec, H_gen, S_gen, H_bar, S_bar, w.dft, nullptr, nullptr, s), "block dft");
+  return hip_status(launch_block_dft(p, prec, H_gen, S_gen, H_bar, S_bar, w.dft, nullptr, nullptr, s, half),
+                    "block dft");
+}
+
+int32_t lhf_block_fft(lhf_plan_t p, int32_t prec, const void* H_gen, const void* S_gen, void* H_bar,
+                      void* S_bar, void* ws, size_t ws_bytes, lhf_stream_t stream) {
+  return block_fft(p, prec, H_gen, S_gen, H_bar, S_bar, ws, ws_bytes, stream, false);
+}
+
+int32_t lhf_block_fft_half(lhf_plan_t p, int32_t prec, const void* H_gen, const void* S_gen, void* H_half,
+                           void* S_half, void* ws, size_t ws_bytes, lhf_stream_t stream) {
+  return block_fft(p, prec, H_gen, S_gen, H_half, S_half, ws, ws_bytes, stream, true);
 }
 
 int32_t lhf_block_fft_dual(lhf_plan_t p, const double* H_gen64, const double* S_gen64, void* H_bar64,
@@ -99,8 +110,8 @@ int32_t lhf_block_fft_dual(lhf_plan_t p, const double* H_gen64, const double* S_
                     "block dft");
 }
 
-int32_t lhf_fourier_blocks(lhf_plan_t p, const double* grams64, void* H_bar64, void* S_bar64, void* ws,
-                           size_t ws_bytes, lhf_stream_t stream) {
+static int32_t fourier_blocks(lhf_plan_t p, const double* grams64, void* H_bar64, void* S_bar64, void* ws,
+                              size_t ws_bytes, lhf_stream_t stream, bool half) {
   if (!p) { set_error("NULL plan"); return LHF_ERR_INVALID; }
   if (!H_bar64 || !S_bar64) { set_error("H_bar64 and S_bar64 are required"); return LHF_ERR_INVALID; }
   if (!p->sep_ok) {
@@ -111,8 +122,18 @@ int32_t lhf_fourier_blocks(lhf_plan_t p, const double* grams64, void* H_bar64, v
   if (st != LHF_OK) return st;
   Ws w = ws_view(p, ws);
   return hip_status(launch_fourier_sep(p, grams64 ? grams64 : w.grams64, w.gh, static_cast<double2*>(H_bar64),
-                                       static_cast<double2*>(S_bar64), static_cast<hipStream_t>(stream)),
+                                       static_cast<double2*>(S_bar64), static_cast<hipStream_t>(stream), half),
                     "separable fourier blocks");
+}
+
+int32_t lhf_fourier_blocks(lhf_plan_t p, const double* grams64, void* H_bar64, void* S_bar64, void* ws,
+                           size_t ws_bytes, lhf_stream_t stream) {
+  return fourier_blocks(p, grams64, H_bar64, S_bar64, ws, ws_bytes, stream, false);
+}
+
+int32_t lhf_fourier_blocks_half(lhf_plan_t p, const double* grams64, void* H_half64, void* S_half64, void* ws,
+                                size_t ws_bytes, lhf_stream_t stream) {
+  return fourier_blocks(p, grams64, H_half64, S_half64, ws, ws_bytes, stream, true);
 }
 
 int32_t lhf_heev_batched(lhf_plan_t p, uint32_t flags, const void* H_bar, const void* S_bar,

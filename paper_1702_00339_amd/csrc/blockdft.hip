@@ -36,6 +36,18 @@ __host__ __device__ __forceinline__ int slot_cell(const DimDev& D, int s) {
   return k < 0 ? k + D.L : k;
 }
 
+// Element of the half layout [L1][L2][L3/2+1][m0][m0] (the Hermitian
+// half-space along k3: the blocks j3 > L3/2 are conjugates of kept ones) for
+// the full-layout element `flat` of lattice L, or -1 for j3 > L3/2.
+__device__ __forceinline__ int64_t half_index(const LatDev& L, int64_t flat) {
+  const int L3 = L.L[2];
+  if (L3 == 1) return flat;
+  const int E = L.m0 * L.m0, L3h = L3 / 2 + 1;
+  const int64_t q = flat / E, r = q / L3;
+  const int e = (int)(flat - q * E), j3 = (int)(q - r * L3);
+  return j3 < L3h ? (r * L3h + j3) * E + e : -1;
+}
+
 __host__ __device__ __forceinline__ int nslot(const DimDev& D) { return D.L == 1 ? 1 : D.nshift; }
 
 __device__ __forceinline__ int find_task(const DftTask* __restrict__ tasks, int ntasks, int64_t wg0) {
@@ -62,7 +74,8 @@ __global__ void __launch_bounds__(256) dft_pass_kernel(const LatDev* __restrict_
                                                        typename Cx<R>::T* __restrict__ tmp,
                                                        typename Cx<R>::T* __restrict__ barH,
                                                        typename Cx<R>::T* __restrict__ barS,
-                                                       float2* __restrict__ b32H, float2* __restrict__ b32S) {
+                                                       float2* __restrict__ b32H, float2* __restrict__ b32S,
+                                                       int half) {
   typedef typename Cx<R>::T C;
   const int64_t wg0 = (int64_t)blockIdx.x * 256;
   const DftTask T = tasks[find_task(tasks, ntasks, wg0)];
@@ -125,8 +138,11 @@ __global__ void __launch_bounds__(256) dft_pass_kernel(const LatDev* __restrict_
   for (int b = 0; b < BMAX; ++b)
     if (b < B) idx[b] = (j0 * kb[b]) % Ld;
   const C* Tw = lds_tw ? sT : tw + D.tw_off;
-  C* Y = T.out_final ? (isH ? barH : barS) + L.gen_off : tmp + T.out_off + (isH ? 0 : T.out_half);
-  C* dst = Y + (int64_t)o * Ld * I + i;
+  const bool hout = half && T.out_final;   // final blocks in the half layout
+  C* Y = T.out_final ? (isH ? barH : barS) + (hout ? L.half_off : L.gen_off)
+                     : tmp + T.out_off + (isH ? 0 : T.out_half);
+  const int64_t f0 = (int64_t)o * Ld * I + i;
+  C* dst = Y + f0;
   // complex64 copy of final blocks (the FP64 transform of the mixed pipeline)
   float2* d32 = (T.out_final && b32H) ? (isH ? b32H : b32S) + L.gen_off + (int64_t)o * Ld * I + i : nullptr;
   for (int j = j0; j < j1; ++j) {
@@ -144,7 +160,12 @@ __global__ void __launch_bounds__(256) dft_pass_kernel(const LatDev* __restrict_
     C r;
     r.x = re;
     r.y = im;
-    dst[(int64_t)j * I] = r;
+    if (hout) {
+      const int64_t h = half_index(L, f0 + (int64_t)j * I);
+      if (h >= 0) Y[h] = r;
+    } else {
+      dst[(int64_t)j * I] = r;
+    }
     if (d32) d32[(int64_t)j * I] = make_float2((float)re, (float)im);
   }
 }
@@ -158,7 +179,8 @@ __global__ void __launch_bounds__(256) dft_wide_kernel(const LatDev* __restrict_
                                                        typename Cx<R>::T* __restrict__ tmp,
                                                        typename Cx<R>::T* __restrict__ barH,
                                                        typename Cx<R>::T* __restrict__ barS,
-                                                       float2* __restrict__ b32H, float2* __restrict__ b32S) {
+                                                       float2* __restrict__ b32H, float2* __restrict__ b32S,
+                                                       int half) {
   typedef typename Cx<R>::T C;
   const int64_t wg0 = (int64_t)blockIdx.x * 256;
   const DftTask T = tasks[find_task(tasks, ntasks, wg0)];
@@ -202,11 +224,18 @@ __global__ void __launch_bounds__(256) dft_wide_kernel(const LatDev* __restrict_
     re += w.x * xr - w.y * xi;
     im += w.x * xi + w.y * xr;
   }
-  C* Y = T.out_final ? (isH ? barH : barS) + L.gen_off : tmp + T.out_off + (isH ? 0 : T.out_half);
+  const bool hout = half && T.out_final;   // final blocks in the half layout
+  C* Y = T.out_final ? (isH ? barH : barS) + (hout ? L.half_off : L.gen_off)
+                     : tmp + T.out_off + (isH ? 0 : T.out_half);
   C r;
   r.x = re;
   r.y = im;
-  Y[tid] = r;
+  if (hout) {
+    const int64_t h = half_index(L, tid);
+    if (h >= 0) Y[h] = r;
+  } else {
+    Y[tid] = r;
+  }
   if (T.out_final && b32H) ((isH ? b32H : b32S) + L.gen_off)[tid] = make_float2((float)re, (float)im);
 }
 
@@ -234,7 +263,7 @@ __device__ __forceinline__ void fused_last_stage(const LatDev& L, int J2C, int j
                                                  const typename Cx<R>::T* T2, const typename Cx<R>::T* tw1, bool isH,
                                                  typename Cx<R>::T* __restrict__ barH,
                                                  typename Cx<R>::T* __restrict__ barS, float2* __restrict__ b32H,
-                                                 float2* __restrict__ b32S) {
+                                                 float2* __restrict__ b32S, bool half) {
   typedef typename Cx<R>::T C;
   constexpr int EC = kFusedEC;
   const DimDev& D0 = L.dim[0];
@@ -260,10 +289,13 @@ __device__ __forceinline__ void fused_last_stage(const LatDev& L, int J2C, int j
       stp[s1] = (nrep * k1) % L1;
     }
   }
-  const int64_t yoff = L.gen_off + ((int64_t)(j2lo + jj) * L3 + j3) * E + e0 + ec;
+  // full layout [L1][L2][L3][E], or the half layout with L3 / 2 + 1 planes
+  // (the caller runs no workgroup for j3 > L3 / 2 then)
+  const int L3o = half ? L3 / 2 + 1 : L3;
+  const int64_t yoff = (half ? L.half_off : L.gen_off) + ((int64_t)(j2lo + jj) * L3o + j3) * E + e0 + ec;
   C* Y = (isH ? barH : barS) + yoff;
   float2* Y32 = b32H ? (isH ? b32H : b32S) + yoff : nullptr;
-  const int64_t jstride = (int64_t)L2 * L3 * E;
+  const int64_t jstride = (int64_t)L2 * L3o * E;
   const R zs = tw1[Q % L1].y < R(0) ? R(-1) : R(1);   // zeta = zs i when R1 = 4
   // output j1 = j + q Q sits (j1 - j) jstride past the base output j
   const int64_t ystep = (int64_t)nrep * jstride, qstep = (int64_t)Q * jstride;
@@ -330,7 +362,8 @@ __global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict
                                                         const R* __restrict__ genH, const R* __restrict__ genS,
                                                         typename Cx<R>::T* __restrict__ barH,
                                                         typename Cx<R>::T* __restrict__ barS,
-                                                        float2* __restrict__ b32H, float2* __restrict__ b32S) {
+                                                        float2* __restrict__ b32H, float2* __restrict__ b32S,
+                                                        int half) {
   typedef typename Cx<R>::T C;
   extern __shared__ char lds_raw[];
   const int64_t wg = blockIdx.x;
@@ -349,6 +382,7 @@ __global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict
   loc /= T.nec;
   const int j2c = (int)(loc % T.nj2c);
   const int j3 = (int)(loc / T.nj2c);
+  if (half && j3 > L3 / 2) return;   // the conjugate half: the whole workgroup
   const int e0 = eci * EC, ecn = min(EC, E - e0);
   const int j2lo = j2c * J2C, j2n = min(J2C, L2 - j2lo);
   C* T1 = reinterpret_cast<C*>(lds_raw);   // [B1][B2][EC]
@@ -448,10 +482,11 @@ __global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict
       stp[s1] = (nrep * k1) % L1;
     }
   }
-  const int64_t yoff = L.gen_off + ((int64_t)(j2lo + jj) * L3 + j3) * E + e0 + ec;
+  const int L3o = half ? L3 / 2 + 1 : L3;   // planes along j3 of the output layout
+  const int64_t yoff = (half ? L.half_off : L.gen_off) + ((int64_t)(j2lo + jj) * L3o + j3) * E + e0 + ec;
   C* Y = (blockIdx.y == 0 ? barH : barS) + yoff;
   float2* Y32 = b32H ? (blockIdx.y == 0 ? b32H : b32S) + yoff : nullptr;
-  const int64_t jstride = (int64_t)L2 * L3 * E;
+  const int64_t jstride = (int64_t)L2 * L3o * E;
   const R zs = tw1[Q % L1].y < R(0) ? R(-1) : R(1);   // zeta = zs i when R1 = 4
   // output j1 = j + q Q sits (j1 - j) jstride past the base output j
   const int64_t ystep = (int64_t)nrep * jstride, qstep = (int64_t)Q * jstride;
@@ -507,20 +542,21 @@ int band_class(int B) { return B <= 4 ? 0 : B <= 8 ? 1 : B <= 16 ? 2 : B <= 32 ?
 template <typename R>
 hipError_t dft_launch_all(const lhf_plan_s* p, const R* gH, const R* gS, typename Cx<R>::T* bH,
                           typename Cx<R>::T* bS, typename Cx<R>::T* tmp, const typename Cx<R>::T* tw,
-                          float2* b32H, float2* b32S, hipStream_t s) {
+                          float2* b32H, float2* b32S, bool half, hipStream_t s) {
+  const int hf = half ? 1 : 0;
   typedef typename Cx<R>::T C;
   if (p->n_fused > 0) {
     const dim3 grid((unsigned)p->fused_wgs, 2);
     const size_t shb = (size_t)p->fused_lds / 16 * sizeof(C);
     if (p->fused_bmax <= 8)
       hipLaunchKernelGGL((dft_fused_kernel<R, 8>), grid, dim3(256), shb, s, p->d_lat, p->d_fused, p->n_fused, tw, gH,
-                         gS, bH, bS, b32H, b32S);
+                         gS, bH, bS, b32H, b32S, hf);
     else if (p->fused_bmax <= 16)
       hipLaunchKernelGGL((dft_fused_kernel<R, 16>), grid, dim3(256), shb, s, p->d_lat, p->d_fused, p->n_fused, tw, gH,
-                         gS, bH, bS, b32H, b32S);
+                         gS, bH, bS, b32H, b32S, hf);
     else
       hipLaunchKernelGGL((dft_fused_kernel<R, 32>), grid, dim3(256), shb, s, p->d_lat, p->d_fused, p->n_fused, tw, gH,
-                         gS, bH, bS, b32H, b32S);
+                         gS, bH, bS, b32H, b32S, hf);
   }
   for (const DftLaunch& l : p->dft_launches) {
     const dim3 grid((unsigned)(l.threads / 256), 2);
@@ -530,10 +566,10 @@ hipError_t dft_launch_all(const lhf_plan_s* p, const R* gH, const R* gS, typenam
 #define LHF_PASS(BM)                                                                                      \
   if (first)                                                                                              \
     hipLaunchKernelGGL((dft_pass_kernel<R, BM, true>), grid, dim3(256), shb, s, p->d_lat, tk, l.nt, tw,   \
-                       gH, gS, tmp, bH, bS, b32H, b32S);                                                              \
+                       gH, gS, tmp, bH, bS, b32H, b32S, hf);                                                           \
   else                                                                                                    \
     hipLaunchKernelGGL((dft_pass_kernel<R, BM, false>), grid, dim3(256), shb, s, p->d_lat, tk, l.nt, tw,  \
-                       gH, gS, tmp, bH, bS, b32H, b32S);
+                       gH, gS, tmp, bH, bS, b32H, b32S, hf);
     switch (l.cls) {
       case 0: LHF_PASS(4) break;
       case 1: LHF_PASS(8) break;
@@ -542,10 +578,10 @@ hipError_t dft_launch_all(const lhf_plan_s* p, const R* gH, const R* gS, typenam
       default:
         if (first)
           hipLaunchKernelGGL((dft_wide_kernel<R, true>), grid, dim3(256), 0, s, p->d_lat, tk, l.nt, tw, gH, gS,
-                             tmp, bH, bS, b32H, b32S);
+                             tmp, bH, bS, b32H, b32S, hf);
         else
           hipLaunchKernelGGL((dft_wide_kernel<R, false>), grid, dim3(256), 0, s, p->d_lat, tk, l.nt, tw, gH, gS,
-                             tmp, bH, bS, b32H, b32S);
+                             tmp, bH, bS, b32H, b32S, hf);
     }
 #undef LHF_PASS
   }
@@ -610,7 +646,7 @@ __global__ void __launch_bounds__(256) sep_fused_kernel(const LatDev* __restrict
                                                         const double2* __restrict__ tw,
                                                         const double* __restrict__ grams,
                                                         const double2* __restrict__ gh, double2* __restrict__ barH,
-                                                        double2* __restrict__ barS) {
+                                                        double2* __restrict__ barS, int half) {
   typedef double2 C;
   extern __shared__ char lds_raw[];
   const int64_t wg = blockIdx.x;
@@ -627,6 +663,7 @@ __global__ void __launch_bounds__(256) sep_fused_kernel(const LatDev* __restrict
   loc /= T.nec;
   const int j2c = (int)(loc % T.nj2c);
   const int j3 = (int)(loc / T.nj2c);
+  if (half && j3 > L3 / 2) return;   // the conjugate half: the whole workgroup
   const int e0 = eci * EC, ecn = min(EC, m2 - e0);
   const int j2lo = j2c * J2C, j2n = min(J2C, L2 - j2lo);
   C* T2 = reinterpret_cast<C*>(lds_raw);             // [B1][J2C][EC]
@@ -703,7 +740,7 @@ __global__ void __launch_bounds__(256) sep_fused_kernel(const LatDev* __restrict
     }
   }
   __syncthreads();
-  fused_last_stage<double, BM>(L, J2C, j2lo, j2n, j3, e0, ecn, T2, tw1, isH, barH, barS, nullptr, nullptr);
+  fused_last_stage<double, BM>(L, J2C, j2lo, j2n, j3, e0, ecn, T2, tw1, isH, barH, barS, nullptr, nullptr, half != 0);
 }
 
 constexpr int kChainEC = 8;    // block entries per chain workgroup
@@ -726,7 +763,8 @@ __global__ void __launch_bounds__(256) sep_chain_kernel(const LatDev* __restrict
                                                         const FusedTask* __restrict__ tasks, int ntasks,
                                                         const double2* __restrict__ tw,
                                                         const double* __restrict__ grams,
-                                                        double2* __restrict__ barH, double2* __restrict__ barS) {
+                                                        double2* __restrict__ barH, double2* __restrict__ barS,
+                                                        int half) {
   constexpr int EC = kChainEC, JC = kChainJC, TC = kChainTC, BC = kChainB;
   static_assert(BC * EC == 256 && JC * EC == 256, "one (slot, entry) and one (j, entry) pair per thread");
   __shared__ double Qs[TC][EC];
@@ -799,7 +837,7 @@ __global__ void __launch_bounds__(256) sep_chain_kernel(const LatDev* __restrict
       sr += w.x * as;
       si += w.y * as;
     }
-    const int64_t o = L.gen_off + (int64_t)(j0 + jj) * E + e;
+    const int64_t o = (half ? L.half_off : L.gen_off) + (int64_t)(j0 + jj) * E + e;   // L3 = 1: both layouts agree
     barH[o] = make_double2(hr, hi);
     barS[o] = make_double2(sr, si);
   }
@@ -1006,11 +1044,12 @@ void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tas
 }
 
 hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* gh, double2* bar_h, double2* bar_s,
-                              hipStream_t s) {
+                              hipStream_t s, bool half) {
+  const int hf = half ? 1 : 0;
   if (!p->sep_ok || (p->n_sep > 0 && !gh)) return hipErrorInvalidValue;
   if (p->n_sep_chain > 0)
     hipLaunchKernelGGL(sep_chain_kernel, dim3((unsigned)p->sep_chain_wgs), dim3(256), 0, s, p->d_lat,
-                       p->d_sep_chain, p->n_sep_chain, p->d_tw64, g64, bar_h, bar_s);
+                       p->d_sep_chain, p->n_sep_chain, p->d_tw64, g64, bar_h, bar_s, hf);
   if (p->n_sep == 0) return hipGetLastError();
   hipLaunchKernelGGL(gram_dft_kernel, dim3((unsigned)(p->gh_threads / 256)), dim3(256), 0, s, p->d_lat,
                      p->d_gh_items, p->n_gh_items, g64, p->d_tw64, gh);
@@ -1018,23 +1057,24 @@ hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* g
   const size_t shb = (size_t)p->sep_lds;
   if (p->sep_bmax <= 8)
     hipLaunchKernelGGL(sep_fused_kernel<8>, grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, p->d_tw64, g64,
-                       gh, bar_h, bar_s);
+                       gh, bar_h, bar_s, hf);
   else if (p->sep_bmax <= 16)
     hipLaunchKernelGGL(sep_fused_kernel<16>, grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, p->d_tw64, g64,
-                       gh, bar_h, bar_s);
+                       gh, bar_h, bar_s, hf);
   else
     hipLaunchKernelGGL(sep_fused_kernel<32>, grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, p->d_tw64, g64,
-                       gh, bar_h, bar_s);
+                       gh, bar_h, bar_s, hf);
   return hipGetLastError();
 }
 
 hipError_t launch_block_dft(const lhf_plan_s* p, int prec, const void* gen_h, const void* gen_s, void* bar_h,
-                            void* bar_s, void* tmp, float2* b32_h, float2* b32_s, hipStream_t s) {
+                            void* bar_s, void* tmp, float2* b32_h, float2* b32_s, hipStream_t s, bool half) {
+  if (half && b32_h) return hipErrorInvalidValue;   // no complex64 copy of the half layout
   if (prec == LHF_PREC_FP64)
     return dft_launch_all<double>(p, (const double*)gen_h, (const double*)gen_s, (double2*)bar_h, (double2*)bar_s,
-                                  (double2*)tmp, p->d_tw64, b32_h, b32_s, s);
+                                  (double2*)tmp, p->d_tw64, b32_h, b32_s, half, s);
   return dft_launch_all<float>(p, (const float*)gen_h, (const float*)gen_s, (float2*)bar_h, (float2*)bar_s,
-                               (float2*)tmp, p->d_tw32, nullptr, nullptr, s);
+                               (float2*)tmp, p->d_tw32, nullptr, nullptr, half, s);
 }
 
 }  // namespace lhf

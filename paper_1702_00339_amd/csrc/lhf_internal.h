@@ -51,6 +51,7 @@ struct LatDev {
   int64_t gen_off;            // elements of this lattice's generator / Fourier stack
   int64_t w_off;              // eigenvalue offset (nblk m0)
   int64_t blk_off;            // first global block index
+  int64_t half_off;           // elements of this lattice's stack in the half layout [L1][L2][L3/2+1][m0][m0]
   DimDev dim[3];
   int32_t lpow[kMaxM0][3];    // angular power per function and dimension
   double alpha[kMaxM0];

@@ -255,7 +255,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->prec = prec; p->gram = gram; p->nlat = nlat;
   p->lat.resize(nlat);
   std::string err;
-  int64_t fac = 0, grams = 0, part = 0, tw = 0, gen = 0, w = 0, blk = 0, gh = 0;
+  int64_t fac = 0, grams = 0, part = 0, tw = 0, gen = 0, w = 0, blk = 0, gh = 0, half = 0;
   for (int i = 0; i < nlat; ++i) {
     int32_t st = derive_lattice(lats[i], i, p->lat[i], err);
     if (st != LHF_OK) { set_error(err); delete p; return st; }
@@ -271,6 +271,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
       if (d > 0) { D.gh_off = gh; gh += (int64_t)L.T * D.L * L.m0 * L.m0; }
     }
     L.gen_off = gen; gen += (int64_t)L.nblk * L.m0 * L.m0;
+    L.half_off = half; half += (int64_t)L.L[0] * L.L[1] * (L.L[2] / 2 + 1) * L.m0 * L.m0;
     L.w_off = w; w += (int64_t)L.nblk * L.m0;
     L.blk_off = blk; blk += L.nblk;
   }
@@ -293,6 +294,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   p->sizes.nlat = nlat;
   p->sizes.nblocks = blk;
   p->sizes.gen_elems = gen;
+  p->sizes.half_elems = half;
   p->sizes.w_elems = w;
   p->sizes.grams_elems = grams;
   p->fac_doubles = fac;

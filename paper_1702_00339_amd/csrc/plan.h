@@ -111,15 +111,18 @@ hipError_t launch_combine(const lhf_plan_s* p, const double* g64, const float* g
 void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std::vector<DftTask>& tasks,
                     std::vector<DftLaunch>& launches, int64_t& tmp_elems, std::vector<FusedTask>& fused,
                     int64_t& fused_wgs, int32_t& fused_bmax, int32_t& fused_lds);
-// b32_h, b32_s (FP64 transforms only, may be NULL): complex64 copies of the blocks
+// b32_h, b32_s (FP64 transforms only, may be NULL): complex64 copies of the blocks;
+// half: write only the Hermitian half-space along k3, layout [L1][L2][L3/2+1][m0][m0]
+// at LatDev::half_off (no complex64 copies then)
 hipError_t launch_block_dft(const lhf_plan_s* p, int prec, const void* gen_h, const void* gen_s,
-                            void* bar_h, void* bar_s, void* tmp, float2* b32_h, float2* b32_s, hipStream_t s);
+                            void* bar_h, void* bar_s, void* tmp, float2* b32_h, float2* b32_s, hipStream_t s,
+                            bool half = false);
 // blockdft.hip: separable Fourier blocks from the FP64 Grams (complex128 out)
 void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tasks, std::vector<GhItem>& items,
                     int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, std::vector<FusedTask>& chain,
                     int64_t& chain_wgs, bool& ok);
 hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* gh, double2* bar_h, double2* bar_s,
-                              hipStream_t s);
+                              hipStream_t s, bool half = false);
 // eigvec.hip: full-lattice eigenvectors of selected (block, column) pairs of one lattice
 hipError_t launch_eigvecs(const lhf_plan_s* p, int li, const double2* V, int nsel, const int32_t* sel, double2* U,
                           hipStream_t s);

@@ -39,7 +39,8 @@ class lhf_lattice(C.Structure):
 
 class lhf_sizes(C.Structure):
     _fields_ = [("nlat", C.c_int64), ("nblocks", C.c_int64), ("gen_elems", C.c_int64),
-                ("w_elems", C.c_int64), ("grams_elems", C.c_int64), ("ws_bytes", C.c_size_t)]
+                ("w_elems", C.c_int64), ("grams_elems", C.c_int64), ("ws_bytes", C.c_size_t),
+                ("half_elems", C.c_int64)]
 
 
 class lhf_step_args(C.Structure):
@@ -98,8 +99,10 @@ def load(path: str = LIB_PATH):
         "lhf_plan_destroy": (i32, [vp]),
         "lhf_assemble_blocks": (i32, [vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "lhf_block_fft": (i32, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),
+        "lhf_block_fft_half": (i32, [vp, i32, vp, vp, vp, vp, vp, sz, vp]),
         "lhf_block_fft_dual": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "lhf_fourier_blocks": (i32, [vp, vp, vp, vp, vp, sz, vp]),
+        "lhf_fourier_blocks_half": (i32, [vp, vp, vp, vp, vp, sz, vp]),
         "lhf_fourier_blocks_noalloc": (i32, [vp, vp, vp, vp, vp]),
         "lhf_heev_batched": (i32, [vp, u32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "lhf_eigvecs_lattice": (i32, [vp, i32, vp, i32, vp, vp, vp]),
@@ -138,7 +141,8 @@ def load(path: str = LIB_PATH):
 def exported_symbols():
     """Names the binding expects the library to export."""
     return ["lhf_plan_create", "lhf_plan_sizes", "lhf_plan_band", "lhf_workspace_size", "lhf_plan_destroy",
-            "lhf_assemble_blocks", "lhf_block_fft", "lhf_block_fft_dual", "lhf_fourier_blocks",
+            "lhf_assemble_blocks", "lhf_block_fft", "lhf_block_fft_half", "lhf_block_fft_dual", "lhf_fourier_blocks",
+            "lhf_fourier_blocks_half",
             "lhf_fourier_blocks_noalloc", "lhf_heev_batched", "lhf_eigvecs_lattice", "lhf_step", "lhf_graph_create",
             "lhf_graph_launch", "lhf_graph_destroy", "lhf_plan_get_tuning", "lhf_plan_set_tuning",
             "lhf_plan_autotune", "lhf_toeplitz_create", "lhf_box_exact_create", "lhf_toeplitz3_create",
@@ -255,6 +259,10 @@ class Plan:
         _check(load().lhf_block_fft(self.handle, prec, _ptr(H_gen), _ptr(S_gen), _ptr(H_bar), _ptr(S_bar),
                                     _ptr(ws), ws.numel(), _stream()))
 
+    def lhf_block_fft_half(self, prec, H_gen, S_gen, H_half, S_half, ws):
+        _check(load().lhf_block_fft_half(self.handle, prec, _ptr(H_gen), _ptr(S_gen), _ptr(H_half), _ptr(S_half),
+                                         _ptr(ws), ws.numel(), _stream()))
+
     def lhf_block_fft_dual(self, H_gen64, S_gen64, H_bar64, S_bar64, H_bar32, S_bar32, ws):
         _check(load().lhf_block_fft_dual(self.handle, _ptr(H_gen64), _ptr(S_gen64), _ptr(H_bar64), _ptr(S_bar64),
                                          _ptr(H_bar32), _ptr(S_bar32), _ptr(ws), ws.numel(), _stream()))
@@ -262,6 +270,10 @@ class Plan:
     def lhf_fourier_blocks(self, grams64, H_bar64, S_bar64, ws):
         _check(load().lhf_fourier_blocks(self.handle, _ptr(grams64), _ptr(H_bar64), _ptr(S_bar64), _ptr(ws),
                                          ws.numel(), _stream()))
+
+    def lhf_fourier_blocks_half(self, grams64, H_half64, S_half64, ws):
+        _check(load().lhf_fourier_blocks_half(self.handle, _ptr(grams64), _ptr(H_half64), _ptr(S_half64),
+                                              _ptr(ws), ws.numel(), _stream()))
 
     def lhf_fourier_blocks_noalloc(self, grams64, H_bar64, S_bar64):
         _check(load().lhf_fourier_blocks_noalloc(self.handle, _ptr(grams64), _ptr(H_bar64), _ptr(S_bar64),
