@@ -436,6 +436,12 @@ def bench_c5(torch, np, lhf, steps):
         ms = event_ms(lambda: op.lhf_toeplitz_matvec(prec, x, yH, yS, mws), steps, torch)
         nbytes = 3 * N * ncols * 8 + 2 * P * m0 * m0 * csz + 2 * nent * m0 * m0 * 8
         mv[name] = {"avg_launch_ms": ms, "bytes": nbytes, "GB/s": nbytes / (ms * 1e-3) / 1e9}
+    # the FP32 route with FP32 vectors (lhf_toeplitz_matvec_f32): x and y in 4 bytes
+    x32 = x.float()
+    yH32, yS32 = torch.empty_like(x32), torch.empty_like(x32)
+    ms = event_ms(lambda: op.lhf_toeplitz_matvec_f32(x32, yH32, yS32, mws), steps, torch)
+    nbytes = 3 * N * ncols * 4 + 2 * P * m0 * m0 * 8 + 2 * nent * m0 * m0 * 8
+    mv["fp32_io"] = {"avg_launch_ms": ms, "bytes": nbytes, "GB/s": nbytes / (ms * 1e-3) / 1e9}
     return {"workload": "c5: Dirichlet 512x1x1 chain, m0=16, n=4096x256x256, R=30, 26 defect cells",
             "metric": "time to the 32 lowest eigenpairs", "create_ms": t_create * 1e3, "eigs_ms": t_eigs * 1e3,
             "unit": "ms", "lobpcg_iterations": it, "residual": res, "max_abs_eig_err_ha": err,

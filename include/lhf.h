@@ -447,6 +447,15 @@ size_t lhf_toeplitz_matvec_workspace(lhf_toeplitz_t tp, int32_t ncols);
  * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE. */
 int32_t lhf_toeplitz_matvec(lhf_toeplitz_t tp, int32_t prec, int32_t ncols, const double* x, double* y_H,
                             double* y_S, int32_t ld, void* d_ws, size_t ws_bytes, lhf_stream_t stream);
+/* lhf_toeplitz_matvec of the FP32 route with FP32 input and output: the
+ * Toeplitz part through the complex64 circulant embedding (Remark 3.2) and the
+ * cross corrections accumulated in FP64 registers, x, y_H, y_S device FP32
+ * [N][ld] (half the vector bytes of the FP64-interface call); the same
+ * workspace as lhf_toeplitz_matvec.  y_S may be NULL.
+ * Errors: LHF_ERR_INVALID, LHF_ERR_WORKSPACE, LHF_ERR_UNSUPPORTED (a
+ * three-level operator: FP64 input only). */
+int32_t lhf_toeplitz_matvec_f32(lhf_toeplitz_t tp, int32_t ncols, const float* x, float* y_H, float* y_S,
+                                int32_t ld, void* d_ws, size_t ws_bytes, lhf_stream_t stream);
 /* Workspace bytes of lhf_toeplitz_eigs for nev wanted eigenpairs. */
 size_t lhf_toeplitz_eigs_workspace(lhf_toeplitz_t tp, int32_t nev);
 /* The nev lowest eigenpairs of (H_model, S_model) by block LOBPCG (Knyazev)

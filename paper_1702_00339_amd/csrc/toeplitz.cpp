@@ -629,6 +629,25 @@ int32_t lhf_toeplitz_matvec(lhf_toeplitz_t t, int32_t prec, int32_t ncols, const
   return hip_status(e, "lhf_toeplitz_matvec");
 }
 
+int32_t lhf_toeplitz_matvec_f32(lhf_toeplitz_t t, int32_t ncols, const float* x, float* yH, float* yS, int32_t ld,
+                                void* ws, size_t ws_bytes, lhf_stream_t stream) {
+  if (!t) { set_error("NULL operator"); return LHF_ERR_INVALID; }
+  if (t->three) { set_error("FP32 input and output: one-level and exact box operators only"); return LHF_ERR_UNSUPPORTED; }
+  if (ncols < 1 || ncols > kMaxCols || ld < ncols) { set_error("need 1 <= ncols <= 128 and ld >= ncols"); return LHF_ERR_INVALID; }
+  if (!x || !yH) { set_error("x and y_H are required"); return LHF_ERR_INVALID; }
+  const size_t need = lhf_toeplitz_matvec_workspace(t, ncols);
+  if (!ws || ws_bytes < need) {
+    set_error("workspace of " + std::to_string(ws_bytes) + " bytes given, " + std::to_string(need) + " needed");
+    return LHF_ERR_WORKSPACE;
+  }
+  char* w = static_cast<char*>(ws);
+  const size_t part = (size_t)t->P * t->m0 * ncols * sizeof(double2);
+  hipError_t e = toep_launch_apply32(t->L, t->m0, t->P, ncols, x, ld, t->d_cH32, yS ? t->d_cS32 : nullptr, t->d_tw32,
+                                     w, w + part, w + 2 * part, yH, yS, t->d_row_ptr, t->d_row_cell, t->nrows,
+                                     t->d_ent, t->d_dH, t->d_dS, static_cast<hipStream_t>(stream), t->exact);
+  return hip_status(e, "lhf_toeplitz_matvec_f32");
+}
+
 }  // extern "C"
 
 namespace {

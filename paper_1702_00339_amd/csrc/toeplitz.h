@@ -88,6 +88,12 @@ hipError_t toep_launch_apply(int prec, int L, int m0, int P, int ncols, const do
                              void* yhatS, double* yH, double* yS, const int32_t* row_ptr, const int32_t* row_cell,
                              int nrows, const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s,
                              bool exact = false);
+// the same with FP32 x and y: complex64 transform, crosses accumulated in FP64
+hipError_t toep_launch_apply32(int L, int m0, int P, int ncols, const float* x, int ld, const void* opH,
+                               const void* opS, const void* tw, void* xhat, void* yhatH, void* yhatS, float* yH,
+                               float* yS, const int32_t* row_ptr, const int32_t* row_cell, int nrows,
+                               const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s,
+                               bool exact = false);
 
 // dense FP64 kernels (lobpcg.hip); row-major [N][ld] blocks of vectors
 hipError_t dense_gram(int N, int k1, int k2, const double* A, int lda, const double* B, int ldb, double* part,

@@ -390,10 +390,10 @@ __device__ void fft_lds(C* a, int P, int bits, int CB, const C* __restrict__ tw)
 }
 
 // Forward transform over the cell index of columns c = mu ncols + j of x
-// (FP64 [N][ld]) zero-padded to P; output xhat[f][mu][j].
-template <typename R>
+// ([N][ld], FP64 or FP32 entries IO) zero-padded to P; output xhat[f][mu][j].
+template <typename R, typename IO>
 __global__ void __launch_bounds__(256) fft_fwd_kernel(int L, int m0, int P, int bits, int ncols, int CB,
-                                                      const double* __restrict__ x, int ld,
+                                                      const IO* __restrict__ x, int ld,
                                                       const typename Cx<R>::T* __restrict__ tw,
                                                       typename Cx<R>::T* __restrict__ xhat) {
   typedef typename Cx<R>::T C;
@@ -455,20 +455,20 @@ __global__ void __launch_bounds__(256) freq_mul_kernel(int m0, int ncols, const 
 }
 
 // Inverse transform of yhat[f][mu][j] and the first L blocks, real part / P,
-// into y (FP64 [N][ld]); grid y selects the operator.
-template <typename R>
+// into y ([N][ld], entries IO); grid y selects the operator.
+template <typename R, typename IO>
 __global__ void __launch_bounds__(256) fft_inv_kernel(int L, int m0, int P, int bits, int ncols, int CB,
                                                       const typename Cx<R>::T* __restrict__ tw,
                                                       const typename Cx<R>::T* __restrict__ yhH,
                                                       const typename Cx<R>::T* __restrict__ yhS,
-                                                      double* __restrict__ yH, double* __restrict__ yS, int ld) {
+                                                      IO* __restrict__ yH, IO* __restrict__ yS, int ld) {
   typedef typename Cx<R>::T C;
   extern __shared__ char lraw[];
   C* a = reinterpret_cast<C*>(lraw);
   const int ncol = m0 * ncols;
   const int c0 = blockIdx.x * CB;
   const C* src = blockIdx.y == 0 ? yhH : yhS;
-  double* y = blockIdx.y == 0 ? yH : yS;
+  IO* y = blockIdx.y == 0 ? yH : yS;
   for (int e = threadIdx.x; e < CB * P; e += 256) {
     const int cc = e / P, f = e % P, c = c0 + cc;
     C v;
@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(256) fft_inv_kernel(int L, int m0, int P, int 
     const int cc = e / L, k = e % L, c = c0 + cc;
     if (c < ncol) {
       const int mu = c / ncols, j = c % ncols;
-      y[((int64_t)k * m0 + mu) * ld + j] = (double)a[cc * P + k].x * inv;
+      y[((int64_t)k * m0 + mu) * ld + j] = (IO)((double)a[cc * P + k].x * inv);
     }
   }
 }
@@ -498,20 +498,20 @@ constexpr int kCrossAcc = kMaxM0 / kCrossMG;   // rows per thread
 // the sum (the block-sparse product of the exact box operator).  Per entry
 // the workgroup stages D_q (m0 x m0) and the chunk's columns of the m0 rows of
 // block m_q of x in LDS; thread (j, g) accumulates rows g, g + 8, ... of
-// column j over the entries in order.
-template <bool SET>
-__global__ void __launch_bounds__(256) cross_apply_kernel(int m0, int ncols, const double* __restrict__ x, int ld,
+// column j over the entries in order, in FP64 for either I/O type IO.
+template <bool SET, typename IO>
+__global__ void __launch_bounds__(256) cross_apply_kernel(int m0, int ncols, const IO* __restrict__ x, int ld,
                                                           const int32_t* __restrict__ row_ptr,
                                                           const int32_t* __restrict__ row_cell,
                                                           const CrossEntry* __restrict__ ent,
                                                           const double* __restrict__ dH,
-                                                          const double* __restrict__ dS, double* __restrict__ yH,
-                                                          double* __restrict__ yS) {
+                                                          const double* __restrict__ dS, IO* __restrict__ yH,
+                                                          IO* __restrict__ yS) {
   __shared__ double xs[kMaxM0][kCrossJ];
   __shared__ double ds[kMaxM0][kMaxM0 + 1];
   const int r = blockIdx.x, k = row_cell[r], j0 = blockIdx.y * kCrossJ;
   const double* Dm = blockIdx.z == 0 ? dH : dS;
-  double* y = blockIdx.z == 0 ? yH : yS;
+  IO* y = blockIdx.z == 0 ? yH : yS;
   const int jl = threadIdx.x % kCrossJ, g = threadIdx.x / kCrossJ, j = j0 + jl;
   const int mm = m0 * m0;
   double acc[kCrossAcc];
@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(256) cross_apply_kernel(int m0, int ncols, con
     for (int e = threadIdx.x; e < mm; e += 256) ds[e / m0][e % m0] = d[e];
     for (int e = threadIdx.x; e < m0 * kCrossJ; e += 256) {
       const int nu = e / kCrossJ, jj = e % kCrossJ;
-      xs[nu][jj] = j0 + jj < ncols ? x[((int64_t)m * m0 + nu) * ld + j0 + jj] : 0.0;
+      xs[nu][jj] = j0 + jj < ncols ? (double)x[((int64_t)m * m0 + nu) * ld + j0 + jj] : 0.0;
     }
     __syncthreads();
     for (int nu = 0; nu < m0; ++nu) {
@@ -541,16 +541,16 @@ __global__ void __launch_bounds__(256) cross_apply_kernel(int m0, int ncols, con
     for (int t = 0; t < kCrossAcc; ++t) {
       const int mu = g + kCrossMG * t;
       if (mu < m0) {
-        double* yp = y + ((int64_t)k * m0 + mu) * ld + j;
-        *yp = SET ? acc[t] : *yp + acc[t];
+        IO* yp = y + ((int64_t)k * m0 + mu) * ld + j;
+        *yp = (IO)(SET ? acc[t] : (double)*yp + acc[t]);
       }
     }
   }
 }
 
-template <typename R>
-hipError_t apply_t(int L, int m0, int P, int ncols, const double* x, int ld, const void* opH, const void* opS,
-                   const void* tw, void* xhat, void* yhH, void* yhS, double* yH, double* yS, hipStream_t s) {
+template <typename R, typename IO>
+hipError_t apply_t(int L, int m0, int P, int ncols, const IO* x, int ld, const void* opH, const void* opS,
+                   const void* tw, void* xhat, void* yhH, void* yhS, IO* yH, IO* yS, hipStream_t s) {
   typedef typename Cx<R>::T C;
   int bits = 0;
   while ((1 << bits) < P) ++bits;
@@ -559,13 +559,13 @@ hipError_t apply_t(int L, int m0, int P, int ncols, const double* x, int ld, con
   const unsigned gx = (unsigned)((ncol + CB - 1) / CB);
   const size_t lds = (size_t)CB * P * sizeof(C);
   const int nops = opS ? 2 : 1;
-  hipLaunchKernelGGL((fft_fwd_kernel<R>), dim3(gx), dim3(256), lds, s, L, m0, P, bits, ncols, CB, x, ld,
+  hipLaunchKernelGGL((fft_fwd_kernel<R, IO>), dim3(gx), dim3(256), lds, s, L, m0, P, bits, ncols, CB, x, ld,
                      (const C*)tw, (C*)xhat);
   const size_t lm = sizeof(C) * ((size_t)m0 * m0 + (size_t)m0 * ncols);
   (void)hipFuncSetAttribute((const void*)freq_mul_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lm);
   hipLaunchKernelGGL((freq_mul_kernel<R>), dim3(P, nops), dim3(256), lm, s, m0, ncols, (const C*)opH,
                      (const C*)opS, (const C*)xhat, (C*)yhH, (C*)yhS);
-  hipLaunchKernelGGL((fft_inv_kernel<R>), dim3(gx, nops), dim3(256), lds, s, L, m0, P, bits, ncols, CB,
+  hipLaunchKernelGGL((fft_inv_kernel<R, IO>), dim3(gx, nops), dim3(256), lds, s, L, m0, P, bits, ncols, CB,
                      (const C*)tw, (const C*)yhH, (const C*)yhS, yH, yS, ld);
   return hipGetLastError();
 }
@@ -630,23 +630,41 @@ hipError_t toep_launch_to32(const double2* src, float2* dst, int64_t n, hipStrea
   return hipGetLastError();
 }
 
+template <typename IO>
+static hipError_t launch_apply_io(int prec, int L, int m0, int P, int ncols, const IO* x, int ld, const void* opH,
+                                  const void* opS, const void* tw, void* xhat, void* yhatH, void* yhatS, IO* yH,
+                                  IO* yS, const int32_t* row_ptr, const int32_t* row_cell, int nrows,
+                                  const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s,
+                                  bool exact) {
+  const dim3 grid(nrows, (ncols + kCrossJ - 1) / kCrossJ, (exact ? yS : opS) ? 2 : 1);
+  if (exact) {
+    hipLaunchKernelGGL((cross_apply_kernel<true, IO>), grid, dim3(256), 0, s, m0, ncols, x, ld, row_ptr, row_cell,
+                       ent, dH, dS, yH, yS);
+    return hipGetLastError();
+  }
+  hipError_t e = prec == LHF_PREC_FP64
+                     ? apply_t<double, IO>(L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS, s)
+                     : apply_t<float, IO>(L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS, s);
+  if (e != hipSuccess || nrows == 0) return e;
+  hipLaunchKernelGGL((cross_apply_kernel<false, IO>), grid, dim3(256), 0, s, m0, ncols, x, ld, row_ptr, row_cell,
+                     ent, dH, dS, yH, yS);
+  return hipGetLastError();
+}
+
 hipError_t toep_launch_apply(int prec, int L, int m0, int P, int ncols, const double* x, int ld, const void* opH,
                              const void* opS, const void* tw, void* xhat, void* yhatH, void* yhatS, double* yH,
                              double* yS, const int32_t* row_ptr, const int32_t* row_cell, int nrows,
                              const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s, bool exact) {
-  const dim3 grid(nrows, (ncols + kCrossJ - 1) / kCrossJ, (exact ? yS : opS) ? 2 : 1);
-  if (exact) {
-    hipLaunchKernelGGL(cross_apply_kernel<true>, grid, dim3(256), 0, s, m0, ncols, x, ld, row_ptr, row_cell, ent, dH,
-                       dS, yH, yS);
-    return hipGetLastError();
-  }
-  hipError_t e = prec == LHF_PREC_FP64
-                     ? apply_t<double>(L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS, s)
-                     : apply_t<float>(L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS, s);
-  if (e != hipSuccess || nrows == 0) return e;
-  hipLaunchKernelGGL(cross_apply_kernel<false>, grid, dim3(256), 0, s, m0, ncols, x, ld, row_ptr, row_cell, ent, dH,
-                     dS, yH, yS);
-  return hipGetLastError();
+  return launch_apply_io<double>(prec, L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS, row_ptr,
+                                 row_cell, nrows, ent, dH, dS, s, exact);
+}
+
+hipError_t toep_launch_apply32(int L, int m0, int P, int ncols, const float* x, int ld, const void* opH,
+                               const void* opS, const void* tw, void* xhat, void* yhatH, void* yhatS, float* yH,
+                               float* yS, const int32_t* row_ptr, const int32_t* row_cell, int nrows,
+                               const CrossEntry* ent, const double* dH, const double* dS, hipStream_t s, bool exact) {
+  return launch_apply_io<float>(LHF_PREC_MIXED, L, m0, P, ncols, x, ld, opH, opS, tw, xhat, yhatH, yhatS, yH, yS,
+                                row_ptr, row_cell, nrows, ent, dH, dS, s, exact);
 }
 
 }  // namespace lhf

@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH):
         "lhf_toeplitz_blocks": (i32, [vp, vp, vp, vp, vp, vp]),
         "lhf_toeplitz_matvec_workspace": (sz, [vp, i32]),
         "lhf_toeplitz_matvec": (i32, [vp, i32, i32, vp, vp, vp, i32, vp, sz, vp]),
+        "lhf_toeplitz_matvec_f32": (i32, [vp, i32, vp, vp, vp, i32, vp, sz, vp]),
         "lhf_toeplitz_eigs_workspace": (sz, [vp, i32]),
         "lhf_toeplitz_eigs": (i32, [vp, i32, i32, C.c_double, C.c_uint64, vp, vp, C.POINTER(i32),
                                     C.POINTER(C.c_double), vp, sz, vp]),
@@ -147,7 +148,8 @@ def exported_symbols():
             "lhf_graph_launch", "lhf_graph_destroy", "lhf_plan_get_tuning", "lhf_plan_set_tuning",
             "lhf_plan_autotune", "lhf_toeplitz_create", "lhf_box_exact_create", "lhf_toeplitz3_create",
             "lhf_toeplitz3_generators", "lhf_toeplitz_get_info", "lhf_toeplitz_blocks",
-            "lhf_toeplitz_matvec_workspace", "lhf_toeplitz_matvec", "lhf_toeplitz_eigs_workspace",
+            "lhf_toeplitz_matvec_workspace", "lhf_toeplitz_matvec", "lhf_toeplitz_matvec_f32",
+            "lhf_toeplitz_eigs_workspace",
             "lhf_toeplitz_eigs", "lhf_toeplitz_destroy", "lhf_dense_syev",
             "lhf_status_string", "lhf_last_error", "lhf_version"]
 
@@ -400,6 +402,11 @@ class Toeplitz:
         ncols = x.shape[1]
         _check(load().lhf_toeplitz_matvec(self.handle, prec, ncols, _ptr(x), _ptr(y_H), _ptr(y_S), x.stride(0),
                                           _ptr(ws), ws.numel(), _stream()))
+
+    def lhf_toeplitz_matvec_f32(self, x, y_H, y_S, ws):
+        ncols = x.shape[1]
+        _check(load().lhf_toeplitz_matvec_f32(self.handle, ncols, _ptr(x), _ptr(y_H), _ptr(y_S), x.stride(0),
+                                              _ptr(ws), ws.numel(), _stream()))
 
     def eigs_workspace(self, nev, device="cuda"):
         import torch

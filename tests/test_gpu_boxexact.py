@@ -100,6 +100,31 @@ def test_exact_matvec_matches_dense(small, ncols, ld):
     assert np.abs(YH[:, :ncols].cpu().numpy() - yH_ref).max() <= 1e-12 * np.abs(yH_ref).max()
 
 
+@pytest.mark.parametrize("ncols,ld", [(7, 7), (40, 41)])
+def test_exact_matvec_f32_interface(small, ncols, ld):
+    """lhf_toeplitz_matvec_f32 on the exact box operator (block-sparse
+    product, FP64 accumulation, FP32 input and output): against the dense
+    operator on the FP32-rounded input within FP32 output rounding."""
+    inst, _, _, H, S = small
+    op = lhf.Toeplitz(inst, exact=True)
+    N = H.shape[0]
+    rng = np.random.Generator(np.random.PCG64(ncols + 300))
+    x32 = rng.standard_normal((N, ncols)).astype(np.float32)
+    X = torch.zeros((N, ld), dtype=torch.float32, device="cuda")
+    X[:, :ncols] = torch.from_numpy(x32)
+    ws = op.matvec_workspace(ncols)
+    YH = torch.full((N, ld), float("nan"), dtype=torch.float32, device="cuda")
+    YS = torch.full((N, ld), float("nan"), dtype=torch.float32, device="cuda")
+    op.lhf_toeplitz_matvec_f32(X[:, :ncols], YH[:, :ncols], YS[:, :ncols], ws)
+    torch.cuda.synchronize()
+    x = x32.astype(np.float64)
+    yH_ref, yS_ref = H @ x, S @ x
+    assert np.abs(YH[:, :ncols].double().cpu().numpy() - yH_ref).max() <= 1e-6 * np.abs(yH_ref).max()
+    assert np.abs(YS[:, :ncols].double().cpu().numpy() - yS_ref).max() <= 1e-6 * np.abs(yS_ref).max()
+    if ld > ncols:
+        assert torch.isnan(YH[:, ncols:]).all()
+
+
 def test_exact_eigs_small_matches_lapack(small):
     inst, _, _, H, S = small
     op = lhf.Toeplitz(inst, exact=True)

@@ -110,6 +110,44 @@ def test_matvec_matches_dense(small, ncols, ld):
     assert np.abs(YH[:, :ncols].cpu().numpy() - yH_ref).max() <= 1e-12 * np.abs(yH_ref).max()
 
 
+@pytest.mark.parametrize("ncols,ld", [(7, 7), (5, 9)])
+def test_matvec_f32_interface_matches_dense(small, ncols, ld):
+    """lhf_toeplitz_matvec_f32: FP32 x and y, the FP32 route's arithmetic.
+    Against the dense model on the FP32-rounded input within the FP32 route's
+    2e-5, and against the FP64-interface FP32 route on the same input within
+    FP32 output rounding (1e-6 relative)."""
+    inst, model, _, _, H, S = small
+    op = lhf.Toeplitz(inst)
+    N = H.shape[0]
+    rng = np.random.Generator(np.random.PCG64(100 + ncols))
+    x32 = rng.standard_normal((N, ncols)).astype(np.float32)
+    x = x32.astype(np.float64)
+    X = torch.zeros((N, ld), dtype=torch.float32, device="cuda")
+    X[:, :ncols] = torch.from_numpy(x32)
+    ws = op.matvec_workspace(ncols)
+    YH = torch.full((N, ld), float("nan"), dtype=torch.float32, device="cuda")
+    YS = torch.full((N, ld), float("nan"), dtype=torch.float32, device="cuda")
+    op.lhf_toeplitz_matvec_f32(X[:, :ncols], YH[:, :ncols], YS[:, :ncols], ws)
+    X64 = torch.from_numpy(x).cuda()
+    RH = torch.empty((N, ncols), dtype=torch.float64, device="cuda")
+    RS = torch.empty_like(RH)
+    op.lhf_toeplitz_matvec(lhf.LHF_PREC_MIXED, X64, RH, RS, ws)
+    torch.cuda.synchronize()
+    yH_ref, yS_ref = H @ x, S @ x
+    yh, ys = YH[:, :ncols].double().cpu().numpy(), YS[:, :ncols].double().cpu().numpy()
+    assert np.abs(yh - yH_ref).max() <= 2e-5 * np.abs(yH_ref).max()
+    assert np.abs(ys - yS_ref).max() <= 2e-5 * np.abs(yS_ref).max()
+    assert np.abs(yh - RH.cpu().numpy()).max() <= 1e-6 * np.abs(yH_ref).max()
+    assert np.abs(ys - RS.cpu().numpy()).max() <= 1e-6 * np.abs(yS_ref).max()
+    if ld > ncols:
+        assert torch.isnan(YH[:, ncols:]).all() and torch.isnan(YS[:, ncols:]).all()
+    # H only (x and y share the leading dimension ld)
+    YH2 = torch.empty((N, ld), dtype=torch.float32, device="cuda")
+    op.lhf_toeplitz_matvec_f32(X[:, :ncols], YH2[:, :ncols], None, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(YH2[:, :ncols], YH[:, :ncols])
+
+
 def test_eigs_small_matches_lapack(small):
     inst, model, _, _, H, S = small
     op = lhf.Toeplitz(inst)

@@ -91,6 +91,16 @@ def test_matvec_matches_dense(L, ncols, ld):
             assert torch.isnan(YH[:, ncols:]).all()
 
 
+def test_matvec_f32_interface_refused():
+    """The FP32-interface matvec takes one-level and exact box operators only."""
+    op = lhf.Toeplitz(_box(CASES[0]), levels=3)
+    N = op.info.N
+    X = torch.zeros((N, 2), dtype=torch.float32, device="cuda")
+    Y = torch.zeros_like(X)
+    with pytest.raises(lhf.LhfError):
+        op.lhf_toeplitz_matvec_f32(X, Y, None, op.matvec_workspace(2))
+
+
 def test_eigs_match_lapack():
     # wide enough exponents that neighbouring cells couple: the lowest band
     # spreads over 1.3 Ha with a 0.06 Ha gap after the 12th eigenvalue (a
