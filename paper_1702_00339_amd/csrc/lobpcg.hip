@@ -6,6 +6,7 @@
 // over N are split into fixed chunks whose partial results are added in chunk
 // order, so every result is deterministic.
 #include <algorithm>
+#include <type_traits>
 
 #include "toeplitz.h"
 
@@ -241,118 +242,146 @@ __global__ void __launch_bounds__(256) copy_cols_kernel(int N, int k, const doub
   B[(e / k) * ldb + e % k] = A[(e / k) * lda + e % k];
 }
 
-__global__ void __launch_bounds__(256) scale_sym_kernel(int m, const double* __restrict__ G, int ldg,
-                                                        double* __restrict__ Gs, int lds, double* __restrict__ d) {
-  __shared__ double dv[kMaxSmall];
-  for (int i = threadIdx.x; i < m; i += 256) {
-    const double g = G[i * ldg + i];
-    dv[i] = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
-    d[i] = dv[i];
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < m * m; e += 256) {
-    const int i = e / m, j = e % m;
-    Gs[i * lds + j] = 0.5 * (G[i * ldg + j] + G[j * ldg + i]) * dv[i] * dv[j];
-  }
+constexpr int kCholThreads = 1024;
+constexpr int kCholCols = 128;                                 // column slots (> m: the rest stay zero)
+constexpr int kCholRG = kCholThreads / kCholCols;              // row groups
+constexpr int kCholW = (kMaxSmall + kCholRG - 1) / kCholRG;    // rows per thread
+static_assert(kCholCols >= kMaxSmall && kCholW * kCholRG >= kMaxSmall, "one slot per column and row");
+static_assert(kCholW == 14, "the dispatch below names every block count");
+
+// 1 / x for a normal x to within a few ulps: the hardware estimate refined by
+// two Newton steps.
+__device__ __forceinline__ double chol_recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
 }
 
-constexpr int kCholThreads = 1024;   // 8 row groups x 128 columns
-constexpr int kCholCols = 128;
-constexpr int kCholB = 4;           // rows per batch of a thread
-static_assert(kMaxSmall <= kCholCols, "one column per lane of a row group");
+template <int N>
+using CholIC = std::integral_constant<int, N>;
+// F(CholIC<J>{}) for a block count 1 <= J <= kCholW known only at run time
+#define CHOL_DISPATCH(J, F)                                                                                   \
+  switch (J) {                                                                                                \
+    case 1: F(CholIC<1>{}); break;   case 2: F(CholIC<2>{}); break;   case 3: F(CholIC<3>{}); break;          \
+    case 4: F(CholIC<4>{}); break;   case 5: F(CholIC<5>{}); break;   case 6: F(CholIC<6>{}); break;          \
+    case 7: F(CholIC<7>{}); break;   case 8: F(CholIC<8>{}); break;   case 9: F(CholIC<9>{}); break;          \
+    case 10: F(CholIC<10>{}); break; case 11: F(CholIC<11>{}); break; case 12: F(CholIC<12>{}); break;        \
+    case 13: F(CholIC<13>{}); break; case 14: F(CholIC<14>{}); break; default: break;                         \
+  }
 
-// S-orthonormalisation by Cholesky-QR with deflation, one workgroup.  Gs is
-// the scaled Gram matrix D G D (unit diagonal) of the basis columns in the
-// order [X W P].  Gaussian elimination of [Gs | I] by rows yields the unit
-// lower triangular L^-1 =: E and the pivots p_j (Schur complements: the
-// squared S-distance of scaled column j from the span of the kept columns
-// before it), with E Gs E^T = diag(p).  A column whose pivot is at most
-// `drop` is not used to eliminate and gets no output column, so the kept
-// set K satisfies E_KK Gs_KK E_KK^T = diag(p_K).  Output: the kk kept columns
-// of T = D E^T diag(p)^-1/2 (m x kk, upper triangular in the kept indices;
+// S-orthonormalisation by Cholesky-QR with deflation, one workgroup.  The
+// Gram matrix G of the basis columns in the order [X W P] is scaled on load,
+// Gs = D (G + G^T) / 2 D with D = diag(G)^-1/2 (unit diagonal).  Gaussian
+// elimination of [Gs | I] by rows yields the unit lower triangular L^-1 =: E
+// and the pivots p_j (Schur complements: the squared S-distance of scaled
+// column j from the span of the kept columns before it), with
+// E Gs E^T = diag(p).  A column whose pivot is at most `drop` is not used to
+// eliminate and gets no output column, so the kept set K satisfies
+// E_KK Gs_KK E_KK^T = diag(p_K).  Output: the kk kept columns of
+// T = D E^T diag(p)^-1/2 (m x kk, upper triangular in the kept indices;
 // T^T G T = I), and kk in *kk_out (as a double).
 //
-// E and the eliminated Gs share one m x m array in LDS: before step j, row
-// i > j holds E[i][c] in slots c < j and the partially eliminated Gs in
-// slots c >= j.  Step j reads row j and a snapshot of column j (written by
-// the previous step into a double-buffered vector), so one barrier per step.
-__global__ void __launch_bounds__(kCholThreads) cholqr_t_kernel(int m, const double* __restrict__ Gs, int ldg,
-                                                                const double* __restrict__ d, double drop,
-                                                                double* __restrict__ T, int ldt,
-                                                                double* __restrict__ kk_out) {
-  extern __shared__ double a[];   // m x m, row stride m
-  __shared__ double colv[2][kMaxSmall], rs[kMaxSmall];
-  __shared__ int src[kMaxSmall];
-  __shared__ int nkeep;
-  const int tid = threadIdx.x, c = tid % kCholCols, rg = tid / kCholCols;
-  constexpr int kRG = kCholThreads / kCholCols;
-  for (int e = tid; e < m * m; e += kCholThreads) {
-    const int i = e / m, k = e - i * m;
-    a[e] = Gs[i * ldg + k];
-    if (k == 0) colv[0][i] = a[e];
+// E and the eliminated Gs share one m x m array, in registers: lane c of row
+// group g holds column c at the rows of reversed index idx = m - 1 - i =
+// g + kCholRG k; before step j, row i > j holds E[i][c] in columns c < j and
+// the partially eliminated Gs in columns c >= j.  Step j reads row j and
+// column j (zero at the rows up to j) from double-buffered LDS vectors, updates
+// its rows after j (the first J = ceil((m - 1 - j) / kCholRG) of its register
+// rows: the steps run in phases of equal J compiled for that J) and publishes
+// row and column j + 1; one barrier per step.
+__global__ void __launch_bounds__(kCholThreads) cholqr_kernel(int m, const double* __restrict__ G, int ldg,
+                                                              double drop, double* __restrict__ T, int ldt,
+                                                              double* __restrict__ kk_out) {
+  __shared__ double rowb[2][kCholCols], colb[2][kCholCols], dsc[kCholCols], rs[kCholCols];
+  __shared__ int kidx[kCholCols];
+  const int tid = threadIdx.x, c = tid % kCholCols, g = tid / kCholCols;
+  for (int i = tid; i < kCholCols; i += kCholThreads) {
+    const double gi = i < m ? G[(int64_t)i * ldg + i] : 0.0;
+    dsc[i] = gi > 0.0 ? 1.0 / sqrt(gi) : 0.0;
   }
   __syncthreads();
-  for (int j = 0; j + 1 < m; ++j) {
-    const double* cj = colv[j & 1];
-    double* cn = colv[(j + 1) & 1];
-    const double p = cj[j];
-    const double rp = p > drop ? 1.0 / p : 0.0;   // dropped: f = 0 leaves the rows as they are
-    if (c < m) {
-      const double rj = a[j * m + c];
-      // rows in batches of kCholB (loads of a batch in flight together)
-      for (int i0 = j + 1 + rg; i0 < m; i0 += kCholB * kRG) {
-        // unconditional loads (rows clamped into range) so that they issue together
-        double f[kCholB], v[kCholB];
+  double a[kCholW];
 #pragma unroll
-        for (int u = 0; u < kCholB; ++u) {
-          const int i = min(i0 + u * kRG, m - 1);
-          f[u] = cj[i];
-          v[u] = a[i * m + c];
-        }
-#pragma unroll
-        for (int u = 0; u < kCholB; ++u) {
-          const int i = i0 + u * kRG;
-          if (i < m) {
-            // c < j: E[i][c] -= f E[j][c]; c == j: E[i][j] = -f (E[j][j] = 1); c > j: Schur update
-            const double fu = f[u] * rp;
-            const double nv = c == j ? -fu : v[u] - fu * rj;
-            a[i * m + c] = nv;
-            if (c == j + 1) cn[i] = nv;
-          }
-        }
-      }
-    }
-    __syncthreads();
+  for (int k = 0; k < kCholW; ++k) {
+    const int idx = g + kCholRG * k, r = m - 1 - idx;
+    a[k] = (c < m && idx < m) ? 0.5 * (G[(int64_t)r * ldg + c] + G[(int64_t)c * ldg + r]) * dsc[r] * dsc[c] : 0.0;
   }
-  // slot (j, j) holds p_j, slots (j, c < j) hold E[j][c]
-  if (tid == 0) {
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      const double p = a[j * m + j];
-      if (p > drop) {
-        rs[k] = 1.0 / sqrt(p);
-        src[k++] = j;
-      }
-    }
-    nkeep = k;
-    *kk_out = (double)k;
+  // row 0 (reversed index m - 1) and column 0 below the diagonal
+#pragma unroll
+  for (int k = 0; k < kCholW; ++k) {
+    const int idx = g + kCholRG * k;
+    if (idx == m - 1) rowb[0][c] = a[k];
+    if (c == 0) colb[0][idx] = idx < m - 1 ? a[k] : 0.0;
   }
   __syncthreads();
-  const int kk = nkeep;
-  for (int e = tid; e < m * kk; e += kCholThreads) {
-    const int r = e / kk, k = e - r * kk, j = src[k];
-    const double ejr = r < j ? a[j * m + r] : (r == j ? 1.0 : 0.0);
-    T[r * ldt + k] = d[r] * ejr * rs[k];
+  auto steps = [&](auto Jc, int jb, int je) {
+    constexpr int J = decltype(Jc)::value;
+#pragma unroll 1
+    for (int j = jb; j < je; ++j) {
+      const int bs = j & 1, na = m - 1 - j;   // rows after j: reversed indices below na
+      const double p = rowb[bs][j];
+      const double rp = p > drop ? chol_recip(p) : 0.0;   // dropped: zero multipliers
+      const double rj = rowb[bs][c];
+      double f[J];
+#pragma unroll
+      for (int k = 0; k < J; ++k) f[k] = colb[bs][g + kCholRG * k] * rp;
+      // register row k of this lane has reversed index g + kCholRG k: it lies
+      // after row j for k < ka, and after row j + 1 for k < k1; row j + 1
+      // (reversed index na - 1, in the last of the J blocks) is register row
+      // J - 1 of row group gr
+      const int ka = (na - g + kCholRG - 1) / kCholRG, r1 = na - 1;
+      const int k1 = (r1 - g + kCholRG - 1) / kCholRG, gr = r1 % kCholRG;
+      // E[i][c] -= f E[j][c] (c < j) or the Schur update (c > j) ...
+#pragma unroll
+      for (int k = 0; k < J; ++k) a[k] = fma(-f[k], rj, a[k]);
+      // ... and column j takes the multipliers, E[i][j] = -f_i / p_j (one
+      // lane per row group)
+      if (c == j) {
+#pragma unroll
+        for (int k = 0; k < J; ++k)
+          if (k < ka) a[k] = -f[k];
+      }
+      // row j + 1 and column j + 1 below the diagonal into the other buffers
+      if (g == gr) rowb[bs ^ 1][c] = a[J - 1];
+      if (c == j + 1) {
+#pragma unroll
+        for (int k = 0; k < J; ++k) colb[bs ^ 1][g + kCholRG * k] = k < k1 ? a[k] : 0.0;
+      }
+      __syncthreads();
+    }
+  };
+  for (int j0 = 0; j0 < m - 1;) {
+    const int J = (m - 1 - j0 + kCholRG - 1) / kCholRG;
+    const int je = min(m - 1, m - 1 - kCholRG * (J - 1));   // the first step with fewer blocks
+    CHOL_DISPATCH(J, [&](auto Jc) { steps(Jc, j0, je); });
+    j0 = je;
   }
-}
-
-__global__ void __launch_bounds__(256) symmetrize_kernel(int m, double* __restrict__ G, int ldg) {
-  for (int e = threadIdx.x; e < m * m; e += 256) {
-    const int i = e / m, j = e % m;
-    if (i < j) {
-      const double s = 0.5 * (G[i * ldg + j] + G[j * ldg + i]);
-      G[i * ldg + j] = s;
-      G[j * ldg + i] = s;
+  // pivots p_j on the diagonal; kept columns numbered in order (two ballots)
+#pragma unroll
+  for (int k = 0; k < kCholW; ++k) {
+    const int idx = g + kCholRG * k, r = m - 1 - idx;
+    if (idx < m && r == c) rs[c] = a[k] > drop ? 1.0 / sqrt(a[k]) : 0.0;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const bool k0 = tid < m && rs[tid] > 0.0, k1 = tid + 64 < m && rs[tid + 64] > 0.0;
+    const unsigned long long b0 = __ballot(k0), b1 = __ballot(k1);
+    const unsigned long long below = (1ull << tid) - 1ull;   // lanes before this one
+    kidx[tid] = k0 ? __popcll(b0 & below) : -1;
+    kidx[tid + 64] = k1 ? __popcll(b0) + __popcll(b1 & below) : -1;
+    if (tid == 0) *kk_out = (double)(__popcll(b0) + __popcll(b1));
+  }
+  __syncthreads();
+  // T[r][kidx[j]] = d_r E[j][r] / sqrt(p_j) for kept j: the thread of column r
+  // and row j writes it (E[j][j] = 1, zero above)
+  if (c < m) {
+#pragma unroll
+    for (int k = 0; k < kCholW; ++k) {
+      const int idx = g + kCholRG * k, j = m - 1 - idx;
+      if (idx < m && kidx[j] >= 0) {
+        const double ejr = c < j ? a[k] : (c == j ? 1.0 : 0.0);
+        T[(int64_t)c * ldt + kidx[j]] = dsc[c] * ejr * rs[j];
+      }
     }
   }
 }
@@ -405,22 +434,10 @@ hipError_t dense_copy_cols(int N, int k, const double* A, int lda, double* B, in
   return hipGetLastError();
 }
 
-hipError_t dense_scale_sym(int m, const double* G, int ldg, double* Gs, int lds, double* dvec, hipStream_t s) {
-  hipLaunchKernelGGL(scale_sym_kernel, dim3(1), dim3(256), 0, s, m, G, ldg, Gs, lds, dvec);
-  return hipGetLastError();
-}
-
-hipError_t dense_cholqr_t(int m, const double* Gs, int ldg, const double* dvec, double drop, double* T, int ldt,
-                          double* kk_out, hipStream_t s) {
+hipError_t dense_cholqr(int m, const double* G, int ldg, double drop, double* T, int ldt, double* kk_out,
+                        hipStream_t s) {
   if (m < 1 || m > kMaxSmall) return hipErrorInvalidValue;
-  const size_t lds = sizeof(double) * (size_t)m * m;
-  (void)hipFuncSetAttribute((const void*)cholqr_t_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(cholqr_t_kernel, dim3(1), dim3(kCholThreads), lds, s, m, Gs, ldg, dvec, drop, T, ldt, kk_out);
-  return hipGetLastError();
-}
-
-hipError_t dense_symmetrize(int m, double* G, int ldg, hipStream_t s) {
-  hipLaunchKernelGGL(symmetrize_kernel, dim3(1), dim3(256), 0, s, m, G, ldg);
+  hipLaunchKernelGGL(cholqr_kernel, dim3(1), dim3(kCholThreads), 0, s, m, G, ldg, drop, T, ldt, kk_out);
   return hipGetLastError();
 }
 

@@ -659,7 +659,7 @@ constexpr double kDropPivot = 1e-10;   // Cholesky-QR: squared relative distance
 
 struct EigWs {
   double *X, *HX, *SX, *P, *R, *W, *Q, *HQ, *SQ, *Q2, *HQ2, *SQ2;
-  double *G, *Gs, *lam, *dvec, *T, *GH, *th, *C, *C2, *norms, *part, *rpart;
+  double *G, *lam, *T, *GH, *th, *C, *C2, *norms, *part, *rpart;
   char* mv;
   size_t mv_bytes;
 };
@@ -678,7 +678,7 @@ size_t eigs_layout(const lhf_toeplitz_s* t, int nev, EigWs* w, char* base) {
   take(d.Q, N * mx); take(d.HQ, N * mx); take(d.SQ, N * mx);
   take(d.Q2, N * mx); take(d.HQ2, N * mx); take(d.SQ2, N * mx);
   const size_t sq = (size_t)kMaxSmall * kMaxSmall;
-  take(d.G, sq); take(d.Gs, sq); take(d.lam, kMaxSmall); take(d.dvec, kMaxSmall);
+  take(d.G, sq); take(d.lam, kMaxSmall);
   take(d.T, sq); take(d.GH, sq); take(d.th, kMaxSmall); take(d.C, sq); take(d.C2, sq); take(d.norms, kMaxSmall);
   take(d.part, (size_t)kGramChunks * sq); take(d.rpart, (size_t)kChunks * kMaxSmall);
   d.mv_bytes = lhf_toeplitz_matvec_workspace(const_cast<lhf_toeplitz_s*>(t), mx);
@@ -777,8 +777,7 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t t, int32_t nev, int32_t maxit, double t
     // are numerically in the span of the ones before them
     matvec(prec, m, w.Q, mx, w.HQ, w.SQ);
     ck(dense_gram(N, m, m, w.Q, mx, w.SQ, mx, w.part, kGramChunks, w.G, S, s));
-    ck(dense_scale_sym(m, w.G, S, w.Gs, S, w.dvec, s));
-    ck(dense_cholqr_t(m, w.Gs, S, w.dvec, kDropPivot, w.T, S, w.lam, s));
+    ck(dense_cholqr(m, w.G, S, kDropPivot, w.T, S, w.lam, s));
     ck(hipMemcpyAsync(hl.data(), w.lam, sizeof(double), hipMemcpyDeviceToHost, s));
     ck(hipStreamSynchronize(s));
     if (e != hipSuccess) break;
@@ -787,8 +786,7 @@ int32_t lhf_toeplitz_eigs(lhf_toeplitz_t t, int32_t nev, int32_t maxit, double t
     ck(dense_combine3(N, m, kk, w.Q, w.HQ, w.SQ, mx, w.T, S, w.Q2, w.HQ2, w.SQ2, mx, s));
     // Rayleigh-Ritz in FP64
     ck(dense_gram(N, kk, kk, w.Q2, mx, w.HQ2, mx, w.part, kGramChunks, w.GH, S, s));
-    ck(dense_symmetrize(kk, w.GH, S, s));
-    ck(dense_syev_low(kk, nb, w.GH, S, w.th, w.C, S, s));
+    ck(dense_syev_low(kk, nb, w.GH, S, w.th, w.C, S, s));   // reads (GH + GH^T) / 2
     ck(dense_combine3(N, kk, nb, w.Q2, w.HQ2, w.SQ2, mx, w.C, S, w.W, w.HX, w.SX, nb, s));   // X_new, HX, SX
     if (it > 0) {
       // P = X_new - X (X^T S X_new)

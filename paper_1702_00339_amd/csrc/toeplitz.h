@@ -112,14 +112,12 @@ hipError_t dense_residual(int N, int k, const double* HX, const double* SX, int 
                           int ldr, double* part, int nchunk, double* norms, hipStream_t s);
 hipError_t dense_random(int N, int k, uint64_t seed, double* X, int ld, hipStream_t s);
 hipError_t dense_copy_cols(int N, int k, const double* A, int lda, double* B, int ldb, hipStream_t s);
-// Gs = D G D with D = diag(G)^-1/2 (d written to dvec)
-hipError_t dense_scale_sym(int m, const double* G, int ldg, double* Gs, int lds, double* dvec, hipStream_t s);
-// Cholesky-QR of the scaled Gram Gs (unit diagonal) with deflation: columns
-// whose pivot (squared distance from the span of the kept columns before
-// them) is <= drop are dropped; T (m x kk) = D L^-T diag(p)^-1/2 on the kept
-// columns, so T^T G T = I; kk written to *kk_out as a double
-hipError_t dense_cholqr_t(int m, const double* Gs, int ldg, const double* dvec, double drop, double* T, int ldt,
-                          double* kk_out, hipStream_t s);
-hipError_t dense_symmetrize(int m, double* G, int ldg, hipStream_t s);
+// Cholesky-QR with deflation of the Gram matrix G (read as (G + G^T) / 2 and
+// scaled on load to Gs = D G D, D = diag(G)^-1/2): columns whose pivot (the
+// squared distance of scaled column j from the span of the kept columns
+// before it) is <= drop are dropped; T (m x kk) = D L^-T diag(p)^-1/2 on the
+// kept columns, so T^T G T = I; kk written to *kk_out as a double
+hipError_t dense_cholqr(int m, const double* G, int ldg, double drop, double* T, int ldt, double* kk_out,
+                        hipStream_t s);
 
 }  // namespace lhf
