@@ -53,20 +53,25 @@ HEEV_FLOPS_PER_M3 = 150.0                    # algorithmic eigensolve work per b
 # HBM bytes per call (FETCH_SIZE + WRITE_SIZE, KiB, each scaled by what the counter reads for a plain
 # 512 MiB device copy) of the headline kernels, from two rocprofv3 --pmc runs of `bench.py
 # --probe-traffic` (profiles/traffic_per_dispatch.md).  Each entry names the source files of its kernels
-# and their SHA-1 (first 16 hex digits) when counted, and the route it was counted on; an entry whose
-# sources have changed since, or whose route is not the one timed, is reported as null.
+# and their SHA-1 (first 16 hex digits) when counted, and the route it was counted on (a list holds one
+# entry per route); an entry whose sources have changed since, or whose route is not the one timed, is
+# reported as null.
 TRAFFIC_KIB = {
     "c2": {
-        "eigensolve": {"kib": 1229.6, "route": "fp64=4,wide=4", "src": ["heev.hip", "sturm.h"], "sha": "b9495542673ada50"},
-        "fourier": {"kib": 4127.2, "route": "sep", "src": ["blockdft.hip"], "sha": "47aefc9e22736b74"},
+        "eigensolve": {"kib": 1233.2, "route": "fp64=4,wide=4", "src": ["heev.hip", "sturm.h", "dpp.h"], "sha": "2d52cf7efc8892d1"},
+        "fourier": {"kib": 4131.9, "route": "sep", "src": ["blockdft.hip"], "sha": "cea000fae32c8314"},
     },
     "c3": {
-        "eigensolve": {"kib": 35990.6, "route": "fp64=2,wide=0", "src": ["heev.hip", "sturm.h"], "sha": "b9495542673ada50"},
-        "fourier": {"kib": 71329.6, "route": "sep", "src": ["blockdft.hip"], "sha": "47aefc9e22736b74"},
+        "eigensolve": {"kib": 35988.9, "route": "fp64=2,wide=0", "src": ["heev.hip", "sturm.h", "dpp.h"], "sha": "2d52cf7efc8892d1"},
+        "fourier": {"kib": 71337.8, "route": "sep", "src": ["blockdft.hip"], "sha": "cea000fae32c8314"},
     },
     "c4": {
-        "eigensolve": {"kib": 606643.2, "route": "fp64=15,wide=1", "src": ["heev.hip", "sturm.h"], "sha": "b9495542673ada50"},
-        "fourier": {"kib": 1466177.5, "route": "sep", "src": ["blockdft.hip"], "sha": "47aefc9e22736b74"},
+        "eigensolve": [
+            {"kib": 606495.2, "route": "fp64=15,wide=0", "src": ["heev.hip", "sturm.h", "dpp.h"], "sha": "2d52cf7efc8892d1"},
+            # the same run's dispatches with the M = 4 class in the wide layout
+            {"kib": 606646.6, "route": "fp64=15,wide=1", "src": ["heev.hip", "sturm.h", "dpp.h"], "sha": "2d52cf7efc8892d1"},
+        ],
+        "fourier": {"kib": 1464116.7, "route": "sep", "src": ["blockdft.hip"], "sha": "cea000fae32c8314"},
     },
 }
 
@@ -101,10 +106,11 @@ def src_sha(files):
 
 
 def traffic_bytes(cfg, kernel, route):
-    e = TRAFFIC_KIB.get(cfg, {}).get(kernel)
-    if not e or e["route"] != route or src_sha(e["src"]) != e["sha"]:
-        return None
-    return e["kib"] * 1024.0
+    ents = TRAFFIC_KIB.get(cfg, {}).get(kernel) or []
+    for e in ents if isinstance(ents, list) else [ents]:
+        if e["route"] == route and src_sha(e["src"]) == e["sha"]:
+            return e["kib"] * 1024.0
+    return None
 
 
 def time_graph(graph, steps, torch):
