@@ -344,12 +344,17 @@ __global__ void __launch_bounds__(kRrThreads) rr_syev_kernel(int m, int k, const
         for (int jb = 0; jb < m; jb += 8) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) rb[q] = de[jb + 4 + q];
+          // the reads above stay here, in flight while the first half is counted
+          // (an empty asm that may change memory: they cannot move below it, and
+          // the next iteration cannot read the same rows afresh)
+          asm volatile("" ::: "memory");
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             if (jb + q > 0) sturm_row<SPLIT>(ra[q].x, ra[q].y, x, p1, p2, neg, cnt);
           const int jn = jb + 8 < kRrRows ? jb + 8 : jb;   // the next block
 #pragma unroll
           for (int q = 0; q < 4; ++q) ra[q] = de[jn + q];
+          asm volatile("" ::: "memory");
 #pragma unroll
           for (int q = 0; q < 4; ++q) sturm_row<SPLIT>(rb[q].x, rb[q].y, x, p1, p2, neg, cnt);
           const double s = fabs(p1) > kBig ? kSmall : (fabs(p1) < kSmall ? kBig : 1.0);
