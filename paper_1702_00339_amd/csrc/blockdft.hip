@@ -257,7 +257,9 @@ __device__ __forceinline__ int find_fused(const FusedTask* __restrict__ t, int n
 // are summed by slot residue a = s1 mod 4 (k1 = s1 + off mod R1), and Y_q =
 // zeta^(q off) sum_a zeta^(q a) S_a: one complex multiply-add per input for R1
 // outputs.  A thread owns one (j2, e) column with its B1 inputs in registers
-// and walks groups of R1 outputs j1 with incrementally updated twiddle indices.
+// and walks groups of R1 outputs j1.  Slot cells are consecutive mod L1
+// (k1(s1) = k1(0) + s1), so output j's twiddle index j k1(s1) mod L1 starts
+// at j k1(0) mod L1 and steps by j from one slot to the next.
 template <typename R, int BM>
 __device__ __forceinline__ void fused_last_stage(const LatDev& L, int J2C, int j2lo, int j2n, int j3, int e0, int ecn,
                                                  const typename Cx<R>::T* T2, const typename Cx<R>::T* tw1, bool isH,
@@ -276,19 +278,18 @@ __device__ __forceinline__ void fused_last_stage(const LatDev& L, int J2C, int j
   const int R1 = (L1 & 3) == 0 ? 4 : (L1 & 1) == 0 ? 2 : 1;
   const int Q = L1 / R1;
   const int off = slot_cell(D0, 0) % R1;
+  // inputs past the band are zero, so the sums below may run past it in
+  // whole groups of four slots (the twiddle index stays in range regardless)
   R xr[BM], xi[BM];
-  int idx[BM], stp[BM];
 #pragma unroll
   for (int s1 = 0; s1 < BM; ++s1) {
-    if (s1 < B1) {
-      const C x = T2[(s1 * J2C + jj) * EC + ec];
-      xr[s1] = x.x;
-      xi[s1] = x.y;
-      const int k1 = slot_cell(D0, s1);
-      idx[s1] = (rep * k1) % L1;
-      stp[s1] = (nrep * k1) % L1;
-    }
+    const C x = T2[(min(s1, B1 - 1) * J2C + jj) * EC + ec];
+    xr[s1] = s1 < B1 ? x.x : R(0);
+    xi[s1] = s1 < B1 ? x.y : R(0);
   }
+  const int k0 = slot_cell(D0, 0);
+  int base = (int)(((int64_t)rep * k0) % L1);   // j k1(0) mod L1 for the current j
+  const int bstep = (int)(((int64_t)nrep * k0) % L1);
   // full layout [L1][L2][L3][E], or the half layout with L3 / 2 + 1 planes
   // (the caller runs no workgroup for j3 > L3 / 2 then)
   const int L3o = half ? L3 / 2 + 1 : L3;
@@ -310,16 +311,26 @@ __device__ __forceinline__ void fused_last_stage(const LatDev& L, int J2C, int j
   };
   for (int j = rep; j < Q; j += nrep, ybase += ystep) {
     R sr[4] = {R(0), R(0), R(0), R(0)}, si[4] = {R(0), R(0), R(0), R(0)};
+    int ix = base;   // j k1(s1) mod L1; j < Q <= L1
+    // opaque, or the compiler keeps one index register per slot across j
+    asm volatile("" : "+v"(ix));
+    // groups of four slots up to the band (a uniform branch per group, the
+    // group's twiddle reads in flight together)
 #pragma unroll
-    for (int s1 = 0; s1 < BM; ++s1) {
-      if (s1 < B1) {
-        const C w = tw1[idx[s1]];
-        sr[s1 & 3] += w.x * xr[s1] - w.y * xi[s1];
-        si[s1 & 3] += w.x * xi[s1] + w.y * xr[s1];
-        idx[s1] += stp[s1];
-        if (idx[s1] >= L1) idx[s1] -= L1;
+    for (int s0 = 0; s0 < BM; s0 += 4) {
+      if (s0 < B1) {
+#pragma unroll
+        for (int s1 = s0; s1 < s0 + 4 && s1 < BM; ++s1) {
+          const C w = tw1[ix];
+          sr[s1 & 3] += w.x * xr[s1] - w.y * xi[s1];
+          si[s1 & 3] += w.x * xi[s1] + w.y * xr[s1];
+          ix += j;
+          if (ix >= L1) ix -= L1;
+        }
       }
     }
+    base += bstep;
+    if (base >= L1) base -= L1;
     if (R1 == 4) {
       // U_q = sum_a zeta^(q a) S_a; zeta (x + i y) = zs (-y + i x); Y_q = zeta^(q off) U_q
       const R ar = sr[0] + sr[2], ai = si[0] + si[2], br = sr[0] - sr[2], bi = si[0] - si[2];
@@ -457,84 +468,9 @@ __global__ void __launch_bounds__(256) dft_fused_kernel(const LatDev* __restrict
     }
   }
   __syncthreads();
-  // stage 3: the outputs j1 = j + q Q (q < R1, Q = L1 / R1, R1 = 4, 2 or 1
-  // as L1 allows) share the twiddles w1^(j k1) up to zeta^(q k1), zeta =
-  // w1^Q = +-i or -1.  The inputs are summed by slot residue a = s1 mod 4
-  // (k1 = s1 + off mod R1), and Y_q = zeta^(q off) sum_a zeta^(q a) S_a: one
-  // complex multiply-add per input for R1 outputs.
-  const int ncol = J2C * EC, nrep = 256 / ncol;
-  const int col = tid % ncol, rep = tid / ncol;
-  const int jj = col / EC;
-  if (rep >= nrep || jj >= j2n || ec >= ecn) return;
-  const int R1 = (L1 & 3) == 0 ? 4 : (L1 & 1) == 0 ? 2 : 1;
-  const int Q = L1 / R1;
-  const int off = slot_cell(D0, 0) % R1;
-  R xr[BM], xi[BM];
-  int idx[BM], stp[BM];
-#pragma unroll
-  for (int s1 = 0; s1 < BM; ++s1) {
-    if (s1 < B1) {
-      const C x = T2[(s1 * J2C + jj) * EC + ec];
-      xr[s1] = x.x;
-      xi[s1] = x.y;
-      const int k1 = slot_cell(D0, s1);
-      idx[s1] = (rep * k1) % L1;
-      stp[s1] = (nrep * k1) % L1;
-    }
-  }
-  const int L3o = half ? L3 / 2 + 1 : L3;   // planes along j3 of the output layout
-  const int64_t yoff = (half ? L.half_off : L.gen_off) + ((int64_t)(j2lo + jj) * L3o + j3) * E + e0 + ec;
-  C* Y = (blockIdx.y == 0 ? barH : barS) + yoff;
-  float2* Y32 = b32H ? (blockIdx.y == 0 ? b32H : b32S) + yoff : nullptr;
-  const int64_t jstride = (int64_t)L2 * L3o * E;
-  const R zs = tw1[Q % L1].y < R(0) ? R(-1) : R(1);   // zeta = zs i when R1 = 4
-  // output j1 = j + q Q sits (j1 - j) jstride past the base output j
-  const int64_t ystep = (int64_t)nrep * jstride, qstep = (int64_t)Q * jstride;
-  int64_t ybase = (int64_t)rep * jstride;
-  auto put = [&](int q, R re, R im) {
-    C v;
-    v.x = re;
-    v.y = im;
-    const int64_t o = ybase + q * qstep;
-    Y[o] = v;
-    if (Y32) Y32[o] = make_float2((float)re, (float)im);
-  };
-  for (int j = rep; j < Q; j += nrep, ybase += ystep) {
-    R sr[4] = {R(0), R(0), R(0), R(0)}, si[4] = {R(0), R(0), R(0), R(0)};
-#pragma unroll
-    for (int s1 = 0; s1 < BM; ++s1) {
-      if (s1 < B1) {
-        const C w = tw1[idx[s1]];
-        sr[s1 & 3] += w.x * xr[s1] - w.y * xi[s1];
-        si[s1 & 3] += w.x * xi[s1] + w.y * xr[s1];
-        idx[s1] += stp[s1];
-        if (idx[s1] >= L1) idx[s1] -= L1;
-      }
-    }
-    if (R1 == 4) {
-      // U_q = sum_a zeta^(q a) S_a; zeta (x + i y) = zs (-y + i x); Y_q = zeta^(q off) U_q
-      const R ar = sr[0] + sr[2], ai = si[0] + si[2], br = sr[0] - sr[2], bi = si[0] - si[2];
-      const R cr = sr[1] + sr[3], ci = si[1] + si[3], dr = sr[1] - sr[3], di = si[1] - si[3];
-      auto rot = [&](int q, R yr, R yi) {
-        const int m = (q * off) & 3;
-        if (m == 1) { const R tr = -zs * yi; yi = zs * yr; yr = tr; }
-        else if (m == 2) { yr = -yr; yi = -yi; }
-        else if (m == 3) { const R tr = zs * yi; yi = -zs * yr; yr = tr; }
-        put(q, yr, yi);
-      };
-      rot(0, ar + cr, ai + ci);
-      rot(1, br - zs * di, bi + zs * dr);
-      rot(2, ar - cr, ai - ci);
-      rot(3, br + zs * di, bi - zs * dr);
-    } else if (R1 == 2) {
-      const R er = sr[0] + sr[2], ei = si[0] + si[2], orr = sr[1] + sr[3], oi = si[1] + si[3];
-      put(0, er + orr, ei + oi);
-      const R sg = (off & 1) ? R(-1) : R(1);
-      put(1, sg * (er - orr), sg * (ei - oi));
-    } else {
-      put(0, sr[0] + sr[1] + sr[2] + sr[3], si[0] + si[1] + si[2] + si[3]);
-    }
-  }
+  // stage 3: every j1 of the band's columns
+  fused_last_stage<R, BM>(L, J2C, j2lo, j2n, j3, e0, ecn, T2, tw1, blockIdx.y == 0, barH, barS, b32H, b32S,
+                          half != 0);
 }
 
 int band_class(int B) { return B <= 4 ? 0 : B <= 8 ? 1 : B <= 16 ? 2 : B <= 32 ? 3 : 4; }
@@ -600,6 +536,8 @@ hipError_t dft_launch_all(const lhf_plan_s* p, const R* gH, const R* gS, typenam
 // and the last stage transforms dimension 1 as in the fused kernel.  No
 // generator stack is formed or read; every Fourier block is written once.
 
+constexpr int kGhBatch = 16;   // slots of a transformed Gram entry loaded together
+
 // G^ along dimensions 2 and 3: gh[t][j][e] = sum over slots s of w^(j k_s) G[t][s][e]
 __global__ void __launch_bounds__(256) gram_dft_kernel(const LatDev* __restrict__ lats,
                                                        const GhItem* __restrict__ items, int nitems,
@@ -622,26 +560,74 @@ __global__ void __launch_bounds__(256) gram_dft_kernel(const LatDev* __restrict_
   const int t = (int)(idx / ((int64_t)m2 * D.L));
   double re = 0.0, im = 0.0;
   const int ns = nslot(D);
-#pragma unroll 4
-  for (int s = 0; s < ns; ++s) {
-    const double2 w = tw[D.tw_off + (int)(((int64_t)j * slot_cell(D, s)) % D.L)];
-    const double g = grams[D.gram_off + ((int64_t)t * D.nshift + s) * m2 + e];
-    re += w.x * g;
-    im += w.y * g;
+  const double* gp = grams + D.gram_off + (int64_t)t * D.nshift * m2 + e;
+  const double2* wt = tw + D.tw_off;
+  // slot cells are consecutive mod L, so the twiddle index j k_s mod L
+  // starts at j k_0 mod L and steps by j (< L); the loads of kGhBatch slots
+  // are in flight together
+  int ix = (int)(((int64_t)j * slot_cell(D, 0)) % D.L);
+  for (int s0 = 0; s0 < ns; s0 += kGhBatch) {
+    double2 w[kGhBatch];
+    double g[kGhBatch];
+#pragma unroll
+    for (int u = 0; u < kGhBatch; ++u) {
+      w[u] = make_double2(0.0, 0.0);
+      g[u] = 0.0;
+      if (s0 + u < ns) {
+        w[u] = wt[ix];
+        g[u] = gp[(int64_t)(s0 + u) * m2];
+      }
+      ix += j;
+      if (ix >= D.L) ix -= D.L;
+    }
+#pragma unroll
+    for (int u = 0; u < kGhBatch; ++u) {
+      re += w[u].x * g[u];
+      im += w[u].y * g[u];
+    }
   }
   gh[D.gh_off + idx] = make_double2(re, im);
 }
 
-constexpr int kSepTC = 8;   // Gram terms staged in LDS per step
+constexpr int kSepLds = 40960;   // LDS per workgroup: four of them per CU
+
+// Bytes after the staged Grams for slot reads past the band: (nsp - 1) kFusedEC
+// doubles at most, nsp = 256 / (J2C kFusedEC)
+__host__ __device__ inline int sep_pad_bytes(int J2C) { return 256 / J2C * 8; }
+constexpr int kSepQR = 4;   // staged products per thread and round (two rounds)
+constexpr int kSepGR = 8;   // staged Gram entries per thread and round (two rounds)
+
+// Gram terms per chunk of the separable kernel: each term stages G1_t[s1][ec]
+// (B1 kFusedEC doubles) and Q_t[jj][ec] (J2C kFusedEC complex) in LDS; the
+// chunk, its padding and the L1 twiddles fit kSepLds, and its entries fit the
+// two staging rounds of 256 threads (at least one term: B1 <= 32, J2C <= 16)
+__host__ __device__ inline int sep_term_chunk(int B1, int J2C, int L1, int nterm) {
+  const int per = B1 * kFusedEC * 8 + J2C * kFusedEC * 16;
+  int fit = (kSepLds - sep_pad_bytes(J2C) - L1 * 16) / per;
+  const int fg = 2 * kSepGR * 256 / (B1 * kFusedEC), fq = 2 * kSepQR * 256 / (J2C * kFusedEC);
+  fit = fit < fg ? fit : fg;
+  fit = fit < fq ? fit : fq;
+  return fit < 1 ? 1 : (fit < nterm ? fit : nterm);
+}
+// LDS of the separable kernel before its twiddles: the chunk's products,
+// Grams and padding, or T2, whichever is larger
+__host__ __device__ inline int sep_stage_bytes(int B1, int J2C, int L1, int nterm) {
+  const int g = sep_term_chunk(B1, J2C, L1, nterm) * (B1 * kFusedEC * 8 + J2C * kFusedEC * 16) + sep_pad_bytes(J2C);
+  const int t2 = B1 * J2C * kFusedEC * 16;
+  return g > t2 ? g : t2;
+}
 
 // Workgroup (lattice, entry chunk, j2 chunk, j3) as in dft_fused_kernel;
 // grid y: H, S.  With Q_0 = P_ks / 2, Q_1 = P_ss / 2 and Q_t = -P_t (t >= 2)
 // for H, and Q_0 = P_ss for S (one term), T2[s1] = sum_t G1_t[s1] Q_t.  The
-// terms go in steps of kSepTC: the workgroup stages G1_t[s1][ec] and
-// Q_t[jj][ec] in LDS, then thread (column (jj, ec), part sp) accumulates the
-// slots s1 = sp, sp + nsp, ... of its column.
+// terms go in chunks (sep_term_chunk): the workgroup stages the chunk's
+// G1_t[s1][ec] and Q_t[jj][ec] in LDS with every load of the chunk in flight
+// at once, then thread (column (jj, ec), part sp) accumulates the slots
+// s1 = sp, sp + nsp, ... of its column from LDS alone.  T2 takes the stage's
+// place once every term is in.
 template <int BM>
-__global__ void __launch_bounds__(256) sep_fused_kernel(const LatDev* __restrict__ lats,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM <= 16 ? 4 : 1)))
+sep_fused_kernel(const LatDev* __restrict__ lats,
                                                         const FusedTask* __restrict__ tasks, int ntasks,
                                                         const double2* __restrict__ tw,
                                                         const double* __restrict__ grams,
@@ -666,73 +652,128 @@ __global__ void __launch_bounds__(256) sep_fused_kernel(const LatDev* __restrict
   if (half && j3 > L3 / 2) return;   // the conjugate half: the whole workgroup
   const int e0 = eci * EC, ecn = min(EC, m2 - e0);
   const int j2lo = j2c * J2C, j2n = min(J2C, L2 - j2lo);
-  C* T2 = reinterpret_cast<C*>(lds_raw);             // [B1][J2C][EC]
-  C* tw1 = T2 + B1 * J2C * EC;                       // [L1]
-  C* Qs = tw1 + L1;                                  // [kSepTC][J2C][EC]
-  double* G1s = reinterpret_cast<double*>(Qs + kSepTC * J2C * EC);   // [kSepTC][B1][EC]
+  const int ncol = J2C * EC;
   const int tid = threadIdx.x;
-  for (int q = tid; q < L1; q += 256) tw1[q] = tw[D0.tw_off + q];
   const bool isH = blockIdx.y == 0;
   const int nterm = isH ? L.T : 1;
-  const int ncol = J2C * EC, nsp = 256 / ncol;
+  const int tch = sep_term_chunk(B1, J2C, L1, L.T);   // the S pass fits the H chunk
+  // LDS: [Qs | G1s | padding] or T2, then tw1
+  const int stage_bytes = sep_stage_bytes(B1, J2C, L1, L.T);
+  C* T2 = reinterpret_cast<C*>(lds_raw);
+  C* Qs = reinterpret_cast<C*>(lds_raw);                       // [tch][ncol]
+  double* G1s = reinterpret_cast<double*>(Qs + tch * ncol);    // [tch][B1][EC]
+  C* tw1 = reinterpret_cast<C*>(lds_raw + stage_bytes);
+  for (int q = tid; q < L1; q += 256) tw1[q] = tw[D0.tw_off + q];
+  const int nsp = 256 / ncol;
   const int col = tid % ncol, sp = tid / ncol;
   const int jj = col / EC, ec = col % EC;
+  const bool mine = sp < nsp && jj < j2n && ec < ecn;
   constexpr int NA = (BM + 1) / 2;   // slots per thread (nsp >= 2)
+  // slots sp + nsp u, u < nu, of the column (the last may lie past the band:
+  // it reads the next term's Grams or the padding into a sum that is never used)
+  const int nu = __builtin_amdgcn_readfirstlane(min(NA, (B1 + nsp - 1) / nsp));
+  const int ustride = nsp * EC;
   double ar[NA], ai[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) ar[u] = ai[u] = 0.0;
   const double2* g2 = gh + D1.gh_off;   // [t][L2][m2]
   const double2* g3 = gh + D2.gh_off;   // [t][L3][m2]
   const int64_t st2 = (int64_t)L2 * m2, st3 = (int64_t)L3 * m2;
-  for (int t0 = 0; t0 < nterm; t0 += kSepTC) {
-    const int tc = min(kSepTC, nterm - t0);
-    // Q_t for this step's terms, one (term, column) per thread
-    for (int q = tid; q < tc * ncol; q += 256) {
-      const int tt = q / ncol, c2 = q % ncol, qj = c2 / EC, qe = c2 % EC;
-      C v = make_double2(0.0, 0.0);
-      if (qj < j2n && qe < ecn) {
+  for (int t0 = 0; t0 < nterm; t0 += tch) {
+    const int tc = min(tch, nterm - t0);
+    if (t0 > 0) __syncthreads();   // the previous chunk is consumed
+    // the thread's first item, opaque so that no item's index is kept across chunks
+    int qb = tid;
+    asm volatile("" : "+v"(qb));
+    // Q_t[col]: item q = qb + 256 u is (term t0 + q / ncol, column q mod ncol);
+    // G1_t[s1][ec]: element q = qb + 256 u is (row r = q / EC, entry q mod EC),
+    // row r = (term t0 + r / B1, slot r mod B1); B1 is nshift or 1, so the
+    // row's Gram block is t0 nshift + r rs with rs = 1 or nshift.  Each round
+    // has its Gram and product loads in flight together.
+    const int nq = tc * ncol, ng = tc * B1 * EC, qe1 = qb % EC;
+    const int rs = B1 == 1 ? D0.nshift : 1;
+    const double* gb = grams + D0.gram_off + ((int64_t)t0 * D0.nshift + (qb / EC) * rs) * m2 + e0 + qe1;
+    const int64_t ustep = (int64_t)(256 / EC) * rs * m2;   // 256 / EC rows further
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (qb + 256 * kSepQR * r >= nq && qb + 256 * kSepGR * r >= ng) break;
+      double v[kSepGR];
+#pragma unroll
+      for (int u = 0; u < kSepGR; ++u) {
+        const int q = qb + 256 * (kSepGR * r + u);
+        v[u] = 0.0;
+        if (q < ng && qe1 < ecn) v[u] = gb[(kSepGR * r + u) * ustep];
+      }
+      C a2[kSepQR], a3[kSepQR], k2 = make_double2(0.0, 0.0), k3 = k2;
+      bool live[kSepQR];
+      int tq[kSepQR];
+#pragma unroll
+      for (int u = 0; u < kSepQR; ++u) {
+        const int q = qb + 256 * (kSepQR * r + u);
+        const int tt = q / ncol, c2 = q - tt * ncol, qj = c2 / EC, qe = c2 % EC;
         const int t = t0 + tt;
-        const int64_t o2 = (int64_t)(j2lo + qj) * m2 + e0 + qe, o3 = (int64_t)j3 * m2 + e0 + qe;
-        if (t >= 2) {
-          const C a2 = g2[t * st2 + o2], a3 = g3[t * st3 + o3];
-          v = make_double2(-(a2.x * a3.x - a2.y * a3.y), -(a2.x * a3.y + a2.y * a3.x));
-        } else {
-          const C s2 = g2[o2], s3 = g3[o3];
-          if (t == 1 || !isH) {
-            const double h = isH ? 0.5 : 1.0;   // Q_1 = P_ss / 2 (H), Q_0 = P_ss (S)
-            v = make_double2(h * (s2.x * s3.x - s2.y * s3.y), h * (s2.x * s3.y + s2.y * s3.x));
-          } else {
-            const C k2 = g2[st2 + o2], k3 = g3[st3 + o3];   // Q_0 = P_ks / 2
-            v = make_double2(0.5 * ((k2.x * s3.x - k2.y * s3.y) + (s2.x * k3.x - s2.y * k3.y)),
-                             0.5 * ((k2.x * s3.y + k2.y * s3.x) + (s2.x * k3.y + s2.y * k3.x)));
+        live[u] = q < nq && qj < j2n && qe < ecn;
+        tq[u] = t;
+        a2[u] = a3[u] = make_double2(0.0, 0.0);
+        if (live[u]) {
+          const int64_t o2 = (int64_t)(j2lo + qj) * m2 + e0 + qe, o3 = (int64_t)j3 * m2 + e0 + qe;
+          const int tA = t < 2 ? 0 : t;   // terms 0 and 1 are formed from S^2 and S^3
+          a2[u] = g2[tA * st2 + o2];
+          a3[u] = g3[tA * st3 + o3];
+          if (r == 0 && u == 0 && isH && t == 0) {   // only the first item can be term 0
+            k2 = g2[st2 + o2];
+            k3 = g3[st3 + o3];
           }
         }
       }
-      Qs[q] = v;
-    }
-    // G1_t[s1][ec] for this step's terms
-    for (int q = tid; q < tc * B1 * EC; q += 256) {
-      const int tt = q / (B1 * EC), r = q % (B1 * EC), s1 = r / EC, qe = r % EC;
-      G1s[q] = qe < ecn ? grams[D0.gram_off + ((int64_t)(t0 + tt) * D0.nshift + s1) * m2 + e0 + qe] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kSepGR; ++u) {
+        const int q = qb + 256 * (kSepGR * r + u);
+        if (q < ng) G1s[q] = v[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kSepQR; ++u) {
+        const int q = qb + 256 * (kSepQR * r + u);
+        if (q < nq) {
+          // branch-free: a divergent switch over t here was lowered with the
+          // negation of the t >= 2 case missing
+          const int t = tq[u];
+          const C x = a2[u], y = a3[u];
+          // P_t (t >= 2) or P_ss (t < 2) times 1 (S), 1/2 (H, t = 1) or -1 (H, t >= 2)
+          const double h = !isH ? 1.0 : (t == 1 ? 0.5 : -1.0);
+          double vx = h * (x.x * y.x - x.y * y.y), vy = h * (x.x * y.y + x.y * y.x);
+          const bool ks = isH && t == 0;   // H, t = 0: P_ks / 2
+          const double kx = 0.5 * ((k2.x * y.x - k2.y * y.y) + (x.x * k3.x - x.y * k3.y));
+          const double ky = 0.5 * ((k2.x * y.y + k2.y * y.x) + (x.x * k3.y + x.y * k3.x));
+          vx = ks ? kx : vx;
+          vy = ks ? ky : vy;
+          Qs[q] = make_double2(live[u] ? vx : 0.0, live[u] ? vy : 0.0);
+        }
+      }
     }
     __syncthreads();
-    if (sp < nsp) {
+    if (mine) {
+      const C* qp = Qs + col;
+      const double* gp = G1s + sp * EC + ec;
+#pragma unroll 2
       for (int tt = 0; tt < tc; ++tt) {
-        const C qv = Qs[tt * ncol + col];
+        const C qv = qp[tt * ncol];
+        double g[NA];
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
-          const int s1 = sp + nsp * u;
-          if (s1 < B1) {
-            const double g = G1s[(tt * B1 + s1) * EC + ec];
-            ar[u] += g * qv.x;
-            ai[u] += g * qv.y;
-          }
+          g[u] = 0.0;
+          if (u < nu) g[u] = gp[tt * B1 * EC + u * ustride];
+        }
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+          ar[u] += g[u] * qv.x;
+          ai[u] += g[u] * qv.y;
         }
       }
     }
-    __syncthreads();
   }
-  if (sp < nsp) {
+  __syncthreads();   // every stage read is done before T2 overwrites it
+  if (mine) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int s1 = sp + nsp * u;
@@ -1026,8 +1067,8 @@ void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tas
     t.nec = (L.m0 * L.m0 + kFusedEC - 1) / kFusedEC;
     t.J2C = std::min(L.L[1], kFusedJ2);
     t.nj2c = (L.L[1] + t.J2C - 1) / t.J2C;
-    const int64_t bytes = ((int64_t)B1 * t.J2C * kFusedEC + L.L[0] + (int64_t)kSepTC * t.J2C * kFusedEC) * 16 +
-                          (int64_t)kSepTC * B1 * kFusedEC * 8;
+    // the Gram stage or T2, whichever is larger, then the dimension-1 twiddles
+    const int64_t bytes = (int64_t)sep_stage_bytes(B1, t.J2C, L.L[0], L.T) + (int64_t)L.L[0] * 16;
     if (B1 > 32 || bytes > 65536) ok = false;
     t.wg_base = wgs;
     wgs += (int64_t)L.L[2] * t.nj2c * t.nec;
