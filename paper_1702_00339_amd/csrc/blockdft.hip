@@ -595,7 +595,7 @@ constexpr int kSepLds = 40960;   // LDS per workgroup: four of them per CU
 // doubles at most, nsp = 256 / (J2C kFusedEC)
 __host__ __device__ inline int sep_pad_bytes(int J2C) { return 256 / J2C * 8; }
 constexpr int kSepQR = 4;   // staged products per thread and round (two rounds)
-constexpr int kSepGR = 8;   // staged Gram entries per thread and round (two rounds)
+constexpr int kSepGR = 6;   // staged Gram entries per thread and round (two rounds)
 
 // Gram terms per chunk of the separable kernel: each term stages G1_t[s1][ec]
 // (B1 kFusedEC doubles) and Q_t[jj][ec] (J2C kFusedEC complex) in LDS; the
