@@ -89,6 +89,32 @@ def test_fp64_pipeline_matches_oracle(case, fourier):
     assert (np.abs(got - ref) <= tol).all(), np.abs(got - ref).max()
 
 
+# lattices with one cell along the first axis: the dimension-1 Grams keep
+# every image shift while the band has one slot
+FIRST_AXIS_ONE = [
+    dict(L=(1, 4, 3), n=(14, 32, 24), n_s=2, n_p=1, seed=112),                   # 3D
+    dict(L=(1, 5, 1), n=(16, 40, 12), n_s=3, n_p=0, seed=113),                   # 2D, odd L2
+]
+
+
+@pytest.mark.parametrize("case", FIRST_AXIS_ONE, ids=_ids)
+def test_separable_one_cell_first_axis(case):
+    """Separable Fourier blocks (Theorem 3.3) when the first axis is one cell:
+    the staged dimension-1 rows then step by whole shift blocks instead of
+    slots.  Blocks and eigenvalues against the oracle, as in the TINY cases."""
+    inst = tiny_instance(**{"R": 8, **case})
+    print(inst.summary(), flush=True)
+    res, ref = _eig_ref(inst)
+    pipe = _run(inst, lhf.LHF_PREC_FP64, fourier="sep")
+    assert pipe.separable()
+    Hb, Sb = pipe.stacks("H_bar")[0], pipe.stacks("S_bar")[0]
+    assert np.abs(Hb - res["H_bar"]).max() <= 1e-12 * np.abs(res["H_bar"]).max()
+    assert np.abs(Sb - res["S_bar"]).max() <= 1e-12 * np.abs(res["S_bar"]).max()
+    got = pipe.eigenvalues()[0]
+    tol = 1e-10 * np.maximum(np.abs(ref), 1.0)
+    assert (np.abs(got - ref) <= tol).all(), np.abs(got - ref).max()
+
+
 @pytest.mark.parametrize("case", TINY, ids=_ids)
 @pytest.mark.parametrize("gram", [lhf.LHF_GRAM_BF16X3, lhf.LHF_GRAM_FP16X3, lhf.LHF_GRAM_FP32, lhf.LHF_GRAM_FP64])
 def test_mixed_pipeline_matches_oracle(case, gram):
