@@ -617,6 +617,68 @@ __host__ __device__ inline int sep_stage_bytes(int B1, int J2C, int L1, int nter
   return g > t2 ? g : t2;
 }
 
+// Asynchronous staging (lattices with m0^2 a multiple of 8: whole, 16-byte
+// aligned entry chunks): kSepBufs chunk buffers, each holding per term the
+// dimension-1 Grams G1_t[s1][ec] (B1 kFusedEC doubles) and the transformed
+// factors F2_t[jj][ec] (J2C kFusedEC complex) and F3_t[ec] (kFusedEC complex),
+// copied from global memory to LDS by the 16-byte global_load_lds, every copy
+// of a chunk in flight at once.  With two buffers the next chunk is in flight
+// while the current one is summed; summing a chunk takes far less than a copy
+// round, so one buffer of twice the terms (half the rounds) is faster.
+constexpr int kSepBufs = 1;
+__host__ __device__ inline int sep_async_term_bytes(int B1, int J2C) {
+  return B1 * kFusedEC * 8 + J2C * kFusedEC * 16 + kFusedEC * 16;
+}
+// terms per buffer, 0 when fewer than two fit (terms 0 and 1 must share a chunk)
+__host__ __device__ inline int sep_async_chunk(int B1, int J2C, int L1, int nterm) {
+  const int fit = (kSepLds - kSepBufs * sep_pad_bytes(J2C) - L1 * 16) / (kSepBufs * sep_async_term_bytes(B1, J2C));
+  if (fit < 2) return 0;
+  return fit < nterm ? fit : (nterm > 2 ? nterm : 2);
+}
+__host__ __device__ inline int sep_async_buf_bytes(int B1, int J2C, int L1, int nterm) {
+  return sep_async_chunk(B1, J2C, L1, nterm) * sep_async_term_bytes(B1, J2C) + sep_pad_bytes(J2C);
+}
+__host__ __device__ inline bool sep_async_ok(int m2, int B1, int J2C, int L1, int nterm) {
+  return m2 % kFusedEC == 0 && sep_async_chunk(B1, J2C, L1, nterm) >= 2;
+}
+// LDS of the separable kernel before its twiddles, for either staging
+__host__ __device__ inline int sep_lds_stage(int m2, int B1, int J2C, int L1, int nterm) {
+  if (!sep_async_ok(m2, B1, J2C, L1, nterm)) return sep_stage_bytes(B1, J2C, L1, nterm);
+  const int g = kSepBufs * sep_async_buf_bytes(B1, J2C, L1, nterm), t2 = B1 * J2C * kFusedEC * 16;
+  return g > t2 ? g : t2;
+}
+
+// Issue the copies of one chunk (terms t0 .. t0 + tc - 1) into an LDS buffer:
+// 16-byte piece P of a region goes to region + 16 P, lane order within a wave
+__device__ __forceinline__ void sep_async_issue(char* buf, int tc, int tcap, int B1, int J2C, int j2n,
+                                                const double* g1, int64_t rowstep, const double2* f2,
+                                                int64_t st2, int m2, const double2* f3, int64_t st3) {
+  constexpr int EC = kFusedEC;
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  const int tid = threadIdx.x, wb = tid & ~63;
+  char* r1 = buf;                                              // G1 [tcap][B1][EC]
+  char* r2 = r1 + tcap * B1 * EC * 8;                          // F2 [tcap][J2C][EC]
+  char* r3 = r2 + tcap * J2C * EC * 16;                        // F3 [tcap][EC]
+  const int n1 = tc * B1 * 4, n2 = tc * J2C * EC, n3 = tc * EC;
+  for (int P = tid; P - (tid & 63) < n1; P += 256) {
+    // row r = P / 4 of 8 doubles (term t0 + r / B1, slot r mod B1), quarter P mod 4
+    if (P < n1)
+      __builtin_amdgcn_global_load_lds((const void*)(g1 + (P >> 2) * rowstep + 2 * (P & 3)),
+                                       (lds_ptr)(r1 + (P - tid + wb) * 16), 16, 0, 0);
+  }
+  for (int P = tid; P - (tid & 63) < n2; P += 256) {
+    const int tt = P / (J2C * EC), jj = (P / EC) % J2C, ec = P % EC;
+    if (P < n2 && jj < j2n)
+      __builtin_amdgcn_global_load_lds((const void*)(f2 + tt * st2 + (int64_t)jj * m2 + ec),
+                                       (lds_ptr)(r2 + (P - tid + wb) * 16), 16, 0, 0);
+  }
+  for (int P = tid; P - (tid & 63) < n3; P += 256) {
+    if (P < n3)
+      __builtin_amdgcn_global_load_lds((const void*)(f3 + (P / EC) * st3 + P % EC),
+                                       (lds_ptr)(r3 + (P - tid + wb) * 16), 16, 0, 0);
+  }
+}
+
 // Workgroup (lattice, entry chunk, j2 chunk, j3) as in dft_fused_kernel;
 // grid y: H, S.  With Q_0 = P_ks / 2, Q_1 = P_ss / 2 and Q_t = -P_t (t >= 2)
 // for H, and Q_0 = P_ss for S (one term), T2[s1] = sum_t G1_t[s1] Q_t.  The
@@ -625,7 +687,7 @@ __host__ __device__ inline int sep_stage_bytes(int B1, int J2C, int L1, int nter
 // at once, then thread (column (jj, ec), part sp) accumulates the slots
 // s1 = sp, sp + nsp, ... of its column from LDS alone.  T2 takes the stage's
 // place once every term is in.
-template <int BM>
+template <int BM, bool ASYNC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM <= 16 ? 4 : 1)))
 sep_fused_kernel(const LatDev* __restrict__ lats,
                                                         const FusedTask* __restrict__ tasks, int ntasks,
@@ -657,8 +719,10 @@ sep_fused_kernel(const LatDev* __restrict__ lats,
   const bool isH = blockIdx.y == 0;
   const int nterm = isH ? L.T : 1;
   const int tch = sep_term_chunk(B1, J2C, L1, L.T);   // the S pass fits the H chunk
-  // LDS: [Qs | G1s | padding] or T2, then tw1
-  const int stage_bytes = sep_stage_bytes(B1, J2C, L1, L.T);
+  // LDS: the stage (synchronous: [Qs | G1s | padding]; asynchronous, which the
+  // plan chooses only when every lattice allows it: two chunk buffers) or T2,
+  // then tw1
+  const int stage_bytes = ASYNC ? sep_lds_stage(m2, B1, J2C, L1, L.T) : sep_stage_bytes(B1, J2C, L1, L.T);
   C* T2 = reinterpret_cast<C*>(lds_raw);
   C* Qs = reinterpret_cast<C*>(lds_raw);                       // [tch][ncol]
   double* G1s = reinterpret_cast<double*>(Qs + tch * ncol);    // [tch][B1][EC]
@@ -679,7 +743,76 @@ sep_fused_kernel(const LatDev* __restrict__ lats,
   const double2* g2 = gh + D1.gh_off;   // [t][L2][m2]
   const double2* g3 = gh + D2.gh_off;   // [t][L3][m2]
   const int64_t st2 = (int64_t)L2 * m2, st3 = (int64_t)L3 * m2;
-  for (int t0 = 0; t0 < nterm; t0 += tch) {
+  // T2 contributions of staged term tt with product qv (G1 rows from gp)
+  auto accum = [&](const double* gp, int tt, C qv) {
+    double g[NA];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      g[u] = 0.0;
+      if (u < nu) g[u] = gp[tt * B1 * EC + u * ustride];
+    }
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      ar[u] += g[u] * qv.x;
+      ai[u] += g[u] * qv.y;
+    }
+  };
+  if constexpr (ASYNC) {
+    const int tcap = sep_async_chunk(B1, J2C, L1, L.T), bufb = sep_async_buf_bytes(B1, J2C, L1, L.T);
+    const int64_t rowstep = (int64_t)(B1 == 1 ? D0.nshift : 1) * m2;   // staged row r: Gram block t0 nshift + r rs
+    const double* g1b = grams + D0.gram_off + e0;
+    const double2* f2b = g2 + (int64_t)j2lo * m2 + e0;
+    const double2* f3b = g3 + (int64_t)j3 * m2 + e0;
+    const int nch = (nterm + tcap - 1) / tcap;
+    auto issue = [&](int k) {
+      const int t0 = k * tcap, tc = min(tcap, nterm - t0);
+      sep_async_issue(lds_raw + (k % kSepBufs) * bufb, tc, tcap, B1, J2C, j2n, g1b + (int64_t)t0 * D0.nshift * m2, rowstep,
+                      f2b + t0 * st2, st2, m2, f3b + t0 * st3, st3);
+    };
+    issue(0);
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's copies have landed
+    __syncthreads();                 // and everyone's
+    for (int k = 0; k < nch; ++k) {
+      // with two buffers the next chunk goes to the other one, whose last
+      // reader passed the barrier below
+      if (kSepBufs == 2 && k + 1 < nch) issue(k + 1);
+      const int t0 = k * tcap, tc = min(tcap, nterm - t0);
+      if (mine) {
+        const char* buf = lds_raw + (k % kSepBufs) * bufb;
+        const double* gp = reinterpret_cast<const double*>(buf) + sp * EC + ec;
+        const C* F2 = reinterpret_cast<const C*>(buf + tcap * B1 * EC * 8) + jj * EC + ec;   // [tt][J2C][EC]
+        const C* F3 = reinterpret_cast<const C*>(buf + tcap * B1 * EC * 8 + tcap * J2C * EC * 16) + ec;   // [tt][EC]
+        int tt0 = 0;
+        if (t0 == 0) {
+          // terms 0 and 1 from S^2, S^3 (t = 0) and K^2, K^3 (t = 1)
+          const C S2 = F2[0], S3 = F3[0];
+          const C pss = make_double2(S2.x * S3.x - S2.y * S3.y, S2.x * S3.y + S2.y * S3.x);
+          if (isH) {
+            const C K2 = F2[J2C * EC], K3 = F3[EC];
+            accum(gp, 0, make_double2(0.5 * ((K2.x * S3.x - K2.y * S3.y) + (S2.x * K3.x - S2.y * K3.y)),
+                                      0.5 * ((K2.x * S3.y + K2.y * S3.x) + (S2.x * K3.y + S2.y * K3.x))));
+            accum(gp, 1, make_double2(0.5 * pss.x, 0.5 * pss.y));
+            tt0 = 2;
+          } else {
+            accum(gp, 0, pss);
+            tt0 = 1;
+          }
+        }
+#pragma unroll 1
+        for (int tt = tt0; tt < tc; ++tt) {
+          const C a = F2[tt * J2C * EC], b = F3[tt * EC];
+          accum(gp, tt, make_double2(-(a.x * b.x - a.y * b.y), -(a.x * b.y + a.y * b.x)));
+        }
+      }
+      if (kSepBufs == 1 && k + 1 < nch) {
+        __syncthreads();   // this chunk is read
+        issue(k + 1);
+      }
+      __builtin_amdgcn_s_waitcnt(0);   // the next chunk's copies have landed
+      __syncthreads();                 // everyone's, and this chunk is read
+    }
+  }
+  for (int t0 = 0; !ASYNC && t0 < nterm; t0 += tch) {
     const int tc = min(tch, nterm - t0);
     if (t0 > 0) __syncthreads();   // the previous chunk is consumed
     // the thread's first item, opaque so that no item's index is kept across chunks
@@ -1034,7 +1167,7 @@ void plan_block_dft(const std::vector<LatDev>& lats, int64_t target_threads, std
 // 64 KiB of LDS.
 void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tasks, std::vector<GhItem>& items,
                     int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, std::vector<FusedTask>& chain,
-                    int64_t& chain_wgs, bool& ok) {
+                    int64_t& chain_wgs, bool& ok, bool& async) {
   tasks.clear();
   items.clear();
   chain.clear();
@@ -1044,6 +1177,8 @@ void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tas
   lds = 0;
   gh_threads = 0;
   ok = !lats.empty();
+  async = true;
+  int32_t lds_sync = 0, lds_async = 0;
   for (int li = 0; li < (int)lats.size(); ++li) {
     const LatDev& L = lats[li];
     const int B1 = nslot(L.dim[0]);
@@ -1067,19 +1202,27 @@ void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tas
     t.nec = (L.m0 * L.m0 + kFusedEC - 1) / kFusedEC;
     t.J2C = std::min(L.L[1], kFusedJ2);
     t.nj2c = (L.L[1] + t.J2C - 1) / t.J2C;
-    // the Gram stage or T2, whichever is larger, then the dimension-1 twiddles
-    const int64_t bytes = (int64_t)sep_stage_bytes(B1, t.J2C, L.L[0], L.T) + (int64_t)L.L[0] * 16;
-    if (B1 > 32 || bytes > 65536) ok = false;
+    // the stage of either staging or T2, whichever is larger, then the
+    // dimension-1 twiddles; the asynchronous copies need every lattice to
+    // allow them, with 16-byte aligned Gram rows
+    const int m2 = L.m0 * L.m0;
+    const int64_t bsync = (int64_t)sep_stage_bytes(B1, t.J2C, L.L[0], L.T) + (int64_t)L.L[0] * 16;
+    const int64_t basync = (int64_t)sep_lds_stage(m2, B1, t.J2C, L.L[0], L.T) + (int64_t)L.L[0] * 16;
+    if (B1 > 32 || bsync > 65536) ok = false;
+    if (!sep_async_ok(m2, B1, t.J2C, L.L[0], L.T) || (L.dim[0].gram_off & 1) != 0 || basync > 65536) async = false;
     t.wg_base = wgs;
     wgs += (int64_t)L.L[2] * t.nj2c * t.nec;
     tasks.push_back(t);
     bmax = std::max(bmax, B1);
-    lds = std::max<int32_t>(lds, (int32_t)bytes);
+    lds_sync = std::max<int32_t>(lds_sync, (int32_t)bsync);
+    lds_async = std::max<int32_t>(lds_async, (int32_t)basync);
     for (int d = 1; d < 3; ++d) {
       items.push_back(GhItem{li, d, gh_threads});
       gh_threads += ((int64_t)L.T * L.L[d] * L.m0 * L.m0 + 255) / 256 * 256;
     }
   }
+  if (tasks.empty()) async = false;
+  lds = async ? lds_async : lds_sync;
   order_fused_tasks(lats, tasks, false);
   order_fused_tasks(lats, chain, true);
 }
@@ -1096,15 +1239,21 @@ hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* g
                      p->d_gh_items, p->n_gh_items, g64, p->d_tw64, gh);
   const dim3 grid((unsigned)p->sep_wgs, 2);
   const size_t shb = (size_t)p->sep_lds;
-  if (p->sep_bmax <= 8)
-    hipLaunchKernelGGL(sep_fused_kernel<8>, grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, p->d_tw64, g64,
-                       gh, bar_h, bar_s, hf);
-  else if (p->sep_bmax <= 16)
-    hipLaunchKernelGGL(sep_fused_kernel<16>, grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, p->d_tw64, g64,
-                       gh, bar_h, bar_s, hf);
-  else
-    hipLaunchKernelGGL(sep_fused_kernel<32>, grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, p->d_tw64, g64,
-                       gh, bar_h, bar_s, hf);
+#define LHF_SEP(BM)                                                                                          \
+  if (p->sep_async)                                                                                          \
+    hipLaunchKernelGGL((sep_fused_kernel<BM, true>), grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep,  \
+                       p->d_tw64, g64, gh, bar_h, bar_s, hf);                                                \
+  else                                                                                                       \
+    hipLaunchKernelGGL((sep_fused_kernel<BM, false>), grid, dim3(256), shb, s, p->d_lat, p->d_sep, p->n_sep, \
+                       p->d_tw64, g64, gh, bar_h, bar_s, hf);
+  if (p->sep_bmax <= 8) {
+    LHF_SEP(8)
+  } else if (p->sep_bmax <= 16) {
+    LHF_SEP(16)
+  } else {
+    LHF_SEP(32)
+  }
+#undef LHF_SEP
   return hipGetLastError();
 }
 

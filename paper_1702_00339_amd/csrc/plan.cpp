@@ -286,7 +286,7 @@ int32_t lhf_plan_create(const lhf_lattice* lats, int32_t nlat, int32_t prec, int
   std::vector<GhItem> gh_items;
   std::vector<FusedTask> sep_chain;
   plan_separable(p->lat, sep, gh_items, p->sep_wgs, p->sep_bmax, p->sep_lds, p->gh_threads, sep_chain,
-                 p->sep_chain_wgs, p->sep_ok);
+                 p->sep_chain_wgs, p->sep_ok, p->sep_async);
   p->n_sep = (int32_t)sep.size();
   p->n_sep_chain = (int32_t)sep_chain.size();
   p->n_gh_items = (int32_t)gh_items.size();

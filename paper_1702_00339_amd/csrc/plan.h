@@ -43,6 +43,7 @@ struct lhf_plan_s {
   int64_t sep_wgs = 0;
   int32_t sep_bmax = 0;                 // largest first-dimension band
   int32_t sep_lds = 0;                  // bytes of LDS per workgroup
+  bool sep_async = false;               // the separable kernel stages by asynchronous copies (every lattice allows it)
   lhf::GhItem* d_gh_items = nullptr;    // 1D transforms of the Grams along dimensions 2, 3
   int32_t n_gh_items = 0;
   int64_t gh_threads = 0;
@@ -120,7 +121,7 @@ hipError_t launch_block_dft(const lhf_plan_s* p, int prec, const void* gen_h, co
 // blockdft.hip: separable Fourier blocks from the FP64 Grams (complex128 out)
 void plan_separable(const std::vector<LatDev>& lats, std::vector<FusedTask>& tasks, std::vector<GhItem>& items,
                     int64_t& wgs, int32_t& bmax, int32_t& lds, int64_t& gh_threads, std::vector<FusedTask>& chain,
-                    int64_t& chain_wgs, bool& ok);
+                    int64_t& chain_wgs, bool& ok, bool& async);
 hipError_t launch_fourier_sep(const lhf_plan_s* p, const double* g64, double2* gh, double2* bar_h, double2* bar_s,
                               hipStream_t s, bool half = false);
 // eigvec.hip: full-lattice eigenvectors of selected (block, column) pairs of one lattice

@@ -90,10 +90,12 @@ def test_fp64_pipeline_matches_oracle(case, fourier):
 
 
 # lattices with one cell along the first axis: the dimension-1 Grams keep
-# every image shift while the band has one slot
+# every image shift while the band has one slot (m0^2 a multiple of 8 takes
+# the asynchronous staging, the others the synchronous one)
 FIRST_AXIS_ONE = [
     dict(L=(1, 4, 3), n=(14, 32, 24), n_s=2, n_p=1, seed=112),                   # 3D
     dict(L=(1, 5, 1), n=(16, 40, 12), n_s=3, n_p=0, seed=113),                   # 2D, odd L2
+    dict(L=(1, 4, 3), n=(14, 32, 24), n_s=4, n_p=0, seed=114),                   # m0 = 4: asynchronous staging
 ]
 
 
