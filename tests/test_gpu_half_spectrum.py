@@ -121,6 +121,30 @@ def test_fourier_blocks_half_is_the_kept_planes():
         off += L1 * L2 * L3 * E
 
 
+def test_fourier_blocks_half_asynchronous_staging():
+    """The separable route's half layout when every lattice has m0^2 a
+    multiple of 8 (the asynchronously staged kernel), even and odd L3; the
+    full blocks of that kernel against the block DFT route."""
+    insts = [tiny_instance(L=(4, 3, 2), n=(32, 24, 16), n_s=4, n_p=0, seed=208, R=6),
+             tiny_instance(L=(6, 2, 5), n=(48, 16, 40), n_s=4, n_p=0, seed=209, R=6)]
+    assert all(i.m0 * i.m0 % 8 == 0 for i in insts)
+    pipe = Pipeline(insts, prec=lhf.LHF_PREC_FP64, fourier="dft")
+    pipe.step()   # fills the FP64 Grams and the block DFT's Fourier blocks
+    Hd, Sd = pipe.H_bar.clone(), pipe.S_bar.clone()
+    sz = pipe.plan.sizes
+    Hf = torch.zeros(int(sz.gen_elems), dtype=torch.complex128, device="cuda")
+    Sf = torch.zeros_like(Hf)
+    Hh = torch.full((int(sz.half_elems),), float("nan"), dtype=torch.complex128, device="cuda")
+    Sh = torch.full_like(Hh, float("nan"))
+    pipe.plan.lhf_fourier_blocks(pipe.grams64, Hf, Sf, pipe.ws)
+    pipe.plan.lhf_fourier_blocks_half(pipe.grams64, Hh, Sh, pipe.ws)
+    torch.cuda.synchronize()
+    assert (Hf - Hd).abs().max().item() <= 1e-13 * Hd.abs().max().item()
+    assert (Sf - Sd).abs().max().item() <= 1e-13 * Sd.abs().max().item()
+    _check_half(insts, Hf, Hh)
+    _check_half(insts, Sf, Sh)
+
+
 def test_half_rejects_missing_buffers():
     pipe = Pipeline(tiny_instance(**{"R": 6, **SHAPES[0]}), prec=lhf.LHF_PREC_FP64, fourier="dft")
     with pytest.raises(lhf.LhfError):
