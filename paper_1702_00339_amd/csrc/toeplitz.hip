@@ -366,16 +366,17 @@ __device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((un
 
 // In-place radix-2 transform of CB columns of length P in LDS (natural-order
 // output from bit-reversed input).  INV: conjugate twiddles.
+// P = 2^bits, so every index of a butterfly is a shift or a mask
 template <typename C, bool INV>
 __device__ void fft_lds(C* a, int P, int bits, int CB, const C* __restrict__ tw) {
   for (int s = 1; s <= bits; ++s) {
+    const int hb = bits - 1;   // P / 2 = 2^hb butterflies per column
     const int half = 1 << (s - 1);
-    const int tstride = P >> s;
-    for (int b = threadIdx.x; b < CB * (P / 2); b += blockDim.x) {
-      const int cc = b / (P / 2), bb = b % (P / 2);
-      const int grp = bb / half, pos = bb % half;
-      const int i0 = grp * 2 * half + pos, i1 = i0 + half;
-      C w = tw[pos * tstride];
+    for (int b = threadIdx.x; b < (CB << hb); b += blockDim.x) {
+      const int cc = b >> hb, bb = b & ((1 << hb) - 1);
+      const int grp = bb >> (s - 1), pos = bb & (half - 1);
+      const int i0 = (grp << s) + pos, i1 = i0 + half;
+      C w = tw[pos << (bits - s)];   // w_P^(pos P / 2^s)
       if (INV) w.y = -w.y;
       C* col = a + cc * P;
       const C u = col[i0], v0 = col[i1];
@@ -402,7 +403,7 @@ __global__ void __launch_bounds__(256) fft_fwd_kernel(int L, int m0, int P, int 
   const int ncol = m0 * ncols;
   const int c0 = blockIdx.x * CB;
   for (int e = threadIdx.x; e < CB * P; e += 256) {
-    const int cc = e / P, k = e % P, c = c0 + cc;
+    const int cc = e >> bits, k = e & (P - 1), c = c0 + cc;
     C v;
     v.x = 0;
     v.y = 0;
@@ -415,7 +416,7 @@ __global__ void __launch_bounds__(256) fft_fwd_kernel(int L, int m0, int P, int 
   __syncthreads();
   fft_lds<C, false>(a, P, bits, CB, tw);
   for (int e = threadIdx.x; e < CB * P; e += 256) {
-    const int cc = e / P, f = e % P, c = c0 + cc;
+    const int cc = e >> bits, f = e & (P - 1), c = c0 + cc;
     if (c < ncol) xhat[(int64_t)f * ncol + c] = a[cc * P + f];
   }
 }
@@ -470,7 +471,7 @@ __global__ void __launch_bounds__(256) fft_inv_kernel(int L, int m0, int P, int 
   const C* src = blockIdx.y == 0 ? yhH : yhS;
   IO* y = blockIdx.y == 0 ? yH : yS;
   for (int e = threadIdx.x; e < CB * P; e += 256) {
-    const int cc = e / P, f = e % P, c = c0 + cc;
+    const int cc = e >> bits, f = e & (P - 1), c = c0 + cc;
     C v;
     v.x = 0;
     v.y = 0;
