@@ -364,27 +364,66 @@ __global__ void __launch_bounds__(256) to32_kernel(const double2* __restrict__ s
 
 __device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
 
-// In-place radix-2 transform of CB columns of length P in LDS (natural-order
-// output from bit-reversed input).  INV: conjugate twiddles.
-// P = 2^bits, so every index of a butterfly is a shift or a mask
+// In-place radix-2 transform of CB columns of length P = 2^bits in LDS
+// (natural-order output from bit-reversed input).  INV: conjugate twiddles.
+// Stages go in pairs: a thread takes the four elements i0 + {0, 1, 2, 3} h
+// (h = 2^(s-1)) through stage s (pairs (0, 1), (2, 3), twiddle of position p)
+// and stage s + 1 (pairs (0, 2), (1, 3), twiddles of p and p + h), one barrier
+// and one LDS pass per pair; an odd last stage runs alone.  Every index is a
+// shift or a mask.
+template <typename C, bool INV>
+__device__ __forceinline__ C fft_tw(const C* __restrict__ tw, int k) {
+  C w = tw[k];
+  if (INV) w.y = -w.y;
+  return w;
+}
+template <typename C>
+__device__ __forceinline__ C fft_mul(C a, C w) {
+  C v;
+  v.x = a.x * w.x - a.y * w.y;
+  v.y = a.x * w.y + a.y * w.x;
+  return v;
+}
+template <typename C>
+__device__ __forceinline__ void fft_bfly(C& a, C& b, C w) {
+  const C v = fft_mul(b, w);
+  b.x = a.x - v.x;
+  b.y = a.y - v.y;
+  a.x = a.x + v.x;
+  a.y = a.y + v.y;
+}
 template <typename C, bool INV>
 __device__ void fft_lds(C* a, int P, int bits, int CB, const C* __restrict__ tw) {
-  for (int s = 1; s <= bits; ++s) {
-    const int hb = bits - 1;   // P / 2 = 2^hb butterflies per column
-    const int half = 1 << (s - 1);
+  int s = 1;
+  for (; s + 1 <= bits; s += 2) {
+    const int half = 1 << (s - 1), qb = bits - 2;   // P / 4 = 2^qb groups of four per column
+    for (int q = threadIdx.x; q < (CB << qb); q += blockDim.x) {
+      const int cc = q >> qb, qq = q & ((1 << qb) - 1);
+      const int grp = qq >> (s - 1), pos = qq & (half - 1);
+      C* col = a + cc * P + (grp << (s + 1)) + pos;
+      C x0 = col[0], x1 = col[half], x2 = col[2 * half], x3 = col[3 * half];
+      const C w = fft_tw<C, INV>(tw, pos << (bits - s));
+      fft_bfly(x0, x1, w);
+      fft_bfly(x2, x3, w);
+      fft_bfly(x0, x2, fft_tw<C, INV>(tw, pos << (bits - s - 1)));
+      fft_bfly(x1, x3, fft_tw<C, INV>(tw, (pos + half) << (bits - s - 1)));
+      col[0] = x0;
+      col[half] = x1;
+      col[2 * half] = x2;
+      col[3 * half] = x3;
+    }
+    __syncthreads();
+  }
+  if (s == bits) {
+    const int hb = bits - 1, half = 1 << (s - 1);
     for (int b = threadIdx.x; b < (CB << hb); b += blockDim.x) {
       const int cc = b >> hb, bb = b & ((1 << hb) - 1);
       const int grp = bb >> (s - 1), pos = bb & (half - 1);
-      const int i0 = (grp << s) + pos, i1 = i0 + half;
-      C w = tw[pos << (bits - s)];   // w_P^(pos P / 2^s)
-      if (INV) w.y = -w.y;
-      C* col = a + cc * P;
-      const C u = col[i0], v0 = col[i1];
-      C v;
-      v.x = v0.x * w.x - v0.y * w.y;
-      v.y = v0.x * w.y + v0.y * w.x;
-      col[i0].x = u.x + v.x; col[i0].y = u.y + v.y;
-      col[i1].x = u.x - v.x; col[i1].y = u.y - v.y;
+      C* col = a + cc * P + (grp << s) + pos;
+      C x0 = col[0], x1 = col[half];
+      fft_bfly(x0, x1, fft_tw<C, INV>(tw, pos << (bits - s)));
+      col[0] = x0;
+      col[half] = x1;
     }
     __syncthreads();
   }
