@@ -364,8 +364,8 @@ __global__ void __launch_bounds__(256) to32_kernel(const double2* __restrict__ s
 
 __device__ __forceinline__ int bitrev(int x, int bits) { return (int)(__brev((unsigned)x) >> (32 - bits)); }
 
-// In-place radix-2 transform of CB columns of length P = 2^bits in LDS
-// (natural-order output from bit-reversed input).  INV: conjugate twiddles.
+// In-place radix-2 transform of CB columns of length P = 2^bits in LDS, S
+// apart (natural-order output from bit-reversed input).  INV: conjugate twiddles.
 // Stages go in pairs: a thread takes the four elements i0 + {0, 1, 2, 3} h
 // (h = 2^(s-1)) through stage s (pairs (0, 1), (2, 3), twiddle of position p)
 // and stage s + 1 (pairs (0, 2), (1, 3), twiddles of p and p + h), one barrier
@@ -393,14 +393,14 @@ __device__ __forceinline__ void fft_bfly(C& a, C& b, C w) {
   a.y = a.y + v.y;
 }
 template <typename C, bool INV>
-__device__ void fft_lds(C* a, int P, int bits, int CB, const C* __restrict__ tw) {
+__device__ void fft_lds(C* a, int P, int S, int bits, int CB, const C* __restrict__ tw) {
   int s = 1;
   for (; s + 1 <= bits; s += 2) {
     const int half = 1 << (s - 1), qb = bits - 2;   // P / 4 = 2^qb groups of four per column
     for (int q = threadIdx.x; q < (CB << qb); q += blockDim.x) {
       const int cc = q >> qb, qq = q & ((1 << qb) - 1);
       const int grp = qq >> (s - 1), pos = qq & (half - 1);
-      C* col = a + cc * P + (grp << (s + 1)) + pos;
+      C* col = a + cc * S + (grp << (s + 1)) + pos;
       C x0 = col[0], x1 = col[half], x2 = col[2 * half], x3 = col[3 * half];
       const C w = fft_tw<C, INV>(tw, pos << (bits - s));
       fft_bfly(x0, x1, w);
@@ -419,7 +419,7 @@ __device__ void fft_lds(C* a, int P, int bits, int CB, const C* __restrict__ tw)
     for (int b = threadIdx.x; b < (CB << hb); b += blockDim.x) {
       const int cc = b >> hb, bb = b & ((1 << hb) - 1);
       const int grp = bb >> (s - 1), pos = bb & (half - 1);
-      C* col = a + cc * P + (grp << s) + pos;
+      C* col = a + cc * S + (grp << s) + pos;
       C x0 = col[0], x1 = col[half];
       fft_bfly(x0, x1, fft_tw<C, INV>(tw, pos << (bits - s)));
       col[0] = x0;
@@ -441,8 +441,12 @@ __global__ void __launch_bounds__(256) fft_fwd_kernel(int L, int m0, int P, int 
   C* a = reinterpret_cast<C*>(lraw);
   const int ncol = m0 * ncols;
   const int c0 = blockIdx.x * CB;
+  // the workgroup's CB columns are adjacent in x and in xhat, so consecutive
+  // threads take consecutive columns (CB is a power of two); columns sit
+  // S = P + 1 apart in LDS, off one bank
+  const int cbits = __builtin_ctz(CB), S = P + 1;
   for (int e = threadIdx.x; e < CB * P; e += 256) {
-    const int cc = e >> bits, k = e & (P - 1), c = c0 + cc;
+    const int cc = e & (CB - 1), k = e >> cbits, c = c0 + cc;
     C v;
     v.x = 0;
     v.y = 0;
@@ -450,13 +454,13 @@ __global__ void __launch_bounds__(256) fft_fwd_kernel(int L, int m0, int P, int 
       const int mu = c / ncols, j = c % ncols;
       v.x = (R)x[((int64_t)k * m0 + mu) * ld + j];
     }
-    a[cc * P + bitrev(k, bits)] = v;
+    a[cc * S + bitrev(k, bits)] = v;
   }
   __syncthreads();
-  fft_lds<C, false>(a, P, bits, CB, tw);
+  fft_lds<C, false>(a, P, S, bits, CB, tw);
   for (int e = threadIdx.x; e < CB * P; e += 256) {
-    const int cc = e >> bits, f = e & (P - 1), c = c0 + cc;
-    if (c < ncol) xhat[(int64_t)f * ncol + c] = a[cc * P + f];
+    const int cc = e & (CB - 1), f = e >> cbits, c = c0 + cc;
+    if (c < ncol) xhat[(int64_t)f * ncol + c] = a[cc * S + f];
   }
 }
 
@@ -509,22 +513,24 @@ __global__ void __launch_bounds__(256) fft_inv_kernel(int L, int m0, int P, int 
   const int c0 = blockIdx.x * CB;
   const C* src = blockIdx.y == 0 ? yhH : yhS;
   IO* y = blockIdx.y == 0 ? yH : yS;
+  // consecutive threads take consecutive (adjacent) columns, as in the forward kernel
+  const int cbits = __builtin_ctz(CB), S = P + 1;
   for (int e = threadIdx.x; e < CB * P; e += 256) {
-    const int cc = e >> bits, f = e & (P - 1), c = c0 + cc;
+    const int cc = e & (CB - 1), f = e >> cbits, c = c0 + cc;
     C v;
     v.x = 0;
     v.y = 0;
     if (c < ncol) v = src[(int64_t)f * ncol + c];
-    a[cc * P + bitrev(f, bits)] = v;
+    a[cc * S + bitrev(f, bits)] = v;
   }
   __syncthreads();
-  fft_lds<C, true>(a, P, bits, CB, tw);
+  fft_lds<C, true>(a, P, S, bits, CB, tw);
   const double inv = 1.0 / P;
   for (int e = threadIdx.x; e < CB * L; e += 256) {
-    const int cc = e / L, k = e % L, c = c0 + cc;
+    const int cc = e & (CB - 1), k = e >> cbits, c = c0 + cc;
     if (c < ncol) {
       const int mu = c / ncols, j = c % ncols;
-      y[((int64_t)k * m0 + mu) * ld + j] = (IO)((double)a[cc * P + k].x * inv);
+      y[((int64_t)k * m0 + mu) * ld + j] = (IO)((double)a[cc * S + k].x * inv);
     }
   }
 }
@@ -594,11 +600,13 @@ hipError_t apply_t(int L, int m0, int P, int ncols, const IO* x, int ld, const v
   typedef typename Cx<R>::T C;
   int bits = 0;
   while ((1 << bits) < P) ++bits;
-  const int CB = std::max(1, std::min(16, 65536 / (P * (int)sizeof(C))));
+  const int CB = std::max(1, std::min(16, 65536 / (P * (int)sizeof(C))));   // a power of two (P is)
   const int ncol = m0 * ncols;
   const unsigned gx = (unsigned)((ncol + CB - 1) / CB);
-  const size_t lds = (size_t)CB * P * sizeof(C);
+  const size_t lds = (size_t)CB * (P + 1) * sizeof(C);   // columns P + 1 apart
   const int nops = opS ? 2 : 1;
+  (void)hipFuncSetAttribute((const void*)fft_fwd_kernel<R, IO>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)fft_inv_kernel<R, IO>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL((fft_fwd_kernel<R, IO>), dim3(gx), dim3(256), lds, s, L, m0, P, bits, ncols, CB, x, ld,
                      (const C*)tw, (C*)xhat);
   const size_t lm = sizeof(C) * ((size_t)m0 * m0 + (size_t)m0 * ncols);
