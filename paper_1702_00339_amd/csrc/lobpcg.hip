@@ -188,7 +188,10 @@ __global__ void __launch_bounds__(256) combine_kernel(int N, int k1, int k2, con
   }
 }
 
-// R = HX - SX diag(theta); part[c][j] = sum over chunk rows of R^2
+// R = HX - SX diag(theta); part[c][j] = sum over chunk rows of R^2.  The
+// blocks are row-major, so consecutive threads take consecutive columns of a
+// tile of up to 256 (coalesced) and 256 / kc row lanes walk the chunk's rows;
+// the lanes' sums of a column are added in lane order.
 __global__ void __launch_bounds__(256) residual_kernel(int N, int k, int chunk, const double* __restrict__ HX,
                                                        const double* __restrict__ SX, int ld,
                                                        const double* __restrict__ theta, double* __restrict__ R,
@@ -196,20 +199,25 @@ __global__ void __launch_bounds__(256) residual_kernel(int N, int k, int chunk, 
   __shared__ double red[256];
   const int c = blockIdx.x;
   const int n0 = c * chunk, n1 = min(N, n0 + chunk);
-  for (int j = 0; j < k; ++j) {
+  for (int j0 = 0; j0 < k; j0 += 256) {
+    const int kc = min(256, k - j0), nr = 256 / kc;
+    const int jl = threadIdx.x % kc, rl = threadIdx.x / kc, j = j0 + jl;
     double s = 0.0;
-    for (int n = n0 + threadIdx.x; n < n1; n += 256) {
-      const double r = HX[(int64_t)n * ld + j] - SX[(int64_t)n * ld + j] * theta[j];
-      R[(int64_t)n * ldr + j] = r;
-      s += r * r;
+    if (rl < nr) {
+      const double th = theta[j];
+      for (int n = n0 + rl; n < n1; n += nr) {
+        const double r = HX[(int64_t)n * ld + j] - SX[(int64_t)n * ld + j] * th;
+        R[(int64_t)n * ldr + j] = r;
+        s += r * r;
+      }
     }
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
+    if (threadIdx.x < kc) {
+      double t = 0.0;
+      for (int q = 0; q < nr; ++q) t += red[q * kc + threadIdx.x];
+      part[(int64_t)c * k + j0 + threadIdx.x] = t;
     }
-    if (threadIdx.x == 0) part[(int64_t)c * k + j] = red[0];
     __syncthreads();
   }
 }
