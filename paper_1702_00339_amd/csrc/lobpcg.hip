@@ -110,6 +110,7 @@ constexpr int kCbR = 32;                              // rows per combine workgr
 constexpr int kCbK = 16;                              // inner-dimension chunk staged per step
 constexpr int kCbC = 8;                               // columns per thread
 constexpr int kCbG = (kMaxSmall + kCbC - 1) / kCbC;   // 14 column groups
+static_assert(kCbC == 8, "the combine kernel's column-slot dispatch covers 1 .. 8");
 
 // Y_a = beta Z + A_a T for a = blockIdx.y (beta only with one product).  A
 // workgroup owns kCbR rows; thread (rg, cg) owns rows 2 rg, 2 rg + 1 and
@@ -126,6 +127,7 @@ __global__ void __launch_bounds__(256) combine_kernel(int N, int k1, int k2, con
   const int r0 = blockIdx.x * kCbR, t = threadIdx.x;
   const int rg = t / kCbG, cg = t % kCbG;
   const bool act = rg < kCbR / 2;
+  const int ncu = (k2 + kCbG - 1) / kCbG;   // column slots in use (uniform)
   double acc[2][kCbC];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -161,15 +163,30 @@ __global__ void __launch_bounds__(256) combine_kernel(int N, int k1, int k2, con
     __syncthreads();
     if (kc + kCbK < k1) fetch(kc + kCbK);
     if (act) {
+      // only the column slots c < ncu reach a column j = cg + kCbG c < k2
+      // (the others would multiply staged zeros), unrolled per count
+      auto sums = [&](auto ncc) {
+        constexpr int NC = decltype(ncc)::value;
 #pragma unroll 4
-      for (int kk = 0; kk < kCbK; ++kk) {
-        const double a0 = As[2 * rg][kk], a1 = As[2 * rg + 1][kk];
+        for (int kk = 0; kk < kCbK; ++kk) {
+          const double a0 = As[2 * rg][kk], a1 = As[2 * rg + 1][kk];
 #pragma unroll
-        for (int c = 0; c < kCbC; ++c) {
-          const double tv = Ts[kk][cg + kCbG * c];
-          acc[0][c] += a0 * tv;
-          acc[1][c] += a1 * tv;
+          for (int c = 0; c < NC; ++c) {
+            const double tv = Ts[kk][cg + kCbG * c];
+            acc[0][c] += a0 * tv;
+            acc[1][c] += a1 * tv;
+          }
         }
+      };
+      switch (ncu) {
+        case 1: sums(std::integral_constant<int, 1>{}); break;
+        case 2: sums(std::integral_constant<int, 2>{}); break;
+        case 3: sums(std::integral_constant<int, 3>{}); break;
+        case 4: sums(std::integral_constant<int, 4>{}); break;
+        case 5: sums(std::integral_constant<int, 5>{}); break;
+        case 6: sums(std::integral_constant<int, 6>{}); break;
+        case 7: sums(std::integral_constant<int, 7>{}); break;
+        default: sums(std::integral_constant<int, kCbC>{}); break;
       }
     }
     __syncthreads();
