@@ -239,13 +239,21 @@ __global__ void __launch_bounds__(256) residual_kernel(int N, int k, int chunk, 
   }
 }
 
+// norms[j] = sqrt(sum over chunks of part[c][j]): one workgroup per column,
+// the chunks strided over its threads, then a tree in LDS (fixed order)
 __global__ void __launch_bounds__(256) norms_kernel(int k, int nchunk, const double* __restrict__ part,
                                                     double* __restrict__ norms) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= k) return;
+  __shared__ double red[256];
+  const int j = blockIdx.x;
   double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * k + j];
-  norms[j] = sqrt(s);
+  for (int c = threadIdx.x; c < nchunk; c += 256) s += part[(int64_t)c * k + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) norms[j] = sqrt(red[0]);
 }
 
 // SplitMix64 (Steele, Lea and Flood, 2014): a counter-based stream; values
@@ -443,7 +451,7 @@ hipError_t dense_residual(int N, int k, const double* HX, const double* SX, int 
                           int ldr, double* part, int nchunk, double* norms, hipStream_t s) {
   const int chunk = (N + nchunk - 1) / nchunk;
   hipLaunchKernelGGL(residual_kernel, dim3(nchunk), dim3(256), 0, s, N, k, chunk, HX, SX, ld, theta, R, ldr, part);
-  hipLaunchKernelGGL(norms_kernel, dim3((k + 255) / 256), dim3(256), 0, s, k, nchunk, part, norms);
+  if (k > 0) hipLaunchKernelGGL(norms_kernel, dim3(k), dim3(256), 0, s, k, nchunk, part, norms);
   return hipGetLastError();
 }
 

@@ -653,7 +653,7 @@ int32_t lhf_toeplitz_matvec_f32(lhf_toeplitz_t t, int32_t ncols, const float* x,
 namespace {
 
 constexpr int kGuard = 4;     // block vectors beyond the wanted ones
-constexpr int kChunks = 32;   // row chunks of the residual norms
+constexpr int kChunks = 256;   // row chunks of the residual norms (a workgroup each)
 constexpr int kGramChunks = 64;   // row chunks of the Gram products
 constexpr double kDropPivot = 1e-10;   // Cholesky-QR: squared relative distance below which a column is dropped
 
