@@ -563,15 +563,39 @@ __global__ void __launch_bounds__(256) cross_apply_kernel(int m0, int ncols, con
   double acc[kCrossAcc];
 #pragma unroll
   for (int t = 0; t < kCrossAcc; ++t) acc[t] = 0.0;
-  for (int q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
+  // the next entry's D_q and x block are fetched into registers while the
+  // current one is used
+  constexpr int kFD = kMaxM0 * kMaxM0 / 256, kFX = kMaxM0 * kCrossJ / 256;
+  double rd[kFD], rx[kFX];
+  auto fetch = [&](int q) {
     const int m = ent[q].m;
     const double* d = Dm + (int64_t)q * mm;
-    for (int e = threadIdx.x; e < mm; e += 256) ds[e / m0][e % m0] = d[e];
-    for (int e = threadIdx.x; e < m0 * kCrossJ; e += 256) {
-      const int nu = e / kCrossJ, jj = e % kCrossJ;
-      xs[nu][jj] = j0 + jj < ncols ? (double)x[((int64_t)m * m0 + nu) * ld + j0 + jj] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kFD; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      rd[u] = e < mm ? d[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kFX; ++u) {
+      const int e = threadIdx.x + 256 * u, nu = e / kCrossJ, jj = e % kCrossJ;
+      rx[u] = e < m0 * kCrossJ && j0 + jj < ncols ? (double)x[((int64_t)m * m0 + nu) * ld + j0 + jj] : 0.0;
+    }
+  };
+  const int qa = row_ptr[r], qe = row_ptr[r + 1];
+  if (qa < qe) fetch(qa);
+  for (int q = qa; q < qe; ++q) {
+#pragma unroll
+    for (int u = 0; u < kFD; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < mm) ds[e / m0][e % m0] = rd[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kFX; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if (e < m0 * kCrossJ) xs[e / kCrossJ][e % kCrossJ] = rx[u];
     }
     __syncthreads();
+    if (q + 1 < qe) fetch(q + 1);
     for (int nu = 0; nu < m0; ++nu) {
       const double xv = xs[nu][jl];
 #pragma unroll
