@@ -59,11 +59,11 @@ HEEV_FLOPS_PER_M3 = 150.0                    # algorithmic eigensolve work per b
 TRAFFIC_KIB = {
     "c2": {
         "eigensolve": {"kib": 1233.2, "route": "fp64=4,wide=4", "src": ["heev.hip", "sturm.h", "dpp.h"], "sha": "2d52cf7efc8892d1"},
-        "fourier": {"kib": 4123.2, "route": "sep", "src": ["blockdft.hip"], "sha": "24fdb510881ca36f"},
+        "fourier": {"kib": 4123.2, "route": "sep", "src": ["blockdft.hip"], "sha": "550f7bca970db033"},
     },
     "c3": {
         "eigensolve": {"kib": 35988.9, "route": "fp64=2,wide=0", "src": ["heev.hip", "sturm.h", "dpp.h"], "sha": "2d52cf7efc8892d1"},
-        "fourier": {"kib": 71354.8, "route": "sep", "src": ["blockdft.hip"], "sha": "24fdb510881ca36f"},
+        "fourier": {"kib": 71354.8, "route": "sep", "src": ["blockdft.hip"], "sha": "550f7bca970db033"},
     },
     "c4": {
         "eigensolve": [
@@ -71,7 +71,7 @@ TRAFFIC_KIB = {
             # the same run's dispatches with the M = 4 class in the wide layout
             {"kib": 606646.6, "route": "fp64=15,wide=1", "src": ["heev.hip", "sturm.h", "dpp.h"], "sha": "2d52cf7efc8892d1"},
         ],
-        "fourier": {"kib": 1471752.7, "route": "sep", "src": ["blockdft.hip"], "sha": "24fdb510881ca36f"},
+        "fourier": {"kib": 1471752.7, "route": "sep", "src": ["blockdft.hip"], "sha": "550f7bca970db033"},
     },
 }
 

@@ -682,11 +682,14 @@ __device__ __forceinline__ void sep_async_issue(char* buf, int tc, int tcap, int
 // Workgroup (lattice, entry chunk, j2 chunk, j3) as in dft_fused_kernel;
 // grid y: H, S.  With Q_0 = P_ks / 2, Q_1 = P_ss / 2 and Q_t = -P_t (t >= 2)
 // for H, and Q_0 = P_ss for S (one term), T2[s1] = sum_t G1_t[s1] Q_t.  The
-// terms go in chunks (sep_term_chunk): the workgroup stages the chunk's
-// G1_t[s1][ec] and Q_t[jj][ec] in LDS with every load of the chunk in flight
-// at once, then thread (column (jj, ec), part sp) accumulates the slots
-// s1 = sp, sp + nsp, ... of its column from LDS alone.  T2 takes the stage's
-// place once every term is in.
+// terms go in chunks staged in LDS, then thread (column (jj, ec), part sp)
+// accumulates the slots s1 = sp, sp + nsp, ... of its column from LDS alone;
+// T2 takes the stage's place once every term is in.  ASYNC (the plan's
+// choice when every lattice allows it): the chunk's G1_t and the transformed
+// factors of dimensions 2 and 3 arrive by global-to-LDS copies
+// (sep_async_issue, sep_async_chunk) and the products are formed while
+// summing; otherwise the workgroup loads G1_t and the factors in registers,
+// forms Q_t, and stores both (sep_term_chunk), two rounds of loads per chunk.
 template <int BM, bool ASYNC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BM <= 16 ? 4 : 1)))
 sep_fused_kernel(const LatDev* __restrict__ lats,
